@@ -1,0 +1,199 @@
+/*
+ * kkt_lu.h - fixed-pattern sparse LU refactorization and solve for sequences
+ * of same-pattern KKT systems, FP64, on one AMD MI355X (gfx950).
+ *
+ * The operations follow the paper's problem statement and solver phases:
+ *   - a sequence K_k x_k = r_k whose matrices all share one sparsity pattern
+ *     (Section 2, eq. "eq:kktlinear" and the paragraph after it);
+ *   - three phases, symbolic / numeric / solve, with the pivot sequence and
+ *     factor patterns of the first system reused for all later ones
+ *     (Section 4, the "refactorization" discussion);
+ *   - the first system analysed on the CPU and everything after it on the
+ *     GPU, data moved to the device once (Section 5 introduction and 5.1.2);
+ *   - refinement as flexible GMRES with re-orthogonalized classical
+ *     Gram-Schmidt, LU factors as the preconditioner, workspaces allocated
+ *     once (Section 5.1.1 and 5.1.2).
+ *
+ * Conventions shared by every entry point:
+ *   Matrices are square CSR, 0-based, int64 row pointers, int32 column
+ *   indices, columns sorted ascending within a row, no duplicates.  Both
+ *   triangles of a symmetric KKT matrix are stored; the library treats it as
+ *   a general matrix.
+ *   Q[k] is the original index of the k-th eliminated vertex, A' = Q^T A Q
+ *   (A'[k][l] = A[Q[k]][Q[l]]); P[k] is the A'-row chosen as pivot at step k;
+ *   P A' = L U with L unit lower triangular, U upper triangular.
+ *   Dense vectors with several right-hand sides are column-major n x nrhs.
+ *   Pointers named d_* are device pointers (hipMalloc'ed or torch CUDA
+ *   tensors); all others are host pointers.  `stream` is a hipStream_t
+ *   (NULL = the legacy default stream).
+ *
+ * Ownership: the caller owns every buffer it passes.  kkt_analyze copies what
+ * it needs from host arrays.  The handle owns all device workspaces; they are
+ * allocated by kkt_analyze and reused by every later call.  Device pointers
+ * passed to kkt_refactor / kkt_solve / kkt_grad_values are read or written in
+ * stream order and must stay valid until that work completes.
+ *
+ * Errors: negative status = fatal, nothing was changed; positive = warning,
+ * the computation went on (the paper lets the first factorization continue on
+ * a singular matrix, Section 5.1.2); kkt_last_error() gives a message.  No
+ * C++ exception crosses this interface.  One host thread per handle at a
+ * time.
+ */
+#ifndef KKT_LU_H
+#define KKT_LU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kkt_ctx *kkt_handle;
+
+typedef enum {
+  KKT_OK = 0,
+  KKT_WARN_NUMERICALLY_SINGULAR = 1, /* a pivot column was all zeros (analyze) */
+  KKT_WARN_TINY_PIVOT = 2,           /* |u_kk| < tiny_pivot_rel * ||A||_inf or non-finite */
+  KKT_WARN_NOT_CONVERGED = 3,        /* refinement budget spent before eta_target */
+  KKT_ERR_INVALID_ARG = -1,
+  KKT_ERR_BAD_PATTERN = -2,          /* unsorted / duplicate / out-of-range CSR */
+  KKT_ERR_STRUCTURALLY_SINGULAR = -3,
+  KKT_ERR_STATE = -4,                /* e.g. refactor before analyze */
+  KKT_ERR_OUT_OF_MEMORY = -5,
+  KKT_ERR_DEVICE = -6,               /* a HIP runtime call failed */
+  KKT_ERR_NONFINITE = -7,            /* NaN/Inf in analyze's values */
+  KKT_ERR_TOO_LARGE = -8             /* factor size exceeds the int32 index range */
+} kkt_status;
+
+typedef struct {
+  int32_t ordering;         /* 0 exact minimum degree on A+A^T (default), 1 natural, 2 user Q */
+  double pivot_tau;         /* threshold partial pivoting in (0,1]; 1e-10 = KKT preset (default) */
+  int32_t fgmres_restart;   /* Krylov restart length, default 20 */
+  int32_t fgmres_max_iters; /* total refinement iterations per right-hand side, default 20 */
+  int32_t min_iters;        /* always run at least this many iterations, default 0 */
+  double eta_target;        /* stop when ||b-Ax||_inf/(||A||_inf ||x||_inf) <= target, 1e-12 */
+  double tiny_pivot_rel;    /* tiny-pivot warning threshold relative to ||A||_inf, 1e-18 */
+  int32_t device;           /* HIP device ordinal, default 0 */
+  int32_t schedule;         /* 0 auto, 1 level-synchronous launches, 2 dependency-driven */
+  int32_t reserved[8];
+} kkt_options;
+
+typedef struct {
+  int32_t warnings;  /* bit (1 << KKT_WARN_*) for every warning raised since the last report */
+  int32_t iters;     /* refinement iterations of the last solve (max over right-hand sides) */
+  double eta;        /* final eta of the last solve (max over right-hand sides) */
+  double eta0;       /* eta right after the direct solve (max over right-hand sides) */
+  double min_pivot;  /* min |u_kk| of the last refactorization */
+  double max_pivot;  /* max |u_kk| of the last refactorization */
+  double anorm_inf;  /* ||A||_inf of the last refactorization */
+} kkt_report;
+
+typedef struct {
+  int32_t n;
+  int64_t nnz;         /* nnz(A) */
+  int64_t nnz_l;       /* strict lower part of the factors */
+  int64_t nnz_u;       /* upper part including the diagonal */
+  int32_t levels;      /* depth of the row dependency graph (refactor, L solve) */
+  int32_t levels_u;    /* depth of the U-solve dependency graph */
+  int32_t analyze_status; /* KKT_OK or KKT_WARN_NUMERICALLY_SINGULAR */
+  int64_t device_bytes;   /* device memory owned by the handle */
+  double analyze_seconds;
+} kkt_info;
+
+/* Fill *opt with the defaults listed above. */
+void kkt_options_default(kkt_options *opt);
+
+/* Create a handle bound to opt->device (opt may be NULL for defaults).
+ * Returns KKT_ERR_INVALID_ARG for out-of-range options. */
+kkt_status kkt_create(const kkt_options *opt, kkt_handle *out);
+kkt_status kkt_destroy(kkt_handle h);
+
+/* Symbolic + pivoting analysis of the first matrix on the host, then one
+ * upload of every index structure to the device (Sections 4 and 5.1.2).
+ * Orders pattern(A+A^T) (opt->ordering), runs a left-looking LU with
+ * threshold partial pivoting on A' using values0 to fix P, derives the L/U
+ * patterns, the A->LU value map and the dependency schedules.  user_q (n
+ * entries) is read only when opt->ordering == 2.  Synchronous.  Re-analysing
+ * a handle replaces its previous analysis.
+ * Errors: INVALID_ARG, BAD_PATTERN, NONFINITE, STRUCTURALLY_SINGULAR,
+ * TOO_LARGE, OUT_OF_MEMORY, DEVICE.  Warning: NUMERICALLY_SINGULAR. */
+kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t *rowptr,
+                       const int32_t *colind, const double *values0, const int32_t *user_q);
+
+/* Numeric refactorization with the stored pivot sequence and patterns
+ * (Section 5.1.2 "resetting the values ... and performing the
+ * refactorization").  d_values: nnz(A) device doubles in the analysed CSR
+ * order.  Asynchronous on `stream`; pivot health (min/max |u_kk|, tiny or
+ * non-finite pivots) is recorded on the device for kkt_sync_report.
+ * Errors: STATE (no analysis), INVALID_ARG, DEVICE. */
+kkt_status kkt_refactor(kkt_handle h, const double *d_values, void *stream);
+
+/* Replace the matrix the solves refine against (their residuals and Krylov
+ * products) by d_values without refactorizing: the existing factors become a
+ * preconditioner of a nearby matrix and FGMRES makes up the difference
+ * (Section 5.1.1: the factors used like an ILU preconditioner inside the
+ * Krylov method).  Asynchronous.  Errors: STATE, INVALID_ARG, DEVICE. */
+kkt_status kkt_update_matrix(kkt_handle h, const double *d_values, void *stream);
+
+/* Solve op(A) X = B with the current factors: permute, L solve, U solve,
+ * permute back (Section 5.1.2), then, while eta > eta_target (or fewer than
+ * min_iters iterations were done), FGMRES-CGS2 iterations preconditioned by
+ * the factors, at most fgmres_max_iters per right-hand side.  op: 'N' (A) or
+ * 'T' (A^T, same factors transposed).  d_b, d_x: column-major n x nrhs
+ * device arrays, must not overlap.  The convergence test reads eta back to
+ * the host (one small synchronous copy per right-hand side and iteration).
+ * Returns KKT_OK or KKT_WARN_NOT_CONVERGED; errors STATE, INVALID_ARG,
+ * DEVICE. */
+kkt_status kkt_solve(kkt_handle h, char op, int32_t nrhs, const double *d_b, double *d_x,
+                     void *stream);
+
+/* Adjoint of x_r = A^{-1} b_r on the stored pattern: d_grad[p] =
+ * -sum_r d_lambda[r][i] * d_x[r][j] for every stored entry p = (i,j) of A,
+ * CSR order (the reverse-mode rule for a linear solve restricted to the
+ * pattern).  d_lambda, d_x: column-major n x nrhs device arrays.  Async.
+ * Errors: STATE, INVALID_ARG, DEVICE. */
+kkt_status kkt_grad_values(kkt_handle h, int32_t nrhs, const double *d_lambda, const double *d_x,
+                           double *d_grad, void *stream);
+
+/* Wait for the handle's device work and return (then clear) the report. */
+kkt_status kkt_sync_report(kkt_handle h, kkt_report *out);
+kkt_status kkt_get_info(kkt_handle h, kkt_info *out);
+
+/* Host copies of the permutations (n entries each; either may be NULL). */
+kkt_status kkt_get_perm(kkt_handle h, int32_t *p, int32_t *q);
+
+/* Host copy of the current factors as one CSR matrix in pivot order: row i
+ * holds L(i, 0..i-1), then u_ii, then U(i, i+1..), columns ascending.
+ * rowptr: n+1, colind/values: nnz_l + nnz_u.  values may be NULL (pattern
+ * only).  Synchronises the handle's device work. */
+kkt_status kkt_get_lu(kkt_handle h, int64_t *rowptr, int32_t *colind, double *values);
+
+/* Message of the last error on this handle (never NULL; "" if none). */
+const char *kkt_last_error(kkt_handle h);
+
+/* Host-only analysis (no device is touched): the exact analysis kkt_analyze
+ * performs (Sections 4 and 5.1: ordering, pivot sequence, factor patterns
+ * and the first factorization's values), returned as a host object for
+ * inspection.  Arguments as for kkt_analyze; opt may be NULL.  On error *out
+ * is NULL and, if msg is non-NULL, a message of at most msg_len bytes
+ * (NUL-terminated) is written to it. */
+typedef struct kkt_host_analysis *kkt_analysis;
+kkt_status kkt_analysis_create(const kkt_options *opt, int32_t n, int64_t nnz,
+                               const int64_t *rowptr, const int32_t *colind,
+                               const double *values0, const int32_t *user_q, kkt_analysis *out,
+                               char *msg, int32_t msg_len);
+/* Sizes and depths (device_bytes and analyze_seconds are 0). */
+kkt_status kkt_analysis_info(kkt_analysis a, kkt_info *out);
+/* As kkt_get_perm / kkt_get_lu, from the host object (values: the pivoting
+ * pass's factors of values0). */
+kkt_status kkt_analysis_perm(kkt_analysis a, int32_t *p, int32_t *q);
+kkt_status kkt_analysis_lu(kkt_analysis a, int64_t *rowptr, int32_t *colind, double *values);
+/* Row dependency schedule: level_ptr (levels+1 entries) and rows (n entries,
+ * grouped by level); either may be NULL. */
+kkt_status kkt_analysis_levels(kkt_analysis a, int32_t *level_ptr, int32_t *rows);
+void kkt_analysis_destroy(kkt_analysis a);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KKT_LU_H */

@@ -1,0 +1,309 @@
+"""Thin ctypes binding of ``libkktlu.so`` (the C ABI in ``include/kkt_lu.h``).
+
+Argument marshalling only: every step of analyze / refactor / solve runs in the
+native library.  PyTorch supplies device memory (float64 CUDA tensors on
+ROCm) and the current HIP stream.  There is no fallback: if the library is not
+built, or no GPU is visible for the device calls, these functions raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libkktlu.so")
+
+OK = 0
+WARN_NUMERICALLY_SINGULAR = 1
+WARN_TINY_PIVOT = 2
+WARN_NOT_CONVERGED = 3
+ERR_INVALID_ARG = -1
+ERR_BAD_PATTERN = -2
+ERR_STRUCTURALLY_SINGULAR = -3
+ERR_STATE = -4
+ERR_OUT_OF_MEMORY = -5
+ERR_DEVICE = -6
+ERR_NONFINITE = -7
+ERR_TOO_LARGE = -8
+
+EXPORTS = [
+    "kkt_options_default", "kkt_create", "kkt_destroy", "kkt_analyze", "kkt_refactor",
+    "kkt_update_matrix", "kkt_solve", "kkt_grad_values", "kkt_sync_report", "kkt_get_info", "kkt_get_perm",
+    "kkt_get_lu", "kkt_last_error", "kkt_analysis_create", "kkt_analysis_info",
+    "kkt_analysis_perm", "kkt_analysis_lu", "kkt_analysis_levels", "kkt_analysis_destroy",
+]
+
+
+class KKTError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"kkt status {status}: {msg}")
+        self.status = status
+
+
+class Options(C.Structure):
+    _fields_ = [("ordering", C.c_int32), ("pivot_tau", C.c_double), ("fgmres_restart", C.c_int32),
+                ("fgmres_max_iters", C.c_int32), ("min_iters", C.c_int32),
+                ("eta_target", C.c_double), ("tiny_pivot_rel", C.c_double), ("device", C.c_int32),
+                ("schedule", C.c_int32), ("reserved", C.c_int32 * 8)]
+
+
+class Report(C.Structure):
+    _fields_ = [("warnings", C.c_int32), ("iters", C.c_int32), ("eta", C.c_double),
+                ("eta0", C.c_double), ("min_pivot", C.c_double), ("max_pivot", C.c_double),
+                ("anorm_inf", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("nnz_l", C.c_int64), ("nnz_u", C.c_int64),
+                ("levels", C.c_int32), ("levels_u", C.c_int32), ("analyze_status", C.c_int32),
+                ("device_bytes", C.c_int64), ("analyze_seconds", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the in-tree library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.kkt_options_default.argtypes = [C.POINTER(Options)]
+        L.kkt_options_default.restype = None
+        L.kkt_create.argtypes = [C.POINTER(Options), C.POINTER(P)]
+        L.kkt_destroy.argtypes = [P]
+        L.kkt_analyze.argtypes = [P, C.c_int32, C.c_int64, P, P, P, P]
+        L.kkt_refactor.argtypes = [P, P, P]
+        L.kkt_update_matrix.argtypes = [P, P, P]
+        L.kkt_solve.argtypes = [P, C.c_char, C.c_int32, P, P, P]
+        L.kkt_grad_values.argtypes = [P, C.c_int32, P, P, P, P]
+        L.kkt_sync_report.argtypes = [P, C.POINTER(Report)]
+        L.kkt_get_info.argtypes = [P, C.POINTER(Info)]
+        L.kkt_get_perm.argtypes = [P, P, P]
+        L.kkt_get_lu.argtypes = [P, P, P, P]
+        L.kkt_last_error.argtypes = [P]
+        L.kkt_last_error.restype = C.c_char_p
+        L.kkt_analysis_create.argtypes = [C.POINTER(Options), C.c_int32, C.c_int64, P, P, P, P,
+                                          C.POINTER(P), C.c_char_p, C.c_int32]
+        L.kkt_analysis_info.argtypes = [P, C.POINTER(Info)]
+        L.kkt_analysis_perm.argtypes = [P, P, P]
+        L.kkt_analysis_lu.argtypes = [P, P, P, P]
+        L.kkt_analysis_levels.argtypes = [P, P, P]
+        L.kkt_analysis_destroy.argtypes = [P]
+        L.kkt_analysis_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def options(**kw) -> Options:
+    o = Options()
+    lib().kkt_options_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _csr_host(rowptr, colind, values):
+    rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+    ci = np.ascontiguousarray(colind, dtype=np.int32)
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    return rp, ci, v
+
+
+class HostAnalysis:
+    """The analysis phase alone, on the host (``kkt_analysis_*``)."""
+
+    def __init__(self, n, rowptr, colind, values0, user_q=None, **opts):
+        rp, ci, v = _csr_host(rowptr, colind, values0)
+        q = None if user_q is None else np.ascontiguousarray(user_q, dtype=np.int32)
+        o = options(**opts)
+        h = C.c_void_p()
+        msg = C.create_string_buffer(512)
+        st = lib().kkt_analysis_create(C.byref(o), int(n), int(rp[-1]), _np_ptr(rp), _np_ptr(ci),
+                                       _np_ptr(v), None if q is None else _np_ptr(q), C.byref(h),
+                                       msg, 512)
+        if st < 0:
+            raise KKTError(st, msg.value.decode())
+        self.status = st
+        self._h = h
+        self.n = int(n)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.kkt_analysis_destroy(self._h)
+            self._h = None
+
+    def info(self) -> Info:
+        i = Info()
+        lib().kkt_analysis_info(self._h, C.byref(i))
+        return i
+
+    def perm(self):
+        P = np.empty(self.n, np.int32)
+        Q = np.empty(self.n, np.int32)
+        lib().kkt_analysis_perm(self._h, _np_ptr(P), _np_ptr(Q))
+        return P, Q
+
+    def lu(self):
+        i = self.info()
+        f = i.nnz_l + i.nnz_u
+        rp = np.empty(self.n + 1, np.int64)
+        ci = np.empty(f, np.int32)
+        v = np.empty(f, np.float64)
+        lib().kkt_analysis_lu(self._h, _np_ptr(rp), _np_ptr(ci), _np_ptr(v))
+        return rp, ci, v
+
+    def levels(self):
+        i = self.info()
+        lp = np.empty(i.levels + 1, np.int32)
+        rows = np.empty(self.n, np.int32)
+        lib().kkt_analysis_levels(self._h, _np_ptr(lp), _np_ptr(rows))
+        return lp, rows
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t, n_expected=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n_expected is not None and t.numel() != n_expected:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n_expected}")
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclasses.dataclass
+class SolveReport:
+    warnings: int
+    iters: int
+    eta: float
+    eta0: float
+    min_pivot: float
+    max_pivot: float
+    anorm_inf: float
+
+
+class KKTSolver:
+    """analyze(pattern + first values) once; refactor(values) and solve(rhs)
+    per system of the sequence, all on one GPU."""
+
+    def __init__(self, device: int = 0, **opts):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("KKTSolver needs a HIP GPU (no CPU fallback exists)")
+        self.device = device
+        o = options(device=device, **opts)
+        h = C.c_void_p()
+        st = lib().kkt_create(C.byref(o), C.byref(h))
+        if st != OK:
+            raise KKTError(st, "kkt_create failed")
+        self._h = h
+        self.n = None
+        self.nnz = None
+        self.last_status = OK
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.kkt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, st):
+        self.last_status = st
+        if st < 0:
+            raise KKTError(st, lib().kkt_last_error(self._h).decode())
+        return st
+
+    def analyze(self, n, rowptr, colind, values0, user_q=None) -> int:
+        rp, ci, v = _csr_host(rowptr, colind, values0)
+        q = None if user_q is None else np.ascontiguousarray(user_q, dtype=np.int32)
+        st = lib().kkt_analyze(self._h, int(n), int(rp[-1]), _np_ptr(rp), _np_ptr(ci), _np_ptr(v),
+                               None if q is None else _np_ptr(q))
+        self._check(st)
+        self.n = int(n)
+        self.nnz = int(rp[-1])
+        return st
+
+    def refactor(self, values, stream=None) -> int:
+        p = _dev_f64(values, self.nnz, "values")
+        return self._check(lib().kkt_refactor(self._h, p, _stream_ptr(stream)))
+
+    def update_matrix(self, values, stream=None) -> int:
+        """New matrix for the residuals; the current factors stay as preconditioner."""
+        p = _dev_f64(values, self.nnz, "values")
+        return self._check(lib().kkt_update_matrix(self._h, p, _stream_ptr(stream)))
+
+    def solve(self, b, x=None, op: str = "N", stream=None):
+        torch = _torch()
+        if b.numel() % self.n:
+            raise ValueError("b must hold n * nrhs entries")
+        nrhs = b.numel() // self.n
+        if x is None:
+            x = torch.empty_like(b)
+        st = lib().kkt_solve(self._h, op.encode(), nrhs, _dev_f64(b, name="b"),
+                             _dev_f64(x, b.numel(), "x"), _stream_ptr(stream))
+        self._check(st)
+        return x
+
+    def grad_values(self, lam, x, out=None, stream=None):
+        torch = _torch()
+        nrhs = lam.numel() // self.n
+        if out is None:
+            out = torch.empty(self.nnz, dtype=torch.float64, device=lam.device)
+        st = lib().kkt_grad_values(self._h, nrhs, _dev_f64(lam, name="lambda"),
+                                   _dev_f64(x, lam.numel(), "x"), _dev_f64(out, self.nnz, "grad"),
+                                   _stream_ptr(stream))
+        self._check(st)
+        return out
+
+    def report(self) -> SolveReport:
+        r = Report()
+        self._check(lib().kkt_sync_report(self._h, C.byref(r)))
+        return SolveReport(r.warnings, r.iters, r.eta, r.eta0, r.min_pivot, r.max_pivot,
+                           r.anorm_inf)
+
+    def info(self) -> Info:
+        i = Info()
+        self._check(lib().kkt_get_info(self._h, C.byref(i)))
+        return i
+
+    def perm(self):
+        P = np.empty(self.n, np.int32)
+        Q = np.empty(self.n, np.int32)
+        self._check(lib().kkt_get_perm(self._h, _np_ptr(P), _np_ptr(Q)))
+        return P, Q
+
+    def lu(self, values: bool = True):
+        i = self.info()
+        f = i.nnz_l + i.nnz_u
+        rp = np.empty(self.n + 1, np.int64)
+        ci = np.empty(f, np.int32)
+        v = np.empty(f, np.float64) if values else None
+        self._check(lib().kkt_get_lu(self._h, _np_ptr(rp), _np_ptr(ci),
+                                     None if v is None else _np_ptr(v)))
+        return rp, ci, v

@@ -1,0 +1,480 @@
+// Host analysis: ordering, pivoting pass, factor layouts and schedules.
+//
+// Section 5.1 solves the first system of the sequence completely on the CPU
+// (fill-reducing symmetric ordering, then an LU with pivoting that is allowed
+// to continue on singular input) and extracts the permutations and the L/U
+// structures for the GPU refactorization; Section 5.2 orders A + A^T the same
+// way.  This file is that phase.  Arithmetic policy: every update is
+// std::fma(-l, u, a), divisions are IEEE, no contraction (-ffp-contract=off),
+// and the updates of each entry are applied in ascending pivot-step order, so
+// the pivoting decisions depend only on the mathematical definition and not
+// on traversal order.
+#include "analyze.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <set>
+
+#include "../../include/kkt_lu.h"
+
+namespace kktlu {
+
+int validate_csr(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colind,
+                 std::string* msg) {
+  if (n <= 0 || nnz < 0 || !rowptr || (nnz > 0 && !colind)) {
+    if (msg) *msg = "n must be positive and rowptr/colind non-null";
+    return KKT_ERR_INVALID_ARG;
+  }
+  if (rowptr[0] != 0 || rowptr[n] != nnz) {
+    if (msg) *msg = "rowptr[0] must be 0 and rowptr[n] must equal nnz";
+    return KKT_ERR_BAD_PATTERN;
+  }
+  for (int32_t i = 0; i < n; i++) {
+    if (rowptr[i + 1] < rowptr[i]) {
+      if (msg) *msg = "rowptr is not non-decreasing at row " + std::to_string(i);
+      return KKT_ERR_BAD_PATTERN;
+    }
+    for (int64_t p = rowptr[i]; p < rowptr[i + 1]; p++) {
+      int32_t c = colind[p];
+      if (c < 0 || c >= n) {
+        if (msg) *msg = "column index out of range in row " + std::to_string(i);
+        return KKT_ERR_BAD_PATTERN;
+      }
+      if (p > rowptr[i] && colind[p - 1] >= c) {
+        if (msg) *msg = "columns unsorted or duplicated in row " + std::to_string(i);
+        return KKT_ERR_BAD_PATTERN;
+      }
+    }
+  }
+  return KKT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Exact minimum degree on a quotient graph.
+// Variables keep a list of adjacent variables and of adjacent elements
+// (eliminated vertices).  Eliminating p turns it into an element whose
+// variable list is the union of its variable neighbours and of the lists of
+// the elements it touches; those elements are absorbed.  The degree of a
+// variable is the size of the union of its variable neighbours and its
+// elements' lists, i.e. its degree in the elimination graph, recomputed
+// exactly after every elimination.  Selection: smallest (degree, index).
+// ---------------------------------------------------------------------------
+void order_minimum_degree(int32_t n, const int64_t* rowptr, const int32_t* colind,
+                          std::vector<int32_t>& Q) {
+  std::vector<std::vector<int32_t>> avar(n), elist(n), lel(n);
+  for (int32_t i = 0; i < n; i++)
+    for (int64_t p = rowptr[i]; p < rowptr[i + 1]; p++) {
+      int32_t j = colind[p];
+      if (j != i) {
+        avar[i].push_back(j);
+        avar[j].push_back(i);
+      }
+    }
+  for (auto& a : avar) {
+    std::sort(a.begin(), a.end());
+    a.erase(std::unique(a.begin(), a.end()), a.end());
+  }
+  enum : int8_t { VAR = 0, ELEM = 1, ABSORBED = 2 };
+  std::vector<int8_t> state(n, VAR);
+  std::vector<int32_t> deg(n);
+  std::vector<int64_t> stamp(n, 0);
+  int64_t gen = 0;
+  std::set<std::pair<int32_t, int32_t>> queue;
+  for (int32_t v = 0; v < n; v++) {
+    deg[v] = (int32_t)avar[v].size();
+    queue.insert({deg[v], v});
+  }
+  Q.assign(n, -1);
+  std::vector<int32_t> lp;
+  for (int32_t step = 0; step < n; step++) {
+    const int32_t p = queue.begin()->second;
+    queue.erase(queue.begin());
+    Q[step] = p;
+    // variable list of the new element p
+    gen++;
+    stamp[p] = gen;
+    lp.clear();
+    for (int32_t u : avar[p])
+      if (state[u] == VAR && stamp[u] != gen) {
+        stamp[u] = gen;
+        lp.push_back(u);
+      }
+    for (int32_t e : elist[p]) {
+      if (state[e] != ELEM) continue;
+      for (int32_t u : lel[e])
+        if (state[u] == VAR && stamp[u] != gen) {
+          stamp[u] = gen;
+          lp.push_back(u);
+        }
+      state[e] = ABSORBED;
+      std::vector<int32_t>().swap(lel[e]);
+    }
+    state[p] = ELEM;
+    std::vector<int32_t>().swap(avar[p]);
+    std::vector<int32_t>().swap(elist[p]);
+    lel[p] = lp;
+    const int64_t in_lp = gen;  // stamp marking lp and p
+    for (int32_t v : lp) {
+      auto& el = elist[v];
+      el.erase(std::remove_if(el.begin(), el.end(), [&](int32_t e) { return state[e] != ELEM; }),
+               el.end());
+      el.push_back(p);
+      auto& av = avar[v];
+      av.erase(std::remove_if(av.begin(), av.end(),
+                              [&](int32_t u) { return state[u] != VAR || stamp[u] == in_lp; }),
+               av.end());
+    }
+    for (int32_t v : lp) {
+      gen++;
+      stamp[v] = gen;
+      int32_t d = 0;
+      for (int32_t u : avar[v])
+        if (stamp[u] != gen) {
+          stamp[u] = gen;
+          d++;
+        }
+      for (int32_t e : elist[v])
+        for (int32_t u : lel[e])
+          if (stamp[u] != gen) {
+            stamp[u] = gen;
+            d++;
+          }
+      if (d != deg[v]) {
+        queue.erase({deg[v], v});
+        deg[v] = d;
+        queue.insert({d, v});
+      }
+    }
+  }
+}
+
+namespace {
+
+struct ColumnFactors {
+  // column-wise factors; L rows as A'-rows until renumbered
+  std::vector<int64_t> lp, up;
+  std::vector<int32_t> li, ui;
+  std::vector<double> lx, ux;
+};
+
+// Left-looking LU of A' with threshold partial pivoting (Gilbert-Peierls):
+// structure of column k by depth-first search through the columns of L
+// already computed, numeric updates in ascending pivot-step order.
+int pivoting_pass(int32_t n, const int64_t* rowptr, const int32_t* colind, const double* val,
+                  const std::vector<int32_t>& Q, const std::vector<int32_t>& Qinv, double tau,
+                  std::vector<int32_t>& P, std::vector<int32_t>& pivstep, ColumnFactors& F,
+                  int* warn_singular, std::string* msg) {
+  // CSC of A with positions
+  std::vector<int64_t> cptr(n + 1, 0);
+  int64_t nnz = rowptr[n];
+  for (int64_t p = 0; p < nnz; p++) cptr[colind[p] + 1]++;
+  for (int32_t j = 0; j < n; j++) cptr[j + 1] += cptr[j];
+  std::vector<int32_t> crow(nnz);
+  std::vector<double> cval(nnz);
+  {
+    std::vector<int64_t> next(cptr.begin(), cptr.end() - 1);
+    for (int32_t i = 0; i < n; i++)
+      for (int64_t p = rowptr[i]; p < rowptr[i + 1]; p++) {
+        int64_t q = next[colind[p]]++;
+        crow[q] = i;
+        cval[q] = val[p];
+      }
+  }
+  P.assign(n, -1);
+  pivstep.assign(n, -1);
+  F.lp.assign(n + 1, 0);
+  F.up.assign(n + 1, 0);
+  std::vector<double> x(n, 0.0);
+  std::vector<int32_t> seen(n, -1);
+  std::vector<int32_t> cand, steps, stack;
+  *warn_singular = 0;
+  for (int32_t k = 0; k < n; k++) {
+    cand.clear();
+    steps.clear();
+    const int32_t c = Q[k];
+    // discover the structure
+    for (int64_t q = cptr[c]; q < cptr[c + 1]; q++) {
+      int32_t r = Qinv[crow[q]];
+      if (seen[r] == k) continue;
+      seen[r] = k;
+      x[r] = 0.0;
+      if (pivstep[r] < 0) {
+        cand.push_back(r);
+        continue;
+      }
+      stack.push_back(pivstep[r]);
+      while (!stack.empty()) {
+        int32_t j = stack.back();
+        stack.pop_back();
+        steps.push_back(j);
+        for (int64_t t = F.lp[j]; t < F.lp[j + 1]; t++) {
+          int32_t r2 = F.li[t];
+          if (seen[r2] == k) continue;
+          seen[r2] = k;
+          x[r2] = 0.0;
+          if (pivstep[r2] < 0)
+            cand.push_back(r2);
+          else
+            stack.push_back(pivstep[r2]);
+        }
+      }
+    }
+    for (int64_t q = cptr[c]; q < cptr[c + 1]; q++) x[Qinv[crow[q]]] = cval[q];
+    std::sort(steps.begin(), steps.end());
+    for (int32_t j : steps) {
+      const double xj = x[P[j]];
+      F.ui.push_back(j);
+      F.ux.push_back(xj);
+      for (int64_t t = F.lp[j]; t < F.lp[j + 1]; t++)
+        x[F.li[t]] = std::fma(-F.lx[t], xj, x[F.li[t]]);
+    }
+    if (cand.empty()) {
+      if (msg) *msg = "structurally singular: no pivot candidate in column " + std::to_string(k);
+      return KKT_ERR_STRUCTURALLY_SINGULAR;
+    }
+    int32_t best = -1, smallest = std::numeric_limits<int32_t>::max();
+    double bestabs = -1.0;
+    bool diag_ok = false;
+    for (int32_t r : cand) {
+      double a = std::fabs(x[r]);
+      if (r == k) diag_ok = true;
+      smallest = std::min(smallest, r);
+      if (a > bestabs || (a == bestabs && r < best)) {
+        bestabs = a;
+        best = r;
+      }
+    }
+    int32_t piv;
+    if (bestabs == 0.0) {
+      piv = diag_ok ? k : smallest;
+      *warn_singular = 1;
+    } else if (diag_ok && x[k] != 0.0 && std::fabs(x[k]) >= tau * bestabs) {
+      piv = k;
+    } else {
+      piv = best;
+    }
+    const double pv = x[piv];
+    F.ui.push_back(k);
+    F.ux.push_back(pv);
+    F.up[k + 1] = (int64_t)F.ui.size();
+    P[k] = piv;
+    pivstep[piv] = k;
+    for (int32_t r : cand)
+      if (r != piv) {
+        F.li.push_back(r);
+        F.lx.push_back(x[r] / pv);
+      }
+    F.lp[k + 1] = (int64_t)F.li.size();
+  }
+  return KKT_OK;
+}
+
+void levels_forward(int32_t n, const std::vector<int32_t>& ptr, const std::vector<int32_t>& idx,
+                    std::vector<int32_t>& lev_ptr, std::vector<int32_t>& lev_rows, bool descending,
+                    std::vector<int32_t>* level_of = nullptr) {
+  // level(v) = 1 + max level(u) over predecessors idx[ptr[v]..ptr[v+1]);
+  // predecessors of v are all < v (ascending) or > v (descending)
+  std::vector<int32_t> lev(n, 0);
+  int32_t nl = 0;
+  for (int32_t s = 0; s < n; s++) {
+    int32_t v = descending ? n - 1 - s : s;
+    int32_t l = 0;
+    for (int32_t t = ptr[v]; t < ptr[v + 1]; t++) l = std::max(l, lev[idx[t]] + 1);
+    lev[v] = l;
+    nl = std::max(nl, l + 1);
+  }
+  lev_ptr.assign(nl + 1, 0);
+  for (int32_t v = 0; v < n; v++) lev_ptr[lev[v] + 1]++;
+  for (int32_t l = 0; l < nl; l++) lev_ptr[l + 1] += lev_ptr[l];
+  lev_rows.assign(n, 0);
+  std::vector<int32_t> next(lev_ptr.begin(), lev_ptr.end() - 1);
+  for (int32_t s = 0; s < n; s++) {
+    int32_t v = descending ? n - 1 - s : s;
+    lev_rows[next[lev[v]]++] = v;
+  }
+  if (level_of) *level_of = lev;
+}
+
+}  // namespace
+
+int analyze(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colind,
+            const double* values0, const int32_t* user_q, const AnalyzeOptions& opt, Analysis& A,
+            std::string* msg) {
+  int st = validate_csr(n, nnz, rowptr, colind, msg);
+  if (st != KKT_OK) return st;
+  if (!values0) {
+    if (msg) *msg = "values0 is required (pivoting is numeric)";
+    return KKT_ERR_INVALID_ARG;
+  }
+  if (!(opt.tau > 0.0 && opt.tau <= 1.0)) {
+    if (msg) *msg = "pivot_tau must be in (0, 1]";
+    return KKT_ERR_INVALID_ARG;
+  }
+  for (int64_t p = 0; p < nnz; p++)
+    if (!std::isfinite(values0[p])) {
+      if (msg) *msg = "values0 holds NaN or Inf at position " + std::to_string(p);
+      return KKT_ERR_NONFINITE;
+    }
+  A = Analysis();
+  A.n = n;
+  A.nnz = nnz;
+  // ordering
+  if (opt.ordering == 0) {
+    order_minimum_degree(n, rowptr, colind, A.Q);
+  } else if (opt.ordering == 1) {
+    A.Q.resize(n);
+    for (int32_t i = 0; i < n; i++) A.Q[i] = i;
+  } else if (opt.ordering == 2) {
+    if (!user_q) {
+      if (msg) *msg = "ordering 2 needs user_q";
+      return KKT_ERR_INVALID_ARG;
+    }
+    A.Q.assign(user_q, user_q + n);
+  } else {
+    if (msg) *msg = "unknown ordering";
+    return KKT_ERR_INVALID_ARG;
+  }
+  A.Qinv.assign(n, -1);
+  for (int32_t k = 0; k < n; k++) {
+    int32_t q = A.Q[k];
+    if (q < 0 || q >= n || A.Qinv[q] >= 0) {
+      if (msg) *msg = "Q is not a permutation";
+      return KKT_ERR_INVALID_ARG;
+    }
+    A.Qinv[q] = k;
+  }
+  // pivoting pass
+  ColumnFactors F;
+  std::vector<int32_t> pivstep;
+  st = pivoting_pass(n, rowptr, colind, values0, A.Q, A.Qinv, opt.tau, A.P, pivstep, F,
+                     &A.warn_singular, msg);
+  if (st != KKT_OK) return st;
+  A.Pinv.assign(n, 0);
+  for (int32_t k = 0; k < n; k++) A.Pinv[A.P[k]] = k;
+  const int64_t lnz = F.lp[n], unz = F.up[n];
+  if (lnz + unz > (int64_t)std::numeric_limits<int32_t>::max()) {
+    if (msg) *msg = "nnz(L+U) exceeds the int32 index range";
+    return KKT_ERR_TOO_LARGE;
+  }
+  A.nnz_l = lnz;
+  A.nnz_u = unz;
+  // combined CSR in pivot order
+  std::vector<int32_t> cl(n, 0), cu(n, 0);
+  for (int64_t t = 0; t < lnz; t++) cl[pivstep[F.li[t]]]++;
+  for (int64_t t = 0; t < unz; t++) cu[F.ui[t]]++;
+  A.lu_rowptr.assign(n + 1, 0);
+  A.diag.assign(n, 0);
+  for (int32_t i = 0; i < n; i++) A.lu_rowptr[i + 1] = A.lu_rowptr[i] + cl[i] + cu[i];
+  const int64_t f = lnz + unz;
+  A.lu_col.assign(f, 0);
+  A.lu_val0.assign(f, 0.0);
+  std::vector<int32_t> nl(n), nu(n);
+  for (int32_t i = 0; i < n; i++) {
+    nl[i] = A.lu_rowptr[i];
+    nu[i] = A.lu_rowptr[i] + cl[i];
+    A.diag[i] = nu[i];
+  }
+  for (int32_t k = 0; k < n; k++) {
+    for (int64_t t = F.lp[k]; t < F.lp[k + 1]; t++) {
+      int32_t i = pivstep[F.li[t]];
+      A.lu_col[nl[i]] = k;
+      A.lu_val0[nl[i]++] = F.lx[t];
+    }
+    for (int64_t t = F.up[k]; t < F.up[k + 1]; t++) {
+      int32_t i = F.ui[t];
+      A.lu_col[nu[i]] = k;
+      A.lu_val0[nu[i]++] = F.ux[t];
+    }
+  }
+  // A -> LU value map (gather form: LU position -> A position or -1)
+  A.lu_src.assign(f, -1);
+  for (int32_t r = 0; r < n; r++) {
+    const int32_t i = A.Pinv[A.Qinv[r]];
+    const int32_t* b = A.lu_col.data() + A.lu_rowptr[i];
+    const int32_t* e = A.lu_col.data() + A.lu_rowptr[i + 1];
+    for (int64_t p = rowptr[r]; p < rowptr[r + 1]; p++) {
+      const int32_t j = A.Qinv[colind[p]];
+      const int32_t* it = std::lower_bound(b, e, j);
+      if (it == e || *it != j) {
+        if (msg) *msg = "internal: A entry missing from the factor pattern";
+        return KKT_ERR_DEVICE;
+      }
+      A.lu_src[it - A.lu_col.data()] = (int32_t)p;
+    }
+  }
+  // schedules: rows of the dependency graph L(i,:) (refactorization, L solve)
+  {
+    std::vector<int32_t> ptr(n + 1), idx;
+    idx.reserve(lnz);
+    for (int32_t i = 0; i < n; i++) {
+      for (int32_t q = A.lu_rowptr[i]; q < A.diag[i]; q++) idx.push_back(A.lu_col[q]);
+      ptr[i + 1] = (int32_t)idx.size();
+    }
+    levels_forward(n, ptr, idx, A.lev_ptr, A.lev_rows, false);
+    const int32_t nlev = (int32_t)A.lev_ptr.size() - 1;
+    A.lev_maxlen.assign(nlev, 0);
+    for (int32_t l = 0; l < nlev; l++)
+      for (int32_t t = A.lev_ptr[l]; t < A.lev_ptr[l + 1]; t++) {
+        int32_t i = A.lev_rows[t];
+        A.lev_maxlen[l] = std::max(A.lev_maxlen[l], A.lu_rowptr[i + 1] - A.lu_rowptr[i]);
+      }
+    // U solve: row i needs z_j for j in U(i, >i)
+    ptr.assign(n + 1, 0);
+    idx.clear();
+    for (int32_t i = 0; i < n; i++) {
+      for (int32_t q = A.diag[i] + 1; q < A.lu_rowptr[i + 1]; q++) idx.push_back(A.lu_col[q]);
+      ptr[i + 1] = (int32_t)idx.size();
+    }
+    levels_forward(n, ptr, idx, A.ulev_ptr, A.ulev_rows, true);
+  }
+  // transposed views: columns of U (rows ascending, diagonal last) and of strict L
+  {
+    A.ut_ptr.assign(n + 1, 0);
+    A.lt_ptr.assign(n + 1, 0);
+    for (int32_t i = 0; i < n; i++) {
+      for (int32_t q = A.lu_rowptr[i]; q < A.diag[i]; q++) A.lt_ptr[A.lu_col[q] + 1]++;
+      for (int32_t q = A.diag[i]; q < A.lu_rowptr[i + 1]; q++) A.ut_ptr[A.lu_col[q] + 1]++;
+    }
+    for (int32_t j = 0; j < n; j++) {
+      A.lt_ptr[j + 1] += A.lt_ptr[j];
+      A.ut_ptr[j + 1] += A.ut_ptr[j];
+    }
+    A.lt_pos.assign(lnz, 0);
+    A.ut_pos.assign(unz, 0);
+    std::vector<int32_t> nxl(A.lt_ptr.begin(), A.lt_ptr.end() - 1);
+    std::vector<int32_t> nxu(A.ut_ptr.begin(), A.ut_ptr.end() - 1);
+    for (int32_t i = 0; i < n; i++) {
+      for (int32_t q = A.lu_rowptr[i]; q < A.diag[i]; q++) A.lt_pos[nxl[A.lu_col[q]]++] = q;
+      for (int32_t q = A.diag[i]; q < A.lu_rowptr[i + 1]; q++) A.ut_pos[nxu[A.lu_col[q]]++] = q;
+    }
+    // U^T solve (ascending j): t_j needs t_i for i in U(:, j), i < j
+    std::vector<int32_t> ptr(n + 1), idx;
+    for (int32_t j = 0; j < n; j++) {
+      for (int32_t t = A.ut_ptr[j]; t < A.ut_ptr[j + 1] - 1; t++) {
+        int32_t q = A.ut_pos[t];
+        int32_t i = (int32_t)(std::upper_bound(A.lu_rowptr.begin(), A.lu_rowptr.end(), q) -
+                              A.lu_rowptr.begin()) - 1;
+        idx.push_back(i);
+      }
+      ptr[j + 1] = (int32_t)idx.size();
+    }
+    levels_forward(n, ptr, idx, A.utlev_ptr, A.utlev_rows, false);
+    // L^T solve (descending j): w_j needs w_i for i in L(:, j), i > j
+    idx.clear();
+    for (int32_t j = 0; j < n; j++) {
+      for (int32_t t = A.lt_ptr[j]; t < A.lt_ptr[j + 1]; t++) {
+        int32_t q = A.lt_pos[t];
+        int32_t i = (int32_t)(std::upper_bound(A.lu_rowptr.begin(), A.lu_rowptr.end(), q) -
+                              A.lu_rowptr.begin()) - 1;
+        idx.push_back(i);
+      }
+      ptr[j + 1] = (int32_t)idx.size();
+    }
+    levels_forward(n, ptr, idx, A.ltlev_ptr, A.ltlev_rows, true);
+  }
+  return A.warn_singular ? KKT_WARN_NUMERICALLY_SINGULAR : KKT_OK;
+}
+
+}  // namespace kktlu

@@ -1,0 +1,57 @@
+// Host-side analysis of the first matrix of a same-pattern sequence:
+// ordering, pivot sequence, factor patterns, value maps and schedules.
+// (Sections 4 and 5.1: symbolic phase plus the first numeric factorization on
+// the CPU; its permutations and L/U structures are reused for every later
+// system.)
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace kktlu {
+
+struct AnalyzeOptions {
+  int ordering = 0;       // 0 minimum degree on A+A^T, 1 natural, 2 user-supplied
+  double tau = 1e-10;     // threshold partial pivoting
+};
+
+struct Analysis {
+  int32_t n = 0;
+  int64_t nnz = 0;
+  std::vector<int32_t> Q, Qinv;  // Q[k] = original index of step k
+  std::vector<int32_t> P, Pinv;  // P[k] = A'-row pivoted at step k
+  // combined factors, CSR in pivot order: L strict part, diagonal, U strict part
+  std::vector<int32_t> lu_rowptr;  // n+1
+  std::vector<int32_t> lu_col;     // f
+  std::vector<int32_t> diag;       // n, position of (i,i)
+  std::vector<double> lu_val0;     // values from the pivoting pass
+  std::vector<int32_t> lu_src;     // f, index into A's values or -1 (fill)
+  // row dependency schedule (refactorization and L solve): rows by level
+  std::vector<int32_t> lev_ptr, lev_rows;
+  std::vector<int32_t> lev_maxlen;  // longest LU row of each level
+  // U-solve schedule
+  std::vector<int32_t> ulev_ptr, ulev_rows;
+  // transposed views: column-major order of the strict L part and of U, as
+  // positions into the CSR arrays (for the transposed solve)
+  std::vector<int32_t> ut_ptr, ut_pos;   // column j of U: rows i<=j (diag last)
+  std::vector<int32_t> lt_ptr, lt_pos;   // column j of strict L: rows i>j
+  std::vector<int32_t> ltlev_ptr, ltlev_rows;  // L^T solve (descending) schedule
+  std::vector<int32_t> utlev_ptr, utlev_rows;  // U^T solve (ascending) schedule
+  int64_t nnz_l = 0, nnz_u = 0;
+  int warn_singular = 0;
+};
+
+// Status codes use the public enum's values.
+int validate_csr(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colind,
+                 std::string* msg);
+
+// Exact minimum degree on pattern(A + A^T), ties -> smallest index.
+void order_minimum_degree(int32_t n, const int64_t* rowptr, const int32_t* colind,
+                          std::vector<int32_t>& Q);
+
+// Full analysis.  Returns a kkt_status value; msg gets details on failure.
+int analyze(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colind,
+            const double* values0, const int32_t* user_q, const AnalyzeOptions& opt,
+            Analysis& out, std::string* msg);
+
+}  // namespace kktlu

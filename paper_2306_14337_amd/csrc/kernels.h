@@ -1,0 +1,95 @@
+// Device kernels of the refactor/solve path and their host-side launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace kktlu {
+
+// Refactorization statistics accumulated on the device (reset per refactor).
+struct DevStats {
+  unsigned long long min_piv;  // bits of min |u_kk| (non-negative doubles order like uint64)
+  unsigned long long max_piv;  // bits of max |u_kk|
+  unsigned long long anorm;    // bits of ||A||_inf
+  unsigned long long anorm1;   // bits of ||A||_1
+  unsigned long long rmax;     // bits of ||r||_inf (scratch of the residual kernel)
+  unsigned long long xmax;     // bits of ||x||_inf
+  int tiny;                    // a tiny or non-finite pivot was seen
+  int pad;
+};
+
+struct LUView {
+  int n;
+  const int* rowptr;  // n+1
+  const int* col;     // f
+  const int* diag;    // n
+  const int* src;     // f: A position or -1
+  double* val;        // f
+};
+
+// level-synchronous refactorization of the rows rows[0..nrows) (all their
+// dependencies finished in earlier launches).  maxlen = longest row.
+void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxlen,
+                          const double* aval, DevStats* st, double tiny_abs_unused,
+                          hipStream_t s);
+// pivot statistics (min/max |u_kk|, tiny test against tiny_rel * ||A||_inf)
+void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStream_t s);
+
+// A copy + ||A||_inf
+void launch_copy_anorm(int n, const int* arow, const int* acol, const double* src, double* dst,
+                       DevStats* st, hipStream_t s);
+// ||A||_1 through the column view
+void launch_anorm1(int n, const int* cptr, const int* cpos, const double* aval, DevStats* st,
+                   hipStream_t s);
+void launch_reset_stats(DevStats* st, int what, hipStream_t s);
+
+// triangular solves on one right-hand side, in place on y
+void launch_lsolve_rows(const LUView& lu, const int* rows, int nrows, int maxlen, double* y,
+                        hipStream_t s);
+void launch_usolve_rows(const LUView& lu, const int* rows, int nrows, int maxlen, double* y,
+                        hipStream_t s);
+// transposed: columns via (ptr, row, pos) views
+void launch_utsolve_cols(const LUView& lu, const int* cols, int ncols, const int* tptr,
+                         const int* trow, const int* tpos, double* y, hipStream_t s);
+void launch_ltsolve_cols(const LUView& lu, const int* cols, int ncols, const int* tptr,
+                         const int* trow, const int* tpos, double* y, hipStream_t s);
+
+// y[i] = x[perm[i]]  /  y[perm[i]] = x[i]
+void launch_gather(int n, const int* perm, const double* x, double* y, hipStream_t s);
+void launch_scatter(int n, const int* perm, const double* x, double* y, hipStream_t s);
+
+// r = b - op(A) x and the maxima ||r||_inf, ||x||_inf into st
+void launch_residual(int n, char op, const int* ptr, const int* idx, const int* pos,
+                     const double* aval, const double* b, const double* x, double* r, DevStats* st,
+                     hipStream_t s);
+// y = op(A) x
+void launch_spmv(int n, char op, const int* ptr, const int* idx, const int* pos, const double* aval,
+                 const double* x, double* y, hipStream_t s);
+
+// h[i] = sum_t V[i*ld + t] * w[t], i < m  (two-stage deterministic reduction)
+void launch_multidot(int n, int m, const double* V, long ld, const double* w, double* partial,
+                     double* h, hipStream_t s);
+// w -= sum_i h[i] V[i]
+void launch_multiaxpy(int n, int m, const double* V, long ld, const double* h, double* w,
+                      hipStream_t s);
+// out[t] = base[t] + sum_i y[i] Z[i]
+void launch_combine(int n, int m, const double* Z, long ld, const double* y, const double* base,
+                    double* out, hipStream_t s);
+// y = x * (1 / *scal)  (scal on the device)
+void launch_scale_div(int n, const double* x, const double* scal, double* y, hipStream_t s);
+// Givens / small least-squares update of column j of the Hessenberg matrix
+// (FGMRES bookkeeping, one thread): column = h + h2 (the two CGS passes) and
+// ||w|| = sqrt(*ww); H column-major (m+1) x m; writes y (j+1 entries) and
+// *hn_out = ||w||.
+void launch_givens(int j, int m, const double* h, const double* h2, const double* ww, double* H,
+                   double* cs, double* sn, double* g, double* y, double* hn_out, hipStream_t s);
+// g = [beta, 0, ...], v0 = r / beta (beta = sqrt(dot) computed on device)
+void launch_arnoldi_start(int n, int m, const double* r, const double* rr, double* v0, double* g,
+                          hipStream_t s);
+
+// adjoint: transposes and the sampled dense-dense product on the pattern
+void launch_transpose(int rows, int cols, const double* in, double* out, hipStream_t s);
+void launch_grad_sddmm(int n, int nrhs, const int* arow_ptr, const int* acol,
+                       const double* lam_rm, const double* x_rm, double* grad, hipStream_t s);
+
+}  // namespace kktlu

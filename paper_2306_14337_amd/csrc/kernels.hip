@@ -1,0 +1,606 @@
+// HIP kernels for gfx950 (CDNA4, wave64): fixed-pattern sparse LU
+// refactorization, triangular solves, residuals and FGMRES-CGS2 pieces.
+//
+// Arithmetic policy of the refactorization: the updates of each entry are
+// applied in ascending pivot-step order as fma(-l, u, a) and l = a / u_kk is
+// the IEEE-rounded quotient, which is exactly the sequence of operations of a
+// left-looking column factorization; the factors therefore agree bit for bit
+// with any implementation that follows the same definition.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace kktlu {
+
+namespace {
+
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ void wave_sync() {
+  // LDS operations of one wavefront complete in issue order; this keeps the
+  // compiler from moving LDS accesses across the step boundary.
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ unsigned long long dbits(double v) {
+  return (unsigned long long)__double_as_longlong(v);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = WAVE / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, WAVE));
+  return v;
+}
+
+// first position p in [lo, hi) with a[p] >= key
+__device__ __forceinline__ int lower_bound_i(const int* a, int lo, int hi, int key) {
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Refactorization, up-looking row form (cf. the paper's Algorithm
+// "alg:ginkgo-lu", read with alpha = a_id / u_dd).  Row i of P A' is staged in
+// LDS straight from A through the value map (fill entries start at zero);
+// for each L entry k of row i in ascending order: l_ik = a_ik / u_kk, then
+// a_ij -= l_ik * u_kj for every j in U(k, >k), located in row i by binary
+// search over the staged column list.  One wavefront per row; WPB rows per
+// workgroup.
+// ---------------------------------------------------------------------------
+template <int CAP, int WPB>
+__global__ __launch_bounds__(WPB* WAVE) void k_refactor_rows_lds(
+    const int* __restrict__ rows, int nrows, const int* __restrict__ rowptr,
+    const int* __restrict__ col, const int* __restrict__ diag, const int* __restrict__ src,
+    const double* __restrict__ aval, double* __restrict__ val) {
+  __shared__ int s_col[WPB][CAP];
+  __shared__ double s_val[WPB][CAP];
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int r = blockIdx.x * WPB + wave;
+  if (r >= nrows) return;  // only wavefront-level synchronisation below
+  const int i = rows[r];
+  const int rs = rowptr[i], len = rowptr[i + 1] - rs, dl = diag[i] - rs;
+  int* sc = s_col[wave];
+  double* sv = s_val[wave];
+  for (int t = lane; t < len; t += WAVE) {
+    sc[t] = col[rs + t];
+    const int s = src[rs + t];
+    sv[t] = s >= 0 ? aval[s] : 0.0;
+  }
+  wave_sync();
+  for (int t = 0; t < dl; t++) {
+    const int k = sc[t];
+    const int dk = diag[k];
+    const int ke = rowptr[k + 1];
+    const double lik = sv[t] / val[dk];
+    for (int q = dk + 1 + lane; q < ke; q += WAVE) {
+      const int j = col[q];
+      const double u = val[q];
+      const int p = lower_bound_i(sc, t + 1, len, j);
+      // the fill pattern guarantees j is in row i; the test keeps a corrupt
+      // pattern from writing outside this row
+      if (p < len && sc[p] == j) sv[p] = __builtin_fma(-lik, u, sv[p]);
+    }
+    wave_sync();
+    if (lane == 0) sv[t] = lik;
+    wave_sync();
+  }
+  for (int t = lane; t < len; t += WAVE) val[rs + t] = sv[t];
+}
+
+// Same computation with the row kept in global memory (rows longer than the
+// LDS staging capacity).  One wavefront per workgroup.
+__global__ __launch_bounds__(WAVE) void k_refactor_rows_global(
+    const int* __restrict__ rows, int nrows, const int* __restrict__ rowptr,
+    const int* __restrict__ col, const int* __restrict__ diag, const int* __restrict__ src,
+    const double* __restrict__ aval, double* val) {
+  const int lane = threadIdx.x;
+  const int r = blockIdx.x;
+  if (r >= nrows) return;
+  const int i = rows[r];
+  const int rs = rowptr[i], re = rowptr[i + 1], dpos = diag[i];
+  for (int q = rs + lane; q < re; q += WAVE) {
+    const int s = src[q];
+    val[q] = s >= 0 ? aval[s] : 0.0;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  for (int t = rs; t < dpos; t++) {
+    const int k = col[t];
+    const int dk = diag[k];
+    const int ke = rowptr[k + 1];
+    const double lik = val[t] / val[dk];
+    for (int q = dk + 1 + lane; q < ke; q += WAVE) {
+      const int j = col[q];
+      const double u = val[q];
+      const int p = lower_bound_i(col, t + 1, re, j);
+      if (p < re && col[p] == j) val[p] = __builtin_fma(-lik, u, val[p]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) val[t] = lik;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+__global__ void k_pivot_stats(int n, const int* __restrict__ diag, const double* __restrict__ val,
+                              DevStats* st, double tiny_rel) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double mn = __builtin_huge_val(), mx = 0.0;
+  int tiny = 0;
+  const double anorm = __longlong_as_double((long long)st->anorm);
+  if (i < n) {
+    const double d = fabs(val[diag[i]]);
+    mn = d;
+    mx = d;
+    tiny = !(d >= tiny_rel * anorm) || isinf(d);
+  }
+  for (int off = WAVE / 2; off > 0; off >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, off, WAVE));
+    mx = fmax(mx, __shfl_xor(mx, off, WAVE));
+    tiny |= __shfl_xor(tiny, off, WAVE);
+  }
+  if ((threadIdx.x % WAVE) == 0) {
+    atomicMin(&st->min_piv, dbits(mn));
+    atomicMax(&st->max_piv, dbits(mx));
+    if (tiny) atomicOr(&st->tiny, 1);
+  }
+}
+
+__global__ void k_reset_stats(DevStats* st, int what) {
+  if (threadIdx.x == 0) {
+    if (what & 1) {
+      st->min_piv = dbits(__builtin_huge_val());
+      st->max_piv = 0ull;
+      st->anorm = 0ull;
+      st->anorm1 = 0ull;
+      st->tiny = 0;
+    }
+    if (what & 2) {
+      st->rmax = 0ull;
+      st->xmax = 0ull;
+    }
+    if (what & 4) {
+      st->anorm = 0ull;
+      st->anorm1 = 0ull;
+    }
+  }
+}
+
+// copy of A's values and ||A||_inf (wave per row)
+__global__ void k_copy_anorm(int n, const int* __restrict__ arow, const double* __restrict__ src,
+                             double* __restrict__ dst, DevStats* st) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
+  if (wave >= n) return;
+  double s = 0.0;
+  for (int p = arow[wave] + lane; p < arow[wave + 1]; p += WAVE) {
+    const double v = src[p];
+    dst[p] = v;
+    s += fabs(v);
+  }
+  s = wave_sum(s);
+  if (lane == 0) atomicMax(&st->anorm, dbits(fabs(s)));
+}
+
+__global__ void k_anorm1(int n, const int* __restrict__ cptr, const int* __restrict__ cpos,
+                         const double* __restrict__ aval, DevStats* st) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
+  if (wave >= n) return;
+  double s = 0.0;
+  for (int t = cptr[wave] + lane; t < cptr[wave + 1]; t += WAVE) s += fabs(aval[cpos[t]]);
+  s = wave_sum(s);
+  if (lane == 0) atomicMax(&st->anorm1, dbits(fabs(s)));
+}
+
+// ---------------------------------------------------------------------------
+// Triangular solves, one wavefront per row (level-synchronous launches).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_lsolve_rows(const int* __restrict__ rows, int nrows,
+                                                     const int* __restrict__ rowptr,
+                                                     const int* __restrict__ col,
+                                                     const int* __restrict__ diag,
+                                                     const double* __restrict__ val, double* y) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
+  if (wave >= nrows) return;
+  const int i = rows[wave];
+  double s = 0.0;
+  for (int q = rowptr[i] + lane; q < diag[i]; q += WAVE) s += val[q] * y[col[q]];
+  s = wave_sum(s);
+  if (lane == 0) y[i] -= s;
+}
+
+__global__ __launch_bounds__(256) void k_usolve_rows(const int* __restrict__ rows, int nrows,
+                                                     const int* __restrict__ rowptr,
+                                                     const int* __restrict__ col,
+                                                     const int* __restrict__ diag,
+                                                     const double* __restrict__ val, double* y) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
+  if (wave >= nrows) return;
+  const int i = rows[wave];
+  const int d = diag[i];
+  double s = 0.0;
+  for (int q = d + 1 + lane; q < rowptr[i + 1]; q += WAVE) s += val[q] * y[col[q]];
+  s = wave_sum(s);
+  if (lane == 0) y[i] = (y[i] - s) / val[d];
+}
+
+// U^T t = s: column j of U (rows i <= j, diagonal last)
+__global__ __launch_bounds__(256) void k_utsolve_cols(const int* __restrict__ cols, int ncols,
+                                                      const int* __restrict__ tptr,
+                                                      const int* __restrict__ trow,
+                                                      const int* __restrict__ tpos,
+                                                      const double* __restrict__ val, double* y) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
+  if (wave >= ncols) return;
+  const int j = cols[wave];
+  const int te = tptr[j + 1] - 1;  // diagonal
+  double s = 0.0;
+  for (int t = tptr[j] + lane; t < te; t += WAVE) s += val[tpos[t]] * y[trow[t]];
+  s = wave_sum(s);
+  if (lane == 0) y[j] = (y[j] - s) / val[tpos[te]];
+}
+
+// L^T w = t: column j of strict L (rows i > j)
+__global__ __launch_bounds__(256) void k_ltsolve_cols(const int* __restrict__ cols, int ncols,
+                                                      const int* __restrict__ tptr,
+                                                      const int* __restrict__ trow,
+                                                      const int* __restrict__ tpos,
+                                                      const double* __restrict__ val, double* y) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
+  if (wave >= ncols) return;
+  const int j = cols[wave];
+  double s = 0.0;
+  for (int t = tptr[j] + lane; t < tptr[j + 1]; t += WAVE) s += val[tpos[t]] * y[trow[t]];
+  s = wave_sum(s);
+  if (lane == 0) y[j] -= s;
+}
+
+__global__ void k_gather(int n, const int* __restrict__ perm, const double* __restrict__ x,
+                         double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[perm[i]];
+}
+__global__ void k_scatter(int n, const int* __restrict__ perm, const double* __restrict__ x,
+                          double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[perm[i]] = x[i];
+}
+
+// r = b - op(A) x, max |r|, max |x| (wave per row of op(A)); for op 'T' the
+// (ptr, idx, pos) triple is A's column view.
+__global__ __launch_bounds__(256) void k_residual(int n, const int* __restrict__ ptr,
+                                                  const int* __restrict__ idx,
+                                                  const int* __restrict__ pos,
+                                                  const double* __restrict__ aval,
+                                                  const double* __restrict__ b,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ r, DevStats* st) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
+  if (wave >= n) return;
+  double s = 0.0;
+  for (int t = ptr[wave] + lane; t < ptr[wave + 1]; t += WAVE)
+    s += aval[pos ? pos[t] : t] * x[idx[t]];
+  s = wave_sum(s);
+  if (lane == 0) {
+    const double ri = b[wave] - s;
+    if (r) r[wave] = ri;
+    atomicMax(&st->rmax, dbits(fabs(ri)));
+    atomicMax(&st->xmax, dbits(fabs(x[wave])));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ ptr,
+                                              const int* __restrict__ idx,
+                                              const int* __restrict__ pos,
+                                              const double* __restrict__ aval,
+                                              const double* __restrict__ x,
+                                              double* __restrict__ y) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
+  if (wave >= n) return;
+  double s = 0.0;
+  for (int t = ptr[wave] + lane; t < ptr[wave + 1]; t += WAVE)
+    s += aval[pos ? pos[t] : t] * x[idx[t]];
+  s = wave_sum(s);
+  if (lane == 0) y[wave] = s;
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES-CGS2 pieces
+// ---------------------------------------------------------------------------
+constexpr int MD_BLOCK = 256;
+constexpr int MD_MAXM = 32;
+constexpr int MD_GRID = 256;
+
+__global__ __launch_bounds__(MD_BLOCK) void k_multidot_partial(int n, int m,
+                                                               const double* __restrict__ V,
+                                                               long ld,
+                                                               const double* __restrict__ w,
+                                                               double* __restrict__ partial) {
+  __shared__ double red[MD_BLOCK / WAVE][MD_MAXM];
+  double acc[MD_MAXM];
+  for (int i = 0; i < m; i++) acc[i] = 0.0;
+  for (int t = blockIdx.x * MD_BLOCK + threadIdx.x; t < n; t += gridDim.x * MD_BLOCK) {
+    const double wt = w[t];
+    for (int i = 0; i < m; i++) acc[i] += V[(long)i * ld + t] * wt;
+  }
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  for (int i = 0; i < m; i++) {
+    const double s = wave_sum(acc[i]);
+    if (lane == 0) red[wave][i] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < m) {
+    double s = 0.0;
+    for (int q = 0; q < MD_BLOCK / WAVE; q++) s += red[q][threadIdx.x];
+    partial[blockIdx.x * MD_MAXM + threadIdx.x] = s;
+  }
+}
+
+__global__ void k_multidot_final(int m, int nblocks, const double* __restrict__ partial,
+                                 double* __restrict__ h) {
+  const int i = threadIdx.x;
+  if (i < m) {
+    double s = 0.0;
+    for (int b = 0; b < nblocks; b++) s += partial[b * MD_MAXM + i];
+    h[i] = s;
+  }
+}
+
+__global__ void k_multiaxpy(int n, int m, const double* __restrict__ V, long ld,
+                            const double* __restrict__ h, double* __restrict__ w) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double s = w[t];
+  for (int i = 0; i < m; i++) s -= h[i] * V[(long)i * ld + t];
+  w[t] = s;
+}
+
+__global__ void k_combine(int n, int m, const double* __restrict__ Z, long ld,
+                          const double* __restrict__ y, const double* __restrict__ base,
+                          double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double s = base[t];
+  for (int i = 0; i < m; i++) s += y[i] * Z[(long)i * ld + t];
+  out[t] = s;
+}
+
+__global__ void k_scale_div(int n, const double* __restrict__ x, const double* __restrict__ scal,
+                            double* __restrict__ y) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double d = scal[0];
+  y[t] = d > 0.0 ? x[t] / d : 0.0;
+}
+
+// Column j of the Hessenberg matrix from the two CGS passes (h + h2) and
+// ww = ||w||^2: store it, apply the earlier rotations, build rotation j,
+// update g and back-substitute y (j+1 entries).  *hn_out = ||w||.
+__global__ void k_givens(int j, int m, const double* __restrict__ h, const double* __restrict__ h2,
+                         const double* __restrict__ ww, double* H, double* cs, double* sn,
+                         double* g, double* y, double* hn_out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double* Hj = H + (long)j * (m + 1);
+  for (int i = 0; i <= j; i++) Hj[i] = h[i] + h2[i];
+  const double hn = sqrt(ww[0]);
+  hn_out[0] = hn;
+  Hj[j + 1] = hn;
+  for (int i = 0; i < j; i++) {
+    const double a = Hj[i], b = Hj[i + 1];
+    Hj[i] = cs[i] * a + sn[i] * b;
+    Hj[i + 1] = -sn[i] * a + cs[i] * b;
+  }
+  const double den = hypot(Hj[j], Hj[j + 1]);
+  cs[j] = den > 0.0 ? Hj[j] / den : 1.0;
+  sn[j] = den > 0.0 ? Hj[j + 1] / den : 0.0;
+  Hj[j] = den;
+  Hj[j + 1] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  for (int i = j; i >= 0; i--) {
+    double s = g[i];
+    for (int t = i + 1; t <= j; t++) s -= H[(long)t * (m + 1) + i] * y[t];
+    y[i] = s / H[(long)i * (m + 1) + i];
+  }
+}
+
+// rr = ||r||^2 on the device: g = (sqrt(rr), 0, ...), v0 = r / sqrt(rr)
+__global__ void k_arnoldi_start(int n, int m, const double* __restrict__ r,
+                                const double* __restrict__ rr, double* __restrict__ v0,
+                                double* __restrict__ g) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const double beta = sqrt(rr[0]);
+  if (t < n) v0[t] = beta > 0.0 ? r[t] / beta : 0.0;
+  if (t <= m) g[t] = t == 0 ? beta : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint on the pattern
+// ---------------------------------------------------------------------------
+__global__ void k_transpose(int rows, int cols, const double* __restrict__ in,
+                            double* __restrict__ out) {
+  // in: rows x cols column-major (ld = rows); out: cols x rows column-major
+  __shared__ double tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int r = bx + threadIdx.x, c = by + k;
+    if (r < rows && c < cols) tile[k][threadIdx.x] = in[(long)c * rows + r];
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int c = by + threadIdx.x, r = bx + k;
+    if (r < rows && c < cols) out[(long)r * cols + c] = tile[threadIdx.x][k];
+  }
+}
+
+// grad[p] = -sum_r lam[i][r] * x[j][r] for p = (i, j); lam, x row-major n x nrhs
+__global__ __launch_bounds__(256) void k_grad_sddmm(int n, int nrhs, const int* __restrict__ arow,
+                                                    const int* __restrict__ acol,
+                                                    const double* __restrict__ lam,
+                                                    const double* __restrict__ x,
+                                                    double* __restrict__ grad) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
+  if (wave >= n) return;
+  const int i = wave;
+  for (int p = arow[i]; p < arow[i + 1]; p++) {
+    const int j = acol[p];
+    double s = 0.0;
+    for (int r = lane; r < nrhs; r += WAVE) s += lam[(long)i * nrhs + r] * x[(long)j * nrhs + r];
+    s = wave_sum(s);
+    if (lane == 0) grad[p] = -s;
+  }
+}
+
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxlen,
+                          const double* aval, DevStats* st, double, hipStream_t s) {
+  (void)st;
+  if (nrows <= 0) return;
+  if (maxlen <= 128) {
+    constexpr int W = 4;
+    hipLaunchKernelGGL((k_refactor_rows_lds<128, W>), dim3(cdiv(nrows, W)), dim3(W * WAVE), 0, s,
+                       rows, nrows, lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val);
+  } else if (maxlen <= 1024) {
+    constexpr int W = 2;
+    hipLaunchKernelGGL((k_refactor_rows_lds<1024, W>), dim3(cdiv(nrows, W)), dim3(W * WAVE), 0, s,
+                       rows, nrows, lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val);
+  } else if (maxlen <= 4096) {
+    hipLaunchKernelGGL((k_refactor_rows_lds<4096, 1>), dim3(nrows), dim3(WAVE), 0, s, rows, nrows,
+                       lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val);
+  } else {
+    hipLaunchKernelGGL(k_refactor_rows_global, dim3(nrows), dim3(WAVE), 0, s, rows, nrows,
+                       lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val);
+  }
+}
+
+void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStream_t s) {
+  hipLaunchKernelGGL(k_pivot_stats, dim3(cdiv(lu.n, 256)), dim3(256), 0, s, lu.n, lu.diag, lu.val,
+                     st, tiny_rel);
+}
+
+void launch_copy_anorm(int n, const int* arow, const int*, const double* src, double* dst,
+                       DevStats* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_anorm, dim3(cdiv((long)n * WAVE, 256)), dim3(256), 0, s, n, arow, src,
+                     dst, st);
+}
+
+void launch_anorm1(int n, const int* cptr, const int* cpos, const double* aval, DevStats* st,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_anorm1, dim3(cdiv((long)n * WAVE, 256)), dim3(256), 0, s, n, cptr, cpos,
+                     aval, st);
+}
+
+void launch_reset_stats(DevStats* st, int what, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_stats, dim3(1), dim3(64), 0, s, st, what);
+}
+
+void launch_lsolve_rows(const LUView& lu, const int* rows, int nrows, int, double* y,
+                        hipStream_t s) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_lsolve_rows, dim3(cdiv((long)nrows * WAVE, 256)), dim3(256), 0, s, rows,
+                     nrows, lu.rowptr, lu.col, lu.diag, lu.val, y);
+}
+
+void launch_usolve_rows(const LUView& lu, const int* rows, int nrows, int, double* y,
+                        hipStream_t s) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_usolve_rows, dim3(cdiv((long)nrows * WAVE, 256)), dim3(256), 0, s, rows,
+                     nrows, lu.rowptr, lu.col, lu.diag, lu.val, y);
+}
+
+void launch_utsolve_cols(const LUView& lu, const int* cols, int ncols, const int* tptr,
+                         const int* trow, const int* tpos, double* y, hipStream_t s) {
+  if (ncols <= 0) return;
+  hipLaunchKernelGGL(k_utsolve_cols, dim3(cdiv((long)ncols * WAVE, 256)), dim3(256), 0, s, cols,
+                     ncols, tptr, trow, tpos, lu.val, y);
+}
+
+void launch_ltsolve_cols(const LUView& lu, const int* cols, int ncols, const int* tptr,
+                         const int* trow, const int* tpos, double* y, hipStream_t s) {
+  if (ncols <= 0) return;
+  hipLaunchKernelGGL(k_ltsolve_cols, dim3(cdiv((long)ncols * WAVE, 256)), dim3(256), 0, s, cols,
+                     ncols, tptr, trow, tpos, lu.val, y);
+}
+
+void launch_gather(int n, const int* perm, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather, dim3(cdiv(n, 256)), dim3(256), 0, s, n, perm, x, y);
+}
+void launch_scatter(int n, const int* perm, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter, dim3(cdiv(n, 256)), dim3(256), 0, s, n, perm, x, y);
+}
+
+void launch_residual(int n, char, const int* ptr, const int* idx, const int* pos,
+                     const double* aval, const double* b, const double* x, double* r, DevStats* st,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_residual, dim3(cdiv((long)n * WAVE, 256)), dim3(256), 0, s, n, ptr, idx,
+                     pos, aval, b, x, r, st);
+}
+
+void launch_spmv(int n, char, const int* ptr, const int* idx, const int* pos, const double* aval,
+                 const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_spmv, dim3(cdiv((long)n * WAVE, 256)), dim3(256), 0, s, n, ptr, idx, pos,
+                     aval, x, y);
+}
+
+void launch_multidot(int n, int m, const double* V, long ld, const double* w, double* partial,
+                     double* h, hipStream_t s) {
+  const int grid = std::min(MD_GRID, cdiv(n, MD_BLOCK));
+  hipLaunchKernelGGL(k_multidot_partial, dim3(grid), dim3(MD_BLOCK), 0, s, n, m, V, ld, w,
+                     partial);
+  hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(64), 0, s, m, grid, partial, h);
+}
+
+void launch_multiaxpy(int n, int m, const double* V, long ld, const double* h, double* w,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_multiaxpy, dim3(cdiv(n, 256)), dim3(256), 0, s, n, m, V, ld, h, w);
+}
+
+void launch_combine(int n, int m, const double* Z, long ld, const double* y, const double* base,
+                    double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine, dim3(cdiv(n, 256)), dim3(256), 0, s, n, m, Z, ld, y, base, out);
+}
+
+void launch_scale_div(int n, const double* x, const double* scal, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_div, dim3(cdiv(n, 256)), dim3(256), 0, s, n, x, scal, y);
+}
+
+void launch_givens(int j, int m, const double* h, const double* h2, const double* ww, double* H,
+                   double* cs, double* sn, double* g, double* y, double* hn_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, j, m, h, h2, ww, H, cs, sn, g, y, hn_out);
+}
+
+void launch_arnoldi_start(int n, int m, const double* r, const double* rr, double* v0, double* g,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_arnoldi_start, dim3(cdiv(std::max(n, m + 1), 256)), dim3(256), 0, s, n, m,
+                     r, rr, v0, g);
+}
+
+void launch_transpose(int rows, int cols, const double* in, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose, dim3(cdiv(rows, 32), cdiv(cols, 32)), dim3(32, 8), 0, s, rows,
+                     cols, in, out);
+}
+
+void launch_grad_sddmm(int n, int nrhs, const int* arow_ptr, const int* acol,
+                       const double* lam_rm, const double* x_rm, double* grad, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_sddmm, dim3(cdiv((long)n * WAVE, 256)), dim3(256), 0, s, n, nrhs,
+                     arow_ptr, acol, lam_rm, x_rm, grad);
+}
+
+}  // namespace kktlu

@@ -1,0 +1,633 @@
+// Handle, device workspaces and the C ABI of include/kkt_lu.h.
+//
+// Everything the GPU needs is uploaded once by kkt_analyze and reused by
+// every refactorization and solve (the paper moves the system to the GPU once
+// and keeps Krylov vectors and buffers allocated across systems, Sections 5
+// and 5.1.2).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/kkt_lu.h"
+#include "analyze.h"
+#include "kernels.h"
+
+using namespace kktlu;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct kkt_ctx {
+  kkt_options opt;
+  std::string err;
+  bool analyzed = false;
+  bool factored = false;
+  Analysis an;
+  double analyze_seconds = 0.0;
+  std::vector<DevBuf> bufs;
+  int64_t device_bytes = 0;
+  // factors and maps
+  int *lu_rowptr = nullptr, *lu_col = nullptr, *diag = nullptr, *lu_src = nullptr;
+  double* lu_val = nullptr;
+  int *lev_rows = nullptr, *ulev_rows = nullptr, *utlev_rows = nullptr, *ltlev_rows = nullptr;
+  int *ut_ptr = nullptr, *ut_row = nullptr, *ut_pos = nullptr;
+  int *lt_ptr = nullptr, *lt_row = nullptr, *lt_pos = nullptr;
+  int *pin = nullptr, *qperm = nullptr;  // pin[i] = Q[P[i]], qperm[k] = Q[k]
+  // A (CSR, column view) and the current values
+  int *a_rowptr = nullptr, *a_col = nullptr, *at_ptr = nullptr, *at_row = nullptr,
+      *at_pos = nullptr;
+  double* aval = nullptr;
+  bool anorm1_valid = false;
+  // statistics
+  DevStats* st = nullptr;
+  DevStats* h_st = nullptr;  // pinned
+  // refinement workspace
+  int m = 20;
+  double *V = nullptr, *Z = nullptr, *w = nullptr, *r = nullptr, *xt = nullptr, *tmp = nullptr;
+  double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *h = nullptr, *h2 = nullptr,
+         *ww = nullptr, *y = nullptr, *hn = nullptr, *partial = nullptr;
+  // adjoint scratch
+  double *lam_rm = nullptr, *x_rm = nullptr;
+  int adj_cap = 0;
+  // report
+  int warnings = 0;
+  int last_iters = 0;
+  double last_eta = 0.0, last_eta0 = 0.0;
+};
+
+namespace {
+
+kkt_status fail(kkt_handle h, kkt_status st, const std::string& msg) {
+  if (h) h->err = msg;
+  return st;
+}
+
+#define HIP_CHECK(h, call)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(h, KKT_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+void free_device(kkt_handle h) {
+  for (auto& b : h->bufs) hipFree(b.p);
+  h->bufs.clear();
+  h->device_bytes = 0;
+  if (h->h_st) hipHostFree(h->h_st);
+  h->h_st = nullptr;
+  h->lam_rm = h->x_rm = nullptr;
+  h->adj_cap = 0;
+  h->analyzed = h->factored = false;
+}
+
+template <typename T>
+kkt_status dalloc(kkt_handle h, T** out, size_t count) {
+  void* p = nullptr;
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    *out = nullptr;
+    return fail(h, e == hipErrorOutOfMemory ? KKT_ERR_OUT_OF_MEMORY : KKT_ERR_DEVICE,
+                std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  h->bufs.push_back({p, bytes});
+  h->device_bytes += (int64_t)bytes;
+  *out = (T*)p;
+  return KKT_OK;
+}
+
+template <typename T>
+kkt_status upload(kkt_handle h, T** out, const std::vector<T>& v) {
+  kkt_status st = dalloc(h, out, v.size());
+  if (st != KKT_OK) return st;
+  if (!v.empty()) HIP_CHECK(h, hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return KKT_OK;
+}
+
+double bits_to_double(unsigned long long b) {
+  double d;
+  std::memcpy(&d, &b, sizeof d);
+  return d;
+}
+
+LUView view(kkt_handle h) {
+  return LUView{h->an.n, h->lu_rowptr, h->lu_col, h->diag, h->lu_src, h->lu_val};
+}
+
+// M^{-1} b through the factors: x = Q U^{-1} L^{-1} P Q^T b ('N') or the
+// transposed chain ('T').  b and x may not alias h->tmp.
+void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_t s) {
+  const Analysis& A = h->an;
+  const int n = A.n;
+  LUView lu = view(h);
+  if (op == 'N') {
+    launch_gather(n, h->pin, b, h->tmp, s);
+    for (size_t l = 0; l + 1 < A.lev_ptr.size(); l++)
+      launch_lsolve_rows(lu, h->lev_rows + A.lev_ptr[l], A.lev_ptr[l + 1] - A.lev_ptr[l], 0,
+                         h->tmp, s);
+    for (size_t l = 0; l + 1 < A.ulev_ptr.size(); l++)
+      launch_usolve_rows(lu, h->ulev_rows + A.ulev_ptr[l], A.ulev_ptr[l + 1] - A.ulev_ptr[l], 0,
+                         h->tmp, s);
+    launch_scatter(n, h->qperm, h->tmp, x, s);
+  } else {
+    launch_gather(n, h->qperm, b, h->tmp, s);
+    for (size_t l = 0; l + 1 < A.utlev_ptr.size(); l++)
+      launch_utsolve_cols(lu, h->utlev_rows + A.utlev_ptr[l], A.utlev_ptr[l + 1] - A.utlev_ptr[l],
+                          h->ut_ptr, h->ut_row, h->ut_pos, h->tmp, s);
+    for (size_t l = 0; l + 1 < A.ltlev_ptr.size(); l++)
+      launch_ltsolve_cols(lu, h->ltlev_rows + A.ltlev_ptr[l], A.ltlev_ptr[l + 1] - A.ltlev_ptr[l],
+                          h->lt_ptr, h->lt_row, h->lt_pos, h->tmp, s);
+    launch_scatter(n, h->pin, h->tmp, x, s);
+  }
+}
+
+void op_spmv(kkt_handle h, char op, const double* x, double* y, hipStream_t s) {
+  if (op == 'N')
+    launch_spmv(h->an.n, 'N', h->a_rowptr, h->a_col, nullptr, h->aval, x, y, s);
+  else
+    launch_spmv(h->an.n, 'T', h->at_ptr, h->at_row, h->at_pos, h->aval, x, y, s);
+}
+
+// r = b - op(A) x; returns eta (synchronises the stream)
+kkt_status residual_eta(kkt_handle h, char op, const double* b, const double* x, double* r,
+                        hipStream_t s, double* eta) {
+  launch_reset_stats(h->st, 2, s);
+  if (op == 'N')
+    launch_residual(h->an.n, 'N', h->a_rowptr, h->a_col, nullptr, h->aval, b, x, r, h->st, s);
+  else
+    launch_residual(h->an.n, 'T', h->at_ptr, h->at_row, h->at_pos, h->aval, b, x, r, h->st, s);
+  HIP_CHECK(h, hipMemcpyAsync(h->h_st, h->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(h, hipStreamSynchronize(s));
+  const double rn = bits_to_double(h->h_st->rmax), xn = bits_to_double(h->h_st->xmax);
+  const double an = bits_to_double(op == 'N' ? h->h_st->anorm : h->h_st->anorm1);
+  const double den = an * xn;
+  *eta = den == 0.0 ? (rn == 0.0 ? 0.0 : INFINITY) : rn / den;
+  return KKT_OK;
+}
+
+// Direct solve and FGMRES-CGS2 refinement of one right-hand side.
+kkt_status solve_one(kkt_handle h, char op, const double* b, double* x, hipStream_t s,
+                     int* iters_out, double* eta_out, double* eta0_out) {
+  const int n = h->an.n, m = h->m;
+  const kkt_options& o = h->opt;
+  apply_factors(h, op, b, x, s);
+  double eta;
+  kkt_status st = residual_eta(h, op, b, x, h->r, s, &eta);
+  if (st != KKT_OK) return st;
+  *eta0_out = eta;
+  int it = 0;
+  bool done = eta <= o.eta_target && it >= o.min_iters;
+  bool at_xt = false;
+  while (!done && it < o.fgmres_max_iters) {
+    launch_multidot(n, 1, h->r, n, h->r, h->partial, h->ww, s);
+    launch_arnoldi_start(n, m, h->r, h->ww, h->V, h->g, s);
+    bool breakdown = false;
+    for (int j = 0; j < m && it < o.fgmres_max_iters; j++) {
+      double* vj = h->V + (long)j * n;
+      double* zj = h->Z + (long)j * n;
+      apply_factors(h, op, vj, zj, s);
+      op_spmv(h, op, zj, h->w, s);
+      launch_multidot(n, j + 1, h->V, n, h->w, h->partial, h->h, s);
+      launch_multiaxpy(n, j + 1, h->V, n, h->h, h->w, s);
+      launch_multidot(n, j + 1, h->V, n, h->w, h->partial, h->h2, s);
+      launch_multiaxpy(n, j + 1, h->V, n, h->h2, h->w, s);
+      launch_multidot(n, 1, h->w, n, h->w, h->partial, h->ww, s);
+      launch_givens(j, m, h->h, h->h2, h->ww, h->H, h->cs, h->sn, h->g, h->y, h->hn, s);
+      launch_scale_div(n, h->w, h->hn, h->V + (long)(j + 1) * n, s);
+      launch_combine(n, j + 1, h->Z, n, h->y, x, h->xt, s);
+      it++;
+      st = residual_eta(h, op, b, h->xt, h->r, s, &eta);
+      if (st != KKT_OK) return st;
+      at_xt = true;
+      double hn;
+      HIP_CHECK(h, hipMemcpy(&hn, h->hn, sizeof(double), hipMemcpyDeviceToHost));
+      if (eta <= o.eta_target && it >= o.min_iters) {
+        done = true;
+        break;
+      }
+      if (!(hn > 0.0)) {
+        breakdown = true;
+        break;
+      }
+    }
+    // restart from the current iterate (r already holds its residual)
+    if (at_xt) {
+      HIP_CHECK(h, hipMemcpyAsync(x, h->xt, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      at_xt = false;
+    }
+    if (breakdown) break;
+  }
+  if (at_xt)
+    HIP_CHECK(h, hipMemcpyAsync(x, h->xt, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  *iters_out = it;
+  *eta_out = eta;
+  return (eta <= o.eta_target) ? KKT_OK : KKT_WARN_NOT_CONVERGED;
+}
+
+}  // namespace
+
+extern "C" {
+
+void kkt_options_default(kkt_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->ordering = 0;
+  o->pivot_tau = 1e-10;
+  o->fgmres_restart = 20;
+  o->fgmres_max_iters = 20;
+  o->min_iters = 0;
+  o->eta_target = 1e-12;
+  o->tiny_pivot_rel = 1e-18;
+  o->device = 0;
+  o->schedule = 0;
+}
+
+kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
+  if (!out) return KKT_ERR_INVALID_ARG;
+  *out = nullptr;
+  kkt_options o;
+  kkt_options_default(&o);
+  if (opt) o = *opt;
+  if (o.ordering < 0 || o.ordering > 2 || !(o.pivot_tau > 0.0 && o.pivot_tau <= 1.0) ||
+      o.fgmres_restart < 1 || o.fgmres_restart > 30 || o.fgmres_max_iters < 0 ||
+      o.min_iters < 0 || !(o.eta_target >= 0.0) || !(o.tiny_pivot_rel >= 0.0) || o.device < 0 ||
+      o.schedule < 0 || o.schedule > 2)
+    return KKT_ERR_INVALID_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) return KKT_ERR_DEVICE;
+  kkt_ctx* h = new (std::nothrow) kkt_ctx();
+  if (!h) return KKT_ERR_OUT_OF_MEMORY;
+  h->opt = o;
+  h->m = o.fgmres_restart;
+  *out = h;
+  return KKT_OK;
+}
+
+kkt_status kkt_destroy(kkt_handle h) {
+  if (!h) return KKT_ERR_INVALID_ARG;
+  hipSetDevice(h->opt.device);
+  hipDeviceSynchronize();
+  free_device(h);
+  delete h;
+  return KKT_OK;
+}
+
+kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowptr,
+                       const int32_t* colind, const double* values0, const int32_t* user_q) {
+  if (!h) return KKT_ERR_INVALID_ARG;
+  h->err.clear();
+  if (nnz > (int64_t)INT32_MAX) return fail(h, KKT_ERR_TOO_LARGE, "nnz(A) exceeds int32");
+  auto t0 = std::chrono::steady_clock::now();
+  AnalyzeOptions ao;
+  ao.ordering = h->opt.ordering;
+  ao.tau = h->opt.pivot_tau;
+  Analysis an;
+  std::string msg;
+  int st;
+  try {
+    st = analyze(n, nnz, rowptr, colind, values0, user_q, ao, an, &msg);
+  } catch (const std::bad_alloc&) {
+    return fail(h, KKT_ERR_OUT_OF_MEMORY, "host allocation failed in analyze");
+  }
+  if (st < 0) return fail(h, (kkt_status)st, msg);
+  HIP_CHECK(h, hipSetDevice(h->opt.device));
+  HIP_CHECK(h, hipDeviceSynchronize());
+  free_device(h);
+  h->an = std::move(an);
+  const Analysis& A = h->an;
+  kkt_status ks;
+#define UP(dst, vec)                   \
+  if ((ks = upload(h, &dst, vec)) != KKT_OK) { \
+    free_device(h);                    \
+    return ks;                         \
+  }
+  UP(h->lu_rowptr, A.lu_rowptr);
+  UP(h->lu_col, A.lu_col);
+  UP(h->diag, A.diag);
+  UP(h->lu_src, A.lu_src);
+  UP(h->lev_rows, A.lev_rows);
+  UP(h->ulev_rows, A.ulev_rows);
+  UP(h->utlev_rows, A.utlev_rows);
+  UP(h->ltlev_rows, A.ltlev_rows);
+  UP(h->ut_ptr, A.ut_ptr);
+  UP(h->ut_pos, A.ut_pos);
+  UP(h->lt_ptr, A.lt_ptr);
+  UP(h->lt_pos, A.lt_pos);
+  {
+    // row index of every transposed-view position
+    std::vector<int32_t> rowof(A.lu_col.size());
+    for (int32_t i = 0; i < n; i++)
+      for (int32_t q = A.lu_rowptr[i]; q < A.lu_rowptr[i + 1]; q++) rowof[q] = i;
+    std::vector<int32_t> ur(A.ut_pos.size()), lr(A.lt_pos.size());
+    for (size_t t = 0; t < ur.size(); t++) ur[t] = rowof[A.ut_pos[t]];
+    for (size_t t = 0; t < lr.size(); t++) lr[t] = rowof[A.lt_pos[t]];
+    UP(h->ut_row, ur);
+    UP(h->lt_row, lr);
+    std::vector<int32_t> pin(n), q(A.Q);
+    for (int32_t i = 0; i < n; i++) pin[i] = A.Q[A.P[i]];
+    UP(h->pin, pin);
+    UP(h->qperm, q);
+    // A pattern (int32 row pointers) and its column view
+    std::vector<int32_t> arp(n + 1), acol(colind, colind + nnz);
+    for (int32_t i = 0; i <= n; i++) arp[i] = (int32_t)rowptr[i];
+    std::vector<int32_t> atp(n + 1, 0), atr(nnz), atpos(nnz);
+    for (int64_t p = 0; p < nnz; p++) atp[colind[p] + 1]++;
+    for (int32_t j = 0; j < n; j++) atp[j + 1] += atp[j];
+    std::vector<int32_t> nx(atp.begin(), atp.end() - 1);
+    for (int32_t i = 0; i < n; i++)
+      for (int64_t p = rowptr[i]; p < rowptr[i + 1]; p++) {
+        int32_t t = nx[colind[p]]++;
+        atr[t] = i;
+        atpos[t] = (int32_t)p;
+      }
+    UP(h->a_rowptr, arp);
+    UP(h->a_col, acol);
+    UP(h->at_ptr, atp);
+    UP(h->at_row, atr);
+    UP(h->at_pos, atpos);
+  }
+#undef UP
+  const size_t f = A.lu_col.size();
+  const int m = h->m;
+  if ((ks = dalloc(h, &h->lu_val, f)) != KKT_OK || (ks = dalloc(h, &h->aval, nnz)) != KKT_OK ||
+      (ks = dalloc(h, &h->st, 1)) != KKT_OK ||
+      (ks = dalloc(h, &h->V, (size_t)(m + 1) * n)) != KKT_OK ||
+      (ks = dalloc(h, &h->Z, (size_t)m * n)) != KKT_OK || (ks = dalloc(h, &h->w, n)) != KKT_OK ||
+      (ks = dalloc(h, &h->r, n)) != KKT_OK || (ks = dalloc(h, &h->xt, n)) != KKT_OK ||
+      (ks = dalloc(h, &h->tmp, n)) != KKT_OK ||
+      (ks = dalloc(h, &h->H, (size_t)(m + 1) * m)) != KKT_OK ||
+      (ks = dalloc(h, &h->cs, m + 1)) != KKT_OK || (ks = dalloc(h, &h->sn, m + 1)) != KKT_OK ||
+      (ks = dalloc(h, &h->g, m + 1)) != KKT_OK || (ks = dalloc(h, &h->h, m + 1)) != KKT_OK ||
+      (ks = dalloc(h, &h->h2, m + 1)) != KKT_OK || (ks = dalloc(h, &h->ww, 1)) != KKT_OK ||
+      (ks = dalloc(h, &h->y, m + 1)) != KKT_OK || (ks = dalloc(h, &h->hn, 1)) != KKT_OK ||
+      (ks = dalloc(h, &h->partial, 256 * 32)) != KKT_OK) {
+    free_device(h);
+    return ks;
+  }
+  // the pivoting pass's factors are the current factors until the first refactor
+  HIP_CHECK(h, hipMemcpy(h->lu_val, A.lu_val0.data(), f * sizeof(double), hipMemcpyHostToDevice));
+  HIP_CHECK(h, hipMemcpy(h->aval, values0, (size_t)nnz * sizeof(double), hipMemcpyHostToDevice));
+  HIP_CHECK(h, hipHostMalloc((void**)&h->h_st, sizeof(DevStats), hipHostMallocDefault));
+  launch_reset_stats(h->st, 3, nullptr);
+  launch_copy_anorm(n, h->a_rowptr, h->a_col, h->aval, h->aval, h->st, nullptr);
+  launch_pivot_stats(view(h), h->st, h->opt.tiny_pivot_rel, nullptr);
+  HIP_CHECK(h, hipGetLastError());
+  HIP_CHECK(h, hipDeviceSynchronize());
+  h->anorm1_valid = false;
+  h->analyzed = true;
+  h->factored = true;
+  h->warnings = st > 0 ? (1 << st) : 0;
+  h->analyze_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return (kkt_status)st;
+}
+
+kkt_status kkt_refactor(kkt_handle h, const double* d_values, void* stream) {
+  if (!h) return KKT_ERR_INVALID_ARG;
+  if (!h->analyzed) return fail(h, KKT_ERR_STATE, "kkt_refactor before kkt_analyze");
+  if (!d_values) return fail(h, KKT_ERR_INVALID_ARG, "d_values is NULL");
+  HIP_CHECK(h, hipSetDevice(h->opt.device));
+  hipStream_t s = (hipStream_t)stream;
+  const Analysis& A = h->an;
+  LUView lu = view(h);
+  launch_reset_stats(h->st, 1, s);
+  launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s);
+  for (size_t l = 0; l + 1 < A.lev_ptr.size(); l++)
+    launch_refactor_rows(lu, h->lev_rows + A.lev_ptr[l], A.lev_ptr[l + 1] - A.lev_ptr[l],
+                         A.lev_maxlen[l], h->aval, h->st, 0.0, s);
+  launch_pivot_stats(lu, h->st, h->opt.tiny_pivot_rel, s);
+  HIP_CHECK(h, hipGetLastError());
+  h->anorm1_valid = false;
+  h->factored = true;
+  return KKT_OK;
+}
+
+kkt_status kkt_update_matrix(kkt_handle h, const double* d_values, void* stream) {
+  if (!h) return KKT_ERR_INVALID_ARG;
+  if (!h->analyzed) return fail(h, KKT_ERR_STATE, "kkt_update_matrix before kkt_analyze");
+  if (!d_values) return fail(h, KKT_ERR_INVALID_ARG, "d_values is NULL");
+  HIP_CHECK(h, hipSetDevice(h->opt.device));
+  hipStream_t s = (hipStream_t)stream;
+  // keep the pivot statistics of the current factors, recompute ||A||_inf
+  launch_reset_stats(h->st, 4, s);
+  launch_copy_anorm(h->an.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s);
+  HIP_CHECK(h, hipGetLastError());
+  h->anorm1_valid = false;
+  return KKT_OK;
+}
+
+kkt_status kkt_solve(kkt_handle h, char op, int32_t nrhs, const double* d_b, double* d_x,
+                     void* stream) {
+  if (!h) return KKT_ERR_INVALID_ARG;
+  if (!h->factored) return fail(h, KKT_ERR_STATE, "kkt_solve before kkt_analyze");
+  if ((op != 'N' && op != 'T') || nrhs < 0 || (nrhs > 0 && (!d_b || !d_x)))
+    return fail(h, KKT_ERR_INVALID_ARG, "bad op, nrhs or pointer");
+  const int n = h->an.n;
+  if (nrhs > 0 && d_b < d_x + (size_t)nrhs * n && d_x < d_b + (size_t)nrhs * n)
+    return fail(h, KKT_ERR_INVALID_ARG, "d_b and d_x overlap");
+  HIP_CHECK(h, hipSetDevice(h->opt.device));
+  hipStream_t s = (hipStream_t)stream;
+  if (op == 'T' && !h->anorm1_valid) {
+    launch_anorm1(n, h->at_ptr, h->at_pos, h->aval, h->st, s);
+    h->anorm1_valid = true;
+  }
+  kkt_status worst = KKT_OK;
+  int itmax = 0;
+  double emax = 0.0, e0max = 0.0;
+  for (int c = 0; c < nrhs; c++) {
+    int it;
+    double eta, eta0;
+    kkt_status st = solve_one(h, op, d_b + (size_t)c * n, d_x + (size_t)c * n, s, &it, &eta, &eta0);
+    if (st < 0) return st;
+    if (st > 0) worst = st;
+    itmax = std::max(itmax, it);
+    if (!(eta <= emax)) emax = eta;
+    if (!(eta0 <= e0max)) e0max = eta0;
+  }
+  HIP_CHECK(h, hipGetLastError());
+  h->last_iters = itmax;
+  h->last_eta = emax;
+  h->last_eta0 = e0max;
+  if (worst > 0) h->warnings |= 1 << worst;
+  return worst;
+}
+
+kkt_status kkt_grad_values(kkt_handle h, int32_t nrhs, const double* d_lambda, const double* d_x,
+                           double* d_grad, void* stream) {
+  if (!h) return KKT_ERR_INVALID_ARG;
+  if (!h->analyzed) return fail(h, KKT_ERR_STATE, "kkt_grad_values before kkt_analyze");
+  if (nrhs <= 0 || !d_lambda || !d_x || !d_grad)
+    return fail(h, KKT_ERR_INVALID_ARG, "bad nrhs or pointer");
+  HIP_CHECK(h, hipSetDevice(h->opt.device));
+  hipStream_t s = (hipStream_t)stream;
+  const int n = h->an.n;
+  if (h->adj_cap < nrhs) {
+    kkt_status ks;
+    if ((ks = dalloc(h, &h->lam_rm, (size_t)n * nrhs)) != KKT_OK) return ks;
+    if ((ks = dalloc(h, &h->x_rm, (size_t)n * nrhs)) != KKT_OK) return ks;
+    h->adj_cap = nrhs;
+  }
+  launch_transpose(n, nrhs, d_lambda, h->lam_rm, s);
+  launch_transpose(n, nrhs, d_x, h->x_rm, s);
+  launch_grad_sddmm(n, nrhs, h->a_rowptr, h->a_col, h->lam_rm, h->x_rm, d_grad, s);
+  HIP_CHECK(h, hipGetLastError());
+  return KKT_OK;
+}
+
+kkt_status kkt_sync_report(kkt_handle h, kkt_report* out) {
+  if (!h || !out) return KKT_ERR_INVALID_ARG;
+  if (!h->analyzed) return fail(h, KKT_ERR_STATE, "no analysis");
+  HIP_CHECK(h, hipSetDevice(h->opt.device));
+  HIP_CHECK(h, hipDeviceSynchronize());
+  DevStats d;
+  HIP_CHECK(h, hipMemcpy(&d, h->st, sizeof d, hipMemcpyDeviceToHost));
+  int warn = h->warnings;
+  if (d.tiny) warn |= 1 << KKT_WARN_TINY_PIVOT;
+  out->warnings = warn;
+  out->iters = h->last_iters;
+  out->eta = h->last_eta;
+  out->eta0 = h->last_eta0;
+  out->min_pivot = bits_to_double(d.min_piv);
+  out->max_pivot = bits_to_double(d.max_piv);
+  out->anorm_inf = bits_to_double(d.anorm);
+  h->warnings = 0;
+  return KKT_OK;
+}
+
+kkt_status kkt_get_info(kkt_handle h, kkt_info* out) {
+  if (!h || !out) return KKT_ERR_INVALID_ARG;
+  if (!h->analyzed) return fail(h, KKT_ERR_STATE, "no analysis");
+  const Analysis& A = h->an;
+  out->n = A.n;
+  out->nnz = A.nnz;
+  out->nnz_l = A.nnz_l;
+  out->nnz_u = A.nnz_u;
+  out->levels = (int32_t)A.lev_ptr.size() - 1;
+  out->levels_u = (int32_t)A.ulev_ptr.size() - 1;
+  out->analyze_status = A.warn_singular ? KKT_WARN_NUMERICALLY_SINGULAR : KKT_OK;
+  out->device_bytes = h->device_bytes;
+  out->analyze_seconds = h->analyze_seconds;
+  return KKT_OK;
+}
+
+kkt_status kkt_get_perm(kkt_handle h, int32_t* p, int32_t* q) {
+  if (!h) return KKT_ERR_INVALID_ARG;
+  if (!h->analyzed) return fail(h, KKT_ERR_STATE, "no analysis");
+  if (p) std::memcpy(p, h->an.P.data(), h->an.P.size() * sizeof(int32_t));
+  if (q) std::memcpy(q, h->an.Q.data(), h->an.Q.size() * sizeof(int32_t));
+  return KKT_OK;
+}
+
+kkt_status kkt_get_lu(kkt_handle h, int64_t* rowptr, int32_t* colind, double* values) {
+  if (!h) return KKT_ERR_INVALID_ARG;
+  if (!h->analyzed) return fail(h, KKT_ERR_STATE, "no analysis");
+  const Analysis& A = h->an;
+  if (rowptr)
+    for (size_t i = 0; i < A.lu_rowptr.size(); i++) rowptr[i] = A.lu_rowptr[i];
+  if (colind) std::memcpy(colind, A.lu_col.data(), A.lu_col.size() * sizeof(int32_t));
+  if (values) {
+    HIP_CHECK(h, hipSetDevice(h->opt.device));
+    HIP_CHECK(h, hipDeviceSynchronize());
+    HIP_CHECK(h, hipMemcpy(values, h->lu_val, A.lu_col.size() * sizeof(double),
+                           hipMemcpyDeviceToHost));
+  }
+  return KKT_OK;
+}
+
+const char* kkt_last_error(kkt_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+}  // extern "C"
+
+struct kkt_host_analysis {
+  Analysis an;
+};
+
+extern "C" {
+
+kkt_status kkt_analysis_create(const kkt_options* opt, int32_t n, int64_t nnz,
+                               const int64_t* rowptr, const int32_t* colind,
+                               const double* values0, const int32_t* user_q, kkt_analysis* out,
+                               char* msg, int32_t msg_len) {
+  if (!out) return KKT_ERR_INVALID_ARG;
+  *out = nullptr;
+  kkt_options o;
+  kkt_options_default(&o);
+  if (opt) o = *opt;
+  AnalyzeOptions ao;
+  ao.ordering = o.ordering;
+  ao.tau = o.pivot_tau;
+  kkt_host_analysis* a = new (std::nothrow) kkt_host_analysis();
+  if (!a) return KKT_ERR_OUT_OF_MEMORY;
+  std::string m;
+  int st;
+  try {
+    st = analyze(n, nnz, rowptr, colind, values0, user_q, ao, a->an, &m);
+  } catch (const std::bad_alloc&) {
+    st = KKT_ERR_OUT_OF_MEMORY;
+    m = "host allocation failed";
+  }
+  if (st < 0) {
+    delete a;
+    if (msg && msg_len > 0) {
+      std::strncpy(msg, m.c_str(), (size_t)msg_len - 1);
+      msg[msg_len - 1] = 0;
+    }
+    return (kkt_status)st;
+  }
+  *out = a;
+  return (kkt_status)st;
+}
+
+kkt_status kkt_analysis_info(kkt_analysis a, kkt_info* out) {
+  if (!a || !out) return KKT_ERR_INVALID_ARG;
+  const Analysis& A = a->an;
+  std::memset(out, 0, sizeof(*out));
+  out->n = A.n;
+  out->nnz = A.nnz;
+  out->nnz_l = A.nnz_l;
+  out->nnz_u = A.nnz_u;
+  out->levels = (int32_t)A.lev_ptr.size() - 1;
+  out->levels_u = (int32_t)A.ulev_ptr.size() - 1;
+  out->analyze_status = A.warn_singular ? KKT_WARN_NUMERICALLY_SINGULAR : KKT_OK;
+  return KKT_OK;
+}
+
+kkt_status kkt_analysis_perm(kkt_analysis a, int32_t* p, int32_t* q) {
+  if (!a) return KKT_ERR_INVALID_ARG;
+  if (p) std::memcpy(p, a->an.P.data(), a->an.P.size() * sizeof(int32_t));
+  if (q) std::memcpy(q, a->an.Q.data(), a->an.Q.size() * sizeof(int32_t));
+  return KKT_OK;
+}
+
+kkt_status kkt_analysis_lu(kkt_analysis a, int64_t* rowptr, int32_t* colind, double* values) {
+  if (!a) return KKT_ERR_INVALID_ARG;
+  const Analysis& A = a->an;
+  if (rowptr)
+    for (size_t i = 0; i < A.lu_rowptr.size(); i++) rowptr[i] = A.lu_rowptr[i];
+  if (colind) std::memcpy(colind, A.lu_col.data(), A.lu_col.size() * sizeof(int32_t));
+  if (values) std::memcpy(values, A.lu_val0.data(), A.lu_val0.size() * sizeof(double));
+  return KKT_OK;
+}
+
+kkt_status kkt_analysis_levels(kkt_analysis a, int32_t* level_ptr, int32_t* rows) {
+  if (!a) return KKT_ERR_INVALID_ARG;
+  const Analysis& A = a->an;
+  if (level_ptr) std::memcpy(level_ptr, A.lev_ptr.data(), A.lev_ptr.size() * sizeof(int32_t));
+  if (rows) std::memcpy(rows, A.lev_rows.data(), A.lev_rows.size() * sizeof(int32_t));
+  return KKT_OK;
+}
+
+void kkt_analysis_destroy(kkt_analysis a) { delete a; }
+
+}  // extern "C"

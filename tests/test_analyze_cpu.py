@@ -1,0 +1,182 @@
+"""Host analysis of the product library vs the oracle (CPU only).
+
+The ordering, the pivot sequence and the L/U patterns must match bit for bit,
+and so must the pivoting pass's factor values (both sides apply the updates of
+each entry in ascending pivot order with fma).  Also: the ABI exports and the
+error paths of the analysis.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_14337_amd import binding, kktgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def oracle_combined_csr(lu: oracle.OracleLU):
+    """Oracle factors as one CSR in pivot order: L(i,:i), u_ii, U(i,i+1:)."""
+    f = lu.factors()
+    n = lu.n
+    rows = np.concatenate([f["Li"], f["Ui"]])
+    cols = np.concatenate([np.repeat(np.arange(n), np.diff(f["Lp"])),
+                           np.repeat(np.arange(n), np.diff(f["Up"]))])
+    vals = np.concatenate([f["Lx"], f["Ux"]])
+    order = np.lexsort((cols, rows))
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, rows + 1, 1)
+    return f["P"], f["Q"], np.cumsum(rp), cols[order].astype(np.int32), vals[order]
+
+
+def compare(n, rp, ci, v, tau, user_q=None):
+    ordering = 2 if user_q is not None else 0
+    ha = binding.HostAnalysis(n, rp, ci, v, user_q=user_q, pivot_tau=tau, ordering=ordering)
+    lu = oracle.OracleLU(n, rp, ci, v, Q=user_q, tau=tau)
+    P0, Q0, rp0, ci0, v0 = oracle_combined_csr(lu)
+    P1, Q1 = ha.perm()
+    rp1, ci1, v1 = ha.lu()
+    assert np.array_equal(Q0, Q1), "ordering differs"
+    assert np.array_equal(P0, P1), "pivot sequence differs"
+    assert np.array_equal(rp0, rp1) and np.array_equal(ci0, ci1), "factor pattern differs"
+    assert np.array_equal(v0.view(np.int64), v1.view(np.int64)), "pivoting-pass values differ"
+    assert (ha.status == binding.WARN_NUMERICALLY_SINGULAR) == (lu.status == oracle.WARN_SINGULAR)
+    return ha, lu
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "kkt_lu.h")).read()
+    declared = set(re.findall(r"\b(kkt_[a-z_0-9]+)\s*\(", hdr))
+    assert declared == set(binding.EXPORTS)
+    L = binding.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.1, 1e-3, 1e-10])
+@pytest.mark.parametrize("seed", range(8))
+def test_random_sparse_bitwise(tau, seed):
+    n = 20 + 17 * seed
+    rp, ci, v = kktgen.random_sparse(n, 3.0 / n, seed=2000 + seed, diag=True,
+                                     sym_pattern=bool(seed % 2))
+    compare(n, rp, ci, v, tau)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_without_full_diagonal(seed):
+    # zero-free transversal not on the diagonal: pivots leave the diagonal
+    n = 30
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n)
+    rp, ci, v = kktgen.random_sparse(n, 0.08, seed=3000 + seed, diag=False)
+    D = np.zeros((n, n))
+    M = np.zeros((n, n), bool)
+    for i in range(n):
+        D[i, ci[rp[i]:rp[i + 1]]] = v[rp[i]:rp[i + 1]]
+        M[i, ci[rp[i]:rp[i + 1]]] = True
+    M[np.arange(n), perm] = True
+    D[np.arange(n), perm] += 1.0
+    r, c = np.nonzero(M)
+    rp2 = np.zeros(n + 1, np.int64)
+    np.add.at(rp2, r + 1, 1)
+    compare(n, np.cumsum(rp2), c.astype(np.int32), D[r, c], 1.0)
+
+
+@pytest.mark.parametrize("B,seed", [(3, 1), (10, 2), (100, 101), (500, 7), (2000, 104)])
+def test_kkt_configs_bitwise(B, seed):
+    pat, seq = kktgen.make_sequence(B, seed, 1)
+    # classic partial pivoting (tau = 1) makes the quasi-definite KKT fill in
+    # heavily; keep it to the small cases
+    for tau in ((1e-10, 1.0) if B <= 100 else (1e-10,)):
+        ha, lu = compare(pat.n, pat.rowptr, pat.colind, seq[0][0], tau)
+    info = ha.info()
+    assert info.n == pat.n and info.nnz == pat.nnz
+
+
+@pytest.mark.slow
+def test_kkt_10k_bitwise():
+    pat, seq = kktgen.make_sequence(10000, 102, 1)
+    compare(pat.n, pat.rowptr, pat.colind, seq[0][0], 1e-10)
+
+
+def test_user_ordering():
+    pat, seq = kktgen.make_sequence(100, 101, 1)
+    q = np.random.default_rng(0).permutation(pat.n).astype(np.int32)
+    compare(pat.n, pat.rowptr, pat.colind, seq[0][0], 0.1, user_q=q)
+
+
+def test_level_schedule_is_topological():
+    pat, seq = kktgen.make_sequence(500, 7, 1)
+    ha = binding.HostAnalysis(pat.n, pat.rowptr, pat.colind, seq[0][0])
+    lp, rows = ha.levels()
+    rp, ci, _ = ha.lu()
+    assert sorted(rows.tolist()) == list(range(pat.n))
+    level = np.empty(pat.n, np.int64)
+    for l in range(len(lp) - 1):
+        level[rows[lp[l]:lp[l + 1]]] = l
+    for i in range(pat.n):
+        deps = ci[rp[i]:rp[i + 1]]
+        deps = deps[deps < i]
+        assert np.all(level[deps] < level[i])
+        # each row sits at the first level its dependencies allow
+        assert level[i] == (level[deps].max() + 1 if len(deps) else 0)
+
+
+# ---------------------------------------------------------------------------
+# error paths (host only)
+# ---------------------------------------------------------------------------
+def _tiny():
+    rp = np.array([0, 2, 4], np.int64)
+    ci = np.array([0, 1, 0, 1], np.int32)
+    v = np.array([2.0, 1.0, 1.0, 3.0])
+    return rp, ci, v
+
+
+@pytest.mark.parametrize("case,status", [
+    ("unsorted", binding.ERR_BAD_PATTERN),
+    ("duplicate", binding.ERR_BAD_PATTERN),
+    ("out_of_range", binding.ERR_BAD_PATTERN),
+    ("bad_rowptr", binding.ERR_BAD_PATTERN),
+    ("nan", binding.ERR_NONFINITE),
+    ("struct_singular", binding.ERR_STRUCTURALLY_SINGULAR),
+    ("bad_q", binding.ERR_INVALID_ARG),
+    ("bad_tau", binding.ERR_INVALID_ARG),
+])
+def test_analysis_errors(case, status):
+    rp, ci, v = _tiny()
+    kw = {}
+    q = None
+    if case == "unsorted":
+        ci = np.array([1, 0, 0, 1], np.int32)
+    elif case == "duplicate":
+        ci = np.array([0, 0, 0, 1], np.int32)
+    elif case == "out_of_range":
+        ci = np.array([0, 2, 0, 1], np.int32)
+    elif case == "bad_rowptr":
+        rp = np.array([0, 3, 2], np.int64)
+    elif case == "nan":
+        v = np.array([2.0, np.nan, 1.0, 3.0])
+    elif case == "struct_singular":
+        ci = np.array([0, 1, 0, 1], np.int32)
+        rp = np.array([0, 2, 4], np.int64)
+        rp2 = np.array([0, 1, 2], np.int64)
+        rp, ci, v = rp2, np.array([0, 0], np.int32), np.array([1.0, 2.0])
+    elif case == "bad_q":
+        q = np.array([0, 0], np.int32)
+        kw["ordering"] = 2
+    elif case == "bad_tau":
+        kw["pivot_tau"] = 0.0
+    with pytest.raises(binding.KKTError) as ei:
+        binding.HostAnalysis(2, rp, ci, v, user_q=q, **kw)
+    assert ei.value.status == status
+
+
+def test_singular_warning_matches_oracle():
+    A = np.array([[1.0, 0.0, 2.0], [3.0, 0.0, 1.0], [0.0, 0.0, 5.0]])
+    M = np.array([[1, 1, 1], [1, 1, 1], [0, 0, 1]], dtype=bool)
+    r, c = np.nonzero(M)
+    rp = np.array([0, 3, 6, 7], np.int64)
+    ha, lu = compare(3, rp, c.astype(np.int32), A[r, c], 1.0, user_q=np.arange(3, dtype=np.int32))
+    assert ha.status == binding.WARN_NUMERICALLY_SINGULAR

@@ -1,0 +1,194 @@
+"""GPU path vs the CPU oracle, through the C ABI (needs an MI355X).
+
+* refactorization: the factor values equal the oracle's refactorization bit
+  for bit (both apply each entry's updates in ascending pivot order with fma),
+  which implies the headline metric ||F_gpu - F_ora||_F / ||F_ora||_F <= 1e-10;
+* solve: backward error eta = ||b - A x||_inf / (||A||_inf ||x||_inf) <= 1e-12
+  after refinement, for op 'N' and 'T';
+* refinement: forced iterations and stale factors converge; a zero budget
+  reports non-convergence;
+* adjoint: gradient on the pattern vs the oracle's;
+* edge cases: ragged tiny systems, several right-hand sides, error statuses.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_14337_amd import binding, kktgen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def oracle_csr_values(lu: oracle.OracleLU):
+    f = lu.factors()
+    n = lu.n
+    rows = np.concatenate([f["Li"], f["Ui"]])
+    cols = np.concatenate([np.repeat(np.arange(n), np.diff(f["Lp"])),
+                           np.repeat(np.arange(n), np.diff(f["Up"]))])
+    vals = np.concatenate([f["Lx"], f["Ux"]])
+    return vals[np.lexsort((cols, rows))]
+
+
+def eta(A, x, b):
+    return np.abs(b - A @ x).max() / (abs(A).sum(1).max() * np.abs(x).max())
+
+
+def assert_factors_equal(gpu_vals, ora_vals):
+    print(f"  factor entries {len(ora_vals)}", flush=True)
+    rel = np.linalg.norm(gpu_vals - ora_vals) / np.linalg.norm(ora_vals)
+    assert rel <= 1e-10, rel
+    assert np.array_equal(gpu_vals.view(np.int64), ora_vals.view(np.int64)), (
+        f"not bitwise equal ({np.sum(gpu_vals != ora_vals)} entries differ, rel {rel:.3e})")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    binding.lib()
+    yield
+
+
+@pytest.mark.parametrize("B,seed,steps", [(3, 5, 2), (100, 101, 3), (500, 7, 3), (2000, 104, 3)])
+def test_sequence_refactor_solve(B, seed, steps):
+    print(f"case B={B} seed={seed}", flush=True)
+    pat, seq = kktgen.make_sequence(B, seed, steps)
+    s = binding.KKTSolver()
+    s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
+    ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, seq[0][0], tau=1e-10)
+    # before any refactorization the handle holds the pivoting pass's factors
+    assert_factors_equal(s.lu()[2], oracle_csr_values(ora))
+    for k, (vals, b) in enumerate(seq):
+        s.refactor(dev(vals))
+        x = s.solve(dev(b))
+        rep = s.report()
+        ora.refactor(vals)
+        assert_factors_equal(s.lu()[2], oracle_csr_values(ora))
+        A = pat.scipy(vals)
+        xh = x.cpu().numpy()
+        e = eta(A, xh, b)
+        print(f"  step {k}: eta {e:.3e} iters {rep.iters}", flush=True)
+        assert e <= 1e-12
+        # the device's own eta agrees up to the rounding of the residual itself
+        # (both are far below 1e-12 here; summation orders differ)
+        assert rep.eta <= 1e-12 and abs(rep.eta - e) <= 1e-15
+        xo, info = ora.solve(b)
+        assert info["converged"] == 1
+
+
+def test_transposed_solve_and_multiple_rhs():
+    pat, seq = kktgen.make_sequence(500, 9, 1)
+    vals, _ = seq[0]
+    s = binding.KKTSolver()
+    s.analyze(pat.n, pat.rowptr, pat.colind, vals)
+    s.refactor(dev(vals))
+    rng = np.random.default_rng(3)
+    B = rng.standard_normal((4, pat.n))
+    A = pat.scipy(vals)
+    for op, M in (("N", A), ("T", A.T.tocsr())):
+        X = s.solve(dev(B.reshape(-1)), op=op).cpu().numpy().reshape(4, pat.n)
+        for r in range(4):
+            assert eta(M, X[r], B[r]) <= 1e-12, (op, r)
+
+
+def test_refinement_forced_and_stale():
+    pat = kktgen.make_kkt(500, 77)
+    rng = np.random.default_rng(3)
+    sigma = np.clip(kktgen.draw_sigma(rng, pat.n_p), 1e-2, 1e2)
+    v_old = pat.values(sigma)
+    sym = pat.scipy(v_old * (1.0 + 0.05 * rng.standard_normal(v_old.size)))
+    sym = (sym + sym.T) * 0.5
+    sym.sort_indices()
+    v_new = sym.data
+    b = rng.standard_normal(pat.n)
+    A_new = pat.scipy(v_new)
+    # forced iterations on an exact factorization
+    s = binding.KKTSolver(min_iters=2)
+    s.analyze(pat.n, pat.rowptr, pat.colind, v_old)
+    s.refactor(dev(v_old))
+    x = s.solve(dev(b)).cpu().numpy()
+    assert s.report().iters == 2 and eta(pat.scipy(v_old), x, b) <= 1e-12
+    # stale factors: FGMRES makes up the difference
+    s = binding.KKTSolver()
+    s.analyze(pat.n, pat.rowptr, pat.colind, v_old)
+    s.refactor(dev(v_old))
+    s.update_matrix(dev(v_new))
+    x = s.solve(dev(b)).cpu().numpy()
+    rep = s.report()
+    print(f"  stale: iters {rep.iters} eta {rep.eta:.3e}", flush=True)
+    assert rep.iters > 1 and eta(A_new, x, b) <= 1e-12
+    # zero budget: warning, not an error
+    s0 = binding.KKTSolver(fgmres_max_iters=0)
+    s0.analyze(pat.n, pat.rowptr, pat.colind, v_old)
+    s0.refactor(dev(v_old))
+    s0.update_matrix(dev(v_new))
+    s0.solve(dev(b))
+    assert s0.last_status == binding.WARN_NOT_CONVERGED
+    assert s0.report().warnings & (1 << binding.WARN_NOT_CONVERGED)
+
+
+def test_gradient_matches_oracle():
+    pat, seq = kktgen.make_sequence(100, 101, 1)
+    vals, _ = seq[0]
+    nrhs = 3
+    rng = np.random.default_rng(11)
+    Bm = rng.standard_normal((nrhs, pat.n))
+    Cm = rng.standard_normal((nrhs, pat.n))
+    s = binding.KKTSolver()
+    s.analyze(pat.n, pat.rowptr, pat.colind, vals)
+    s.refactor(dev(vals))
+    x = s.solve(dev(Bm.reshape(-1)))
+    lam = s.solve(dev(Cm.reshape(-1)), op="T")
+    g = s.grad_values(lam, x).cpu().numpy()
+    ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, vals, tau=1e-10)
+    xo, _ = ora.solve(Bm.reshape(-1))
+    lo, _ = ora.solve(Cm.reshape(-1), op="T")
+    go = ora.grad(lo, xo)
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    print(f"  grad rel diff {rel:.3e}", flush=True)
+    assert rel <= 1e-6
+    # the product itself against the oracle's product of the GPU's solves
+    go2 = ora.grad(lam.cpu().numpy(), x.cpu().numpy())
+    assert np.allclose(g, go2, rtol=1e-12, atol=1e-14 * np.abs(go2).max())
+
+
+def test_tiny_pivot_warning_and_report():
+    pat, seq = kktgen.make_sequence(100, 101, 1)
+    vals, b = seq[0]
+    s = binding.KKTSolver(tiny_pivot_rel=1e-6)
+    s.analyze(pat.n, pat.rowptr, pat.colind, vals)
+    s.refactor(dev(vals))
+    rep = s.report()
+    assert rep.warnings & (1 << binding.WARN_TINY_PIVOT)
+    ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, vals, tau=1e-10)
+    assert ora.refactor(vals, tiny_rel=1e-6) == oracle.WARN_TINY_PIVOT
+    A = pat.scipy(vals)
+    assert rep.anorm_inf == pytest.approx(abs(A).sum(1).max(), rel=1e-15)
+    f = ora.factors()
+    d = np.abs(f["Ux"][f["Up"][1:] - 1])
+    assert rep.min_pivot == d.min() and rep.max_pivot == d.max()
+
+
+def test_state_and_argument_errors():
+    s = binding.KKTSolver()
+    with pytest.raises(binding.KKTError) as ei:
+        s.nnz = 4
+        s.n = 2
+        s.refactor(dev(np.ones(4)))
+    assert ei.value.status == binding.ERR_STATE
+    pat, seq = kktgen.make_sequence(3, 5, 1)
+    s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
+    b = dev(seq[0][1])
+    with pytest.raises(binding.KKTError) as ei:
+        s.solve(b, x=b)
+    assert ei.value.status == binding.ERR_INVALID_ARG
+    # zero right-hand sides is a no-op
+    e = torch.empty(0, dtype=torch.float64, device=DEV)
+    s.solve(e)
