@@ -15,7 +15,27 @@ struct DevStats {
   unsigned long long rmax;     // bits of ||r||_inf (scratch of the residual kernel)
   unsigned long long xmax;     // bits of ||x||_inf
   int tiny;                    // a tiny or non-finite pivot was seen
-  int pad;
+  int stall;                   // a dependency wait hit its spin limit (sticky)
+};
+
+// Scheduling state of the dependency-driven kernels, kept on the device so
+// that a captured launch sequence replays correctly: the kernel that precedes
+// a dependency-driven phase zeroes its ticket counter and advances its epoch;
+// a row is finished in the current phase when ready[row] == epoch.
+// Slots: 0 refactorization, 1 first triangular solve, 2 second one.
+struct SyncState {
+  unsigned int ticket[4];
+  int epoch[4];
+};
+
+// Work chunks of a triangular-solve schedule: chunk c covers rows
+// rows[start[c] .. start[c] + count) of one level, each row handled by a
+// group of G = 1 << lg lanes; meta[c] = (lg << 8) | count.
+struct ChunkSched {
+  int nchunks;
+  const int* start;
+  const int* meta;
+  const int* rows;
 };
 
 struct LUView {
@@ -32,12 +52,32 @@ struct LUView {
 void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxlen,
                           const double* aval, DevStats* st, double tiny_abs_unused,
                           hipStream_t s);
+// Dependency-driven refactorization of all rows in one launch: waves take
+// rows in topological order (order[]) through a ticket counter and wait on
+// per-row ready flags.  cap = LDS staging capacity per row (>= longest row).
+// Returns false if the configuration cannot be launched.
+// Every wait is bounded: past the spin limit a wave sets *stall, and waves
+// that see *stall stop waiting, so the grid always drains.
+bool launch_refactor_syncfree(const LUView& lu, const int* order, int cap, const double* aval,
+                              int* ready, SyncState* ss, int* stall, hipStream_t s);
+// Dependency-driven triangular solve of one right-hand side in place on y.
+// mode 0: unit L rows, 1: U rows, 2: U^T columns (tptr/trow/tpos view of U),
+// 3: unit L^T columns (view of strict L).  slot: SyncState slot (1 or 2).
+void launch_trisolve_syncfree(int mode, const LUView& lu, const ChunkSched& cs, const int* tptr,
+                              const int* trow, const int* tpos, double* y, int* ready,
+                              SyncState* ss, int slot, int* stall, hipStream_t s);
+// zero the tickets and advance the epochs of the slots in mask (bit k = slot k)
+void launch_sync_prep(SyncState* ss, int mask, hipStream_t s);
+// y[i] = x[perm[i]] and, if ss != nullptr, the sync_prep of mask (fused)
+void launch_gather_prep(int n, const int* perm, const double* x, double* y, SyncState* ss,
+                        int mask, hipStream_t s);
+
 // pivot statistics (min/max |u_kk|, tiny test against tiny_rel * ||A||_inf)
 void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStream_t s);
 
-// A copy + ||A||_inf
+// A copy + ||A||_inf (and, if ss != nullptr, the sync_prep of slot 0)
 void launch_copy_anorm(int n, const int* arow, const int* acol, const double* src, double* dst,
-                       DevStats* st, hipStream_t s);
+                       DevStats* st, hipStream_t s, SyncState* ss = nullptr);
 // ||A||_1 through the column view
 void launch_anorm1(int n, const int* cptr, const int* cpos, const double* aval, DevStats* st,
                    hipStream_t s);

@@ -134,6 +134,209 @@ __global__ __launch_bounds__(WAVE) void k_refactor_rows_global(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Dependency-driven ("sync-free") variants.  Waves fetch work in topological
+// order through a ticket counter; a wave only ever waits for rows with smaller
+// tickets, which were fetched by waves that are already running, so the
+// oldest unfinished row always has its inputs and the grid drains.  A
+// finished row is published with a device-scope release (its values, then
+// ready[row] = epoch); a consumer observes the flag with device-scope loads
+// and issues one device-scope acquire for a whole batch of ready inputs (the
+// eight XCDs have separate L2 caches).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int ld_flag(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_flag(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// 2^20 polling rounds (each a device-scope load plus a short sleep, about a
+// microsecond): far longer than any legitimate wait of one factorization or
+// solve, short enough that a broken schedule drains in about a second
+constexpr int SPIN_LIMIT = 1 << 20;
+
+// Broadcast of a lane-0 value through a scalar register.  Unlike a shuffle,
+// the result is provably wave-uniform, so loops whose exit depends on it stay
+// uniform loops (a shuffle-broadcast exit condition lets the compiler treat
+// the loop as divergent and split lane 0's flag store out of it).
+__device__ __forceinline__ unsigned int bcast0(unsigned int v) {
+  return (unsigned int)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// One more round of waiting allowed?  False once the limit is hit here (the
+// wave raises *stall) or anywhere else (another wave raised it).
+__device__ __forceinline__ bool keep_waiting(int* spins, int* stall) {
+  if (ld_flag(stall)) return false;
+  if (++*spins > SPIN_LIMIT) {
+    st_flag(stall, 1);
+    return false;
+  }
+  __builtin_amdgcn_s_sleep(1);
+  return true;
+}
+
+// Up-looking refactorization, as k_refactor_rows_lds, in one launch.  The L
+// entries of a row are consumed in ascending order; before entry t the wave
+// checks (one lane per entry) how many of the next 64 inputs are finished and
+// takes one acquire fence for all of them.
+//
+// No branch in the work loop depends on the lane index: the ticket atomic is
+// issued by every lane (only lane 0 adds 1) and every lane stores the same
+// flag value.  A lane-0-only region at the loop boundary lets the compiler
+// split the loop so that lanes 1..63 iterate without lane 0 on a stale
+// ticket, which never terminates.
+template <int WPB>
+__global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
+    const int* __restrict__ order, int n, const int* __restrict__ rowptr,
+    const int* __restrict__ col, const int* __restrict__ diag, const int* __restrict__ src,
+    const double* __restrict__ aval, double* val, int* ready, SyncState* ss, int* stall, int cap) {
+  extern __shared__ double smem_d[];
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  double* sv = smem_d + (size_t)wave * cap;
+  int* sc = reinterpret_cast<int*>(smem_d + (size_t)WPB * cap) + (size_t)wave * cap;
+  const int epoch = ss->epoch[0];
+  unsigned int* ticket = &ss->ticket[0];
+  for (;;) {
+    const unsigned int tk = bcast0(atomicAdd(ticket, lane == 0 ? 1u : 0u));
+    if (tk >= (unsigned int)n) break;
+    const int i = order[tk];
+    const int rs = rowptr[i], len = rowptr[i + 1] - rs, dl = diag[i] - rs;
+    for (int t = lane; t < len; t += WAVE) {
+      sc[t] = col[rs + t];
+      const int s = src[rs + t];
+      sv[t] = s >= 0 ? aval[s] : 0.0;
+    }
+    wave_sync();
+    int ready_upto = 0, spins = 0;
+    for (int t = 0; t < dl; t++) {
+      if (t >= ready_upto) {
+        for (;;) {
+          const int q = t + lane;
+          const bool ok = q >= dl || ld_flag(ready + sc[q]) == epoch;
+          const unsigned long long bad = __ballot(!ok);
+          const int first_bad = bad ? __ffsll((long long)bad) - 1 : WAVE;
+          if (first_bad > 0) {
+            ready_upto = t + first_bad;
+            break;
+          }
+          if (!bcast0(keep_waiting(&spins, stall) ? 1u : 0u)) {
+            ready_upto = dl;
+            break;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      const int k = sc[t];
+      const int dk = diag[k];
+      const int ke = rowptr[k + 1];
+      const double lik = sv[t] / val[dk];
+      for (int q = dk + 1 + lane; q < ke; q += WAVE) {
+        const int j = col[q];
+        const double u = val[q];
+        const int p = lower_bound_i(sc, t + 1, len, j);
+        if (p < len && sc[p] == j) sv[p] = __builtin_fma(-lik, u, sv[p]);
+      }
+      wave_sync();
+      sv[t] = lik;  // every lane writes the same value
+      wave_sync();
+    }
+    for (int t = lane; t < len; t += WAVE) val[rs + t] = sv[t];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    st_flag(ready + i, epoch);  // every lane, same address and value
+  }
+}
+
+// Triangular solve of one right-hand side, dependency driven.  A wave takes
+// one chunk (rows of one level, G lanes per row); every lane waits for the
+// inputs of its own entries, the wave takes one acquire fence, the groups
+// reduce their dot products and publish their rows.
+//   MODE 0  L rows:   y_i -= sum_{q < diag_i} val_q y_{col_q}
+//   MODE 1  U rows:   y_i = (y_i - sum_{q > diag_i} val_q y_{col_q}) / u_ii
+//   MODE 2  U^T cols: y_j = (y_j - sum_t val_{pos_t} y_{row_t}) / u_jj
+//   MODE 3  L^T cols: y_j -= sum_t val_{pos_t} y_{row_t}
+// As in the refactorization, no lane-indexed branch guards a store: every
+// lane of a group writes its row's (identical) result and flag, and lanes
+// without a row write to the spare slot n of y and ready (n + 1 entries).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_trisolve_syncfree(
+    int n, int nchunks, const int* __restrict__ ch_start, const int* __restrict__ ch_meta,
+    const int* __restrict__ rows, const int* __restrict__ rowptr, const int* __restrict__ col,
+    const int* __restrict__ diag, const int* __restrict__ tptr, const int* __restrict__ trow,
+    const int* __restrict__ tpos, const double* __restrict__ val, double* y, int* ready,
+    SyncState* ss, int slot, int* stall) {
+  const int lane = threadIdx.x % WAVE;
+  const int epoch = ss->epoch[slot];
+  unsigned int* ticket = &ss->ticket[slot];
+  for (;;) {
+    const unsigned int tk = bcast0(atomicAdd(ticket, lane == 0 ? 1u : 0u));
+    if (tk >= (unsigned int)nchunks) break;
+    const int meta = ch_meta[tk];
+    const int lg = meta >> 8, cnt = meta & 0xff;
+    const int G = 1 << lg;
+    const int grp = lane >> lg, gl = lane & (G - 1);
+    const bool active = grp < cnt;
+    const int i = active ? rows[ch_start[tk] + grp] : n;
+    int b = 0, e = 0, dpos = 0;
+    if (active) {
+      if (MODE == 0) {
+        b = rowptr[i];
+        e = diag[i];
+      } else if (MODE == 1) {
+        dpos = diag[i];
+        b = dpos + 1;
+        e = rowptr[i + 1];
+      } else if (MODE == 2) {
+        b = tptr[i];
+        e = tptr[i + 1] - 1;
+        dpos = tpos[e];
+      } else {
+        b = tptr[i];
+        e = tptr[i + 1];
+      }
+    }
+    int spins = 0;
+    for (int q = b + gl; q < e; q += G) {
+      const int k = MODE <= 1 ? col[q] : trow[q];
+      while (ld_flag(ready + k) != epoch && keep_waiting(&spins, stall)) {
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double s = 0.0;
+    for (int q = b + gl; q < e; q += G) {
+      if (MODE <= 1)
+        s += val[q] * y[col[q]];
+      else
+        s += val[tpos[q]] * y[trow[q]];
+    }
+    // butterfly: every lane of the group ends with the same sum
+    for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, WAVE);
+    const double yi = y[i];
+    y[i] = (MODE == 0 || MODE == 3) ? yi - s : (yi - s) / val[dpos];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    st_flag(ready + i, epoch);
+  }
+}
+
+__device__ __forceinline__ void sync_prep(SyncState* ss, int mask) {
+  for (int k = 0; k < 4; k++)
+    if (mask & (1 << k)) {
+      ss->ticket[k] = 0u;
+      ss->epoch[k] = ss->epoch[k] + 1;
+    }
+}
+
+__global__ void k_sync_prep(SyncState* ss, int mask) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) sync_prep(ss, mask);
+}
+
+__global__ void k_gather_prep(int n, const int* __restrict__ perm, const double* __restrict__ x,
+                              double* __restrict__ y, SyncState* ss, int mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[perm[i]];
+  if (ss && i == 0) sync_prep(ss, mask);
+}
+
 __global__ void k_pivot_stats(int n, const int* __restrict__ diag, const double* __restrict__ val,
                               DevStats* st, double tiny_rel) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -175,13 +378,15 @@ __global__ void k_reset_stats(DevStats* st, int what) {
       st->anorm = 0ull;
       st->anorm1 = 0ull;
     }
+    if (what & 8) st->stall = 0;
   }
 }
 
 // copy of A's values and ||A||_inf (wave per row)
 __global__ void k_copy_anorm(int n, const int* __restrict__ arow, const double* __restrict__ src,
-                             double* __restrict__ dst, DevStats* st) {
+                             double* dst, DevStats* st, SyncState* ss) {
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
+  if (ss && blockIdx.x == 0 && threadIdx.x == 0) sync_prep(ss, 1);
   if (wave >= n) return;
   double s = 0.0;
   for (int p = arow[wave] + lane; p < arow[wave + 1]; p += WAVE) {
@@ -496,9 +701,75 @@ void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStre
 }
 
 void launch_copy_anorm(int n, const int* arow, const int*, const double* src, double* dst,
-                       DevStats* st, hipStream_t s) {
+                       DevStats* st, hipStream_t s, SyncState* ss) {
   hipLaunchKernelGGL(k_copy_anorm, dim3(cdiv((long)n * WAVE, 256)), dim3(256), 0, s, n, arow, src,
-                     dst, st);
+                     dst, st, ss);
+}
+
+bool launch_refactor_syncfree(const LUView& lu, const int* order, int cap, const double* aval,
+                              int* ready, SyncState* ss, int* stall, hipStream_t s) {
+  cap = (cap + 1) & ~1;
+  const size_t per_wave = (size_t)cap * (sizeof(double) + sizeof(int));
+  if (per_wave > 64 * 1024) return false;
+  static int ncu = 0;
+  if (ncu == 0) {
+    int d = 0;
+    hipGetDevice(&d);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
+    if (ncu <= 0) ncu = 256;
+  }
+  auto go = [&](auto kernel, int wpb) {
+    const size_t shm = per_wave * wpb;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, wpb * WAVE, shm) != hipSuccess ||
+        nb <= 0)
+      nb = 1;
+    const int grid = std::max(1, std::min(nb * ncu, cdiv(lu.n, wpb)));
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(wpb * WAVE), shm, s, order, lu.n, lu.rowptr,
+                       lu.col, lu.diag, lu.src, aval, lu.val, ready, ss, stall, cap);
+  };
+  if (per_wave * 4 <= 32 * 1024)
+    go(k_refactor_syncfree<4>, 4);
+  else if (per_wave * 2 <= 64 * 1024)
+    go(k_refactor_syncfree<2>, 2);
+  else
+    go(k_refactor_syncfree<1>, 1);
+  return true;
+}
+
+void launch_trisolve_syncfree(int mode, const LUView& lu, const ChunkSched& cs, const int* tptr,
+                              const int* trow, const int* tpos, double* y, int* ready,
+                              SyncState* ss, int slot, int* stall, hipStream_t s) {
+  if (cs.nchunks <= 0) return;
+  static int ncu = 0;
+  if (ncu == 0) {
+    int d = 0;
+    hipGetDevice(&d);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
+    if (ncu <= 0) ncu = 256;
+  }
+  const int grid = std::max(1, std::min(ncu * 8, cdiv(cs.nchunks, 4)));
+#define TS_LAUNCH(M)                                                                            \
+  hipLaunchKernelGGL(k_trisolve_syncfree<M>, dim3(grid), dim3(256), 0, s, lu.n, cs.nchunks,       \
+                     cs.start, \
+                     cs.meta, cs.rows, lu.rowptr, lu.col, lu.diag, tptr, trow, tpos, lu.val, y, \
+                     ready, ss, slot, stall)
+  switch (mode) {
+    case 0: TS_LAUNCH(0); break;
+    case 1: TS_LAUNCH(1); break;
+    case 2: TS_LAUNCH(2); break;
+    default: TS_LAUNCH(3); break;
+  }
+#undef TS_LAUNCH
+}
+
+void launch_sync_prep(SyncState* ss, int mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_sync_prep, dim3(1), dim3(64), 0, s, ss, mask);
+}
+
+void launch_gather_prep(int n, const int* perm, const double* x, double* y, SyncState* ss,
+                        int mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_prep, dim3(cdiv(n, 256)), dim3(256), 0, s, n, perm, x, y, ss, mask);
 }
 
 void launch_anorm1(int n, const int* cptr, const int* cpos, const double* aval, DevStats* st,

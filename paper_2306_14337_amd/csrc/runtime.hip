@@ -49,6 +49,12 @@ struct kkt_ctx {
       *at_pos = nullptr;
   double* aval = nullptr;
   bool anorm1_valid = false;
+  // dependency-driven schedules
+  bool syncfree = false;
+  int cap = 0;  // longest LU row (LDS staging capacity)
+  SyncState* ss = nullptr;
+  int *ready_ref = nullptr, *ready_a = nullptr, *ready_b = nullptr;
+  ChunkSched ch_l{}, ch_u{}, ch_ut{}, ch_lt{};
   // statistics
   DevStats* st = nullptr;
   DevStats* h_st = nullptr;  // pinned
@@ -131,6 +137,24 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
   const Analysis& A = h->an;
   const int n = A.n;
   LUView lu = view(h);
+  if (h->syncfree) {
+    if (op == 'N') {
+      launch_gather_prep(n, h->pin, b, h->tmp, h->ss, 0x6, s);
+      launch_trisolve_syncfree(0, lu, h->ch_l, nullptr, nullptr, nullptr, h->tmp, h->ready_a,
+                               h->ss, 1, &h->st->stall, s);
+      launch_trisolve_syncfree(1, lu, h->ch_u, nullptr, nullptr, nullptr, h->tmp, h->ready_b,
+                               h->ss, 2, &h->st->stall, s);
+      launch_scatter(n, h->qperm, h->tmp, x, s);
+    } else {
+      launch_gather_prep(n, h->qperm, b, h->tmp, h->ss, 0x6, s);
+      launch_trisolve_syncfree(2, lu, h->ch_ut, h->ut_ptr, h->ut_row, h->ut_pos, h->tmp,
+                               h->ready_a, h->ss, 1, &h->st->stall, s);
+      launch_trisolve_syncfree(3, lu, h->ch_lt, h->lt_ptr, h->lt_row, h->lt_pos, h->tmp,
+                               h->ready_b, h->ss, 2, &h->st->stall, s);
+      launch_scatter(n, h->pin, h->tmp, x, s);
+    }
+    return;
+  }
   if (op == 'N') {
     launch_gather(n, h->pin, b, h->tmp, s);
     for (size_t l = 0; l + 1 < A.lev_ptr.size(); l++)
@@ -169,6 +193,8 @@ kkt_status residual_eta(kkt_handle h, char op, const double* b, const double* x,
     launch_residual(h->an.n, 'T', h->at_ptr, h->at_row, h->at_pos, h->aval, b, x, r, h->st, s);
   HIP_CHECK(h, hipMemcpyAsync(h->h_st, h->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
   HIP_CHECK(h, hipStreamSynchronize(s));
+  if (h->h_st->stall)
+    return fail(h, KKT_ERR_DEVICE, "a dependency wait hit its spin limit (results invalid)");
   const double rn = bits_to_double(h->h_st->rmax), xn = bits_to_double(h->h_st->xmax);
   const double an = bits_to_double(op == 'N' ? h->h_st->anorm : h->h_st->anorm1);
   const double den = an * xn;
@@ -357,6 +383,76 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
     UP(h->at_row, atr);
     UP(h->at_pos, atpos);
   }
+  {
+    // chunked level schedules of the four triangular solves: rows of one
+    // level, G lanes per row with G the smallest power of two in [4, 64]
+    // giving at most four entries per lane for the level's longest row
+    auto chunks = [&](const std::vector<int32_t>& lp, const std::vector<int32_t>& rows,
+                      auto len_of, ChunkSched& cs, std::vector<int32_t>& st,
+                      std::vector<int32_t>& me) {
+      st.clear();
+      me.clear();
+      for (size_t l = 0; l + 1 < lp.size(); l++) {
+        int mx = 0;
+        for (int32_t t = lp[l]; t < lp[l + 1]; t++) mx = std::max(mx, (int)len_of(rows[t]));
+        int lg = 2;
+        while (lg < 6 && (4 << lg) < mx) lg++;
+        const int per = 64 >> lg;
+        for (int32_t t = lp[l]; t < lp[l + 1]; t += per) {
+          st.push_back(t);
+          me.push_back((lg << 8) | std::min(per, lp[l + 1] - t));
+        }
+      }
+      cs.nchunks = (int)st.size();
+      cs.rows = nullptr;
+    };
+    std::vector<int32_t> st1, me1;
+    int* dptr;
+    int* dmeta;
+    chunks(A.lev_ptr, A.lev_rows, [&](int i) { return A.diag[i] - A.lu_rowptr[i]; }, h->ch_l, st1,
+           me1);
+    UP(dptr, st1);
+    UP(dmeta, me1);
+    h->ch_l.start = dptr;
+    h->ch_l.meta = dmeta;
+    h->ch_l.rows = h->lev_rows;
+    chunks(A.ulev_ptr, A.ulev_rows, [&](int i) { return A.lu_rowptr[i + 1] - A.diag[i] - 1; },
+           h->ch_u, st1, me1);
+    UP(dptr, st1);
+    UP(dmeta, me1);
+    h->ch_u.start = dptr;
+    h->ch_u.meta = dmeta;
+    h->ch_u.rows = h->ulev_rows;
+    chunks(A.utlev_ptr, A.utlev_rows, [&](int j) { return A.ut_ptr[j + 1] - A.ut_ptr[j] - 1; },
+           h->ch_ut, st1, me1);
+    UP(dptr, st1);
+    UP(dmeta, me1);
+    h->ch_ut.start = dptr;
+    h->ch_ut.meta = dmeta;
+    h->ch_ut.rows = h->utlev_rows;
+    chunks(A.ltlev_ptr, A.ltlev_rows, [&](int j) { return A.lt_ptr[j + 1] - A.lt_ptr[j]; },
+           h->ch_lt, st1, me1);
+    UP(dptr, st1);
+    UP(dmeta, me1);
+    h->ch_lt.start = dptr;
+    h->ch_lt.meta = dmeta;
+    h->ch_lt.rows = h->ltlev_rows;
+    std::vector<int32_t> zeros(n + 1, 0);  // slot n: spare target of idle lanes
+    UP(h->ready_ref, zeros);
+    UP(h->ready_a, zeros);
+    UP(h->ready_b, zeros);
+    std::vector<SyncState> ss0(1);
+    std::memset(ss0.data(), 0, sizeof(SyncState));
+    UP(h->ss, ss0);
+    h->cap = 0;
+    for (int v : A.lev_maxlen) h->cap = std::max(h->cap, v);
+    const bool fits = (size_t)((h->cap + 1) & ~1) * 12 <= 64 * 1024;
+    h->syncfree = h->opt.schedule == 2 || (h->opt.schedule == 0 && fits);
+    if (h->opt.schedule == 2 && !fits) {
+      free_device(h);
+      return fail(h, KKT_ERR_INVALID_ARG, "rows too long for the dependency-driven schedule");
+    }
+  }
 #undef UP
   const size_t f = A.lu_col.size();
   const int m = h->m;
@@ -365,7 +461,7 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
       (ks = dalloc(h, &h->V, (size_t)(m + 1) * n)) != KKT_OK ||
       (ks = dalloc(h, &h->Z, (size_t)m * n)) != KKT_OK || (ks = dalloc(h, &h->w, n)) != KKT_OK ||
       (ks = dalloc(h, &h->r, n)) != KKT_OK || (ks = dalloc(h, &h->xt, n)) != KKT_OK ||
-      (ks = dalloc(h, &h->tmp, n)) != KKT_OK ||
+      (ks = dalloc(h, &h->tmp, (size_t)n + 1)) != KKT_OK ||
       (ks = dalloc(h, &h->H, (size_t)(m + 1) * m)) != KKT_OK ||
       (ks = dalloc(h, &h->cs, m + 1)) != KKT_OK || (ks = dalloc(h, &h->sn, m + 1)) != KKT_OK ||
       (ks = dalloc(h, &h->g, m + 1)) != KKT_OK || (ks = dalloc(h, &h->h, m + 1)) != KKT_OK ||
@@ -379,7 +475,7 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
   HIP_CHECK(h, hipMemcpy(h->lu_val, A.lu_val0.data(), f * sizeof(double), hipMemcpyHostToDevice));
   HIP_CHECK(h, hipMemcpy(h->aval, values0, (size_t)nnz * sizeof(double), hipMemcpyHostToDevice));
   HIP_CHECK(h, hipHostMalloc((void**)&h->h_st, sizeof(DevStats), hipHostMallocDefault));
-  launch_reset_stats(h->st, 3, nullptr);
+  launch_reset_stats(h->st, 1 | 2 | 8, nullptr);
   launch_copy_anorm(n, h->a_rowptr, h->a_col, h->aval, h->aval, h->st, nullptr);
   launch_pivot_stats(view(h), h->st, h->opt.tiny_pivot_rel, nullptr);
   HIP_CHECK(h, hipGetLastError());
@@ -402,10 +498,17 @@ kkt_status kkt_refactor(kkt_handle h, const double* d_values, void* stream) {
   const Analysis& A = h->an;
   LUView lu = view(h);
   launch_reset_stats(h->st, 1, s);
-  launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s);
-  for (size_t l = 0; l + 1 < A.lev_ptr.size(); l++)
-    launch_refactor_rows(lu, h->lev_rows + A.lev_ptr[l], A.lev_ptr[l + 1] - A.lev_ptr[l],
-                         A.lev_maxlen[l], h->aval, h->st, 0.0, s);
+  if (h->syncfree) {
+    launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, h->ss);
+    if (!launch_refactor_syncfree(lu, h->lev_rows, h->cap, h->aval, h->ready_ref, h->ss,
+                                  &h->st->stall, s))
+      return fail(h, KKT_ERR_DEVICE, "dependency-driven refactorization not launchable");
+  } else {
+    launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s);
+    for (size_t l = 0; l + 1 < A.lev_ptr.size(); l++)
+      launch_refactor_rows(lu, h->lev_rows + A.lev_ptr[l], A.lev_ptr[l + 1] - A.lev_ptr[l],
+                           A.lev_maxlen[l], h->aval, h->st, 0.0, s);
+  }
   launch_pivot_stats(lu, h->st, h->opt.tiny_pivot_rel, s);
   HIP_CHECK(h, hipGetLastError());
   h->anorm1_valid = false;
@@ -492,6 +595,7 @@ kkt_status kkt_sync_report(kkt_handle h, kkt_report* out) {
   HIP_CHECK(h, hipDeviceSynchronize());
   DevStats d;
   HIP_CHECK(h, hipMemcpy(&d, h->st, sizeof d, hipMemcpyDeviceToHost));
+  if (d.stall) return fail(h, KKT_ERR_DEVICE, "a dependency wait hit its spin limit (results invalid)");
   int warn = h->warnings;
   if (d.tiny) warn |= 1 << KKT_WARN_TINY_PIVOT;
   out->warnings = warn;

@@ -56,11 +56,15 @@ def _gpu():
     yield
 
 
+SCHEDULES = [1, 2]  # level-synchronous launches, dependency-driven single launch
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("B,seed,steps", [(3, 5, 2), (100, 101, 3), (500, 7, 3), (2000, 104, 3)])
-def test_sequence_refactor_solve(B, seed, steps):
-    print(f"case B={B} seed={seed}", flush=True)
+def test_sequence_refactor_solve(B, seed, steps, schedule):
+    print(f"case B={B} seed={seed} schedule={schedule}", flush=True)
     pat, seq = kktgen.make_sequence(B, seed, steps)
-    s = binding.KKTSolver()
+    s = binding.KKTSolver(schedule=schedule)
     s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
     ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, seq[0][0], tau=1e-10)
     # before any refactorization the handle holds the pivoting pass's factors
@@ -83,10 +87,11 @@ def test_sequence_refactor_solve(B, seed, steps):
         assert info["converged"] == 1
 
 
-def test_transposed_solve_and_multiple_rhs():
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_transposed_solve_and_multiple_rhs(schedule):
     pat, seq = kktgen.make_sequence(500, 9, 1)
     vals, _ = seq[0]
-    s = binding.KKTSolver()
+    s = binding.KKTSolver(schedule=schedule)
     s.analyze(pat.n, pat.rowptr, pat.colind, vals)
     s.refactor(dev(vals))
     rng = np.random.default_rng(3)
