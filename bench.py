@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", type=int, default=0,
                     help="0 auto, 1 level-synchronous launches, 2 dependency-driven")
+    ap.add_argument("--sync-mode", type=int, default=0,
+                    help="0 default, 1 acquire/release fences, 2 device-coherent accesses")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -81,7 +83,7 @@ def main():
     print(f"# generated B={args.buses} n={pat.n} nnz={pat.nnz} in {t_gen:.1f}s", file=sys.stderr,
           flush=True)
 
-    s = binding.KKTSolver(device=0, schedule=args.schedule)
+    s = binding.KKTSolver(device=0, schedule=args.schedule, sync_mode=args.sync_mode)
     t0 = time.perf_counter()
     s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
     t_an = time.perf_counter() - t0
@@ -149,7 +151,8 @@ def main():
                                f"B={args.buses} buses, n={pat.n}, nnz={pat.nnz}, "
                                f"{args.steps} timed same-pattern matrices, 1 RHS, tau=1e-10",
                    "buses": args.buses, "n": pat.n, "nnz": pat.nnz, "nnz_lu": nnz_lu,
-                   "levels": info.levels, "seed": args.seed, "schedule": args.schedule},
+                   "levels": info.levels, "seed": args.seed, "schedule": args.schedule,
+                   "sync_mode": args.sync_mode},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "refactorization (all launches of one kkt_refactor)",

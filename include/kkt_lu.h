@@ -75,7 +75,10 @@ typedef struct {
   double tiny_pivot_rel;    /* tiny-pivot warning threshold relative to ||A||_inf, 1e-18 */
   int32_t device;           /* HIP device ordinal, default 0 */
   int32_t schedule;         /* 0 auto, 1 level-synchronous launches, 2 dependency-driven */
-  int32_t reserved[8];
+  int32_t sync_mode;        /* dependency-driven publication: 0 default, 1 device-scope
+                               acquire/release fences, 2 device-coherent accesses (the solution
+                               value is its own ready flag in the triangular solves) */
+  int32_t reserved[7];
 } kkt_options;
 
 typedef struct {

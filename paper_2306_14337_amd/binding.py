@@ -47,7 +47,7 @@ class Options(C.Structure):
     _fields_ = [("ordering", C.c_int32), ("pivot_tau", C.c_double), ("fgmres_restart", C.c_int32),
                 ("fgmres_max_iters", C.c_int32), ("min_iters", C.c_int32),
                 ("eta_target", C.c_double), ("tiny_pivot_rel", C.c_double), ("device", C.c_int32),
-                ("schedule", C.c_int32), ("reserved", C.c_int32 * 8)]
+                ("schedule", C.c_int32), ("sync_mode", C.c_int32), ("reserved", C.c_int32 * 7)]
 
 
 class Report(C.Structure):

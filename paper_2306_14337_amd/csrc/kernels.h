@@ -58,14 +58,23 @@ void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxl
 // Returns false if the configuration cannot be launched.
 // Every wait is bounded: past the spin limit a wave sets *stall, and waves
 // that see *stall stop waiting, so the grid always drains.
+// light: device-coherent data accesses instead of acquire/release fences.
 bool launch_refactor_syncfree(const LUView& lu, const int* order, int cap, const double* aval,
-                              int* ready, SyncState* ss, int* stall, hipStream_t s);
+                              int* ready, SyncState* ss, int* stall, bool light, hipStream_t s);
 // Dependency-driven triangular solve of one right-hand side in place on y.
 // mode 0: unit L rows, 1: U rows, 2: U^T columns (tptr/trow/tpos view of U),
 // 3: unit L^T columns (view of strict L).  slot: SyncState slot (1 or 2).
 void launch_trisolve_syncfree(int mode, const LUView& lu, const ChunkSched& cs, const int* tptr,
                               const int* trow, const int* tpos, double* y, int* ready,
                               SyncState* ss, int slot, int* stall, hipStream_t s);
+// Value-as-flag triangular solve: reads right-hand side c, writes y, which
+// must hold the sentinel on entry (launch_gather_sentinel); c, y: n+1 entries.
+void launch_trisolve_vflag(int mode, const LUView& lu, const ChunkSched& cs, const int* tptr,
+                           const int* trow, const int* tpos, const double* c, double* y,
+                           SyncState* ss, int slot, int* stall, hipStream_t s);
+// c[i] = x[perm[i]]; y, z := sentinel; plus the sync_prep of mask
+void launch_gather_sentinel(int n, const int* perm, const double* x, double* c, double* y,
+                            double* z, SyncState* ss, int mask, hipStream_t s);
 // zero the tickets and advance the epochs of the slots in mask (bit k = slot k)
 void launch_sync_prep(SyncState* ss, int mask, hipStream_t s);
 // y[i] = x[perm[i]] and, if ss != nullptr, the sync_prep of mask (fused)

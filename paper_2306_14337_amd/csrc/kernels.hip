@@ -176,6 +176,23 @@ __device__ __forceinline__ bool keep_waiting(int* spins, int* stall) {
   return true;
 }
 
+// Device-coherent ("light") publication: data written with device-scope
+// stores (write-through to the level shared by all XCDs) and read with
+// device-scope loads, so neither an L2 writeback nor an L2 invalidate is
+// needed; the producer only waits for its stores to complete before raising
+// the flag.
+__device__ __forceinline__ double ld_coh(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stores_done() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);  // every outstanding memory operation complete
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Up-looking refactorization, as k_refactor_rows_lds, in one launch.  The L
 // entries of a row are consumed in ascending order; before entry t the wave
 // checks (one lane per entry) how many of the next 64 inputs are finished and
@@ -186,7 +203,7 @@ __device__ __forceinline__ bool keep_waiting(int* spins, int* stall) {
 // flag value.  A lane-0-only region at the loop boundary lets the compiler
 // split the loop so that lanes 1..63 iterate without lane 0 on a stale
 // ticket, which never terminates.
-template <int WPB>
+template <int WPB, bool LIGHT>
 __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
     const int* __restrict__ order, int n, const int* __restrict__ rowptr,
     const int* __restrict__ col, const int* __restrict__ diag, const int* __restrict__ src,
@@ -225,15 +242,15 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
             break;
           }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (!LIGHT) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       const int k = sc[t];
       const int dk = diag[k];
       const int ke = rowptr[k + 1];
-      const double lik = sv[t] / val[dk];
+      const double lik = sv[t] / (LIGHT ? ld_coh(val + dk) : val[dk]);
       for (int q = dk + 1 + lane; q < ke; q += WAVE) {
         const int j = col[q];
-        const double u = val[q];
+        const double u = LIGHT ? ld_coh(val + q) : val[q];
         const int p = lower_bound_i(sc, t + 1, len, j);
         if (p < len && sc[p] == j) sv[p] = __builtin_fma(-lik, u, sv[p]);
       }
@@ -241,8 +258,16 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
       sv[t] = lik;  // every lane writes the same value
       wave_sync();
     }
-    for (int t = lane; t < len; t += WAVE) val[rs + t] = sv[t];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    for (int t = lane; t < len; t += WAVE) {
+      if (LIGHT)
+        st_coh(val + rs + t, sv[t]);
+      else
+        val[rs + t] = sv[t];
+    }
+    if (LIGHT)
+      stores_done();
+    else
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     st_flag(ready + i, epoch);  // every lane, same address and value
   }
 }
@@ -318,6 +343,69 @@ __global__ __launch_bounds__(256) void k_trisolve_syncfree(
   }
 }
 
+// Value-as-flag triangular solve: the output vector starts filled with a
+// signaling-NaN bit pattern that no arithmetic result can carry (results are
+// quiet NaNs at worst), so a consumer spins on the value itself with
+// device-scope loads and the producer publishes with one device-scope store:
+// one round trip per dependency and no fences.  Input c and output y are
+// separate arrays (n + 1 entries; slot n takes idle lanes' writes).
+constexpr unsigned long long SENTINEL = 0x7FF0DEAD5EED0001ull;
+
+__device__ __forceinline__ bool is_sentinel(double v) {
+  return (unsigned long long)__double_as_longlong(v) == SENTINEL;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_trisolve_vflag(
+    int n, int nchunks, const int* __restrict__ ch_start, const int* __restrict__ ch_meta,
+    const int* __restrict__ rows, const int* __restrict__ rowptr, const int* __restrict__ col,
+    const int* __restrict__ diag, const int* __restrict__ tptr, const int* __restrict__ trow,
+    const int* __restrict__ tpos, const double* __restrict__ val, const double* __restrict__ c,
+    double* y, SyncState* ss, int slot, int* stall) {
+  const int lane = threadIdx.x % WAVE;
+  unsigned int* ticket = &ss->ticket[slot];
+  for (;;) {
+    const unsigned int tk = bcast0(atomicAdd(ticket, lane == 0 ? 1u : 0u));
+    if (tk >= (unsigned int)nchunks) break;
+    const int meta = ch_meta[tk];
+    const int lg = meta >> 8, cnt = meta & 0xff;
+    const int G = 1 << lg;
+    const int grp = lane >> lg, gl = lane & (G - 1);
+    const bool active = grp < cnt;
+    const int i = active ? rows[ch_start[tk] + grp] : n;
+    int b = 0, e = 0, dpos = 0;
+    if (active) {
+      if (MODE == 0) {
+        b = rowptr[i];
+        e = diag[i];
+      } else if (MODE == 1) {
+        dpos = diag[i];
+        b = dpos + 1;
+        e = rowptr[i + 1];
+      } else if (MODE == 2) {
+        b = tptr[i];
+        e = tptr[i + 1] - 1;
+        dpos = tpos[e];
+      } else {
+        b = tptr[i];
+        e = tptr[i + 1];
+      }
+    }
+    int spins = 0;
+    double s = 0.0;
+    for (int q = b + gl; q < e; q += G) {
+      const int k = MODE <= 1 ? col[q] : trow[q];
+      const double v = MODE <= 1 ? val[q] : val[tpos[q]];
+      double yk = ld_coh(y + k);
+      while (is_sentinel(yk) && keep_waiting(&spins, stall)) yk = ld_coh(y + k);
+      s += v * yk;
+    }
+    for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, WAVE);
+    const double ci = c[i];
+    st_coh(y + i, (MODE == 0 || MODE == 3) ? ci - s : (ci - s) / val[dpos]);
+  }
+}
+
 __device__ __forceinline__ void sync_prep(SyncState* ss, int mask) {
   for (int k = 0; k < 4; k++)
     if (mask & (1 << k)) {
@@ -328,6 +416,21 @@ __device__ __forceinline__ void sync_prep(SyncState* ss, int mask) {
 
 __global__ void k_sync_prep(SyncState* ss, int mask) {
   if (threadIdx.x == 0 && blockIdx.x == 0) sync_prep(ss, mask);
+}
+
+// c[i] = x[perm[i]], and the two solve outputs y, z set to the sentinel
+__global__ void k_gather_sentinel(int n, const int* __restrict__ perm,
+                                  const double* __restrict__ x, double* __restrict__ c,
+                                  double* __restrict__ y, double* __restrict__ z, SyncState* ss,
+                                  int mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    c[i] = x[perm[i]];
+    const double sent = __longlong_as_double((long long)SENTINEL);
+    y[i] = sent;
+    z[i] = sent;
+  }
+  if (ss && i == 0) sync_prep(ss, mask);
 }
 
 __global__ void k_gather_prep(int n, const int* __restrict__ perm, const double* __restrict__ x,
@@ -707,15 +810,15 @@ void launch_copy_anorm(int n, const int* arow, const int*, const double* src, do
 }
 
 bool launch_refactor_syncfree(const LUView& lu, const int* order, int cap, const double* aval,
-                              int* ready, SyncState* ss, int* stall, hipStream_t s) {
+                              int* ready, SyncState* ss, int* stall, bool light, hipStream_t s) {
   cap = (cap + 1) & ~1;
   const size_t per_wave = (size_t)cap * (sizeof(double) + sizeof(int));
   if (per_wave > 64 * 1024) return false;
   static int ncu = 0;
   if (ncu == 0) {
     int d = 0;
-    hipGetDevice(&d);
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
+    (void)hipGetDevice(&d);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
     if (ncu <= 0) ncu = 256;
   }
   auto go = [&](auto kernel, int wpb) {
@@ -728,12 +831,21 @@ bool launch_refactor_syncfree(const LUView& lu, const int* order, int cap, const
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(wpb * WAVE), shm, s, order, lu.n, lu.rowptr,
                        lu.col, lu.diag, lu.src, aval, lu.val, ready, ss, stall, cap);
   };
-  if (per_wave * 4 <= 32 * 1024)
-    go(k_refactor_syncfree<4>, 4);
-  else if (per_wave * 2 <= 64 * 1024)
-    go(k_refactor_syncfree<2>, 2);
-  else
-    go(k_refactor_syncfree<1>, 1);
+  if (light) {
+    if (per_wave * 4 <= 32 * 1024)
+      go(k_refactor_syncfree<4, true>, 4);
+    else if (per_wave * 2 <= 64 * 1024)
+      go(k_refactor_syncfree<2, true>, 2);
+    else
+      go(k_refactor_syncfree<1, true>, 1);
+  } else {
+    if (per_wave * 4 <= 32 * 1024)
+      go(k_refactor_syncfree<4, false>, 4);
+    else if (per_wave * 2 <= 64 * 1024)
+      go(k_refactor_syncfree<2, false>, 2);
+    else
+      go(k_refactor_syncfree<1, false>, 1);
+  }
   return true;
 }
 
@@ -744,8 +856,8 @@ void launch_trisolve_syncfree(int mode, const LUView& lu, const ChunkSched& cs, 
   static int ncu = 0;
   if (ncu == 0) {
     int d = 0;
-    hipGetDevice(&d);
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
+    (void)hipGetDevice(&d);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
     if (ncu <= 0) ncu = 256;
   }
   const int grid = std::max(1, std::min(ncu * 8, cdiv(cs.nchunks, 4)));
@@ -761,6 +873,37 @@ void launch_trisolve_syncfree(int mode, const LUView& lu, const ChunkSched& cs, 
     default: TS_LAUNCH(3); break;
   }
 #undef TS_LAUNCH
+}
+
+void launch_trisolve_vflag(int mode, const LUView& lu, const ChunkSched& cs, const int* tptr,
+                           const int* trow, const int* tpos, const double* c, double* y,
+                           SyncState* ss, int slot, int* stall, hipStream_t s) {
+  if (cs.nchunks <= 0) return;
+  static int ncu = 0;
+  if (ncu == 0) {
+    int d = 0;
+    (void)hipGetDevice(&d);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
+    if (ncu <= 0) ncu = 256;
+  }
+  const int grid = std::max(1, std::min(ncu * 8, cdiv(cs.nchunks, 4)));
+#define TV_LAUNCH(M)                                                                          \
+  hipLaunchKernelGGL(k_trisolve_vflag<M>, dim3(grid), dim3(256), 0, s, lu.n, cs.nchunks,      \
+                     cs.start, cs.meta, cs.rows, lu.rowptr, lu.col, lu.diag, tptr, trow, tpos, \
+                     lu.val, c, y, ss, slot, stall)
+  switch (mode) {
+    case 0: TV_LAUNCH(0); break;
+    case 1: TV_LAUNCH(1); break;
+    case 2: TV_LAUNCH(2); break;
+    default: TV_LAUNCH(3); break;
+  }
+#undef TV_LAUNCH
+}
+
+void launch_gather_sentinel(int n, const int* perm, const double* x, double* c, double* y,
+                            double* z, SyncState* ss, int mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_sentinel, dim3(cdiv(n, 256)), dim3(256), 0, s, n, perm, x, c, y, z,
+                     ss, mask);
 }
 
 void launch_sync_prep(SyncState* ss, int mask, hipStream_t s) {

@@ -51,7 +51,9 @@ struct kkt_ctx {
   bool anorm1_valid = false;
   // dependency-driven schedules
   bool syncfree = false;
-  int cap = 0;  // longest LU row (LDS staging capacity)
+  bool light = true;  // device-coherent publication instead of acquire/release fences
+  int cap = 0;        // longest LU row (LDS staging capacity)
+  double *tc = nullptr, *ty = nullptr, *tz = nullptr;  // value-as-flag solve buffers (n+1)
   SyncState* ss = nullptr;
   int *ready_ref = nullptr, *ready_a = nullptr, *ready_b = nullptr;
   ChunkSched ch_l{}, ch_u{}, ch_ut{}, ch_lt{};
@@ -137,6 +139,24 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
   const Analysis& A = h->an;
   const int n = A.n;
   LUView lu = view(h);
+  if (h->syncfree && h->light) {
+    if (op == 'N') {
+      launch_gather_sentinel(n, h->pin, b, h->tc, h->ty, h->tz, h->ss, 0x6, s);
+      launch_trisolve_vflag(0, lu, h->ch_l, nullptr, nullptr, nullptr, h->tc, h->ty, h->ss, 1,
+                            &h->st->stall, s);
+      launch_trisolve_vflag(1, lu, h->ch_u, nullptr, nullptr, nullptr, h->ty, h->tz, h->ss, 2,
+                            &h->st->stall, s);
+      launch_scatter(n, h->qperm, h->tz, x, s);
+    } else {
+      launch_gather_sentinel(n, h->qperm, b, h->tc, h->ty, h->tz, h->ss, 0x6, s);
+      launch_trisolve_vflag(2, lu, h->ch_ut, h->ut_ptr, h->ut_row, h->ut_pos, h->tc, h->ty,
+                            h->ss, 1, &h->st->stall, s);
+      launch_trisolve_vflag(3, lu, h->ch_lt, h->lt_ptr, h->lt_row, h->lt_pos, h->ty, h->tz,
+                            h->ss, 2, &h->st->stall, s);
+      launch_scatter(n, h->pin, h->tz, x, s);
+    }
+    return;
+  }
   if (h->syncfree) {
     if (op == 'N') {
       launch_gather_prep(n, h->pin, b, h->tmp, h->ss, 0x6, s);
@@ -288,7 +308,7 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
   if (o.ordering < 0 || o.ordering > 2 || !(o.pivot_tau > 0.0 && o.pivot_tau <= 1.0) ||
       o.fgmres_restart < 1 || o.fgmres_restart > 30 || o.fgmres_max_iters < 0 ||
       o.min_iters < 0 || !(o.eta_target >= 0.0) || !(o.tiny_pivot_rel >= 0.0) || o.device < 0 ||
-      o.schedule < 0 || o.schedule > 2)
+      o.schedule < 0 || o.schedule > 2 || o.sync_mode < 0 || o.sync_mode > 2)
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) return KKT_ERR_DEVICE;
@@ -448,6 +468,7 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
     for (int v : A.lev_maxlen) h->cap = std::max(h->cap, v);
     const bool fits = (size_t)((h->cap + 1) & ~1) * 12 <= 64 * 1024;
     h->syncfree = h->opt.schedule == 2 || (h->opt.schedule == 0 && fits);
+    h->light = h->opt.sync_mode != 1;
     if (h->opt.schedule == 2 && !fits) {
       free_device(h);
       return fail(h, KKT_ERR_INVALID_ARG, "rows too long for the dependency-driven schedule");
@@ -462,6 +483,9 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
       (ks = dalloc(h, &h->Z, (size_t)m * n)) != KKT_OK || (ks = dalloc(h, &h->w, n)) != KKT_OK ||
       (ks = dalloc(h, &h->r, n)) != KKT_OK || (ks = dalloc(h, &h->xt, n)) != KKT_OK ||
       (ks = dalloc(h, &h->tmp, (size_t)n + 1)) != KKT_OK ||
+      (ks = dalloc(h, &h->tc, (size_t)n + 1)) != KKT_OK ||
+      (ks = dalloc(h, &h->ty, (size_t)n + 1)) != KKT_OK ||
+      (ks = dalloc(h, &h->tz, (size_t)n + 1)) != KKT_OK ||
       (ks = dalloc(h, &h->H, (size_t)(m + 1) * m)) != KKT_OK ||
       (ks = dalloc(h, &h->cs, m + 1)) != KKT_OK || (ks = dalloc(h, &h->sn, m + 1)) != KKT_OK ||
       (ks = dalloc(h, &h->g, m + 1)) != KKT_OK || (ks = dalloc(h, &h->h, m + 1)) != KKT_OK ||
@@ -501,7 +525,7 @@ kkt_status kkt_refactor(kkt_handle h, const double* d_values, void* stream) {
   if (h->syncfree) {
     launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, h->ss);
     if (!launch_refactor_syncfree(lu, h->lev_rows, h->cap, h->aval, h->ready_ref, h->ss,
-                                  &h->st->stall, s))
+                                  &h->st->stall, h->light, s))
       return fail(h, KKT_ERR_DEVICE, "dependency-driven refactorization not launchable");
   } else {
     launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s);

@@ -56,7 +56,9 @@ def _gpu():
     yield
 
 
-SCHEDULES = [1, 2]  # level-synchronous launches, dependency-driven single launch
+# (schedule, sync_mode): level-synchronous launches; dependency-driven with
+# acquire/release fences; dependency-driven with device-coherent accesses
+SCHEDULES = [(1, 0), (2, 1), (2, 2)]
 
 
 @pytest.mark.parametrize("schedule", SCHEDULES)
@@ -64,7 +66,7 @@ SCHEDULES = [1, 2]  # level-synchronous launches, dependency-driven single launc
 def test_sequence_refactor_solve(B, seed, steps, schedule):
     print(f"case B={B} seed={seed} schedule={schedule}", flush=True)
     pat, seq = kktgen.make_sequence(B, seed, steps)
-    s = binding.KKTSolver(schedule=schedule)
+    s = binding.KKTSolver(schedule=schedule[0], sync_mode=schedule[1])
     s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
     ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, seq[0][0], tau=1e-10)
     # before any refactorization the handle holds the pivoting pass's factors
@@ -91,7 +93,7 @@ def test_sequence_refactor_solve(B, seed, steps, schedule):
 def test_transposed_solve_and_multiple_rhs(schedule):
     pat, seq = kktgen.make_sequence(500, 9, 1)
     vals, _ = seq[0]
-    s = binding.KKTSolver(schedule=schedule)
+    s = binding.KKTSolver(schedule=schedule[0], sync_mode=schedule[1])
     s.analyze(pat.n, pat.rowptr, pat.colind, vals)
     s.refactor(dev(vals))
     rng = np.random.default_rng(3)
