@@ -307,3 +307,42 @@ class KKTSolver:
         self._check(lib().kkt_get_lu(self._h, _np_ptr(rp), _np_ptr(ci),
                                      None if v is None else _np_ptr(v)))
         return rp, ci, v
+
+
+class KKTSolveFn:
+    """Differentiable x = A(values)^{-1} b on a fixed pattern.
+
+    ``KKTSolveFn.apply(solver, values, b)`` refactorizes with ``values`` and
+    solves; the backward pass solves A^T lambda = dL/dx with the same factors
+    (transposed) and returns dL/db = lambda and dL/dvalues[p] =
+    -sum_r lambda_r[i] x_r[j] for every stored entry p = (i, j) of the pattern.
+    b is n (one right-hand side) or n * nrhs (column-major).
+    """
+
+    _fn = None
+
+    @classmethod
+    def apply(cls, solver: "KKTSolver", values, b):
+        if cls._fn is None:
+            torch = _torch()
+
+            class _Fn(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, solver, values, b):
+                    solver.refactor(values.detach().contiguous())
+                    x = solver.solve(b.detach().contiguous())
+                    ctx.solver = solver
+                    ctx.save_for_backward(x)
+                    return x
+
+                @staticmethod
+                def backward(ctx, gx):
+                    (x,) = ctx.saved_tensors
+                    s = ctx.solver
+                    lam = s.solve(gx.contiguous(), op="T")
+                    gvals = s.grad_values(lam, x) if ctx.needs_input_grad[1] else None
+                    gb = lam if ctx.needs_input_grad[2] else None
+                    return None, gvals, gb
+
+            cls._fn = _Fn
+        return cls._fn.apply(solver, values, b)

@@ -72,6 +72,23 @@ void launch_trisolve_syncfree(int mode, const LUView& lu, const ChunkSched& cs, 
 void launch_trisolve_vflag(int mode, const LUView& lu, const ChunkSched& cs, const int* tptr,
                            const int* trow, const int* tpos, const double* c, double* y,
                            SyncState* ss, int slot, int* stall, hipStream_t s);
+// Right-hand sides per multi-column pass.
+constexpr int MAX_RHS_PASS = 32;
+// The same for nr <= MAX_RHS_PASS columns at once; c, y column-major with
+// leading dimension n + 1.
+void launch_trisolve_vflag_mr(int mode, int nr, const LUView& lu, const ChunkSched& cs,
+                              const int* tptr, const int* trow, const int* tpos, const double* c,
+                              double* y, SyncState* ss, int slot, int* stall, hipStream_t s);
+// c[r][i] = x[r][perm[i]] (x: ld n; c, y, z: ld n + 1), y, z := sentinel
+void launch_gather_sentinel_mr(int n, int nr, const int* perm, const double* x, double* c,
+                               double* y, double* z, SyncState* ss, int mask, hipStream_t s);
+// x[r][perm[i]] = z[r][i]
+void launch_scatter_mr(int n, int nr, const int* perm, const double* z, double* x, hipStream_t s);
+// per-column max |B - op(A) X| and max |X| into colmax[2r], colmax[2r+1]
+// (uint64 bit patterns of non-negative doubles); zeroes colmax first
+void launch_residual_mr(int n, int nr, const int* ptr, const int* idx, const int* pos,
+                        const double* aval, const double* B, const double* X,
+                        unsigned long long* colmax, hipStream_t s);
 // c[i] = x[perm[i]]; y, z := sentinel; plus the sync_prep of mask
 void launch_gather_sentinel(int n, const int* perm, const double* x, double* c, double* y,
                             double* z, SyncState* ss, int mask, hipStream_t s);

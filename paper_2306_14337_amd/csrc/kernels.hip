@@ -166,13 +166,18 @@ __device__ __forceinline__ unsigned int bcast0(unsigned int v) {
 
 // One more round of waiting allowed?  False once the limit is hit here (the
 // wave raises *stall) or anywhere else (another wave raised it).
+// The stall flag is polled every 64th round only, and the pause between
+// rounds grows with the wait (up to ~33 x 64 cycles): waves far ahead of the
+// dependency front keep their polling traffic off the memory system that the
+// front's producers are using.
 __device__ __forceinline__ bool keep_waiting(int* spins, int* stall) {
-  if (ld_flag(stall)) return false;
+  if ((*spins & 63) == 63 && ld_flag(stall)) return false;
   if (++*spins > SPIN_LIMIT) {
     st_flag(stall, 1);
     return false;
   }
-  __builtin_amdgcn_s_sleep(1);
+  const int naps = min(*spins >> 3, 32);
+  for (int z = 0; z <= naps; z++) __builtin_amdgcn_s_sleep(1);
   return true;
 }
 
@@ -210,8 +215,10 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
     const double* __restrict__ aval, double* val, int* ready, SyncState* ss, int* stall, int cap) {
   extern __shared__ double smem_d[];
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  // LDS per wave: values (cap doubles), pivot-row bounds (cap int2), columns (cap ints)
   double* sv = smem_d + (size_t)wave * cap;
-  int* sc = reinterpret_cast<int*>(smem_d + (size_t)WPB * cap) + (size_t)wave * cap;
+  int2* sk = reinterpret_cast<int2*>(smem_d + (size_t)WPB * cap) + (size_t)wave * cap;
+  int* sc = reinterpret_cast<int*>(smem_d + (size_t)WPB * cap * 2) + (size_t)wave * cap;
   const int epoch = ss->epoch[0];
   unsigned int* ticket = &ss->ticket[0];
   for (;;) {
@@ -224,8 +231,19 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
       const int s = src[rs + t];
       sv[t] = s >= 0 ? aval[s] : 0.0;
     }
+    // bounds (diagonal position, row end) of every pivot row this row needs,
+    // loaded in parallel up front
+    for (int t = lane; t < dl; t += WAVE) {
+      const int k = sc[t];
+      sk[t] = make_int2(diag[k], rowptr[k + 1]);
+    }
     wave_sync();
     int ready_upto = 0, spins = 0;
+    // software pipeline: the pivot and the first 64 entries of the next ready
+    // pivot row are in flight while the current one is applied
+    double ukk = 0.0, u0 = 0.0;
+    int j0 = -1;
+    bool have = false;
     for (int t = 0; t < dl; t++) {
       if (t >= ready_upto) {
         for (;;) {
@@ -237,18 +255,47 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
             ready_upto = t + first_bad;
             break;
           }
-          if (!bcast0(keep_waiting(&spins, stall) ? 1u : 0u)) {
+          // entry t itself is missing: poll that one flag (a single request
+          // per wave) until it is set, then re-check the batch
+          const int kt = sc[t];
+          bool go = true;
+          while (go && bcast0((unsigned int)ld_flag(ready + kt)) != (unsigned int)epoch)
+            go = bcast0(keep_waiting(&spins, stall) ? 1u : 0u) != 0u;
+          if (!go) {
             ready_upto = dl;
             break;
           }
         }
         if (!LIGHT) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
-      const int k = sc[t];
-      const int dk = diag[k];
-      const int ke = rowptr[k + 1];
-      const double lik = sv[t] / (LIGHT ? ld_coh(val + dk) : val[dk]);
-      for (int q = dk + 1 + lane; q < ke; q += WAVE) {
+      const int2 kk = sk[t];
+      if (!have) {
+        ukk = LIGHT ? ld_coh(val + kk.x) : val[kk.x];
+        const int q = kk.x + 1 + lane;
+        j0 = -1;
+        if (q < kk.y) {
+          j0 = col[q];
+          u0 = LIGHT ? ld_coh(val + q) : val[q];
+        }
+      }
+      double ukk_n = 0.0, u0_n = 0.0;
+      int j0_n = -1;
+      const bool have_n = t + 1 < dl && t + 1 < ready_upto;
+      if (have_n) {
+        const int2 kn = sk[t + 1];
+        ukk_n = LIGHT ? ld_coh(val + kn.x) : val[kn.x];
+        const int q = kn.x + 1 + lane;
+        if (q < kn.y) {
+          j0_n = col[q];
+          u0_n = LIGHT ? ld_coh(val + q) : val[q];
+        }
+      }
+      const double lik = sv[t] / ukk;
+      if (j0 >= 0) {
+        const int p = lower_bound_i(sc, t + 1, len, j0);
+        if (p < len && sc[p] == j0) sv[p] = __builtin_fma(-lik, u0, sv[p]);
+      }
+      for (int q = kk.x + 1 + WAVE + lane; q < kk.y; q += WAVE) {
         const int j = col[q];
         const double u = LIGHT ? ld_coh(val + q) : val[q];
         const int p = lower_bound_i(sc, t + 1, len, j);
@@ -257,6 +304,10 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
       wave_sync();
       sv[t] = lik;  // every lane writes the same value
       wave_sync();
+      ukk = ukk_n;
+      u0 = u0_n;
+      j0 = j0_n;
+      have = have_n;
     }
     for (int t = lane; t < len; t += WAVE) {
       if (LIGHT)
@@ -393,12 +444,30 @@ __global__ __launch_bounds__(256) void k_trisolve_vflag(
     }
     int spins = 0;
     double s = 0.0;
-    for (int q = b + gl; q < e; q += G) {
-      const int k = MODE <= 1 ? col[q] : trow[q];
-      const double v = MODE <= 1 ? val[q] : val[tpos[q]];
-      double yk = ld_coh(y + k);
-      while (is_sentinel(yk) && keep_waiting(&spins, stall)) yk = ld_coh(y + k);
-      s += v * yk;
+    // batches of VB entries per lane: all VB dependency loads are in flight
+    // together, then each is checked (and re-polled only if not yet written);
+    // the per-lane summation order stays ascending
+    constexpr int VB = 8;
+    for (int q0 = b + gl; q0 < e; q0 += VB * G) {
+      int k[VB];
+      double v[VB], yk[VB];
+#pragma unroll
+      for (int u = 0; u < VB; u++) {
+        const int q = q0 + u * G;
+        k[u] = n;
+        v[u] = 0.0;
+        if (q < e) {
+          k[u] = MODE <= 1 ? col[q] : trow[q];
+          v[u] = MODE <= 1 ? val[q] : val[tpos[q]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < VB; u++) yk[u] = q0 + u * G < e ? ld_coh(y + k[u]) : 0.0;
+#pragma unroll
+      for (int u = 0; u < VB; u++) {
+        while (is_sentinel(yk[u]) && keep_waiting(&spins, stall)) yk[u] = ld_coh(y + k[u]);
+        if (q0 + u * G < e) s += v[u] * yk[u];
+      }
     }
     for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, WAVE);
     const double ci = c[i];
@@ -418,6 +487,82 @@ __global__ void k_sync_prep(SyncState* ss, int mask) {
   if (threadIdx.x == 0 && blockIdx.x == 0) sync_prep(ss, mask);
 }
 
+// Several right-hand sides in one launch (nr <= NR, column-major with leading
+// dimension ld = n + 1): each entry's NR dependency loads are in flight
+// together; the dependency depth is paid once for all columns.
+template <int MODE, int NR>
+__global__ __launch_bounds__(256) void k_trisolve_vflag_mr(
+    int n, int nr, int ld, int nchunks, const int* __restrict__ ch_start,
+    const int* __restrict__ ch_meta, const int* __restrict__ rows, const int* __restrict__ rowptr,
+    const int* __restrict__ col, const int* __restrict__ diag, const int* __restrict__ tptr,
+    const int* __restrict__ trow, const int* __restrict__ tpos, const double* __restrict__ val,
+    const double* __restrict__ c, double* y, SyncState* ss, int slot, int* stall) {
+  const int lane = threadIdx.x % WAVE;
+  unsigned int* ticket = &ss->ticket[slot];
+  for (;;) {
+    const unsigned int tk = bcast0(atomicAdd(ticket, lane == 0 ? 1u : 0u));
+    if (tk >= (unsigned int)nchunks) break;
+    const int meta = ch_meta[tk];
+    const int lg = meta >> 8, cnt = meta & 0xff;
+    const int G = 1 << lg;
+    const int grp = lane >> lg, gl = lane & (G - 1);
+    const bool active = grp < cnt;
+    const int i = active ? rows[ch_start[tk] + grp] : n;
+    int b = 0, e = 0, dpos = 0;
+    if (active) {
+      if (MODE == 0) {
+        b = rowptr[i];
+        e = diag[i];
+      } else if (MODE == 1) {
+        dpos = diag[i];
+        b = dpos + 1;
+        e = rowptr[i + 1];
+      } else if (MODE == 2) {
+        b = tptr[i];
+        e = tptr[i + 1] - 1;
+        dpos = tpos[e];
+      } else {
+        b = tptr[i];
+        e = tptr[i + 1];
+      }
+    }
+    int spins = 0;
+    double acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) acc[r] = 0.0;
+    for (int q = b + gl; q < e; q += G) {
+      const int k = MODE <= 1 ? col[q] : trow[q];
+      const double v = MODE <= 1 ? val[q] : val[tpos[q]];
+      double yk[NR];
+#pragma unroll
+      for (int r = 0; r < NR; r++) yk[r] = r < nr ? ld_coh(y + (size_t)r * ld + k) : 0.0;
+#pragma unroll
+      for (int r = 0; r < NR; r++) {
+        while (is_sentinel(yk[r]) && keep_waiting(&spins, stall))
+          yk[r] = ld_coh(y + (size_t)r * ld + k);
+        acc[r] += v * yk[r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+      double s = acc[r];
+      for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, WAVE);
+      if (r < nr) {
+        const double ci = c[(size_t)r * ld + i];
+        st_coh(y + (size_t)r * ld + i,
+               (MODE == 0 || MODE == 3) ? ci - s : (ci - s) / val[dpos]);
+      }
+    }
+  }
+}
+
+// multi-column gather: c[r][i] = x[r][perm[i]] (x: ld n, c/y/z: ld n + 1),
+// y and z set to the sentinel; plus the sync_prep of mask
+__global__ void k_gather_sentinel_mr(int n, int nr, const int* __restrict__ perm,
+                                     const double* __restrict__ x, double* __restrict__ c,
+                                     double* __restrict__ y, double* __restrict__ z,
+                                     SyncState* ss, int mask);
+
 // c[i] = x[perm[i]], and the two solve outputs y, z set to the sentinel
 __global__ void k_gather_sentinel(int n, const int* __restrict__ perm,
                                   const double* __restrict__ x, double* __restrict__ c,
@@ -431,6 +576,30 @@ __global__ void k_gather_sentinel(int n, const int* __restrict__ perm,
     z[i] = sent;
   }
   if (ss && i == 0) sync_prep(ss, mask);
+}
+
+__global__ void k_gather_sentinel_mr(int n, int nr, const int* __restrict__ perm,
+                                     const double* __restrict__ x, double* __restrict__ c,
+                                     double* __restrict__ y, double* __restrict__ z,
+                                     SyncState* ss, int mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i < n && r < nr) {
+    const size_t o = (size_t)r * (n + 1) + i;
+    c[o] = x[(size_t)r * n + perm[i]];
+    const double sent = __longlong_as_double((long long)SENTINEL);
+    y[o] = sent;
+    z[o] = sent;
+  }
+  if (ss && i == 0 && r == 0) sync_prep(ss, mask);
+}
+
+// x[r][perm[i]] = z[r][i] (z: ld n + 1, x: ld n)
+__global__ void k_scatter_mr(int n, int nr, const int* __restrict__ perm,
+                             const double* __restrict__ z, double* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i < n && r < nr) x[(size_t)r * n + perm[i]] = z[(size_t)r * (n + 1) + i];
 }
 
 __global__ void k_gather_prep(int n, const int* __restrict__ perm, const double* __restrict__ x,
@@ -485,30 +654,74 @@ __global__ void k_reset_stats(DevStats* st, int what) {
   }
 }
 
-// copy of A's values and ||A||_inf (wave per row)
-__global__ void k_copy_anorm(int n, const int* __restrict__ arow, const double* __restrict__ src,
-                             double* dst, DevStats* st, SyncState* ss) {
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
-  if (ss && blockIdx.x == 0 && threadIdx.x == 0) sync_prep(ss, 1);
-  if (wave >= n) return;
-  double s = 0.0;
-  for (int p = arow[wave] + lane; p < arow[wave + 1]; p += WAVE) {
-    const double v = src[p];
-    dst[p] = v;
-    s += fabs(v);
-  }
-  s = wave_sum(s);
-  if (lane == 0) atomicMax(&st->anorm, dbits(fabs(s)));
+// ---------------------------------------------------------------------------
+// Passes over A (copy + norms, residual, SpMV).  KKT rows are short (about 8
+// entries), so 8 lanes share a row and a wave covers 8 rows; rows are
+// grid-strided and every wave issues one atomic for its reductions (one
+// atomic per row on a single address serialises the whole pass).
+// ---------------------------------------------------------------------------
+constexpr int RG = 8;  // lanes per row
+
+// max that propagates NaN (fmax would drop it and hide a broken solution)
+__device__ __forceinline__ double nanmax(double a, double b) {
+  if (a != a) return a;
+  if (b != b) return b;
+  return a > b ? a : b;
 }
 
-__global__ void k_anorm1(int n, const int* __restrict__ cptr, const int* __restrict__ cpos,
-                         const double* __restrict__ aval, DevStats* st) {
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
-  if (wave >= n) return;
-  double s = 0.0;
-  for (int t = cptr[wave] + lane; t < cptr[wave + 1]; t += WAVE) s += fabs(aval[cpos[t]]);
-  s = wave_sum(s);
-  if (lane == 0) atomicMax(&st->anorm1, dbits(fabs(s)));
+__device__ __forceinline__ double group_sum(double v) {
+  for (int off = RG / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+__device__ __forceinline__ double wave_nanmax(double v) {
+  for (int off = WAVE / 2; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off, WAVE));
+  return v;
+}
+
+// copy of A's values and ||A||_inf
+__global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict__ arow,
+                                                    const double* __restrict__ src, double* dst,
+                                                    DevStats* st, SyncState* ss) {
+  const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int nw = gridDim.x * blockDim.x / WAVE;
+  if (ss && blockIdx.x == 0 && threadIdx.x == 0) sync_prep(ss, 1);
+  double m = 0.0;
+  for (int r0 = wid * (WAVE / RG); r0 < n; r0 += nw * (WAVE / RG)) {
+    const int i = r0 + g;
+    double s = 0.0;
+    if (i < n)
+      for (int p = arow[i] + gl; p < arow[i + 1]; p += RG) {
+        const double v = src[p];
+        dst[p] = v;
+        s += fabs(v);
+      }
+    s = group_sum(s);
+    if (i < n) m = nanmax(m, s);
+  }
+  m = wave_nanmax(m);
+  if (lane == 0) atomicMax(&st->anorm, dbits(m));
+}
+
+// ||A||_1 through the column view
+__global__ __launch_bounds__(256) void k_anorm1(int n, const int* __restrict__ cptr,
+                                                const int* __restrict__ cpos,
+                                                const double* __restrict__ aval, DevStats* st) {
+  const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int nw = gridDim.x * blockDim.x / WAVE;
+  double m = 0.0;
+  for (int r0 = wid * (WAVE / RG); r0 < n; r0 += nw * (WAVE / RG)) {
+    const int j = r0 + g;
+    double s = 0.0;
+    if (j < n)
+      for (int t = cptr[j] + gl; t < cptr[j + 1]; t += RG) s += fabs(aval[cpos[t]]);
+    s = group_sum(s);
+    if (j < n) m = nanmax(m, s);
+  }
+  m = wave_nanmax(m);
+  if (lane == 0) atomicMax(&st->anorm1, dbits(m));
 }
 
 // ---------------------------------------------------------------------------
@@ -585,8 +798,8 @@ __global__ void k_scatter(int n, const int* __restrict__ perm, const double* __r
   if (i < n) y[perm[i]] = x[i];
 }
 
-// r = b - op(A) x, max |r|, max |x| (wave per row of op(A)); for op 'T' the
-// (ptr, idx, pos) triple is A's column view.
+// r = b - op(A) x, max |r|, max |x| (8 lanes per row of op(A), one atomic
+// per wave); for op 'T' the (ptr, idx, pos) triple is A's column view.
 __global__ __launch_bounds__(256) void k_residual(int n, const int* __restrict__ ptr,
                                                   const int* __restrict__ idx,
                                                   const int* __restrict__ pos,
@@ -594,18 +807,68 @@ __global__ __launch_bounds__(256) void k_residual(int n, const int* __restrict__
                                                   const double* __restrict__ b,
                                                   const double* __restrict__ x,
                                                   double* __restrict__ r, DevStats* st) {
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
-  if (wave >= n) return;
-  double s = 0.0;
-  for (int t = ptr[wave] + lane; t < ptr[wave + 1]; t += WAVE)
-    s += aval[pos ? pos[t] : t] * x[idx[t]];
-  s = wave_sum(s);
-  if (lane == 0) {
-    const double ri = b[wave] - s;
-    if (r) r[wave] = ri;
-    atomicMax(&st->rmax, dbits(fabs(ri)));
-    atomicMax(&st->xmax, dbits(fabs(x[wave])));
+  const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int nw = gridDim.x * blockDim.x / WAVE;
+  double rm = 0.0, xm = 0.0;
+  for (int r0 = wid * (WAVE / RG); r0 < n; r0 += nw * (WAVE / RG)) {
+    const int i = r0 + g;
+    double s = 0.0;
+    if (i < n)
+      for (int t = ptr[i] + gl; t < ptr[i + 1]; t += RG) s += aval[pos ? pos[t] : t] * x[idx[t]];
+    s = group_sum(s);
+    if (i < n) {
+      const double ri = b[i] - s;
+      if (r && gl == 0) r[i] = ri;
+      rm = nanmax(rm, fabs(ri));
+      xm = nanmax(xm, fabs(x[i]));
+    }
   }
+  rm = wave_nanmax(rm);
+  xm = wave_nanmax(xm);
+  if (lane == 0) {
+    atomicMax(&st->rmax, dbits(rm));
+    atomicMax(&st->xmax, dbits(xm));
+  }
+}
+
+// Column r = blockIdx.y of R = B - op(A) X (all ld n): per-column maxima
+// colmax[2r] = max |r|, colmax[2r+1] = max |x| (uint64 bit patterns).
+__global__ __launch_bounds__(256) void k_residual_mr(int n, const int* __restrict__ ptr,
+                                                     const int* __restrict__ idx,
+                                                     const int* __restrict__ pos,
+                                                     const double* __restrict__ aval,
+                                                     const double* __restrict__ B,
+                                                     const double* __restrict__ X,
+                                                     unsigned long long* colmax) {
+  const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int nw = gridDim.x * blockDim.x / WAVE;
+  const double* b = B + (size_t)blockIdx.y * n;
+  const double* x = X + (size_t)blockIdx.y * n;
+  double rm = 0.0, xm = 0.0;
+  for (int r0 = wid * (WAVE / RG); r0 < n; r0 += nw * (WAVE / RG)) {
+    const int i = r0 + g;
+    double s = 0.0;
+    if (i < n)
+      for (int t = ptr[i] + gl; t < ptr[i + 1]; t += RG) s += aval[pos ? pos[t] : t] * x[idx[t]];
+    s = group_sum(s);
+    if (i < n) {
+      rm = nanmax(rm, fabs(b[i] - s));
+      xm = nanmax(xm, fabs(x[i]));
+    }
+  }
+  rm = wave_nanmax(rm);
+  xm = wave_nanmax(xm);
+  if (lane == 0) {
+    atomicMax(colmax + 2 * blockIdx.y, dbits(rm));
+    atomicMax(colmax + 2 * blockIdx.y + 1, dbits(xm));
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0ull;
 }
 
 __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ ptr,
@@ -614,13 +877,17 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ ptr
                                               const double* __restrict__ aval,
                                               const double* __restrict__ x,
                                               double* __restrict__ y) {
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
-  if (wave >= n) return;
-  double s = 0.0;
-  for (int t = ptr[wave] + lane; t < ptr[wave + 1]; t += WAVE)
-    s += aval[pos ? pos[t] : t] * x[idx[t]];
-  s = wave_sum(s);
-  if (lane == 0) y[wave] = s;
+  const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int nw = gridDim.x * blockDim.x / WAVE;
+  for (int r0 = wid * (WAVE / RG); r0 < n; r0 += nw * (WAVE / RG)) {
+    const int i = r0 + g;
+    double s = 0.0;
+    if (i < n)
+      for (int t = ptr[i] + gl; t < ptr[i + 1]; t += RG) s += aval[pos ? pos[t] : t] * x[idx[t]];
+    s = group_sum(s);
+    if (i < n && gl == 0) y[i] = s;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -772,6 +1039,10 @@ __global__ __launch_bounds__(256) void k_grad_sddmm(int n, int nrhs, const int* 
 
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
+// grid of the grid-strided row passes: 32 rows per 256-thread block, capped
+// so that each wave loops over several row groups (one atomic per wave)
+inline int rows_grid(int n) { return std::max(1, std::min(cdiv(n, 32), 2048)); }
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -805,14 +1076,14 @@ void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStre
 
 void launch_copy_anorm(int n, const int* arow, const int*, const double* src, double* dst,
                        DevStats* st, hipStream_t s, SyncState* ss) {
-  hipLaunchKernelGGL(k_copy_anorm, dim3(cdiv((long)n * WAVE, 256)), dim3(256), 0, s, n, arow, src,
+  hipLaunchKernelGGL(k_copy_anorm, dim3(rows_grid(n)), dim3(256), 0, s, n, arow, src,
                      dst, st, ss);
 }
 
 bool launch_refactor_syncfree(const LUView& lu, const int* order, int cap, const double* aval,
                               int* ready, SyncState* ss, int* stall, bool light, hipStream_t s) {
   cap = (cap + 1) & ~1;
-  const size_t per_wave = (size_t)cap * (sizeof(double) + sizeof(int));
+  const size_t per_wave = (size_t)cap * (sizeof(double) + sizeof(int2) + sizeof(int));
   if (per_wave > 64 * 1024) return false;
   static int ncu = 0;
   if (ncu == 0) {
@@ -900,6 +1171,59 @@ void launch_trisolve_vflag(int mode, const LUView& lu, const ChunkSched& cs, con
 #undef TV_LAUNCH
 }
 
+void launch_trisolve_vflag_mr(int mode, int nr, const LUView& lu, const ChunkSched& cs,
+                              const int* tptr, const int* trow, const int* tpos, const double* c,
+                              double* y, SyncState* ss, int slot, int* stall, hipStream_t s) {
+  if (cs.nchunks <= 0 || nr <= 0) return;
+  static int ncu = 0;
+  if (ncu == 0) {
+    int d = 0;
+    (void)hipGetDevice(&d);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
+    if (ncu <= 0) ncu = 256;
+  }
+  const int grid = std::max(1, std::min(ncu * 8, cdiv(cs.nchunks, 4)));
+  const int ld = lu.n + 1;
+#define TM_LAUNCH(M, R)                                                                        \
+  hipLaunchKernelGGL((k_trisolve_vflag_mr<M, R>), dim3(grid), dim3(256), 0, s, lu.n, nr, ld,   \
+                     cs.nchunks, cs.start, cs.meta, cs.rows, lu.rowptr, lu.col, lu.diag, tptr, \
+                     trow, tpos, lu.val, c, y, ss, slot, stall)
+#define TM_MODES(R)                 \
+  switch (mode) {                   \
+    case 0: TM_LAUNCH(0, R); break; \
+    case 1: TM_LAUNCH(1, R); break; \
+    case 2: TM_LAUNCH(2, R); break; \
+    default: TM_LAUNCH(3, R); break; \
+  }
+  if (nr <= 4) {
+    TM_MODES(4)
+  } else if (nr <= 8) {
+    TM_MODES(8)
+  } else {
+    TM_MODES(MAX_RHS_PASS)
+  }
+#undef TM_MODES
+#undef TM_LAUNCH
+}
+
+void launch_gather_sentinel_mr(int n, int nr, const int* perm, const double* x, double* c,
+                               double* y, double* z, SyncState* ss, int mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_sentinel_mr, dim3(cdiv(n, 256), nr), dim3(256), 0, s, n, nr, perm,
+                     x, c, y, z, ss, mask);
+}
+
+void launch_scatter_mr(int n, int nr, const int* perm, const double* z, double* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_mr, dim3(cdiv(n, 256), nr), dim3(256), 0, s, n, nr, perm, z, x);
+}
+
+void launch_residual_mr(int n, int nr, const int* ptr, const int* idx, const int* pos,
+                        const double* aval, const double* B, const double* X,
+                        unsigned long long* colmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, colmax, 2 * nr);
+  hipLaunchKernelGGL(k_residual_mr, dim3(std::max(1, rows_grid(n) / 4), nr), dim3(256), 0, s, n,
+                     ptr, idx, pos, aval, B, X, colmax);
+}
+
 void launch_gather_sentinel(int n, const int* perm, const double* x, double* c, double* y,
                             double* z, SyncState* ss, int mask, hipStream_t s) {
   hipLaunchKernelGGL(k_gather_sentinel, dim3(cdiv(n, 256)), dim3(256), 0, s, n, perm, x, c, y, z,
@@ -917,7 +1241,7 @@ void launch_gather_prep(int n, const int* perm, const double* x, double* y, Sync
 
 void launch_anorm1(int n, const int* cptr, const int* cpos, const double* aval, DevStats* st,
                    hipStream_t s) {
-  hipLaunchKernelGGL(k_anorm1, dim3(cdiv((long)n * WAVE, 256)), dim3(256), 0, s, n, cptr, cpos,
+  hipLaunchKernelGGL(k_anorm1, dim3(rows_grid(n)), dim3(256), 0, s, n, cptr, cpos,
                      aval, st);
 }
 
@@ -963,13 +1287,13 @@ void launch_scatter(int n, const int* perm, const double* x, double* y, hipStrea
 void launch_residual(int n, char, const int* ptr, const int* idx, const int* pos,
                      const double* aval, const double* b, const double* x, double* r, DevStats* st,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, dim3(cdiv((long)n * WAVE, 256)), dim3(256), 0, s, n, ptr, idx,
+  hipLaunchKernelGGL(k_residual, dim3(rows_grid(n)), dim3(256), 0, s, n, ptr, idx,
                      pos, aval, b, x, r, st);
 }
 
 void launch_spmv(int n, char, const int* ptr, const int* idx, const int* pos, const double* aval,
                  const double* x, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_spmv, dim3(cdiv((long)n * WAVE, 256)), dim3(256), 0, s, n, ptr, idx, pos,
+  hipLaunchKernelGGL(k_spmv, dim3(rows_grid(n)), dim3(256), 0, s, n, ptr, idx, pos,
                      aval, x, y);
 }
 

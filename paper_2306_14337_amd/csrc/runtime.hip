@@ -54,6 +54,11 @@ struct kkt_ctx {
   bool light = true;  // device-coherent publication instead of acquire/release fences
   int cap = 0;        // longest LU row (LDS staging capacity)
   double *tc = nullptr, *ty = nullptr, *tz = nullptr;  // value-as-flag solve buffers (n+1)
+  // multi-column solves: (n+1) x mcap buffers (grown on demand), per-column maxima
+  double *mc = nullptr, *my = nullptr, *mz = nullptr;
+  int mcap = 0;
+  unsigned long long* colmax = nullptr;
+  unsigned long long* h_colmax = nullptr;  // pinned
   SyncState* ss = nullptr;
   int *ready_ref = nullptr, *ready_a = nullptr, *ready_b = nullptr;
   ChunkSched ch_l{}, ch_u{}, ch_ut{}, ch_lt{};
@@ -92,8 +97,12 @@ void free_device(kkt_handle h) {
   for (auto& b : h->bufs) hipFree(b.p);
   h->bufs.clear();
   h->device_bytes = 0;
-  if (h->h_st) hipHostFree(h->h_st);
+  if (h->h_st) (void)hipHostFree(h->h_st);
   h->h_st = nullptr;
+  if (h->h_colmax) (void)hipHostFree(h->h_colmax);
+  h->h_colmax = nullptr;
+  h->mc = h->my = h->mz = nullptr;
+  h->mcap = 0;
   h->lam_rm = h->x_rm = nullptr;
   h->adj_cap = 0;
   h->analyzed = h->factored = false;
@@ -196,6 +205,41 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
   }
 }
 
+// (n+1) x nr buffers of the multi-column solve
+kkt_status ensure_multi(kkt_handle h, int nr) {
+  if (h->mcap >= nr) return KKT_OK;
+  const size_t cnt = (size_t)(h->an.n + 1) * MAX_RHS_PASS;
+  kkt_status ks;
+  if ((ks = dalloc(h, &h->mc, cnt)) != KKT_OK || (ks = dalloc(h, &h->my, cnt)) != KKT_OK ||
+      (ks = dalloc(h, &h->mz, cnt)) != KKT_OK)
+    return ks;
+  h->mcap = MAX_RHS_PASS;
+  return KKT_OK;
+}
+
+// M^{-1} B for nr <= MAX_RHS_PASS columns (dependency-driven, value-as-flag)
+void apply_factors_multi(kkt_handle h, char op, int nr, const double* b, double* x,
+                         hipStream_t s) {
+  const int n = h->an.n;
+  LUView lu = view(h);
+  int* stall = &h->st->stall;
+  if (op == 'N') {
+    launch_gather_sentinel_mr(n, nr, h->pin, b, h->mc, h->my, h->mz, h->ss, 0x6, s);
+    launch_trisolve_vflag_mr(0, nr, lu, h->ch_l, nullptr, nullptr, nullptr, h->mc, h->my, h->ss,
+                             1, stall, s);
+    launch_trisolve_vflag_mr(1, nr, lu, h->ch_u, nullptr, nullptr, nullptr, h->my, h->mz, h->ss,
+                             2, stall, s);
+    launch_scatter_mr(n, nr, h->qperm, h->mz, x, s);
+  } else {
+    launch_gather_sentinel_mr(n, nr, h->qperm, b, h->mc, h->my, h->mz, h->ss, 0x6, s);
+    launch_trisolve_vflag_mr(2, nr, lu, h->ch_ut, h->ut_ptr, h->ut_row, h->ut_pos, h->mc, h->my,
+                             h->ss, 1, stall, s);
+    launch_trisolve_vflag_mr(3, nr, lu, h->ch_lt, h->lt_ptr, h->lt_row, h->lt_pos, h->my, h->mz,
+                             h->ss, 2, stall, s);
+    launch_scatter_mr(n, nr, h->pin, h->mz, x, s);
+  }
+}
+
 void op_spmv(kkt_handle h, char op, const double* x, double* y, hipStream_t s) {
   if (op == 'N')
     launch_spmv(h->an.n, 'N', h->a_rowptr, h->a_col, nullptr, h->aval, x, y, s);
@@ -222,12 +266,13 @@ kkt_status residual_eta(kkt_handle h, char op, const double* b, const double* x,
   return KKT_OK;
 }
 
-// Direct solve and FGMRES-CGS2 refinement of one right-hand side.
+// Direct solve (skipped when direct_done: x already holds it) and FGMRES-CGS2
+// refinement of one right-hand side.
 kkt_status solve_one(kkt_handle h, char op, const double* b, double* x, hipStream_t s,
-                     int* iters_out, double* eta_out, double* eta0_out) {
+                     int* iters_out, double* eta_out, double* eta0_out, bool direct_done = false) {
   const int n = h->an.n, m = h->m;
   const kkt_options& o = h->opt;
-  apply_factors(h, op, b, x, s);
+  if (!direct_done) apply_factors(h, op, b, x, s);
   double eta;
   kkt_status st = residual_eta(h, op, b, x, h->r, s, &eta);
   if (st != KKT_OK) return st;
@@ -406,7 +451,8 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
   {
     // chunked level schedules of the four triangular solves: rows of one
     // level, G lanes per row with G the smallest power of two in [4, 64]
-    // giving at most four entries per lane for the level's longest row
+    // giving at most eight entries per lane (one load batch) for the level's
+    // longest row
     auto chunks = [&](const std::vector<int32_t>& lp, const std::vector<int32_t>& rows,
                       auto len_of, ChunkSched& cs, std::vector<int32_t>& st,
                       std::vector<int32_t>& me) {
@@ -416,7 +462,7 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
         int mx = 0;
         for (int32_t t = lp[l]; t < lp[l + 1]; t++) mx = std::max(mx, (int)len_of(rows[t]));
         int lg = 2;
-        while (lg < 6 && (4 << lg) < mx) lg++;
+        while (lg < 6 && (8 << lg) < mx) lg++;
         const int per = 64 >> lg;
         for (int32_t t = lp[l]; t < lp[l + 1]; t += per) {
           st.push_back(t);
@@ -466,7 +512,8 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
     UP(h->ss, ss0);
     h->cap = 0;
     for (int v : A.lev_maxlen) h->cap = std::max(h->cap, v);
-    const bool fits = (size_t)((h->cap + 1) & ~1) * 12 <= 64 * 1024;
+    // LDS per row: value, column and pivot-row bounds of every entry (20 bytes)
+    const bool fits = (size_t)((h->cap + 1) & ~1) * 20 <= 64 * 1024;
     h->syncfree = h->opt.schedule == 2 || (h->opt.schedule == 0 && fits);
     h->light = h->opt.sync_mode != 1;
     if (h->opt.schedule == 2 && !fits) {
@@ -499,6 +546,12 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
   HIP_CHECK(h, hipMemcpy(h->lu_val, A.lu_val0.data(), f * sizeof(double), hipMemcpyHostToDevice));
   HIP_CHECK(h, hipMemcpy(h->aval, values0, (size_t)nnz * sizeof(double), hipMemcpyHostToDevice));
   HIP_CHECK(h, hipHostMalloc((void**)&h->h_st, sizeof(DevStats), hipHostMallocDefault));
+  HIP_CHECK(h, hipHostMalloc((void**)&h->h_colmax, sizeof(unsigned long long) * 2 * MAX_RHS_PASS,
+                             hipHostMallocDefault));
+  if ((ks = dalloc(h, &h->colmax, 2 * MAX_RHS_PASS)) != KKT_OK) {
+    free_device(h);
+    return ks;
+  }
   launch_reset_stats(h->st, 1 | 2 | 8, nullptr);
   launch_copy_anorm(n, h->a_rowptr, h->a_col, h->aval, h->aval, h->st, nullptr);
   launch_pivot_stats(view(h), h->st, h->opt.tiny_pivot_rel, nullptr);
@@ -572,15 +625,59 @@ kkt_status kkt_solve(kkt_handle h, char op, int32_t nrhs, const double* d_b, dou
   kkt_status worst = KKT_OK;
   int itmax = 0;
   double emax = 0.0, e0max = 0.0;
-  for (int c = 0; c < nrhs; c++) {
-    int it;
-    double eta, eta0;
-    kkt_status st = solve_one(h, op, d_b + (size_t)c * n, d_x + (size_t)c * n, s, &it, &eta, &eta0);
-    if (st < 0) return st;
+  auto account = [&](kkt_status st, int it, double eta, double eta0) {
     if (st > 0) worst = st;
     itmax = std::max(itmax, it);
     if (!(eta <= emax)) emax = eta;
     if (!(eta0 <= e0max)) e0max = eta0;
+  };
+  if (h->syncfree && h->light && nrhs > 1) {
+    // all columns of a pass through one dependency-driven launch per
+    // triangle, one read-back of every column's eta, refinement only where
+    // a column misses the target
+    for (int c0 = 0; c0 < nrhs; c0 += MAX_RHS_PASS) {
+      const int nr = std::min(MAX_RHS_PASS, nrhs - c0);
+      const double* b = d_b + (size_t)c0 * n;
+      double* x = d_x + (size_t)c0 * n;
+      kkt_status ks = ensure_multi(h, nr);
+      if (ks != KKT_OK) return ks;
+      apply_factors_multi(h, op, nr, b, x, s);
+      if (op == 'N')
+        launch_residual_mr(n, nr, h->a_rowptr, h->a_col, nullptr, h->aval, b, x, h->colmax, s);
+      else
+        launch_residual_mr(n, nr, h->at_ptr, h->at_row, h->at_pos, h->aval, b, x, h->colmax, s);
+      HIP_CHECK(h, hipMemcpyAsync(h->h_colmax, h->colmax, sizeof(unsigned long long) * 2 * nr,
+                                  hipMemcpyDeviceToHost, s));
+      HIP_CHECK(h, hipMemcpyAsync(h->h_st, h->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
+      HIP_CHECK(h, hipStreamSynchronize(s));
+      if (h->h_st->stall)
+        return fail(h, KKT_ERR_DEVICE, "a dependency wait hit its spin limit (results invalid)");
+      const double an = bits_to_double(op == 'N' ? h->h_st->anorm : h->h_st->anorm1);
+      for (int c = 0; c < nr; c++) {
+        const double rn = bits_to_double(h->h_colmax[2 * c]);
+        const double den = an * bits_to_double(h->h_colmax[2 * c + 1]);
+        const double eta0 = den == 0.0 ? (rn == 0.0 ? 0.0 : INFINITY) : rn / den;
+        if (eta0 <= h->opt.eta_target && h->opt.min_iters == 0) {
+          account(KKT_OK, 0, eta0, eta0);
+          continue;
+        }
+        int it;
+        double eta, e0;
+        kkt_status st = solve_one(h, op, b + (size_t)c * n, x + (size_t)c * n, s, &it, &eta, &e0,
+                                  true);
+        if (st < 0) return st;
+        account(st, it, eta, eta0);
+      }
+    }
+  } else {
+    for (int c = 0; c < nrhs; c++) {
+      int it;
+      double eta, eta0;
+      kkt_status st =
+          solve_one(h, op, d_b + (size_t)c * n, d_x + (size_t)c * n, s, &it, &eta, &eta0);
+      if (st < 0) return st;
+      account(st, it, eta, eta0);
+    }
   }
   HIP_CHECK(h, hipGetLastError());
   h->last_iters = itmax;

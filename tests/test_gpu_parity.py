@@ -199,3 +199,64 @@ def test_state_and_argument_errors():
     # zero right-hand sides is a no-op
     e = torch.empty(0, dtype=torch.float64, device=DEV)
     s.solve(e)
+
+
+def test_many_rhs_two_passes():
+    pat, seq = kktgen.make_sequence(500, 21, 1)
+    vals, _ = seq[0]
+    s = binding.KKTSolver()
+    s.analyze(pat.n, pat.rowptr, pat.colind, vals)
+    s.refactor(dev(vals))
+    nr = 33  # crosses the 32-column pass boundary
+    Bm = np.random.default_rng(5).standard_normal((nr, pat.n))
+    A = pat.scipy(vals)
+    for op, M in (("N", A), ("T", A.T.tocsr())):
+        X = s.solve(dev(Bm.reshape(-1)), op=op).cpu().numpy().reshape(nr, pat.n)
+        etas = [eta(M, X[r], Bm[r]) for r in range(nr)]
+        print(f"  {op}: max eta {max(etas):.3e}", flush=True)
+        assert max(etas) <= 1e-12
+
+
+def _twin(B, seed):
+    """KKT of the configs' pattern with Sigma clamped to [1e-2, 1e2] and a
+    (2,2) block of -1: condition ~1e8, so gradients can be pinned tightly."""
+    pat = kktgen.make_kkt(B, seed)
+    rng = np.random.default_rng(seed)
+    vals = pat.values(np.clip(kktgen.draw_sigma(rng, pat.n_p), 1e-2, 1e2))
+    lo = pat.rowptr[pat.n_p]
+    vals[lo:] = np.where(pat.colind[lo:] >= pat.n_p, -1.0, vals[lo:])
+    return pat, vals
+
+
+def test_autograd_function_oracle_and_finite_differences():
+    pat, vals = _twin(100, 31)
+    nrhs = 2
+    rng = np.random.default_rng(7)
+    Bm = rng.standard_normal((nrhs, pat.n))
+    Cm = rng.standard_normal((nrhs, pat.n))
+    s = binding.KKTSolver()
+    s.analyze(pat.n, pat.rowptr, pat.colind, vals)
+    v = dev(vals).requires_grad_(True)
+    b = dev(Bm.reshape(-1)).requires_grad_(True)
+    x = binding.KKTSolveFn.apply(s, v, b)
+    loss = (x * dev(Cm.reshape(-1))).sum()
+    loss.backward()
+    gv = v.grad.cpu().numpy()
+    gb = b.grad.cpu().numpy()
+    ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, vals, tau=1e-10)
+    xo, _ = ora.solve(Bm.reshape(-1))
+    lo, _ = ora.solve(Cm.reshape(-1), op="T")
+    go = ora.grad(lo, xo)
+    assert np.linalg.norm(gv - go) / np.linalg.norm(go) <= 1e-9
+    assert np.linalg.norm(gb - lo) / np.linalg.norm(lo) <= 1e-9
+    # central finite differences of L = sum_r c_r^T A^{-1} b_r (dense, float64)
+    A = pat.scipy(vals).toarray()
+    rows = np.repeat(np.arange(pat.n), np.diff(pat.rowptr))
+    h = 1e-6
+    for p in np.random.default_rng(3).choice(pat.nnz, 16, replace=False):
+        dA = np.zeros_like(A)
+        dA[rows[p], pat.colind[p]] = h
+        Lp = np.sum(Cm.T * np.linalg.solve(A + dA, Bm.T))
+        Lm = np.sum(Cm.T * np.linalg.solve(A - dA, Bm.T))
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - gv[p]) <= 1e-5 * abs(gv[p]) + 1e-7, (p, fd, gv[p])
