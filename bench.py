@@ -53,6 +53,131 @@ def cpu_baseline(pat, seq, budget_s: float = 20.0):
                        f"(oracle analysis {t_an:.1f} s not counted)")
 
 
+def _eta(A, x, b):
+    return float(np.abs(b - A @ x).max() / (abs(A).sum(1).max() * np.abs(x).max()))
+
+
+def bench_adjoint(torch, binding, kktgen, steps=5, B=10000, seed=105, nrhs=32):
+    """Forward (refactor + 32-RHS solve) + backward (32-RHS transposed solve +
+    gradient on the pattern) vs the plain loop of 2 x 32 single-RHS solves."""
+    dev = torch.device("cuda:0")
+    pat = kktgen.make_kkt(B, seed)
+    rng = np.random.default_rng(seed * 10)
+    vals = pat.values(kktgen.draw_sigma(rng, pat.n_p))
+    Bm = rng.standard_normal(nrhs * pat.n)
+    Cm = np.random.default_rng(seed * 10 + 1).standard_normal(nrhs * pat.n)
+    s = binding.KKTSolver()
+    s.analyze(pat.n, pat.rowptr, pat.colind, vals)
+    v = torch.from_numpy(vals).to(dev)
+    b = torch.from_numpy(Bm).to(dev)
+    c = torch.from_numpy(Cm).to(dev)
+    x = torch.empty_like(b)
+    lam = torch.empty_like(c)
+    g = torch.empty(pat.nnz, dtype=torch.float64, device=dev)
+
+    def fused():
+        s.refactor(v)
+        s.solve(b, x)
+        s.solve(c, lam, op="T")
+        s.grad_values(lam, x, g)
+
+    def loop():
+        s.refactor(v)
+        for r in range(nrhs):
+            sl = slice(r * pat.n, (r + 1) * pat.n)
+            s.solve(b[sl], x[sl])
+        for r in range(nrhs):
+            sl = slice(r * pat.n, (r + 1) * pat.n)
+            s.solve(c[sl], lam[sl], op="T")
+        s.grad_values(lam, x, g)
+
+    out = {}
+    for name, fn in (("fused", fused), ("loop", loop)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        out[name] = steps / (time.perf_counter() - t0)
+    A = pat.scipy(vals)
+    xh = x.cpu().numpy().reshape(nrhs, pat.n)
+    lh = lam.cpu().numpy().reshape(nrhs, pat.n)
+    eta_x = max(_eta(A, xh[r], Bm[r * pat.n:(r + 1) * pat.n]) for r in range(nrhs))
+    eta_l = max(_eta(A.T.tocsr(), lh[r], Cm[r * pat.n:(r + 1) * pat.n]) for r in range(nrhs))
+    return {"workload": f"adjoint, B={B} buses, n={pat.n}, {nrhs} RHS, fwd+bwd",
+            "fwd_bwd_per_s": out["fused"], "loop_fwd_bwd_per_s": out["loop"],
+            "speedup_vs_loop": out["fused"] / out["loop"], "eta_max_x": eta_x,
+            "eta_max_lambda": eta_l}
+
+
+def bench_batched(torch, binding, kktgen, steps=5, seed=104, n_a=128, n_b=128, B_a=2000):
+    """256 scenario instances (128 sharing one B=2000 pattern, 128 with their
+    own B ~ U[500, 5000]) in one captured graph replay, vs the plain loop of
+    per-instance refactor + solve calls on the same GPU."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    ga = kktgen.make_batch_group_a(B_a, seed, n_a)
+    gb = kktgen.make_batch_group_b(seed, seed * 10, n_b)
+    t_gen = time.perf_counter() - t0
+    insts = [(0, p, v, r) for p, v, r in ga] + [(1 + i, p, v, r) for i, (p, v, r) in enumerate(gb)]
+    patterns = [(ga[0][0].n, ga[0][0].rowptr, ga[0][0].colind, ga[0][1])]
+    patterns += [(p.n, p.rowptr, p.colind, v) for p, v, _ in gb]
+    s = binding.KKTSolver()
+    t0 = time.perf_counter()
+    s.analyze_batch(patterns, [p for p, *_ in insts])
+    t_an = time.perf_counter() - t0
+    vbuf = torch.from_numpy(np.concatenate([v for _, _, v, _ in insts])).to(dev)
+    bbuf = torch.from_numpy(np.concatenate([r for *_, r in insts])).to(dev)
+    xbuf = torch.empty_like(bbuf)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    s.graph_capture(vbuf, bbuf, xbuf, stream)
+    s.graph_launch(stream)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.graph_launch(stream)
+    stream.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    etas = s.batch_eta()
+    # plain loop: one handle per distinct pattern, instances one after another
+    handles = [None] * len(patterns)
+
+    def mk(p):
+        h = binding.KKTSolver()
+        n, rp, ci, v0 = patterns[p]
+        h.analyze(n, rp, ci, v0)
+        return h
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        handles = list(ex.map(mk, range(len(patterns))))
+    vals_d = [torch.from_numpy(v).to(dev) for _, _, v, _ in insts]
+    rhs_d = [torch.from_numpy(r).to(dev) for *_, r in insts]
+    xs = [torch.empty_like(r) for r in rhs_d]
+
+    def loop():
+        for t, (p, *_rest) in enumerate(insts):
+            handles[p].refactor(vals_d[t])
+            handles[p].solve(rhs_d[t], xs[t])
+
+    loop()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loop()
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    count = len(insts)
+    return {"workload": f"batched, {n_a} instances sharing one B={B_a} pattern + {n_b} instances "
+                        f"with own B~U[500,5000], one captured graph per batch step",
+            "instances": count, "rows_total": s.n, "ms_per_batch": t_batch * 1e3,
+            "inst_per_s": count / t_batch, "loop_inst_per_s": count / t_loop,
+            "speedup_vs_loop": t_loop / t_batch, "eta_max": float(etas.max()),
+            "generate_s": t_gen, "analyze_s": t_an}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +186,8 @@ def main():
     ap.add_argument("--buses", type=int, default=70000)
     ap.add_argument("--seed", type=int, default=103)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the adjoint and batched workloads")
     ap.add_argument("--schedule", type=int, default=0,
                     help="0 auto, 1 level-synchronous launches, 2 dependency-driven")
     ap.add_argument("--sync-mode", type=int, default=0,
@@ -164,7 +291,15 @@ def main():
         "analyze_s": t_an,
         "wall_s": wall,
     }
+    del vals_d, rhs_d, xs, s
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        print("# adjoint workload", file=sys.stderr, flush=True)
+        out["adjoint"] = bench_adjoint(torch, binding, kktgen)
+        print("# batched workload", file=sys.stderr, flush=True)
+        out["batched"] = bench_batched(torch, binding, kktgen)
     if not args.no_cpu_baseline:
+        print("# cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(pat, seq[args.warmup:])
     print(json.dumps(out), flush=True)
 

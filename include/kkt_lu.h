@@ -78,7 +78,10 @@ typedef struct {
   int32_t sync_mode;        /* dependency-driven publication: 0 default, 1 device-scope
                                acquire/release fences, 2 device-coherent accesses (the solution
                                value is its own ready flag in the triangular solves) */
-  int32_t reserved[7];
+  int32_t solve_entries_per_lane; /* triangular-solve chunking: lanes per row sized so each lane
+                                     holds at most this many entries (0 = 8; 1..64) */
+  int32_t refactor_waves_per_block; /* dependency-driven refactorization: 0 auto, 1, 2 or 4 */
+  int32_t reserved[5];
 } kkt_options;
 
 typedef struct {
@@ -157,6 +160,39 @@ kkt_status kkt_solve(kkt_handle h, char op, int32_t nrhs, const double *d_b, dou
  * Errors: STATE, INVALID_ARG, DEVICE. */
 kkt_status kkt_grad_values(kkt_handle h, int32_t nrhs, const double *d_lambda, const double *d_x,
                            double *d_grad, void *stream);
+
+/* Batch of independent instances (scenarios, contingencies) solved as one
+ * block-diagonal system in shared launches.  npat distinct patterns, pattern
+ * p given by n[p], nnz[p], rowptr[p], colind[p] and its first values
+ * values0[p]; instance t uses pattern inst_pattern[t] (count instances) and
+ * reuses that pattern's ordering, pivot sequence and factor pattern, the
+ * refactorization premise of Sections 4 and 5.1.  Patterns are analysed in
+ * parallel host threads.  Afterwards the handle works on the concatenation:
+ * kkt_refactor takes all instances' values back to back (CSR order of each),
+ * kkt_solve / kkt_graph_* take all right-hand sides back to back, and eta is
+ * judged per instance (kkt_batch_eta).  Errors as kkt_analyze. */
+kkt_status kkt_analyze_batch(kkt_handle h, int32_t npat, const int32_t *n, const int64_t *nnz,
+                             const int64_t *const *rowptr, const int32_t *const *colind,
+                             const double *const *values0, int32_t count,
+                             const int32_t *inst_pattern);
+/* Instance offsets of a batch: row_offset[count+1] into vectors,
+ * nnz_offset[count+1] into the concatenated values (either may be NULL). */
+kkt_status kkt_batch_layout(kkt_handle h, int64_t *row_offset, int64_t *nnz_offset);
+/* eta of every instance after the last solve or graph replay (count
+ * entries); synchronises. */
+kkt_status kkt_batch_eta(kkt_handle h, double *eta);
+
+/* Capture refactor(d_values) + direct solve (d_b -> d_x) + the residual check
+ * into a HIP graph on `stream` (not the legacy default stream); every
+ * scheduling counter lives on the device, so replays are independent.  The
+ * graph has no host synchronisation and no refinement: after a replay,
+ * kkt_sync_report / kkt_batch_eta give eta, and kkt_solve refines if needed.
+ * The buffers must stay allocated while the graph exists; new values and
+ * right-hand sides are written into the same buffers between replays.
+ * Errors: STATE, INVALID_ARG, DEVICE. */
+kkt_status kkt_graph_capture(kkt_handle h, const double *d_values, const double *d_b,
+                             double *d_x, void *stream);
+kkt_status kkt_graph_launch(kkt_handle h, void *stream);
 
 /* Wait for the handle's device work and return (then clear) the report. */
 kkt_status kkt_sync_report(kkt_handle h, kkt_report *out);

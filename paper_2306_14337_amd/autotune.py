@@ -1,0 +1,110 @@
+"""Schedule autotuner: picks the launch schedule of the refactor/solve path for
+one sparsity pattern by timing candidates on the user's own matrix.
+
+Knobs (all fields of the C options struct):
+  schedule                  1 level-synchronous launches, 2 dependency-driven
+  sync_mode                 1 acquire/release fences, 2 device-coherent accesses
+  solve_entries_per_lane    triangular-solve lanes per row (entries per lane)
+  refactor_waves_per_block  rows in flight per workgroup in the refactorization
+
+The winner is cached in a JSON file keyed by a hash of the pattern (n, row
+pointers, column indices), so a later run with the same pattern skips the
+search.  Candidates that fail (e.g. a schedule the pattern cannot use) are
+skipped.
+"""
+from __future__ import annotations
+
+import hashlib
+import itertools
+import json
+import os
+import time
+
+import numpy as np
+
+DEFAULT_CACHE = os.environ.get(
+    "KKTLU_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "kktlu_autotune.json"))
+
+
+def pattern_key(n, rowptr, colind) -> str:
+    h = hashlib.sha256()
+    h.update(np.int64(n).tobytes())
+    h.update(np.ascontiguousarray(rowptr, dtype=np.int64).tobytes())
+    h.update(np.ascontiguousarray(colind, dtype=np.int32).tobytes())
+    return h.hexdigest()[:32]
+
+
+def candidates(full: bool = False):
+    """Option dicts to try; the first is the library default."""
+    out = [dict(schedule=2, sync_mode=2, solve_entries_per_lane=8, refactor_waves_per_block=0)]
+    spl = (2, 4, 8, 16) if full else (4, 8, 16)
+    wpb = (0, 1, 2, 4) if full else (0, 1)
+    for s, e, w in itertools.product((1, 2), spl, wpb):
+        c = dict(schedule=2, sync_mode=s, solve_entries_per_lane=e, refactor_waves_per_block=w)
+        if c not in out:
+            out.append(c)
+    out.append(dict(schedule=1, sync_mode=0, solve_entries_per_lane=8, refactor_waves_per_block=0))
+    return out
+
+
+def load_cache(path: str = DEFAULT_CACHE) -> dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def store_cache(key: str, entry: dict, path: str = DEFAULT_CACHE) -> None:
+    cache = load_cache(path)
+    cache[key] = entry
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def autotune(n, rowptr, colind, values0, d_values, d_b, repeats: int = 3, full: bool = False,
+             cache_path: str | None = DEFAULT_CACHE, base_options: dict | None = None):
+    """Time refactor+solve for every candidate on (d_values, d_b) and return
+    (best option dict, {candidate index: seconds per step}).  Uses the cache
+    when the pattern was tuned before."""
+    import torch
+
+    from . import binding
+
+    key = pattern_key(n, rowptr, colind)
+    if cache_path:
+        hit = load_cache(cache_path).get(key)
+        if hit:
+            return dict(hit["options"]), {}
+    base = dict(base_options or {})
+    times = {}
+    best, best_t = None, float("inf")
+    for idx, cand in enumerate(candidates(full)):
+        opts = {**base, **cand}
+        try:
+            s = binding.KKTSolver(**opts)
+            s.analyze(n, rowptr, colind, values0)
+            x = torch.empty_like(d_b)
+            s.refactor(d_values)
+            s.solve(d_b, x)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(repeats):
+                s.refactor(d_values)
+                s.solve(d_b, x)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / repeats
+            s.close()
+        except binding.KKTError:
+            continue
+        times[idx] = dt
+        if dt < best_t:
+            best, best_t = cand, dt
+    if best is None:
+        raise RuntimeError("no autotuner candidate ran")
+    if cache_path:
+        store_cache(key, {"options": best, "seconds_per_step": best_t, "n": int(n)}, cache_path)
+    return dict(best), times

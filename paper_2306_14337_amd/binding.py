@@ -34,6 +34,8 @@ EXPORTS = [
     "kkt_update_matrix", "kkt_solve", "kkt_grad_values", "kkt_sync_report", "kkt_get_info", "kkt_get_perm",
     "kkt_get_lu", "kkt_last_error", "kkt_analysis_create", "kkt_analysis_info",
     "kkt_analysis_perm", "kkt_analysis_lu", "kkt_analysis_levels", "kkt_analysis_destroy",
+    "kkt_analyze_batch", "kkt_batch_layout", "kkt_batch_eta", "kkt_graph_capture",
+    "kkt_graph_launch",
 ]
 
 
@@ -47,7 +49,9 @@ class Options(C.Structure):
     _fields_ = [("ordering", C.c_int32), ("pivot_tau", C.c_double), ("fgmres_restart", C.c_int32),
                 ("fgmres_max_iters", C.c_int32), ("min_iters", C.c_int32),
                 ("eta_target", C.c_double), ("tiny_pivot_rel", C.c_double), ("device", C.c_int32),
-                ("schedule", C.c_int32), ("sync_mode", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("schedule", C.c_int32), ("sync_mode", C.c_int32),
+                ("solve_entries_per_lane", C.c_int32), ("refactor_waves_per_block", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class Report(C.Structure):
@@ -96,6 +100,11 @@ def lib():
         L.kkt_analysis_levels.argtypes = [P, P, P]
         L.kkt_analysis_destroy.argtypes = [P]
         L.kkt_analysis_destroy.restype = None
+        L.kkt_analyze_batch.argtypes = [P, C.c_int32, P, P, P, P, P, C.c_int32, P]
+        L.kkt_batch_layout.argtypes = [P, P, P]
+        L.kkt_batch_eta.argtypes = [P, P]
+        L.kkt_graph_capture.argtypes = [P, P, P, P, P]
+        L.kkt_graph_launch.argtypes = [P, P]
         _lib = L
     return _lib
 
@@ -248,6 +257,46 @@ class KKTSolver:
         self.n = int(n)
         self.nnz = int(rp[-1])
         return st
+
+    def analyze_batch(self, patterns, inst_pattern) -> int:
+        """Block-diagonal batch: patterns = [(n, rowptr, colind, values0), ...],
+        inst_pattern[t] = pattern of instance t."""
+        npat = len(patterns)
+        keep = [_csr_host(rp, ci, v) for (_, rp, ci, v) in patterns]
+        ns = np.array([int(p[0]) for p in patterns], np.int32)
+        nnzs = np.array([int(k[0][-1]) for k in keep], np.int64)
+        PP = C.c_void_p * npat
+        rps = PP(*[k[0].ctypes.data for k in keep])
+        cis = PP(*[k[1].ctypes.data for k in keep])
+        vs = PP(*[k[2].ctypes.data for k in keep])
+        ip = np.ascontiguousarray(inst_pattern, dtype=np.int32)
+        st = lib().kkt_analyze_batch(self._h, npat, _np_ptr(ns), _np_ptr(nnzs), rps, cis, vs,
+                                     len(ip), _np_ptr(ip))
+        self._check(st)
+        self.count = len(ip)
+        ro = np.empty(self.count + 1, np.int64)
+        no = np.empty(self.count + 1, np.int64)
+        self._check(lib().kkt_batch_layout(self._h, _np_ptr(ro), _np_ptr(no)))
+        self.row_offset, self.nnz_offset = ro, no
+        self.n = int(ro[-1])
+        self.nnz = int(no[-1])
+        return st
+
+    def batch_eta(self) -> np.ndarray:
+        e = np.empty(self.count, np.float64)
+        self._check(lib().kkt_batch_eta(self._h, _np_ptr(e)))
+        return e
+
+    def graph_capture(self, values, b, x, stream) -> int:
+        """Capture refactor + direct solve + residual check on a non-default stream."""
+        st = lib().kkt_graph_capture(self._h, _dev_f64(values, self.nnz, "values"),
+                                     _dev_f64(b, name="b"), _dev_f64(x, b.numel(), "x"),
+                                     C.c_void_p(stream.cuda_stream))
+        self._graph_keep = (values, b, x)
+        return self._check(st)
+
+    def graph_launch(self, stream) -> int:
+        return self._check(lib().kkt_graph_launch(self._h, C.c_void_p(stream.cuda_stream)))
 
     def refactor(self, values, stream=None) -> int:
         p = _dev_f64(values, self.nnz, "values")

@@ -12,10 +12,12 @@
 #include "analyze.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <limits>
 #include <set>
+#include <thread>
 
 #include "../../include/kkt_lu.h"
 
@@ -475,6 +477,157 @@ int analyze(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colind
     levels_forward(n, ptr, idx, A.ltlev_ptr, A.ltlev_rows, true);
   }
   return A.warn_singular ? KKT_WARN_NUMERICALLY_SINGULAR : KKT_OK;
+}
+
+}  // namespace kktlu
+
+namespace kktlu {
+
+int analyze_batch(int32_t npat, const int32_t* n, const int64_t* nnz,
+                  const int64_t* const* rowptr, const int32_t* const* colind,
+                  const double* const* values0, int32_t count, const int32_t* inst_pattern,
+                  const AnalyzeOptions& opt, Analysis& out, std::vector<int64_t>& row_off,
+                  std::vector<int64_t>& nnz_off, std::string* msg) {
+  if (npat <= 0 || count <= 0 || !n || !nnz || !rowptr || !colind || !values0 || !inst_pattern) {
+    if (msg) *msg = "batch: bad counts or null arrays";
+    return KKT_ERR_INVALID_ARG;
+  }
+  for (int32_t t = 0; t < count; t++)
+    if (inst_pattern[t] < 0 || inst_pattern[t] >= npat) {
+      if (msg) *msg = "batch: inst_pattern out of range";
+      return KKT_ERR_INVALID_ARG;
+    }
+  // one analysis per distinct pattern, patterns spread over host threads
+  std::vector<Analysis> pa(npat);
+  std::vector<int> pst(npat, KKT_OK);
+  std::vector<std::string> pmsg(npat);
+  {
+    std::atomic<int> next(0);
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nth = (int)std::min<unsigned>(hw, (unsigned)npat);
+    auto work = [&]() {
+      for (int p = next++; p < npat; p = next++) {
+        try {
+          pst[p] = analyze(n[p], nnz[p], rowptr[p], colind[p], values0[p], nullptr, opt, pa[p],
+                           &pmsg[p]);
+        } catch (const std::bad_alloc&) {
+          pst[p] = KKT_ERR_OUT_OF_MEMORY;
+          pmsg[p] = "host allocation failed";
+        }
+      }
+    };
+    std::vector<std::thread> th;
+    for (int k = 1; k < nth; k++) th.emplace_back(work);
+    work();
+    for (auto& x : th) x.join();
+  }
+  int warn = 0;
+  for (int32_t p = 0; p < npat; p++) {
+    if (pst[p] < 0) {
+      if (msg) *msg = "batch pattern " + std::to_string(p) + ": " + pmsg[p];
+      return pst[p];
+    }
+    warn |= pa[p].warn_singular;
+  }
+  row_off.assign(count + 1, 0);
+  nnz_off.assign(count + 1, 0);
+  std::vector<int64_t> f_off(count + 1, 0), l_off(count + 1, 0), u_off(count + 1, 0);
+  size_t nlev = 0, nulev = 0, nutlev = 0, nltlev = 0;
+  for (int32_t t = 0; t < count; t++) {
+    const Analysis& a = pa[inst_pattern[t]];
+    row_off[t + 1] = row_off[t] + a.n;
+    nnz_off[t + 1] = nnz_off[t] + a.nnz;
+    f_off[t + 1] = f_off[t] + (int64_t)a.lu_col.size();
+    l_off[t + 1] = l_off[t] + a.nnz_l;
+    u_off[t + 1] = u_off[t] + a.nnz_u;
+    nlev = std::max(nlev, a.lev_ptr.size() - 1);
+    nulev = std::max(nulev, a.ulev_ptr.size() - 1);
+    nutlev = std::max(nutlev, a.utlev_ptr.size() - 1);
+    nltlev = std::max(nltlev, a.ltlev_ptr.size() - 1);
+  }
+  const int64_t N = row_off[count], NNZ = nnz_off[count], F = f_off[count];
+  const int64_t lim = std::numeric_limits<int32_t>::max();
+  if (N > lim || NNZ > lim || F > lim) {
+    if (msg) *msg = "batch exceeds the int32 index range";
+    return KKT_ERR_TOO_LARGE;
+  }
+  Analysis& A = out;
+  A = Analysis();
+  A.n = (int32_t)N;
+  A.nnz = NNZ;
+  A.nnz_l = l_off[count];
+  A.nnz_u = u_off[count];
+  A.warn_singular = warn;
+  A.Q.resize(N);
+  A.Qinv.resize(N);
+  A.P.resize(N);
+  A.Pinv.resize(N);
+  A.lu_rowptr.resize(N + 1);
+  A.diag.resize(N);
+  A.lu_col.resize(F);
+  A.lu_val0.resize(F);
+  A.lu_src.resize(F);
+  A.ut_ptr.resize(N + 1);
+  A.lt_ptr.resize(N + 1);
+  A.ut_pos.resize(A.nnz_u);
+  A.lt_pos.resize(A.nnz_l);
+  for (int32_t t = 0; t < count; t++) {
+    const Analysis& a = pa[inst_pattern[t]];
+    const int32_t ro = (int32_t)row_off[t], fo = (int32_t)f_off[t], no = (int32_t)nnz_off[t];
+    const int32_t lo = (int32_t)l_off[t], uo = (int32_t)u_off[t];
+    for (int32_t k = 0; k < a.n; k++) {
+      A.Q[ro + k] = ro + a.Q[k];
+      A.Qinv[ro + k] = ro + a.Qinv[k];
+      A.P[ro + k] = ro + a.P[k];
+      A.Pinv[ro + k] = ro + a.Pinv[k];
+      A.lu_rowptr[ro + k] = fo + a.lu_rowptr[k];
+      A.diag[ro + k] = fo + a.diag[k];
+      A.ut_ptr[ro + k] = uo + a.ut_ptr[k];
+      A.lt_ptr[ro + k] = lo + a.lt_ptr[k];
+    }
+    for (size_t q = 0; q < a.lu_col.size(); q++) {
+      A.lu_col[fo + q] = ro + a.lu_col[q];
+      A.lu_val0[fo + q] = a.lu_val0[q];
+      A.lu_src[fo + q] = a.lu_src[q] >= 0 ? no + a.lu_src[q] : -1;
+    }
+    for (size_t q = 0; q < a.ut_pos.size(); q++) A.ut_pos[uo + q] = fo + a.ut_pos[q];
+    for (size_t q = 0; q < a.lt_pos.size(); q++) A.lt_pos[lo + q] = fo + a.lt_pos[q];
+  }
+  A.lu_rowptr[N] = (int32_t)F;
+  A.ut_ptr[N] = (int32_t)A.nnz_u;
+  A.lt_ptr[N] = (int32_t)A.nnz_l;
+  // level schedules merged level by level (instances are independent, so the
+  // depth is the largest instance depth, not the sum)
+  auto merge = [&](size_t levels, std::vector<int32_t> Analysis::*ptr,
+                   std::vector<int32_t> Analysis::*rows, std::vector<int32_t>& optr,
+                   std::vector<int32_t>& orows) {
+    optr.assign(levels + 1, 0);
+    for (int32_t t = 0; t < count; t++) {
+      const Analysis& a = pa[inst_pattern[t]];
+      const auto& lp = a.*ptr;
+      for (size_t l = 0; l + 1 < lp.size(); l++) optr[l + 1] += lp[l + 1] - lp[l];
+    }
+    for (size_t l = 0; l < levels; l++) optr[l + 1] += optr[l];
+    orows.assign(N, 0);
+    std::vector<int32_t> fill(optr.begin(), optr.end() - 1);
+    for (int32_t t = 0; t < count; t++) {
+      const Analysis& a = pa[inst_pattern[t]];
+      const auto& lp = a.*ptr;
+      const auto& lr = a.*rows;
+      const int32_t ro = (int32_t)row_off[t];
+      for (size_t l = 0; l + 1 < lp.size(); l++)
+        for (int32_t q = lp[l]; q < lp[l + 1]; q++) orows[fill[l]++] = ro + lr[q];
+    }
+  };
+  merge(nlev, &Analysis::lev_ptr, &Analysis::lev_rows, A.lev_ptr, A.lev_rows);
+  merge(nulev, &Analysis::ulev_ptr, &Analysis::ulev_rows, A.ulev_ptr, A.ulev_rows);
+  merge(nutlev, &Analysis::utlev_ptr, &Analysis::utlev_rows, A.utlev_ptr, A.utlev_rows);
+  merge(nltlev, &Analysis::ltlev_ptr, &Analysis::ltlev_rows, A.ltlev_ptr, A.ltlev_rows);
+  A.lev_maxlen.assign(nlev, 0);
+  for (int32_t p = 0; p < npat; p++)
+    for (size_t l = 0; l < pa[p].lev_maxlen.size(); l++)
+      A.lev_maxlen[l] = std::max(A.lev_maxlen[l], pa[p].lev_maxlen[l]);
+  return warn ? KKT_WARN_NUMERICALLY_SINGULAR : KKT_OK;
 }
 
 }  // namespace kktlu

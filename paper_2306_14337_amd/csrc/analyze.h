@@ -54,4 +54,16 @@ int analyze(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colind
             const double* values0, const int32_t* user_q, const AnalyzeOptions& opt,
             Analysis& out, std::string* msg);
 
+// Batch of independent instances as one block-diagonal system: pattern p
+// (n[p], nnz[p], rowptr[p], colind[p], values0[p]) is analysed once (patterns
+// in parallel threads) and instance t is a copy of the analysis of pattern
+// inst_pattern[t] with its rows and A positions offset; the level schedules
+// are merged level by level.  row_off / nnz_off get the instance offsets
+// (count + 1 entries).
+int analyze_batch(int32_t npat, const int32_t* n, const int64_t* nnz,
+                  const int64_t* const* rowptr, const int32_t* const* colind,
+                  const double* const* values0, int32_t count, const int32_t* inst_pattern,
+                  const AnalyzeOptions& opt, Analysis& out, std::vector<int64_t>& row_off,
+                  std::vector<int64_t>& nnz_off, std::string* msg);
+
 }  // namespace kktlu

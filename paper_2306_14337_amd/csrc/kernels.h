@@ -59,8 +59,10 @@ void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxl
 // Every wait is bounded: past the spin limit a wave sets *stall, and waves
 // that see *stall stop waiting, so the grid always drains.
 // light: device-coherent data accesses instead of acquire/release fences.
+// wpb_pref: waves (rows in flight) per workgroup, 0 = chosen from the LDS need.
 bool launch_refactor_syncfree(const LUView& lu, const int* order, int cap, const double* aval,
-                              int* ready, SyncState* ss, int* stall, bool light, hipStream_t s);
+                              int* ready, SyncState* ss, int* stall, bool light, int wpb_pref,
+                              hipStream_t s);
 // Dependency-driven triangular solve of one right-hand side in place on y.
 // mode 0: unit L rows, 1: U rows, 2: U^T columns (tptr/trow/tpos view of U),
 // 3: unit L^T columns (view of strict L).  slot: SyncState slot (1 or 2).
@@ -101,12 +103,18 @@ void launch_gather_prep(int n, const int* perm, const double* x, double* y, Sync
 // pivot statistics (min/max |u_kk|, tiny test against tiny_rel * ||A||_inf)
 void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStream_t s);
 
-// A copy + ||A||_inf (and, if ss != nullptr, the sync_prep of slot 0)
+// A copy + ||A||_inf (and, if ss != nullptr, the sync_prep of slot 0; if
+// rowabs != nullptr, every row's absolute sum)
 void launch_copy_anorm(int n, const int* arow, const int* acol, const double* src, double* dst,
-                       DevStats* st, hipStream_t s, SyncState* ss = nullptr);
-// ||A||_1 through the column view
+                       DevStats* st, hipStream_t s, SyncState* ss = nullptr,
+                       double* rowabs = nullptr);
+// ||A||_1 through the column view (and every column's absolute sum)
 void launch_anorm1(int n, const int* cptr, const int* cpos, const double* aval, DevStats* st,
-                   hipStream_t s);
+                   hipStream_t s, double* colabs = nullptr);
+// per-instance maxima of a block-diagonal batch: out[3t..3t+2] = max matabs,
+// max |r|, max |x| over rows [row_off[t], row_off[t+1])
+void launch_seg_stats(int count, const int* row_off, const double* matabs, const double* r,
+                      const double* x, double* out, hipStream_t s);
 void launch_reset_stats(DevStats* st, int what, hipStream_t s);
 
 // triangular solves on one right-hand side, in place on y

@@ -679,10 +679,46 @@ __device__ __forceinline__ double wave_nanmax(double v) {
   return v;
 }
 
-// copy of A's values and ||A||_inf
+// Per-instance maxima of a block-diagonal batch: block t reduces rows
+// [row_off[t], row_off[t+1]) to out[3t] = max matabs (the instance's matrix
+// norm), out[3t+1] = max |r|, out[3t+2] = max |x|.
+__global__ __launch_bounds__(256) void k_seg_stats(const int* __restrict__ row_off,
+                                                   const double* __restrict__ matabs,
+                                                   const double* __restrict__ r,
+                                                   const double* __restrict__ x,
+                                                   double* __restrict__ out) {
+  __shared__ double red[3][256 / WAVE];
+  const int t = blockIdx.x;
+  const int a = row_off[t], b = row_off[t + 1];
+  double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+  for (int i = a + threadIdx.x; i < b; i += blockDim.x) {
+    m0 = nanmax(m0, matabs[i]);
+    m1 = nanmax(m1, fabs(r[i]));
+    m2 = nanmax(m2, fabs(x[i]));
+  }
+  m0 = wave_nanmax(m0);
+  m1 = wave_nanmax(m1);
+  m2 = wave_nanmax(m2);
+  const int w = threadIdx.x / WAVE;
+  if (threadIdx.x % WAVE == 0) {
+    red[0][w] = m0;
+    red[1][w] = m1;
+    red[2][w] = m2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double m = 0.0;
+    for (int q = 0; q < 256 / WAVE; q++) m = nanmax(m, red[threadIdx.x][q]);
+    out[3 * t + threadIdx.x] = m;
+  }
+}
+
+// copy of A's values and ||A||_inf (and, if rowabs != nullptr, every row's
+// absolute sum for per-instance norms)
 __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict__ arow,
                                                     const double* __restrict__ src, double* dst,
-                                                    DevStats* st, SyncState* ss) {
+                                                    DevStats* st, SyncState* ss,
+                                                    double* __restrict__ rowabs) {
   const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = gridDim.x * blockDim.x / WAVE;
@@ -698,7 +734,10 @@ __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict
         s += fabs(v);
       }
     s = group_sum(s);
-    if (i < n) m = nanmax(m, s);
+    if (i < n) {
+      m = nanmax(m, s);
+      if (rowabs && gl == 0) rowabs[i] = s;
+    }
   }
   m = wave_nanmax(m);
   if (lane == 0) atomicMax(&st->anorm, dbits(m));
@@ -707,7 +746,8 @@ __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict
 // ||A||_1 through the column view
 __global__ __launch_bounds__(256) void k_anorm1(int n, const int* __restrict__ cptr,
                                                 const int* __restrict__ cpos,
-                                                const double* __restrict__ aval, DevStats* st) {
+                                                const double* __restrict__ aval, DevStats* st,
+                                                double* __restrict__ colabs) {
   const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = gridDim.x * blockDim.x / WAVE;
@@ -718,7 +758,10 @@ __global__ __launch_bounds__(256) void k_anorm1(int n, const int* __restrict__ c
     if (j < n)
       for (int t = cptr[j] + gl; t < cptr[j + 1]; t += RG) s += fabs(aval[cpos[t]]);
     s = group_sum(s);
-    if (j < n) m = nanmax(m, s);
+    if (j < n) {
+      m = nanmax(m, s);
+      if (colabs && gl == 0) colabs[j] = s;
+    }
   }
   m = wave_nanmax(m);
   if (lane == 0) atomicMax(&st->anorm1, dbits(m));
@@ -1075,13 +1118,19 @@ void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStre
 }
 
 void launch_copy_anorm(int n, const int* arow, const int*, const double* src, double* dst,
-                       DevStats* st, hipStream_t s, SyncState* ss) {
+                       DevStats* st, hipStream_t s, SyncState* ss, double* rowabs) {
   hipLaunchKernelGGL(k_copy_anorm, dim3(rows_grid(n)), dim3(256), 0, s, n, arow, src,
-                     dst, st, ss);
+                     dst, st, ss, rowabs);
+}
+
+void launch_seg_stats(int count, const int* row_off, const double* matabs, const double* r,
+                      const double* x, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_stats, dim3(count), dim3(256), 0, s, row_off, matabs, r, x, out);
 }
 
 bool launch_refactor_syncfree(const LUView& lu, const int* order, int cap, const double* aval,
-                              int* ready, SyncState* ss, int* stall, bool light, hipStream_t s) {
+                              int* ready, SyncState* ss, int* stall, bool light, int wpb_pref,
+                              hipStream_t s) {
   cap = (cap + 1) & ~1;
   const size_t per_wave = (size_t)cap * (sizeof(double) + sizeof(int2) + sizeof(int));
   if (per_wave > 64 * 1024) return false;
@@ -1102,17 +1151,28 @@ bool launch_refactor_syncfree(const LUView& lu, const int* order, int cap, const
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(wpb * WAVE), shm, s, order, lu.n, lu.rowptr,
                        lu.col, lu.diag, lu.src, aval, lu.val, ready, ss, stall, cap);
   };
+  // waves per block: the preference if its LDS fits in 64 KiB, else the
+  // largest of 4, 2, 1 that fits (4 only for rows short enough for 32 KiB)
+  int wpb = 1;
+  if (wpb_pref > 0) {
+    wpb = wpb_pref;
+    while (wpb > 1 && per_wave * wpb > 64 * 1024) wpb >>= 1;
+  } else if (per_wave * 4 <= 32 * 1024) {
+    wpb = 4;
+  } else if (per_wave * 2 <= 64 * 1024) {
+    wpb = 2;
+  }
   if (light) {
-    if (per_wave * 4 <= 32 * 1024)
+    if (wpb == 4)
       go(k_refactor_syncfree<4, true>, 4);
-    else if (per_wave * 2 <= 64 * 1024)
+    else if (wpb == 2)
       go(k_refactor_syncfree<2, true>, 2);
     else
       go(k_refactor_syncfree<1, true>, 1);
   } else {
-    if (per_wave * 4 <= 32 * 1024)
+    if (wpb == 4)
       go(k_refactor_syncfree<4, false>, 4);
-    else if (per_wave * 2 <= 64 * 1024)
+    else if (wpb == 2)
       go(k_refactor_syncfree<2, false>, 2);
     else
       go(k_refactor_syncfree<1, false>, 1);
@@ -1240,9 +1300,9 @@ void launch_gather_prep(int n, const int* perm, const double* x, double* y, Sync
 }
 
 void launch_anorm1(int n, const int* cptr, const int* cpos, const double* aval, DevStats* st,
-                   hipStream_t s) {
+                   hipStream_t s, double* colabs) {
   hipLaunchKernelGGL(k_anorm1, dim3(rows_grid(n)), dim3(256), 0, s, n, cptr, cpos,
-                     aval, st);
+                     aval, st, colabs);
 }
 
 void launch_reset_stats(DevStats* st, int what, hipStream_t s) {

@@ -73,6 +73,18 @@ struct kkt_ctx {
   // adjoint scratch
   double *lam_rm = nullptr, *x_rm = nullptr;
   int adj_cap = 0;
+  // block-diagonal batch (batch_count > 0): instance offsets, per-row/column
+  // absolute sums, per-instance maxima (3 per instance) and etas
+  int batch_count = 0;
+  std::vector<int64_t> row_off, nnz_off;
+  int* d_row_off = nullptr;
+  double *rowabs = nullptr, *colabs = nullptr, *inst_out = nullptr;
+  std::vector<double> h_inst, inst_eta;
+  // captured refactor + direct solve + residual
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  const double *graph_b = nullptr, *graph_x = nullptr;
+  bool graph_eta_pending = false;
   // report
   int warnings = 0;
   int last_iters = 0;
@@ -94,7 +106,12 @@ kkt_status fail(kkt_handle h, kkt_status st, const std::string& msg) {
   } while (0)
 
 void free_device(kkt_handle h) {
-  for (auto& b : h->bufs) hipFree(b.p);
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->graph_exec = nullptr;
+  h->graph = nullptr;
+  h->graph_eta_pending = false;
+  for (auto& b : h->bufs) (void)hipFree(b.p);
   h->bufs.clear();
   h->device_bytes = 0;
   if (h->h_st) (void)hipHostFree(h->h_st);
@@ -247,23 +264,62 @@ void op_spmv(kkt_handle h, char op, const double* x, double* y, hipStream_t s) {
     launch_spmv(h->an.n, 'T', h->at_ptr, h->at_row, h->at_pos, h->aval, x, y, s);
 }
 
-// r = b - op(A) x; returns eta (synchronises the stream)
-kkt_status residual_eta(kkt_handle h, char op, const double* b, const double* x, double* r,
-                        hipStream_t s, double* eta) {
+double eta_of(double rn, double an, double xn) {
+  const double den = an * xn;
+  return den == 0.0 ? (rn == 0.0 ? 0.0 : INFINITY) : rn / den;
+}
+
+// Device work of the residual check (no synchronisation: also captured into
+// graphs): r = b - op(A) x with its maxima, and per-instance maxima in a batch.
+void residual_launch(kkt_handle h, char op, const double* b, const double* x, double* r,
+                     hipStream_t s) {
   launch_reset_stats(h->st, 2, s);
   if (op == 'N')
     launch_residual(h->an.n, 'N', h->a_rowptr, h->a_col, nullptr, h->aval, b, x, r, h->st, s);
   else
     launch_residual(h->an.n, 'T', h->at_ptr, h->at_row, h->at_pos, h->aval, b, x, r, h->st, s);
+  if (h->batch_count > 0)
+    launch_seg_stats(h->batch_count, h->d_row_off, op == 'N' ? h->rowabs : h->colabs, r, x,
+                     h->inst_out, s);
+}
+
+// Read back the residual maxima (synchronises the stream); eta = the largest
+// instance eta of a batch, or the system's eta.
+kkt_status read_batch_eta(kkt_handle h, char op, double* eta_max);
+
+kkt_status read_eta(kkt_handle h, char op, hipStream_t s, double* eta) {
   HIP_CHECK(h, hipMemcpyAsync(h->h_st, h->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
   HIP_CHECK(h, hipStreamSynchronize(s));
   if (h->h_st->stall)
     return fail(h, KKT_ERR_DEVICE, "a dependency wait hit its spin limit (results invalid)");
+  if (h->batch_count > 0) return read_batch_eta(h, op, eta);
   const double rn = bits_to_double(h->h_st->rmax), xn = bits_to_double(h->h_st->xmax);
   const double an = bits_to_double(op == 'N' ? h->h_st->anorm : h->h_st->anorm1);
-  const double den = an * xn;
-  *eta = den == 0.0 ? (rn == 0.0 ? 0.0 : INFINITY) : rn / den;
+  *eta = eta_of(rn, an, xn);
   return KKT_OK;
+}
+
+kkt_status read_batch_eta(kkt_handle h, char op, double* eta_max) {
+  (void)op;
+  HIP_CHECK(h, hipDeviceSynchronize());
+  HIP_CHECK(h, hipMemcpy(h->h_inst.data(), h->inst_out, h->h_inst.size() * sizeof(double),
+                         hipMemcpyDeviceToHost));
+  double mx = 0.0;
+  for (int t = 0; t < h->batch_count; t++) {
+    const double e = eta_of(h->h_inst[3 * t + 1], h->h_inst[3 * t], h->h_inst[3 * t + 2]);
+    h->inst_eta[t] = e;
+    if (!(e <= mx)) mx = e;
+  }
+  h->graph_eta_pending = false;
+  if (eta_max) *eta_max = mx;
+  return KKT_OK;
+}
+
+// r = b - op(A) x; returns eta (synchronises the stream)
+kkt_status residual_eta(kkt_handle h, char op, const double* b, const double* x, double* r,
+                        hipStream_t s, double* eta) {
+  residual_launch(h, op, b, x, r, s);
+  return read_eta(h, op, s, eta);
 }
 
 // Direct solve (skipped when direct_done: x already holds it) and FGMRES-CGS2
@@ -353,7 +409,10 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
   if (o.ordering < 0 || o.ordering > 2 || !(o.pivot_tau > 0.0 && o.pivot_tau <= 1.0) ||
       o.fgmres_restart < 1 || o.fgmres_restart > 30 || o.fgmres_max_iters < 0 ||
       o.min_iters < 0 || !(o.eta_target >= 0.0) || !(o.tiny_pivot_rel >= 0.0) || o.device < 0 ||
-      o.schedule < 0 || o.schedule > 2 || o.sync_mode < 0 || o.sync_mode > 2)
+      o.schedule < 0 || o.schedule > 2 || o.sync_mode < 0 || o.sync_mode > 2 ||
+      o.solve_entries_per_lane < 0 || o.solve_entries_per_lane > 64 ||
+      (o.refactor_waves_per_block != 0 && o.refactor_waves_per_block != 1 &&
+       o.refactor_waves_per_block != 2 && o.refactor_waves_per_block != 4))
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) return KKT_ERR_DEVICE;
@@ -374,6 +433,11 @@ kkt_status kkt_destroy(kkt_handle h) {
   return KKT_OK;
 }
 
+static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t n, int64_t nnz,
+                                   const int64_t* rowptr, const int32_t* colind,
+                                   const double* values0,
+                                   std::chrono::steady_clock::time_point t0);
+
 kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowptr,
                        const int32_t* colind, const double* values0, const int32_t* user_q) {
   if (!h) return KKT_ERR_INVALID_ARG;
@@ -392,6 +456,18 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
     return fail(h, KKT_ERR_OUT_OF_MEMORY, "host allocation failed in analyze");
   }
   if (st < 0) return fail(h, (kkt_status)st, msg);
+  h->batch_count = 0;
+  h->row_off.clear();
+  h->nnz_off.clear();
+  return install_analysis(h, std::move(an), st, n, nnz, rowptr, colind, values0, t0);
+}
+
+// Upload of an analysis (single system or block-diagonal batch) and of A's
+// pattern; allocation of every workspace.
+static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t n, int64_t nnz,
+                                   const int64_t* rowptr, const int32_t* colind,
+                                   const double* values0,
+                                   std::chrono::steady_clock::time_point t0) {
   HIP_CHECK(h, hipSetDevice(h->opt.device));
   HIP_CHECK(h, hipDeviceSynchronize());
   free_device(h);
@@ -462,7 +538,8 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
         int mx = 0;
         for (int32_t t = lp[l]; t < lp[l + 1]; t++) mx = std::max(mx, (int)len_of(rows[t]));
         int lg = 2;
-        while (lg < 6 && (8 << lg) < mx) lg++;
+        const int per_lane = h->opt.solve_entries_per_lane > 0 ? h->opt.solve_entries_per_lane : 8;
+        while (lg < 6 && (per_lane << lg) < mx) lg++;
         const int per = 64 >> lg;
         for (int32_t t = lp[l]; t < lp[l + 1]; t += per) {
           st.push_back(t);
@@ -542,6 +619,18 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
     free_device(h);
     return ks;
   }
+  if (h->batch_count > 0) {
+    std::vector<int32_t> ro(h->row_off.begin(), h->row_off.end());
+    if ((ks = upload(h, &h->d_row_off, ro)) != KKT_OK ||
+        (ks = dalloc(h, &h->rowabs, (size_t)n)) != KKT_OK ||
+        (ks = dalloc(h, &h->colabs, (size_t)n)) != KKT_OK ||
+        (ks = dalloc(h, &h->inst_out, (size_t)3 * h->batch_count)) != KKT_OK) {
+      free_device(h);
+      return ks;
+    }
+    h->h_inst.assign((size_t)3 * h->batch_count, 0.0);
+    h->inst_eta.assign(h->batch_count, 0.0);
+  }
   // the pivoting pass's factors are the current factors until the first refactor
   HIP_CHECK(h, hipMemcpy(h->lu_val, A.lu_val0.data(), f * sizeof(double), hipMemcpyHostToDevice));
   HIP_CHECK(h, hipMemcpy(h->aval, values0, (size_t)nnz * sizeof(double), hipMemcpyHostToDevice));
@@ -553,7 +642,8 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
     return ks;
   }
   launch_reset_stats(h->st, 1 | 2 | 8, nullptr);
-  launch_copy_anorm(n, h->a_rowptr, h->a_col, h->aval, h->aval, h->st, nullptr);
+  launch_copy_anorm(n, h->a_rowptr, h->a_col, h->aval, h->aval, h->st, nullptr, nullptr,
+                    h->rowabs);
   launch_pivot_stats(view(h), h->st, h->opt.tiny_pivot_rel, nullptr);
   HIP_CHECK(h, hipGetLastError());
   HIP_CHECK(h, hipDeviceSynchronize());
@@ -566,30 +656,145 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
   return (kkt_status)st;
 }
 
-kkt_status kkt_refactor(kkt_handle h, const double* d_values, void* stream) {
+kkt_status kkt_analyze_batch(kkt_handle h, int32_t npat, const int32_t* n, const int64_t* nnz,
+                             const int64_t* const* rowptr, const int32_t* const* colind,
+                             const double* const* values0, int32_t count,
+                             const int32_t* inst_pattern) {
   if (!h) return KKT_ERR_INVALID_ARG;
-  if (!h->analyzed) return fail(h, KKT_ERR_STATE, "kkt_refactor before kkt_analyze");
-  if (!d_values) return fail(h, KKT_ERR_INVALID_ARG, "d_values is NULL");
-  HIP_CHECK(h, hipSetDevice(h->opt.device));
-  hipStream_t s = (hipStream_t)stream;
+  h->err.clear();
+  auto t0 = std::chrono::steady_clock::now();
+  AnalyzeOptions ao;
+  ao.ordering = h->opt.ordering == 2 ? 0 : h->opt.ordering;
+  ao.tau = h->opt.pivot_tau;
+  Analysis an;
+  std::vector<int64_t> row_off, nnz_off;
+  std::string msg;
+  int st;
+  try {
+    st = analyze_batch(npat, n, nnz, rowptr, colind, values0, count, inst_pattern, ao, an, row_off,
+                       nnz_off, &msg);
+  } catch (const std::bad_alloc&) {
+    return fail(h, KKT_ERR_OUT_OF_MEMORY, "host allocation failed in analyze_batch");
+  }
+  if (st < 0) return fail(h, (kkt_status)st, msg);
+  // the block-diagonal A: instance patterns concatenated with row/column offsets
+  const int32_t N = an.n;
+  const int64_t NNZ = an.nnz;
+  std::vector<int64_t> rp(N + 1);
+  std::vector<int32_t> ci(NNZ);
+  std::vector<double> v0(NNZ);
+  for (int32_t t = 0; t < count; t++) {
+    const int32_t p = inst_pattern[t];
+    const int32_t ro = (int32_t)row_off[t];
+    const int64_t no = nnz_off[t];
+    for (int32_t i = 0; i < n[p]; i++) rp[ro + i] = no + rowptr[p][i];
+    for (int64_t q = 0; q < nnz[p]; q++) {
+      ci[no + q] = ro + colind[p][q];
+      v0[no + q] = values0[p][q];
+    }
+  }
+  rp[N] = NNZ;
+  h->batch_count = count;
+  h->row_off = row_off;
+  h->nnz_off = nnz_off;
+  return install_analysis(h, std::move(an), st, N, NNZ, rp.data(), ci.data(), v0.data(), t0);
+}
+
+kkt_status kkt_batch_layout(kkt_handle h, int64_t* row_offset, int64_t* nnz_offset) {
+  if (!h) return KKT_ERR_INVALID_ARG;
+  if (!h->analyzed || h->batch_count == 0) return fail(h, KKT_ERR_STATE, "no batch analysis");
+  if (row_offset) std::memcpy(row_offset, h->row_off.data(), h->row_off.size() * sizeof(int64_t));
+  if (nnz_offset) std::memcpy(nnz_offset, h->nnz_off.data(), h->nnz_off.size() * sizeof(int64_t));
+  return KKT_OK;
+}
+
+kkt_status kkt_batch_eta(kkt_handle h, double* eta) {
+  if (!h || !eta) return KKT_ERR_INVALID_ARG;
+  if (!h->analyzed || h->batch_count == 0) return fail(h, KKT_ERR_STATE, "no batch analysis");
+  if (h->graph_eta_pending) {
+    kkt_status ks = read_batch_eta(h, 'N', nullptr);
+    if (ks != KKT_OK) return ks;
+  }
+  std::memcpy(eta, h->inst_eta.data(), h->inst_eta.size() * sizeof(double));
+  return KKT_OK;
+}
+
+// The refactorization's launches (stream-ordered only, capturable).
+static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStream_t s) {
   const Analysis& A = h->an;
   LUView lu = view(h);
   launch_reset_stats(h->st, 1, s);
   if (h->syncfree) {
-    launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, h->ss);
+    launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, h->ss, h->rowabs);
     if (!launch_refactor_syncfree(lu, h->lev_rows, h->cap, h->aval, h->ready_ref, h->ss,
-                                  &h->st->stall, h->light, s))
+                                  &h->st->stall, h->light, h->opt.refactor_waves_per_block, s))
       return fail(h, KKT_ERR_DEVICE, "dependency-driven refactorization not launchable");
   } else {
-    launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s);
+    launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, nullptr,
+                      h->rowabs);
     for (size_t l = 0; l + 1 < A.lev_ptr.size(); l++)
       launch_refactor_rows(lu, h->lev_rows + A.lev_ptr[l], A.lev_ptr[l + 1] - A.lev_ptr[l],
                            A.lev_maxlen[l], h->aval, h->st, 0.0, s);
   }
   launch_pivot_stats(lu, h->st, h->opt.tiny_pivot_rel, s);
+  return KKT_OK;
+}
+
+kkt_status kkt_refactor(kkt_handle h, const double* d_values, void* stream) {
+  if (!h) return KKT_ERR_INVALID_ARG;
+  if (!h->analyzed) return fail(h, KKT_ERR_STATE, "kkt_refactor before kkt_analyze");
+  if (!d_values) return fail(h, KKT_ERR_INVALID_ARG, "d_values is NULL");
+  HIP_CHECK(h, hipSetDevice(h->opt.device));
+  kkt_status ks = refactor_launch(h, d_values, (hipStream_t)stream);
+  if (ks != KKT_OK) return ks;
   HIP_CHECK(h, hipGetLastError());
   h->anorm1_valid = false;
   h->factored = true;
+  return KKT_OK;
+}
+
+kkt_status kkt_graph_capture(kkt_handle h, const double* d_values, const double* d_b, double* d_x,
+                             void* stream) {
+  if (!h) return KKT_ERR_INVALID_ARG;
+  if (!h->analyzed) return fail(h, KKT_ERR_STATE, "kkt_graph_capture before kkt_analyze");
+  if (!d_values || !d_b || !d_x || !stream)
+    return fail(h, KKT_ERR_INVALID_ARG, "null pointer or the legacy default stream");
+  HIP_CHECK(h, hipSetDevice(h->opt.device));
+  HIP_CHECK(h, hipDeviceSynchronize());
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->graph_exec = nullptr;
+  h->graph = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_CHECK(h, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+  kkt_status ks = refactor_launch(h, d_values, s);
+  if (ks == KKT_OK) {
+    apply_factors(h, 'N', d_b, d_x, s);
+    residual_launch(h, 'N', d_b, d_x, h->r, s);
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (ks != KKT_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return ks;
+  }
+  if (e != hipSuccess)
+    return fail(h, KKT_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  h->graph = g;
+  HIP_CHECK(h, hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0));
+  h->graph_b = d_b;
+  h->graph_x = d_x;
+  return KKT_OK;
+}
+
+kkt_status kkt_graph_launch(kkt_handle h, void* stream) {
+  if (!h) return KKT_ERR_INVALID_ARG;
+  if (!h->graph_exec) return fail(h, KKT_ERR_STATE, "no captured graph");
+  HIP_CHECK(h, hipSetDevice(h->opt.device));
+  HIP_CHECK(h, hipGraphLaunch(h->graph_exec, (hipStream_t)stream));
+  h->anorm1_valid = false;
+  h->factored = true;
+  h->graph_eta_pending = true;
   return KKT_OK;
 }
 
@@ -601,7 +806,8 @@ kkt_status kkt_update_matrix(kkt_handle h, const double* d_values, void* stream)
   hipStream_t s = (hipStream_t)stream;
   // keep the pivot statistics of the current factors, recompute ||A||_inf
   launch_reset_stats(h->st, 4, s);
-  launch_copy_anorm(h->an.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s);
+  launch_copy_anorm(h->an.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, nullptr,
+                    h->rowabs);
   HIP_CHECK(h, hipGetLastError());
   h->anorm1_valid = false;
   return KKT_OK;
@@ -619,7 +825,7 @@ kkt_status kkt_solve(kkt_handle h, char op, int32_t nrhs, const double* d_b, dou
   HIP_CHECK(h, hipSetDevice(h->opt.device));
   hipStream_t s = (hipStream_t)stream;
   if (op == 'T' && !h->anorm1_valid) {
-    launch_anorm1(n, h->at_ptr, h->at_pos, h->aval, h->st, s);
+    launch_anorm1(n, h->at_ptr, h->at_pos, h->aval, h->st, s, h->colabs);
     h->anorm1_valid = true;
   }
   kkt_status worst = KKT_OK;
@@ -631,7 +837,7 @@ kkt_status kkt_solve(kkt_handle h, char op, int32_t nrhs, const double* d_b, dou
     if (!(eta <= emax)) emax = eta;
     if (!(eta0 <= e0max)) e0max = eta0;
   };
-  if (h->syncfree && h->light && nrhs > 1) {
+  if (h->syncfree && h->light && nrhs > 1 && h->batch_count == 0) {
     // all columns of a pass through one dependency-driven launch per
     // triangle, one read-back of every column's eta, refinement only where
     // a column misses the target
@@ -717,6 +923,18 @@ kkt_status kkt_sync_report(kkt_handle h, kkt_report* out) {
   DevStats d;
   HIP_CHECK(h, hipMemcpy(&d, h->st, sizeof d, hipMemcpyDeviceToHost));
   if (d.stall) return fail(h, KKT_ERR_DEVICE, "a dependency wait hit its spin limit (results invalid)");
+  if (h->graph_eta_pending) {
+    // a replayed graph ran the direct solve and its residual check: no refinement
+    double e = eta_of(bits_to_double(d.rmax), bits_to_double(d.anorm), bits_to_double(d.xmax));
+    if (h->batch_count > 0) {
+      kkt_status ks = read_batch_eta(h, 'N', &e);
+      if (ks != KKT_OK) return ks;
+    }
+    h->last_eta = h->last_eta0 = e;
+    h->last_iters = 0;
+    h->graph_eta_pending = false;
+    if (!(e <= h->opt.eta_target)) h->warnings |= 1 << KKT_WARN_NOT_CONVERGED;
+  }
   int warn = h->warnings;
   if (d.tiny) warn |= 1 << KKT_WARN_TINY_PIVOT;
   out->warnings = warn;

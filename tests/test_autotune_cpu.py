@@ -1,0 +1,31 @@
+"""Autotuner host logic (CPU): candidate space, pattern keys, cache round trip."""
+import numpy as np
+
+from paper_2306_14337_amd import autotune, binding, kktgen
+
+
+def test_candidates_are_valid_options():
+    for full in (False, True):
+        cands = autotune.candidates(full)
+        assert cands[0]["schedule"] == 2 and cands[0]["sync_mode"] == 2
+        assert len({tuple(sorted(c.items())) for c in cands}) == len(cands)
+        for c in cands:
+            o = binding.options(**c)  # every knob is a field of the C options struct
+            assert o.schedule in (1, 2)
+
+
+def test_pattern_key_depends_on_pattern_only():
+    p = kktgen.make_kkt(50, 3)
+    k1 = autotune.pattern_key(p.n, p.rowptr, p.colind)
+    k2 = autotune.pattern_key(p.n, p.rowptr.copy(), p.colind.copy())
+    q = kktgen.make_kkt(50, 4)
+    assert k1 == k2 and k1 != autotune.pattern_key(q.n, q.rowptr, q.colind)
+
+
+def test_cache_round_trip(tmp_path):
+    path = str(tmp_path / "cache.json")
+    assert autotune.load_cache(path) == {}
+    autotune.store_cache("abc", {"options": {"schedule": 2}, "seconds_per_step": 1e-3}, path)
+    autotune.store_cache("def", {"options": {"schedule": 1}, "seconds_per_step": 2e-3}, path)
+    c = autotune.load_cache(path)
+    assert c["abc"]["options"] == {"schedule": 2} and c["def"]["options"] == {"schedule": 1}

@@ -260,3 +260,103 @@ def test_autograd_function_oracle_and_finite_differences():
         Lm = np.sum(Cm.T * np.linalg.solve(A - dA, Bm.T))
         fd = (Lp - Lm) / (2 * h)
         assert abs(fd - gv[p]) <= 1e-5 * abs(gv[p]) + 1e-7, (p, fd, gv[p])
+
+
+def _batch_cases():
+    """4 instances sharing one B=100 pattern (perturbed W, J and own Sigma)
+    plus 3 instances with their own patterns (B = 50, 80, 120)."""
+    ga = kktgen.make_batch_group_a(100, 61, 4)
+    gb = [(kktgen.make_kkt(B, 6100 + i),) for i, B in enumerate((50, 80, 120))]
+    insts = []
+    for pat, vals, rhs in ga:
+        insts.append((0, pat, vals, rhs))
+    patterns = [(ga[0][0].n, ga[0][0].rowptr, ga[0][0].colind, ga[0][1])]
+    for i, (pat,) in enumerate(gb):
+        rng = np.random.default_rng(i)
+        vals = pat.values(kktgen.draw_sigma(rng, pat.n_p))
+        patterns.append((pat.n, pat.rowptr, pat.colind, vals))
+        insts.append((1 + i, pat, vals, rng.standard_normal(pat.n)))
+    return patterns, insts
+
+
+def _instance_lu(s, t):
+    rp, ci, v = s.lu()
+    r0, r1 = s.row_offset[t], s.row_offset[t + 1]
+    return v[rp[r0]:rp[r1]]
+
+
+def test_batch_matches_per_instance_oracle():
+    patterns, insts = _batch_cases()
+    s = binding.KKTSolver()
+    s.analyze_batch(patterns, [p for p, *_ in insts])
+    vals = np.concatenate([v for _, _, v, _ in insts])
+    rhs = np.concatenate([b for *_, b in insts])
+    s.refactor(dev(vals))
+    x = s.solve(dev(rhs)).cpu().numpy()
+    etas = s.batch_eta()
+    for t, (p, pat, v, b) in enumerate(insts):
+        n0, n1 = s.row_offset[t], s.row_offset[t + 1]
+        pn, prp, pci, pv0 = patterns[p]
+        ora = oracle.OracleLU(pn, prp, pci, pv0, tau=1e-10)
+        ora.refactor(v)
+        assert_factors_equal(_instance_lu(s, t), oracle_csr_values(ora))
+        e = eta(pat.scipy(v), x[n0:n1], b)
+        print(f"  instance {t}: eta {e:.3e} (device {etas[t]:.3e})", flush=True)
+        assert e <= 1e-12 and etas[t] <= 1e-12 and abs(etas[t] - e) <= 1e-15
+
+
+def test_graph_replay_matches_eager():
+    patterns, insts = _batch_cases()
+    s = binding.KKTSolver()
+    s.analyze_batch(patterns, [p for p, *_ in insts])
+    rng = np.random.default_rng(17)
+    stream = torch.cuda.Stream()
+    base_v = np.concatenate([v for _, _, v, _ in insts])
+    vbuf = dev(base_v)
+    bbuf = dev(np.concatenate([b for *_, b in insts]))
+    xbuf = torch.empty_like(bbuf)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        s.graph_capture(vbuf, bbuf, xbuf, stream)
+    stream.synchronize()
+    ref = binding.KKTSolver()
+    ref.analyze_batch(patterns, [p for p, *_ in insts])
+    for rep in range(4):
+        # new Sigma-like diagonal scaling per replay, written into the captured buffers
+        v_new = base_v * (1.0 + 0.01 * rng.standard_normal(base_v.size))
+        b_new = rng.standard_normal(bbuf.numel())
+        vbuf.copy_(dev(v_new))
+        bbuf.copy_(dev(b_new))
+        torch.cuda.synchronize()
+        s.graph_launch(stream)
+        stream.synchronize()
+        # eager reference on another handle, with a host synchronisation between replays
+        ref.refactor(dev(v_new))
+        x_ref = ref.solve(dev(b_new)).cpu().numpy()
+        torch.cuda.synchronize()
+        assert np.array_equal(s.lu()[2].view(np.int64), ref.lu()[2].view(np.int64))
+        xg = xbuf.cpu().numpy()
+        etas = s.batch_eta()
+        print(f"  replay {rep}: max eta {etas.max():.3e}", flush=True)
+        assert etas.max() <= 1e-12
+        assert np.allclose(xg, x_ref, rtol=1e-9, atol=1e-12 * np.abs(x_ref).max())
+
+
+def test_autotuner_picks_a_working_schedule(tmp_path):
+    from paper_2306_14337_amd import autotune
+
+    pat, seq = kktgen.make_sequence(500, 12, 1)
+    vals, b = seq[0]
+    cache = str(tmp_path / "tune.json")
+    best, times = autotune.autotune(pat.n, pat.rowptr, pat.colind, vals, dev(vals), dev(b),
+                                    repeats=1, cache_path=cache)
+    print(f"  best {best}, {len(times)} candidates timed", flush=True)
+    assert len(times) >= 2
+    s = binding.KKTSolver(**best)
+    s.analyze(pat.n, pat.rowptr, pat.colind, vals)
+    s.refactor(dev(vals))
+    x = s.solve(dev(b)).cpu().numpy()
+    assert eta(pat.scipy(vals), x, b) <= 1e-12
+    again, t2 = autotune.autotune(pat.n, pat.rowptr, pat.colind, vals, dev(vals), dev(b),
+                                  cache_path=cache)
+    assert again == best and t2 == {}
