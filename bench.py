@@ -192,6 +192,9 @@ def main():
                     help="0 auto, 1 level-synchronous launches, 2 dependency-driven")
     ap.add_argument("--sync-mode", type=int, default=0,
                     help="0 default, 1 acquire/release fences, 2 device-coherent accesses")
+    ap.add_argument("--thin", type=int, default=0,
+                    help="largest triangular-solve level handled by the one-workgroup "
+                         "segment kernel (0 default = 16, -1 none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -210,7 +213,8 @@ def main():
     print(f"# generated B={args.buses} n={pat.n} nnz={pat.nnz} in {t_gen:.1f}s", file=sys.stderr,
           flush=True)
 
-    s = binding.KKTSolver(device=0, schedule=args.schedule, sync_mode=args.sync_mode)
+    s = binding.KKTSolver(device=0, schedule=args.schedule, sync_mode=args.sync_mode,
+                          solve_thin_rows=args.thin)
     t0 = time.perf_counter()
     s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
     t_an = time.perf_counter() - t0
@@ -279,7 +283,7 @@ def main():
                                f"{args.steps} timed same-pattern matrices, 1 RHS, tau=1e-10",
                    "buses": args.buses, "n": pat.n, "nnz": pat.nnz, "nnz_lu": nnz_lu,
                    "levels": info.levels, "seed": args.seed, "schedule": args.schedule,
-                   "sync_mode": args.sync_mode},
+                   "sync_mode": args.sync_mode, "solve_thin_rows": args.thin},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "refactorization (all launches of one kkt_refactor)",

@@ -81,7 +81,15 @@ typedef struct {
   int32_t solve_entries_per_lane; /* triangular-solve chunking: lanes per row sized so each lane
                                      holds at most this many entries (0 = 8; 1..64) */
   int32_t refactor_waves_per_block; /* dependency-driven refactorization: 0 auto, 1, 2 or 4 */
-  int32_t reserved[5];
+  int32_t solve_thin_rows; /* single right-hand-side solves with device-coherent publication:
+                              runs of levels with at most this many rows at either end of a
+                              triangular schedule are solved by one workgroup with barriers
+                              instead of cross-CU flags (0 = 16, -1 = never; at most 16) */
+  int32_t dense_tail; /* dependency-driven refactorization: the trailing block of this many
+                         pivots is finished as a dense LU (bitwise the same factors); 0 = auto
+                         (the largest block of at least 256 and at most 2048 pivots that is at
+                         least half dense, else none), -1 = never */
+  int32_t reserved[3];
 } kkt_options;
 
 typedef struct {
@@ -104,6 +112,7 @@ typedef struct {
   int32_t analyze_status; /* KKT_OK or KKT_WARN_NUMERICALLY_SINGULAR */
   int64_t device_bytes;   /* device memory owned by the handle */
   double analyze_seconds;
+  int32_t dense_tail;     /* pivots in the dense trailing block (0 = none) */
 } kkt_info;
 
 /* Fill *opt with the defaults listed above. */

@@ -51,7 +51,8 @@ class Options(C.Structure):
                 ("eta_target", C.c_double), ("tiny_pivot_rel", C.c_double), ("device", C.c_int32),
                 ("schedule", C.c_int32), ("sync_mode", C.c_int32),
                 ("solve_entries_per_lane", C.c_int32), ("refactor_waves_per_block", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("solve_thin_rows", C.c_int32), ("dense_tail", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class Report(C.Structure):
@@ -63,7 +64,8 @@ class Report(C.Structure):
 class Info(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("nnz_l", C.c_int64), ("nnz_u", C.c_int64),
                 ("levels", C.c_int32), ("levels_u", C.c_int32), ("analyze_status", C.c_int32),
-                ("device_bytes", C.c_int64), ("analyze_seconds", C.c_double)]
+                ("device_bytes", C.c_int64), ("analyze_seconds", C.c_double),
+                ("dense_tail", C.c_int32)]
 
 
 _lib = None

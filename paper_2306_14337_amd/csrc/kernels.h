@@ -38,6 +38,26 @@ struct ChunkSched {
   const int* rows;
 };
 
+// A run of thin levels (few rows each) of a triangular-solve schedule,
+// solved by one workgroup level by level with barriers (no cross-CU
+// dependency traffic).  Rows are in level order; entry q of segment row j
+// (ptr[j] <= q < ptr[j+1]) multiplies val[vpos[q]] with y[src[q]] if
+// src[q] >= 0 (a row outside the segment, final before the launch) or with
+// the segment's own row -src[q]-1 (kept in LDS); dpos[j] is the diagonal's
+// position (U and U^T modes).
+struct SegSched {
+  int nlev = 0, nrows = 0;
+  const int* lev_ptr = nullptr;  // nlev+1, into rows
+  const int* row = nullptr;      // nrows: global row index
+  const int* ptr = nullptr;      // nrows+1
+  const int* src = nullptr;
+  const int* vpos = nullptr;
+  const int* dpos = nullptr;
+};
+// rows of one level a segment kernel handles at most, and segment capacity
+constexpr int SEG_MAX_LEVEL_ROWS = 16;
+constexpr int SEG_MAX_ROWS = 6144;
+
 struct LUView {
   int n;
   const int* rowptr;  // n+1
@@ -60,9 +80,23 @@ void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxl
 // that see *stall stop waiting, so the grid always drains.
 // light: device-coherent data accesses instead of acquire/release fences.
 // wpb_pref: waves (rows in flight) per workgroup, 0 = chosen from the LDS need.
+// c0: first row/column of the dense trailing block (n = none): rows i >= c0
+// apply only the pivots k < c0 (the block is finished by launch_dense_lu).
 bool launch_refactor_syncfree(const LUView& lu, const int* order, int cap, const double* aval,
                               int* ready, SyncState* ss, int* stall, bool light, int wpb_pref,
-                              hipStream_t s);
+                              int c0, hipStream_t s);
+
+// Dense trailing block: rows and columns c0 .. c0+s-1 of the factors in pivot
+// order, held row-major in T (S x S, S = s rounded up to DLU_NB; the padding
+// is an identity block).  scatter: T := the block's LU-pattern entries (zero
+// elsewhere); dense_lu: in-place LU without pivoting, every entry updated by
+// fma(-l_ik, u_kj, a_ij) in ascending k, l_ik = a_ik / u_kk (the order of the
+// sparse refactorization, so the results agree bit for bit); gather: the
+// pattern entries back into the factors.  dsc: DLU_NB^2 doubles of scratch.
+constexpr int DLU_NB = 32;
+void launch_tail_scatter(const LUView& lu, int c0, int s, int S, double* T, hipStream_t st);
+void launch_dense_lu(double* T, int S, double* dsc, hipStream_t st);
+void launch_tail_gather(const LUView& lu, int c0, const double* T, int S, hipStream_t st);
 // Dependency-driven triangular solve of one right-hand side in place on y.
 // mode 0: unit L rows, 1: U rows, 2: U^T columns (tptr/trow/tpos view of U),
 // 3: unit L^T columns (view of strict L).  slot: SyncState slot (1 or 2).
@@ -74,6 +108,11 @@ void launch_trisolve_syncfree(int mode, const LUView& lu, const ChunkSched& cs, 
 void launch_trisolve_vflag(int mode, const LUView& lu, const ChunkSched& cs, const int* tptr,
                            const int* trow, const int* tpos, const double* c, double* y,
                            SyncState* ss, int slot, int* stall, hipStream_t s);
+// One workgroup solves a thin segment (mode as launch_trisolve_syncfree):
+// y[row] = (c[row] - sum) (/ u_ii); plain loads and stores, so the segment
+// must not overlap a dependency-driven launch on the same vector.
+void launch_trisolve_seg(int mode, const SegSched& sg, const double* val, const double* c,
+                         double* y, hipStream_t s);
 // Right-hand sides per multi-column pass.
 constexpr int MAX_RHS_PASS = 32;
 // The same for nr <= MAX_RHS_PASS columns at once; c, y column-major with

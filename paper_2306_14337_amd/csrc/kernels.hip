@@ -212,7 +212,8 @@ template <int WPB, bool LIGHT>
 __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
     const int* __restrict__ order, int n, const int* __restrict__ rowptr,
     const int* __restrict__ col, const int* __restrict__ diag, const int* __restrict__ src,
-    const double* __restrict__ aval, double* val, int* ready, SyncState* ss, int* stall, int cap) {
+    const double* __restrict__ aval, double* val, int* ready, SyncState* ss, int* stall, int cap,
+    int c0) {
   extern __shared__ double smem_d[];
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   // LDS per wave: values (cap doubles), pivot-row bounds (cap int2), columns (cap ints)
@@ -225,7 +226,8 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
     const unsigned int tk = bcast0(atomicAdd(ticket, lane == 0 ? 1u : 0u));
     if (tk >= (unsigned int)n) break;
     const int i = order[tk];
-    const int rs = rowptr[i], len = rowptr[i + 1] - rs, dl = diag[i] - rs;
+    const int rs = rowptr[i], len = rowptr[i + 1] - rs;
+    int dl = diag[i] - rs;
     for (int t = lane; t < len; t += WAVE) {
       sc[t] = col[rs + t];
       const int s = src[rs + t];
@@ -238,6 +240,8 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
       sk[t] = make_int2(diag[k], rowptr[k + 1]);
     }
     wave_sync();
+    // rows of the dense trailing block take only the pivots before it here
+    if (i >= c0) dl = lower_bound_i(sc, 0, dl, c0);
     int ready_upto = 0, spins = 0;
     // software pipeline: the pivot and the first 64 entries of the next ready
     // pivot row are in flight while the current one is applied
@@ -485,6 +489,292 @@ __device__ __forceinline__ void sync_prep(SyncState* ss, int mask) {
 
 __global__ void k_sync_prep(SyncState* ss, int mask) {
   if (threadIdx.x == 0 && blockIdx.x == 0) sync_prep(ss, mask);
+}
+
+// ---------------------------------------------------------------------------
+// Thin segment of a triangular solve on one workgroup.  The top of the
+// elimination tree is a long run of levels with a handful of rows each; across
+// CUs every level costs a device-scope round trip, inside one workgroup it
+// costs two barriers.  Per level the 16 waves are split over the level's rows
+// (waves per row = 16 / rows), each wave reduces its share of a row's dot
+// product, and one thread per row finishes it; segment results stay in LDS.
+// The matrix entries (and the solution values from outside the segment) of
+// level l + 1 are loaded while level l is computed.
+// ---------------------------------------------------------------------------
+constexpr int SEG_THREADS = 1024;
+constexpr int SEG_WAVES = SEG_THREADS / WAVE;
+constexpr int SEG_PF = 4;  // prefetched entries per lane and level
+
+__device__ __forceinline__ void seg_fetch(int lev, int nlev, const int* __restrict__ lev_ptr,
+                                          const int* __restrict__ ptr,
+                                          const int* __restrict__ src,
+                                          const int* __restrict__ vpos,
+                                          const double* __restrict__ val,
+                                          const double* __restrict__ y, int w, int lane, int* fs,
+                                          double* fv, double* fy, int& q0, int& stride, int& e) {
+  q0 = 0;
+  stride = 1;
+  e = 0;
+#pragma unroll
+  for (int k = 0; k < SEG_PF; k++) {
+    fs[k] = 0;
+    fv[k] = 0.0;
+    fy[k] = 0.0;
+  }
+  if (lev >= nlev) return;
+  const int r0 = lev_ptr[lev], nr = lev_ptr[lev + 1] - r0;
+  const int ng = SEG_WAVES / nr;
+  const int rr = w / ng, g = w % ng;
+  if (rr >= nr) return;
+  const int j = r0 + rr;
+  q0 = ptr[j] + g * WAVE + lane;
+  stride = ng * WAVE;
+  e = ptr[j + 1];
+#pragma unroll
+  for (int k = 0; k < SEG_PF; k++) {
+    const int q = q0 + k * stride;
+    if (q < e) {
+      const int sq = src[q];
+      fs[k] = sq;
+      fv[k] = val[vpos[q]];
+      if (sq >= 0) fy[k] = y[sq];
+    }
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(SEG_THREADS) void k_trisolve_seg(
+    int nlev, const int* __restrict__ lev_ptr, const int* __restrict__ row,
+    const int* __restrict__ ptr, const int* __restrict__ src, const int* __restrict__ vpos,
+    const int* __restrict__ dpos, const double* __restrict__ val, const double* __restrict__ c,
+    double* __restrict__ y) {
+  __shared__ double ly[SEG_MAX_ROWS];
+  __shared__ double part[SEG_WAVES];
+  const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  int cs[SEG_PF];
+  double cv[SEG_PF], cy[SEG_PF];
+  int cq0, cstr, ce;
+  seg_fetch(0, nlev, lev_ptr, ptr, src, vpos, val, y, w, lane, cs, cv, cy, cq0, cstr, ce);
+  for (int l = 0; l < nlev; l++) {
+    int ns[SEG_PF];
+    double nv[SEG_PF], ny[SEG_PF];
+    int nq0, nstr, ne;
+    seg_fetch(l + 1, nlev, lev_ptr, ptr, src, vpos, val, y, w, lane, ns, nv, ny, nq0, nstr, ne);
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < SEG_PF; k++) s += cv[k] * (cs[k] >= 0 ? cy[k] : ly[-cs[k] - 1]);
+    for (int q = cq0 + SEG_PF * cstr; q < ce; q += cstr) {
+      const int sq = src[q];
+      s += val[vpos[q]] * (sq >= 0 ? y[sq] : ly[-sq - 1]);
+    }
+    s = wave_sum(s);
+    if (lane == 0) part[w] = s;
+    __syncthreads();
+    const int r0 = lev_ptr[l], nr = lev_ptr[l + 1] - r0;
+    if (threadIdx.x < nr) {
+      const int ng = SEG_WAVES / nr;
+      const int j = r0 + threadIdx.x;
+      double tot = 0.0;
+      for (int g = 0; g < ng; g++) tot += part[threadIdx.x * ng + g];
+      const int i = row[j];
+      double yi = c[i] - tot;
+      if (MODE == 1 || MODE == 2) yi /= val[dpos[j]];
+      ly[j] = yi;
+      y[i] = yi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SEG_PF; k++) {
+      cs[k] = ns[k];
+      cv[k] = nv[k];
+      cy[k] = ny[k];
+    }
+    cq0 = nq0;
+    cstr = nstr;
+    ce = ne;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dense trailing block.  The last rows of the pivot order couple to nearly
+// every later pivot (the top separators of the elimination tree), so their
+// block of the factors is dense and its row-by-row dependency chain is as
+// long as the block.  It is finished as a dense right-looking LU in panels of
+// DLU_NB pivots: one launch factors the panel (diagonal block, the column
+// panel below it, the row panel right of it), one launch applies the panel's
+// rank-DLU_NB update to the trailing matrix.  Every entry still receives
+// fma(-l_ik, u_kj, a_ij) for k in ascending order, and an update whose l or u
+// lies outside the sparse pattern is an exact zero update, so the values are
+// those of the sparse refactorization bit for bit.  FP64 runs at the same
+// peak rate on the vector ALUs as on the matrix cores of this chip, so the
+// tile update uses vector FMAs, which keep that order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+// wave per row r of T: zero the row (unit diagonal on padding rows), then the
+// pattern entries of factor row c0 + r in columns >= c0
+__global__ __launch_bounds__(256) void k_tail_scatter(int c0, int s, int S,
+                                                      const int* __restrict__ rowptr,
+                                                      const int* __restrict__ col,
+                                                      const double* __restrict__ val, double* T) {
+  const int lane = threadIdx.x % WAVE;
+  const int r = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (r >= S) return;
+  double* Tr = T + (size_t)r * S;
+  for (int c = lane; c < S; c += WAVE) Tr[c] = (r >= s && c == r) ? 1.0 : 0.0;
+  if (r >= s) return;
+  stores_done();  // the zeros land before the values at the same addresses
+  const int i = c0 + r;
+  for (int q = rowptr[i] + lane; q < rowptr[i + 1]; q += WAVE) {
+    const int j = col[q];
+    if (j >= c0) Tr[j - c0] = val[q];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tail_gather(int c0, int s, int S,
+                                                     const int* __restrict__ rowptr,
+                                                     const int* __restrict__ col,
+                                                     const double* __restrict__ T, double* val) {
+  const int lane = threadIdx.x % WAVE;
+  const int r = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (r >= s) return;
+  const double* Tr = T + (size_t)r * S;
+  const int i = c0 + r;
+  for (int q = rowptr[i] + lane; q < rowptr[i + 1]; q += WAVE) {
+    const int j = col[q];
+    if (j >= c0) val[q] = Tr[j - c0];
+  }
+}
+
+// Panel k0: wave 0 of every workgroup factors the diagonal block in registers
+// (lane t owns row k0 + t; row k's entries are broadcast with readlane), then
+// workgroups b < nrw update rows k0 + NB + 256 b + tid of the column panel
+// (thread per row) and the others columns of the row panel (thread per
+// column).  The diagonal block in T stays untouched here (other workgroups may
+// still be reading it); its factored form goes to dsc and is copied into T by
+// the following k_dlu_update.
+template <int NB>
+__global__ __launch_bounds__(256) void k_dlu_panel(double* T, int S, int k0, int nrw,
+                                                   double* dsc) {
+  __shared__ double D[NB][NB + 1];
+  const int tid = threadIdx.x;
+  if (tid < WAVE) {
+    const int t = tid;
+    double r[NB];
+#pragma unroll
+    for (int j = 0; j < NB; j++) r[j] = t < NB ? T[(size_t)(k0 + t) * S + k0 + j] : 0.0;
+#pragma unroll
+    for (int k = 0; k < NB; k++) {
+      const double ukk = readlane_d(r[k], k);
+      const double l = r[k] / ukk;
+#pragma unroll
+      for (int j = k + 1; j < NB; j++) {
+        const double nv = __builtin_fma(-l, readlane_d(r[j], k), r[j]);
+        r[j] = t > k ? nv : r[j];
+      }
+      r[k] = t > k ? l : r[k];
+    }
+    if (t < NB) {
+#pragma unroll
+      for (int j = 0; j < NB; j++) D[t][j] = r[j];
+    }
+  }
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int e = tid; e < NB * NB; e += blockDim.x) dsc[e] = D[e / NB][e % NB];
+  const int b = blockIdx.x;
+  if (b < nrw) {
+    const int i = k0 + NB + b * blockDim.x + tid;
+    if (i < S) {
+      double* Ti = T + (size_t)i * S + k0;
+      double r[NB];
+#pragma unroll
+      for (int j = 0; j < NB; j++) r[j] = Ti[j];
+#pragma unroll
+      for (int k = 0; k < NB; k++) {
+        const double l = r[k] / D[k][k];
+        r[k] = l;
+#pragma unroll
+        for (int j = k + 1; j < NB; j++) r[j] = __builtin_fma(-l, D[k][j], r[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < NB; j++) Ti[j] = r[j];
+    }
+  } else {
+    const int j = k0 + NB + (b - nrw) * blockDim.x + tid;
+    if (j < S) {
+      double c[NB];
+#pragma unroll
+      for (int t = 0; t < NB; t++) c[t] = T[(size_t)(k0 + t) * S + j];
+#pragma unroll
+      for (int k = 0; k < NB; k++) {
+#pragma unroll
+        for (int t = k + 1; t < NB; t++) c[t] = __builtin_fma(-D[t][k], c[k], c[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < NB; t++) T[(size_t)(k0 + t) * S + j] = c[t];
+    }
+  }
+}
+
+// Trailing update of panel k0 on 64 x 64 tiles (4 x 4 entries per thread,
+// rows ty + 16 a, columns tx + 16 b): a_ij = fma(-l_ik, u_kj, a_ij) for the
+// panel's k in ascending order.  Tile (0, 0) also installs the factored
+// diagonal block of the panel from dsc.
+template <int NB>
+__global__ __launch_bounds__(256) void k_dlu_update(double* T, int S, int k0,
+                                                    const double* __restrict__ dsc) {
+  __shared__ double Ls[64][NB + 1];
+  __shared__ double Us[NB][64];
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && blockIdx.y == 0)
+    for (int e = tid; e < NB * NB; e += 256)
+      T[(size_t)(k0 + e / NB) * S + k0 + e % NB] = dsc[e];
+  const int base = k0 + NB;
+  const int r0 = base + blockIdx.y * 64, q0 = base + blockIdx.x * 64;
+  if (r0 >= S || q0 >= S) return;
+  for (int e = tid; e < 64 * NB; e += 256) {
+    const int ii = e / NB, k = e % NB;
+    Ls[ii][k] = r0 + ii < S ? T[(size_t)(r0 + ii) * S + k0 + k] : 0.0;
+  }
+  for (int e = tid; e < NB * 64; e += 256) {
+    const int k = e / 64, jj = e % 64;
+    Us[k][jj] = q0 + jj < S ? T[(size_t)(k0 + k) * S + q0 + jj] : 0.0;
+  }
+  __syncthreads();
+  const int tx = tid % 16, ty = tid / 16;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      const int r = r0 + ty + 16 * a, q = q0 + tx + 16 * c;
+      acc[a][c] = (r < S && q < S) ? T[(size_t)r * S + q] : 0.0;
+    }
+#pragma unroll 4
+  for (int k = 0; k < NB; k++) {
+    double lv[4], uv[4];
+#pragma unroll
+    for (int a = 0; a < 4; a++) lv[a] = Ls[ty + 16 * a][k];
+#pragma unroll
+    for (int c = 0; c < 4; c++) uv[c] = Us[k][tx + 16 * c];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int c = 0; c < 4; c++) acc[a][c] = __builtin_fma(-lv[a], uv[c], acc[a][c]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      const int r = r0 + ty + 16 * a, q = q0 + tx + 16 * c;
+      if (r < S && q < S) T[(size_t)r * S + q] = acc[a][c];
+    }
 }
 
 // Several right-hand sides in one launch (nr <= NR, column-major with leading
@@ -1130,7 +1420,7 @@ void launch_seg_stats(int count, const int* row_off, const double* matabs, const
 
 bool launch_refactor_syncfree(const LUView& lu, const int* order, int cap, const double* aval,
                               int* ready, SyncState* ss, int* stall, bool light, int wpb_pref,
-                              hipStream_t s) {
+                              int c0, hipStream_t s) {
   cap = (cap + 1) & ~1;
   const size_t per_wave = (size_t)cap * (sizeof(double) + sizeof(int2) + sizeof(int));
   if (per_wave > 64 * 1024) return false;
@@ -1149,7 +1439,7 @@ bool launch_refactor_syncfree(const LUView& lu, const int* order, int cap, const
       nb = 1;
     const int grid = std::max(1, std::min(nb * ncu, cdiv(lu.n, wpb)));
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(wpb * WAVE), shm, s, order, lu.n, lu.rowptr,
-                       lu.col, lu.diag, lu.src, aval, lu.val, ready, ss, stall, cap);
+                       lu.col, lu.diag, lu.src, aval, lu.val, ready, ss, stall, cap, c0);
   };
   // waves per block: the preference if its LDS fits in 64 KiB, else the
   // largest of 4, 2, 1 that fits (4 only for rows short enough for 32 KiB)
@@ -1264,6 +1554,46 @@ void launch_trisolve_vflag_mr(int mode, int nr, const LUView& lu, const ChunkSch
   }
 #undef TM_MODES
 #undef TM_LAUNCH
+}
+
+void launch_tail_scatter(const LUView& lu, int c0, int s, int S, double* T, hipStream_t st) {
+  if (s <= 0) return;
+  hipLaunchKernelGGL(k_tail_scatter, dim3(cdiv(S, 4)), dim3(256), 0, st, c0, s, S, lu.rowptr,
+                     lu.col, lu.val, T);
+}
+
+void launch_tail_gather(const LUView& lu, int c0, const double* T, int S, hipStream_t st) {
+  const int s = lu.n - c0;
+  if (s <= 0) return;
+  hipLaunchKernelGGL(k_tail_gather, dim3(cdiv(s, 4)), dim3(256), 0, st, c0, s, S, lu.rowptr,
+                     lu.col, T, lu.val);
+}
+
+void launch_dense_lu(double* T, int S, double* dsc, hipStream_t st) {
+  for (int k0 = 0; k0 < S; k0 += DLU_NB) {
+    const int rest = S - k0 - DLU_NB;
+    const int nrw = cdiv(rest, 256);
+    hipLaunchKernelGGL(k_dlu_panel<DLU_NB>, dim3(std::max(1, 2 * nrw)), dim3(256), 0, st, T, S,
+                       k0, nrw, dsc);
+    const int nt = std::max(1, cdiv(rest, 64));
+    hipLaunchKernelGGL(k_dlu_update<DLU_NB>, dim3(nt, nt), dim3(256), 0, st, T, S, k0,
+                       (const double*)dsc);
+  }
+}
+
+void launch_trisolve_seg(int mode, const SegSched& sg, const double* val, const double* c,
+                         double* y, hipStream_t s) {
+  if (sg.nlev <= 0) return;
+#define SG_LAUNCH(M)                                                                             \
+  hipLaunchKernelGGL(k_trisolve_seg<M>, dim3(1), dim3(SEG_THREADS), 0, s, sg.nlev, sg.lev_ptr, \
+                     sg.row, sg.ptr, sg.src, sg.vpos, sg.dpos, val, c, y)
+  switch (mode) {
+    case 0: SG_LAUNCH(0); break;
+    case 1: SG_LAUNCH(1); break;
+    case 2: SG_LAUNCH(2); break;
+    default: SG_LAUNCH(3); break;
+  }
+#undef SG_LAUNCH
 }
 
 void launch_gather_sentinel_mr(int n, int nr, const int* perm, const double* x, double* c,

@@ -62,6 +62,14 @@ struct kkt_ctx {
   SyncState* ss = nullptr;
   int *ready_ref = nullptr, *ready_a = nullptr, *ready_b = nullptr;
   ChunkSched ch_l{}, ch_u{}, ch_ut{}, ch_lt{};
+  // single right-hand side: thin leading/trailing level runs solved by one
+  // workgroup (index = solve mode) and the chunk schedules of the levels between
+  SegSched seg_pre[4]{}, seg_post[4]{};
+  ChunkSched chb[4]{};
+  // dense trailing block of the refactorization: pivots tail_c0 .. n-1
+  // (tail_s of them), row-major tail_S x tail_S workspace and panel scratch
+  int tail_s = 0, tail_c0 = 0, tail_S = 0;
+  double *tail_T = nullptr, *tail_dsc = nullptr;
   // statistics
   DevStats* st = nullptr;
   DevStats* h_st = nullptr;  // pinned
@@ -166,19 +174,24 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
   const int n = A.n;
   LUView lu = view(h);
   if (h->syncfree && h->light) {
+    // per triangle: thin leading levels (one workgroup), the levels between
+    // (dependency-driven), thin trailing levels (one workgroup)
+    auto tri = [&](int mode, const int* tp, const int* tr, const int* tq, const double* c,
+                   double* y, int slot) {
+      launch_trisolve_seg(mode, h->seg_pre[mode], h->lu_val, c, y, s);
+      launch_trisolve_vflag(mode, lu, h->chb[mode], tp, tr, tq, c, y, h->ss, slot, &h->st->stall,
+                            s);
+      launch_trisolve_seg(mode, h->seg_post[mode], h->lu_val, c, y, s);
+    };
     if (op == 'N') {
       launch_gather_sentinel(n, h->pin, b, h->tc, h->ty, h->tz, h->ss, 0x6, s);
-      launch_trisolve_vflag(0, lu, h->ch_l, nullptr, nullptr, nullptr, h->tc, h->ty, h->ss, 1,
-                            &h->st->stall, s);
-      launch_trisolve_vflag(1, lu, h->ch_u, nullptr, nullptr, nullptr, h->ty, h->tz, h->ss, 2,
-                            &h->st->stall, s);
+      tri(0, nullptr, nullptr, nullptr, h->tc, h->ty, 1);
+      tri(1, nullptr, nullptr, nullptr, h->ty, h->tz, 2);
       launch_scatter(n, h->qperm, h->tz, x, s);
     } else {
       launch_gather_sentinel(n, h->qperm, b, h->tc, h->ty, h->tz, h->ss, 0x6, s);
-      launch_trisolve_vflag(2, lu, h->ch_ut, h->ut_ptr, h->ut_row, h->ut_pos, h->tc, h->ty,
-                            h->ss, 1, &h->st->stall, s);
-      launch_trisolve_vflag(3, lu, h->ch_lt, h->lt_ptr, h->lt_row, h->lt_pos, h->ty, h->tz,
-                            h->ss, 2, &h->st->stall, s);
+      tri(2, h->ut_ptr, h->ut_row, h->ut_pos, h->tc, h->ty, 1);
+      tri(3, h->lt_ptr, h->lt_row, h->lt_pos, h->ty, h->tz, 2);
       launch_scatter(n, h->pin, h->tz, x, s);
     }
     return;
@@ -412,7 +425,9 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
       o.schedule < 0 || o.schedule > 2 || o.sync_mode < 0 || o.sync_mode > 2 ||
       o.solve_entries_per_lane < 0 || o.solve_entries_per_lane > 64 ||
       (o.refactor_waves_per_block != 0 && o.refactor_waves_per_block != 1 &&
-       o.refactor_waves_per_block != 2 && o.refactor_waves_per_block != 4))
+       o.refactor_waves_per_block != 2 && o.refactor_waves_per_block != 4) ||
+      o.solve_thin_rows < -1 || o.solve_thin_rows > SEG_MAX_LEVEL_ROWS || o.dense_tail < -1 ||
+      o.dense_tail > 16384)
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) return KKT_ERR_DEVICE;
@@ -531,10 +546,11 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     // longest row
     auto chunks = [&](const std::vector<int32_t>& lp, const std::vector<int32_t>& rows,
                       auto len_of, ChunkSched& cs, std::vector<int32_t>& st,
-                      std::vector<int32_t>& me) {
+                      std::vector<int32_t>& me, size_t l0 = 0, size_t l1 = SIZE_MAX) {
       st.clear();
       me.clear();
-      for (size_t l = 0; l + 1 < lp.size(); l++) {
+      l1 = std::min(l1, lp.size() - 1);
+      for (size_t l = l0; l < l1; l++) {
         int mx = 0;
         for (int32_t t = lp[l]; t < lp[l + 1]; t++) mx = std::max(mx, (int)len_of(rows[t]));
         int lg = 2;
@@ -580,6 +596,123 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     h->ch_lt.start = dptr;
     h->ch_lt.meta = dmeta;
     h->ch_lt.rows = h->ltlev_rows;
+    // thin runs at both ends of each schedule (modes 0 L, 1 U, 2 U^T, 3 L^T)
+    const int thin = h->opt.solve_thin_rows == 0 ? SEG_MAX_LEVEL_ROWS : h->opt.solve_thin_rows;
+    const std::vector<int32_t>* tlp[4] = {&A.lev_ptr, &A.ulev_ptr, &A.utlev_ptr, &A.ltlev_ptr};
+    const std::vector<int32_t>* trows[4] = {&A.lev_rows, &A.ulev_rows, &A.utlev_rows,
+                                             &A.ltlev_rows};
+    int* trows_dev[4] = {h->lev_rows, h->ulev_rows, h->utlev_rows, h->ltlev_rows};
+    std::vector<int32_t> lu_row_of(A.lu_col.size());
+    for (int32_t i = 0; i < n; i++)
+      for (int32_t q = A.lu_rowptr[i]; q < A.lu_rowptr[i + 1]; q++) lu_row_of[q] = i;
+    // entries of row i of the mode's triangle: (dependency row, value position)
+    auto entries = [&](int mode, int i, std::vector<int32_t>& dep, std::vector<int32_t>& pos,
+                       int32_t& dpos) {
+      dep.clear();
+      pos.clear();
+      dpos = -1;
+      if (mode == 0) {
+        for (int32_t q = A.lu_rowptr[i]; q < A.diag[i]; q++) {
+          dep.push_back(A.lu_col[q]);
+          pos.push_back(q);
+        }
+      } else if (mode == 1) {
+        dpos = A.diag[i];
+        for (int32_t q = A.diag[i] + 1; q < A.lu_rowptr[i + 1]; q++) {
+          dep.push_back(A.lu_col[q]);
+          pos.push_back(q);
+        }
+      } else {
+        const std::vector<int32_t>& tp = mode == 2 ? A.ut_ptr : A.lt_ptr;
+        const std::vector<int32_t>& tq = mode == 2 ? A.ut_pos : A.lt_pos;
+        const int32_t e = mode == 2 ? tp[i + 1] - 1 : tp[i + 1];
+        if (mode == 2) dpos = tq[e];
+        for (int32_t q = tp[i]; q < e; q++) {
+          dep.push_back(lu_row_of[tq[q]]);
+          pos.push_back(tq[q]);
+        }
+      }
+    };
+    std::vector<int32_t> slot_of(n, -1), dep, pos;
+    auto seg_build = [&](int mode, size_t l0, size_t l1, SegSched& sg) -> kkt_status {
+      const std::vector<int32_t>& lp = *tlp[mode];
+      const std::vector<int32_t>& rows = *trows[mode];
+      std::vector<int32_t> slp{0}, srow, sptr{0}, ssrc, svpos, sdpos;
+      for (size_t l = l0; l < l1; l++) {
+        for (int32_t t = lp[l]; t < lp[l + 1]; t++) {
+          const int32_t i = rows[t];
+          int32_t dp;
+          entries(mode, i, dep, pos, dp);
+          for (size_t k = 0; k < dep.size(); k++) {
+            const int32_t j = dep[k];
+            ssrc.push_back(slot_of[j] >= 0 ? -(slot_of[j] + 1) : j);
+            svpos.push_back(pos[k]);
+          }
+          slot_of[i] = (int32_t)srow.size();
+          srow.push_back(i);
+          sptr.push_back((int32_t)ssrc.size());
+          sdpos.push_back(dp < 0 ? 0 : dp);
+        }
+        slp.push_back((int32_t)srow.size());
+      }
+      for (int32_t i : srow) slot_of[i] = -1;
+      sg.nlev = (int)(l1 - l0);
+      sg.nrows = (int)srow.size();
+      if (sg.nlev == 0) return KKT_OK;
+      if (ssrc.empty()) {
+        ssrc.push_back(0);
+        svpos.push_back(0);
+      }
+      int *a, *b, *c, *d, *e, *f;
+      kkt_status k2;
+      if ((k2 = upload(h, &a, slp)) != KKT_OK || (k2 = upload(h, &b, srow)) != KKT_OK ||
+          (k2 = upload(h, &c, sptr)) != KKT_OK || (k2 = upload(h, &d, ssrc)) != KKT_OK ||
+          (k2 = upload(h, &e, svpos)) != KKT_OK || (k2 = upload(h, &f, sdpos)) != KKT_OK)
+        return k2;
+      sg.lev_ptr = a;
+      sg.row = b;
+      sg.ptr = c;
+      sg.src = d;
+      sg.vpos = e;
+      sg.dpos = f;
+      return KKT_OK;
+    };
+    auto len_fn = [&](int mode, int i) -> int {
+      int32_t dp;
+      entries(mode, i, dep, pos, dp);
+      return (int)dep.size();
+    };
+    for (int mode = 0; mode < 4; mode++) {
+      const std::vector<int32_t>& lp = *tlp[mode];
+      const size_t nl = lp.size() - 1;
+      auto width = [&](size_t l) { return lp[l + 1] - lp[l]; };
+      size_t a = 0, b = nl;  // bulk levels [a, b)
+      if (thin > 0) {
+        int rows = 0;
+        auto fits = [&](size_t l) {
+          return width(l) >= 1 && width(l) <= thin && rows + width(l) <= SEG_MAX_ROWS;
+        };
+        while (a < nl && fits(a)) rows += width(a++);
+        rows = 0;
+        while (b > a && fits(b - 1)) rows += width(--b);
+      }
+      h->seg_pre[mode] = SegSched{};
+      h->seg_post[mode] = SegSched{};
+      if ((ks = seg_build(mode, 0, a, h->seg_pre[mode])) != KKT_OK ||
+          (ks = seg_build(mode, b, nl, h->seg_post[mode])) != KKT_OK) {
+        free_device(h);
+        return ks;
+      }
+      chunks(lp, *trows[mode], [&](int i) { return len_fn(mode, i); }, h->chb[mode], st1, me1, a,
+             b);
+      if (h->chb[mode].nchunks > 0) {
+        UP(dptr, st1);
+        UP(dmeta, me1);
+        h->chb[mode].start = dptr;
+        h->chb[mode].meta = dmeta;
+      }
+      h->chb[mode].rows = trows_dev[mode];
+    }
     std::vector<int32_t> zeros(n + 1, 0);  // slot n: spare target of idle lanes
     UP(h->ready_ref, zeros);
     UP(h->ready_a, zeros);
@@ -597,6 +730,28 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
       free_device(h);
       return fail(h, KKT_ERR_INVALID_ARG, "rows too long for the dependency-driven schedule");
     }
+    // dense trailing block: density of the trailing s x s block of the factor
+    // pattern for every s up to the limit (entry (i, j) lies in the blocks with
+    // s >= n - min(i, j))
+    h->tail_s = 0;
+    if (h->syncfree && h->batch_count == 0 && h->opt.dense_tail >= 0) {
+      const int smax = std::min(n, h->opt.dense_tail > 0 ? h->opt.dense_tail : 2048);
+      std::vector<int64_t> cnt((size_t)smax + 1, 0);
+      for (int32_t i = n - smax; i < n; i++)
+        for (int32_t q = A.lu_rowptr[i]; q < A.lu_rowptr[i + 1]; q++) {
+          const int32_t j = A.lu_col[q];
+          if (j >= n - smax) cnt[(size_t)(n - std::min(i, j))]++;
+        }
+      for (int sz = 1; sz <= smax; sz++) cnt[sz] += cnt[sz - 1];
+      if (h->opt.dense_tail > 0) {
+        h->tail_s = smax;
+      } else {
+        for (int sz = 256; sz <= smax; sz += 32)
+          if (2 * cnt[sz] >= (int64_t)sz * sz) h->tail_s = sz;
+      }
+    }
+    h->tail_c0 = n - h->tail_s;
+    h->tail_S = (h->tail_s + DLU_NB - 1) / DLU_NB * DLU_NB;
   }
 #undef UP
   const size_t f = A.lu_col.size();
@@ -616,6 +771,12 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
       (ks = dalloc(h, &h->h2, m + 1)) != KKT_OK || (ks = dalloc(h, &h->ww, 1)) != KKT_OK ||
       (ks = dalloc(h, &h->y, m + 1)) != KKT_OK || (ks = dalloc(h, &h->hn, 1)) != KKT_OK ||
       (ks = dalloc(h, &h->partial, 256 * 32)) != KKT_OK) {
+    free_device(h);
+    return ks;
+  }
+  if (h->tail_s > 0 &&
+      ((ks = dalloc(h, &h->tail_T, (size_t)h->tail_S * h->tail_S)) != KKT_OK ||
+       (ks = dalloc(h, &h->tail_dsc, (size_t)DLU_NB * DLU_NB)) != KKT_OK)) {
     free_device(h);
     return ks;
   }
@@ -727,8 +888,14 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
   if (h->syncfree) {
     launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, h->ss, h->rowabs);
     if (!launch_refactor_syncfree(lu, h->lev_rows, h->cap, h->aval, h->ready_ref, h->ss,
-                                  &h->st->stall, h->light, h->opt.refactor_waves_per_block, s))
+                                  &h->st->stall, h->light, h->opt.refactor_waves_per_block,
+                                  h->tail_c0, s))
       return fail(h, KKT_ERR_DEVICE, "dependency-driven refactorization not launchable");
+    if (h->tail_s > 0) {
+      launch_tail_scatter(lu, h->tail_c0, h->tail_s, h->tail_S, h->tail_T, s);
+      launch_dense_lu(h->tail_T, h->tail_S, h->tail_dsc, s);
+      launch_tail_gather(lu, h->tail_c0, h->tail_T, h->tail_S, s);
+    }
   } else {
     launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, nullptr,
                       h->rowabs);
@@ -961,6 +1128,7 @@ kkt_status kkt_get_info(kkt_handle h, kkt_info* out) {
   out->analyze_status = A.warn_singular ? KKT_WARN_NUMERICALLY_SINGULAR : KKT_OK;
   out->device_bytes = h->device_bytes;
   out->analyze_seconds = h->analyze_seconds;
+  out->dense_tail = h->tail_s;
   return KKT_OK;
 }
 

@@ -180,3 +180,17 @@ def test_singular_warning_matches_oracle():
     rp = np.array([0, 3, 6, 7], np.int64)
     ha, lu = compare(3, rp, c.astype(np.int32), A[r, c], 1.0, user_q=np.arange(3, dtype=np.int32))
     assert ha.status == binding.WARN_NUMERICALLY_SINGULAR
+
+
+@pytest.mark.parametrize("field,value", [
+    ("solve_thin_rows", 17), ("solve_thin_rows", -2), ("refactor_waves_per_block", 3),
+    ("dense_tail", -2), ("dense_tail", 16385),
+    ("solve_entries_per_lane", 65), ("sync_mode", 3), ("fgmres_restart", 31),
+])
+def test_create_rejects_bad_options(field, value):
+    # option validation precedes any device call, so it runs without a GPU
+    import ctypes as C
+    o = binding.options(**{field: value})
+    h = C.c_void_p()
+    assert binding.lib().kkt_create(C.byref(o), C.byref(h)) == binding.ERR_INVALID_ARG
+    assert not h.value
