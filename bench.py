@@ -195,6 +195,10 @@ def main():
     ap.add_argument("--thin", type=int, default=0,
                     help="largest triangular-solve level handled by the one-workgroup "
                          "segment kernel (0 default = 16, -1 none)")
+    ap.add_argument("--solve-bpc", type=int, default=0,
+                    help="triangular-solve workgroups per CU (0 default = 8)")
+    ap.add_argument("--dense-tail", type=int, default=0,
+                    help="dense trailing block size (0 auto, -1 none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -214,7 +218,8 @@ def main():
           flush=True)
 
     s = binding.KKTSolver(device=0, schedule=args.schedule, sync_mode=args.sync_mode,
-                          solve_thin_rows=args.thin)
+                          solve_thin_rows=args.thin, solve_blocks_per_cu=args.solve_bpc,
+                          dense_tail=args.dense_tail)
     t0 = time.perf_counter()
     s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
     t_an = time.perf_counter() - t0
@@ -283,7 +288,8 @@ def main():
                                f"{args.steps} timed same-pattern matrices, 1 RHS, tau=1e-10",
                    "buses": args.buses, "n": pat.n, "nnz": pat.nnz, "nnz_lu": nnz_lu,
                    "levels": info.levels, "seed": args.seed, "schedule": args.schedule,
-                   "sync_mode": args.sync_mode, "solve_thin_rows": args.thin},
+                   "sync_mode": args.sync_mode, "solve_thin_rows": args.thin,
+                   "solve_blocks_per_cu": args.solve_bpc, "dense_tail": info.dense_tail},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "refactorization (all launches of one kkt_refactor)",

@@ -6,6 +6,11 @@ Knobs (all fields of the C options struct):
   sync_mode                 1 acquire/release fences, 2 device-coherent accesses
   solve_entries_per_lane    triangular-solve lanes per row (entries per lane)
   refactor_waves_per_block  rows in flight per workgroup in the refactorization
+  solve_thin_rows           widest level of the one-workgroup solve segments
+  dense_tail                size of the dense trailing block (0 auto, -1 none)
+
+The search is in two stages: the launch-shape candidates first, then the
+segment and dense-block variants of the winner.
 
 The winner is cached in a JSON file keyed by a hash of the pattern (n, row
 pointers, column indices), so a later run with the same pattern skips the
@@ -47,6 +52,17 @@ def candidates(full: bool = False):
     return out
 
 
+def refinements(best: dict):
+    """Second-stage variants of the first stage's winner."""
+    out = []
+    if best.get("schedule") != 2:
+        return out
+    for thin in (-1, 16):
+        out.append({**best, "solve_thin_rows": thin})
+    out.append({**best, "dense_tail": -1})
+    return out
+
+
 def load_cache(path: str = DEFAULT_CACHE) -> dict:
     try:
         with open(path) as f:
@@ -82,7 +98,8 @@ def autotune(n, rowptr, colind, values0, d_values, d_b, repeats: int = 3, full: 
     base = dict(base_options or {})
     times = {}
     best, best_t = None, float("inf")
-    for idx, cand in enumerate(candidates(full)):
+
+    def run(cand):
         opts = {**base, **cand}
         try:
             s = binding.KKTSolver(**opts)
@@ -99,12 +116,26 @@ def autotune(n, rowptr, colind, values0, d_values, d_b, repeats: int = 3, full: 
             dt = (time.perf_counter() - t0) / repeats
             s.close()
         except binding.KKTError:
+            return None
+        return dt
+
+    first = candidates(full)
+    for idx, cand in enumerate(first):
+        dt = run(cand)
+        if dt is None:
             continue
         times[idx] = dt
         if dt < best_t:
             best, best_t = cand, dt
     if best is None:
         raise RuntimeError("no autotuner candidate ran")
+    for idx, cand in enumerate(refinements(best), start=len(first)):
+        dt = run(cand)
+        if dt is None:
+            continue
+        times[idx] = dt
+        if dt < best_t:
+            best, best_t = cand, dt
     if cache_path:
         store_cache(key, {"options": best, "seconds_per_step": best_t, "n": int(n)}, cache_path)
     return dict(best), times

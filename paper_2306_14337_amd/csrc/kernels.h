@@ -18,6 +18,9 @@ struct DevStats {
   int stall;                   // a dependency wait hit its spin limit (sticky)
 };
 
+// Refactorization rows are split into at most this many bands by row length.
+constexpr int REF_MAX_BANDS = 4;
+
 // Scheduling state of the dependency-driven kernels, kept on the device so
 // that a captured launch sequence replays correctly: the kernel that precedes
 // a dependency-driven phase zeroes its ticket counter and advances its epoch;
@@ -26,6 +29,9 @@ struct DevStats {
 struct SyncState {
   unsigned int ticket[4];
   int epoch[4];
+  // refactorization bands (one launch each, see launch_refactor_syncfree):
+  // ticket counters, reset with slot 0
+  unsigned int band_ticket[REF_MAX_BANDS];
 };
 
 // Work chunks of a triangular-solve schedule: chunk c covers rows
@@ -36,6 +42,7 @@ struct ChunkSched {
   const int* start;
   const int* meta;
   const int* rows;
+  int blocks_per_cu = 8;  // persistent grid: 256-thread workgroups per CU
 };
 
 // A run of thin levels (few rows each) of a triangular-solve schedule,
@@ -55,8 +62,9 @@ struct SegSched {
   const int* dpos = nullptr;
 };
 // rows of one level a segment kernel handles at most, and segment capacity
-constexpr int SEG_MAX_LEVEL_ROWS = 16;
-constexpr int SEG_MAX_ROWS = 6144;
+// (its results stay in LDS: 128 KiB)
+constexpr int SEG_MAX_LEVEL_ROWS = 256;
+constexpr int SEG_MAX_ROWS = 16384;
 
 struct LUView {
   int n;
@@ -82,9 +90,16 @@ void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxl
 // wpb_pref: waves (rows in flight) per workgroup, 0 = chosen from the LDS need.
 // c0: first row/column of the dense trailing block (n = none): rows i >= c0
 // apply only the pivots k < c0 (the block is finished by launch_dense_lu).
-bool launch_refactor_syncfree(const LUView& lu, const int* order, int cap, const double* aval,
-                              int* ready, SyncState* ss, int* stall, bool light, int wpb_pref,
-                              int c0, hipStream_t s);
+// Band b: the rows order[cstart[0] .. cstart[nchunks]) (topological order;
+// every dependency outside them finished by an earlier launch), taken by the
+// waves in chunks order[cstart[c] .. cstart[c+1]) of rows of one level (one
+// ticket per chunk: the single counter's atomic rate would otherwise bound
+// the wide levels), cap >= their longest row, the band's ticket counter
+// ss->band_ticket[b].
+bool launch_refactor_syncfree(const LUView& lu, const int* order, const int* cstart,
+                              int nchunks, int band, int cap, const double* aval, int* ready,
+                              SyncState* ss, int* stall, bool light, int wpb_pref, int c0,
+                              hipStream_t s);
 
 // Dense trailing block: rows and columns c0 .. c0+s-1 of the factors in pivot
 // order, held row-major in T (S x S, S = s rounded up to DLU_NB; the padding

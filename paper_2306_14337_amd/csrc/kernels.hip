@@ -166,18 +166,17 @@ __device__ __forceinline__ unsigned int bcast0(unsigned int v) {
 
 // One more round of waiting allowed?  False once the limit is hit here (the
 // wave raises *stall) or anywhere else (another wave raised it).
-// The stall flag is polled every 64th round only, and the pause between
-// rounds grows with the wait (up to ~33 x 64 cycles): waves far ahead of the
-// dependency front keep their polling traffic off the memory system that the
-// front's producers are using.
+// The stall flag is polled every 64th round only; between rounds the wave
+// pauses 64 cycles.  (A pause growing with the wait, meant to keep far-ahead
+// waves off the memory system, measured slower: it delays the waves at the
+// dependency front by up to the pause length.)
 __device__ __forceinline__ bool keep_waiting(int* spins, int* stall) {
   if ((*spins & 63) == 63 && ld_flag(stall)) return false;
   if (++*spins > SPIN_LIMIT) {
     st_flag(stall, 1);
     return false;
   }
-  const int naps = min(*spins >> 3, 32);
-  for (int z = 0; z <= naps; z++) __builtin_amdgcn_s_sleep(1);
+  __builtin_amdgcn_s_sleep(1);
   return true;
 }
 
@@ -210,7 +209,8 @@ __device__ __forceinline__ void stores_done() {
 // ticket, which never terminates.
 template <int WPB, bool LIGHT>
 __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
-    const int* __restrict__ order, int n, const int* __restrict__ rowptr,
+    const int* __restrict__ order, const int* __restrict__ cstart, int nchunks,
+    unsigned int* ticket, const int* __restrict__ rowptr,
     const int* __restrict__ col, const int* __restrict__ diag, const int* __restrict__ src,
     const double* __restrict__ aval, double* val, int* ready, SyncState* ss, int* stall, int cap,
     int c0) {
@@ -221,11 +221,13 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
   int2* sk = reinterpret_cast<int2*>(smem_d + (size_t)WPB * cap) + (size_t)wave * cap;
   int* sc = reinterpret_cast<int*>(smem_d + (size_t)WPB * cap * 2) + (size_t)wave * cap;
   const int epoch = ss->epoch[0];
-  unsigned int* ticket = &ss->ticket[0];
   for (;;) {
     const unsigned int tk = bcast0(atomicAdd(ticket, lane == 0 ? 1u : 0u));
-    if (tk >= (unsigned int)n) break;
-    const int i = order[tk];
+    if (tk >= (unsigned int)nchunks) break;
+    const int r_end = cstart[tk + 1];
+    for (int r = cstart[tk]; r < r_end; r++) {
+    const int i = order[r];
+    wave_sync();  // the previous row of this chunk is done with the staging area
     const int rs = rowptr[i], len = rowptr[i + 1] - rs;
     int dl = diag[i] - rs;
     for (int t = lane; t < len; t += WAVE) {
@@ -324,6 +326,7 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
     else
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     st_flag(ready + i, epoch);  // every lane, same address and value
+    }
   }
 }
 
@@ -484,6 +487,8 @@ __device__ __forceinline__ void sync_prep(SyncState* ss, int mask) {
     if (mask & (1 << k)) {
       ss->ticket[k] = 0u;
       ss->epoch[k] = ss->epoch[k] + 1;
+      if (k == 0)
+        for (int b = 0; b < REF_MAX_BANDS; b++) ss->band_ticket[b] = 0u;
     }
 }
 
@@ -505,16 +510,43 @@ constexpr int SEG_THREADS = 1024;
 constexpr int SEG_WAVES = SEG_THREADS / WAVE;
 constexpr int SEG_PF = 4;  // prefetched entries per lane and level
 
+// Work of one level for the calling thread.  Levels of up to 16 rows: waves
+// per row ng = 16 / rows, thread t < rows finishes row t from the waves'
+// partial sums.  Wider levels (up to SEG_MAX_LEVEL_ROWS rows): G = 1024 / P
+// lanes per row (P = rows rounded up to a power of two), the group's first
+// lane finishes the row from a shuffle reduction.  The finishing thread also
+// prefetches its row index, right-hand side and (U, U^T) diagonal.
+struct SegWork {
+  int q0, stride, e;  // entries q0, q0 + stride, ... < e
+  int slot, ri;       // finisher: segment slot and row index (slot < 0: none)
+  double rc, rd;
+};
+
+__device__ __forceinline__ int seg_group(int nr) {
+  int p = 32;
+  while (p < nr) p <<= 1;
+  return SEG_THREADS / p;
+}
+
+template <int MODE>
 __device__ __forceinline__ void seg_fetch(int lev, int nlev, const int* __restrict__ lev_ptr,
+                                          const int* __restrict__ row,
                                           const int* __restrict__ ptr,
                                           const int* __restrict__ src,
                                           const int* __restrict__ vpos,
+                                          const int* __restrict__ dpos,
                                           const double* __restrict__ val,
-                                          const double* __restrict__ y, int w, int lane, int* fs,
-                                          double* fv, double* fy, int& q0, int& stride, int& e) {
-  q0 = 0;
-  stride = 1;
-  e = 0;
+                                          const double* __restrict__ c,
+                                          const double* __restrict__ y, int* fs, double* fv,
+                                          double* fy, SegWork& wk) {
+  const int t = threadIdx.x, w = t / WAVE, lane = t % WAVE;
+  wk.q0 = 0;
+  wk.stride = 1;
+  wk.e = 0;
+  wk.slot = -1;
+  wk.ri = 0;
+  wk.rc = 0.0;
+  wk.rd = 1.0;
 #pragma unroll
   for (int k = 0; k < SEG_PF; k++) {
     fs[k] = 0;
@@ -523,17 +555,38 @@ __device__ __forceinline__ void seg_fetch(int lev, int nlev, const int* __restri
   }
   if (lev >= nlev) return;
   const int r0 = lev_ptr[lev], nr = lev_ptr[lev + 1] - r0;
-  const int ng = SEG_WAVES / nr;
-  const int rr = w / ng, g = w % ng;
-  if (rr >= nr) return;
-  const int j = r0 + rr;
-  q0 = ptr[j] + g * WAVE + lane;
-  stride = ng * WAVE;
-  e = ptr[j + 1];
+  int j = -1;
+  if (nr <= 16) {
+    if (t < nr) wk.slot = r0 + t;
+    const int ng = SEG_WAVES / nr;
+    const int rr = w / ng, g = w % ng;
+    if (rr < nr) {
+      j = r0 + rr;
+      wk.q0 = g * WAVE + lane;
+      wk.stride = ng * WAVE;
+    }
+  } else {
+    const int G = seg_group(nr);
+    const int rr = t / G, gl = t % G;
+    if (rr < nr) {
+      j = r0 + rr;
+      wk.q0 = gl;
+      wk.stride = G;
+      if (gl == 0) wk.slot = j;
+    }
+  }
+  if (wk.slot >= 0) {
+    wk.ri = row[wk.slot];
+    wk.rc = c[wk.ri];
+    if (MODE == 1 || MODE == 2) wk.rd = val[dpos[wk.slot]];
+  }
+  if (j < 0) return;
+  wk.q0 += ptr[j];
+  wk.e = ptr[j + 1];
 #pragma unroll
   for (int k = 0; k < SEG_PF; k++) {
-    const int q = q0 + k * stride;
-    if (q < e) {
+    const int q = wk.q0 + k * wk.stride;
+    if (q < wk.e) {
       const int sq = src[q];
       fs[k] = sq;
       fv[k] = val[vpos[q]];
@@ -553,34 +606,40 @@ __global__ __launch_bounds__(SEG_THREADS) void k_trisolve_seg(
   const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   int cs[SEG_PF];
   double cv[SEG_PF], cy[SEG_PF];
-  int cq0, cstr, ce;
-  seg_fetch(0, nlev, lev_ptr, ptr, src, vpos, val, y, w, lane, cs, cv, cy, cq0, cstr, ce);
+  SegWork cw;
+  seg_fetch<MODE>(0, nlev, lev_ptr, row, ptr, src, vpos, dpos, val, c, y, cs, cv, cy, cw);
   for (int l = 0; l < nlev; l++) {
     int ns[SEG_PF];
     double nv[SEG_PF], ny[SEG_PF];
-    int nq0, nstr, ne;
-    seg_fetch(l + 1, nlev, lev_ptr, ptr, src, vpos, val, y, w, lane, ns, nv, ny, nq0, nstr, ne);
+    SegWork nw;
+    seg_fetch<MODE>(l + 1, nlev, lev_ptr, row, ptr, src, vpos, dpos, val, c, y, ns, nv, ny, nw);
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < SEG_PF; k++) s += cv[k] * (cs[k] >= 0 ? cy[k] : ly[-cs[k] - 1]);
-    for (int q = cq0 + SEG_PF * cstr; q < ce; q += cstr) {
+    for (int q = cw.q0 + SEG_PF * cw.stride; q < cw.e; q += cw.stride) {
       const int sq = src[q];
       s += val[vpos[q]] * (sq >= 0 ? y[sq] : ly[-sq - 1]);
     }
-    s = wave_sum(s);
-    if (lane == 0) part[w] = s;
-    __syncthreads();
-    const int r0 = lev_ptr[l], nr = lev_ptr[l + 1] - r0;
-    if (threadIdx.x < nr) {
+    const int nr = lev_ptr[l + 1] - lev_ptr[l];
+    double tot;
+    if (nr <= 16) {
+      s = wave_sum(s);
+      if (lane == 0) part[w] = s;
+      __syncthreads();
       const int ng = SEG_WAVES / nr;
-      const int j = r0 + threadIdx.x;
-      double tot = 0.0;
-      for (int g = 0; g < ng; g++) tot += part[threadIdx.x * ng + g];
-      const int i = row[j];
-      double yi = c[i] - tot;
-      if (MODE == 1 || MODE == 2) yi /= val[dpos[j]];
-      ly[j] = yi;
-      y[i] = yi;
+      tot = 0.0;
+      if (cw.slot >= 0)
+        for (int g = 0; g < ng; g++) tot += part[(int)threadIdx.x * ng + g];
+    } else {
+      const int G = seg_group(nr);
+      for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, WAVE);
+      tot = s;
+    }
+    if (cw.slot >= 0) {
+      double yi = cw.rc - tot;
+      if (MODE == 1 || MODE == 2) yi /= cw.rd;
+      ly[cw.slot] = yi;
+      y[cw.ri] = yi;
     }
     __syncthreads();
 #pragma unroll
@@ -589,9 +648,7 @@ __global__ __launch_bounds__(SEG_THREADS) void k_trisolve_seg(
       cv[k] = nv[k];
       cy[k] = ny[k];
     }
-    cq0 = nq0;
-    cstr = nstr;
-    ce = ne;
+    cw = nw;
   }
 }
 
@@ -899,24 +956,38 @@ __global__ void k_gather_prep(int n, const int* __restrict__ perm, const double*
   if (ss && i == 0) sync_prep(ss, mask);
 }
 
-__global__ void k_pivot_stats(int n, const int* __restrict__ diag, const double* __restrict__ val,
-                              DevStats* st, double tiny_rel) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_pivot_stats(int n, const int* __restrict__ diag,
+                                                     const double* __restrict__ val, DevStats* st,
+                                                     double tiny_rel) {
   double mn = __builtin_huge_val(), mx = 0.0;
   int tiny = 0;
   const double anorm = __longlong_as_double((long long)st->anorm);
-  if (i < n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const double d = fabs(val[diag[i]]);
-    mn = d;
-    mx = d;
-    tiny = !(d >= tiny_rel * anorm) || isinf(d);
+    mn = fmin(mn, d);
+    mx = fmax(mx, d);
+    tiny |= !(d >= tiny_rel * anorm) || isinf(d);
   }
   for (int off = WAVE / 2; off > 0; off >>= 1) {
     mn = fmin(mn, __shfl_xor(mn, off, WAVE));
     mx = fmax(mx, __shfl_xor(mx, off, WAVE));
     tiny |= __shfl_xor(tiny, off, WAVE);
   }
-  if ((threadIdx.x % WAVE) == 0) {
+  __shared__ double rmn[4], rmx[4];
+  __shared__ int rt[4];
+  const int w = threadIdx.x / WAVE;
+  if (threadIdx.x % WAVE == 0) {
+    rmn[w] = mn;
+    rmx[w] = mx;
+    rt[w] = tiny;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < (int)(blockDim.x / WAVE); q++) {
+      mn = fmin(mn, rmn[q]);
+      mx = fmax(mx, rmx[q]);
+      tiny |= rt[q];
+    }
     atomicMin(&st->min_piv, dbits(mn));
     atomicMax(&st->max_piv, dbits(mx));
     if (tiny) atomicOr(&st->tiny, 1);
@@ -967,6 +1038,21 @@ __device__ __forceinline__ double group_sum(double v) {
 __device__ __forceinline__ double wave_nanmax(double v) {
   for (int off = WAVE / 2; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off, WAVE));
   return v;
+}
+
+// max over a 256-thread workgroup (NaN-propagating), valid in thread 0; the
+// caller then issues one atomic per workgroup: same-address atomics
+// serialize, so one per wave over a large grid costs more than the pass
+__device__ __forceinline__ double block_nanmax(double v, double* red) {
+  v = wave_nanmax(v);
+  const int w = threadIdx.x / WAVE;
+  __syncthreads();  // red may still be read by a previous call
+  if (threadIdx.x % WAVE == 0) red[w] = v;
+  __syncthreads();
+  double m = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < (int)(blockDim.x / WAVE); q++) m = nanmax(m, red[q]);
+  return m;
 }
 
 // Per-instance maxima of a block-diagonal batch: block t reduces rows
@@ -1029,8 +1115,9 @@ __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict
       if (rowabs && gl == 0) rowabs[i] = s;
     }
   }
-  m = wave_nanmax(m);
-  if (lane == 0) atomicMax(&st->anorm, dbits(m));
+  __shared__ double red[4];
+  m = block_nanmax(m, red);
+  if (threadIdx.x == 0) atomicMax(&st->anorm, dbits(m));
 }
 
 // ||A||_1 through the column view
@@ -1053,8 +1140,9 @@ __global__ __launch_bounds__(256) void k_anorm1(int n, const int* __restrict__ c
       if (colabs && gl == 0) colabs[j] = s;
     }
   }
-  m = wave_nanmax(m);
-  if (lane == 0) atomicMax(&st->anorm1, dbits(m));
+  __shared__ double red[4];
+  m = block_nanmax(m, red);
+  if (threadIdx.x == 0) atomicMax(&st->anorm1, dbits(m));
 }
 
 // ---------------------------------------------------------------------------
@@ -1157,9 +1245,10 @@ __global__ __launch_bounds__(256) void k_residual(int n, const int* __restrict__
       xm = nanmax(xm, fabs(x[i]));
     }
   }
-  rm = wave_nanmax(rm);
-  xm = wave_nanmax(xm);
-  if (lane == 0) {
+  __shared__ double red[2][4];
+  rm = block_nanmax(rm, red[0]);
+  xm = block_nanmax(xm, red[1]);
+  if (threadIdx.x == 0) {
     atomicMax(&st->rmax, dbits(rm));
     atomicMax(&st->xmax, dbits(xm));
   }
@@ -1191,9 +1280,10 @@ __global__ __launch_bounds__(256) void k_residual_mr(int n, const int* __restric
       xm = nanmax(xm, fabs(x[i]));
     }
   }
-  rm = wave_nanmax(rm);
-  xm = wave_nanmax(xm);
-  if (lane == 0) {
+  __shared__ double red[2][4];
+  rm = block_nanmax(rm, red[0]);
+  xm = block_nanmax(xm, red[1]);
+  if (threadIdx.x == 0) {
     atomicMax(colmax + 2 * blockIdx.y, dbits(rm));
     atomicMax(colmax + 2 * blockIdx.y + 1, dbits(xm));
   }
@@ -1374,7 +1464,9 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 // grid of the grid-strided row passes: 32 rows per 256-thread block, capped
 // so that each wave loops over several row groups (one atomic per wave)
-inline int rows_grid(int n) { return std::max(1, std::min(cdiv(n, 32), 2048)); }
+// grids of the row passes: enough waves to stream A at full bandwidth, few
+// enough workgroups that their one atomic each stays cheap
+inline int rows_grid(int n) { return std::max(1, std::min(cdiv(n, 32), 1024)); }
 
 }  // namespace
 
@@ -1403,7 +1495,8 @@ void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxl
 }
 
 void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStream_t s) {
-  hipLaunchKernelGGL(k_pivot_stats, dim3(cdiv(lu.n, 256)), dim3(256), 0, s, lu.n, lu.diag, lu.val,
+  hipLaunchKernelGGL(k_pivot_stats, dim3(std::max(1, std::min(cdiv(lu.n, 256), 1024))), dim3(256),
+                     0, s, lu.n, lu.diag, lu.val,
                      st, tiny_rel);
 }
 
@@ -1418,9 +1511,12 @@ void launch_seg_stats(int count, const int* row_off, const double* matabs, const
   hipLaunchKernelGGL(k_seg_stats, dim3(count), dim3(256), 0, s, row_off, matabs, r, x, out);
 }
 
-bool launch_refactor_syncfree(const LUView& lu, const int* order, int cap, const double* aval,
-                              int* ready, SyncState* ss, int* stall, bool light, int wpb_pref,
-                              int c0, hipStream_t s) {
+bool launch_refactor_syncfree(const LUView& lu, const int* order, const int* cstart,
+                              int nchunks, int band, int cap, const double* aval, int* ready,
+                              SyncState* ss, int* stall, bool light, int wpb_pref, int c0,
+                              hipStream_t s) {
+  if (nchunks <= 0) return true;
+  if (band < 0 || band >= REF_MAX_BANDS) return false;
   cap = (cap + 1) & ~1;
   const size_t per_wave = (size_t)cap * (sizeof(double) + sizeof(int2) + sizeof(int));
   if (per_wave > 64 * 1024) return false;
@@ -1437,9 +1533,10 @@ bool launch_refactor_syncfree(const LUView& lu, const int* order, int cap, const
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, wpb * WAVE, shm) != hipSuccess ||
         nb <= 0)
       nb = 1;
-    const int grid = std::max(1, std::min(nb * ncu, cdiv(lu.n, wpb)));
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(wpb * WAVE), shm, s, order, lu.n, lu.rowptr,
-                       lu.col, lu.diag, lu.src, aval, lu.val, ready, ss, stall, cap, c0);
+    const int grid = std::max(1, std::min(nb * ncu, cdiv(nchunks, wpb)));
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(wpb * WAVE), shm, s, order, cstart, nchunks,
+                       &ss->band_ticket[band], lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val,
+                       ready, ss, stall, cap, c0);
   };
   // waves per block: the preference if its LDS fits in 64 KiB, else the
   // largest of 4, 2, 1 that fits (4 only for rows short enough for 32 KiB)
@@ -1481,7 +1578,7 @@ void launch_trisolve_syncfree(int mode, const LUView& lu, const ChunkSched& cs, 
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
     if (ncu <= 0) ncu = 256;
   }
-  const int grid = std::max(1, std::min(ncu * 8, cdiv(cs.nchunks, 4)));
+  const int grid = std::max(1, std::min(ncu * cs.blocks_per_cu, cdiv(cs.nchunks, 4)));
 #define TS_LAUNCH(M)                                                                            \
   hipLaunchKernelGGL(k_trisolve_syncfree<M>, dim3(grid), dim3(256), 0, s, lu.n, cs.nchunks,       \
                      cs.start, \
@@ -1507,7 +1604,7 @@ void launch_trisolve_vflag(int mode, const LUView& lu, const ChunkSched& cs, con
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
     if (ncu <= 0) ncu = 256;
   }
-  const int grid = std::max(1, std::min(ncu * 8, cdiv(cs.nchunks, 4)));
+  const int grid = std::max(1, std::min(ncu * cs.blocks_per_cu, cdiv(cs.nchunks, 4)));
 #define TV_LAUNCH(M)                                                                          \
   hipLaunchKernelGGL(k_trisolve_vflag<M>, dim3(grid), dim3(256), 0, s, lu.n, cs.nchunks,      \
                      cs.start, cs.meta, cs.rows, lu.rowptr, lu.col, lu.diag, tptr, trow, tpos, \
@@ -1532,7 +1629,7 @@ void launch_trisolve_vflag_mr(int mode, int nr, const LUView& lu, const ChunkSch
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
     if (ncu <= 0) ncu = 256;
   }
-  const int grid = std::max(1, std::min(ncu * 8, cdiv(cs.nchunks, 4)));
+  const int grid = std::max(1, std::min(ncu * cs.blocks_per_cu, cdiv(cs.nchunks, 4)));
   const int ld = lu.n + 1;
 #define TM_LAUNCH(M, R)                                                                        \
   hipLaunchKernelGGL((k_trisolve_vflag_mr<M, R>), dim3(grid), dim3(256), 0, s, lu.n, nr, ld,   \

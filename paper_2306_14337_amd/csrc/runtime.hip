@@ -70,6 +70,13 @@ struct kkt_ctx {
   // (tail_s of them), row-major tail_S x tail_S workspace and panel scratch
   int tail_s = 0, tail_c0 = 0, tail_S = 0;
   double *tail_T = nullptr, *tail_dsc = nullptr;
+  // refactorization bands: chunks ref_cstart[band_chunk_lo[b] ..
+  // + band_nchunks[b]] of ref_order (each band's chunk list ends with its end
+  // offset), longest row band_cap[b]
+  int *ref_order = nullptr, *ref_cstart = nullptr;
+  int nbands = 0;
+  int band_chunk_lo[REF_MAX_BANDS] = {}, band_nchunks[REF_MAX_BANDS] = {},
+      band_cap[REF_MAX_BANDS] = {};
   // statistics
   DevStats* st = nullptr;
   DevStats* h_st = nullptr;  // pinned
@@ -427,7 +434,7 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
       (o.refactor_waves_per_block != 0 && o.refactor_waves_per_block != 1 &&
        o.refactor_waves_per_block != 2 && o.refactor_waves_per_block != 4) ||
       o.solve_thin_rows < -1 || o.solve_thin_rows > SEG_MAX_LEVEL_ROWS || o.dense_tail < -1 ||
-      o.dense_tail > 16384)
+      o.dense_tail > 16384 || o.solve_blocks_per_cu < 0 || o.solve_blocks_per_cu > 8)
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) return KKT_ERR_DEVICE;
@@ -713,6 +720,10 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
       }
       h->chb[mode].rows = trows_dev[mode];
     }
+    const int bpc = h->opt.solve_blocks_per_cu > 0 ? h->opt.solve_blocks_per_cu : 8;
+    for (ChunkSched* c : {&h->ch_l, &h->ch_u, &h->ch_ut, &h->ch_lt, &h->chb[0], &h->chb[1],
+                          &h->chb[2], &h->chb[3]})
+      c->blocks_per_cu = bpc;
     std::vector<int32_t> zeros(n + 1, 0);  // slot n: spare target of idle lanes
     UP(h->ready_ref, zeros);
     UP(h->ready_a, zeros);
@@ -722,6 +733,53 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     UP(h->ss, ss0);
     h->cap = 0;
     for (int v : A.lev_maxlen) h->cap = std::max(h->cap, v);
+    // refactorization bands: a row's band is set by its length (LDS staging
+    // size, hence rows in flight per CU) and raised to the band of any row it
+    // depends on; each band is one launch, in level order
+    {
+      static const int band_len[REF_MAX_BANDS - 1] = {128, 512, 1 << 30};
+      std::vector<int8_t> band(n, 0);
+      for (int32_t i = 0; i < n; i++) {
+        const int len = A.lu_rowptr[i + 1] - A.lu_rowptr[i];
+        int b = 0;
+        while (b < REF_MAX_BANDS - 2 && len > band_len[b]) b++;
+        for (int32_t q = A.lu_rowptr[i]; q < A.diag[i]; q++) b = std::max(b, (int)band[A.lu_col[q]]);
+        band[i] = (int8_t)b;
+      }
+      // chunks: rows of one level, up to 16 per ticket on wide levels
+      std::vector<int32_t> order, cst;
+      std::vector<int32_t> lev_of(n);
+      for (size_t l = 0; l + 1 < A.lev_ptr.size(); l++)
+        for (int32_t t = A.lev_ptr[l]; t < A.lev_ptr[l + 1]; t++) lev_of[A.lev_rows[t]] = (int32_t)l;
+      order.reserve(n);
+      h->nbands = 0;
+      for (int b = 0; b < REF_MAX_BANDS - 1; b++) {
+        const int lo = (int)order.size();
+        const int clo = (int)cst.size();
+        int mx = 0;
+        for (int32_t i : A.lev_rows)
+          if (band[i] == b) {
+            order.push_back(i);
+            mx = std::max(mx, A.lu_rowptr[i + 1] - A.lu_rowptr[i]);
+          }
+        const int hi = (int)order.size();
+        if (hi == lo) continue;
+        for (int t = lo; t < hi;) {
+          int e = t;
+          while (e < hi && lev_of[order[e]] == lev_of[order[t]]) e++;
+          const int per = std::max(1, std::min(16, (e - t) / 8192));
+          for (int c = t; c < e; c += per) cst.push_back(c);
+          t = e;
+        }
+        h->band_chunk_lo[h->nbands] = clo;
+        h->band_nchunks[h->nbands] = (int)cst.size() - clo;
+        h->band_cap[h->nbands] = mx;
+        cst.push_back(hi);  // end of the band's last chunk
+        h->nbands++;
+      }
+      UP(h->ref_order, order);
+      UP(h->ref_cstart, cst);
+    }
     // LDS per row: value, column and pivot-row bounds of every entry (20 bytes)
     const bool fits = (size_t)((h->cap + 1) & ~1) * 20 <= 64 * 1024;
     h->syncfree = h->opt.schedule == 2 || (h->opt.schedule == 0 && fits);
@@ -887,10 +945,12 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
   launch_reset_stats(h->st, 1, s);
   if (h->syncfree) {
     launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, h->ss, h->rowabs);
-    if (!launch_refactor_syncfree(lu, h->lev_rows, h->cap, h->aval, h->ready_ref, h->ss,
-                                  &h->st->stall, h->light, h->opt.refactor_waves_per_block,
-                                  h->tail_c0, s))
-      return fail(h, KKT_ERR_DEVICE, "dependency-driven refactorization not launchable");
+    for (int b = 0; b < h->nbands; b++)
+      if (!launch_refactor_syncfree(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
+                                    h->band_nchunks[b], b, h->band_cap[b], h->aval, h->ready_ref,
+                                    h->ss, &h->st->stall, h->light,
+                                    h->opt.refactor_waves_per_block, h->tail_c0, s))
+        return fail(h, KKT_ERR_DEVICE, "dependency-driven refactorization not launchable");
     if (h->tail_s > 0) {
       launch_tail_scatter(lu, h->tail_c0, h->tail_s, h->tail_S, h->tail_T, s);
       launch_dense_lu(h->tail_T, h->tail_S, h->tail_dsc, s);

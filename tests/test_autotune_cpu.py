@@ -29,3 +29,14 @@ def test_cache_round_trip(tmp_path):
     autotune.store_cache("def", {"options": {"schedule": 1}, "seconds_per_step": 2e-3}, path)
     c = autotune.load_cache(path)
     assert c["abc"]["options"] == {"schedule": 2} and c["def"]["options"] == {"schedule": 1}
+
+
+def test_refinements_vary_segments_and_dense_block():
+    best = autotune.candidates()[0]
+    ref = autotune.refinements(best)
+    assert {r.get("solve_thin_rows") for r in ref} >= {-1, 16}
+    assert any(r.get("dense_tail") == -1 for r in ref)
+    for r in ref:
+        binding.options(**r)  # valid option fields
+        assert {k: v for k, v in r.items() if k not in ("solve_thin_rows", "dense_tail")} == best
+    assert autotune.refinements(dict(schedule=1, sync_mode=0)) == []

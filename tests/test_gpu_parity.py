@@ -116,7 +116,7 @@ def test_dense_tail_bitwise(B, seed, tail):
         assert eta(pat.scipy(vals), x, b) <= 1e-12
 
 
-@pytest.mark.parametrize("thin", [-1, 1, 16])
+@pytest.mark.parametrize("thin", [-1, 1, 16, 40, 256])
 @pytest.mark.parametrize("B,seed", [(3, 5), (500, 7), (2000, 104)])
 def test_direct_solve_matches_oracle_apply(B, seed, thin):
     # no refinement: the GPU's x = Q U^-1 L^-1 P Q^T b (and the transposed
