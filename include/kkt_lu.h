@@ -84,7 +84,7 @@ typedef struct {
   int32_t solve_thin_rows; /* single right-hand-side solves with device-coherent publication:
                               runs of levels with at most this many rows at either end of a
                               triangular schedule are solved by one workgroup with barriers
-                              instead of cross-CU flags (0 = 256, -1 = never; at most 256) */
+                              instead of cross-CU flags (0 = 16, -1 = never; at most 256) */
   int32_t dense_tail; /* dependency-driven refactorization: the trailing block of this many
                          pivots is finished as a dense LU (bitwise the same factors); 0 = auto
                          (the largest block of at least 256 and at most 2048 pivots that is at

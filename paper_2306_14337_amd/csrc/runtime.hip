@@ -604,7 +604,7 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     h->ch_lt.meta = dmeta;
     h->ch_lt.rows = h->ltlev_rows;
     // thin runs at both ends of each schedule (modes 0 L, 1 U, 2 U^T, 3 L^T)
-    const int thin = h->opt.solve_thin_rows == 0 ? SEG_MAX_LEVEL_ROWS : h->opt.solve_thin_rows;
+    const int thin = h->opt.solve_thin_rows == 0 ? 16 : h->opt.solve_thin_rows;
     const std::vector<int32_t>* tlp[4] = {&A.lev_ptr, &A.ulev_ptr, &A.utlev_ptr, &A.ltlev_ptr};
     const std::vector<int32_t>* trows[4] = {&A.lev_rows, &A.ulev_rows, &A.utlev_rows,
                                              &A.ltlev_rows};
