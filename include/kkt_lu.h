@@ -86,13 +86,18 @@ typedef struct {
                               triangular schedule are solved by one workgroup with barriers
                               instead of cross-CU flags (0 = 16, -1 = never; at most 256) */
   int32_t dense_tail; /* dependency-driven refactorization: the trailing block of this many
-                         pivots is finished as a dense LU (bitwise the same factors); 0 = auto
-                         (the largest block of at least 256 and at most 2048 pivots that is at
-                         least half dense, else none), -1 = never */
+                         pivots is finished as a dense LU (bitwise the same factors) and the
+                         solves treat it as a dense triangle; 0 = auto (the largest block of
+                         at least 256 and at most 2048 pivots that is at least half dense,
+                         else none), -1 = never, at most 2048 */
   int32_t solve_blocks_per_cu; /* dependency-driven triangular solves: 256-thread workgroups
                                   per CU in the persistent grid (0 = 8; 1..8): fewer waves
                                   waiting ahead of the dependency front poll less */
-  int32_t reserved[2];
+  int32_t solve_chain; /* single right-hand-side solves with device-coherent publication:
+                          longest run of chained rows (each depending on the one before)
+                          solved by one wave (0 = 32, 1..32; -1 = no chain blocks: level
+                          chunks plus one-workgroup thin segments) */
+  int32_t reserved[1];
 } kkt_options;
 
 typedef struct {

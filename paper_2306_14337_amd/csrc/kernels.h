@@ -66,6 +66,25 @@ struct SegSched {
 constexpr int SEG_MAX_LEVEL_ROWS = 256;
 constexpr int SEG_MAX_ROWS = 16384;
 
+// Chain-blocked schedule of a triangular solve (k_trisolve_sn): chunk c has
+// rows rows[start[c] .. start[c] + k) (slots), meta[c] = (chain << 16) |
+// (lg << 8) | k with G = 1 << lg lanes per row; a chain chunk's rows are
+// consecutive in the solve order starting at row base[c], each depending on
+// earlier rows of the chunk only through its internal entries; split[slot]
+// separates a row's external entries from its internal ones.
+constexpr int SN_KMAX = 32;
+struct SnSched {
+  int nchunks = 0;
+  const int* start = nullptr;
+  const int* meta = nullptr;
+  const int* base = nullptr;
+  const int* rows = nullptr;
+  const int* split = nullptr;
+  int blocks_per_cu = 8;
+};
+// largest dense trailing block (its solve keeps the block's vector in LDS)
+constexpr int DENSE_TAIL_MAX = 2048;
+
 struct LUView {
   int n;
   const int* rowptr;  // n+1
@@ -128,6 +147,19 @@ void launch_trisolve_vflag(int mode, const LUView& lu, const ChunkSched& cs, con
 // must not overlap a dependency-driven launch on the same vector.
 void launch_trisolve_seg(int mode, const SegSched& sg, const double* val, const double* c,
                          double* y, hipStream_t s);
+// Chain-blocked value-as-flag solve (modes as launch_trisolve_syncfree);
+// c, y: n + 1 entries, y holding the sentinel wherever it is not yet final.
+void launch_trisolve_sn(int mode, const LUView& lu, const SnSched& sn, const int* tptr,
+                        const int* trow, const int* tpos, const double* c, double* y,
+                        SyncState* ss, int slot, int* stall, hipStream_t s);
+// Dense trailing block of a solve (rows c0 .. c0 + s - 1, T as left by
+// launch_dense_lu or launch_tail_scatter): modes 0 and 2 first form
+// rhs = c - external terms (split[t]: end of row c0 + t's entries outside the
+// block), then every mode solves its dense triangle into y[c0 ..].  For modes
+// 1 and 3 the block comes first and rhs is c + c0.  rhs_buf: S doubles.
+void launch_tail_solve(int mode, const LUView& lu, const double* T, int S, int s, int c0,
+                       const int* split, const int* tptr, const int* trow, const int* tpos,
+                       const double* c, double* rhs_buf, double* y, hipStream_t st);
 // Right-hand sides per multi-column pass.
 constexpr int MAX_RHS_PASS = 32;
 // The same for nr <= MAX_RHS_PASS columns at once; c, y column-major with

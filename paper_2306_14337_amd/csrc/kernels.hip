@@ -834,6 +834,210 @@ __global__ __launch_bounds__(256) void k_dlu_update(double* T, int S, int k0,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Chain-blocked triangular solve (value-as-flag publication).  Consecutive
+// rows of the solve order in which each row depends on the one before form a
+// chain block of up to SN_KMAX rows, solved by one wave: the external terms
+// of all rows first (their inputs come from earlier blocks, waited for as in
+// k_trisolve_vflag), then the block's own triangle in registers and LDS, so a
+// chain of k rows costs one cross-CU hop instead of k.  Rows without a chain
+// are grouped per level as in k_trisolve_vflag.  Entries of a slot's row:
+//   MODE 0  L row i:    external [rowptr_i, split), internal [split, diag_i)
+//   MODE 1  U row i:    internal (diag_i, split), external [split, rowptr_i+1)
+//   MODE 2  U^T col i:  external [tptr_i, split), internal [split, tptr_i+1 - 1)
+//   MODE 3  L^T col i:  internal [tptr_i, split), external [split, tptr_i+1)
+// Internal entry with dependency row j sits in triangle column
+// j - base (modes 0, 2) or base - j (modes 1, 3).
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_trisolve_sn(
+    int n, int nchunks, const int* __restrict__ ch_start, const int* __restrict__ ch_meta,
+    const int* __restrict__ ch_base, const int* __restrict__ rows,
+    const int* __restrict__ split, const int* __restrict__ rowptr, const int* __restrict__ col,
+    const int* __restrict__ diag, const int* __restrict__ tptr, const int* __restrict__ trow,
+    const int* __restrict__ tpos, const double* __restrict__ val, const double* __restrict__ c,
+    double* y, SyncState* ss, int slot, int* stall) {
+  __shared__ double tri_all[256 / WAVE][SN_KMAX * SN_KMAX];
+  const int lane = threadIdx.x % WAVE;
+  double* tri = tri_all[threadIdx.x / WAVE];
+  unsigned int* ticket = &ss->ticket[slot];
+  for (;;) {
+    const unsigned int tk = bcast0(atomicAdd(ticket, lane == 0 ? 1u : 0u));
+    if (tk >= (unsigned int)nchunks) break;
+    const int meta = ch_meta[tk];
+    const int k = meta & 0xff, lg = (meta >> 8) & 0xf;
+    const bool chain = (meta >> 16) != 0;
+    const int G = 1 << lg;
+    const int grp = lane >> lg, gl = lane & (G - 1);
+    const bool active = grp < k;
+    const int s0 = ch_start[tk];
+    const int i = active ? rows[s0 + grp] : n;
+    const int sp = active ? split[s0 + grp] : 0;
+    int eb = 0, ee = 0, ib = 0, ie = 0, dpos = 0;
+    if (active) {
+      if (MODE == 0) {
+        eb = rowptr[i];
+        ee = sp;
+        ib = sp;
+        ie = diag[i];
+      } else if (MODE == 1) {
+        dpos = diag[i];
+        ib = dpos + 1;
+        ie = sp;
+        eb = sp;
+        ee = rowptr[i + 1];
+      } else if (MODE == 2) {
+        eb = tptr[i];
+        ee = sp;
+        ib = sp;
+        ie = tptr[i + 1] - 1;
+        dpos = tpos[ie];
+      } else {
+        ib = tptr[i];
+        ie = sp;
+        eb = sp;
+        ee = tptr[i + 1];
+      }
+    }
+    const double ci = c[i];
+    const double dv = (MODE == 1 || MODE == 2) && active ? val[dpos] : 1.0;
+    if (chain) {
+      // the block's own triangle into LDS (issued before the waits below)
+      const int b = ch_base[tk];
+      for (int e = lane; e < k * SN_KMAX; e += WAVE) tri[e] = 0.0;
+      wave_sync();
+      for (int q = ib + gl; q < ie; q += G) {
+        const int j = MODE <= 1 ? col[q] : trow[q];
+        const double v = MODE <= 1 ? val[q] : val[tpos[q]];
+        const int sg = (MODE == 0 || MODE == 2) ? j - b : b - j;
+        tri[grp * SN_KMAX + sg] = v;
+      }
+    }
+    int spins = 0;
+    double s = 0.0;
+    constexpr int VB = 8;
+    for (int q0 = eb + gl; q0 < ee; q0 += VB * G) {
+      int kk[VB];
+      double v[VB], yk[VB];
+#pragma unroll
+      for (int u = 0; u < VB; u++) {
+        const int q = q0 + u * G;
+        kk[u] = n;
+        v[u] = 0.0;
+        if (q < ee) {
+          kk[u] = MODE <= 1 ? col[q] : trow[q];
+          v[u] = MODE <= 1 ? val[q] : val[tpos[q]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < VB; u++) yk[u] = q0 + u * G < ee ? ld_coh(y + kk[u]) : 0.0;
+#pragma unroll
+      for (int u = 0; u < VB; u++) {
+        while (is_sentinel(yk[u]) && keep_waiting(&spins, stall)) yk[u] = ld_coh(y + kk[u]);
+        if (q0 + u * G < ee) s += v[u] * yk[u];
+      }
+    }
+    for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, WAVE);
+    if (chain) {
+      wave_sync();
+      // row sg is final at step sg: its value goes to every lane, the later
+      // rows take their term with it
+      for (int sg = 0; sg < k; sg++) {
+        double yv = ci - s;
+        if (MODE == 1 || MODE == 2) yv /= dv;
+        const double ys = readlane_d(yv, sg << lg);
+        if (grp > sg && active) s += tri[grp * SN_KMAX + sg] * ys;
+      }
+    }
+    double yv = ci - s;
+    if (MODE == 1 || MODE == 2) yv /= dv;
+    st_coh(y + i, yv);
+  }
+}
+
+// External terms of the dense trailing block's rows (modes 0 and 2; their
+// inputs are final): rhs[t] = c[c0 + t] - sum over the entries before split[t]
+// of row (MODE 0) / column (MODE 2) c0 + t; rhs[t] = 0 on padding rows.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_tail_ext(int c0, int s, int S,
+                                                  const int* __restrict__ split,
+                                                  const int* __restrict__ rowptr,
+                                                  const int* __restrict__ col,
+                                                  const int* __restrict__ tptr,
+                                                  const int* __restrict__ trow,
+                                                  const int* __restrict__ tpos,
+                                                  const double* __restrict__ val,
+                                                  const double* __restrict__ c,
+                                                  const double* __restrict__ y, double* rhs) {
+  const int lane = threadIdx.x % WAVE;
+  const int t = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (t >= S) return;
+  if (t >= s) {
+    if (lane == 0) rhs[t] = 0.0;
+    return;
+  }
+  const int i = c0 + t;
+  const int b = MODE == 0 ? rowptr[i] : tptr[i];
+  double acc = 0.0;
+  for (int q = b + lane; q < split[t]; q += WAVE)
+    acc += MODE == 0 ? val[q] * y[col[q]] : val[tpos[q]] * y[trow[q]];
+  acc = wave_sum(acc);
+  if (lane == 0) rhs[t] = c[i] - acc;
+}
+
+// Dense triangular solve on the trailing block by one workgroup, blocks of
+// TB = 32 rows: wave 0 solves the block's diagonal triangle with the block's
+// matrix rows in registers (broadcast by readlane), then all threads take the
+// block's terms out of the remaining rows (row per thread).  x lives in LDS.
+//   MODE 0: L (unit lower), forward      MODE 1: U (upper), backward
+//   MODE 2: U^T (lower), forward         MODE 3: L^T (unit upper), backward
+// M[r][q] is T[r][q] (modes 0, 1) or T[q][r] (modes 2, 3).
+constexpr int TB = 32;
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_tail_trsv(const double* __restrict__ T, int S, int s,
+                                                    int c0, const double* __restrict__ rhs,
+                                                    double* y) {
+  __shared__ double x[DENSE_TAIL_MAX];
+  constexpr bool fwd = MODE == 0 || MODE == 2;
+  constexpr bool trans = MODE == 2 || MODE == 3;
+  auto M = [&](int r, int q) -> double {
+    return trans ? T[(size_t)q * S + r] : T[(size_t)r * S + q];
+  };
+  for (int t = threadIdx.x; t < S; t += blockDim.x) x[t] = t < s ? rhs[t] : 0.0;
+  __syncthreads();
+  const int nb = S / TB;
+  for (int bb = 0; bb < nb; bb++) {
+    const int b0 = (fwd ? bb : nb - 1 - bb) * TB;
+    if (threadIdx.x < WAVE) {
+      const int r = threadIdx.x;
+      double m[TB];
+#pragma unroll
+      for (int q = 0; q < TB; q++) m[q] = r < TB ? M(b0 + r, b0 + q) : 0.0;
+      double xr = r < TB ? x[b0 + r] : 0.0;
+#pragma unroll
+      for (int st = 0; st < TB; st++) {
+        const int q = fwd ? st : TB - 1 - st;
+        if (MODE == 1 || MODE == 2) xr = r == q ? xr / m[q] : xr;
+        const double xq = readlane_d(xr, q);
+        const bool later = fwd ? r > q : r < q;
+        if (later) xr = __builtin_fma(-m[q], xq, xr);
+      }
+      if (r < TB) x[b0 + r] = xr;
+    }
+    __syncthreads();
+    // remaining rows: after the block (forward) or before it (backward)
+    const int lo = fwd ? b0 + TB : 0, hi = fwd ? S : b0;
+    for (int r = lo + threadIdx.x; r < hi; r += blockDim.x) {
+      double acc = x[r];
+#pragma unroll 8
+      for (int q = 0; q < TB; q++) acc = __builtin_fma(-M(r, b0 + q), x[b0 + q], acc);
+      x[r] = acc;
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < s; t += blockDim.x) y[c0 + t] = x[t];
+}
+
 // Several right-hand sides in one launch (nr <= NR, column-major with leading
 // dimension ld = n + 1): each entry's NR dependency loads are in flight
 // together; the dependency depth is paid once for all columns.
@@ -1675,6 +1879,61 @@ void launch_dense_lu(double* T, int S, double* dsc, hipStream_t st) {
     const int nt = std::max(1, cdiv(rest, 64));
     hipLaunchKernelGGL(k_dlu_update<DLU_NB>, dim3(nt, nt), dim3(256), 0, st, T, S, k0,
                        (const double*)dsc);
+  }
+}
+
+void launch_trisolve_sn(int mode, const LUView& lu, const SnSched& sn, const int* tptr,
+                        const int* trow, const int* tpos, const double* c, double* y,
+                        SyncState* ss, int slot, int* stall, hipStream_t s) {
+  if (sn.nchunks <= 0) return;
+  static int ncu = 0;
+  if (ncu == 0) {
+    int d = 0;
+    (void)hipGetDevice(&d);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
+    if (ncu <= 0) ncu = 256;
+  }
+  const int grid = std::max(1, std::min(ncu * sn.blocks_per_cu, cdiv(sn.nchunks, 4)));
+#define SN_LAUNCH(M)                                                                           \
+  hipLaunchKernelGGL(k_trisolve_sn<M>, dim3(grid), dim3(256), 0, s, lu.n, sn.nchunks, sn.start, \
+                     sn.meta, sn.base, sn.rows, sn.split, lu.rowptr, lu.col, lu.diag, tptr, trow, \
+                     tpos, lu.val, c, y, ss, slot, stall)
+  switch (mode) {
+    case 0: SN_LAUNCH(0); break;
+    case 1: SN_LAUNCH(1); break;
+    case 2: SN_LAUNCH(2); break;
+    default: SN_LAUNCH(3); break;
+  }
+#undef SN_LAUNCH
+}
+
+void launch_tail_solve(int mode, const LUView& lu, const double* T, int S, int s, int c0,
+                       const int* split, const int* tptr, const int* trow, const int* tpos,
+                       const double* c, double* rhs_buf, double* y, hipStream_t st) {
+  if (s <= 0 || S > DENSE_TAIL_MAX) return;
+  const double* rhs = c + c0;
+  if (mode == 0 || mode == 2) {
+    if (mode == 0)
+      hipLaunchKernelGGL(k_tail_ext<0>, dim3(cdiv(S, 4)), dim3(256), 0, st, c0, s, S, split,
+                         lu.rowptr, lu.col, tptr, trow, tpos, lu.val, c, y, rhs_buf);
+    else
+      hipLaunchKernelGGL(k_tail_ext<2>, dim3(cdiv(S, 4)), dim3(256), 0, st, c0, s, S, split,
+                         lu.rowptr, lu.col, tptr, trow, tpos, lu.val, c, y, rhs_buf);
+    rhs = rhs_buf;
+  }
+  switch (mode) {
+    case 0:
+      hipLaunchKernelGGL(k_tail_trsv<0>, dim3(1), dim3(1024), 0, st, T, S, s, c0, rhs, y);
+      break;
+    case 1:
+      hipLaunchKernelGGL(k_tail_trsv<1>, dim3(1), dim3(1024), 0, st, T, S, s, c0, rhs, y);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_tail_trsv<2>, dim3(1), dim3(1024), 0, st, T, S, s, c0, rhs, y);
+      break;
+    default:
+      hipLaunchKernelGGL(k_tail_trsv<3>, dim3(1), dim3(1024), 0, st, T, S, s, c0, rhs, y);
+      break;
   }
 }
 

@@ -69,7 +69,12 @@ struct kkt_ctx {
   // dense trailing block of the refactorization: pivots tail_c0 .. n-1
   // (tail_s of them), row-major tail_S x tail_S workspace and panel scratch
   int tail_s = 0, tail_c0 = 0, tail_S = 0;
-  double *tail_T = nullptr, *tail_dsc = nullptr;
+  double *tail_T = nullptr, *tail_dsc = nullptr, *tail_rhs = nullptr;
+  int *tail_split0 = nullptr, *tail_split2 = nullptr;
+  // chain-blocked single right-hand-side solves (modes 0 L, 1 U, 2 U^T, 3 L^T)
+  bool use_sn = false;
+  SnSched chs[4]{};
+  int chs_levels[4] = {};
   // refactorization bands: chunks ref_cstart[band_chunk_lo[b] ..
   // + band_nchunks[b]] of ref_order (each band's chunk list ends with its end
   // offset), longest row band_cap[b]
@@ -180,6 +185,36 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
   const Analysis& A = h->an;
   const int n = A.n;
   LUView lu = view(h);
+  if (h->use_sn) {
+    // chain-blocked sparse rows and the dense trailing block: the block comes
+    // last in the forward solves (L, U^T) and first in the backward ones
+    int* stall = &h->st->stall;
+    const int c0 = h->tail_c0, ts = h->tail_s, S = h->tail_S;
+    if (op == 'N') {
+      launch_gather_sentinel(n, h->pin, b, h->tc, h->ty, h->tz, h->ss, 0x6, s);
+      launch_trisolve_sn(0, lu, h->chs[0], nullptr, nullptr, nullptr, h->tc, h->ty, h->ss, 1,
+                         stall, s);
+      launch_tail_solve(0, lu, h->tail_T, S, ts, c0, h->tail_split0, nullptr, nullptr, nullptr,
+                        h->tc, h->tail_rhs, h->ty, s);
+      launch_tail_solve(1, lu, h->tail_T, S, ts, c0, nullptr, nullptr, nullptr, nullptr, h->ty,
+                        h->tail_rhs, h->tz, s);
+      launch_trisolve_sn(1, lu, h->chs[1], nullptr, nullptr, nullptr, h->ty, h->tz, h->ss, 2,
+                         stall, s);
+      launch_scatter(n, h->qperm, h->tz, x, s);
+    } else {
+      launch_gather_sentinel(n, h->qperm, b, h->tc, h->ty, h->tz, h->ss, 0x6, s);
+      launch_trisolve_sn(2, lu, h->chs[2], h->ut_ptr, h->ut_row, h->ut_pos, h->tc, h->ty, h->ss,
+                         1, stall, s);
+      launch_tail_solve(2, lu, h->tail_T, S, ts, c0, h->tail_split2, h->ut_ptr, h->ut_row,
+                        h->ut_pos, h->tc, h->tail_rhs, h->ty, s);
+      launch_tail_solve(3, lu, h->tail_T, S, ts, c0, nullptr, nullptr, nullptr, nullptr, h->ty,
+                        h->tail_rhs, h->tz, s);
+      launch_trisolve_sn(3, lu, h->chs[3], h->lt_ptr, h->lt_row, h->lt_pos, h->ty, h->tz, h->ss,
+                         2, stall, s);
+      launch_scatter(n, h->pin, h->tz, x, s);
+    }
+    return;
+  }
   if (h->syncfree && h->light) {
     // per triangle: thin leading levels (one workgroup), the levels between
     // (dependency-driven), thin trailing levels (one workgroup)
@@ -434,7 +469,8 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
       (o.refactor_waves_per_block != 0 && o.refactor_waves_per_block != 1 &&
        o.refactor_waves_per_block != 2 && o.refactor_waves_per_block != 4) ||
       o.solve_thin_rows < -1 || o.solve_thin_rows > SEG_MAX_LEVEL_ROWS || o.dense_tail < -1 ||
-      o.dense_tail > 16384 || o.solve_blocks_per_cu < 0 || o.solve_blocks_per_cu > 8)
+      o.dense_tail > DENSE_TAIL_MAX || o.solve_blocks_per_cu < 0 || o.solve_blocks_per_cu > 8 ||
+      o.solve_chain < -1 || o.solve_chain > SN_KMAX)
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) return KKT_ERR_DEVICE;
@@ -811,6 +847,180 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     h->tail_c0 = n - h->tail_s;
     h->tail_S = (h->tail_s + DLU_NB - 1) / DLU_NB * DLU_NB;
   }
+  // chain-blocked schedules of the four solves over the rows outside the
+  // dense trailing block (modes 0 L, 1 U, 2 U^T, 3 L^T)
+  h->use_sn = h->syncfree && h->light && h->batch_count == 0 && h->opt.solve_chain >= 0;
+  if (h->use_sn) {
+    const int c0 = h->tail_c0;
+    const int kmax = h->opt.solve_chain > 0 ? std::min(h->opt.solve_chain, SN_KMAX) : SN_KMAX;
+    std::vector<int32_t> rowof(A.lu_col.size());
+    for (int32_t i = 0; i < n; i++)
+      for (int32_t q = A.lu_rowptr[i]; q < A.lu_rowptr[i + 1]; q++) rowof[q] = i;
+    for (int mode = 0; mode < 4; mode++) {
+      const bool fwd = mode == 0 || mode == 2;
+      // dependency list of row i (ascending dependency index), diagonal excluded
+      auto lb = [&](int32_t i) -> int32_t {
+        return mode == 0 ? A.lu_rowptr[i]
+               : mode == 1 ? A.diag[i] + 1
+               : mode == 2 ? A.ut_ptr[i]
+                           : A.lt_ptr[i];
+      };
+      auto le = [&](int32_t i) -> int32_t {
+        return mode == 0 ? A.diag[i]
+               : mode == 1 ? A.lu_rowptr[i + 1]
+               : mode == 2 ? A.ut_ptr[i + 1] - 1
+                           : A.lt_ptr[i + 1];
+      };
+      auto dep = [&](int32_t q) -> int32_t {
+        return mode <= 1 ? A.lu_col[q] : rowof[mode == 2 ? A.ut_pos[q] : A.lt_pos[q]];
+      };
+      // items: runs of consecutive rows (solve order) each depending on the
+      // previous one, up to kmax rows and 64 lanes at <= 32 entries per lane
+      std::vector<int32_t> item_of(c0, -1), item_first, item_len, item_lev;
+      auto lanes_for = [](int len) {
+        int g = 1;
+        while (g < 64 && g * 32 < len) g <<= 1;
+        return g;
+      };
+      auto p2 = [](int k) {
+        int p = 1;
+        while (p < k) p <<= 1;
+        return p;
+      };
+      int cur_max = 0;
+      for (int32_t t = 0; t < c0; t++) {
+        const int32_t i = fwd ? t : c0 - 1 - t;
+        const int32_t b = lb(i), e = le(i);
+        const int len = e - b;
+        bool ext = false;
+        if (!item_first.empty() && t > 0) {
+          const int32_t p = fwd ? i - 1 : i + 1;
+          const bool chained = len > 0 && (fwd ? dep(e - 1) == p : dep(b) == p);
+          const int k = item_len.back();
+          const int mx = std::max(cur_max, len);
+          ext = chained && k < kmax && p2(k + 1) * lanes_for(mx) <= 64;
+        }
+        if (ext) {
+          item_len.back()++;
+          cur_max = std::max(cur_max, len);
+        } else {
+          item_first.push_back(i);
+          item_len.push_back(1);
+          cur_max = len;
+        }
+        item_of[i] = (int32_t)item_first.size() - 1;
+      }
+      const int nitems = (int)item_first.size();
+      item_lev.assign(nitems, 0);
+      int nlev = 0;
+      for (int it = 0; it < nitems; it++) {
+        int lv = 0;
+        for (int r = 0; r < item_len[it]; r++) {
+          const int32_t i = fwd ? item_first[it] + r : item_first[it] - r;
+          for (int32_t q = lb(i); q < le(i); q++) {
+            const int32_t j = dep(q);
+            if (j >= c0 || item_of[j] == it) continue;
+            lv = std::max(lv, item_lev[item_of[j]] + 1);
+          }
+        }
+        item_lev[it] = lv;
+        nlev = std::max(nlev, lv + 1);
+      }
+      // chunks in level order
+      std::vector<int32_t> by_lev_ptr(nlev + 1, 0), by_lev(nitems);
+      for (int it = 0; it < nitems; it++) by_lev_ptr[item_lev[it] + 1]++;
+      for (int l = 0; l < nlev; l++) by_lev_ptr[l + 1] += by_lev_ptr[l];
+      {
+        std::vector<int32_t> fill(by_lev_ptr.begin(), by_lev_ptr.end() - 1);
+        for (int it = 0; it < nitems; it++) by_lev[fill[item_lev[it]]++] = it;
+      }
+      std::vector<int32_t> cst, cmeta, cbase, crow, csplit;
+      auto split_of = [&](int32_t i, bool chain, int32_t base) -> int32_t {
+        const int32_t b = lb(i), e = le(i);
+        if (!chain) return (mode == 0 || mode == 2) ? e : b;
+        // internal dependencies: rows of the chunk, i.e. index >= base
+        // (forward) or <= base (backward)
+        int32_t q = b;
+        if (fwd)
+          while (q < e && dep(q) < base) q++;
+        else
+          while (q < e && dep(q) <= base) q++;
+        return q;
+      };
+      for (int l = 0; l < nlev; l++) {
+        std::vector<int32_t> singles;
+        for (int32_t t = by_lev_ptr[l]; t < by_lev_ptr[l + 1]; t++) {
+          const int it = by_lev[t];
+          const int k = item_len[it];
+          if (k == 1) {
+            singles.push_back(item_first[it]);
+            continue;
+          }
+          int lg = 0;
+          while ((1 << lg) * p2(k) < 64) lg++;
+          cst.push_back((int32_t)crow.size());
+          cmeta.push_back((1 << 16) | (lg << 8) | k);
+          cbase.push_back(item_first[it]);
+          for (int r = 0; r < k; r++) {
+            const int32_t i = fwd ? item_first[it] + r : item_first[it] - r;
+            crow.push_back(i);
+            csplit.push_back(split_of(i, true, item_first[it]));
+          }
+        }
+        if (singles.empty()) continue;
+        int mx = 0;
+        for (int32_t i : singles) mx = std::max(mx, le(i) - lb(i));
+        const int per_lane =
+            h->opt.solve_entries_per_lane > 0 ? h->opt.solve_entries_per_lane : 8;
+        int lg = 2;
+        while (lg < 6 && (per_lane << lg) < mx) lg++;
+        const int per = 64 >> lg;
+        for (size_t a = 0; a < singles.size(); a += per) {
+          const int k = (int)std::min<size_t>(per, singles.size() - a);
+          cst.push_back((int32_t)crow.size());
+          cmeta.push_back((lg << 8) | k);
+          cbase.push_back(0);
+          for (int r = 0; r < k; r++) {
+            crow.push_back(singles[a + r]);
+            csplit.push_back(split_of(singles[a + r], false, 0));
+          }
+        }
+      }
+      SnSched& sn = h->chs[mode];
+      sn = SnSched{};
+      sn.nchunks = (int)cst.size();
+      sn.blocks_per_cu = h->opt.solve_blocks_per_cu > 0 ? h->opt.solve_blocks_per_cu : 8;
+      h->chs_levels[mode] = nlev;
+      if (sn.nchunks > 0) {
+        int *a1, *a2, *a3, *a4, *a5;
+        UP(a1, cst);
+        UP(a2, cmeta);
+        UP(a3, cbase);
+        UP(a4, crow);
+        UP(a5, csplit);
+        sn.start = a1;
+        sn.meta = a2;
+        sn.base = a3;
+        sn.rows = a4;
+        sn.split = a5;
+      }
+    }
+    // external/internal boundary of the dense block's rows (modes 0 and 2)
+    if (h->tail_s > 0) {
+      std::vector<int32_t> s0(h->tail_s), s2(h->tail_s);
+      for (int t = 0; t < h->tail_s; t++) {
+        const int32_t i = c0 + t;
+        int32_t q = A.lu_rowptr[i];
+        while (q < A.diag[i] && A.lu_col[q] < c0) q++;
+        s0[t] = q;
+        q = A.ut_ptr[i];
+        while (q < A.ut_ptr[i + 1] - 1 && rowof[A.ut_pos[q]] < c0) q++;
+        s2[t] = q;
+      }
+      UP(h->tail_split0, s0);
+      UP(h->tail_split2, s2);
+    }
+  }
 #undef UP
   const size_t f = A.lu_col.size();
   const int m = h->m;
@@ -834,7 +1044,8 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   }
   if (h->tail_s > 0 &&
       ((ks = dalloc(h, &h->tail_T, (size_t)h->tail_S * h->tail_S)) != KKT_OK ||
-       (ks = dalloc(h, &h->tail_dsc, (size_t)DLU_NB * DLU_NB)) != KKT_OK)) {
+       (ks = dalloc(h, &h->tail_dsc, (size_t)DLU_NB * DLU_NB)) != KKT_OK ||
+       (ks = dalloc(h, &h->tail_rhs, (size_t)h->tail_S)) != KKT_OK)) {
     free_device(h);
     return ks;
   }
@@ -864,6 +1075,9 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   launch_copy_anorm(n, h->a_rowptr, h->a_col, h->aval, h->aval, h->st, nullptr, nullptr,
                     h->rowabs);
   launch_pivot_stats(view(h), h->st, h->opt.tiny_pivot_rel, nullptr);
+  // the dense block's copy of the pivoting pass's factors (the solves read it)
+  if (h->tail_s > 0)
+    launch_tail_scatter(view(h), h->tail_c0, h->tail_s, h->tail_S, h->tail_T, nullptr);
   HIP_CHECK(h, hipGetLastError());
   HIP_CHECK(h, hipDeviceSynchronize());
   h->anorm1_valid = false;

@@ -116,29 +116,46 @@ def test_dense_tail_bitwise(B, seed, tail):
         assert eta(pat.scipy(vals), x, b) <= 1e-12
 
 
-@pytest.mark.parametrize("thin", [-1, 1, 16, 40, 256])
+# solve layouts: chain blocks (solve_chain) with and without the dense block;
+# the older level-chunk + one-workgroup segment path (solve_chain=-1) for
+# several segment widths
+SOLVE_LAYOUTS = [
+    dict(solve_chain=0), dict(solve_chain=1), dict(solve_chain=8),
+    dict(solve_chain=0, dense_tail=-1), dict(solve_chain=0, dense_tail=200),
+    dict(solve_chain=-1, solve_thin_rows=-1), dict(solve_chain=-1, solve_thin_rows=1),
+    dict(solve_chain=-1, solve_thin_rows=16), dict(solve_chain=-1, solve_thin_rows=40),
+    dict(solve_chain=-1, solve_thin_rows=256),
+]
+
+
+@pytest.mark.parametrize("layout", SOLVE_LAYOUTS, ids=lambda d: "-".join(f"{k}{v}" for k, v in d.items()))
 @pytest.mark.parametrize("B,seed", [(3, 5), (500, 7), (2000, 104)])
-def test_direct_solve_matches_oracle_apply(B, seed, thin):
+def test_direct_solve_matches_oracle_apply(B, seed, layout):
     # no refinement: the GPU's x = Q U^-1 L^-1 P Q^T b (and the transposed
-    # chain) against the oracle's; thin = largest level solved by the
-    # one-workgroup segment kernel (-1: none, all levels dependency-driven)
-    print(f"case B={B} seed={seed} thin={thin}", flush=True)
+    # chain) against the oracle's
+    print(f"case B={B} seed={seed} {layout}", flush=True)
     pat, seq = kktgen.make_sequence(B, seed, 1)
     vals, b = seq[0]
-    s = binding.KKTSolver(schedule=2, sync_mode=2, fgmres_max_iters=0, solve_thin_rows=thin)
+    opts = dict(layout)
+    if opts.get("dense_tail", 0) > pat.n:
+        opts["dense_tail"] = pat.n
+    s = binding.KKTSolver(schedule=2, sync_mode=2, fgmres_max_iters=0, **opts)
     s.analyze(pat.n, pat.rowptr, pat.colind, vals)
-    s.refactor(dev(vals))
     ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, vals, tau=1e-10)
     A = pat.scipy(vals)
-    for op, M in (("N", A), ("T", A.T.tocsr())):
-        x = s.solve(dev(b), op=op).cpu().numpy()
-        xo = ora.apply(b, op)
-        # the two differ only in the summation order inside each row
-        err = np.abs(x - xo).max() / np.abs(xo).max()
-        print(f"  op {op}: rel diff {err:.3e} eta {eta(M, x, b):.3e} "
-              f"oracle eta {eta(M, xo, b):.3e}", flush=True)
-        assert err <= 1e-8, (op, err)
-        assert eta(M, x, b) <= max(100 * eta(M, xo, b), 1e-14), op
+    # first with the analysis's own factors, then after a refactorization
+    for stage in ("analysis", "refactor"):
+        if stage == "refactor":
+            s.refactor(dev(vals))
+        for op, M in (("N", A), ("T", A.T.tocsr())):
+            x = s.solve(dev(b), op=op).cpu().numpy()
+            xo = ora.apply(b, op)
+            # the two differ only in the summation order inside each row
+            err = np.abs(x - xo).max() / np.abs(xo).max()
+            print(f"  {stage} op {op}: rel diff {err:.3e} eta {eta(M, x, b):.3e} "
+                  f"oracle eta {eta(M, xo, b):.3e}", flush=True)
+            assert err <= 1e-8, (stage, op, err)
+            assert eta(M, x, b) <= max(100 * eta(M, xo, b), 1e-14), (stage, op)
 
 
 @pytest.mark.parametrize("schedule", SCHEDULES)
