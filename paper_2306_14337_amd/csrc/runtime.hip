@@ -769,53 +769,6 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     UP(h->ss, ss0);
     h->cap = 0;
     for (int v : A.lev_maxlen) h->cap = std::max(h->cap, v);
-    // refactorization bands: a row's band is set by its length (LDS staging
-    // size, hence rows in flight per CU) and raised to the band of any row it
-    // depends on; each band is one launch, in level order
-    {
-      static const int band_len[REF_MAX_BANDS - 1] = {128, 512, 1 << 30};
-      std::vector<int8_t> band(n, 0);
-      for (int32_t i = 0; i < n; i++) {
-        const int len = A.lu_rowptr[i + 1] - A.lu_rowptr[i];
-        int b = 0;
-        while (b < REF_MAX_BANDS - 2 && len > band_len[b]) b++;
-        for (int32_t q = A.lu_rowptr[i]; q < A.diag[i]; q++) b = std::max(b, (int)band[A.lu_col[q]]);
-        band[i] = (int8_t)b;
-      }
-      // chunks: rows of one level, up to 16 per ticket on wide levels
-      std::vector<int32_t> order, cst;
-      std::vector<int32_t> lev_of(n);
-      for (size_t l = 0; l + 1 < A.lev_ptr.size(); l++)
-        for (int32_t t = A.lev_ptr[l]; t < A.lev_ptr[l + 1]; t++) lev_of[A.lev_rows[t]] = (int32_t)l;
-      order.reserve(n);
-      h->nbands = 0;
-      for (int b = 0; b < REF_MAX_BANDS - 1; b++) {
-        const int lo = (int)order.size();
-        const int clo = (int)cst.size();
-        int mx = 0;
-        for (int32_t i : A.lev_rows)
-          if (band[i] == b) {
-            order.push_back(i);
-            mx = std::max(mx, A.lu_rowptr[i + 1] - A.lu_rowptr[i]);
-          }
-        const int hi = (int)order.size();
-        if (hi == lo) continue;
-        for (int t = lo; t < hi;) {
-          int e = t;
-          while (e < hi && lev_of[order[e]] == lev_of[order[t]]) e++;
-          const int per = std::max(1, std::min(16, (e - t) / 8192));
-          for (int c = t; c < e; c += per) cst.push_back(c);
-          t = e;
-        }
-        h->band_chunk_lo[h->nbands] = clo;
-        h->band_nchunks[h->nbands] = (int)cst.size() - clo;
-        h->band_cap[h->nbands] = mx;
-        cst.push_back(hi);  // end of the band's last chunk
-        h->nbands++;
-      }
-      UP(h->ref_order, order);
-      UP(h->ref_cstart, cst);
-    }
     // LDS per row: value, column and pivot-row bounds of every entry (20 bytes)
     const bool fits = (size_t)((h->cap + 1) & ~1) * 20 <= 64 * 1024;
     h->syncfree = h->opt.schedule == 2 || (h->opt.schedule == 0 && fits);
@@ -846,6 +799,94 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     }
     h->tail_c0 = n - h->tail_s;
     h->tail_S = (h->tail_s + DLU_NB - 1) / DLU_NB * DLU_NB;
+  }
+  // refactorization bands: a row's band is set by its length (LDS staging
+  // size, hence rows in flight per CU) and raised to the band of any row it
+  // depends on; each band is one launch.  Within a band rows go by level of
+  // the sparse phase's dependency graph (rows of the dense block do not
+  // depend on each other there), and within a level by decreasing height
+  // (longest chain of rows depending on them), so that a level's rows on the
+  // critical chains are handed out first.
+  {
+    static const int band_len[REF_MAX_BANDS - 1] = {128, 512, 1 << 30};
+    const int c0 = h->tail_c0;
+    std::vector<int32_t> rowof(A.lu_col.size());
+    for (int32_t i = 0; i < n; i++)
+      for (int32_t q = A.lu_rowptr[i]; q < A.lu_rowptr[i + 1]; q++) rowof[q] = i;
+    std::vector<int32_t> height(n, 0), level(n, 0);
+    int hmax = 0, lmax = 0;
+    for (int32_t k = n - 1; k >= 0; k--) {
+      int hk = 0;
+      for (int32_t q = A.lt_ptr[k]; q < A.lt_ptr[k + 1]; q++) {
+        const int32_t i = rowof[A.lt_pos[q]];
+        if (k >= c0 && i >= c0) continue;
+        hk = std::max(hk, height[i] + 1);
+      }
+      height[k] = hk;
+      hmax = std::max(hmax, hk);
+    }
+    for (int32_t i = 0; i < n; i++) {
+      int li = 0;
+      for (int32_t q = A.lu_rowptr[i]; q < A.diag[i]; q++) {
+        const int32_t k = A.lu_col[q];
+        if (i >= c0 && k >= c0) break;
+        li = std::max(li, level[k] + 1);
+      }
+      level[i] = li;
+      lmax = std::max(lmax, li);
+    }
+    std::vector<int8_t> band(n, 0);
+    for (int32_t i = 0; i < n; i++) {
+      const int len = A.lu_rowptr[i + 1] - A.lu_rowptr[i];
+      int b = 0;
+      while (b < REF_MAX_BANDS - 2 && len > band_len[b]) b++;
+      for (int32_t q = A.lu_rowptr[i]; q < A.diag[i]; q++) b = std::max(b, (int)band[A.lu_col[q]]);
+      band[i] = (int8_t)b;
+    }
+    // rows by (level, decreasing height): two stable counting sorts
+    std::vector<int32_t> by_h(n), by_lh(n);
+    {
+      std::vector<int32_t> cnt(hmax + 2, 0);
+      for (int32_t i = 0; i < n; i++) cnt[hmax - height[i] + 1]++;
+      for (int v = 0; v <= hmax; v++) cnt[v + 1] += cnt[v];
+      for (int32_t i = 0; i < n; i++) by_h[cnt[hmax - height[i]]++] = i;
+      std::vector<int32_t> lc(lmax + 2, 0);
+      for (int32_t i = 0; i < n; i++) lc[level[i] + 1]++;
+      for (int v = 0; v <= lmax; v++) lc[v + 1] += lc[v];
+      for (int32_t i : by_h) by_lh[lc[level[i]]++] = i;
+    }
+    // chunks: rows of one level (independent of each other), up to 16 per
+    // ticket on wide levels; one device-scope ticket counter serializes at
+    // about 10 ns per ticket, so single-row tickets would bound the wide part
+    std::vector<int32_t> order, cst;
+    order.reserve(n);
+    h->nbands = 0;
+    for (int b = 0; b < REF_MAX_BANDS - 1; b++) {
+      const int lo = (int)order.size();
+      const int clo = (int)cst.size();
+      int mx = 0;
+      for (int32_t i : by_lh)
+        if (band[i] == b) {
+          order.push_back(i);
+          mx = std::max(mx, A.lu_rowptr[i + 1] - A.lu_rowptr[i]);
+        }
+      const int hi = (int)order.size();
+      if (hi == lo) continue;
+      for (int t = lo; t < hi;) {
+        int e = t;
+        while (e < hi && level[order[e]] == level[order[t]]) e++;
+        const int per = std::max(1, std::min(16, (e - t) / 8192));
+        for (int c = t; c < e; c += per) cst.push_back(c);
+        t = e;
+      }
+      h->band_chunk_lo[h->nbands] = clo;
+      h->band_nchunks[h->nbands] = (int)cst.size() - clo;
+      h->band_cap[h->nbands] = mx;
+      cst.push_back(hi);  // end of the band's last chunk
+      h->nbands++;
+    }
+    UP(h->ref_order, order);
+    UP(h->ref_cstart, cst);
   }
   // chain-blocked schedules of the four solves over the rows outside the
   // dense trailing block (modes 0 L, 1 U, 2 U^T, 3 L^T)
