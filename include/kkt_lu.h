@@ -97,7 +97,10 @@ typedef struct {
                           longest run of chained rows (each depending on the one before)
                           solved by one wave (0 = 32, 1..32; -1 = no chain blocks: level
                           chunks plus one-workgroup thin segments) */
-  int32_t reserved[1];
+  int32_t refactor_map; /* dependency-driven refactorization: 0 = precomputed update positions
+                           (one 16-bit entry per multiply-add of the factorization, built once
+                           at analysis), -1 = binary search of each update's column instead */
+  int32_t reserved[4];
 } kkt_options;
 
 typedef struct {

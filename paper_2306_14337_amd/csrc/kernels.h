@@ -115,10 +115,15 @@ void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxl
 // ticket per chunk: the single counter's atomic rate would otherwise bound
 // the wide levels), cap >= their longest row, the band's ticket counter
 // ss->band_ticket[b].
+// moff/map (both or neither): precomputed update positions (launch_build_refmap)
+// replacing the per-entry binary search.
 bool launch_refactor_syncfree(const LUView& lu, const int* order, const int* cstart,
                               int nchunks, int band, int cap, const double* aval, int* ready,
                               SyncState* ss, int* stall, bool light, int wpb_pref, int c0,
-                              hipStream_t s);
+                              const int* moff, const unsigned short* map, hipStream_t s);
+// map[moff[q] + u] = position in row i of U(k, >k)'s u-th column, for every L
+// entry q = (i, k) (moff: offsets indexed by factor position, host-computed)
+void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map, hipStream_t s);
 
 // Dense trailing block: rows and columns c0 .. c0+s-1 of the factors in pivot
 // order, held row-major in T (S x S, S = s rounded up to DLU_NB; the padding

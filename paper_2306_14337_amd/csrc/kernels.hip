@@ -207,13 +207,39 @@ __device__ __forceinline__ void stores_done() {
 // flag value.  A lane-0-only region at the loop boundary lets the compiler
 // split the loop so that lanes 1..63 iterate without lane 0 on a stale
 // ticket, which never terminates.
-template <int WPB, bool LIGHT>
+// Update maps of the refactorization, built once per analysis: for the L
+// entry q = (i, k), map[moff[q] + u] = position (from the row start) of the
+// column of U(k, >k)'s u-th entry in row i.  Wave per row, lanes over U(k).
+__global__ __launch_bounds__(256) void k_build_refmap(int n, const int* __restrict__ rowptr,
+                                                      const int* __restrict__ col,
+                                                      const int* __restrict__ diag,
+                                                      const int* __restrict__ moff,
+                                                      unsigned short* __restrict__ map) {
+  const int lane = threadIdx.x % WAVE;
+  const int nw = gridDim.x * blockDim.x / WAVE;
+  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE; i < n; i += nw) {
+    const int rs = rowptr[i], re = rowptr[i + 1];
+    for (int q = rs; q < diag[i]; q++) {
+      const int k = col[q], ub = diag[k] + 1, ue = rowptr[k + 1];
+      const int mo = moff[q];
+      for (int u = ub + lane; u < ue; u += WAVE) {
+        const int p = lower_bound_i(col, q + 1, re, col[u]);
+        map[mo + (u - ub)] = (unsigned short)(p - rs);
+      }
+    }
+  }
+}
+
+// MAPPED: the target position of every update comes from a precomputed map
+// (map[moff[q] + u] = position in row i of the u-th entry of U(k, >k) for
+// the L entry q = (i, k)) instead of a binary search over the staged columns.
+template <int WPB, bool LIGHT, bool MAPPED>
 __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
     const int* __restrict__ order, const int* __restrict__ cstart, int nchunks,
     unsigned int* ticket, const int* __restrict__ rowptr,
     const int* __restrict__ col, const int* __restrict__ diag, const int* __restrict__ src,
     const double* __restrict__ aval, double* val, int* ready, SyncState* ss, int* stall, int cap,
-    int c0) {
+    int c0, const int* __restrict__ moff, const unsigned short* __restrict__ map) {
   extern __shared__ double smem_d[];
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   // LDS per wave: values (cap doubles), pivot-row bounds (cap int2), columns (cap ints)
@@ -248,7 +274,7 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
     // software pipeline: the pivot and the first 64 entries of the next ready
     // pivot row are in flight while the current one is applied
     double ukk = 0.0, u0 = 0.0;
-    int j0 = -1;
+    int j0 = -1, mo = 0;
     bool have = false;
     for (int t = 0; t < dl; t++) {
       if (t >= ready_upto) {
@@ -275,37 +301,63 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
         if (!LIGHT) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       const int2 kk = sk[t];
+      // j0: first-chunk entry's column (binary search) or target position (map)
       if (!have) {
         ukk = LIGHT ? ld_coh(val + kk.x) : val[kk.x];
         const int q = kk.x + 1 + lane;
         j0 = -1;
+        if (MAPPED) mo = moff[rs + t];
         if (q < kk.y) {
-          j0 = col[q];
+          j0 = MAPPED ? (int)map[mo + lane] : col[q];
           u0 = LIGHT ? ld_coh(val + q) : val[q];
         }
       }
       double ukk_n = 0.0, u0_n = 0.0;
-      int j0_n = -1;
+      int j0_n = -1, mo_n = 0;
       const bool have_n = t + 1 < dl && t + 1 < ready_upto;
       if (have_n) {
         const int2 kn = sk[t + 1];
         ukk_n = LIGHT ? ld_coh(val + kn.x) : val[kn.x];
         const int q = kn.x + 1 + lane;
+        if (MAPPED) mo_n = moff[rs + t + 1];
         if (q < kn.y) {
-          j0_n = col[q];
+          j0_n = MAPPED ? (int)map[mo_n + lane] : col[q];
           u0_n = LIGHT ? ld_coh(val + q) : val[q];
         }
       }
       const double lik = sv[t] / ukk;
-      if (j0 >= 0) {
-        const int p = lower_bound_i(sc, t + 1, len, j0);
-        if (p < len && sc[p] == j0) sv[p] = __builtin_fma(-lik, u0, sv[p]);
-      }
-      for (int q = kk.x + 1 + WAVE + lane; q < kk.y; q += WAVE) {
-        const int j = col[q];
-        const double u = LIGHT ? ld_coh(val + q) : val[q];
-        const int p = lower_bound_i(sc, t + 1, len, j);
-        if (p < len && sc[p] == j) sv[p] = __builtin_fma(-lik, u, sv[p]);
+      if (MAPPED) {
+        if (j0 >= 0) sv[j0] = __builtin_fma(-lik, u0, sv[j0]);
+        // remaining chunks: four loads of each kind in flight per lane
+        const int ub = kk.x + 1;
+        for (int q0 = ub + WAVE + lane; q0 < kk.y; q0 += 4 * WAVE) {
+          double u[4];
+          int p[4];
+#pragma unroll
+          for (int z = 0; z < 4; z++) {
+            const int q = q0 + z * WAVE;
+            p[z] = -1;
+            u[z] = 0.0;
+            if (q < kk.y) {
+              p[z] = map[mo + (q - ub)];
+              u[z] = LIGHT ? ld_coh(val + q) : val[q];
+            }
+          }
+#pragma unroll
+          for (int z = 0; z < 4; z++)
+            if (p[z] >= 0) sv[p[z]] = __builtin_fma(-lik, u[z], sv[p[z]]);
+        }
+      } else {
+        if (j0 >= 0) {
+          const int p = lower_bound_i(sc, t + 1, len, j0);
+          if (p < len && sc[p] == j0) sv[p] = __builtin_fma(-lik, u0, sv[p]);
+        }
+        for (int q = kk.x + 1 + WAVE + lane; q < kk.y; q += WAVE) {
+          const int j = col[q];
+          const double u = LIGHT ? ld_coh(val + q) : val[q];
+          const int p = lower_bound_i(sc, t + 1, len, j);
+          if (p < len && sc[p] == j) sv[p] = __builtin_fma(-lik, u, sv[p]);
+        }
       }
       wave_sync();
       sv[t] = lik;  // every lane writes the same value
@@ -313,6 +365,7 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
       ukk = ukk_n;
       u0 = u0_n;
       j0 = j0_n;
+      mo = mo_n;
       have = have_n;
     }
     for (int t = lane; t < len; t += WAVE) {
@@ -1715,10 +1768,15 @@ void launch_seg_stats(int count, const int* row_off, const double* matabs, const
   hipLaunchKernelGGL(k_seg_stats, dim3(count), dim3(256), 0, s, row_off, matabs, r, x, out);
 }
 
+void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_refmap, dim3(std::max(1, std::min(cdiv(lu.n, 4), 4096))), dim3(256),
+                     0, s, lu.n, lu.rowptr, lu.col, lu.diag, moff, map);
+}
+
 bool launch_refactor_syncfree(const LUView& lu, const int* order, const int* cstart,
                               int nchunks, int band, int cap, const double* aval, int* ready,
                               SyncState* ss, int* stall, bool light, int wpb_pref, int c0,
-                              hipStream_t s) {
+                              const int* moff, const unsigned short* map, hipStream_t s) {
   if (nchunks <= 0) return true;
   if (band < 0 || band >= REF_MAX_BANDS) return false;
   cap = (cap + 1) & ~1;
@@ -1740,7 +1798,7 @@ bool launch_refactor_syncfree(const LUView& lu, const int* order, const int* cst
     const int grid = std::max(1, std::min(nb * ncu, cdiv(nchunks, wpb)));
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(wpb * WAVE), shm, s, order, cstart, nchunks,
                        &ss->band_ticket[band], lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val,
-                       ready, ss, stall, cap, c0);
+                       ready, ss, stall, cap, c0, moff, map);
   };
   // waves per block: the preference if its LDS fits in 64 KiB, else the
   // largest of 4, 2, 1 that fits (4 only for rows short enough for 32 KiB)
@@ -1753,21 +1811,30 @@ bool launch_refactor_syncfree(const LUView& lu, const int* order, const int* cst
   } else if (per_wave * 2 <= 64 * 1024) {
     wpb = 2;
   }
+  const bool mapped = moff != nullptr && map != nullptr;
+#define RF_GO(W, L)                                   \
+  do {                                                \
+    if (mapped)                                       \
+      go(k_refactor_syncfree<W, L, true>, W);         \
+    else                                              \
+      go(k_refactor_syncfree<W, L, false>, W);        \
+  } while (0)
   if (light) {
     if (wpb == 4)
-      go(k_refactor_syncfree<4, true>, 4);
+      RF_GO(4, true);
     else if (wpb == 2)
-      go(k_refactor_syncfree<2, true>, 2);
+      RF_GO(2, true);
     else
-      go(k_refactor_syncfree<1, true>, 1);
+      RF_GO(1, true);
   } else {
     if (wpb == 4)
-      go(k_refactor_syncfree<4, false>, 4);
+      RF_GO(4, false);
     else if (wpb == 2)
-      go(k_refactor_syncfree<2, false>, 2);
+      RF_GO(2, false);
     else
-      go(k_refactor_syncfree<1, false>, 1);
+      RF_GO(1, false);
   }
+#undef RF_GO
   return true;
 }
 

@@ -79,6 +79,10 @@ struct kkt_ctx {
   // + band_nchunks[b]] of ref_order (each band's chunk list ends with its end
   // offset), longest row band_cap[b]
   int *ref_order = nullptr, *ref_cstart = nullptr;
+  // precomputed update positions of the refactorization (null: binary search)
+  int* ref_moff = nullptr;
+  unsigned short* ref_map = nullptr;
+  int64_t ref_map_entries = 0;
   int nbands = 0;
   int band_chunk_lo[REF_MAX_BANDS] = {}, band_nchunks[REF_MAX_BANDS] = {},
       band_cap[REF_MAX_BANDS] = {};
@@ -470,7 +474,7 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
        o.refactor_waves_per_block != 2 && o.refactor_waves_per_block != 4) ||
       o.solve_thin_rows < -1 || o.solve_thin_rows > SEG_MAX_LEVEL_ROWS || o.dense_tail < -1 ||
       o.dense_tail > DENSE_TAIL_MAX || o.solve_blocks_per_cu < 0 || o.solve_blocks_per_cu > 8 ||
-      o.solve_chain < -1 || o.solve_chain > SN_KMAX)
+      o.solve_chain < -1 || o.solve_chain > SN_KMAX || o.refactor_map < -1 || o.refactor_map > 0)
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) return KKT_ERR_DEVICE;
@@ -888,6 +892,33 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     UP(h->ref_order, order);
     UP(h->ref_cstart, cst);
   }
+  // update maps of the dependency-driven refactorization: one 16-bit row
+  // position per multiply-add (rows must be shorter than 65536 entries and
+  // the total must fit int32 offsets)
+  h->ref_moff = nullptr;
+  h->ref_map = nullptr;
+  h->ref_map_entries = 0;
+  if (h->syncfree && h->opt.refactor_map >= 0) {
+    std::vector<int32_t> moff(A.lu_col.size(), 0);
+    int64_t tot = 0;
+    int maxlen = 0;
+    for (int32_t i = 0; i < n; i++) {
+      maxlen = std::max(maxlen, A.lu_rowptr[i + 1] - A.lu_rowptr[i]);
+      for (int32_t q = A.lu_rowptr[i]; q < A.diag[i]; q++) {
+        const int32_t k = A.lu_col[q];
+        moff[q] = (int32_t)std::min<int64_t>(tot, INT32_MAX);
+        tot += A.lu_rowptr[k + 1] - A.diag[k] - 1;
+      }
+    }
+    if (maxlen < 65536 && tot < INT32_MAX && tot > 0) {
+      UP(h->ref_moff, moff);
+      if ((ks = dalloc(h, &h->ref_map, (size_t)tot)) != KKT_OK) {
+        free_device(h);
+        return ks;
+      }
+      h->ref_map_entries = tot;
+    }
+  }
   // chain-blocked schedules of the four solves over the rows outside the
   // dense trailing block (modes 0 L, 1 U, 2 U^T, 3 L^T)
   h->use_sn = h->syncfree && h->light && h->batch_count == 0 && h->opt.solve_chain >= 0;
@@ -1116,6 +1147,7 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   launch_copy_anorm(n, h->a_rowptr, h->a_col, h->aval, h->aval, h->st, nullptr, nullptr,
                     h->rowabs);
   launch_pivot_stats(view(h), h->st, h->opt.tiny_pivot_rel, nullptr);
+  if (h->ref_map) launch_build_refmap(view(h), h->ref_moff, h->ref_map, nullptr);
   // the dense block's copy of the pivoting pass's factors (the solves read it)
   if (h->tail_s > 0)
     launch_tail_scatter(view(h), h->tail_c0, h->tail_s, h->tail_S, h->tail_T, nullptr);
@@ -1204,7 +1236,8 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
       if (!launch_refactor_syncfree(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
                                     h->band_nchunks[b], b, h->band_cap[b], h->aval, h->ready_ref,
                                     h->ss, &h->st->stall, h->light,
-                                    h->opt.refactor_waves_per_block, h->tail_c0, s))
+                                    h->opt.refactor_waves_per_block, h->tail_c0, h->ref_moff,
+                                    h->ref_map, s))
         return fail(h, KKT_ERR_DEVICE, "dependency-driven refactorization not launchable");
     if (h->tail_s > 0) {
       launch_tail_scatter(lu, h->tail_c0, h->tail_s, h->tail_S, h->tail_T, s);

@@ -89,6 +89,20 @@ def test_sequence_refactor_solve(B, seed, steps, schedule):
         assert info["converged"] == 1
 
 
+@pytest.mark.parametrize("B,seed", [(100, 101), (2000, 104)])
+def test_refactor_without_update_maps_bitwise(B, seed):
+    # binary search of each update's column instead of the precomputed map
+    print(f"case B={B} seed={seed} refactor_map=-1", flush=True)
+    pat, seq = kktgen.make_sequence(B, seed, 2)
+    s = binding.KKTSolver(schedule=2, sync_mode=2, refactor_map=-1)
+    s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
+    ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, seq[0][0], tau=1e-10)
+    for vals, b in seq:
+        s.refactor(dev(vals))
+        ora.refactor(vals)
+        assert_factors_equal(s.lu()[2], oracle_csr_values(ora))
+
+
 @pytest.mark.parametrize("B,seed,tail", [
     (3, 5, 26),       # the whole matrix is the dense block (n = 26, padded to 32)
     (100, 101, 100),  # padded block, ragged last panel
