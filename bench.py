@@ -22,6 +22,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+# HBM traffic of one refactorization measured with rocprofv3 PMC counters
+# (FETCH_SIZE, WRITE_SIZE), valid only for the kernel sources it was taken on
+PMC_FILE = os.path.join(ROOT, "profiles", "refactor_70k_pmc.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2306_14337_amd", "csrc", f)
+                  for f in ("kernels.hip", "kernels.h", "runtime.hip")]
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(buses: int):
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per refactorization from the
+    committed PMC summary, or None if it is absent, for another size, or
+    taken on different kernel sources."""
+    try:
+        with open(PMC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("buses") != buses or d.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return float(d["hbm_bytes_per_refactor"])
 
 
 def algorithmic_bytes(nnz_a: int, nnz_lu: int, n: int):
@@ -199,6 +227,10 @@ def main():
                     help="triangular-solve workgroups per CU (0 default = 8)")
     ap.add_argument("--dense-tail", type=int, default=0,
                     help="dense trailing block size (0 auto, -1 none)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 2 GiB read + 2 GiB write elementwise kernel before timing, its "
+                         "source evicted from the 256 MiB last-level cache by a 1 GiB fill (the "
+                         "scale of the PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -234,6 +266,15 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
+    if args.copy_calibration:
+        src = torch.ones(256 << 20, dtype=torch.float64, device=dev)
+        flush = torch.zeros(128 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst, flush
+        torch.cuda.empty_cache()
     for k in range(args.warmup):
         s.refactor(vals_d[k])
         s.solve(rhs_d[k], xs[k])
@@ -291,7 +332,7 @@ def main():
                    "sync_mode": args.sync_mode, "solve_thin_rows": args.thin,
                    "solve_blocks_per_cu": args.solve_bpc, "dense_tail": info.dense_tail},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.buses),
                      "kernel": "refactorization (all launches of one kkt_refactor)",
                      "bytes_per_launch": ref_b, "avg_ms": t_ref_med * 1e3},
         "phases_ms": {"refactor_median": float(np.median(t_ref)),
