@@ -227,6 +227,8 @@ def main():
                     help="triangular-solve workgroups per CU (0 default = 8)")
     ap.add_argument("--dense-tail", type=int, default=0,
                     help="dense trailing block size (0 auto, -1 none)")
+    ap.add_argument("--solve-chain", type=int, default=0,
+                    help="longest chain block of the solves (0 default = 32, -1 level chunks)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 2 GiB read + 2 GiB write elementwise kernel before timing, its "
                          "source evicted from the 256 MiB last-level cache by a 1 GiB fill (the "
@@ -251,7 +253,7 @@ def main():
 
     s = binding.KKTSolver(device=0, schedule=args.schedule, sync_mode=args.sync_mode,
                           solve_thin_rows=args.thin, solve_blocks_per_cu=args.solve_bpc,
-                          dense_tail=args.dense_tail)
+                          dense_tail=args.dense_tail, solve_chain=args.solve_chain)
     t0 = time.perf_counter()
     s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
     t_an = time.perf_counter() - t0
@@ -330,7 +332,8 @@ def main():
                    "buses": args.buses, "n": pat.n, "nnz": pat.nnz, "nnz_lu": nnz_lu,
                    "levels": info.levels, "seed": args.seed, "schedule": args.schedule,
                    "sync_mode": args.sync_mode, "solve_thin_rows": args.thin,
-                   "solve_blocks_per_cu": args.solve_bpc, "dense_tail": info.dense_tail},
+                   "solve_blocks_per_cu": args.solve_bpc, "solve_chain": args.solve_chain,
+                   "dense_tail": info.dense_tail},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.buses),
                      "kernel": "refactorization (all launches of one kkt_refactor)",

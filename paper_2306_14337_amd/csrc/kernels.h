@@ -152,17 +152,20 @@ void launch_trisolve_vflag(int mode, const LUView& lu, const ChunkSched& cs, con
 // must not overlap a dependency-driven launch on the same vector.
 void launch_trisolve_seg(int mode, const SegSched& sg, const double* val, const double* c,
                          double* y, hipStream_t s);
-// Chain-blocked value-as-flag solve (modes as launch_trisolve_syncfree);
-// c, y: n + 1 entries, y holding the sentinel wherever it is not yet final.
-void launch_trisolve_sn(int mode, const LUView& lu, const SnSched& sn, const int* tptr,
+// Chain-blocked value-as-flag solve (modes as launch_trisolve_syncfree) of
+// nr <= SN_MAX_RHS right-hand sides; c, y column-major with leading dimension
+// n + 1, y holding the sentinel wherever it is not yet final.
+constexpr int SN_MAX_RHS = 8;
+void launch_trisolve_sn(int mode, int nr, const LUView& lu, const SnSched& sn, const int* tptr,
                         const int* trow, const int* tpos, const double* c, double* y,
                         SyncState* ss, int slot, int* stall, hipStream_t s);
 // Dense trailing block of a solve (rows c0 .. c0 + s - 1, T as left by
-// launch_dense_lu or launch_tail_scatter): modes 0 and 2 first form
-// rhs = c - external terms (split[t]: end of row c0 + t's entries outside the
-// block), then every mode solves its dense triangle into y[c0 ..].  For modes
-// 1 and 3 the block comes first and rhs is c + c0.  rhs_buf: S doubles.
-void launch_tail_solve(int mode, const LUView& lu, const double* T, int S, int s, int c0,
+// launch_dense_lu or launch_tail_scatter), nr columns (ld n + 1): modes 0
+// and 2 first form rhs = c - external terms (split[t]: end of row c0 + t's
+// entries outside the block), then every mode solves its dense triangle into
+// y[c0 ..].  For modes 1 and 3 the block comes first and rhs is c + c0.
+// rhs_buf: 8 S doubles.
+void launch_tail_solve(int mode, int nr, const LUView& lu, const double* T, int S, int s, int c0,
                        const int* split, const int* tptr, const int* trow, const int* tpos,
                        const double* c, double* rhs_buf, double* y, hipStream_t st);
 // Right-hand sides per multi-column pass.

@@ -902,10 +902,12 @@ __global__ __launch_bounds__(256) void k_dlu_update(double* T, int S, int k0,
 // Internal entry with dependency row j sits in triangle column
 // j - base (modes 0, 2) or base - j (modes 1, 3).
 // ---------------------------------------------------------------------------
-template <int MODE>
+// NR >= nr right-hand sides (column r at c + r * ld, y + r * ld; ld = n + 1
+// for several, unused for one): every lane keeps nr sums.
+template <int MODE, int NR>
 __global__ __launch_bounds__(256) void k_trisolve_sn(
-    int n, int nchunks, const int* __restrict__ ch_start, const int* __restrict__ ch_meta,
-    const int* __restrict__ ch_base, const int* __restrict__ rows,
+    int n, int nr, int ld, int nchunks, const int* __restrict__ ch_start,
+    const int* __restrict__ ch_meta, const int* __restrict__ ch_base, const int* __restrict__ rows,
     const int* __restrict__ split, const int* __restrict__ rowptr, const int* __restrict__ col,
     const int* __restrict__ diag, const int* __restrict__ tptr, const int* __restrict__ trow,
     const int* __restrict__ tpos, const double* __restrict__ val, const double* __restrict__ c,
@@ -952,7 +954,9 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(
         ee = tptr[i + 1];
       }
     }
-    const double ci = c[i];
+    double ci[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) ci[r] = r < nr ? c[(size_t)r * ld + i] : 0.0;
     const double dv = (MODE == 1 || MODE == 2) && active ? val[dpos] : 1.0;
     if (chain) {
       // the block's own triangle into LDS (issued before the waits below)
@@ -967,11 +971,13 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(
       }
     }
     int spins = 0;
-    double s = 0.0;
-    constexpr int VB = 8;
+    double s[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) s[r] = 0.0;
+    constexpr int VB = NR == 1 ? 8 : (NR <= 4 ? 2 : 1);
     for (int q0 = eb + gl; q0 < ee; q0 += VB * G) {
       int kk[VB];
-      double v[VB], yk[VB];
+      double v[VB], yk[VB][NR];
 #pragma unroll
       for (int u = 0; u < VB; u++) {
         const int q = q0 + u * G;
@@ -983,28 +989,43 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(
         }
       }
 #pragma unroll
-      for (int u = 0; u < VB; u++) yk[u] = q0 + u * G < ee ? ld_coh(y + kk[u]) : 0.0;
+      for (int u = 0; u < VB; u++)
 #pragma unroll
-      for (int u = 0; u < VB; u++) {
-        while (is_sentinel(yk[u]) && keep_waiting(&spins, stall)) yk[u] = ld_coh(y + kk[u]);
-        if (q0 + u * G < ee) s += v[u] * yk[u];
-      }
+        for (int r = 0; r < NR; r++)
+          yk[u][r] = (q0 + u * G < ee && r < nr) ? ld_coh(y + (size_t)r * ld + kk[u]) : 0.0;
+#pragma unroll
+      for (int u = 0; u < VB; u++)
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+          while (is_sentinel(yk[u][r]) && keep_waiting(&spins, stall))
+            yk[u][r] = ld_coh(y + (size_t)r * ld + kk[u]);
+          if (q0 + u * G < ee) s[r] += v[u] * yk[u][r];
+        }
     }
-    for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, WAVE);
+#pragma unroll
+    for (int r = 0; r < NR; r++)
+      for (int off = G >> 1; off > 0; off >>= 1) s[r] += __shfl_xor(s[r], off, WAVE);
     if (chain) {
       wave_sync();
-      // row sg is final at step sg: its value goes to every lane, the later
-      // rows take their term with it
+      // row sg is final at step sg: its values go to every lane, the later
+      // rows take their terms with them
       for (int sg = 0; sg < k; sg++) {
-        double yv = ci - s;
-        if (MODE == 1 || MODE == 2) yv /= dv;
-        const double ys = readlane_d(yv, sg << lg);
-        if (grp > sg && active) s += tri[grp * SN_KMAX + sg] * ys;
+        const double tv = (grp > sg && active) ? tri[grp * SN_KMAX + sg] : 0.0;
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+          double yv = ci[r] - s[r];
+          if (MODE == 1 || MODE == 2) yv /= dv;
+          const double ys = readlane_d(yv, sg << lg);
+          s[r] += tv * ys;
+        }
       }
     }
-    double yv = ci - s;
-    if (MODE == 1 || MODE == 2) yv /= dv;
-    st_coh(y + i, yv);
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+      double yv = ci[r] - s[r];
+      if (MODE == 1 || MODE == 2) yv /= dv;
+      if (r < nr) st_coh(y + (size_t)r * ld + i, yv);
+    }
   }
 }
 
@@ -1012,7 +1033,7 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(
 // inputs are final): rhs[t] = c[c0 + t] - sum over the entries before split[t]
 // of row (MODE 0) / column (MODE 2) c0 + t; rhs[t] = 0 on padding rows.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_tail_ext(int c0, int s, int S,
+__global__ __launch_bounds__(256) void k_tail_ext(int c0, int s, int S, int nr, int ld,
                                                   const int* __restrict__ split,
                                                   const int* __restrict__ rowptr,
                                                   const int* __restrict__ col,
@@ -1024,45 +1045,54 @@ __global__ __launch_bounds__(256) void k_tail_ext(int c0, int s, int S,
                                                   const double* __restrict__ y, double* rhs) {
   const int lane = threadIdx.x % WAVE;
   const int t = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-  if (t >= S) return;
+  const int r = blockIdx.y;
+  if (t >= S || r >= nr) return;
   if (t >= s) {
-    if (lane == 0) rhs[t] = 0.0;
+    if (lane == 0) rhs[(size_t)r * S + t] = 0.0;
     return;
   }
   const int i = c0 + t;
+  const double* yr = y + (size_t)r * ld;
   const int b = MODE == 0 ? rowptr[i] : tptr[i];
   double acc = 0.0;
   for (int q = b + lane; q < split[t]; q += WAVE)
-    acc += MODE == 0 ? val[q] * y[col[q]] : val[tpos[q]] * y[trow[q]];
+    acc += MODE == 0 ? val[q] * yr[col[q]] : val[tpos[q]] * yr[trow[q]];
   acc = wave_sum(acc);
-  if (lane == 0) rhs[t] = c[i] - acc;
+  if (lane == 0) rhs[(size_t)r * S + t] = c[(size_t)r * ld + i] - acc;
 }
 
 // Dense triangular solve on the trailing block by one workgroup, blocks of
-// TB = 32 rows: wave 0 solves the block's diagonal triangle with the block's
-// matrix rows in registers (broadcast by readlane), then all threads take the
-// block's terms out of the remaining rows (row per thread).  x lives in LDS.
+// TB = 32 rows: for each block, wave r (r < nr) solves column r's diagonal
+// triangle with the block's matrix rows in registers (broadcast by readlane),
+// then every thread takes the block's terms out of one remaining row for all
+// columns.  x (nr columns of S) lives in LDS.
 //   MODE 0: L (unit lower), forward      MODE 1: U (upper), backward
 //   MODE 2: U^T (lower), forward         MODE 3: L^T (unit upper), backward
-// M[r][q] is T[r][q] (modes 0, 1) or T[q][r] (modes 2, 3).
+// M[r][q] is T[r][q] (modes 0, 1) or T[q][r] (modes 2, 3).  rhs: column r at
+// rhs + r * rld; y: column r at y + r * ld.
 constexpr int TB = 32;
-template <int MODE>
+constexpr int TAIL_NR = 8;  // columns per dense-block solve launch
+template <int MODE, int NRT>
 __global__ __launch_bounds__(1024) void k_tail_trsv(const double* __restrict__ T, int S, int s,
-                                                    int c0, const double* __restrict__ rhs,
-                                                    double* y) {
-  __shared__ double x[DENSE_TAIL_MAX];
+                                                    int c0, int nr, const double* __restrict__ rhs,
+                                                    int rld, double* y, int ld) {
+  extern __shared__ double xs[];
   constexpr bool fwd = MODE == 0 || MODE == 2;
   constexpr bool trans = MODE == 2 || MODE == 3;
   auto M = [&](int r, int q) -> double {
     return trans ? T[(size_t)q * S + r] : T[(size_t)r * S + q];
   };
-  for (int t = threadIdx.x; t < S; t += blockDim.x) x[t] = t < s ? rhs[t] : 0.0;
+  for (int cr = 0; cr < nr; cr++)
+    for (int t = threadIdx.x; t < S; t += blockDim.x)
+      xs[(size_t)cr * S + t] = t < s ? rhs[(size_t)cr * rld + t] : 0.0;
   __syncthreads();
   const int nb = S / TB;
+  const int wv = threadIdx.x / WAVE;
   for (int bb = 0; bb < nb; bb++) {
     const int b0 = (fwd ? bb : nb - 1 - bb) * TB;
-    if (threadIdx.x < WAVE) {
-      const int r = threadIdx.x;
+    if (wv < nr) {
+      double* x = xs + (size_t)wv * S;
+      const int r = threadIdx.x % WAVE;
       double m[TB];
 #pragma unroll
       for (int q = 0; q < TB; q++) m[q] = r < TB ? M(b0 + r, b0 + q) : 0.0;
@@ -1080,15 +1110,29 @@ __global__ __launch_bounds__(1024) void k_tail_trsv(const double* __restrict__ T
     __syncthreads();
     // remaining rows: after the block (forward) or before it (backward)
     const int lo = fwd ? b0 + TB : 0, hi = fwd ? S : b0;
-    for (int r = lo + threadIdx.x; r < hi; r += blockDim.x) {
-      double acc = x[r];
-#pragma unroll 8
-      for (int q = 0; q < TB; q++) acc = __builtin_fma(-M(r, b0 + q), x[b0 + q], acc);
-      x[r] = acc;
+    for (int row = lo + threadIdx.x; row < hi; row += blockDim.x) {
+      // NRT == 1: the single column needs no guard (nr == 1)
+      double acc[NRT];
+#pragma unroll
+      for (int cr = 0; cr < NRT; cr++)
+        acc[cr] = (NRT == 1 || cr < nr) ? xs[(size_t)cr * S + row] : 0.0;
+#pragma unroll 4
+      for (int q = 0; q < TB; q++) {
+        const double mv = M(row, b0 + q);
+#pragma unroll
+        for (int cr = 0; cr < NRT; cr++)
+          if (NRT == 1 || cr < nr)
+            acc[cr] = __builtin_fma(-mv, xs[(size_t)cr * S + b0 + q], acc[cr]);
+      }
+#pragma unroll
+      for (int cr = 0; cr < NRT; cr++)
+        if (NRT == 1 || cr < nr) xs[(size_t)cr * S + row] = acc[cr];
     }
     __syncthreads();
   }
-  for (int t = threadIdx.x; t < s; t += blockDim.x) y[c0 + t] = x[t];
+  for (int cr = 0; cr < nr; cr++)
+    for (int t = threadIdx.x; t < s; t += blockDim.x)
+      y[(size_t)cr * ld + c0 + t] = xs[(size_t)cr * S + t];
 }
 
 // Several right-hand sides in one launch (nr <= NR, column-major with leading
@@ -1949,10 +1993,10 @@ void launch_dense_lu(double* T, int S, double* dsc, hipStream_t st) {
   }
 }
 
-void launch_trisolve_sn(int mode, const LUView& lu, const SnSched& sn, const int* tptr,
+void launch_trisolve_sn(int mode, int nr, const LUView& lu, const SnSched& sn, const int* tptr,
                         const int* trow, const int* tpos, const double* c, double* y,
                         SyncState* ss, int slot, int* stall, hipStream_t s) {
-  if (sn.nchunks <= 0) return;
+  if (sn.nchunks <= 0 || nr <= 0) return;
   static int ncu = 0;
   if (ncu == 0) {
     int d = 0;
@@ -1961,46 +2005,79 @@ void launch_trisolve_sn(int mode, const LUView& lu, const SnSched& sn, const int
     if (ncu <= 0) ncu = 256;
   }
   const int grid = std::max(1, std::min(ncu * sn.blocks_per_cu, cdiv(sn.nchunks, 4)));
-#define SN_LAUNCH(M)                                                                           \
-  hipLaunchKernelGGL(k_trisolve_sn<M>, dim3(grid), dim3(256), 0, s, lu.n, sn.nchunks, sn.start, \
-                     sn.meta, sn.base, sn.rows, sn.split, lu.rowptr, lu.col, lu.diag, tptr, trow, \
-                     tpos, lu.val, c, y, ss, slot, stall)
-  switch (mode) {
-    case 0: SN_LAUNCH(0); break;
-    case 1: SN_LAUNCH(1); break;
-    case 2: SN_LAUNCH(2); break;
-    default: SN_LAUNCH(3); break;
+  const int ld = lu.n + 1;
+#define SN_LAUNCH(M, R)                                                                         \
+  hipLaunchKernelGGL((k_trisolve_sn<M, R>), dim3(grid), dim3(256), 0, s, lu.n, nr, ld,          \
+                     sn.nchunks, sn.start, sn.meta, sn.base, sn.rows, sn.split, lu.rowptr,       \
+                     lu.col, lu.diag, tptr, trow, tpos, lu.val, c, y, ss, slot, stall)
+#define SN_MODES(R)                 \
+  switch (mode) {                   \
+    case 0: SN_LAUNCH(0, R); break; \
+    case 1: SN_LAUNCH(1, R); break; \
+    case 2: SN_LAUNCH(2, R); break; \
+    default: SN_LAUNCH(3, R); break; \
   }
+  if (nr == 1) {
+    SN_MODES(1)
+  } else if (nr <= 4) {
+    SN_MODES(4)
+  } else {
+    SN_MODES(SN_MAX_RHS)
+  }
+#undef SN_MODES
 #undef SN_LAUNCH
 }
 
-void launch_tail_solve(int mode, const LUView& lu, const double* T, int S, int s, int c0,
+void launch_tail_solve(int mode, int nr, const LUView& lu, const double* T, int S, int s, int c0,
                        const int* split, const int* tptr, const int* trow, const int* tpos,
                        const double* c, double* rhs_buf, double* y, hipStream_t st) {
-  if (s <= 0 || S > DENSE_TAIL_MAX) return;
-  const double* rhs = c + c0;
-  if (mode == 0 || mode == 2) {
-    if (mode == 0)
-      hipLaunchKernelGGL(k_tail_ext<0>, dim3(cdiv(S, 4)), dim3(256), 0, st, c0, s, S, split,
-                         lu.rowptr, lu.col, tptr, trow, tpos, lu.val, c, y, rhs_buf);
-    else
-      hipLaunchKernelGGL(k_tail_ext<2>, dim3(cdiv(S, 4)), dim3(256), 0, st, c0, s, S, split,
-                         lu.rowptr, lu.col, tptr, trow, tpos, lu.val, c, y, rhs_buf);
-    rhs = rhs_buf;
+  if (s <= 0 || S > DENSE_TAIL_MAX || nr <= 0) return;
+  const int ld = lu.n + 1;
+  for (int r0 = 0; r0 < nr; r0 += TAIL_NR) {
+    const int k = std::min(TAIL_NR, nr - r0);
+    const double* cr = c + (size_t)r0 * ld;
+    double* yr = y + (size_t)r0 * ld;
+    const double* rhs = cr + c0;
+    int rld = ld;
+    if (mode == 0 || mode == 2) {
+      if (mode == 0)
+        hipLaunchKernelGGL(k_tail_ext<0>, dim3(cdiv(S, 4), k), dim3(256), 0, st, c0, s, S, k, ld,
+                           split, lu.rowptr, lu.col, tptr, trow, tpos, lu.val, cr, yr, rhs_buf);
+      else
+        hipLaunchKernelGGL(k_tail_ext<2>, dim3(cdiv(S, 4), k), dim3(256), 0, st, c0, s, S, k, ld,
+                           split, lu.rowptr, lu.col, tptr, trow, tpos, lu.val, cr, yr, rhs_buf);
+      rhs = rhs_buf;
+      rld = S;
+    }
+    const size_t shm = (size_t)k * S * sizeof(double);
+    static bool attr_set = false;
+    const int mx = TAIL_NR * DENSE_TAIL_MAX * (int)sizeof(double);
+#define TT_ATTR(M, R)                                                                   \
+  (void)hipFuncSetAttribute((const void*)k_tail_trsv<M, R>,                             \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, mx)
+    if (!attr_set) {
+      TT_ATTR(0, 1); TT_ATTR(1, 1); TT_ATTR(2, 1); TT_ATTR(3, 1);
+      TT_ATTR(0, TAIL_NR); TT_ATTR(1, TAIL_NR); TT_ATTR(2, TAIL_NR); TT_ATTR(3, TAIL_NR);
+      attr_set = true;
+    }
+#undef TT_ATTR
+#define TT_LAUNCH(M, R)                                                                          \
+  hipLaunchKernelGGL((k_tail_trsv<M, R>), dim3(1), dim3(1024), shm, st, T, S, s, c0, k, rhs, rld, \
+                     yr, ld)
+#define TT_MODES(R)                 \
+  switch (mode) {                   \
+    case 0: TT_LAUNCH(0, R); break; \
+    case 1: TT_LAUNCH(1, R); break; \
+    case 2: TT_LAUNCH(2, R); break; \
+    default: TT_LAUNCH(3, R); break; \
   }
-  switch (mode) {
-    case 0:
-      hipLaunchKernelGGL(k_tail_trsv<0>, dim3(1), dim3(1024), 0, st, T, S, s, c0, rhs, y);
-      break;
-    case 1:
-      hipLaunchKernelGGL(k_tail_trsv<1>, dim3(1), dim3(1024), 0, st, T, S, s, c0, rhs, y);
-      break;
-    case 2:
-      hipLaunchKernelGGL(k_tail_trsv<2>, dim3(1), dim3(1024), 0, st, T, S, s, c0, rhs, y);
-      break;
-    default:
-      hipLaunchKernelGGL(k_tail_trsv<3>, dim3(1), dim3(1024), 0, st, T, S, s, c0, rhs, y);
-      break;
+    if (k == 1) {
+      TT_MODES(1)
+    } else {
+      TT_MODES(TAIL_NR)
+    }
+#undef TT_MODES
+#undef TT_LAUNCH
   }
 }
 

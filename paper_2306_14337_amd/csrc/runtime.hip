@@ -196,24 +196,24 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
     const int c0 = h->tail_c0, ts = h->tail_s, S = h->tail_S;
     if (op == 'N') {
       launch_gather_sentinel(n, h->pin, b, h->tc, h->ty, h->tz, h->ss, 0x6, s);
-      launch_trisolve_sn(0, lu, h->chs[0], nullptr, nullptr, nullptr, h->tc, h->ty, h->ss, 1,
+      launch_trisolve_sn(0, 1, lu, h->chs[0], nullptr, nullptr, nullptr, h->tc, h->ty, h->ss, 1,
                          stall, s);
-      launch_tail_solve(0, lu, h->tail_T, S, ts, c0, h->tail_split0, nullptr, nullptr, nullptr,
+      launch_tail_solve(0, 1, lu, h->tail_T, S, ts, c0, h->tail_split0, nullptr, nullptr, nullptr,
                         h->tc, h->tail_rhs, h->ty, s);
-      launch_tail_solve(1, lu, h->tail_T, S, ts, c0, nullptr, nullptr, nullptr, nullptr, h->ty,
+      launch_tail_solve(1, 1, lu, h->tail_T, S, ts, c0, nullptr, nullptr, nullptr, nullptr, h->ty,
                         h->tail_rhs, h->tz, s);
-      launch_trisolve_sn(1, lu, h->chs[1], nullptr, nullptr, nullptr, h->ty, h->tz, h->ss, 2,
+      launch_trisolve_sn(1, 1, lu, h->chs[1], nullptr, nullptr, nullptr, h->ty, h->tz, h->ss, 2,
                          stall, s);
       launch_scatter(n, h->qperm, h->tz, x, s);
     } else {
       launch_gather_sentinel(n, h->qperm, b, h->tc, h->ty, h->tz, h->ss, 0x6, s);
-      launch_trisolve_sn(2, lu, h->chs[2], h->ut_ptr, h->ut_row, h->ut_pos, h->tc, h->ty, h->ss,
+      launch_trisolve_sn(2, 1, lu, h->chs[2], h->ut_ptr, h->ut_row, h->ut_pos, h->tc, h->ty, h->ss,
                          1, stall, s);
-      launch_tail_solve(2, lu, h->tail_T, S, ts, c0, h->tail_split2, h->ut_ptr, h->ut_row,
+      launch_tail_solve(2, 1, lu, h->tail_T, S, ts, c0, h->tail_split2, h->ut_ptr, h->ut_row,
                         h->ut_pos, h->tc, h->tail_rhs, h->ty, s);
-      launch_tail_solve(3, lu, h->tail_T, S, ts, c0, nullptr, nullptr, nullptr, nullptr, h->ty,
+      launch_tail_solve(3, 1, lu, h->tail_T, S, ts, c0, nullptr, nullptr, nullptr, nullptr, h->ty,
                         h->tail_rhs, h->tz, s);
-      launch_trisolve_sn(3, lu, h->chs[3], h->lt_ptr, h->lt_row, h->lt_pos, h->ty, h->tz, h->ss,
+      launch_trisolve_sn(3, 1, lu, h->chs[3], h->lt_ptr, h->lt_row, h->lt_pos, h->ty, h->tz, h->ss,
                          2, stall, s);
       launch_scatter(n, h->pin, h->tz, x, s);
     }
@@ -299,6 +299,41 @@ void apply_factors_multi(kkt_handle h, char op, int nr, const double* b, double*
   const int n = h->an.n;
   LUView lu = view(h);
   int* stall = &h->st->stall;
+  if (h->use_sn) {
+    // chain-blocked sparse rows and the dense block, SN_MAX_RHS columns a pass
+    const int c0 = h->tail_c0, ts = h->tail_s, S = h->tail_S;
+    const size_t ld = (size_t)n + 1;
+    for (int r0 = 0; r0 < nr; r0 += SN_MAX_RHS) {
+      const int k = std::min(SN_MAX_RHS, nr - r0);
+      const double* bb = b + (size_t)r0 * n;
+      double* xx = x + (size_t)r0 * n;
+      double *mc = h->mc + r0 * ld, *my = h->my + r0 * ld, *mz = h->mz + r0 * ld;
+      if (op == 'N') {
+        launch_gather_sentinel_mr(n, k, h->pin, bb, mc, my, mz, h->ss, 0x6, s);
+        launch_trisolve_sn(0, k, lu, h->chs[0], nullptr, nullptr, nullptr, mc, my, h->ss, 1,
+                           stall, s);
+        launch_tail_solve(0, k, lu, h->tail_T, S, ts, c0, h->tail_split0, nullptr, nullptr,
+                          nullptr, mc, h->tail_rhs, my, s);
+        launch_tail_solve(1, k, lu, h->tail_T, S, ts, c0, nullptr, nullptr, nullptr, nullptr, my,
+                          h->tail_rhs, mz, s);
+        launch_trisolve_sn(1, k, lu, h->chs[1], nullptr, nullptr, nullptr, my, mz, h->ss, 2,
+                           stall, s);
+        launch_scatter_mr(n, k, h->qperm, mz, xx, s);
+      } else {
+        launch_gather_sentinel_mr(n, k, h->qperm, bb, mc, my, mz, h->ss, 0x6, s);
+        launch_trisolve_sn(2, k, lu, h->chs[2], h->ut_ptr, h->ut_row, h->ut_pos, mc, my, h->ss, 1,
+                           stall, s);
+        launch_tail_solve(2, k, lu, h->tail_T, S, ts, c0, h->tail_split2, h->ut_ptr, h->ut_row,
+                          h->ut_pos, mc, h->tail_rhs, my, s);
+        launch_tail_solve(3, k, lu, h->tail_T, S, ts, c0, nullptr, nullptr, nullptr, nullptr, my,
+                          h->tail_rhs, mz, s);
+        launch_trisolve_sn(3, k, lu, h->chs[3], h->lt_ptr, h->lt_row, h->lt_pos, my, mz, h->ss, 2,
+                           stall, s);
+        launch_scatter_mr(n, k, h->pin, mz, xx, s);
+      }
+    }
+    return;
+  }
   if (op == 'N') {
     launch_gather_sentinel_mr(n, nr, h->pin, b, h->mc, h->my, h->mz, h->ss, 0x6, s);
     launch_trisolve_vflag_mr(0, nr, lu, h->ch_l, nullptr, nullptr, nullptr, h->mc, h->my, h->ss,
@@ -1117,7 +1152,7 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   if (h->tail_s > 0 &&
       ((ks = dalloc(h, &h->tail_T, (size_t)h->tail_S * h->tail_S)) != KKT_OK ||
        (ks = dalloc(h, &h->tail_dsc, (size_t)DLU_NB * DLU_NB)) != KKT_OK ||
-       (ks = dalloc(h, &h->tail_rhs, (size_t)h->tail_S)) != KKT_OK)) {
+       (ks = dalloc(h, &h->tail_rhs, (size_t)h->tail_S * 8)) != KKT_OK)) {
     free_device(h);
     return ks;
   }

@@ -172,6 +172,27 @@ def test_direct_solve_matches_oracle_apply(B, seed, layout):
             assert eta(M, x, b) <= max(100 * eta(M, xo, b), 1e-14), (stage, op)
 
 
+@pytest.mark.parametrize("layout", [dict(), dict(dense_tail=300), dict(dense_tail=-1),
+                                    dict(solve_chain=-1)],
+                         ids=lambda d: "-".join(f"{k}{v}" for k, v in d.items()) or "default")
+def test_direct_multi_rhs_matches_oracle_apply(layout):
+    # eleven columns: one pass of eight and one of three (both kernel widths),
+    # no refinement, each column against the oracle's direct solve
+    pat, seq = kktgen.make_sequence(2000, 104, 1)
+    vals, _ = seq[0]
+    s = binding.KKTSolver(schedule=2, sync_mode=2, fgmres_max_iters=0, **layout)
+    s.analyze(pat.n, pat.rowptr, pat.colind, vals)
+    s.refactor(dev(vals))
+    ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, vals, tau=1e-10)
+    B = np.random.default_rng(11).standard_normal((11, pat.n))
+    for op in ("N", "T"):
+        X = s.solve(dev(B.reshape(-1)), op=op).cpu().numpy().reshape(11, pat.n)
+        for r in range(11):
+            xo = ora.apply(B[r], op)
+            err = np.abs(X[r] - xo).max() / np.abs(xo).max()
+            assert err <= 1e-8, (layout, op, r, err)
+
+
 @pytest.mark.parametrize("schedule", SCHEDULES)
 def test_transposed_solve_and_multiple_rhs(schedule):
     pat, seq = kktgen.make_sequence(500, 9, 1)
