@@ -175,9 +175,13 @@ constexpr int MAX_RHS_PASS = 32;
 void launch_trisolve_vflag_mr(int mode, int nr, const LUView& lu, const ChunkSched& cs,
                               const int* tptr, const int* trow, const int* tpos, const double* c,
                               double* y, SyncState* ss, int slot, int* stall, hipStream_t s);
-// c[r][i] = x[r][perm[i]] (x: ld n; c, y, z: ld n + 1), y, z := sentinel
+// c[r][i] = x[r][perm[i]] (x: ld n; c, y, z: ld n + 1), y, z := sentinel,
+// except y on rows with triv[i] != 0 (no dependencies in the first triangle):
+// y = c, or c / val[diag[i]] if div
 void launch_gather_sentinel_mr(int n, int nr, const int* perm, const double* x, double* c,
-                               double* y, double* z, SyncState* ss, int mask, hipStream_t s);
+                               double* y, double* z, SyncState* ss, int mask, hipStream_t s,
+                               const unsigned char* triv = nullptr, const int* diag = nullptr,
+                               const double* val = nullptr, int div = 0);
 // x[r][perm[i]] = z[r][i]
 void launch_scatter_mr(int n, int nr, const int* perm, const double* z, double* x, hipStream_t s);
 // per-column max |B - op(A) X| and max |X| into colmax[2r], colmax[2r+1]
@@ -185,9 +189,15 @@ void launch_scatter_mr(int n, int nr, const int* perm, const double* z, double* 
 void launch_residual_mr(int n, int nr, const int* ptr, const int* idx, const int* pos,
                         const double* aval, const double* B, const double* X,
                         unsigned long long* colmax, hipStream_t s);
-// c[i] = x[perm[i]]; y, z := sentinel; plus the sync_prep of mask
+// c[i] = x[perm[i]]; y, z := sentinel (y on trivial rows as in the _mr form);
+// plus the sync_prep of mask
 void launch_gather_sentinel(int n, const int* perm, const double* x, double* c, double* y,
-                            double* z, SyncState* ss, int mask, hipStream_t s);
+                            double* z, SyncState* ss, int mask, hipStream_t s,
+                            const unsigned char* triv = nullptr, const int* diag = nullptr,
+                            const double* val = nullptr, int div = 0);
+// factor rows without pivots: val = staged A row, ready = current epoch
+void launch_refactor_trivial(const LUView& lu, const int* rows, int nrows, const double* aval,
+                             int* ready, const SyncState* ss, hipStream_t s);
 // zero the tickets and advance the epochs of the slots in mask (bit k = slot k)
 void launch_sync_prep(SyncState* ss, int mask, hipStream_t s);
 // y[i] = x[perm[i]] and, if ss != nullptr, the sync_prep of mask (fused)

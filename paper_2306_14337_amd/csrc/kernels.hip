@@ -15,6 +15,7 @@ namespace kktlu {
 namespace {
 
 constexpr int WAVE = 64;
+constexpr int RG_TRIV = 8;  // lanes per row of k_refactor_trivial
 
 __device__ __forceinline__ void wave_sync() {
   // LDS operations of one wavefront complete in issue order; this keeps the
@@ -207,6 +208,32 @@ __device__ __forceinline__ void stores_done() {
 // flag value.  A lane-0-only region at the loop boundary lets the compiler
 // split the loop so that lanes 1..63 iterate without lane 0 on a stale
 // ticket, which never terminates.
+// Rows of the refactorization without pivots (no L entries before the dense
+// block): their factor row is the staged A row.  8 lanes per row; the ready
+// flag carries the epoch of the current refactorization (a later launch reads
+// both, so plain stores suffice).
+__global__ __launch_bounds__(256) void k_refactor_trivial(int nrows, const int* __restrict__ rows,
+                                                          const int* __restrict__ rowptr,
+                                                          const int* __restrict__ src,
+                                                          const double* __restrict__ aval,
+                                                          double* __restrict__ val, int* ready,
+                                                          const SyncState* ss) {
+  const int lane = threadIdx.x % WAVE, g = lane / RG_TRIV, gl = lane % RG_TRIV;
+  const int epoch = ss->epoch[0];
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int nw = gridDim.x * blockDim.x / WAVE;
+  for (int r0 = wid * (WAVE / RG_TRIV); r0 < nrows; r0 += nw * (WAVE / RG_TRIV)) {
+    const int r = r0 + g;
+    if (r >= nrows) continue;
+    const int i = rows[r];
+    for (int q = rowptr[i] + gl; q < rowptr[i + 1]; q += RG_TRIV) {
+      const int sq = src[q];
+      val[q] = sq >= 0 ? aval[sq] : 0.0;
+    }
+    if (gl == 0) ready[i] = epoch;
+  }
+}
+
 // Update maps of the refactorization, built once per analysis: for the L
 // entry q = (i, k), map[moff[q] + u] = position (from the row start) of the
 // column of U(k, >k)'s u-th entry in row i.  Wave per row, lanes over U(k).
@@ -1209,18 +1236,26 @@ __global__ __launch_bounds__(256) void k_trisolve_vflag_mr(
 __global__ void k_gather_sentinel_mr(int n, int nr, const int* __restrict__ perm,
                                      const double* __restrict__ x, double* __restrict__ c,
                                      double* __restrict__ y, double* __restrict__ z,
-                                     SyncState* ss, int mask);
+                                     SyncState* ss, int mask,
+                                     const unsigned char* __restrict__ triv,
+                                     const int* __restrict__ diag,
+                                     const double* __restrict__ val, int div);
 
 // c[i] = x[perm[i]], and the two solve outputs y, z set to the sentinel
+// Rows without dependencies in the first triangle (triv[i] != 0) get their
+// final value here: y = c, or y = c / u_ii when div is set (a U^T first).
 __global__ void k_gather_sentinel(int n, const int* __restrict__ perm,
                                   const double* __restrict__ x, double* __restrict__ c,
                                   double* __restrict__ y, double* __restrict__ z, SyncState* ss,
-                                  int mask) {
+                                  int mask, const unsigned char* __restrict__ triv,
+                                  const int* __restrict__ diag, const double* __restrict__ val,
+                                  int div) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
-    c[i] = x[perm[i]];
+    const double ci = x[perm[i]];
+    c[i] = ci;
     const double sent = __longlong_as_double((long long)SENTINEL);
-    y[i] = sent;
+    y[i] = (triv && triv[i]) ? (div ? ci / val[diag[i]] : ci) : sent;
     z[i] = sent;
   }
   if (ss && i == 0) sync_prep(ss, mask);
@@ -1229,14 +1264,18 @@ __global__ void k_gather_sentinel(int n, const int* __restrict__ perm,
 __global__ void k_gather_sentinel_mr(int n, int nr, const int* __restrict__ perm,
                                      const double* __restrict__ x, double* __restrict__ c,
                                      double* __restrict__ y, double* __restrict__ z,
-                                     SyncState* ss, int mask) {
+                                     SyncState* ss, int mask,
+                                     const unsigned char* __restrict__ triv,
+                                     const int* __restrict__ diag,
+                                     const double* __restrict__ val, int div) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (i < n && r < nr) {
     const size_t o = (size_t)r * (n + 1) + i;
-    c[o] = x[(size_t)r * n + perm[i]];
+    const double ci = x[(size_t)r * n + perm[i]];
+    c[o] = ci;
     const double sent = __longlong_as_double((long long)SENTINEL);
-    y[o] = sent;
+    y[o] = (triv && triv[i]) ? (div ? ci / val[diag[i]] : ci) : sent;
     z[o] = sent;
   }
   if (ss && i == 0 && r == 0) sync_prep(ss, mask);
@@ -1812,6 +1851,13 @@ void launch_seg_stats(int count, const int* row_off, const double* matabs, const
   hipLaunchKernelGGL(k_seg_stats, dim3(count), dim3(256), 0, s, row_off, matabs, r, x, out);
 }
 
+void launch_refactor_trivial(const LUView& lu, const int* rows, int nrows, const double* aval,
+                             int* ready, const SyncState* ss, hipStream_t s) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_refactor_trivial, dim3(std::max(1, std::min(cdiv(nrows, 32), 2048))),
+                     dim3(256), 0, s, nrows, rows, lu.rowptr, lu.src, aval, lu.val, ready, ss);
+}
+
 void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map, hipStream_t s) {
   hipLaunchKernelGGL(k_build_refmap, dim3(std::max(1, std::min(cdiv(lu.n, 4), 4096))), dim3(256),
                      0, s, lu.n, lu.rowptr, lu.col, lu.diag, moff, map);
@@ -2097,9 +2143,11 @@ void launch_trisolve_seg(int mode, const SegSched& sg, const double* val, const 
 }
 
 void launch_gather_sentinel_mr(int n, int nr, const int* perm, const double* x, double* c,
-                               double* y, double* z, SyncState* ss, int mask, hipStream_t s) {
+                               double* y, double* z, SyncState* ss, int mask, hipStream_t s,
+                               const unsigned char* triv, const int* diag, const double* val,
+                               int div) {
   hipLaunchKernelGGL(k_gather_sentinel_mr, dim3(cdiv(n, 256), nr), dim3(256), 0, s, n, nr, perm,
-                     x, c, y, z, ss, mask);
+                     x, c, y, z, ss, mask, triv, diag, val, div);
 }
 
 void launch_scatter_mr(int n, int nr, const int* perm, const double* z, double* x, hipStream_t s) {
@@ -2115,9 +2163,11 @@ void launch_residual_mr(int n, int nr, const int* ptr, const int* idx, const int
 }
 
 void launch_gather_sentinel(int n, const int* perm, const double* x, double* c, double* y,
-                            double* z, SyncState* ss, int mask, hipStream_t s) {
+                            double* z, SyncState* ss, int mask, hipStream_t s,
+                            const unsigned char* triv, const int* diag, const double* val,
+                            int div) {
   hipLaunchKernelGGL(k_gather_sentinel, dim3(cdiv(n, 256)), dim3(256), 0, s, n, perm, x, c, y, z,
-                     ss, mask);
+                     ss, mask, triv, diag, val, div);
 }
 
 void launch_sync_prep(SyncState* ss, int mask, hipStream_t s) {

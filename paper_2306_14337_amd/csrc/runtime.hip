@@ -73,12 +73,16 @@ struct kkt_ctx {
   int *tail_split0 = nullptr, *tail_split2 = nullptr;
   // chain-blocked single right-hand-side solves (modes 0 L, 1 U, 2 U^T, 3 L^T)
   bool use_sn = false;
+  // rows without dependencies in the forward solves (L; U^T), final in the gather
+  uint8_t *sn_triv0 = nullptr, *sn_triv2 = nullptr;
   SnSched chs[4]{};
   int chs_levels[4] = {};
   // refactorization bands: chunks ref_cstart[band_chunk_lo[b] ..
   // + band_nchunks[b]] of ref_order (each band's chunk list ends with its end
   // offset), longest row band_cap[b]
   int *ref_order = nullptr, *ref_cstart = nullptr;
+  int* ref_triv = nullptr;  // rows without pivots (k_refactor_trivial)
+  int ref_ntriv = 0;
   // precomputed update positions of the refactorization (null: binary search)
   int* ref_moff = nullptr;
   unsigned short* ref_map = nullptr;
@@ -195,7 +199,8 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
     int* stall = &h->st->stall;
     const int c0 = h->tail_c0, ts = h->tail_s, S = h->tail_S;
     if (op == 'N') {
-      launch_gather_sentinel(n, h->pin, b, h->tc, h->ty, h->tz, h->ss, 0x6, s);
+      launch_gather_sentinel(n, h->pin, b, h->tc, h->ty, h->tz, h->ss, 0x6, s, h->sn_triv0,
+                             h->diag, h->lu_val, 0);
       launch_trisolve_sn(0, 1, lu, h->chs[0], nullptr, nullptr, nullptr, h->tc, h->ty, h->ss, 1,
                          stall, s);
       launch_tail_solve(0, 1, lu, h->tail_T, S, ts, c0, h->tail_split0, nullptr, nullptr, nullptr,
@@ -206,7 +211,8 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
                          stall, s);
       launch_scatter(n, h->qperm, h->tz, x, s);
     } else {
-      launch_gather_sentinel(n, h->qperm, b, h->tc, h->ty, h->tz, h->ss, 0x6, s);
+      launch_gather_sentinel(n, h->qperm, b, h->tc, h->ty, h->tz, h->ss, 0x6, s, h->sn_triv2,
+                             h->diag, h->lu_val, 1);
       launch_trisolve_sn(2, 1, lu, h->chs[2], h->ut_ptr, h->ut_row, h->ut_pos, h->tc, h->ty, h->ss,
                          1, stall, s);
       launch_tail_solve(2, 1, lu, h->tail_T, S, ts, c0, h->tail_split2, h->ut_ptr, h->ut_row,
@@ -309,7 +315,8 @@ void apply_factors_multi(kkt_handle h, char op, int nr, const double* b, double*
       double* xx = x + (size_t)r0 * n;
       double *mc = h->mc + r0 * ld, *my = h->my + r0 * ld, *mz = h->mz + r0 * ld;
       if (op == 'N') {
-        launch_gather_sentinel_mr(n, k, h->pin, bb, mc, my, mz, h->ss, 0x6, s);
+        launch_gather_sentinel_mr(n, k, h->pin, bb, mc, my, mz, h->ss, 0x6, s, h->sn_triv0,
+                                  h->diag, h->lu_val, 0);
         launch_trisolve_sn(0, k, lu, h->chs[0], nullptr, nullptr, nullptr, mc, my, h->ss, 1,
                            stall, s);
         launch_tail_solve(0, k, lu, h->tail_T, S, ts, c0, h->tail_split0, nullptr, nullptr,
@@ -320,7 +327,8 @@ void apply_factors_multi(kkt_handle h, char op, int nr, const double* b, double*
                            stall, s);
         launch_scatter_mr(n, k, h->qperm, mz, xx, s);
       } else {
-        launch_gather_sentinel_mr(n, k, h->qperm, bb, mc, my, mz, h->ss, 0x6, s);
+        launch_gather_sentinel_mr(n, k, h->qperm, bb, mc, my, mz, h->ss, 0x6, s, h->sn_triv2,
+                                  h->diag, h->lu_val, 1);
         launch_trisolve_sn(2, k, lu, h->chs[2], h->ut_ptr, h->ut_row, h->ut_pos, mc, my, h->ss, 1,
                            stall, s);
         launch_tail_solve(2, k, lu, h->tail_T, S, ts, c0, h->tail_split2, h->ut_ptr, h->ut_row,
@@ -882,6 +890,18 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
       for (int32_t q = A.lu_rowptr[i]; q < A.diag[i]; q++) b = std::max(b, (int)band[A.lu_col[q]]);
       band[i] = (int8_t)b;
     }
+    // rows without pivots in the sparse phase: copied by one parallel pass
+    std::vector<uint8_t> triv(n, 0);
+    std::vector<int32_t> trows;
+    for (int32_t i = 0; i < n; i++) {
+      const bool t = A.diag[i] == A.lu_rowptr[i] || A.lu_col[A.lu_rowptr[i]] >= c0;
+      if (t) {
+        triv[i] = 1;
+        trows.push_back(i);
+      }
+    }
+    h->ref_ntriv = (int)trows.size();
+    if (!trows.empty()) UP(h->ref_triv, trows);
     // rows by (level, decreasing height): two stable counting sorts
     std::vector<int32_t> by_h(n), by_lh(n);
     {
@@ -905,7 +925,7 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
       const int clo = (int)cst.size();
       int mx = 0;
       for (int32_t i : by_lh)
-        if (band[i] == b) {
+        if (band[i] == b && !triv[i]) {
           order.push_back(i);
           mx = std::max(mx, A.lu_rowptr[i + 1] - A.lu_rowptr[i]);
         }
@@ -984,6 +1004,8 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
       // items: runs of consecutive rows (solve order) each depending on the
       // previous one, up to kmax rows and 64 lanes at <= 32 entries per lane
       std::vector<int32_t> item_of(c0, -1), item_first, item_len, item_lev;
+      std::vector<uint8_t> triv(n, 0);
+      int32_t last_row = -1;  // last row added to the current item
       auto lanes_for = [](int len) {
         int g = 1;
         while (g < 64 && g * 32 < len) g <<= 1;
@@ -999,10 +1021,16 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
         const int32_t i = fwd ? t : c0 - 1 - t;
         const int32_t b = lb(i), e = le(i);
         const int len = e - b;
+        if (fwd && len == 0) {
+          // no dependencies: final in the gather pass, not scheduled
+          triv[i] = 1;
+          continue;
+        }
         bool ext = false;
-        if (!item_first.empty() && t > 0) {
+        if (!item_first.empty() && last_row >= 0) {
           const int32_t p = fwd ? i - 1 : i + 1;
-          const bool chained = len > 0 && (fwd ? dep(e - 1) == p : dep(b) == p);
+          const bool chained =
+              p == last_row && len > 0 && (fwd ? dep(e - 1) == p : dep(b) == p);
           const int k = item_len.back();
           const int mx = std::max(cur_max, len);
           ext = chained && k < kmax && p2(k + 1) * lanes_for(mx) <= 64;
@@ -1016,6 +1044,12 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
           cur_max = len;
         }
         item_of[i] = (int32_t)item_first.size() - 1;
+        last_row = i;
+      }
+      if (fwd) {
+        uint8_t* d = nullptr;
+        UP(d, triv);
+        (mode == 0 ? h->sn_triv0 : h->sn_triv2) = d;
       }
       const int nitems = (int)item_first.size();
       item_lev.assign(nitems, 0);
@@ -1026,7 +1060,7 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
           const int32_t i = fwd ? item_first[it] + r : item_first[it] - r;
           for (int32_t q = lb(i); q < le(i); q++) {
             const int32_t j = dep(q);
-            if (j >= c0 || item_of[j] == it) continue;
+            if (j >= c0 || item_of[j] < 0 || item_of[j] == it) continue;
             lv = std::max(lv, item_lev[item_of[j]] + 1);
           }
         }
@@ -1267,6 +1301,7 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
   launch_reset_stats(h->st, 1, s);
   if (h->syncfree) {
     launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, h->ss, h->rowabs);
+    launch_refactor_trivial(lu, h->ref_triv, h->ref_ntriv, h->aval, h->ready_ref, h->ss, s);
     for (int b = 0; b < h->nbands; b++)
       if (!launch_refactor_syncfree(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
                                     h->band_nchunks[b], b, h->band_cap[b], h->aval, h->ready_ref,
