@@ -229,6 +229,11 @@ def main():
                     help="dense trailing block size (0 auto, -1 none)")
     ap.add_argument("--solve-chain", type=int, default=0,
                     help="longest chain block of the solves (0 default = 32, -1 level chunks)")
+    ap.add_argument("--crit-height", type=int, default=0,
+                    help="refactorization rows with this many chained rows after them go first "
+                         "(0 default = 32, -1 level order)")
+    ap.add_argument("--ref-wpcu", type=int, default=0,
+                    help="cap on resident refactorization waves per CU (0 occupancy limit)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 2 GiB read + 2 GiB write elementwise kernel before timing, its "
                          "source evicted from the 256 MiB last-level cache by a 1 GiB fill (the "
@@ -253,7 +258,9 @@ def main():
 
     s = binding.KKTSolver(device=0, schedule=args.schedule, sync_mode=args.sync_mode,
                           solve_thin_rows=args.thin, solve_blocks_per_cu=args.solve_bpc,
-                          dense_tail=args.dense_tail, solve_chain=args.solve_chain)
+                          dense_tail=args.dense_tail, solve_chain=args.solve_chain,
+                          refactor_crit_height=args.crit_height,
+                          refactor_waves_per_cu=args.ref_wpcu)
     t0 = time.perf_counter()
     s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
     t_an = time.perf_counter() - t0

@@ -100,7 +100,12 @@ typedef struct {
   int32_t refactor_map; /* dependency-driven refactorization: 0 = precomputed update positions
                            (one 16-bit entry per multiply-add of the factorization, built once
                            at analysis), -1 = binary search of each update's column instead */
-  int32_t reserved[4];
+  int32_t refactor_crit_height; /* dependency-driven refactorization: rows with at least this many
+                                   rows chained after them are handed out first in their band
+                                   (0 = 32, -1 = plain level order) */
+  int32_t refactor_waves_per_cu; /* dependency-driven refactorization: cap on the resident waves
+                                    per CU of its persistent grid (0 = occupancy limit) */
+  int32_t reserved[2];
 } kkt_options;
 
 typedef struct {

@@ -105,7 +105,9 @@ void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxl
 // Returns false if the configuration cannot be launched.
 // Every wait is bounded: past the spin limit a wave sets *stall, and waves
 // that see *stall stop waiting, so the grid always drains.
-// light: device-coherent data accesses instead of acquire/release fences.
+// light: device-coherent data accesses, every factor value its own ready flag
+// (lu.val must hold the sentinel on entry: launch_fill_sentinel), instead of
+// ready flags with acquire/release fences.
 // wpb_pref: waves (rows in flight) per workgroup, 0 = chosen from the LDS need.
 // c0: first row/column of the dense trailing block (n = none): rows i >= c0
 // apply only the pivots k < c0 (the block is finished by launch_dense_lu).
@@ -116,11 +118,16 @@ void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxl
 // the wide levels), cap >= their longest row, the band's ticket counter
 // ss->band_ticket[b].
 // moff/map (both or neither): precomputed update positions (launch_build_refmap)
-// replacing the per-entry binary search.
+// replacing the per-entry binary search.  max_waves_per_cu > 0 caps the
+// persistent grid below the occupancy limit.
+// luA (nullable): A's values already scattered into factor order (fill
+// positions zero), replacing the gather through lu.src; pbnd (nullable): per
+// L entry (i, k) the pair (diag[k], rowptr[k + 1]).
 bool launch_refactor_syncfree(const LUView& lu, const int* order, const int* cstart,
                               int nchunks, int band, int cap, const double* aval, int* ready,
                               SyncState* ss, int* stall, bool light, int wpb_pref, int c0,
-                              const int* moff, const unsigned short* map, hipStream_t s);
+                              const int* moff, const unsigned short* map, const double* luA,
+                              const int2* pbnd, int max_waves_per_cu, hipStream_t s);
 // map[moff[q] + u] = position in row i of U(k, >k)'s u-th column, for every L
 // entry q = (i, k) (moff: offsets indexed by factor position, host-computed)
 void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map, hipStream_t s);
@@ -195,9 +202,13 @@ void launch_gather_sentinel(int n, const int* perm, const double* x, double* c, 
                             double* z, SyncState* ss, int mask, hipStream_t s,
                             const unsigned char* triv = nullptr, const int* diag = nullptr,
                             const double* val = nullptr, int div = 0);
+// p[0 .. count) := the value-as-flag sentinel (before a device-coherent
+// refactorization: its rows' values are their own ready flags)
+void launch_fill_sentinel(double* p, long long count, hipStream_t s);
 // factor rows without pivots: val = staged A row, ready = current epoch
 void launch_refactor_trivial(const LUView& lu, const int* rows, int nrows, const double* aval,
-                             int* ready, const SyncState* ss, hipStream_t s);
+                             int* ready, const SyncState* ss, hipStream_t s,
+                             const double* luA = nullptr);
 // zero the tickets and advance the epochs of the slots in mask (bit k = slot k)
 void launch_sync_prep(SyncState* ss, int mask, hipStream_t s);
 // y[i] = x[perm[i]] and, if ss != nullptr, the sync_prep of mask (fused)
@@ -208,10 +219,12 @@ void launch_gather_prep(int n, const int* perm, const double* x, double* y, Sync
 void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStream_t s);
 
 // A copy + ||A||_inf (and, if ss != nullptr, the sync_prep of slot 0; if
-// rowabs != nullptr, every row's absolute sum)
+// rowabs != nullptr, every row's absolute sum; if luA != nullptr, the values
+// also scattered into factor order: luA[a2lu[p]] = A[p])
 void launch_copy_anorm(int n, const int* arow, const int* acol, const double* src, double* dst,
                        DevStats* st, hipStream_t s, SyncState* ss = nullptr,
-                       double* rowabs = nullptr);
+                       double* rowabs = nullptr, const int* a2lu = nullptr,
+                       double* luA = nullptr);
 // ||A||_1 through the column view (and every column's absolute sum)
 void launch_anorm1(int n, const int* cptr, const int* cpos, const double* aval, DevStats* st,
                    hipStream_t s, double* colabs = nullptr);

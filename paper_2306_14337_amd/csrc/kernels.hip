@@ -152,6 +152,22 @@ __device__ __forceinline__ void st_flag(int* p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Value-as-flag protocols: a value not yet produced holds a signaling-NaN bit
+// pattern that no arithmetic result carries (results are quiet NaNs at
+// worst); consumers poll the value itself with device-coherent loads.
+constexpr unsigned long long SENTINEL = 0x7FF0DEAD5EED0001ull;
+
+__device__ __forceinline__ bool is_sentinel(double v) {
+  return (unsigned long long)__double_as_longlong(v) == SENTINEL;
+}
+
+__global__ void k_fill_sentinel(double* __restrict__ p, long long count) {
+  const double sent = __longlong_as_double((long long)SENTINEL);
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < count;
+       e += (long long)gridDim.x * blockDim.x)
+    p[e] = sent;
+}
+
 // 2^20 polling rounds (each a device-scope load plus a short sleep, about a
 // microsecond): far longer than any legitimate wait of one factorization or
 // solve, short enough that a broken schedule drains in about a second
@@ -217,7 +233,8 @@ __global__ __launch_bounds__(256) void k_refactor_trivial(int nrows, const int* 
                                                           const int* __restrict__ src,
                                                           const double* __restrict__ aval,
                                                           double* __restrict__ val, int* ready,
-                                                          const SyncState* ss) {
+                                                          const SyncState* ss,
+                                                          const double* __restrict__ luA) {
   const int lane = threadIdx.x % WAVE, g = lane / RG_TRIV, gl = lane % RG_TRIV;
   const int epoch = ss->epoch[0];
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
@@ -227,8 +244,12 @@ __global__ __launch_bounds__(256) void k_refactor_trivial(int nrows, const int* 
     if (r >= nrows) continue;
     const int i = rows[r];
     for (int q = rowptr[i] + gl; q < rowptr[i + 1]; q += RG_TRIV) {
-      const int sq = src[q];
-      val[q] = sq >= 0 ? aval[sq] : 0.0;
+      if (luA) {
+        val[q] = luA[q];
+      } else {
+        const int sq = src[q];
+        val[q] = sq >= 0 ? aval[sq] : 0.0;
+      }
     }
     if (gl == 0) ready[i] = epoch;
   }
@@ -266,7 +287,8 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
     unsigned int* ticket, const int* __restrict__ rowptr,
     const int* __restrict__ col, const int* __restrict__ diag, const int* __restrict__ src,
     const double* __restrict__ aval, double* val, int* ready, SyncState* ss, int* stall, int cap,
-    int c0, const int* __restrict__ moff, const unsigned short* __restrict__ map) {
+    int c0, const int* __restrict__ moff, const unsigned short* __restrict__ map,
+    const double* __restrict__ luA, const int2* __restrict__ pbnd) {
   extern __shared__ double smem_d[];
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   // LDS per wave: values (cap doubles), pivot-row bounds (cap int2), columns (cap ints)
@@ -283,16 +305,26 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
     wave_sync();  // the previous row of this chunk is done with the staging area
     const int rs = rowptr[i], len = rowptr[i + 1] - rs;
     int dl = diag[i] - rs;
+    // the row's columns and A values (luA: already in factor order, else
+    // gathered through src), and the bounds (diagonal position, row end) of
+    // every pivot row it needs (pbnd: precomputed per L entry), all loaded
+    // in parallel up front
     for (int t = lane; t < len; t += WAVE) {
       sc[t] = col[rs + t];
-      const int s = src[rs + t];
-      sv[t] = s >= 0 ? aval[s] : 0.0;
+      if (luA) {
+        sv[t] = luA[rs + t];
+      } else {
+        const int s = src[rs + t];
+        sv[t] = s >= 0 ? aval[s] : 0.0;
+      }
     }
-    // bounds (diagonal position, row end) of every pivot row this row needs,
-    // loaded in parallel up front
     for (int t = lane; t < dl; t += WAVE) {
-      const int k = sc[t];
-      sk[t] = make_int2(diag[k], rowptr[k + 1]);
+      if (pbnd) {
+        sk[t] = pbnd[rs + t];
+      } else {
+        const int k = col[rs + t];
+        sk[t] = make_int2(diag[k], rowptr[k + 1]);
+      }
     }
     wave_sync();
     // rows of the dense trailing block take only the pivots before it here
@@ -306,20 +338,29 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
     for (int t = 0; t < dl; t++) {
       if (t >= ready_upto) {
         for (;;) {
+          // LIGHT: a pivot row is final once its diagonal value is (the
+          // values themselves are the flags; every entry is checked on use)
           const int q = t + lane;
-          const bool ok = q >= dl || ld_flag(ready + sc[q]) == epoch;
+          const bool ok = q >= dl || (LIGHT ? !is_sentinel(ld_coh(val + sk[q].x))
+                                            : ld_flag(ready + sc[q]) == epoch);
           const unsigned long long bad = __ballot(!ok);
           const int first_bad = bad ? __ffsll((long long)bad) - 1 : WAVE;
           if (first_bad > 0) {
             ready_upto = t + first_bad;
             break;
           }
-          // entry t itself is missing: poll that one flag (a single request
-          // per wave) until it is set, then re-check the batch
-          const int kt = sc[t];
+          // entry t itself is missing: poll that one value or flag (a single
+          // request per wave) until it is set, then re-check the batch
           bool go = true;
-          while (go && bcast0((unsigned int)ld_flag(ready + kt)) != (unsigned int)epoch)
-            go = bcast0(keep_waiting(&spins, stall) ? 1u : 0u) != 0u;
+          if (LIGHT) {
+            const int dpt = sk[t].x;
+            while (go && bcast0(is_sentinel(ld_coh(val + dpt)) ? 1u : 0u) != 0u)
+              go = bcast0(keep_waiting(&spins, stall) ? 1u : 0u) != 0u;
+          } else {
+            const int kt = sc[t];
+            while (go && bcast0((unsigned int)ld_flag(ready + kt)) != (unsigned int)epoch)
+              go = bcast0(keep_waiting(&spins, stall) ? 1u : 0u) != 0u;
+          }
           if (!go) {
             ready_upto = dl;
             break;
@@ -353,6 +394,10 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
         }
       }
       const double lik = sv[t] / ukk;
+      // LIGHT: an entry of the pivot row may still be in flight although its
+      // diagonal has landed
+      if (LIGHT && j0 >= 0)
+        while (is_sentinel(u0) && keep_waiting(&spins, stall)) u0 = ld_coh(val + kk.x + 1 + lane);
       if (MAPPED) {
         if (j0 >= 0) sv[j0] = __builtin_fma(-lik, u0, sv[j0]);
         // remaining chunks: four loads of each kind in flight per lane
@@ -371,8 +416,12 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
             }
           }
 #pragma unroll
-          for (int z = 0; z < 4; z++)
+          for (int z = 0; z < 4; z++) {
+            if (LIGHT && p[z] >= 0)
+              while (is_sentinel(u[z]) && keep_waiting(&spins, stall))
+                u[z] = ld_coh(val + q0 + z * WAVE);
             if (p[z] >= 0) sv[p[z]] = __builtin_fma(-lik, u[z], sv[p[z]]);
+          }
         }
       } else {
         if (j0 >= 0) {
@@ -381,7 +430,9 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
         }
         for (int q = kk.x + 1 + WAVE + lane; q < kk.y; q += WAVE) {
           const int j = col[q];
-          const double u = LIGHT ? ld_coh(val + q) : val[q];
+          double u = LIGHT ? ld_coh(val + q) : val[q];
+          if (LIGHT)
+            while (is_sentinel(u) && keep_waiting(&spins, stall)) u = ld_coh(val + q);
           const int p = lower_bound_i(sc, t + 1, len, j);
           if (p < len && sc[p] == j) sv[p] = __builtin_fma(-lik, u, sv[p]);
         }
@@ -395,17 +446,19 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
       mo = mo_n;
       have = have_n;
     }
+    // LIGHT: each value is its own flag (the factor started filled with the
+    // sentinel), so no completion wait and no flag; otherwise values, a
+    // device-scope release, then the flag
     for (int t = lane; t < len; t += WAVE) {
       if (LIGHT)
         st_coh(val + rs + t, sv[t]);
       else
         val[rs + t] = sv[t];
     }
-    if (LIGHT)
-      stores_done();
-    else
+    if (!LIGHT) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    st_flag(ready + i, epoch);  // every lane, same address and value
+      st_flag(ready + i, epoch);  // every lane, same address and value
+    }
     }
   }
 }
@@ -487,11 +540,6 @@ __global__ __launch_bounds__(256) void k_trisolve_syncfree(
 // device-scope loads and the producer publishes with one device-scope store:
 // one round trip per dependency and no fences.  Input c and output y are
 // separate arrays (n + 1 entries; slot n takes idle lanes' writes).
-constexpr unsigned long long SENTINEL = 0x7FF0DEAD5EED0001ull;
-
-__device__ __forceinline__ bool is_sentinel(double v) {
-  return (unsigned long long)__double_as_longlong(v) == SENTINEL;
-}
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_trisolve_vflag(
@@ -1434,7 +1482,9 @@ __global__ __launch_bounds__(256) void k_seg_stats(const int* __restrict__ row_o
 __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict__ arow,
                                                     const double* __restrict__ src, double* dst,
                                                     DevStats* st, SyncState* ss,
-                                                    double* __restrict__ rowabs) {
+                                                    double* __restrict__ rowabs,
+                                                    const int* __restrict__ a2lu,
+                                                    double* __restrict__ luA) {
   const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = gridDim.x * blockDim.x / WAVE;
@@ -1447,6 +1497,7 @@ __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict
       for (int p = arow[i] + gl; p < arow[i + 1]; p += RG) {
         const double v = src[p];
         dst[p] = v;
+        if (luA) luA[a2lu[p]] = v;
         s += fabs(v);
       }
     s = group_sum(s);
@@ -1841,9 +1892,10 @@ void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStre
 }
 
 void launch_copy_anorm(int n, const int* arow, const int*, const double* src, double* dst,
-                       DevStats* st, hipStream_t s, SyncState* ss, double* rowabs) {
+                       DevStats* st, hipStream_t s, SyncState* ss, double* rowabs,
+                       const int* a2lu, double* luA) {
   hipLaunchKernelGGL(k_copy_anorm, dim3(rows_grid(n)), dim3(256), 0, s, n, arow, src,
-                     dst, st, ss, rowabs);
+                     dst, st, ss, rowabs, a2lu, luA);
 }
 
 void launch_seg_stats(int count, const int* row_off, const double* matabs, const double* r,
@@ -1851,11 +1903,18 @@ void launch_seg_stats(int count, const int* row_off, const double* matabs, const
   hipLaunchKernelGGL(k_seg_stats, dim3(count), dim3(256), 0, s, row_off, matabs, r, x, out);
 }
 
+void launch_fill_sentinel(double* p, long long count, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_fill_sentinel, dim3((unsigned)std::min<long long>(4096, (count + 255) / 256)),
+                     dim3(256), 0, s, p, count);
+}
+
 void launch_refactor_trivial(const LUView& lu, const int* rows, int nrows, const double* aval,
-                             int* ready, const SyncState* ss, hipStream_t s) {
+                             int* ready, const SyncState* ss, hipStream_t s, const double* luA) {
   if (nrows <= 0) return;
   hipLaunchKernelGGL(k_refactor_trivial, dim3(std::max(1, std::min(cdiv(nrows, 32), 2048))),
-                     dim3(256), 0, s, nrows, rows, lu.rowptr, lu.src, aval, lu.val, ready, ss);
+                     dim3(256), 0, s, nrows, rows, lu.rowptr, lu.src, aval, lu.val, ready, ss,
+                     luA);
 }
 
 void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map, hipStream_t s) {
@@ -1866,7 +1925,8 @@ void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map,
 bool launch_refactor_syncfree(const LUView& lu, const int* order, const int* cstart,
                               int nchunks, int band, int cap, const double* aval, int* ready,
                               SyncState* ss, int* stall, bool light, int wpb_pref, int c0,
-                              const int* moff, const unsigned short* map, hipStream_t s) {
+                              const int* moff, const unsigned short* map, const double* luA,
+                              const int2* pbnd, int max_waves_per_cu, hipStream_t s) {
   if (nchunks <= 0) return true;
   if (band < 0 || band >= REF_MAX_BANDS) return false;
   cap = (cap + 1) & ~1;
@@ -1885,10 +1945,11 @@ bool launch_refactor_syncfree(const LUView& lu, const int* order, const int* cst
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, wpb * WAVE, shm) != hipSuccess ||
         nb <= 0)
       nb = 1;
+    if (max_waves_per_cu > 0) nb = std::max(1, std::min(nb, max_waves_per_cu / wpb));
     const int grid = std::max(1, std::min(nb * ncu, cdiv(nchunks, wpb)));
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(wpb * WAVE), shm, s, order, cstart, nchunks,
                        &ss->band_ticket[band], lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val,
-                       ready, ss, stall, cap, c0, moff, map);
+                       ready, ss, stall, cap, c0, moff, map, luA, pbnd);
   };
   // waves per block: the preference if its LDS fits in 64 KiB, else the
   // largest of 4, 2, 1 that fits (4 only for rows short enough for 32 KiB)

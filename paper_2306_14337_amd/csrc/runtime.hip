@@ -82,6 +82,11 @@ struct kkt_ctx {
   // offset), longest row band_cap[b]
   int *ref_order = nullptr, *ref_cstart = nullptr;
   int* ref_triv = nullptr;  // rows without pivots (k_refactor_trivial)
+  // A's values in factor order (fill positions zero) and the A -> factor map;
+  // per L entry (i, k): (diag[k], rowptr[k + 1])
+  double* luA = nullptr;
+  int* a2lu = nullptr;
+  int2* ref_pbnd = nullptr;
   int ref_ntriv = 0;
   // precomputed update positions of the refactorization (null: binary search)
   int* ref_moff = nullptr;
@@ -517,7 +522,8 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
        o.refactor_waves_per_block != 2 && o.refactor_waves_per_block != 4) ||
       o.solve_thin_rows < -1 || o.solve_thin_rows > SEG_MAX_LEVEL_ROWS || o.dense_tail < -1 ||
       o.dense_tail > DENSE_TAIL_MAX || o.solve_blocks_per_cu < 0 || o.solve_blocks_per_cu > 8 ||
-      o.solve_chain < -1 || o.solve_chain > SN_KMAX || o.refactor_map < -1 || o.refactor_map > 0)
+      o.solve_chain < -1 || o.solve_chain > SN_KMAX || o.refactor_map < -1 || o.refactor_map > 0 ||
+      o.refactor_crit_height < -1 || o.refactor_waves_per_cu < 0)
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) return KKT_ERR_DEVICE;
@@ -902,6 +908,9 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     }
     h->ref_ntriv = (int)trows.size();
     if (!trows.empty()) UP(h->ref_triv, trows);
+    const int hcrit = h->opt.refactor_crit_height == 0 ? 32
+                      : h->opt.refactor_crit_height < 0 ? INT32_MAX
+                                                        : h->opt.refactor_crit_height;
     // rows by (level, decreasing height): two stable counting sorts
     std::vector<int32_t> by_h(n), by_lh(n);
     {
@@ -924,16 +933,24 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
       const int lo = (int)order.size();
       const int clo = (int)cst.size();
       int mx = 0;
-      for (int32_t i : by_lh)
-        if (band[i] == b && !triv[i]) {
-          order.push_back(i);
-          mx = std::max(mx, A.lu_rowptr[i + 1] - A.lu_rowptr[i]);
-        }
+      // rows on long chains (height >= hcrit) first: the set is closed under
+      // dependencies (a row's dependency has a larger height), so this stays
+      // a topological order, and those rows start before the wide levels of
+      // the rest have been handed out
+      for (int part = 0; part < 2; part++)
+        for (int32_t i : by_lh)
+          if (band[i] == b && !triv[i] && (height[i] >= hcrit) == (part == 0)) {
+            order.push_back(i);
+            mx = std::max(mx, A.lu_rowptr[i + 1] - A.lu_rowptr[i]);
+          }
       const int hi = (int)order.size();
       if (hi == lo) continue;
       for (int t = lo; t < hi;) {
         int e = t;
-        while (e < hi && level[order[e]] == level[order[t]]) e++;
+        const bool crit = height[order[t]] >= hcrit;
+        while (e < hi && level[order[e]] == level[order[t]] &&
+               (height[order[e]] >= hcrit) == crit)
+          e++;
         const int per = std::max(1, std::min(16, (e - t) / 8192));
         for (int c = t; c < e; c += per) cst.push_back(c);
         t = e;
@@ -973,6 +990,28 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
       }
       h->ref_map_entries = tot;
     }
+  }
+  h->luA = nullptr;
+  h->a2lu = nullptr;
+  h->ref_pbnd = nullptr;
+  if (h->syncfree) {
+    std::vector<int32_t> a2lu((size_t)nnz, 0);
+    const size_t fz = A.lu_col.size();
+    for (size_t q = 0; q < fz; q++)
+      if (A.lu_src[q] >= 0) a2lu[A.lu_src[q]] = (int32_t)q;
+    std::vector<int2> pb(fz, make_int2(0, 0));
+    for (int32_t i = 0; i < n; i++)
+      for (int32_t q = A.lu_rowptr[i]; q < A.diag[i]; q++) {
+        const int32_t k = A.lu_col[q];
+        pb[q] = make_int2(A.diag[k], A.lu_rowptr[k + 1]);
+      }
+    UP(h->a2lu, a2lu);
+    UP(h->ref_pbnd, pb);
+    if ((ks = dalloc(h, &h->luA, fz)) != KKT_OK) {
+      free_device(h);
+      return ks;
+    }
+    HIP_CHECK(h, hipMemset(h->luA, 0, fz * sizeof(double)));
   }
   // chain-blocked schedules of the four solves over the rows outside the
   // dense trailing block (modes 0 L, 1 U, 2 U^T, 3 L^T)
@@ -1300,14 +1339,18 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
   LUView lu = view(h);
   launch_reset_stats(h->st, 1, s);
   if (h->syncfree) {
-    launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, h->ss, h->rowabs);
-    launch_refactor_trivial(lu, h->ref_triv, h->ref_ntriv, h->aval, h->ready_ref, h->ss, s);
+    launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, h->ss, h->rowabs,
+                      h->a2lu, h->luA);
+    if (h->light) launch_fill_sentinel(h->lu_val, (long long)A.lu_col.size(), s);
+    launch_refactor_trivial(lu, h->ref_triv, h->ref_ntriv, h->aval, h->ready_ref, h->ss, s,
+                            h->luA);
     for (int b = 0; b < h->nbands; b++)
       if (!launch_refactor_syncfree(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
                                     h->band_nchunks[b], b, h->band_cap[b], h->aval, h->ready_ref,
                                     h->ss, &h->st->stall, h->light,
                                     h->opt.refactor_waves_per_block, h->tail_c0, h->ref_moff,
-                                    h->ref_map, s))
+                                    h->ref_map, h->luA, h->ref_pbnd,
+                                    h->opt.refactor_waves_per_cu, s))
         return fail(h, KKT_ERR_DEVICE, "dependency-driven refactorization not launchable");
     if (h->tail_s > 0) {
       launch_tail_scatter(lu, h->tail_c0, h->tail_s, h->tail_S, h->tail_T, s);
