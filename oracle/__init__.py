@@ -31,7 +31,7 @@ def build(force: bool = True) -> str:
 
 class _SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("min_iters", C.c_int32),
-                ("eta_target", C.c_double)]
+                ("eta_target", C.c_double), ("method", C.c_int32)]
 
 
 class _SolveInfo(C.Structure):
@@ -150,11 +150,13 @@ class OracleLU:
         self._vals_keep = np.ascontiguousarray(values, dtype=np.float64)
         return lib().oracle_set_values(self._h, _p(self._vals_keep))
 
-    def solve(self, b, op: str = "N", restart=20, max_iters=20, min_iters=0, eta_target=1e-12):
+    def solve(self, b, op: str = "N", restart=20, max_iters=20, min_iters=0, eta_target=1e-12,
+              method: str = "fgmres"):
+        """method "fgmres" (FGMRES-CGS2) or "ir" (classical iterative refinement)."""
         b = np.ascontiguousarray(b, dtype=np.float64)
         nrhs = b.size // self.n
         x = np.empty_like(b)
-        o = _SolveOpts(restart, max_iters, min_iters, eta_target)
+        o = _SolveOpts(restart, max_iters, min_iters, eta_target, 1 if method == "ir" else 0)
         info = _SolveInfo()
         st = lib().oracle_solve(self._h, op.encode(), nrhs, _p(b), _p(x), C.byref(o), C.byref(info))
         return x, dict(status=st, iters=info.iters, converged=info.converged, eta=info.eta,

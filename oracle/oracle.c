@@ -702,10 +702,37 @@ static void fgmres_one(const oracle_lu *lu, char op, const double *b, double *x,
   free(y);
 }
 
+/* Classical iterative refinement with the factors as the approximate
+ * inverse (Section 5.1.1: refinement of the direct solution): after the
+ * direct solve, x <- x + M^{-1} (b - A x) until the exit test of fgmres_one
+ * holds or max_iters corrections were applied.  One right-hand side. */
+static void ir_one(const oracle_lu *lu, char op, const double *b, double *x,
+                   const oracle_solve_opts *o, int32_t *iters_out, double *eta_out,
+                   double *eta0_out) {
+  int32_t n = lu->n;
+  size_t N = (size_t)n + 1;
+  double *r = (double *)malloc(N * sizeof(double));
+  double *d = (double *)malloc(N * sizeof(double));
+  oracle_lu_apply(lu, op, b, x);
+  double eta = residual(lu, op, b, x, r);
+  *eta0_out = eta;
+  int32_t it = 0;
+  while (!(eta <= o->eta_target && it >= o->min_iters) && it < o->max_iters) {
+    oracle_lu_apply(lu, op, r, d);
+    for (int32_t t = 0; t < n; t++) x[t] += d[t];
+    it++;
+    eta = residual(lu, op, b, x, r);
+  }
+  *iters_out = it;
+  *eta_out = eta;
+  free(r);
+  free(d);
+}
+
 int oracle_solve(const oracle_lu *lu, char op, int32_t nrhs, const double *b, double *x,
                  const oracle_solve_opts *opt, oracle_solve_info *info) {
   if (!lu || !b || !x || nrhs < 0 || (op != 'N' && op != 'T')) return ORA_ERR_ARG;
-  oracle_solve_opts o = {20, 20, 0, 1e-12};
+  oracle_solve_opts o = {20, 20, 0, 1e-12, 0};
   if (opt) o = *opt;
   int32_t n = lu->n, maxit = 0;
   double emax = 0.0, e0max = 0.0;
@@ -713,7 +740,10 @@ int oracle_solve(const oracle_lu *lu, char op, int32_t nrhs, const double *b, do
   for (int32_t r = 0; r < nrhs; r++) {
     int32_t it;
     double eta, eta0;
-    fgmres_one(lu, op, b + (size_t)r * n, x + (size_t)r * n, &o, &it, &eta, &eta0);
+    if (o.method == 1)
+      ir_one(lu, op, b + (size_t)r * n, x + (size_t)r * n, &o, &it, &eta, &eta0);
+    else
+      fgmres_one(lu, op, b + (size_t)r * n, x + (size_t)r * n, &o, &it, &eta, &eta0);
     if (it > maxit) maxit = it;
     if (!(eta <= emax)) emax = eta;
     if (!(eta0 <= e0max)) e0max = eta0;

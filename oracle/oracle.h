@@ -34,6 +34,7 @@ typedef struct {
   int32_t max_iters; /* total FGMRES iteration budget */
   int32_t min_iters; /* always run at least this many iterations */
   double eta_target; /* exit when ||b-Ax||_inf / (||A||_inf ||x||_inf) <= target */
+  int32_t method;    /* 0 FGMRES-CGS2, 1 classical iterative refinement */
 } oracle_solve_opts;
 
 typedef struct {

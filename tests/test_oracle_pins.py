@@ -571,6 +571,36 @@ def test_fgmres_refines_stale_factor():
     assert info2["iters"] == 2 and info2["converged"] == 1
 
 
+def test_iterative_refinement_steps_match_dense_definition():
+    # classical refinement with a stale factor M = A1: x0 = A1^{-1} b and
+    # x_{k+1} = x_k + A1^{-1} (b - A2 x_k), against dense numpy solves
+    n = 60
+    rp, ci, v = kktgen.random_sparse(n, 0.15, seed=21)
+    A1, Am = dense_from_csr(n, rp, ci, v)
+    A1[np.diag_indices(n)] += 6.0
+    r, c = np.nonzero(Am)
+    A2 = A1.copy()
+    A2[r, c] *= 1.0 + 0.05 * np.random.default_rng(2).standard_normal(len(r))
+    lu = oracle.OracleLU(n, rp, ci, A1[r, c], tau=1.0)
+    lu.set_values(A2[r, c])
+    b = np.random.default_rng(5).standard_normal(n)
+    x = np.linalg.solve(A1, b)
+    for k in range(1, 4):
+        x = x + np.linalg.solve(A1, b - A2 @ x)
+        xk, info = lu.solve(b, method="ir", max_iters=k, eta_target=0.0)
+        assert info["iters"] == k
+        assert np.abs(xk - x).max() <= 1e-12 * np.abs(x).max(), k
+    # it converges linearly, at the rate of the stale factor's error
+    rate = np.abs(np.linalg.eigvals(np.eye(n) - np.linalg.solve(A1, A2))).max()
+    assert rate < 0.5
+    xc, info = lu.solve(b, method="ir", max_iters=60)
+    assert info["converged"] == 1
+    assert np.abs(A2 @ xc - b).max() <= 1e-12 * np.abs(A2).sum(1).max() * np.abs(xc).max()
+    # the same exit test and budget as FGMRES: zero iterations leave it stale
+    _, info0 = lu.solve(b, method="ir", max_iters=0)
+    assert info0["converged"] == 0 and info0["iters"] == 0
+
+
 # ---------------------------------------------------------------------------
 # P9: adjoint closed form dL/dA = -A^{-T} C X^T on the pattern
 # ---------------------------------------------------------------------------
