@@ -105,7 +105,10 @@ typedef struct {
                                    (0 = 32, -1 = plain level order) */
   int32_t refactor_waves_per_cu; /* dependency-driven refactorization: cap on the resident waves
                                     per CU of its persistent grid (0 = occupancy limit) */
-  int32_t reserved[2];
+  int32_t refine; /* refinement method: 0 FGMRES-CGS2 (default), 1 classical iterative
+                     refinement x <- x + M^{-1}(b - A x); both use fgmres_max_iters as the
+                     iteration budget, min_iters and eta_target */
+  int32_t reserved[1];
 } kkt_options;
 
 typedef struct {

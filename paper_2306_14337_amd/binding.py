@@ -54,7 +54,8 @@ class Options(C.Structure):
                 ("solve_thin_rows", C.c_int32), ("dense_tail", C.c_int32),
                 ("solve_blocks_per_cu", C.c_int32), ("solve_chain", C.c_int32),
                 ("refactor_map", C.c_int32), ("refactor_crit_height", C.c_int32),
-                ("refactor_waves_per_cu", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("refactor_waves_per_cu", C.c_int32), ("refine", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class Report(C.Structure):

@@ -266,6 +266,8 @@ void launch_multiaxpy(int n, int m, const double* V, long ld, const double* h, d
 // out[t] = base[t] + sum_i y[i] Z[i]
 void launch_combine(int n, int m, const double* Z, long ld, const double* y, const double* base,
                     double* out, hipStream_t s);
+// x += d
+void launch_add(int n, const double* d, double* x, hipStream_t s);
 // y = x * (1 / *scal)  (scal on the device)
 void launch_scale_div(int n, const double* x, const double* scal, double* y, hipStream_t s);
 // Givens / small least-squares update of column j of the Hessenberg matrix

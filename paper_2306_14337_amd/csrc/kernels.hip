@@ -1773,6 +1773,12 @@ __global__ void k_scale_div(int n, const double* __restrict__ x, const double* _
   y[t] = d > 0.0 ? x[t] / d : 0.0;
 }
 
+// x += d (classical refinement step)
+__global__ void k_add(int n, const double* __restrict__ d, double* __restrict__ x) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) x[t] += d[t];
+}
+
 // Column j of the Hessenberg matrix from the two CGS passes (h + h2) and
 // ww = ||w||^2: store it, apply the earlier rotations, build rotation j,
 // update g and back-substitute y (j+1 entries).  *hn_out = ||w||.
@@ -2314,6 +2320,10 @@ void launch_multiaxpy(int n, int m, const double* V, long ld, const double* h, d
 void launch_combine(int n, int m, const double* Z, long ld, const double* y, const double* base,
                     double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_combine, dim3(cdiv(n, 256)), dim3(256), 0, s, n, m, Z, ld, y, base, out);
+}
+
+void launch_add(int n, const double* d, double* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_add, dim3(cdiv(n, 256)), dim3(256), 0, s, n, d, x);
 }
 
 void launch_scale_div(int n, const double* x, const double* scal, double* y, hipStream_t s) {

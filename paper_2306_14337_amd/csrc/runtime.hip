@@ -442,6 +442,20 @@ kkt_status solve_one(kkt_handle h, char op, const double* b, double* x, hipStrea
   *eta0_out = eta;
   int it = 0;
   bool done = eta <= o.eta_target && it >= o.min_iters;
+  if (o.refine == 1) {
+    // classical iterative refinement: x <- x + M^{-1} r (r from residual_eta)
+    while (!done && it < o.fgmres_max_iters) {
+      apply_factors(h, op, h->r, h->w, s);
+      launch_add(n, h->w, x, s);
+      it++;
+      st = residual_eta(h, op, b, x, h->r, s, &eta);
+      if (st != KKT_OK) return st;
+      done = eta <= o.eta_target && it >= o.min_iters;
+    }
+    *iters_out = it;
+    *eta_out = eta;
+    return (eta <= o.eta_target) ? KKT_OK : KKT_WARN_NOT_CONVERGED;
+  }
   bool at_xt = false;
   while (!done && it < o.fgmres_max_iters) {
     launch_multidot(n, 1, h->r, n, h->r, h->partial, h->ww, s);
@@ -523,7 +537,7 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
       o.solve_thin_rows < -1 || o.solve_thin_rows > SEG_MAX_LEVEL_ROWS || o.dense_tail < -1 ||
       o.dense_tail > DENSE_TAIL_MAX || o.solve_blocks_per_cu < 0 || o.solve_blocks_per_cu > 8 ||
       o.solve_chain < -1 || o.solve_chain > SN_KMAX || o.refactor_map < -1 || o.refactor_map > 0 ||
-      o.refactor_crit_height < -1 || o.refactor_waves_per_cu < 0)
+      o.refactor_crit_height < -1 || o.refactor_waves_per_cu < 0 || o.refine < 0 || o.refine > 1)
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) return KKT_ERR_DEVICE;

@@ -245,6 +245,37 @@ def test_refinement_forced_and_stale():
     assert s0.report().warnings & (1 << binding.WARN_NOT_CONVERGED)
 
 
+@pytest.mark.parametrize("op", ["N", "T"])
+def test_classical_refinement_matches_oracle(op):
+    # refine=1 with stale factors: same method as the oracle's "ir"; the
+    # iterates differ only by rounding, so the iteration counts agree to one
+    pat = kktgen.make_kkt(500, 78)
+    rng = np.random.default_rng(4)
+    sigma = np.clip(kktgen.draw_sigma(rng, pat.n_p), 1e-2, 1e2)
+    v_old = pat.values(sigma)
+    sym = pat.scipy(v_old * (1.0 + 0.005 * rng.standard_normal(v_old.size)))
+    sym = (sym + sym.T) * 0.5
+    sym.sort_indices()
+    v_new = sym.data
+    b = rng.standard_normal(pat.n)
+    s = binding.KKTSolver(refine=1, fgmres_max_iters=40)
+    s.analyze(pat.n, pat.rowptr, pat.colind, v_old)
+    s.refactor(dev(v_old))
+    s.update_matrix(dev(v_new))
+    x = s.solve(dev(b), op=op).cpu().numpy()
+    rep = s.report()
+    ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, v_old, tau=1e-10)
+    ora.set_values(v_new)
+    xo, info = ora.solve(b, op=op, method="ir", max_iters=40)
+    M = pat.scipy(v_new) if op == "N" else pat.scipy(v_new).T.tocsr()
+    print(f"  op {op}: gpu iters {rep.iters} eta {rep.eta:.3e}; oracle iters {info['iters']}",
+          flush=True)
+    assert info["converged"] == 1 and rep.iters > 1
+    assert eta(M, x, b) <= 1e-12
+    assert abs(rep.iters - info["iters"]) <= 1
+    assert np.abs(x - xo).max() <= 1e-6 * np.abs(xo).max()
+
+
 def test_gradient_matches_oracle():
     pat, seq = kktgen.make_sequence(100, 101, 1)
     vals, _ = seq[0]
