@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "oracle.c")
 
-OK, WARN_SINGULAR, WARN_TINY_PIVOT, WARN_NOT_CONVERGED = 0, 1, 2, 3
+OK, WARN_SINGULAR, WARN_TINY_PIVOT, WARN_NOT_CONVERGED, WARN_PERTURBED = 0, 1, 2, 3, 4
 ERR_ARG, ERR_STRUCT_SINGULAR = -1, -3
 
 
@@ -59,6 +59,8 @@ def lib():
         L.oracle_lu_absprod.argtypes = [P, P, P]
         L.oracle_refactor.argtypes = [P, P, C.c_double]
         L.oracle_refactor.restype = C.c_int
+        L.oracle_refactor_perturbed.argtypes = [P, P, C.c_double, C.c_double]
+        L.oracle_refactor_perturbed.restype = C.c_int
         L.oracle_set_values.argtypes = [P, P]
         L.oracle_set_values.restype = C.c_int
         L.oracle_solve.argtypes = [P, C.c_char, C.c_int32, P, P, C.POINTER(_SolveOpts),
@@ -141,8 +143,12 @@ class OracleLU:
         lib().oracle_lu_absprod(self._h, _p(sL), _p(sU))
         return sL, sU
 
-    def refactor(self, values, tiny_rel: float = 1e-18) -> int:
+    def refactor(self, values, tiny_rel: float = 1e-18, perturb_rel: float = 0.0) -> int:
+        """Refactorization; perturb_rel > 0 turns on static pivoting."""
         vals = np.ascontiguousarray(values, dtype=np.float64)
+        if perturb_rel > 0.0:
+            return lib().oracle_refactor_perturbed(self._h, _p(vals), float(tiny_rel),
+                                                  float(perturb_rel))
         return lib().oracle_refactor(self._h, _p(vals), float(tiny_rel))
 
     def set_values(self, values) -> int:

@@ -493,12 +493,22 @@ int oracle_set_values(oracle_lu *lu, const double *val) {
  * L(:,k) = w / u_kk.  A pivot with |u_kk| < tiny_rel * ||A||_inf (or a
  * non-finite one) raises the tiny-pivot warning; the factorization goes on. */
 int oracle_refactor(oracle_lu *lu, const double *val, double tiny_rel) {
+  return oracle_refactor_perturbed(lu, val, tiny_rel, 0.0);
+}
+
+/* The same with static pivoting: a finite pivot with |u_kk| below
+ * perturb_rel * ||A||_inf is replaced by that threshold with the pivot's sign
+ * (copysign) before the column of L is formed; the return value is then
+ * ORA_WARN_PERTURBED (the tiny-pivot test applies to the pivots used). */
+int oracle_refactor_perturbed(oracle_lu *lu, const double *val, double tiny_rel,
+                              double perturb_rel) {
   if (!lu || !val) return ORA_ERR_ARG;
   int32_t n = lu->n;
   set_values(lu, val);
   double *w = (double *)calloc((size_t)n + 1, sizeof(double));
-  int st = ORA_OK;
+  int st = ORA_OK, perturbed = 0;
   double tiny = tiny_rel * lu->anorm_inf;
+  double thr = perturb_rel * lu->anorm_inf;
   for (int32_t k = 0; k < n; k++) {
     int32_t c = lu->Q[k];
     for (int64_t t = lu->Up[k]; t < lu->Up[k + 1]; t++) w[lu->Ui[t]] = 0.0;
@@ -512,6 +522,11 @@ int oracle_refactor(oracle_lu *lu, const double *val, double tiny_rel) {
         w[lu->Li[s]] = fma(-lu->Lx[s], wj, w[lu->Li[s]]);
     }
     double ukk = w[k];
+    if (perturb_rel > 0.0 && fabs(ukk) < thr) {
+      ukk = copysign(thr, ukk);
+      w[k] = ukk;
+      perturbed = 1;
+    }
     if (!(fabs(ukk) >= tiny) && st == ORA_OK) st = ORA_WARN_TINY_PIVOT;
     for (int64_t t = lu->Up[k]; t < lu->Up[k + 1]; t++) lu->Ux[t] = w[lu->Ui[t]];
     for (int64_t s = lu->Lp[k]; s < lu->Lp[k + 1]; s++) lu->Lx[s] = w[lu->Li[s]] / ukk;
@@ -519,6 +534,7 @@ int oracle_refactor(oracle_lu *lu, const double *val, double tiny_rel) {
     for (int64_t s = lu->Lp[k]; s < lu->Lp[k + 1]; s++) w[lu->Li[s]] = 0.0;
   }
   free(w);
+  if (st == ORA_OK && perturbed) st = ORA_WARN_PERTURBED;
   return st;
 }
 

@@ -24,6 +24,7 @@
 #define ORA_WARN_SINGULAR 1
 #define ORA_WARN_TINY_PIVOT 2
 #define ORA_WARN_NOT_CONVERGED 3
+#define ORA_WARN_PERTURBED 4
 #define ORA_ERR_ARG (-1)
 #define ORA_ERR_STRUCT_SINGULAR (-3)
 
@@ -67,6 +68,11 @@ void oracle_lu_absprod(const oracle_lu *lu, double *sL, double *sU);
 /* Refactor with the stored P, Q and patterns (no pivot search).  Returns
  * ORA_OK or ORA_WARN_TINY_PIVOT (|u_kk| < tiny_rel * ||A||_inf). */
 int oracle_refactor(oracle_lu *lu, const double *val, double tiny_rel);
+/* Refactorization with static pivoting (perturb_rel > 0): pivots with
+ * |u_kk| < perturb_rel * ||A||_inf are replaced by copysign of that value.
+ * Returns ORA_WARN_PERTURBED if any was. */
+int oracle_refactor_perturbed(oracle_lu *lu, const double *val, double tiny_rel,
+                              double perturb_rel);
 
 /* Replace the matrix values used by residuals (factors left as they are). */
 int oracle_set_values(oracle_lu *lu, const double *val);

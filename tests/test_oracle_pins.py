@@ -3,6 +3,7 @@ force with exactly rounded fma, the fill-path theorem, closed forms of the
 minimum-degree ordering, textbook GMRES properties and the adjoint's closed
 form.  CPU only.
 """
+import math
 from fractions import Fraction
 import os
 from collections import deque
@@ -398,9 +399,10 @@ def test_refactor_of_first_matrix_is_bitwise_the_pivoting_pass():
     assert err <= 1e-13 * np.abs(Ad).sum(1).max() * max(growth, 1.0)
 
 
-def doolittle_exact(PA):
+def doolittle_exact(PA, thr=0.0):
     """No-pivot dense LU, row by row, each entry updated in ascending k with a
-    correctly rounded fma (the refactorization's arithmetic)."""
+    correctly rounded fma (the refactorization's arithmetic).  thr > 0: static
+    pivoting, a finished pivot below thr in magnitude becomes copysign(thr)."""
     n = PA.shape[0]
     a = [[float(x) for x in row] for row in PA]
     for i in range(n):
@@ -409,6 +411,8 @@ def doolittle_exact(PA):
             a[i][k] = l
             for j in range(k + 1, n):
                 a[i][j] = fma_exact(-l, a[k][j], a[i][j])
+        if thr > 0.0 and abs(a[i][i]) < thr:
+            a[i][i] = math.copysign(thr, a[i][i])
     a = np.array(a)
     return np.tril(a, -1), np.triu(a)
 
@@ -431,6 +435,35 @@ def test_refactor_matches_exact_doolittle(seed):
     assert np.array_equal(L, Ld) and np.array_equal(U, Ud)
     # outside the structural pattern the dense factors are exactly zero
     assert not np.any(Ld[~Lm]) and not np.any(Ud[~Um])
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_refactor_static_pivoting_matches_exact_doolittle(seed):
+    # threshold at the median pivot: about half of the pivots are raised
+    pat = kktgen.make_kkt(3, 50 + seed)
+    rng = np.random.default_rng(seed)
+    v0 = pat.values(kktgen.draw_sigma(rng, pat.n_p))
+    v1 = pat.values(kktgen.draw_sigma(rng, pat.n_p))
+    lu = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, v0, tau=1e-10)
+    lu.refactor(v1)
+    piv = np.abs(lu.factors()["Ux"][np.diff(lu.factors()["Up"]).cumsum() - 1])
+    anorm = np.abs(pat.scipy(v1)).sum(1).max()
+    rel = float(np.median(piv)) / anorm
+    assert lu.refactor(v1, perturb_rel=rel) == oracle.WARN_PERTURBED
+    f = lu.factors()
+    n = pat.n
+    Ad, _ = dense_from_csr(n, pat.rowptr, pat.colind, v1)
+    PA = Ad[np.ix_(f["Q"], f["Q"])][f["P"], :]
+    Ld, Ud = doolittle_exact(PA, thr=rel * anorm)
+    L, _ = csc_dense(n, f["Lp"], f["Li"], f["Lx"])
+    U, _ = csc_dense(n, f["Up"], f["Ui"], f["Ux"])
+    assert np.array_equal(L, Ld) and np.array_equal(U, Ud)
+    assert np.abs(np.diag(U)).min() >= rel * anorm
+    # threshold below every pivot: identical to the plain refactorization
+    lu.refactor(v1)
+    g = lu.factors()
+    assert lu.refactor(v1, perturb_rel=0.5 * piv.min() / anorm) == oracle.OK
+    assert np.array_equal(lu.factors()["Ux"], g["Ux"]) and np.array_equal(lu.factors()["Lx"], g["Lx"])
 
 
 def test_refactor_tiny_pivot_warning():
