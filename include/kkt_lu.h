@@ -55,6 +55,7 @@ typedef enum {
   KKT_WARN_NUMERICALLY_SINGULAR = 1, /* a pivot column was all zeros (analyze) */
   KKT_WARN_TINY_PIVOT = 2,           /* |u_kk| < tiny_pivot_rel * ||A||_inf or non-finite */
   KKT_WARN_NOT_CONVERGED = 3,        /* refinement budget spent before eta_target */
+  KKT_WARN_PERTURBED_PIVOT = 4,      /* a pivot was raised to the static-pivoting threshold */
   KKT_ERR_INVALID_ARG = -1,
   KKT_ERR_BAD_PATTERN = -2,          /* unsorted / duplicate / out-of-range CSR */
   KKT_ERR_STRUCTURALLY_SINGULAR = -3,
@@ -109,6 +110,11 @@ typedef struct {
                      refinement x <- x + M^{-1}(b - A x); both use fgmres_max_iters as the
                      iteration budget, min_iters and eta_target */
   int32_t reserved[1];
+  double pivot_perturb_rel; /* static pivoting in the refactorizations: a pivot with
+                               |u_kk| < pivot_perturb_rel * ||A||_inf becomes
+                               copysign(pivot_perturb_rel * ||A||_inf, u_kk) (warning
+                               KKT_WARN_PERTURBED_PIVOT; refinement corrects the solve);
+                               0 = off (default), < 1 */
 } kkt_options;
 
 typedef struct {

@@ -20,6 +20,7 @@ OK = 0
 WARN_NUMERICALLY_SINGULAR = 1
 WARN_TINY_PIVOT = 2
 WARN_NOT_CONVERGED = 3
+WARN_PERTURBED_PIVOT = 4
 ERR_INVALID_ARG = -1
 ERR_BAD_PATTERN = -2
 ERR_STRUCTURALLY_SINGULAR = -3
@@ -55,7 +56,7 @@ class Options(C.Structure):
                 ("solve_blocks_per_cu", C.c_int32), ("solve_chain", C.c_int32),
                 ("refactor_map", C.c_int32), ("refactor_crit_height", C.c_int32),
                 ("refactor_waves_per_cu", C.c_int32), ("refine", C.c_int32),
-                ("reserved", C.c_int32 * 1)]
+                ("reserved", C.c_int32 * 1), ("pivot_perturb_rel", C.c_double)]
 
 
 class Report(C.Structure):

@@ -16,6 +16,7 @@ struct DevStats {
   unsigned long long xmax;     // bits of ||x||_inf
   int tiny;                    // a tiny or non-finite pivot was seen
   int stall;                   // a dependency wait hit its spin limit (sticky)
+  int perturbed;               // a pivot was raised to the perturbation threshold
 };
 
 // Refactorization rows are split into at most this many bands by row length.
@@ -96,9 +97,11 @@ struct LUView {
 
 // level-synchronous refactorization of the rows rows[0..nrows) (all their
 // dependencies finished in earlier launches).  maxlen = longest row.
+// perturb_rel > 0: a final pivot with |u_ii| < perturb_rel ||A||_inf (from
+// st->anorm) becomes copysign(perturb_rel ||A||_inf, u_ii) and st->perturbed
+// is raised (static pivoting); the same in every refactorization kernel.
 void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxlen,
-                          const double* aval, DevStats* st, double tiny_abs_unused,
-                          hipStream_t s);
+                          const double* aval, DevStats* st, double perturb_rel, hipStream_t s);
 // Dependency-driven refactorization of all rows in one launch: waves take
 // rows in topological order (order[]) through a ticket counter and wait on
 // per-row ready flags.  cap = LDS staging capacity per row (>= longest row).
@@ -127,7 +130,8 @@ bool launch_refactor_syncfree(const LUView& lu, const int* order, const int* cst
                               int nchunks, int band, int cap, const double* aval, int* ready,
                               SyncState* ss, int* stall, bool light, int wpb_pref, int c0,
                               const int* moff, const unsigned short* map, const double* luA,
-                              const int2* pbnd, int max_waves_per_cu, hipStream_t s);
+                              const int2* pbnd, int max_waves_per_cu, DevStats* st,
+                              double perturb_rel, hipStream_t s);
 // map[moff[q] + u] = position in row i of U(k, >k)'s u-th column, for every L
 // entry q = (i, k) (moff: offsets indexed by factor position, host-computed)
 void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map, hipStream_t s);
@@ -141,7 +145,8 @@ void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map,
 // pattern entries back into the factors.  dsc: DLU_NB^2 doubles of scratch.
 constexpr int DLU_NB = 32;
 void launch_tail_scatter(const LUView& lu, int c0, int s, int S, double* T, hipStream_t st);
-void launch_dense_lu(double* T, int S, double* dsc, hipStream_t st);
+void launch_dense_lu(double* T, int S, int s, double* dsc, DevStats* stats, double perturb_rel,
+                     hipStream_t st);
 void launch_tail_gather(const LUView& lu, int c0, const double* T, int S, hipStream_t st);
 // Dependency-driven triangular solve of one right-hand side in place on y.
 // mode 0: unit L rows, 1: U rows, 2: U^T columns (tptr/trow/tpos view of U),
@@ -207,8 +212,8 @@ void launch_gather_sentinel(int n, const int* perm, const double* x, double* c, 
 void launch_fill_sentinel(double* p, long long count, hipStream_t s);
 // factor rows without pivots: val = staged A row, ready = current epoch
 void launch_refactor_trivial(const LUView& lu, const int* rows, int nrows, const double* aval,
-                             int* ready, const SyncState* ss, hipStream_t s,
-                             const double* luA = nullptr);
+                             int* ready, const SyncState* ss, hipStream_t s, const double* luA,
+                             int c0, DevStats* st, double perturb_rel);
 // zero the tickets and advance the epochs of the slots in mask (bit k = slot k)
 void launch_sync_prep(SyncState* ss, int mask, hipStream_t s);
 // y[i] = x[perm[i]] and, if ss != nullptr, the sync_prep of mask (fused)

@@ -39,6 +39,12 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // first position p in [lo, hi) with a[p] >= key
+// Static pivoting: a pivot below the threshold (finite, |d| < thr) takes the
+// threshold's magnitude with its own sign; thr <= 0 disables it.
+__device__ __forceinline__ double perturb_pivot(double d, double thr) {
+  return (thr > 0.0 && fabs(d) < thr) ? copysign(thr, d) : d;
+}
+
 __device__ __forceinline__ int lower_bound_i(const int* a, int lo, int hi, int key) {
   while (lo < hi) {
     int mid = (lo + hi) >> 1;
@@ -63,7 +69,7 @@ template <int CAP, int WPB>
 __global__ __launch_bounds__(WPB* WAVE) void k_refactor_rows_lds(
     const int* __restrict__ rows, int nrows, const int* __restrict__ rowptr,
     const int* __restrict__ col, const int* __restrict__ diag, const int* __restrict__ src,
-    const double* __restrict__ aval, double* __restrict__ val) {
+    const double* __restrict__ aval, double* __restrict__ val, DevStats* st, double prel) {
   __shared__ int s_col[WPB][CAP];
   __shared__ double s_val[WPB][CAP];
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
@@ -96,6 +102,15 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_rows_lds(
     if (lane == 0) sv[t] = lik;
     wave_sync();
   }
+  if (prel > 0.0) {
+    const double thr = prel * __longlong_as_double((long long)st->anorm);
+    const double d = sv[dl];
+    if (fabs(d) < thr) {
+      if (lane == 0) sv[dl] = perturb_pivot(d, thr);
+      st->perturbed = 1;
+    }
+    wave_sync();
+  }
   for (int t = lane; t < len; t += WAVE) val[rs + t] = sv[t];
 }
 
@@ -104,7 +119,7 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_rows_lds(
 __global__ __launch_bounds__(WAVE) void k_refactor_rows_global(
     const int* __restrict__ rows, int nrows, const int* __restrict__ rowptr,
     const int* __restrict__ col, const int* __restrict__ diag, const int* __restrict__ src,
-    const double* __restrict__ aval, double* val) {
+    const double* __restrict__ aval, double* val, DevStats* st, double prel) {
   const int lane = threadIdx.x;
   const int r = blockIdx.x;
   if (r >= nrows) return;
@@ -132,6 +147,14 @@ __global__ __launch_bounds__(WAVE) void k_refactor_rows_global(
     if (lane == 0) val[t] = lik;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
+  }
+  if (prel > 0.0) {
+    const double thr = prel * __longlong_as_double((long long)st->anorm);
+    const double d = val[dpos];
+    if (fabs(d) < thr) {
+      if (lane == 0) val[dpos] = perturb_pivot(d, thr);
+      st->perturbed = 1;
+    }
   }
 }
 
@@ -234,22 +257,32 @@ __global__ __launch_bounds__(256) void k_refactor_trivial(int nrows, const int* 
                                                           const double* __restrict__ aval,
                                                           double* __restrict__ val, int* ready,
                                                           const SyncState* ss,
-                                                          const double* __restrict__ luA) {
+                                                          const double* __restrict__ luA,
+                                                          const int* __restrict__ diag, int c0,
+                                                          DevStats* st, double prel) {
   const int lane = threadIdx.x % WAVE, g = lane / RG_TRIV, gl = lane % RG_TRIV;
   const int epoch = ss->epoch[0];
+  const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm) : 0.0;
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = gridDim.x * blockDim.x / WAVE;
   for (int r0 = wid * (WAVE / RG_TRIV); r0 < nrows; r0 += nw * (WAVE / RG_TRIV)) {
     const int r = r0 + g;
     if (r >= nrows) continue;
     const int i = rows[r];
+    const int dq = i < c0 ? diag[i] : -1;  // pivots of the dense block: there
     for (int q = rowptr[i] + gl; q < rowptr[i + 1]; q += RG_TRIV) {
+      double v;
       if (luA) {
-        val[q] = luA[q];
+        v = luA[q];
       } else {
         const int sq = src[q];
-        val[q] = sq >= 0 ? aval[sq] : 0.0;
+        v = sq >= 0 ? aval[sq] : 0.0;
       }
+      if (q == dq && fabs(v) < thr) {
+        v = perturb_pivot(v, thr);
+        st->perturbed = 1;
+      }
+      val[q] = v;
     }
     if (gl == 0) ready[i] = epoch;
   }
@@ -288,7 +321,7 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
     const int* __restrict__ col, const int* __restrict__ diag, const int* __restrict__ src,
     const double* __restrict__ aval, double* val, int* ready, SyncState* ss, int* stall, int cap,
     int c0, const int* __restrict__ moff, const unsigned short* __restrict__ map,
-    const double* __restrict__ luA, const int2* __restrict__ pbnd) {
+    const double* __restrict__ luA, const int2* __restrict__ pbnd, DevStats* st, double prel) {
   extern __shared__ double smem_d[];
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   // LDS per wave: values (cap doubles), pivot-row bounds (cap int2), columns (cap ints)
@@ -296,6 +329,7 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
   int2* sk = reinterpret_cast<int2*>(smem_d + (size_t)WPB * cap) + (size_t)wave * cap;
   int* sc = reinterpret_cast<int*>(smem_d + (size_t)WPB * cap * 2) + (size_t)wave * cap;
   const int epoch = ss->epoch[0];
+  const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm) : 0.0;
   for (;;) {
     const unsigned int tk = bcast0(atomicAdd(ticket, lane == 0 ? 1u : 0u));
     if (tk >= (unsigned int)nchunks) break;
@@ -445,6 +479,17 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
       j0 = j0_n;
       mo = mo_n;
       have = have_n;
+    }
+    // static pivoting of this row's pivot (rows of the dense block: there)
+    if (thr > 0.0 && i < c0) {
+      const int dr = diag[i] - rs;
+      const double d = sv[dr];
+      if (fabs(d) < thr) {
+        wave_sync();
+        sv[dr] = perturb_pivot(d, thr);  // every lane writes the same value
+        st->perturbed = 1;
+      }
+      wave_sync();
     }
     // LIGHT: each value is its own flag (the factor started filled with the
     // sentinel), so no completion wait and no flag; otherwise values, a
@@ -845,16 +890,22 @@ __global__ __launch_bounds__(256) void k_tail_gather(int c0, int s, int S,
 // the following k_dlu_update.
 template <int NB>
 __global__ __launch_bounds__(256) void k_dlu_panel(double* T, int S, int k0, int nrw,
-                                                   double* dsc) {
+                                                   double* dsc, int s, DevStats* st, double prel) {
   __shared__ double D[NB][NB + 1];
   const int tid = threadIdx.x;
   if (tid < WAVE) {
     const int t = tid;
+    const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm) : 0.0;
     double r[NB];
 #pragma unroll
     for (int j = 0; j < NB; j++) r[j] = t < NB ? T[(size_t)(k0 + t) * S + k0 + j] : 0.0;
 #pragma unroll
     for (int k = 0; k < NB; k++) {
+      // static pivoting of pivot k0 + k (real rows only) before its use
+      if (t == k && k0 + k < s && fabs(r[k]) < thr) {
+        if (blockIdx.x == 0) st->perturbed = 1;
+        r[k] = perturb_pivot(r[k], thr);
+      }
       const double ukk = readlane_d(r[k], k);
       const double l = r[k] / ukk;
 #pragma unroll
@@ -1390,6 +1441,7 @@ __global__ void k_reset_stats(DevStats* st, int what) {
       st->anorm = 0ull;
       st->anorm1 = 0ull;
       st->tiny = 0;
+      st->perturbed = 0;
     }
     if (what & 2) {
       st->rmax = 0ull;
@@ -1871,23 +1923,22 @@ inline int rows_grid(int n) { return std::max(1, std::min(cdiv(n, 32), 1024)); }
 // launchers
 // ---------------------------------------------------------------------------
 void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxlen,
-                          const double* aval, DevStats* st, double, hipStream_t s) {
-  (void)st;
+                          const double* aval, DevStats* st, double prel, hipStream_t s) {
   if (nrows <= 0) return;
   if (maxlen <= 128) {
     constexpr int W = 4;
     hipLaunchKernelGGL((k_refactor_rows_lds<128, W>), dim3(cdiv(nrows, W)), dim3(W * WAVE), 0, s,
-                       rows, nrows, lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val);
+                       rows, nrows, lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val, st, prel);
   } else if (maxlen <= 1024) {
     constexpr int W = 2;
     hipLaunchKernelGGL((k_refactor_rows_lds<1024, W>), dim3(cdiv(nrows, W)), dim3(W * WAVE), 0, s,
-                       rows, nrows, lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val);
+                       rows, nrows, lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val, st, prel);
   } else if (maxlen <= 4096) {
     hipLaunchKernelGGL((k_refactor_rows_lds<4096, 1>), dim3(nrows), dim3(WAVE), 0, s, rows, nrows,
-                       lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val);
+                       lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val, st, prel);
   } else {
     hipLaunchKernelGGL(k_refactor_rows_global, dim3(nrows), dim3(WAVE), 0, s, rows, nrows,
-                       lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val);
+                       lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val, st, prel);
   }
 }
 
@@ -1916,11 +1967,12 @@ void launch_fill_sentinel(double* p, long long count, hipStream_t s) {
 }
 
 void launch_refactor_trivial(const LUView& lu, const int* rows, int nrows, const double* aval,
-                             int* ready, const SyncState* ss, hipStream_t s, const double* luA) {
+                             int* ready, const SyncState* ss, hipStream_t s, const double* luA,
+                             int c0, DevStats* st, double perturb_rel) {
   if (nrows <= 0) return;
   hipLaunchKernelGGL(k_refactor_trivial, dim3(std::max(1, std::min(cdiv(nrows, 32), 2048))),
                      dim3(256), 0, s, nrows, rows, lu.rowptr, lu.src, aval, lu.val, ready, ss,
-                     luA);
+                     luA, lu.diag, c0, st, perturb_rel);
 }
 
 void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map, hipStream_t s) {
@@ -1932,7 +1984,8 @@ bool launch_refactor_syncfree(const LUView& lu, const int* order, const int* cst
                               int nchunks, int band, int cap, const double* aval, int* ready,
                               SyncState* ss, int* stall, bool light, int wpb_pref, int c0,
                               const int* moff, const unsigned short* map, const double* luA,
-                              const int2* pbnd, int max_waves_per_cu, hipStream_t s) {
+                              const int2* pbnd, int max_waves_per_cu, DevStats* st,
+                              double perturb_rel, hipStream_t s) {
   if (nchunks <= 0) return true;
   if (band < 0 || band >= REF_MAX_BANDS) return false;
   cap = (cap + 1) & ~1;
@@ -1955,7 +2008,7 @@ bool launch_refactor_syncfree(const LUView& lu, const int* order, const int* cst
     const int grid = std::max(1, std::min(nb * ncu, cdiv(nchunks, wpb)));
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(wpb * WAVE), shm, s, order, cstart, nchunks,
                        &ss->band_ticket[band], lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val,
-                       ready, ss, stall, cap, c0, moff, map, luA, pbnd);
+                       ready, ss, stall, cap, c0, moff, map, luA, pbnd, st, perturb_rel);
   };
   // waves per block: the preference if its LDS fits in 64 KiB, else the
   // largest of 4, 2, 1 that fits (4 only for rows short enough for 32 KiB)
@@ -2094,12 +2147,13 @@ void launch_tail_gather(const LUView& lu, int c0, const double* T, int S, hipStr
                      lu.col, T, lu.val);
 }
 
-void launch_dense_lu(double* T, int S, double* dsc, hipStream_t st) {
+void launch_dense_lu(double* T, int S, int s, double* dsc, DevStats* stats, double prel,
+                     hipStream_t st) {
   for (int k0 = 0; k0 < S; k0 += DLU_NB) {
     const int rest = S - k0 - DLU_NB;
     const int nrw = cdiv(rest, 256);
     hipLaunchKernelGGL(k_dlu_panel<DLU_NB>, dim3(std::max(1, 2 * nrw)), dim3(256), 0, st, T, S,
-                       k0, nrw, dsc);
+                       k0, nrw, dsc, s, stats, prel);
     const int nt = std::max(1, cdiv(rest, 64));
     hipLaunchKernelGGL(k_dlu_update<DLU_NB>, dim3(nt, nt), dim3(256), 0, st, T, S, k0,
                        (const double*)dsc);

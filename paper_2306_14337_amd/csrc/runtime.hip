@@ -537,7 +537,8 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
       o.solve_thin_rows < -1 || o.solve_thin_rows > SEG_MAX_LEVEL_ROWS || o.dense_tail < -1 ||
       o.dense_tail > DENSE_TAIL_MAX || o.solve_blocks_per_cu < 0 || o.solve_blocks_per_cu > 8 ||
       o.solve_chain < -1 || o.solve_chain > SN_KMAX || o.refactor_map < -1 || o.refactor_map > 0 ||
-      o.refactor_crit_height < -1 || o.refactor_waves_per_cu < 0 || o.refine < 0 || o.refine > 1)
+      o.refactor_crit_height < -1 || o.refactor_waves_per_cu < 0 || o.refine < 0 || o.refine > 1 ||
+      !(o.pivot_perturb_rel >= 0.0 && o.pivot_perturb_rel < 1.0))
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) return KKT_ERR_DEVICE;
@@ -1357,18 +1358,20 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
                       h->a2lu, h->luA);
     if (h->light) launch_fill_sentinel(h->lu_val, (long long)A.lu_col.size(), s);
     launch_refactor_trivial(lu, h->ref_triv, h->ref_ntriv, h->aval, h->ready_ref, h->ss, s,
-                            h->luA);
+                            h->luA, h->tail_c0, h->st, h->opt.pivot_perturb_rel);
     for (int b = 0; b < h->nbands; b++)
       if (!launch_refactor_syncfree(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
                                     h->band_nchunks[b], b, h->band_cap[b], h->aval, h->ready_ref,
                                     h->ss, &h->st->stall, h->light,
                                     h->opt.refactor_waves_per_block, h->tail_c0, h->ref_moff,
                                     h->ref_map, h->luA, h->ref_pbnd,
-                                    h->opt.refactor_waves_per_cu, s))
+                                    h->opt.refactor_waves_per_cu, h->st, h->opt.pivot_perturb_rel,
+                                    s))
         return fail(h, KKT_ERR_DEVICE, "dependency-driven refactorization not launchable");
     if (h->tail_s > 0) {
       launch_tail_scatter(lu, h->tail_c0, h->tail_s, h->tail_S, h->tail_T, s);
-      launch_dense_lu(h->tail_T, h->tail_S, h->tail_dsc, s);
+      launch_dense_lu(h->tail_T, h->tail_S, h->tail_s, h->tail_dsc, h->st,
+                      h->opt.pivot_perturb_rel, s);
       launch_tail_gather(lu, h->tail_c0, h->tail_T, h->tail_S, s);
     }
   } else {
@@ -1376,7 +1379,7 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
                       h->rowabs);
     for (size_t l = 0; l + 1 < A.lev_ptr.size(); l++)
       launch_refactor_rows(lu, h->lev_rows + A.lev_ptr[l], A.lev_ptr[l + 1] - A.lev_ptr[l],
-                           A.lev_maxlen[l], h->aval, h->st, 0.0, s);
+                           A.lev_maxlen[l], h->aval, h->st, h->opt.pivot_perturb_rel, s);
   }
   launch_pivot_stats(lu, h->st, h->opt.tiny_pivot_rel, s);
   return KKT_OK;
@@ -1579,6 +1582,7 @@ kkt_status kkt_sync_report(kkt_handle h, kkt_report* out) {
   }
   int warn = h->warnings;
   if (d.tiny) warn |= 1 << KKT_WARN_TINY_PIVOT;
+  if (d.perturbed) warn |= 1 << KKT_WARN_PERTURBED_PIVOT;
   out->warnings = warn;
   out->iters = h->last_iters;
   out->eta = h->last_eta;

@@ -276,6 +276,42 @@ def test_classical_refinement_matches_oracle(op):
     assert np.abs(x - xo).max() <= 1e-6 * np.abs(xo).max()
 
 
+@pytest.mark.parametrize("layout", [dict(schedule=2, sync_mode=2), dict(schedule=2, sync_mode=2, dense_tail=300),
+                                    dict(schedule=1), dict(schedule=2, sync_mode=1)],
+                         ids=["coherent", "dense-block", "levels", "fences"])
+def test_static_pivoting_bitwise(layout):
+    # threshold at the median pivot magnitude: about half of the pivots are
+    # raised, identically in every refactorization kernel and in the oracle
+    pat, seq = kktgen.make_sequence(500, 7, 2)
+    ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, seq[0][0], tau=1e-10)
+    vals = seq[1][0]
+    ora.refactor(vals)
+    f = ora.factors()
+    piv = np.abs(f["Ux"][np.diff(f["Up"]).cumsum() - 1])
+    anorm = np.abs(pat.scipy(vals)).sum(1).max()
+    rel = float(np.median(piv)) / anorm
+    assert ora.refactor(vals, perturb_rel=rel) == oracle.WARN_PERTURBED
+    s = binding.KKTSolver(pivot_perturb_rel=rel, **layout)
+    s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
+    s.refactor(dev(vals))
+    assert_factors_equal(s.lu()[2], oracle_csr_values(ora))
+    assert s.report().warnings & (1 << binding.WARN_PERTURBED_PIVOT)
+    # a threshold that raises only the few smallest pivots: the perturbed
+    # factors still precondition FGMRES to the target
+    rel2 = 1.01 * float(piv.min()) / anorm
+    s2 = binding.KKTSolver(pivot_perturb_rel=rel2, **layout)
+    s2.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
+    s2.refactor(dev(vals))
+    ora.refactor(vals, perturb_rel=rel2)
+    assert_factors_equal(s2.lu()[2], oracle_csr_values(ora))
+    b = seq[1][1]
+    x = s2.solve(dev(b)).cpu().numpy()
+    rep = s2.report()
+    print(f"  few perturbed: iters {rep.iters} eta {rep.eta:.3e}", flush=True)
+    assert rep.warnings & (1 << binding.WARN_PERTURBED_PIVOT)
+    assert eta(pat.scipy(vals), x, b) <= 1e-12
+
+
 def test_gradient_matches_oracle():
     pat, seq = kktgen.make_sequence(100, 101, 1)
     vals, _ = seq[0]
