@@ -56,6 +56,7 @@ typedef enum {
   KKT_WARN_TINY_PIVOT = 2,           /* |u_kk| < tiny_pivot_rel * ||A||_inf or non-finite */
   KKT_WARN_NOT_CONVERGED = 3,        /* refinement budget spent before eta_target */
   KKT_WARN_PERTURBED_PIVOT = 4,      /* a pivot was raised to the static-pivoting threshold */
+  KKT_WARN_REANALYZED = 5,           /* a solve re-ran the pivoting pass (auto_reanalyze) */
   KKT_ERR_INVALID_ARG = -1,
   KKT_ERR_BAD_PATTERN = -2,          /* unsorted / duplicate / out-of-range CSR */
   KKT_ERR_STRUCTURALLY_SINGULAR = -3,
@@ -109,7 +110,9 @@ typedef struct {
   int32_t refine; /* refinement method: 0 FGMRES-CGS2 (default), 1 classical iterative
                      refinement x <- x + M^{-1}(b - A x); both use fgmres_max_iters as the
                      iteration budget, min_iters and eta_target */
-  int32_t reserved[1];
+  int32_t auto_reanalyze; /* 1: a single-system solve that misses eta_target re-runs the pivoting
+                             pass on the current matrix (kkt_reanalyze) and solves again once
+                             (warning KKT_WARN_REANALYZED); 0 = off (default) */
   double pivot_perturb_rel; /* static pivoting in the refactorizations: a pivot with
                                |u_kk| < pivot_perturb_rel * ||A||_inf becomes
                                copysign(pivot_perturb_rel * ||A||_inf, u_kk) (warning
@@ -159,6 +162,16 @@ kkt_status kkt_destroy(kkt_handle h);
  * TOO_LARGE, OUT_OF_MEMORY, DEVICE.  Warning: NUMERICALLY_SINGULAR. */
 kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t *rowptr,
                        const int32_t *colind, const double *values0, const int32_t *user_q);
+
+/* Re-analysis with new values for a single-system handle: the pivoting pass
+ * (Section 5.1.2) re-runs on d_values (nnz(A) device doubles in the analysed
+ * CSR order; copied to the host after synchronizing `stream`) with the
+ * stored ordering Q, and everything is re-uploaded; the pass's factors are
+ * the current factors afterwards (no kkt_refactor needed).  This is the
+ * re-analysis of Section 5.1.1 for a matrix the stored pivot order no longer
+ * suits.  Synchronous.
+ * Errors: STATE (no single-system analysis), INVALID_ARG, as kkt_analyze. */
+kkt_status kkt_reanalyze(kkt_handle h, const double *d_values, void *stream);
 
 /* Numeric refactorization with the stored pivot sequence and patterns
  * (Section 5.1.2 "resetting the values ... and performing the

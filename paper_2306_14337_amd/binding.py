@@ -21,6 +21,7 @@ WARN_NUMERICALLY_SINGULAR = 1
 WARN_TINY_PIVOT = 2
 WARN_NOT_CONVERGED = 3
 WARN_PERTURBED_PIVOT = 4
+WARN_REANALYZED = 5
 ERR_INVALID_ARG = -1
 ERR_BAD_PATTERN = -2
 ERR_STRUCTURALLY_SINGULAR = -3
@@ -36,7 +37,7 @@ EXPORTS = [
     "kkt_get_lu", "kkt_last_error", "kkt_analysis_create", "kkt_analysis_info",
     "kkt_analysis_perm", "kkt_analysis_lu", "kkt_analysis_levels", "kkt_analysis_destroy",
     "kkt_analyze_batch", "kkt_batch_layout", "kkt_batch_eta", "kkt_graph_capture",
-    "kkt_graph_launch",
+    "kkt_graph_launch", "kkt_reanalyze",
 ]
 
 
@@ -56,7 +57,7 @@ class Options(C.Structure):
                 ("solve_blocks_per_cu", C.c_int32), ("solve_chain", C.c_int32),
                 ("refactor_map", C.c_int32), ("refactor_crit_height", C.c_int32),
                 ("refactor_waves_per_cu", C.c_int32), ("refine", C.c_int32),
-                ("reserved", C.c_int32 * 1), ("pivot_perturb_rel", C.c_double)]
+                ("auto_reanalyze", C.c_int32), ("pivot_perturb_rel", C.c_double)]
 
 
 class Report(C.Structure):
@@ -89,6 +90,7 @@ def lib():
         L.kkt_destroy.argtypes = [P]
         L.kkt_analyze.argtypes = [P, C.c_int32, C.c_int64, P, P, P, P]
         L.kkt_refactor.argtypes = [P, P, P]
+        L.kkt_reanalyze.argtypes = [P, P, P]
         L.kkt_update_matrix.argtypes = [P, P, P]
         L.kkt_solve.argtypes = [P, C.c_char, C.c_int32, P, P, P]
         L.kkt_grad_values.argtypes = [P, C.c_int32, P, P, P, P]
@@ -307,6 +309,12 @@ class KKTSolver:
     def refactor(self, values, stream=None) -> int:
         p = _dev_f64(values, self.nnz, "values")
         return self._check(lib().kkt_refactor(self._h, p, _stream_ptr(stream)))
+
+    def reanalyze(self, values, stream=None) -> int:
+        """Re-run the pivoting pass on new values (keeps the ordering); its
+        factors become the current factors."""
+        p = _dev_f64(values, self.nnz, "values")
+        return self._check(lib().kkt_reanalyze(self._h, p, _stream_ptr(stream)))
 
     def update_matrix(self, values, stream=None) -> int:
         """New matrix for the residuals; the current factors stay as preconditioner."""

@@ -72,6 +72,11 @@ struct kkt_ctx {
   double *tail_T = nullptr, *tail_dsc = nullptr, *tail_rhs = nullptr;
   int *tail_split0 = nullptr, *tail_split2 = nullptr;
   // chain-blocked single right-hand-side solves (modes 0 L, 1 U, 2 U^T, 3 L^T)
+  // single-system pattern (for re-analysis) and the number of re-analyses
+  std::vector<int64_t> pat_rowptr;
+  std::vector<int32_t> pat_colind;
+  int reanalyses = 0;
+  bool in_retry = false;
   bool use_sn = false;
   // rows without dependencies in the forward solves (L; U^T), final in the gather
   uint8_t *sn_triv0 = nullptr, *sn_triv2 = nullptr;
@@ -538,6 +543,7 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
       o.dense_tail > DENSE_TAIL_MAX || o.solve_blocks_per_cu < 0 || o.solve_blocks_per_cu > 8 ||
       o.solve_chain < -1 || o.solve_chain > SN_KMAX || o.refactor_map < -1 || o.refactor_map > 0 ||
       o.refactor_crit_height < -1 || o.refactor_waves_per_cu < 0 || o.refine < 0 || o.refine > 1 ||
+      o.auto_reanalyze < 0 || o.auto_reanalyze > 1 ||
       !(o.pivot_perturb_rel >= 0.0 && o.pivot_perturb_rel < 1.0))
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
@@ -585,7 +591,43 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
   h->batch_count = 0;
   h->row_off.clear();
   h->nnz_off.clear();
+  // the pattern, kept for re-analysis
+  h->pat_rowptr.assign(rowptr, rowptr + n + 1);
+  h->pat_colind.assign(colind, colind + nnz);
   return install_analysis(h, std::move(an), st, n, nnz, rowptr, colind, values0, t0);
+}
+
+kkt_status kkt_reanalyze(kkt_handle h, const double* d_values, void* stream) {
+  if (!h) return KKT_ERR_INVALID_ARG;
+  if (!h->analyzed || h->batch_count > 0 || h->pat_rowptr.empty())
+    return fail(h, KKT_ERR_STATE, "kkt_reanalyze needs a single-system analysis");
+  if (!d_values) return fail(h, KKT_ERR_INVALID_ARG, "d_values is NULL");
+  HIP_CHECK(h, hipSetDevice(h->opt.device));
+  const int32_t n = h->an.n;
+  const int64_t nnz = (int64_t)h->pat_colind.size();
+  std::vector<double> vals((size_t)nnz);
+  HIP_CHECK(h, hipStreamSynchronize((hipStream_t)stream));
+  HIP_CHECK(h, hipMemcpy(vals.data(), d_values, (size_t)nnz * sizeof(double),
+                         hipMemcpyDeviceToHost));
+  // the ordering depends on the pattern only: keep Q, redo the pivoting pass
+  std::vector<int32_t> q(h->an.Q);
+  std::vector<int64_t> rp(h->pat_rowptr);
+  std::vector<int32_t> ci(h->pat_colind);
+  auto t0 = std::chrono::steady_clock::now();
+  AnalyzeOptions ao;
+  ao.ordering = 2;
+  ao.tau = h->opt.pivot_tau;
+  Analysis an;
+  std::string msg;
+  int st;
+  try {
+    st = analyze(n, nnz, rp.data(), ci.data(), vals.data(), q.data(), ao, an, &msg);
+  } catch (const std::bad_alloc&) {
+    return fail(h, KKT_ERR_OUT_OF_MEMORY, "host allocation failed in analyze");
+  }
+  if (st < 0) return fail(h, (kkt_status)st, msg);
+  h->reanalyses++;
+  return install_analysis(h, std::move(an), st, n, nnz, rp.data(), ci.data(), vals.data(), t0);
 }
 
 // Upload of an analysis (single system or block-diagonal batch) and of A's
@@ -1535,6 +1577,19 @@ kkt_status kkt_solve(kkt_handle h, char op, int32_t nrhs, const double* d_b, dou
   h->last_eta = emax;
   h->last_eta0 = e0max;
   if (worst > 0) h->warnings |= 1 << worst;
+  if (worst == KKT_WARN_NOT_CONVERGED && h->opt.auto_reanalyze == 1 && !h->in_retry &&
+      h->batch_count == 0 && !h->pat_rowptr.empty()) {
+    // the stored pivot sequence no longer suits the matrix: redo the pivoting
+    // pass on the current values (the factors of that pass become current)
+    // and solve once more
+    kkt_status ks = kkt_reanalyze(h, h->aval, stream);
+    if (ks < 0) return ks;
+    h->in_retry = true;
+    ks = kkt_solve(h, op, nrhs, d_b, d_x, stream);
+    h->in_retry = false;
+    h->warnings |= 1 << KKT_WARN_REANALYZED;
+    return ks;
+  }
   return worst;
 }
 

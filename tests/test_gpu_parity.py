@@ -11,6 +11,7 @@
 * edge cases: ragged tiny systems, several right-hand sides, error statuses.
 """
 import numpy as np
+import scipy.sparse as sp
 import pytest
 
 import oracle
@@ -310,6 +311,50 @@ def test_static_pivoting_bitwise(layout):
     print(f"  few perturbed: iters {rep.iters} eta {rep.eta:.3e}", flush=True)
     assert rep.warnings & (1 << binding.WARN_PERTURBED_PIVOT)
     assert eta(pat.scipy(vals), x, b) <= 1e-12
+
+
+def _tridiag(n, d, o):
+    rp = [0]
+    ci, v = [], []
+    for i in range(n):
+        for j in (i - 1, i, i + 1):
+            if 0 <= j < n:
+                ci.append(j)
+                v.append(d if i == j else o)
+        rp.append(len(ci))
+    return np.array(rp, np.int64), np.array(ci, np.int32), np.array(v)
+
+
+def test_reanalysis_restores_a_stable_pivot_order():
+    # pivots fixed on a diagonally dominant matrix; the new matrix has a
+    # 1e-14 leading entry, so the stored order grows the factors by 1e14 and
+    # the direct solve misses the target; re-running the pivoting pass
+    # (partial pivoting) swaps the first two rows and the direct solve is exact
+    n = 6
+    rp, ci, v0 = _tridiag(n, 4.0, 1.0)
+    v1 = v0.copy()
+    v1[0] = 1e-14
+    b = np.random.default_rng(9).standard_normal(n)
+    A1 = sp.csr_matrix((v1, ci, rp), shape=(n, n))
+    opts = dict(ordering=1, pivot_tau=1.0, fgmres_max_iters=0)
+    s = binding.KKTSolver(**opts)
+    s.analyze(n, rp, ci, v0)
+    s.refactor(dev(v1))
+    s.solve(dev(b))
+    assert s.last_status == binding.WARN_NOT_CONVERGED
+    s.reanalyze(dev(v1))
+    x = s.solve(dev(b)).cpu().numpy()
+    assert s.last_status == binding.OK and eta(A1, x, b) <= 1e-12
+    ora = oracle.OracleLU(n, rp, ci, v1, Q=np.arange(n, dtype=np.int32), tau=1.0)
+    assert_factors_equal(s.lu()[2], oracle_csr_values(ora))
+    assert not np.array_equal(s.perm()[0], np.arange(n))  # rows were swapped
+    # automatic: the solve re-analyses by itself and reports it
+    s2 = binding.KKTSolver(auto_reanalyze=1, **opts)
+    s2.analyze(n, rp, ci, v0)
+    s2.refactor(dev(v1))
+    x2 = s2.solve(dev(b)).cpu().numpy()
+    assert s2.last_status == binding.OK and eta(A1, x2, b) <= 1e-12
+    assert s2.report().warnings & (1 << binding.WARN_REANALYZED)
 
 
 def test_gradient_matches_oracle():
