@@ -113,6 +113,10 @@ typedef struct {
   int32_t auto_reanalyze; /* 1: a single-system solve that misses eta_target re-runs the pivoting
                              pass on the current matrix (kkt_reanalyze) and solves again once
                              (warning KKT_WARN_REANALYZED); 0 = off (default) */
+  int32_t solve_jacobi_sweeps; /* > 0: op 'N' solves replace the exact triangular solves by
+                                  this many Jacobi sweeps per triangle (approximate triangular
+                                  solves; FGMRES absorbs the difference), 0 = exact (default) */
+  int32_t reserved2;
   double pivot_perturb_rel; /* static pivoting in the refactorizations: a pivot with
                                |u_kk| < pivot_perturb_rel * ||A||_inf becomes
                                copysign(pivot_perturb_rel * ||A||_inf, u_kk) (warning

@@ -273,6 +273,10 @@ void launch_combine(int n, int m, const double* Z, long ld, const double* y, con
                     double* out, hipStream_t s);
 // x += d
 void launch_add(int n, const double* d, double* x, hipStream_t s);
+// one Jacobi sweep of the unit-L (mode 0) or U (mode 1) solve with right-hand
+// side c: yout = c - strict part * yin (then / diagonal for U); all rows at once
+void launch_jacobi_sweep(int mode, const LUView& lu, const double* c, const double* yin,
+                         double* yout, hipStream_t s);
 // y = x * (1 / *scal)  (scal on the device)
 void launch_scale_div(int n, const double* x, const double* scal, double* y, hipStream_t s);
 // Givens / small least-squares update of column j of the Hessenberg matrix

@@ -1756,6 +1756,36 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ ptr
   }
 }
 
+// One Jacobi sweep of a triangular solve (approximate triangular solves,
+// the future-work direction of Section 6): every row at once from the
+// previous iterate, 8 lanes per row.
+//   MODE 0  unit L:  yout_i = c_i - sum_{k<i} l_ik yin_k
+//   MODE 1  U:       yout_i = (c_i - sum_{k>i} u_ik yin_k) / u_ii
+template <int MODE>
+__global__ __launch_bounds__(256) void k_jacobi_sweep(int n, const int* __restrict__ rowptr,
+                                                      const int* __restrict__ col,
+                                                      const int* __restrict__ diag,
+                                                      const double* __restrict__ val,
+                                                      const double* __restrict__ c,
+                                                      const double* __restrict__ yin,
+                                                      double* __restrict__ yout) {
+  const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int nw = gridDim.x * blockDim.x / WAVE;
+  for (int r0 = wid * (WAVE / RG); r0 < n; r0 += nw * (WAVE / RG)) {
+    const int i = r0 + g;
+    double s = 0.0;
+    int dq = 0;
+    if (i < n) {
+      dq = diag[i];
+      const int b = MODE == 0 ? rowptr[i] : dq + 1, e = MODE == 0 ? dq : rowptr[i + 1];
+      for (int q = b + gl; q < e; q += RG) s += val[q] * yin[col[q]];
+    }
+    s = group_sum(s);
+    if (i < n && gl == 0) yout[i] = MODE == 0 ? c[i] - s : (c[i] - s) / val[dq];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // FGMRES-CGS2 pieces
 // ---------------------------------------------------------------------------
@@ -2374,6 +2404,16 @@ void launch_multiaxpy(int n, int m, const double* V, long ld, const double* h, d
 void launch_combine(int n, int m, const double* Z, long ld, const double* y, const double* base,
                     double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_combine, dim3(cdiv(n, 256)), dim3(256), 0, s, n, m, Z, ld, y, base, out);
+}
+
+void launch_jacobi_sweep(int mode, const LUView& lu, const double* c, const double* yin,
+                         double* yout, hipStream_t s) {
+  if (mode == 0)
+    hipLaunchKernelGGL(k_jacobi_sweep<0>, dim3(rows_grid(lu.n)), dim3(256), 0, s, lu.n, lu.rowptr,
+                       lu.col, lu.diag, lu.val, c, yin, yout);
+  else
+    hipLaunchKernelGGL(k_jacobi_sweep<1>, dim3(rows_grid(lu.n)), dim3(256), 0, s, lu.n, lu.rowptr,
+                       lu.col, lu.diag, lu.val, c, yin, yout);
 }
 
 void launch_add(int n, const double* d, double* x, hipStream_t s) {

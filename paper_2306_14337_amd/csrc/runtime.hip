@@ -136,6 +136,8 @@ kkt_status fail(kkt_handle h, kkt_status st, const std::string& msg) {
   return st;
 }
 
+#define HIP_CHECK_VOID(call) (void)(call)
+
 #define HIP_CHECK(h, call)                                                              \
   do {                                                                                  \
     hipError_t e_ = (call);                                                             \
@@ -203,6 +205,31 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
   const Analysis& A = h->an;
   const int n = A.n;
   LUView lu = view(h);
+  const int sweeps = h->opt.solve_jacobi_sweeps;
+  if (sweeps > 0 && op == 'N') {
+    // approximate triangular solves: `sweeps` Jacobi sweeps per triangle,
+    // starting from the right-hand side (FGMRES takes the variable
+    // preconditioner)
+    launch_gather(n, h->pin, b, h->tc, s);
+    const double* cur = h->tc;
+    double* bufs[2] = {h->ty, h->tz};
+    int k = 0;
+    for (int it = 0; it < sweeps; it++, k ^= 1) {
+      launch_jacobi_sweep(0, lu, h->tc, cur, bufs[k], s);
+      cur = bufs[k];
+    }
+    // U: right-hand side cur (copied to tmp), first iterate the right-hand side
+    HIP_CHECK_VOID(hipMemcpyAsync(h->tmp, cur, (size_t)n * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s));
+    const double* cu = h->tmp;
+    cur = h->tmp;
+    for (int it = 0; it < sweeps; it++, k ^= 1) {
+      launch_jacobi_sweep(1, lu, cu, cur, bufs[k], s);
+      cur = bufs[k];
+    }
+    launch_scatter(n, h->qperm, cur, x, s);
+    return;
+  }
   if (h->use_sn) {
     // chain-blocked sparse rows and the dense trailing block: the block comes
     // last in the forward solves (L, U^T) and first in the backward ones
@@ -543,7 +570,7 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
       o.dense_tail > DENSE_TAIL_MAX || o.solve_blocks_per_cu < 0 || o.solve_blocks_per_cu > 8 ||
       o.solve_chain < -1 || o.solve_chain > SN_KMAX || o.refactor_map < -1 || o.refactor_map > 0 ||
       o.refactor_crit_height < -1 || o.refactor_waves_per_cu < 0 || o.refine < 0 || o.refine > 1 ||
-      o.auto_reanalyze < 0 || o.auto_reanalyze > 1 ||
+      o.auto_reanalyze < 0 || o.auto_reanalyze > 1 || o.solve_jacobi_sweeps < 0 ||
       !(o.pivot_perturb_rel >= 0.0 && o.pivot_perturb_rel < 1.0))
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;

@@ -357,6 +357,70 @@ def test_reanalysis_restores_a_stable_pivot_order():
     assert s2.report().warnings & (1 << binding.WARN_REANALYZED)
 
 
+def test_jacobi_sweeps_truncated_and_exact():
+    # approximate triangular solves: k sweeps per triangle.  The GPU's direct
+    # solve equals the truncated sweeps written out with the oracle's factors,
+    # and as many sweeps as the dependency depth give the exact solve
+    pat, seq = kktgen.make_sequence(100, 101, 1)
+    vals, b = seq[0]
+    ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, vals, tau=1e-10)
+    f = ora.factors()
+    n = pat.n
+    L = sp.csc_matrix((f["Lx"], f["Li"], f["Lp"]), shape=(n, n)).tocsr()
+    U = sp.csc_matrix((f["Ux"], f["Ui"], f["Up"]), shape=(n, n)).tocsr()
+    d = U.diagonal()
+    Us = U - sp.diags(d)
+    pin = f["Q"][f["P"]]
+    c = b[pin]
+
+    def sweeps(k):
+        y = c.copy()
+        for _ in range(k):
+            y = c - L @ y
+        z = y.copy()
+        for _ in range(k):
+            z = (y - Us @ z) / d
+        x = np.empty(n)
+        x[f["Q"]] = z
+        return x
+
+    A = pat.scipy(vals)
+    for k in (3, 12):
+        s = binding.KKTSolver(solve_jacobi_sweeps=k, fgmres_max_iters=0)
+        s.analyze(pat.n, pat.rowptr, pat.colind, vals)
+        s.refactor(dev(vals))
+        x = s.solve(dev(b)).cpu().numpy()
+        xr = sweeps(k)
+        assert np.abs(x - xr).max() <= 1e-9 * np.abs(xr).max(), k
+    depth = max(s.info().levels, s.info().levels_u) + 1
+    s = binding.KKTSolver(solve_jacobi_sweeps=depth, fgmres_max_iters=0)
+    s.analyze(pat.n, pat.rowptr, pat.colind, vals)
+    s.refactor(dev(vals))
+    x = s.solve(dev(b)).cpu().numpy()
+    xo = ora.apply(b)
+    assert np.abs(x - xo).max() <= 1e-8 * np.abs(xo).max()
+    assert eta(A, x, b) <= 1e-12
+
+
+def test_jacobi_sweeps_precondition_fgmres():
+    # on a well-conditioned matrix a few sweeps are a good enough
+    # preconditioner for FGMRES to reach the target
+    n = 400
+    rp, ci, v = kktgen.random_sparse(n, 0.01, seed=31)
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n)).toarray()
+    A[np.diag_indices(n)] += 4.0 + np.abs(A).sum(1)
+    Acsr = sp.csr_matrix(A)
+    Acsr.sort_indices()
+    b = np.random.default_rng(6).standard_normal(n)
+    s = binding.KKTSolver(solve_jacobi_sweeps=4)
+    s.analyze(n, Acsr.indptr.astype(np.int64), Acsr.indices.astype(np.int32), Acsr.data)
+    s.refactor(dev(Acsr.data))
+    x = s.solve(dev(b)).cpu().numpy()
+    rep = s.report()
+    print(f"  4 sweeps: iters {rep.iters} eta {rep.eta:.3e}", flush=True)
+    assert s.last_status == binding.OK and eta(Acsr, x, b) <= 1e-12
+
+
 def test_gradient_matches_oracle():
     pat, seq = kktgen.make_sequence(100, 101, 1)
     vals, _ = seq[0]
