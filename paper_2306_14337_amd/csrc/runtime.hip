@@ -1190,6 +1190,21 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
         item_lev[it] = lv;
         nlev = std::max(nlev, lv + 1);
       }
+      // item heights (longest chain of items depending on it): items with a
+      // long chain after them are handed out first (a dependency-closed set,
+      // so the order stays topological), the rest by level
+      std::vector<int32_t> item_h(nitems, 0);
+      for (int it = nitems - 1; it >= 0; it--)
+        for (int r = 0; r < item_len[it]; r++) {
+          const int32_t i = fwd ? item_first[it] + r : item_first[it] - r;
+          for (int32_t q = lb(i); q < le(i); q++) {
+            const int32_t j = dep(q);
+            if (j >= c0 || item_of[j] < 0 || item_of[j] == it) continue;
+            int32_t& hd = item_h[item_of[j]];
+            hd = std::max(hd, item_h[it] + 1);
+          }
+        }
+      const int hcrit = 2;
       // chunks in level order
       std::vector<int32_t> by_lev_ptr(nlev + 1, 0), by_lev(nitems);
       for (int it = 0; it < nitems; it++) by_lev_ptr[item_lev[it] + 1]++;
@@ -1211,10 +1226,12 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
           while (q < e && dep(q) <= base) q++;
         return q;
       };
+      for (int part = 0; part < 2; part++)
       for (int l = 0; l < nlev; l++) {
         std::vector<int32_t> singles;
         for (int32_t t = by_lev_ptr[l]; t < by_lev_ptr[l + 1]; t++) {
           const int it = by_lev[t];
+          if ((item_h[it] >= hcrit) != (part == 0)) continue;
           const int k = item_len[it];
           if (k == 1) {
             singles.push_back(item_first[it]);
