@@ -116,7 +116,10 @@ typedef struct {
   int32_t solve_jacobi_sweeps; /* > 0: op 'N' solves replace the exact triangular solves by
                                   this many Jacobi sweeps per triangle (approximate triangular
                                   solves; FGMRES absorbs the difference), 0 = exact (default) */
-  int32_t reserved2;
+  int32_t refactor_short_rows; /* dependency-driven refactorization with device-coherent
+                                  publication: 0 = rows of the short-row band (at most 256
+                                  entries) take all their updates as one list loaded a window
+                                  at a time (default), -1 = pivot by pivot like the other bands */
   double pivot_perturb_rel; /* static pivoting in the refactorizations: a pivot with
                                |u_kk| < pivot_perturb_rel * ||A||_inf becomes
                                copysign(pivot_perturb_rel * ||A||_inf, u_kk) (warning

@@ -27,12 +27,20 @@ constexpr int REF_MAX_BANDS = 4;
 // a dependency-driven phase zeroes its ticket counter and advances its epoch;
 // a row is finished in the current phase when ready[row] == epoch.
 // Slots: 0 refactorization, 1 first triangular solve, 2 second one.
+// The refactorization bands (one launch each) hand out their chunks through
+// TICKET_STREAMS interleaved counters: chunk c belongs to stream c % S and a
+// workgroup b fetches from stream b % S only (S = min(TICKET_STREAMS, grid)),
+// so one device-scope counter no longer serializes every fetch.  Each counter
+// sits on its own 128-byte line.
+constexpr int TICKET_STREAMS = 8;
+constexpr int TICKET_STRIDE = 32;
+
 struct SyncState {
   unsigned int ticket[4];
   int epoch[4];
-  // refactorization bands (one launch each, see launch_refactor_syncfree):
-  // ticket counters, reset with slot 0
-  unsigned int band_ticket[REF_MAX_BANDS];
+  // refactorization band b, stream s: band_stream[b][s * TICKET_STRIDE]
+  // (reset with slot 0)
+  alignas(128) unsigned int band_stream[REF_MAX_BANDS][TICKET_STREAMS * TICKET_STRIDE];
 };
 
 // Work chunks of a triangular-solve schedule: chunk c covers rows
@@ -117,9 +125,9 @@ void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxl
 // Band b: the rows order[cstart[0] .. cstart[nchunks]) (topological order;
 // every dependency outside them finished by an earlier launch), taken by the
 // waves in chunks order[cstart[c] .. cstart[c+1]) of rows of one level (one
-// ticket per chunk: the single counter's atomic rate would otherwise bound
-// the wide levels), cap >= their longest row, the band's ticket counter
-// ss->band_ticket[b].
+// ticket per chunk: the counters' atomic rate would otherwise bound the wide
+// levels), cap >= their longest row, the band's ticket streams
+// ss->band_stream[b].
 // moff/map (both or neither): precomputed update positions (launch_build_refmap)
 // replacing the per-entry binary search.  max_waves_per_cu > 0 caps the
 // persistent grid below the occupancy limit.
@@ -134,7 +142,22 @@ bool launch_refactor_syncfree(const LUView& lu, const int* order, const int* cst
                               double perturb_rel, hipStream_t s);
 // map[moff[q] + u] = position in row i of U(k, >k)'s u-th column, for every L
 // entry q = (i, k) (moff: offsets indexed by factor position, host-computed)
-void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map, hipStream_t s);
+// flat (nullable, one byte per row): rows of the short-row kernel get packed
+// entries (pivot index << 8) | position (their rows have at most 256 entries)
+void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map,
+                         const unsigned char* flat, hipStream_t s);
+
+// A short-row band: one wave per row, every row of the band at most 256
+// entries, no row of the dense block.  fl[q] for the
+// row's L entries q = (offset of pivot q's first multiply-add in the row's
+// list, U row start of pivot q minus that offset), at the diagonal q =
+// (length of the list, 0); map holds packed entries (launch_build_refmap with
+// flat).  Device-coherent value-as-flag publication only.
+bool launch_refactor_flat(const LUView& lu, const int* order, const int* cstart, int nchunks,
+                          int band, int cap, SyncState* ss, int* stall, const int* moff,
+                          const unsigned short* map, const double* luA, const int2* fl,
+                          int max_waves_per_cu, DevStats* st, double perturb_rel,
+                          hipStream_t s);
 
 // Dense trailing block: rows and columns c0 .. c0+s-1 of the factors in pivot
 // order, held row-major in T (S x S, S = s rounded up to DLU_NB; the padding

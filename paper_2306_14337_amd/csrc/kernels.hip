@@ -204,6 +204,22 @@ __device__ __forceinline__ unsigned int bcast0(unsigned int v) {
   return (unsigned int)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// Next chunk of a launch whose chunks are handed out through nstreams
+// interleaved ticket counters (chunk c in stream c % nstreams, workgroup b
+// fetching from stream b % nstreams; every stream has a workgroup since
+// nstreams <= grid).  Deadlock freedom as with one counter: let u be the
+// lowest unfinished chunk.  Its inputs lie in lower chunks, all finished.  If
+// u was fetched, its wave completes it; if not, every fetched chunk of its
+// stream is lower, hence finished, so that stream's waves are free and one
+// of them fetches u next.  Returns a value >= nchunks once the stream is
+// exhausted.
+__device__ __forceinline__ int next_chunk(unsigned int* streams, int nstreams, int lane) {
+  const int s = (int)(blockIdx.x % (unsigned int)nstreams);
+  const unsigned int m =
+      bcast0(atomicAdd(streams + s * TICKET_STRIDE, lane == 0 ? 1u : 0u));
+  return (int)m * nstreams + s;
+}
+
 // One more round of waiting allowed?  False once the limit is hit here (the
 // wave raises *stall) or anywhere else (another wave raised it).
 // The stall flag is polled every 64th round only; between rounds the wave
@@ -290,22 +306,27 @@ __global__ __launch_bounds__(256) void k_refactor_trivial(int nrows, const int* 
 
 // Update maps of the refactorization, built once per analysis: for the L
 // entry q = (i, k), map[moff[q] + u] = position (from the row start) of the
-// column of U(k, >k)'s u-th entry in row i.  Wave per row, lanes over U(k).
+// column of U(k, >k)'s u-th entry in row i; rows flagged in flat (rows of at
+// most 256 entries) carry (q - row start) << 8 in the high byte as well.
+// Wave per row, lanes over U(k).
 __global__ __launch_bounds__(256) void k_build_refmap(int n, const int* __restrict__ rowptr,
                                                       const int* __restrict__ col,
                                                       const int* __restrict__ diag,
                                                       const int* __restrict__ moff,
-                                                      unsigned short* __restrict__ map) {
+                                                      unsigned short* __restrict__ map,
+                                                      const unsigned char* __restrict__ flat) {
   const int lane = threadIdx.x % WAVE;
   const int nw = gridDim.x * blockDim.x / WAVE;
   for (int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE; i < n; i += nw) {
     const int rs = rowptr[i], re = rowptr[i + 1];
+    const bool packed = flat != nullptr && flat[i] != 0;
     for (int q = rs; q < diag[i]; q++) {
       const int k = col[q], ub = diag[k] + 1, ue = rowptr[k + 1];
       const int mo = moff[q];
+      const int hi = packed ? (q - rs) << 8 : 0;
       for (int u = ub + lane; u < ue; u += WAVE) {
         const int p = lower_bound_i(col, q + 1, re, col[u]);
-        map[mo + (u - ub)] = (unsigned short)(p - rs);
+        map[mo + (u - ub)] = (unsigned short)(hi | (p - rs));
       }
     }
   }
@@ -317,7 +338,7 @@ __global__ __launch_bounds__(256) void k_build_refmap(int n, const int* __restri
 template <int WPB, bool LIGHT, bool MAPPED>
 __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
     const int* __restrict__ order, const int* __restrict__ cstart, int nchunks,
-    unsigned int* ticket, const int* __restrict__ rowptr,
+    unsigned int* tickets, int nstreams, const int* __restrict__ rowptr,
     const int* __restrict__ col, const int* __restrict__ diag, const int* __restrict__ src,
     const double* __restrict__ aval, double* val, int* ready, SyncState* ss, int* stall, int cap,
     int c0, const int* __restrict__ moff, const unsigned short* __restrict__ map,
@@ -331,8 +352,8 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
   const int epoch = ss->epoch[0];
   const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm) : 0.0;
   for (;;) {
-    const unsigned int tk = bcast0(atomicAdd(ticket, lane == 0 ? 1u : 0u));
-    if (tk >= (unsigned int)nchunks) break;
+    const int tk = next_chunk(tickets, nstreams, lane);
+    if (tk >= nchunks) break;
     const int r_end = cstart[tk + 1];
     for (int r = cstart[tk]; r < r_end; r++) {
     const int i = order[r];
@@ -661,7 +682,8 @@ __device__ __forceinline__ void sync_prep(SyncState* ss, int mask) {
       ss->ticket[k] = 0u;
       ss->epoch[k] = ss->epoch[k] + 1;
       if (k == 0)
-        for (int b = 0; b < REF_MAX_BANDS; b++) ss->band_ticket[b] = 0u;
+        for (int b = 0; b < REF_MAX_BANDS; b++)
+          for (int t = 0; t < TICKET_STREAMS; t++) ss->band_stream[b][t * TICKET_STRIDE] = 0u;
     }
 }
 
@@ -1947,6 +1969,146 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 // enough workgroups that their one atomic each stays cheap
 inline int rows_grid(int n) { return std::max(1, std::min(cdiv(n, 32), 1024)); }
 
+
+// Rows of a short-row band (at most 256 entries each; no row of the dense
+// block).  One wave per row, as
+// k_refactor_syncfree, but the row's multiply-adds form one list, pivot after
+// pivot, each pivot row's U entries in order: for the row's L entries q,
+// fl[q] = (offset of pivot q's first list entry, U row start of pivot q minus
+// that offset), and at the diagonal fl = (list length, 0); the packed map
+// gives every list entry as (pivot index << 8) | target position.  Up to 256
+// list entries (four per lane) of pivots already seen finished are loaded at
+// once, so a row costs a few memory round trips rather than one or two per
+// pivot; the arithmetic still runs pivot after pivot in ascending order with
+// the same fma(-l, u, a) and quotient as every other refactorization code.
+// Publication: device-coherent stores of the values into a factor array that
+// holds the sentinel; a pivot row is finished once its diagonal is, and each
+// of its other entries is re-polled while it still reads as the sentinel.
+template <int WPB>
+__global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
+    const int* __restrict__ order, const int* __restrict__ cstart, int nchunks,
+    unsigned int* tickets, int nstreams, const int* __restrict__ rowptr,
+    const int* __restrict__ diag, double* val, int* stall, int cap,
+    const int* __restrict__ moff, const unsigned short* __restrict__ map,
+    const double* __restrict__ luA, const int2* __restrict__ fl, DevStats* st, double prel) {
+  extern __shared__ double smem_d[];
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  // LDS per wave: values (cap doubles), list bounds per L entry (cap int2)
+  double* sv = smem_d + (size_t)wave * cap;
+  int2* sf = reinterpret_cast<int2*>(smem_d + (size_t)WPB * cap) + (size_t)wave * cap;
+  const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm) : 0.0;
+  for (;;) {
+    const int tk = next_chunk(tickets, nstreams, lane);
+    if (tk >= nchunks) break;
+    const int r_end = cstart[tk + 1];
+    for (int r = cstart[tk]; r < r_end; r++) {
+      const int i = order[r];
+      wave_sync();  // the previous row of this chunk is done with the staging area
+      const int rs = rowptr[i], len = rowptr[i + 1] - rs, dl = diag[i] - rs;
+      for (int t = lane; t < len; t += WAVE) sv[t] = luA[rs + t];
+      for (int t = lane; t <= dl; t += WAVE) sf[t] = fl[rs + t];
+      const int mb = dl > 0 ? moff[rs] : 0;
+      wave_sync();
+      int ready_upto = 0, t0 = 0, spins = 0;
+      double dv = 0.0;  // lane q: diagonal of pivot t0 + q
+      int wbeg = 0, wend = 0;
+      double u[4];
+      int tp[4];  // packed map entry of the loaded list entry, -1 if none
+#pragma unroll
+      for (int z = 0; z < 4; z++) {
+        u[z] = 0.0;
+        tp[z] = -1;
+      }
+      for (int t = 0; t < dl; t++) {
+        if (t >= ready_upto) {
+          for (;;) {
+            // one pivot diagonal per lane; the values double as the batch of
+            // pivots for the quotients below
+            const int q = t + lane;
+            bool ok = true;
+            if (q < dl) {
+              const int2 f = sf[q];
+              dv = ld_coh(val + (f.x + f.y - 1));
+              ok = !is_sentinel(dv);
+            }
+            const unsigned long long bad = __ballot(!ok);
+            const int first_bad = bad ? __ffsll((long long)bad) - 1 : WAVE;
+            if (first_bad > 0) {
+              // never past the row's last pivot: sf[ready_upto] bounds the
+              // list windows below
+              ready_upto = min(dl, t + first_bad);
+              t0 = t;
+              break;
+            }
+            // pivot t itself is missing: poll its diagonal (a single request
+            // per wave) until it is set, then re-check the batch
+            const int2 f = sf[t];
+            const int dpt = f.x + f.y - 1;
+            bool go = true;
+            while (go && bcast0(is_sentinel(ld_coh(val + dpt)) ? 1u : 0u) != 0u)
+              go = bcast0(keep_waiting(&spins, stall) ? 1u : 0u) != 0u;
+            if (!go) {  // stalled: drain
+              ready_upto = dl;
+              t0 = t;
+              break;
+            }
+          }
+        }
+        const double ukk = readlane_d(dv, (t - t0) & (WAVE - 1));
+        const double lik = sv[t] / ukk;
+        const int oe = sf[t + 1].x;
+        const int dt = sf[t].y;
+        for (;;) {
+#pragma unroll
+          for (int z = 0; z < 4; z++) {
+            if ((tp[z] >> 8) == t) {
+              while (is_sentinel(u[z]) && keep_waiting(&spins, stall))
+                u[z] = ld_coh(val + (wbeg + lane + z * WAVE + dt));
+              const int p = tp[z] & 255;
+              sv[p] = __builtin_fma(-lik, u[z], sv[p]);
+            }
+          }
+          if (oe <= wend) break;
+          // next window of the list: entries of pivots seen finished
+          // (t < ready_upto <= dl, so the window holds at least pivot t's
+          // next entry; a window that cannot advance means inconsistent
+          // list bounds: report a stall rather than loop)
+          wbeg = wend;
+          wend = min(wbeg + 4 * WAVE, sf[ready_upto].x);
+          if (wend <= wbeg) {
+            st_flag(stall, 1);
+            break;
+          }
+#pragma unroll
+          for (int z = 0; z < 4; z++) {
+            const int e = wbeg + lane + z * WAVE;
+            tp[z] = -1;
+            if (e < wend) {
+              const int m = (int)map[mb + e];
+              tp[z] = m;
+              u[z] = ld_coh(val + (e + sf[m >> 8].y));
+            }
+          }
+        }
+        wave_sync();
+        sv[t] = lik;  // every lane writes the same value
+        wave_sync();
+      }
+      // static pivoting of this row's pivot
+      if (thr > 0.0) {
+        const double d = sv[dl];
+        if (fabs(d) < thr) {
+          wave_sync();
+          sv[dl] = perturb_pivot(d, thr);  // every lane writes the same value
+          st->perturbed = 1;
+        }
+        wave_sync();
+      }
+      for (int t = lane; t < len; t += WAVE) st_coh(val + rs + t, sv[t]);
+    }
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2005,9 +2167,40 @@ void launch_refactor_trivial(const LUView& lu, const int* rows, int nrows, const
                      luA, lu.diag, c0, st, perturb_rel);
 }
 
-void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map, hipStream_t s) {
+void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map,
+                         const unsigned char* flat, hipStream_t s) {
   hipLaunchKernelGGL(k_build_refmap, dim3(std::max(1, std::min(cdiv(lu.n, 4), 4096))), dim3(256),
-                     0, s, lu.n, lu.rowptr, lu.col, lu.diag, moff, map);
+                     0, s, lu.n, lu.rowptr, lu.col, lu.diag, moff, map, flat);
+}
+
+bool launch_refactor_flat(const LUView& lu, const int* order, const int* cstart, int nchunks,
+                          int band, int cap, SyncState* ss, int* stall, const int* moff,
+                          const unsigned short* map, const double* luA, const int2* fl,
+                          int max_waves_per_cu, DevStats* st, double perturb_rel,
+                          hipStream_t s) {
+  if (nchunks <= 0) return true;
+  if (band < 0 || band >= REF_MAX_BANDS || cap > 256 || !moff || !map || !luA || !fl) return false;
+  cap = (cap + 1) & ~1;
+  constexpr int WPB = 4;
+  const size_t shm = (size_t)cap * (sizeof(double) + sizeof(int2)) * WPB;
+  static int ncu = 0;
+  if (ncu == 0) {
+    int d = 0;
+    (void)hipGetDevice(&d);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
+    if (ncu <= 0) ncu = 256;
+  }
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_refactor_flat<WPB>, WPB * WAVE, shm) !=
+          hipSuccess ||
+      nb <= 0)
+    nb = 1;
+  if (max_waves_per_cu > 0) nb = std::max(1, std::min(nb, max_waves_per_cu / WPB));
+  const int grid = std::max(1, std::min(nb * ncu, cdiv(nchunks, WPB)));
+  hipLaunchKernelGGL(k_refactor_flat<WPB>, dim3(grid), dim3(WPB * WAVE), shm, s, order, cstart,
+                     nchunks, ss->band_stream[band], std::min(TICKET_STREAMS, grid), lu.rowptr,
+                     lu.diag, lu.val, stall, cap, moff, map, luA, fl, st, perturb_rel);
+  return true;
 }
 
 bool launch_refactor_syncfree(const LUView& lu, const int* order, const int* cstart,
@@ -2037,7 +2230,8 @@ bool launch_refactor_syncfree(const LUView& lu, const int* order, const int* cst
     if (max_waves_per_cu > 0) nb = std::max(1, std::min(nb, max_waves_per_cu / wpb));
     const int grid = std::max(1, std::min(nb * ncu, cdiv(nchunks, wpb)));
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(wpb * WAVE), shm, s, order, cstart, nchunks,
-                       &ss->band_ticket[band], lu.rowptr, lu.col, lu.diag, lu.src, aval, lu.val,
+                       ss->band_stream[band], std::min(TICKET_STREAMS, grid), lu.rowptr, lu.col,
+                       lu.diag, lu.src, aval, lu.val,
                        ready, ss, stall, cap, c0, moff, map, luA, pbnd, st, perturb_rel);
   };
   // waves per block: the preference if its LDS fits in 64 KiB, else the

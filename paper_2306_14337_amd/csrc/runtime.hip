@@ -97,6 +97,11 @@ struct kkt_ctx {
   int* ref_moff = nullptr;
   unsigned short* ref_map = nullptr;
   int64_t ref_map_entries = 0;
+  // short-row bands (launch_refactor_flat): per-row flag for the packed map
+  // entries and the per-entry list bounds
+  bool band_flat[REF_MAX_BANDS] = {};
+  unsigned char* ref_flat = nullptr;
+  int2* ref_fl = nullptr;
   int nbands = 0;
   int band_chunk_lo[REF_MAX_BANDS] = {}, band_nchunks[REF_MAX_BANDS] = {},
       band_cap[REF_MAX_BANDS] = {};
@@ -571,6 +576,7 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
       o.solve_chain < -1 || o.solve_chain > SN_KMAX || o.refactor_map < -1 || o.refactor_map > 0 ||
       o.refactor_crit_height < -1 || o.refactor_waves_per_cu < 0 || o.refine < 0 || o.refine > 1 ||
       o.auto_reanalyze < 0 || o.auto_reanalyze > 1 || o.solve_jacobi_sweeps < 0 ||
+      o.refactor_short_rows < -1 || o.refactor_short_rows > 0 ||
       !(o.pivot_perturb_rel >= 0.0 && o.pivot_perturb_rel < 1.0))
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
@@ -937,6 +943,9 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     h->tail_c0 = n - h->tail_s;
     h->tail_S = (h->tail_s + DLU_NB - 1) / DLU_NB * DLU_NB;
   }
+  // rows of the short-row bands (packed update maps, launch_refactor_flat)
+  std::vector<uint8_t> flat_row;
+  for (bool& f : h->band_flat) f = false;
   // refactorization bands: a row's band is set by its length (LDS staging
   // size, hence rows in flight per CU) and raised to the band of any row it
   // depends on; each band is one launch.  Within a band rows go by level of
@@ -1013,10 +1022,12 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     std::vector<int32_t> order, cst;
     order.reserve(n);
     h->nbands = 0;
+    flat_row.assign(n, 0);
     for (int b = 0; b < REF_MAX_BANDS - 1; b++) {
       const int lo = (int)order.size();
       const int clo = (int)cst.size();
       int mx = 0;
+      bool short_ok = true;  // rows of <= 256 entries, none of the dense block
       // rows on long chains (height >= hcrit) first: the set is closed under
       // dependencies (a row's dependency has a larger height), so this stays
       // a topological order, and those rows start before the wide levels of
@@ -1026,9 +1037,14 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
           if (band[i] == b && !triv[i] && (height[i] >= hcrit) == (part == 0)) {
             order.push_back(i);
             mx = std::max(mx, A.lu_rowptr[i + 1] - A.lu_rowptr[i]);
+            if (i >= c0) short_ok = false;
           }
       const int hi = (int)order.size();
       if (hi == lo) continue;
+      short_ok = short_ok && mx <= 256;
+      h->band_flat[h->nbands] = short_ok;
+      if (short_ok)
+        for (int t = lo; t < hi; t++) flat_row[order[t]] = 1;
       for (int t = lo; t < hi;) {
         int e = t;
         const bool crit = height[order[t]] >= hcrit;
@@ -1054,6 +1070,8 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   h->ref_moff = nullptr;
   h->ref_map = nullptr;
   h->ref_map_entries = 0;
+  h->ref_fl = nullptr;
+  h->ref_flat = nullptr;
   if (h->syncfree && h->opt.refactor_map >= 0) {
     std::vector<int32_t> moff(A.lu_col.size(), 0);
     int64_t tot = 0;
@@ -1073,8 +1091,32 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
         return ks;
       }
       h->ref_map_entries = tot;
+      // short-row bands: per L entry (list offset of the pivot's updates, its
+      // U row start minus that offset), at the diagonal (list length, 0)
+      bool any_flat = false;
+      if (h->light && h->opt.refactor_short_rows == 0)
+        for (int b = 0; b < h->nbands; b++) any_flat = any_flat || h->band_flat[b];
+      if (any_flat) {
+        std::vector<int2> fl(A.lu_col.size(), make_int2(0, 0));
+        for (int32_t i = 0; i < n; i++) {
+          if (!flat_row[i]) continue;
+          const int32_t rs = A.lu_rowptr[i], d = A.diag[i];
+          int32_t len_list = 0;
+          for (int32_t q = rs; q < d; q++) {
+            const int32_t k = A.lu_col[q];
+            const int32_t fo = moff[q] - moff[rs];
+            fl[q] = make_int2(fo, A.diag[k] + 1 - fo);
+            len_list = fo + (A.lu_rowptr[k + 1] - A.diag[k] - 1);
+          }
+          fl[d] = make_int2(len_list, 0);
+        }
+        UP(h->ref_fl, fl);
+        UP(h->ref_flat, flat_row);
+      }
     }
   }
+  if (!h->ref_fl)
+    for (bool& f : h->band_flat) f = false;
   h->luA = nullptr;
   h->a2lu = nullptr;
   h->ref_pbnd = nullptr;
@@ -1356,7 +1398,7 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   launch_copy_anorm(n, h->a_rowptr, h->a_col, h->aval, h->aval, h->st, nullptr, nullptr,
                     h->rowabs);
   launch_pivot_stats(view(h), h->st, h->opt.tiny_pivot_rel, nullptr);
-  if (h->ref_map) launch_build_refmap(view(h), h->ref_moff, h->ref_map, nullptr);
+  if (h->ref_map) launch_build_refmap(view(h), h->ref_moff, h->ref_map, h->ref_flat, nullptr);
   // the dense block's copy of the pivoting pass's factors (the solves read it)
   if (h->tail_s > 0)
     launch_tail_scatter(view(h), h->tail_c0, h->tail_s, h->tail_S, h->tail_T, nullptr);
@@ -1446,7 +1488,14 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
     launch_refactor_trivial(lu, h->ref_triv, h->ref_ntriv, h->aval, h->ready_ref, h->ss, s,
                             h->luA, h->tail_c0, h->st, h->opt.pivot_perturb_rel);
     for (int b = 0; b < h->nbands; b++)
-      if (!launch_refactor_syncfree(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
+      if (h->band_flat[b]) {
+        if (!launch_refactor_flat(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
+                                  h->band_nchunks[b], b, h->band_cap[b], h->ss, &h->st->stall,
+                                  h->ref_moff, h->ref_map, h->luA, h->ref_fl,
+                                  h->opt.refactor_waves_per_cu, h->st, h->opt.pivot_perturb_rel,
+                                  s))
+          return fail(h, KKT_ERR_DEVICE, "short-row refactorization not launchable");
+      } else if (!launch_refactor_syncfree(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
                                     h->band_nchunks[b], b, h->band_cap[b], h->aval, h->ready_ref,
                                     h->ss, &h->st->stall, h->light,
                                     h->opt.refactor_waves_per_block, h->tail_c0, h->ref_moff,

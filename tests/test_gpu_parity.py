@@ -90,12 +90,15 @@ def test_sequence_refactor_solve(B, seed, steps, schedule):
         assert info["converged"] == 1
 
 
+@pytest.mark.parametrize("variant", [dict(refactor_map=-1), dict(refactor_short_rows=-1)],
+                         ids=["binary-search", "short-rows-pivot-by-pivot"])
 @pytest.mark.parametrize("B,seed", [(100, 101), (2000, 104)])
-def test_refactor_without_update_maps_bitwise(B, seed):
-    # binary search of each update's column instead of the precomputed map
-    print(f"case B={B} seed={seed} refactor_map=-1", flush=True)
+def test_refactor_kernel_variants_bitwise(B, seed, variant):
+    # binary search of each update's column instead of the precomputed map;
+    # the short-row band pivot by pivot instead of as one list of updates
+    print(f"case B={B} seed={seed} {variant}", flush=True)
     pat, seq = kktgen.make_sequence(B, seed, 2)
-    s = binding.KKTSolver(schedule=2, sync_mode=2, refactor_map=-1)
+    s = binding.KKTSolver(schedule=2, sync_mode=2, **variant)
     s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
     ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, seq[0][0], tau=1e-10)
     for vals, b in seq:
