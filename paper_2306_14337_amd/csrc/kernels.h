@@ -41,6 +41,8 @@ struct SyncState {
   // refactorization band b, stream s: band_stream[b][s * TICKET_STRIDE]
   // (reset with slot 0)
   alignas(128) unsigned int band_stream[REF_MAX_BANDS][TICKET_STREAMS * TICKET_STRIDE];
+  // chain-blocked solves of slot k, stream s: slot_stream[k][s * TICKET_STRIDE]
+  alignas(128) unsigned int slot_stream[4][TICKET_STREAMS * TICKET_STRIDE];
 };
 
 // Work chunks of a triangular-solve schedule: chunk c covers rows

@@ -681,6 +681,7 @@ __device__ __forceinline__ void sync_prep(SyncState* ss, int mask) {
     if (mask & (1 << k)) {
       ss->ticket[k] = 0u;
       ss->epoch[k] = ss->epoch[k] + 1;
+      for (int t = 0; t < TICKET_STREAMS; t++) ss->slot_stream[k][t * TICKET_STRIDE] = 0u;
       if (k == 0)
         for (int b = 0; b < REF_MAX_BANDS; b++)
           for (int t = 0; t < TICKET_STREAMS; t++) ss->band_stream[b][t * TICKET_STRIDE] = 0u;
@@ -1059,14 +1060,13 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(
     const int* __restrict__ split, const int* __restrict__ rowptr, const int* __restrict__ col,
     const int* __restrict__ diag, const int* __restrict__ tptr, const int* __restrict__ trow,
     const int* __restrict__ tpos, const double* __restrict__ val, const double* __restrict__ c,
-    double* y, SyncState* ss, int slot, int* stall) {
+    double* y, SyncState* ss, int slot, int nstreams, int* stall) {
   __shared__ double tri_all[256 / WAVE][SN_KMAX * SN_KMAX];
   const int lane = threadIdx.x % WAVE;
   double* tri = tri_all[threadIdx.x / WAVE];
-  unsigned int* ticket = &ss->ticket[slot];
   for (;;) {
-    const unsigned int tk = bcast0(atomicAdd(ticket, lane == 0 ? 1u : 0u));
-    if (tk >= (unsigned int)nchunks) break;
+    const int tk = next_chunk(ss->slot_stream[slot], nstreams, lane);
+    if (tk >= nchunks) break;
     const int meta = ch_meta[tk];
     const int k = meta & 0xff, lg = (meta >> 8) & 0xf;
     const bool chain = (meta >> 16) != 0;
@@ -2395,12 +2395,36 @@ void launch_trisolve_sn(int mode, int nr, const LUView& lu, const SnSched& sn, c
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
     if (ncu <= 0) ncu = 256;
   }
-  const int grid = std::max(1, std::min(ncu * sn.blocks_per_cu, cdiv(sn.nchunks, 4)));
+  // every workgroup resident at once (the ticket streams need a running
+  // workgroup each): at most the occupancy limit per CU
+  static int occ[4][3] = {};
+  const int ri = nr == 1 ? 0 : (nr <= 4 ? 1 : 2);
+  int& nb = occ[mode & 3][ri];
+  if (nb == 0) {
+    auto probe = [&](const void* k) {
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) != hipSuccess || nb <= 0)
+        nb = 1;
+    };
+#define SN_OCC(M, R) probe(reinterpret_cast<const void*>(&k_trisolve_sn<M, R>))
+#define SN_OCC_R(M) \
+  if (ri == 0) SN_OCC(M, 1); else if (ri == 1) SN_OCC(M, 4); else SN_OCC(M, SN_MAX_RHS)
+    switch (mode) {
+      case 0: SN_OCC_R(0); break;
+      case 1: SN_OCC_R(1); break;
+      case 2: SN_OCC_R(2); break;
+      default: SN_OCC_R(3); break;
+    }
+#undef SN_OCC_R
+#undef SN_OCC
+  }
+  const int grid =
+      std::max(1, std::min(ncu * std::min(sn.blocks_per_cu, nb), cdiv(sn.nchunks, 4)));
+  const int nstreams = std::min(TICKET_STREAMS, grid);
   const int ld = lu.n + 1;
 #define SN_LAUNCH(M, R)                                                                         \
   hipLaunchKernelGGL((k_trisolve_sn<M, R>), dim3(grid), dim3(256), 0, s, lu.n, nr, ld,          \
                      sn.nchunks, sn.start, sn.meta, sn.base, sn.rows, sn.split, lu.rowptr,       \
-                     lu.col, lu.diag, tptr, trow, tpos, lu.val, c, y, ss, slot, stall)
+                     lu.col, lu.diag, tptr, trow, tpos, lu.val, c, y, ss, slot, nstreams, stall)
 #define SN_MODES(R)                 \
   switch (mode) {                   \
     case 0: SN_LAUNCH(0, R); break; \
