@@ -125,6 +125,12 @@ typedef struct {
                                copysign(pivot_perturb_rel * ||A||_inf, u_kk) (warning
                                KKT_WARN_PERTURBED_PIVOT; refinement corrects the solve);
                                0 = off (default), < 1 */
+  int32_t refactor_long_rows; /* dependency-driven refactorization with device-coherent
+                                 publication and update maps: 0 = rows of the other bands are
+                                 refactorized by a workgroup each, its waves taking the pivot
+                                 steps in turn with the next pivot rows already in flight
+                                 (default), -1 = one wave per row */
+  int32_t reserved3;
 } kkt_options;
 
 typedef struct {

@@ -404,13 +404,32 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
             ready_upto = t + first_bad;
             break;
           }
-          // entry t itself is missing: poll that one value or flag (a single
-          // request per wave) until it is set, then re-check the batch
+          // entry t itself is missing
           bool go = true;
           if (LIGHT) {
-            const int dpt = sk[t].x;
-            while (go && bcast0(is_sentinel(ld_coh(val + dpt)) ? 1u : 0u) != 0u)
+            // poll the pivot's diagonal together with the first 64 entries
+            // of its U row: once none of them reads as the sentinel they are
+            // the values of this pivot step, so the step starts without a
+            // re-check or a reload (on a chain of rows each waiting for the
+            // one before, this wait is the critical path)
+            const int2 kw = sk[t];
+            const int q = kw.x + 1 + lane;
+            if (MAPPED) mo = moff[rs + t];
+            j0 = -1;
+            if (q < kw.y) j0 = MAPPED ? (int)map[mo + lane] : col[q];
+            for (;;) {
+              ukk = ld_coh(val + kw.x);
+              u0 = q < kw.y ? ld_coh(val + q) : 0.0;
+              const bool miss = is_sentinel(ukk) || (q < kw.y && is_sentinel(u0));
+              if (__ballot(miss) == 0) break;
               go = bcast0(keep_waiting(&spins, stall) ? 1u : 0u) != 0u;
+              if (!go) break;
+            }
+            if (go) {
+              ready_upto = t + 1;
+              have = true;
+              break;
+            }
           } else {
             const int kt = sc[t];
             while (go && bcast0((unsigned int)ld_flag(ready + kt)) != (unsigned int)epoch)
@@ -2109,6 +2128,145 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
   }
 }
 
+
+// Rows of a band by workgroups: one workgroup of WPR waves per row.  The
+// row's pivot steps stay one at a time in ascending order (a workgroup barrier
+// between two steps), but wave w owns the steps t = w, w + WPR, ...: right
+// after its step it loads the pivot, the first R * 64 U entries and their
+// target positions of its next step, so while the other waves apply theirs
+// those loads are in flight, and a step costs about one pass over LDS rather
+// than a memory round trip.  Values that still read as the sentinel are
+// polled again before use (the pivot row was not finished yet).
+template <int WPR>
+__global__ __launch_bounds__(WPR* WAVE) void k_refactor_wg(
+    const int* __restrict__ order, const int* __restrict__ cstart, int nchunks,
+    unsigned int* tickets, int nstreams, const int* __restrict__ rowptr,
+    const int* __restrict__ col, const int* __restrict__ diag, double* val, int* stall, int cap,
+    int c0, const int* __restrict__ moff, const unsigned short* __restrict__ map,
+    const double* __restrict__ luA, const int2* __restrict__ pbnd, DevStats* st, double prel) {
+  constexpr int R = 4;  // prefetched chunks of 64 U entries per pivot step
+  constexpr int NT = WPR * WAVE;
+  extern __shared__ double smem_d[];
+  __shared__ int s_tk;
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  // LDS: values (cap doubles), pivot-row bounds (cap int2), columns and
+  // update-map offsets (cap ints each)
+  double* sv = smem_d;
+  int2* sk = reinterpret_cast<int2*>(smem_d + cap);
+  int* sc = reinterpret_cast<int*>(sk + cap);
+  int* sm = sc + cap;
+  const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm) : 0.0;
+  for (;;) {
+    if (wave == 0) {
+      const int tk = next_chunk(tickets, nstreams, lane);
+      s_tk = tk;  // every lane of wave 0 writes the same value
+    }
+    __syncthreads();
+    const int tk = s_tk;
+    __syncthreads();  // read by every wave before the next fetch overwrites it
+    if (tk >= nchunks) break;
+    const int r_end = cstart[tk + 1];
+    for (int r = cstart[tk]; r < r_end; r++) {
+      const int i = order[r];
+      const int rs = rowptr[i], len = rowptr[i + 1] - rs;
+      int dl = diag[i] - rs;
+      int spins = 0;
+      for (int t = threadIdx.x; t < len; t += NT) {
+        sc[t] = col[rs + t];
+        sv[t] = luA[rs + t];
+      }
+      for (int t = threadIdx.x; t < dl; t += NT) {
+        sk[t] = pbnd[rs + t];
+        sm[t] = moff[rs + t];
+      }
+      __syncthreads();
+      // rows of the dense trailing block take only the pivots before it here
+      if (i >= c0) dl = lower_bound_i(sc, 0, dl, c0);
+      double ukk = 0.0, u[R];
+      int p[R];
+      auto load = [&](int t) {
+        const int2 kk = sk[t];
+        const int mo = sm[t], ub = kk.x + 1;
+        ukk = ld_coh(val + kk.x);
+#pragma unroll
+        for (int z = 0; z < R; z++) {
+          const int q = ub + lane + z * WAVE;
+          p[z] = -1;
+          u[z] = 0.0;
+          if (q < kk.y) {
+            p[z] = map[mo + (q - ub)];
+            u[z] = ld_coh(val + q);
+          }
+        }
+      };
+      if (wave < dl) load(wave);
+      for (int t = 0; t < dl; t++) {
+        if (t % WPR == wave) {
+          const int2 kk = sk[t];
+          const int ub = kk.x + 1;
+          // values loaded before the pivot row was finished: poll them again
+          for (;;) {
+            bool miss = is_sentinel(ukk);
+#pragma unroll
+            for (int z = 0; z < R; z++) miss = miss || (p[z] >= 0 && is_sentinel(u[z]));
+            if (__ballot(miss) == 0) break;
+            if (bcast0(keep_waiting(&spins, stall) ? 1u : 0u) == 0u) break;
+            if (is_sentinel(ukk)) ukk = ld_coh(val + kk.x);
+#pragma unroll
+            for (int z = 0; z < R; z++)
+              if (p[z] >= 0 && is_sentinel(u[z])) u[z] = ld_coh(val + ub + lane + z * WAVE);
+          }
+          const double lik = sv[t] / ukk;
+#pragma unroll
+          for (int z = 0; z < R; z++)
+            if (p[z] >= 0) sv[p[z]] = __builtin_fma(-lik, u[z], sv[p[z]]);
+          // the rest of a longer U row: four loads of each kind in flight per lane
+          const int mo = sm[t];
+          for (int q0 = ub + R * WAVE + lane; q0 < kk.y; q0 += 4 * WAVE) {
+            double v[4];
+            int pq[4];
+#pragma unroll
+            for (int z = 0; z < 4; z++) {
+              const int q = q0 + z * WAVE;
+              pq[z] = -1;
+              v[z] = 0.0;
+              if (q < kk.y) {
+                pq[z] = map[mo + (q - ub)];
+                v[z] = ld_coh(val + q);
+              }
+            }
+#pragma unroll
+            for (int z = 0; z < 4; z++) {
+              if (pq[z] >= 0)
+                while (is_sentinel(v[z]) && keep_waiting(&spins, stall))
+                  v[z] = ld_coh(val + q0 + z * WAVE);
+              if (pq[z] >= 0) sv[pq[z]] = __builtin_fma(-lik, v[z], sv[pq[z]]);
+            }
+          }
+          wave_sync();
+          sv[t] = lik;  // every lane writes the same value
+          wave_sync();
+          if (t + WPR < dl) load(t + WPR);
+        }
+        __syncthreads();
+      }
+      // static pivoting of this row's pivot (rows of the dense block: there)
+      if (thr > 0.0 && i < c0) {
+        const int dr = diag[i] - rs;
+        const double d = sv[dr];
+        __syncthreads();
+        if (fabs(d) < thr) {
+          sv[dr] = perturb_pivot(d, thr);  // every thread writes the same value
+          st->perturbed = 1;
+        }
+        __syncthreads();
+      }
+      for (int t = threadIdx.x; t < len; t += NT) st_coh(val + rs + t, sv[t]);
+      __syncthreads();  // the staging area is reused by the next row
+    }
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2171,6 +2329,37 @@ void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map,
                          const unsigned char* flat, hipStream_t s) {
   hipLaunchKernelGGL(k_build_refmap, dim3(std::max(1, std::min(cdiv(lu.n, 4), 4096))), dim3(256),
                      0, s, lu.n, lu.rowptr, lu.col, lu.diag, moff, map, flat);
+}
+
+bool launch_refactor_wg(const LUView& lu, const int* order, const int* cstart, int nchunks,
+                        int band, int cap, SyncState* ss, int* stall, int c0, const int* moff,
+                        const unsigned short* map, const double* luA, const int2* pbnd,
+                        int max_waves_per_cu, DevStats* st, double perturb_rel, hipStream_t s) {
+  if (nchunks <= 0) return true;
+  if (band < 0 || band >= REF_MAX_BANDS || !moff || !map || !luA || !pbnd) return false;
+  cap = (cap + 1) & ~1;
+  constexpr int WPR = 4;
+  const size_t shm = (size_t)cap * (sizeof(double) + sizeof(int2) + 2 * sizeof(int));
+  if (shm > 64 * 1024) return false;
+  static int ncu = 0;
+  if (ncu == 0) {
+    int d = 0;
+    (void)hipGetDevice(&d);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
+    if (ncu <= 0) ncu = 256;
+  }
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_refactor_wg<WPR>, WPR * WAVE, shm) !=
+          hipSuccess ||
+      nb <= 0)
+    nb = 1;
+  if (max_waves_per_cu > 0) nb = std::max(1, std::min(nb, max_waves_per_cu / WPR));
+  const int grid = std::max(1, std::min(nb * ncu, nchunks));
+  hipLaunchKernelGGL(k_refactor_wg<WPR>, dim3(grid), dim3(WPR * WAVE), shm, s, order, cstart,
+                     nchunks, ss->band_stream[band], std::min(TICKET_STREAMS, grid), lu.rowptr,
+                     lu.col, lu.diag, lu.val, stall, cap, c0, moff, map, luA, pbnd, st,
+                     perturb_rel);
+  return true;
 }
 
 bool launch_refactor_flat(const LUView& lu, const int* order, const int* cstart, int nchunks,

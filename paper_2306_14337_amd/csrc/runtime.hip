@@ -576,7 +576,8 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
       o.solve_chain < -1 || o.solve_chain > SN_KMAX || o.refactor_map < -1 || o.refactor_map > 0 ||
       o.refactor_crit_height < -1 || o.refactor_waves_per_cu < 0 || o.refine < 0 || o.refine > 1 ||
       o.auto_reanalyze < 0 || o.auto_reanalyze > 1 || o.solve_jacobi_sweeps < 0 ||
-      o.refactor_short_rows < -1 || o.refactor_short_rows > 0 ||
+      o.refactor_short_rows < -1 || o.refactor_short_rows > 0 || o.refactor_long_rows < -1 ||
+      o.refactor_long_rows > 0 ||
       !(o.pivot_perturb_rel >= 0.0 && o.pivot_perturb_rel < 1.0))
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
@@ -591,8 +592,8 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
 
 kkt_status kkt_destroy(kkt_handle h) {
   if (!h) return KKT_ERR_INVALID_ARG;
-  hipSetDevice(h->opt.device);
-  hipDeviceSynchronize();
+  (void)hipSetDevice(h->opt.device);
+  (void)hipDeviceSynchronize();
   free_device(h);
   delete h;
   return KKT_OK;
@@ -1495,6 +1496,15 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
                                   h->opt.refactor_waves_per_cu, h->st, h->opt.pivot_perturb_rel,
                                   s))
           return fail(h, KKT_ERR_DEVICE, "short-row refactorization not launchable");
+      } else if (h->light && h->ref_map && h->luA && h->ref_pbnd &&
+                 h->opt.refactor_long_rows == 0 &&
+                 (size_t)((h->band_cap[b] + 1) & ~1) * 24 <= 64 * 1024) {
+        if (!launch_refactor_wg(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
+                                h->band_nchunks[b], b, h->band_cap[b], h->ss, &h->st->stall,
+                                h->tail_c0, h->ref_moff, h->ref_map, h->luA, h->ref_pbnd,
+                                h->opt.refactor_waves_per_cu, h->st, h->opt.pivot_perturb_rel,
+                                s))
+          return fail(h, KKT_ERR_DEVICE, "long-row refactorization not launchable");
       } else if (!launch_refactor_syncfree(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
                                     h->band_nchunks[b], b, h->band_cap[b], h->aval, h->ready_ref,
                                     h->ss, &h->st->stall, h->light,

@@ -187,7 +187,7 @@ def test_singular_warning_matches_oracle():
     ("dense_tail", -2), ("dense_tail", 2049), ("solve_blocks_per_cu", 9),
     ("solve_chain", 33), ("solve_chain", -2), ("refactor_map", 1), ("refactor_map", -2),
     ("refine", 2), ("refactor_crit_height", -2), ("refactor_short_rows", 1),
-    ("refactor_short_rows", -2),
+    ("refactor_short_rows", -2), ("refactor_long_rows", 1), ("refactor_long_rows", -2),
     ("solve_entries_per_lane", 65), ("sync_mode", 3), ("fgmres_restart", 31),
 ])
 def test_create_rejects_bad_options(field, value):

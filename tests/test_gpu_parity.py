@@ -90,12 +90,16 @@ def test_sequence_refactor_solve(B, seed, steps, schedule):
         assert info["converged"] == 1
 
 
-@pytest.mark.parametrize("variant", [dict(refactor_map=-1), dict(refactor_short_rows=-1)],
-                         ids=["binary-search", "short-rows-pivot-by-pivot"])
+@pytest.mark.parametrize("variant", [dict(refactor_map=-1), dict(refactor_short_rows=-1),
+                                     dict(refactor_long_rows=-1),
+                                     dict(refactor_short_rows=-1, refactor_long_rows=-1)],
+                         ids=["binary-search", "short-rows-pivot-by-pivot", "long-rows-wave-per-row",
+                              "wave-per-row-everywhere"])
 @pytest.mark.parametrize("B,seed", [(100, 101), (2000, 104)])
 def test_refactor_kernel_variants_bitwise(B, seed, variant):
     # binary search of each update's column instead of the precomputed map;
-    # the short-row band pivot by pivot instead of as one list of updates
+    # the short-row band pivot by pivot instead of as one list of updates;
+    # one wave per long row instead of a workgroup
     print(f"case B={B} seed={seed} {variant}", flush=True)
     pat, seq = kktgen.make_sequence(B, seed, 2)
     s = binding.KKTSolver(schedule=2, sync_mode=2, **variant)
