@@ -126,10 +126,10 @@ typedef struct {
                                KKT_WARN_PERTURBED_PIVOT; refinement corrects the solve);
                                0 = off (default), < 1 */
   int32_t refactor_long_rows; /* dependency-driven refactorization with device-coherent
-                                 publication and update maps: 0 = rows of the other bands are
-                                 refactorized by a workgroup each, its waves taking the pivot
-                                 steps in turn with the next pivot rows already in flight
-                                 (default), -1 = one wave per row */
+                                 publication and update maps, rows outside the short-row band:
+                                 0 = the pivot rows of the next steps are loaded into registers
+                                 ahead of their steps and only the row's values are staged in LDS
+                                 (default), -1 = each step loads its pivot row when it starts */
   int32_t reserved3;
 } kkt_options;
 

@@ -152,12 +152,13 @@ void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map,
 // Any band: one workgroup of several waves per row, the pivot steps taken by
 // the waves in turn (each has its next pivot row in flight while the others
 // apply theirs).  Device-coherent value-as-flag publication, update maps, A in
-// factor order (luA) and pivot-row bounds (pbnd) required; cap >= the band's
-// longest row.
+// factor order (luA) and pivot-row bounds (pbnd) required; dlc[i] = pivots of
+// row i before the dense trailing block (c0); cap >= the band's longest row.
 bool launch_refactor_wg(const LUView& lu, const int* order, const int* cstart, int nchunks,
-                        int band, int cap, SyncState* ss, int* stall, int c0, const int* moff,
-                        const unsigned short* map, const double* luA, const int2* pbnd,
-                        int max_waves_per_cu, DevStats* st, double perturb_rel, hipStream_t s);
+                        int band, int cap, SyncState* ss, int* stall, int c0, const int* dlc,
+                        const int* moff, const unsigned short* map, const double* luA,
+                        const int2* pbnd, int max_waves_per_cu, DevStats* st, double perturb_rel,
+                        hipStream_t s);
 
 // A short-row band: one wave per row, every row of the band at most 256
 // entries, no row of the dense block.  fl[q] for the

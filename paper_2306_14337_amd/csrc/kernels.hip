@@ -15,6 +15,16 @@ namespace kktlu {
 namespace {
 
 constexpr int WAVE = 64;
+// k_refactor_wg: waves per row and register buffers per wave (pivot steps in
+// flight per row = their product).  Measured at 70k buses (refactorization
+// ms): 1 x 2 3.20, 1 x 3 3.21, 2 x 1 3.28, 4 x 1 3.66, 8 x 1 4.16: more rows
+// in flight beat more waves per row.
+#ifndef KKTLU_WG_WPR
+#define KKTLU_WG_WPR 1
+#endif
+#ifndef KKTLU_WG_DEPTH
+#define KKTLU_WG_DEPTH 2
+#endif
 constexpr int RG_TRIV = 8;  // lanes per row of k_refactor_trivial
 
 __device__ __forceinline__ void wave_sync() {
@@ -2129,33 +2139,44 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
 }
 
 
-// Rows of a band by workgroups: one workgroup of WPR waves per row.  The
-// row's pivot steps stay one at a time in ascending order (a workgroup barrier
-// between two steps), but wave w owns the steps t = w, w + WPR, ...: right
-// after its step it loads the pivot, the first R * 64 U entries and their
-// target positions of its next step, so while the other waves apply theirs
-// those loads are in flight, and a step costs about one pass over LDS rather
-// than a memory round trip.  Values that still read as the sentinel are
-// polled again before use (the pivot row was not finished yet).
-template <int WPR>
+// Rows of a band by workgroups: one workgroup of WPR waves per row (default
+// one).  The row's pivot steps stay one at a time in ascending order (a
+// workgroup barrier between two steps), but wave w owns the steps t = w,
+// w + WPR, ...: right
+// after a step it loads the pivot, the first R * 64 U entries and their
+// target positions of the step WPR * DEPTH later (DEPTH register buffers per
+// wave), so while the other waves apply theirs those loads are in flight, and
+// a step costs about one pass over LDS rather than a memory round trip.
+// Values that still read as the sentinel are polled again before use (the
+// pivot row was not finished yet).  Only the row's values live in LDS (8 bytes
+// per entry, so many long rows fit on a CU at once); each wave keeps the
+// pivot-row bounds and update-map offsets of its next 64 steps in registers,
+// one step per lane.  dlc[i]: pivots of row i in this phase (those before the
+// dense trailing block).
+template <int WPR, int DEPTH>
 __global__ __launch_bounds__(WPR* WAVE) void k_refactor_wg(
     const int* __restrict__ order, const int* __restrict__ cstart, int nchunks,
     unsigned int* tickets, int nstreams, const int* __restrict__ rowptr,
-    const int* __restrict__ col, const int* __restrict__ diag, double* val, int* stall, int cap,
-    int c0, const int* __restrict__ moff, const unsigned short* __restrict__ map,
-    const double* __restrict__ luA, const int2* __restrict__ pbnd, DevStats* st, double prel) {
+    const int* __restrict__ dlc, double* val, int* stall, const int* __restrict__ moff,
+    const unsigned short* __restrict__ map, const double* __restrict__ luA,
+    const int2* __restrict__ pbnd, const int* __restrict__ diag, int c0, DevStats* st,
+    double prel) {
   constexpr int R = 4;  // prefetched chunks of 64 U entries per pivot step
   constexpr int NT = WPR * WAVE;
+  constexpr int AHEAD = WPR * DEPTH;
   extern __shared__ double smem_d[];
   __shared__ int s_tk;
-  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-  // LDS: values (cap doubles), pivot-row bounds (cap int2), columns and
-  // update-map offsets (cap ints each)
-  double* sv = smem_d;
-  int2* sk = reinterpret_cast<int2*>(smem_d + cap);
-  int* sc = reinterpret_cast<int*>(sk + cap);
-  int* sm = sc + cap;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+  const int lane = threadIdx.x % WAVE;
+  double* sv = smem_d;  // the row's values
   const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm) : 0.0;
+  struct Step {
+    double ukk;
+    double u[R];
+    int p[R];
+    int2 kk;  // pivot row: diagonal position, row end
+    int mo;   // update-map offset
+  };
   for (;;) {
     if (wave == 0) {
       const int tk = next_chunk(tickets, nstreams, lane);
@@ -2169,86 +2190,99 @@ __global__ __launch_bounds__(WPR* WAVE) void k_refactor_wg(
     for (int r = cstart[tk]; r < r_end; r++) {
       const int i = order[r];
       const int rs = rowptr[i], len = rowptr[i + 1] - rs;
-      int dl = diag[i] - rs;
+      const int dl = dlc[i];
       int spins = 0;
-      for (int t = threadIdx.x; t < len; t += NT) {
-        sc[t] = col[rs + t];
-        sv[t] = luA[rs + t];
-      }
-      for (int t = threadIdx.x; t < dl; t += NT) {
-        sk[t] = pbnd[rs + t];
-        sm[t] = moff[rs + t];
-      }
-      __syncthreads();
-      // rows of the dense trailing block take only the pivots before it here
-      if (i >= c0) dl = lower_bound_i(sc, 0, dl, c0);
-      double ukk = 0.0, u[R];
-      int p[R];
-      auto load = [&](int t) {
-        const int2 kk = sk[t];
-        const int mo = sm[t], ub = kk.x + 1;
-        ukk = ld_coh(val + kk.x);
+      for (int t = threadIdx.x; t < len; t += NT) sv[t] = luA[rs + t];
+      // this wave's steps w + WPR * (64 * ib + lane): pivot-row bounds, map offsets
+      int ib = -1, ib_mo = 0;
+      int2 ib_kk = make_int2(0, 0);
+      auto load = [&](Step& b, int t) {
+        const int own = (t - wave) / WPR;
+        if ((own >> 6) != ib) {
+          ib = own >> 6;
+          const int tq = wave + WPR * ((ib << 6) + lane);
+          ib_kk = tq < dl ? pbnd[rs + tq] : make_int2(0, 0);
+          ib_mo = tq < dl ? moff[rs + tq] : 0;
+        }
+        const int l = own & (WAVE - 1);
+        b.kk = make_int2(__builtin_amdgcn_readlane(ib_kk.x, l),
+                         __builtin_amdgcn_readlane(ib_kk.y, l));
+        b.mo = __builtin_amdgcn_readlane(ib_mo, l);
+        const int ub = b.kk.x + 1;
+        b.ukk = ld_coh(val + b.kk.x);
 #pragma unroll
         for (int z = 0; z < R; z++) {
           const int q = ub + lane + z * WAVE;
-          p[z] = -1;
-          u[z] = 0.0;
-          if (q < kk.y) {
-            p[z] = map[mo + (q - ub)];
-            u[z] = ld_coh(val + q);
+          b.p[z] = -1;
+          b.u[z] = 0.0;
+          if (q < b.kk.y) {
+            b.p[z] = map[b.mo + (q - ub)];
+            b.u[z] = ld_coh(val + q);
           }
         }
       };
-      if (wave < dl) load(wave);
-      for (int t = 0; t < dl; t++) {
-        if (t % WPR == wave) {
-          const int2 kk = sk[t];
-          const int ub = kk.x + 1;
-          // values loaded before the pivot row was finished: poll them again
-          for (;;) {
-            bool miss = is_sentinel(ukk);
+      auto step = [&](Step& b, int t) {
+        const int ub = b.kk.x + 1;
+        // values loaded before the pivot row was finished: poll them again
+        for (;;) {
+          bool miss = is_sentinel(b.ukk);
 #pragma unroll
-            for (int z = 0; z < R; z++) miss = miss || (p[z] >= 0 && is_sentinel(u[z]));
-            if (__ballot(miss) == 0) break;
-            if (bcast0(keep_waiting(&spins, stall) ? 1u : 0u) == 0u) break;
-            if (is_sentinel(ukk)) ukk = ld_coh(val + kk.x);
-#pragma unroll
-            for (int z = 0; z < R; z++)
-              if (p[z] >= 0 && is_sentinel(u[z])) u[z] = ld_coh(val + ub + lane + z * WAVE);
-          }
-          const double lik = sv[t] / ukk;
+          for (int z = 0; z < R; z++) miss = miss || (b.p[z] >= 0 && is_sentinel(b.u[z]));
+          if (__ballot(miss) == 0) break;
+          if (bcast0(keep_waiting(&spins, stall) ? 1u : 0u) == 0u) break;
+          if (is_sentinel(b.ukk)) b.ukk = ld_coh(val + b.kk.x);
 #pragma unroll
           for (int z = 0; z < R; z++)
-            if (p[z] >= 0) sv[p[z]] = __builtin_fma(-lik, u[z], sv[p[z]]);
-          // the rest of a longer U row: four loads of each kind in flight per lane
-          const int mo = sm[t];
-          for (int q0 = ub + R * WAVE + lane; q0 < kk.y; q0 += 4 * WAVE) {
-            double v[4];
-            int pq[4];
+            if (b.p[z] >= 0 && is_sentinel(b.u[z])) b.u[z] = ld_coh(val + ub + lane + z * WAVE);
+        }
+        const double lik = sv[t] / b.ukk;
 #pragma unroll
-            for (int z = 0; z < 4; z++) {
-              const int q = q0 + z * WAVE;
-              pq[z] = -1;
-              v[z] = 0.0;
-              if (q < kk.y) {
-                pq[z] = map[mo + (q - ub)];
-                v[z] = ld_coh(val + q);
-              }
-            }
+        for (int z = 0; z < R; z++)
+          if (b.p[z] >= 0) sv[b.p[z]] = __builtin_fma(-lik, b.u[z], sv[b.p[z]]);
+        // the rest of a longer U row: four loads of each kind in flight per lane
+        for (int q0 = ub + R * WAVE + lane; q0 < b.kk.y; q0 += 4 * WAVE) {
+          double v[4];
+          int pq[4];
 #pragma unroll
-            for (int z = 0; z < 4; z++) {
-              if (pq[z] >= 0)
-                while (is_sentinel(v[z]) && keep_waiting(&spins, stall))
-                  v[z] = ld_coh(val + q0 + z * WAVE);
-              if (pq[z] >= 0) sv[pq[z]] = __builtin_fma(-lik, v[z], sv[pq[z]]);
+          for (int z = 0; z < 4; z++) {
+            const int q = q0 + z * WAVE;
+            pq[z] = -1;
+            v[z] = 0.0;
+            if (q < b.kk.y) {
+              pq[z] = map[b.mo + (q - ub)];
+              v[z] = ld_coh(val + q);
             }
           }
-          wave_sync();
-          sv[t] = lik;  // every lane writes the same value
-          wave_sync();
-          if (t + WPR < dl) load(t + WPR);
+#pragma unroll
+          for (int z = 0; z < 4; z++) {
+            if (pq[z] >= 0)
+              while (is_sentinel(v[z]) && keep_waiting(&spins, stall))
+                v[z] = ld_coh(val + q0 + z * WAVE);
+            if (pq[z] >= 0) sv[pq[z]] = __builtin_fma(-lik, v[z], sv[pq[z]]);
+          }
         }
-        __syncthreads();
+        wave_sync();
+        sv[t] = lik;  // every lane writes the same value
+        wave_sync();
+      };
+      Step buf[DEPTH];
+#pragma unroll
+      for (int d = 0; d < DEPTH; d++)
+        if (wave + d * WPR < dl) load(buf[d], wave + d * WPR);
+      __syncthreads();  // the row's values are staged
+      for (int tb = 0; tb < dl; tb += AHEAD) {
+#pragma unroll
+        for (int d = 0; d < DEPTH; d++) {
+          for (int w = 0; w < WPR; w++) {
+            const int t = tb + d * WPR + w;
+            if (t >= dl) break;
+            if (w == wave) {
+              step(buf[d], t);
+              if (t + AHEAD < dl) load(buf[d], t + AHEAD);
+            }
+            __syncthreads();
+          }
+        }
       }
       // static pivoting of this row's pivot (rows of the dense block: there)
       if (thr > 0.0 && i < c0) {
@@ -2332,14 +2366,14 @@ void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map,
 }
 
 bool launch_refactor_wg(const LUView& lu, const int* order, const int* cstart, int nchunks,
-                        int band, int cap, SyncState* ss, int* stall, int c0, const int* moff,
-                        const unsigned short* map, const double* luA, const int2* pbnd,
-                        int max_waves_per_cu, DevStats* st, double perturb_rel, hipStream_t s) {
+                        int band, int cap, SyncState* ss, int* stall, int c0, const int* dlc,
+                        const int* moff, const unsigned short* map, const double* luA,
+                        const int2* pbnd, int max_waves_per_cu, DevStats* st, double perturb_rel,
+                        hipStream_t s) {
   if (nchunks <= 0) return true;
-  if (band < 0 || band >= REF_MAX_BANDS || !moff || !map || !luA || !pbnd) return false;
-  cap = (cap + 1) & ~1;
-  constexpr int WPR = 4;
-  const size_t shm = (size_t)cap * (sizeof(double) + sizeof(int2) + 2 * sizeof(int));
+  if (band < 0 || band >= REF_MAX_BANDS || !dlc || !moff || !map || !luA || !pbnd) return false;
+  constexpr int WPR = KKTLU_WG_WPR, DEPTH = KKTLU_WG_DEPTH;
+  const size_t shm = (size_t)std::max(cap, 1) * sizeof(double);
   if (shm > 64 * 1024) return false;
   static int ncu = 0;
   if (ncu == 0) {
@@ -2349,15 +2383,15 @@ bool launch_refactor_wg(const LUView& lu, const int* order, const int* cstart, i
     if (ncu <= 0) ncu = 256;
   }
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_refactor_wg<WPR>, WPR * WAVE, shm) !=
-          hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_refactor_wg<WPR, DEPTH>, WPR * WAVE,
+                                                   shm) != hipSuccess ||
       nb <= 0)
     nb = 1;
   if (max_waves_per_cu > 0) nb = std::max(1, std::min(nb, max_waves_per_cu / WPR));
   const int grid = std::max(1, std::min(nb * ncu, nchunks));
-  hipLaunchKernelGGL(k_refactor_wg<WPR>, dim3(grid), dim3(WPR * WAVE), shm, s, order, cstart,
-                     nchunks, ss->band_stream[band], std::min(TICKET_STREAMS, grid), lu.rowptr,
-                     lu.col, lu.diag, lu.val, stall, cap, c0, moff, map, luA, pbnd, st,
+  hipLaunchKernelGGL((k_refactor_wg<WPR, DEPTH>), dim3(grid), dim3(WPR * WAVE), shm, s, order,
+                     cstart, nchunks, ss->band_stream[band], std::min(TICKET_STREAMS, grid),
+                     lu.rowptr, dlc, lu.val, stall, moff, map, luA, pbnd, lu.diag, c0, st,
                      perturb_rel);
   return true;
 }

@@ -92,6 +92,7 @@ struct kkt_ctx {
   double* luA = nullptr;
   int* a2lu = nullptr;
   int2* ref_pbnd = nullptr;
+  int* ref_dlc = nullptr;  // pivots of each row before the dense trailing block
   int ref_ntriv = 0;
   // precomputed update positions of the refactorization (null: binary search)
   int* ref_moff = nullptr;
@@ -1121,6 +1122,7 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   h->luA = nullptr;
   h->a2lu = nullptr;
   h->ref_pbnd = nullptr;
+  h->ref_dlc = nullptr;
   if (h->syncfree) {
     std::vector<int32_t> a2lu((size_t)nnz, 0);
     const size_t fz = A.lu_col.size();
@@ -1134,6 +1136,13 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
       }
     UP(h->a2lu, a2lu);
     UP(h->ref_pbnd, pb);
+    std::vector<int32_t> dlc(n);
+    for (int32_t i = 0; i < n; i++) {
+      int32_t q = A.lu_rowptr[i];
+      while (q < A.diag[i] && A.lu_col[q] < h->tail_c0) q++;
+      dlc[i] = q - A.lu_rowptr[i];
+    }
+    UP(h->ref_dlc, dlc);
     if ((ks = dalloc(h, &h->luA, fz)) != KKT_OK) {
       free_device(h);
       return ks;
@@ -1496,14 +1505,13 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
                                   h->opt.refactor_waves_per_cu, h->st, h->opt.pivot_perturb_rel,
                                   s))
           return fail(h, KKT_ERR_DEVICE, "short-row refactorization not launchable");
-      } else if (h->light && h->ref_map && h->luA && h->ref_pbnd &&
-                 h->opt.refactor_long_rows == 0 &&
-                 (size_t)((h->band_cap[b] + 1) & ~1) * 24 <= 64 * 1024) {
+      } else if (h->light && h->ref_map && h->luA && h->ref_pbnd && h->ref_dlc &&
+                 h->opt.refactor_long_rows == 0 && (size_t)h->band_cap[b] * 8 <= 64 * 1024) {
         if (!launch_refactor_wg(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
                                 h->band_nchunks[b], b, h->band_cap[b], h->ss, &h->st->stall,
-                                h->tail_c0, h->ref_moff, h->ref_map, h->luA, h->ref_pbnd,
-                                h->opt.refactor_waves_per_cu, h->st, h->opt.pivot_perturb_rel,
-                                s))
+                                h->tail_c0, h->ref_dlc, h->ref_moff, h->ref_map, h->luA,
+                                h->ref_pbnd, h->opt.refactor_waves_per_cu, h->st,
+                                h->opt.pivot_perturb_rel, s))
           return fail(h, KKT_ERR_DEVICE, "long-row refactorization not launchable");
       } else if (!launch_refactor_syncfree(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
                                     h->band_nchunks[b], b, h->band_cap[b], h->aval, h->ready_ref,
