@@ -1265,41 +1265,59 @@ __global__ __launch_bounds__(1024) void k_tail_trsv(const double* __restrict__ T
   __syncthreads();
   const int nb = S / TB;
   const int wv = threadIdx.x / WAVE;
+  __shared__ double ms[TB][TB + 1];  // the block's diagonal triangle
   for (int bb = 0; bb < nb; bb++) {
     const int b0 = (fwd ? bb : nb - 1 - bb) * TB;
+    // remaining rows: after the block (forward) or before it (backward)
+    const int lo = fwd ? b0 + TB : 0, hi = fwd ? S : b0;
+    // nothing here depends on x: one diagonal-block value per thread first,
+    // then all TB matrix values of this thread's first remaining row, so the
+    // latter are still in flight while the block is solved
+    // (unconditional loads at clamped addresses, so that the compiler can
+    // count them and wait for the diagonal value alone)
+    const int dr = (threadIdx.x / TB) % TB, dq = threadIdx.x % TB;
+    const double dv = M(b0 + dr, b0 + dq);
+    const int row0 = lo + threadIdx.x;
+    const int rowc = row0 < S ? row0 : S - 1;
+    double mv[TB];
+#pragma unroll
+    for (int q = 0; q < TB; q++) mv[q] = M(rowc, b0 + q);
+    if (threadIdx.x < TB * TB) ms[dr][dq] = dv;
+    __syncthreads();
     if (wv < nr) {
       double* x = xs + (size_t)wv * S;
       const int r = threadIdx.x % WAVE;
-      double m[TB];
-#pragma unroll
-      for (int q = 0; q < TB; q++) m[q] = r < TB ? M(b0 + r, b0 + q) : 0.0;
+      const int rr = r % TB;
       double xr = r < TB ? x[b0 + r] : 0.0;
 #pragma unroll
       for (int st = 0; st < TB; st++) {
         const int q = fwd ? st : TB - 1 - st;
-        if (MODE == 1 || MODE == 2) xr = r == q ? xr / m[q] : xr;
+        const double mq = ms[rr][q];
+        if (MODE == 1 || MODE == 2) xr = r == q ? xr / mq : xr;
         const double xq = readlane_d(xr, q);
         const bool later = fwd ? r > q : r < q;
-        if (later) xr = __builtin_fma(-m[q], xq, xr);
+        const double nx = __builtin_fma(-mq, xq, xr);
+        xr = later ? nx : xr;
       }
       if (r < TB) x[b0 + r] = xr;
     }
     __syncthreads();
-    // remaining rows: after the block (forward) or before it (backward)
-    const int lo = fwd ? b0 + TB : 0, hi = fwd ? S : b0;
-    for (int row = lo + threadIdx.x; row < hi; row += blockDim.x) {
+    for (int row = row0; row < hi; row += blockDim.x) {
       // NRT == 1: the single column needs no guard (nr == 1)
       double acc[NRT];
 #pragma unroll
       for (int cr = 0; cr < NRT; cr++)
         acc[cr] = (NRT == 1 || cr < nr) ? xs[(size_t)cr * S + row] : 0.0;
-#pragma unroll 4
+      if (row != row0) {
+#pragma unroll
+        for (int q = 0; q < TB; q++) mv[q] = M(row, b0 + q);
+      }
+#pragma unroll
       for (int q = 0; q < TB; q++) {
-        const double mv = M(row, b0 + q);
 #pragma unroll
         for (int cr = 0; cr < NRT; cr++)
           if (NRT == 1 || cr < nr)
-            acc[cr] = __builtin_fma(-mv, xs[(size_t)cr * S + b0 + q], acc[cr]);
+            acc[cr] = __builtin_fma(-mv[q], xs[(size_t)cr * S + b0 + q], acc[cr]);
       }
 #pragma unroll
       for (int cr = 0; cr < NRT; cr++)
