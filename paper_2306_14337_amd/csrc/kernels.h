@@ -216,6 +216,14 @@ void launch_trisolve_sn(int mode, int nr, const LUView& lu, const SnSched& sn, c
 void launch_tail_solve(int mode, int nr, const LUView& lu, const double* T, int S, int s, int c0,
                        const int* split, const int* tptr, const int* trow, const int* tpos,
                        const double* c, double* rhs_buf, double* y, hipStream_t st);
+// One right-hand side, the dense block's rows solved by S / 32 workgroups (one
+// per 32-row block) that take the other blocks' values from y as they appear:
+// y + c0 must hold the sentinel at every position not yet final (or its final
+// value).  Same modes and arguments as launch_tail_solve.
+void launch_tail_solve_mw(int mode, const LUView& lu, const double* T, int S, int s, int c0,
+                          const int* split, const int* tptr, const int* trow, const int* tpos,
+                          const double* c, double* rhs_buf, double* y, int* stall,
+                          hipStream_t st);
 // Right-hand sides per multi-column pass.
 constexpr int MAX_RHS_PASS = 32;
 // The same for nr <= MAX_RHS_PASS columns at once; c, y column-major with

@@ -1330,6 +1330,84 @@ __global__ __launch_bounds__(1024) void k_tail_trsv(const double* __restrict__ T
       y[(size_t)cr * ld + c0 + t] = xs[(size_t)cr * S + t];
 }
 
+// Dense triangular solve on the trailing block, one right-hand side, by
+// S / TB workgroups: workgroup g takes block row b (b = g forward, nb-1-g
+// backward) of TB rows.  Its threads (row r = tid / 8, column lane tid % 8)
+// accumulate the terms of every block the rows depend on as soon as that
+// block's solution values appear in y (they hold the sentinel until then),
+// with the matrix values of the next block already in flight; then wave 0
+// solves the block's diagonal triangle (rows in lanes, readlane broadcasts)
+// and publishes its values with device-coherent stores.  Modes and M as in
+// k_tail_trsv; rhs[t] (t < s) is the right-hand side of block row t, y + c0
+// the output (rows t >= s are the identity padding, x = 0, not stored).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_tail_mw(const double* __restrict__ T, int S, int s,
+                                                 int c0, const double* __restrict__ rhs,
+                                                 double* y, int* stall) {
+  constexpr bool fwd = MODE == 0 || MODE == 2;
+  constexpr bool trans = MODE == 2 || MODE == 3;
+  auto M = [&](int r, int q) -> double {
+    return trans ? T[(size_t)q * S + r] : T[(size_t)r * S + q];
+  };
+  const int nb = S / TB;
+  const int g = blockIdx.x;
+  const int b = fwd ? g : nb - 1 - g;
+  const int tid = threadIdx.x, r = tid >> 3, cl = tid & 7;
+  const int row = b * TB + r;
+  __shared__ double sacc[TB];
+  int spins = 0;
+  double* yb = y + c0;
+  double acc = 0.0;
+  // dependency blocks in solve order: 0 .. b-1 (forward), nb-1 .. b+1 (backward)
+  const int ndep = fwd ? b : nb - 1 - b;
+  double m[4], mn[4];
+  auto load_m = [&](double* dst, int j) {
+    const int bd = fwd ? j : nb - 1 - j;
+#pragma unroll
+    for (int u = 0; u < 4; u++) dst[u] = M(row, bd * TB + cl * 4 + u);
+  };
+  if (ndep > 0) load_m(m, 0);
+  for (int j = 0; j < ndep; j++) {
+    if (j + 1 < ndep) load_m(mn, j + 1);
+    const int bd = fwd ? j : nb - 1 - j;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int t = bd * TB + cl * 4 + u;
+      double xv = 0.0;
+      if (t < s) {
+        xv = ld_coh(yb + t);
+        while (is_sentinel(xv) && keep_waiting(&spins, stall)) xv = ld_coh(yb + t);
+      }
+      acc = __builtin_fma(m[u], xv, acc);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) m[u] = mn[u];
+  }
+  // the 8 column lanes of a row are consecutive lanes of one wave
+  for (int off = 4; off > 0; off >>= 1) acc += __shfl_xor(acc, off, WAVE);
+  if (cl == 0) sacc[r] = acc;
+  __syncthreads();
+  if (tid < WAVE) {
+    const int lr = tid;
+    const int rr = lr % TB;
+    const int rw = b * TB + rr;
+    double md[TB];
+#pragma unroll
+    for (int q = 0; q < TB; q++) md[q] = M(rw, b * TB + q);
+    double xr = (lr < TB && rw < s) ? rhs[rw] - sacc[rr] : 0.0;
+#pragma unroll
+    for (int st = 0; st < TB; st++) {
+      const int q = fwd ? st : TB - 1 - st;
+      if (MODE == 1 || MODE == 2) xr = lr == q ? xr / md[q] : xr;
+      const double xq = readlane_d(xr, q);
+      const bool later = fwd ? lr > q : lr < q;
+      const double nx = __builtin_fma(-md[q], xq, xr);
+      xr = later ? nx : xr;
+    }
+    if (lr < TB && rw < s) st_coh(yb + rw, xr);
+  }
+}
+
 // Several right-hand sides in one launch (nr <= NR, column-major with leading
 // dimension ld = n + 1): each entry's NR dependency loads are in flight
 // together; the dependency depth is paid once for all columns.
@@ -2734,6 +2812,39 @@ void launch_tail_solve(int mode, int nr, const LUView& lu, const double* T, int 
     }
 #undef TT_MODES
 #undef TT_LAUNCH
+  }
+}
+
+void launch_tail_solve_mw(int mode, const LUView& lu, const double* T, int S, int s, int c0,
+                          const int* split, const int* tptr, const int* trow, const int* tpos,
+                          const double* c, double* rhs_buf, double* y, int* stall,
+                          hipStream_t st) {
+  if (s <= 0 || S > DENSE_TAIL_MAX || S % TB != 0) return;
+  const int ld = lu.n + 1;
+  const double* rhs = c + c0;
+  if (mode == 0 || mode == 2) {
+    if (mode == 0)
+      hipLaunchKernelGGL(k_tail_ext<0>, dim3(cdiv(S, 4), 1), dim3(256), 0, st, c0, s, S, 1, ld,
+                         split, lu.rowptr, lu.col, tptr, trow, tpos, lu.val, c, y, rhs_buf);
+    else
+      hipLaunchKernelGGL(k_tail_ext<2>, dim3(cdiv(S, 4), 1), dim3(256), 0, st, c0, s, S, 1, ld,
+                         split, lu.rowptr, lu.col, tptr, trow, tpos, lu.val, c, y, rhs_buf);
+    rhs = rhs_buf;
+  }
+  const int nb = S / TB;
+  switch (mode) {
+    case 0:
+      hipLaunchKernelGGL(k_tail_mw<0>, dim3(nb), dim3(256), 0, st, T, S, s, c0, rhs, y, stall);
+      break;
+    case 1:
+      hipLaunchKernelGGL(k_tail_mw<1>, dim3(nb), dim3(256), 0, st, T, S, s, c0, rhs, y, stall);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_tail_mw<2>, dim3(nb), dim3(256), 0, st, T, S, s, c0, rhs, y, stall);
+      break;
+    default:
+      hipLaunchKernelGGL(k_tail_mw<3>, dim3(nb), dim3(256), 0, st, T, S, s, c0, rhs, y, stall);
+      break;
   }
 }
 

@@ -246,10 +246,10 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
                              h->diag, h->lu_val, 0);
       launch_trisolve_sn(0, 1, lu, h->chs[0], nullptr, nullptr, nullptr, h->tc, h->ty, h->ss, 1,
                          stall, s);
-      launch_tail_solve(0, 1, lu, h->tail_T, S, ts, c0, h->tail_split0, nullptr, nullptr, nullptr,
-                        h->tc, h->tail_rhs, h->ty, s);
-      launch_tail_solve(1, 1, lu, h->tail_T, S, ts, c0, nullptr, nullptr, nullptr, nullptr, h->ty,
-                        h->tail_rhs, h->tz, s);
+      launch_tail_solve_mw(0, lu, h->tail_T, S, ts, c0, h->tail_split0, nullptr, nullptr, nullptr,
+                           h->tc, h->tail_rhs, h->ty, stall, s);
+      launch_tail_solve_mw(1, lu, h->tail_T, S, ts, c0, nullptr, nullptr, nullptr, nullptr, h->ty,
+                           h->tail_rhs, h->tz, stall, s);
       launch_trisolve_sn(1, 1, lu, h->chs[1], nullptr, nullptr, nullptr, h->ty, h->tz, h->ss, 2,
                          stall, s);
       launch_scatter(n, h->qperm, h->tz, x, s);
@@ -258,10 +258,10 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
                              h->diag, h->lu_val, 1);
       launch_trisolve_sn(2, 1, lu, h->chs[2], h->ut_ptr, h->ut_row, h->ut_pos, h->tc, h->ty, h->ss,
                          1, stall, s);
-      launch_tail_solve(2, 1, lu, h->tail_T, S, ts, c0, h->tail_split2, h->ut_ptr, h->ut_row,
-                        h->ut_pos, h->tc, h->tail_rhs, h->ty, s);
-      launch_tail_solve(3, 1, lu, h->tail_T, S, ts, c0, nullptr, nullptr, nullptr, nullptr, h->ty,
-                        h->tail_rhs, h->tz, s);
+      launch_tail_solve_mw(2, lu, h->tail_T, S, ts, c0, h->tail_split2, h->ut_ptr, h->ut_row,
+                           h->ut_pos, h->tc, h->tail_rhs, h->ty, stall, s);
+      launch_tail_solve_mw(3, lu, h->tail_T, S, ts, c0, nullptr, nullptr, nullptr, nullptr, h->ty,
+                           h->tail_rhs, h->tz, stall, s);
       launch_trisolve_sn(3, 1, lu, h->chs[3], h->lt_ptr, h->lt_row, h->lt_pos, h->ty, h->tz, h->ss,
                          2, stall, s);
       launch_scatter(n, h->pin, h->tz, x, s);
