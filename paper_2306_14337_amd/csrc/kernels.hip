@@ -1689,20 +1689,52 @@ __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict
   const int nw = gridDim.x * blockDim.x / WAVE;
   if (ss && blockIdx.x == 0 && threadIdx.x == 0) sync_prep(ss, 1);
   double m = 0.0;
-  for (int r0 = wid * (WAVE / RG); r0 < n; r0 += nw * (WAVE / RG)) {
-    const int i = r0 + g;
-    double s = 0.0;
-    if (i < n)
-      for (int p = arow[i] + gl; p < arow[i + 1]; p += RG) {
+  // four row groups per round, their loads all in flight before any is used
+  constexpr int U = 4;
+  const int stride = nw * (WAVE / RG);
+  for (int r0 = wid * (WAVE / RG); r0 < n; r0 += U * stride) {
+    int ii[U], p0[U], pe[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      ii[u] = r0 + u * stride + g;
+      p0[u] = 0;
+      pe[u] = 0;
+      if (ii[u] < n) {
+        p0[u] = arow[ii[u]] + gl;
+        pe[u] = arow[ii[u] + 1];
+      }
+    }
+    double v0[U];
+    int q0[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      v0[u] = 0.0;
+      q0[u] = 0;
+      if (p0[u] < pe[u]) {
+        v0[u] = src[p0[u]];
+        if (luA) q0[u] = a2lu[p0[u]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      double s = 0.0;
+      if (p0[u] < pe[u]) {
+        dst[p0[u]] = v0[u];
+        if (luA) luA[q0[u]] = v0[u];
+        s = fabs(v0[u]);
+      }
+      for (int p = p0[u] + RG; p < pe[u]; p += RG) {
         const double v = src[p];
         dst[p] = v;
         if (luA) luA[a2lu[p]] = v;
         s += fabs(v);
       }
-    s = group_sum(s);
-    if (i < n) {
-      m = nanmax(m, s);
-      if (rowabs && gl == 0) rowabs[i] = s;
+      s = group_sum(s);
+      const int i = ii[u];
+      if (i < n) {
+        m = nanmax(m, s);
+        if (rowabs && gl == 0) rowabs[i] = s;
+      }
     }
   }
   __shared__ double red[4];
@@ -1822,17 +1854,47 @@ __global__ __launch_bounds__(256) void k_residual(int n, const int* __restrict__
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = gridDim.x * blockDim.x / WAVE;
   double rm = 0.0, xm = 0.0;
-  for (int r0 = wid * (WAVE / RG); r0 < n; r0 += nw * (WAVE / RG)) {
-    const int i = r0 + g;
-    double s = 0.0;
-    if (i < n)
-      for (int t = ptr[i] + gl; t < ptr[i + 1]; t += RG) s += aval[pos ? pos[t] : t] * x[idx[t]];
-    s = group_sum(s);
-    if (i < n) {
-      const double ri = b[i] - s;
-      if (r && gl == 0) r[i] = ri;
-      rm = nanmax(rm, fabs(ri));
-      xm = nanmax(xm, fabs(x[i]));
+  // four row groups per round, their first entries' loads all in flight
+  // before any is used (a wave otherwise waits one gather per round)
+  constexpr int U = 4;
+  const int stride = nw * (WAVE / RG);
+  for (int r0 = wid * (WAVE / RG); r0 < n; r0 += U * stride) {
+    int ii[U], t0[U], te[U];
+    double s[U], av[U], xv[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      ii[u] = r0 + u * stride + g;
+      t0[u] = 0;
+      te[u] = 0;
+      if (ii[u] < n) {
+        t0[u] = ptr[ii[u]] + gl;
+        te[u] = ptr[ii[u] + 1];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      av[u] = 0.0;
+      xv[u] = 0.0;
+      if (t0[u] < te[u]) {
+        av[u] = aval[pos ? pos[t0[u]] : t0[u]];
+        xv[u] = x[idx[t0[u]]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      s[u] = av[u] * xv[u];
+      for (int t = t0[u] + RG; t < te[u]; t += RG) s[u] += aval[pos ? pos[t] : t] * x[idx[t]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const double su = group_sum(s[u]);
+      const int i = ii[u];
+      if (i < n) {
+        const double ri = b[i] - su;
+        if (r && gl == 0) r[i] = ri;
+        rm = nanmax(rm, fabs(ri));
+        xm = nanmax(xm, fabs(x[i]));
+      }
     }
   }
   __shared__ double red[2][4];
