@@ -950,13 +950,17 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   for (bool& f : h->band_flat) f = false;
   // refactorization bands: a row's band is set by its length (LDS staging
   // size, hence rows in flight per CU) and raised to the band of any row it
-  // depends on; each band is one launch.  Within a band rows go by level of
+  // depends on; each band is one launch.  Two bands: rows of at most 128
+  // entries fed only by such rows (the short-row kernel), and the rest (at
+  // 70k buses a third band for rows over 512 entries cost 0.2 ms: every
+  // launch boundary waits for the last rows of the band before it, and a
+  // single band for all rows cost 0.4 ms).  Within a band rows go by level of
   // the sparse phase's dependency graph (rows of the dense block do not
   // depend on each other there), and within a level by decreasing height
   // (longest chain of rows depending on them), so that a level's rows on the
   // critical chains are handed out first.
   {
-    static const int band_len[REF_MAX_BANDS - 1] = {128, 512, 1 << 30};
+    static const int band_len[REF_MAX_BANDS - 1] = {128, 1 << 30, 1 << 30};
     const int c0 = h->tail_c0;
     std::vector<int32_t> rowof(A.lu_col.size());
     for (int32_t i = 0; i < n; i++)
