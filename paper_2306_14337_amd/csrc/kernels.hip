@@ -1090,7 +1090,11 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(
     const int* __restrict__ diag, const int* __restrict__ tptr, const int* __restrict__ trow,
     const int* __restrict__ tpos, const double* __restrict__ val, const double* __restrict__ c,
     double* y, SyncState* ss, int slot, int nstreams, int* stall) {
-  __shared__ double tri_all[256 / WAVE][SN_KMAX * SN_KMAX];
+  // the block's strictly lower triangle, packed by rows: entry (g, h), h < g,
+  // at g (g - 1) / 2 + h (half the LDS of a square, so all eight workgroups
+  // per CU fit)
+  constexpr int TRI = SN_KMAX * (SN_KMAX - 1) / 2;
+  __shared__ double tri_all[256 / WAVE][TRI];
   const int lane = threadIdx.x % WAVE;
   double* tri = tri_all[threadIdx.x / WAVE];
   for (;;) {
@@ -1138,13 +1142,13 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(
     if (chain) {
       // the block's own triangle into LDS (issued before the waits below)
       const int b = ch_base[tk];
-      for (int e = lane; e < k * SN_KMAX; e += WAVE) tri[e] = 0.0;
+      for (int e = lane; e < k * (k - 1) / 2; e += WAVE) tri[e] = 0.0;
       wave_sync();
       for (int q = ib + gl; q < ie; q += G) {
         const int j = MODE <= 1 ? col[q] : trow[q];
         const double v = MODE <= 1 ? val[q] : val[tpos[q]];
         const int sg = (MODE == 0 || MODE == 2) ? j - b : b - j;
-        tri[grp * SN_KMAX + sg] = v;
+        if (sg >= 0 && sg < grp) tri[grp * (grp - 1) / 2 + sg] = v;
       }
     }
     int spins = 0;
@@ -1187,7 +1191,7 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(
       // row sg is final at step sg: its values go to every lane, the later
       // rows take their terms with them
       for (int sg = 0; sg < k; sg++) {
-        const double tv = (grp > sg && active) ? tri[grp * SN_KMAX + sg] : 0.0;
+        const double tv = (grp > sg && active) ? tri[grp * (grp - 1) / 2 + sg] : 0.0;
 #pragma unroll
         for (int r = 0; r < NR; r++) {
           double yv = ci[r] - s[r];
