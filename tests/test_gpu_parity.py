@@ -117,6 +117,7 @@ def test_refactor_kernel_variants_bitwise(B, seed, variant):
     (500, 7, 256),
     (10000, 102, 0),  # automatic size (384 at this size)
     (2000, 104, 700),
+    (10000, 102, 2048),  # the largest dense block: 64 panels, 64 block solves
 ])
 def test_dense_tail_bitwise(B, seed, tail):
     # the trailing block finished as a dense LU gives the oracle's factors bit
@@ -136,6 +137,8 @@ def test_dense_tail_bitwise(B, seed, tail):
         assert_factors_equal(s.lu()[2], oracle_csr_values(ora))
         x = s.solve(dev(b)).cpu().numpy()
         assert eta(pat.scipy(vals), x, b) <= 1e-12
+        xt = s.solve(dev(b), op="T").cpu().numpy()
+        assert eta(pat.scipy(vals).T.tocsr(), xt, b) <= 1e-12
 
 
 # solve layouts: chain blocks (solve_chain) with and without the dense block;
