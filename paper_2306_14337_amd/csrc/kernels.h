@@ -269,11 +269,13 @@ void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStre
 
 // A copy + ||A||_inf (and, if ss != nullptr, the sync_prep of slot 0; if
 // rowabs != nullptr, every row's absolute sum; if luA != nullptr, the values
-// also scattered into factor order: luA[a2lu[p]] = A[p])
+// also scattered into factor order: luA[a2lu[p]] = A[p]).  red (nullable,
+// RED_SCRATCH doubles): scratch of a two-stage maximum over a larger grid.
+constexpr int RED_SCRATCH = 2 * 4096;
 void launch_copy_anorm(int n, const int* arow, const int* acol, const double* src, double* dst,
                        DevStats* st, hipStream_t s, SyncState* ss = nullptr,
                        double* rowabs = nullptr, const int* a2lu = nullptr,
-                       double* luA = nullptr);
+                       double* luA = nullptr, double* red = nullptr);
 // ||A||_1 through the column view (and every column's absolute sum)
 void launch_anorm1(int n, const int* cptr, const int* cpos, const double* aval, DevStats* st,
                    hipStream_t s, double* colabs = nullptr);
@@ -298,10 +300,11 @@ void launch_ltsolve_cols(const LUView& lu, const int* cols, int ncols, const int
 void launch_gather(int n, const int* perm, const double* x, double* y, hipStream_t s);
 void launch_scatter(int n, const int* perm, const double* x, double* y, hipStream_t s);
 
-// r = b - op(A) x and the maxima ||r||_inf, ||x||_inf into st
+// r = b - op(A) x and the maxima ||r||_inf, ||x||_inf into st; red as in
+// launch_copy_anorm
 void launch_residual(int n, char op, const int* ptr, const int* idx, const int* pos,
                      const double* aval, const double* b, const double* x, double* r, DevStats* st,
-                     hipStream_t s);
+                     hipStream_t s, double* red = nullptr);
 // y = op(A) x
 void launch_spmv(int n, char op, const int* ptr, const int* idx, const int* pos, const double* aval,
                  const double* x, double* y, hipStream_t s);

@@ -70,6 +70,7 @@ struct kkt_ctx {
   // (tail_s of them), row-major tail_S x tail_S workspace and panel scratch
   int tail_s = 0, tail_c0 = 0, tail_S = 0;
   double *tail_T = nullptr, *tail_dsc = nullptr, *tail_rhs = nullptr;
+  double* red = nullptr;  // scratch of the two-stage maxima (RED_SCRATCH doubles)
   int *tail_split0 = nullptr, *tail_split2 = nullptr;
   // chain-blocked single right-hand-side solves (modes 0 L, 1 U, 2 U^T, 3 L^T)
   // single-system pattern (for re-analysis) and the number of re-analyses
@@ -420,9 +421,11 @@ void residual_launch(kkt_handle h, char op, const double* b, const double* x, do
                      hipStream_t s) {
   launch_reset_stats(h->st, 2, s);
   if (op == 'N')
-    launch_residual(h->an.n, 'N', h->a_rowptr, h->a_col, nullptr, h->aval, b, x, r, h->st, s);
+    launch_residual(h->an.n, 'N', h->a_rowptr, h->a_col, nullptr, h->aval, b, x, r, h->st, s,
+                    h->red);
   else
-    launch_residual(h->an.n, 'T', h->at_ptr, h->at_row, h->at_pos, h->aval, b, x, r, h->st, s);
+    launch_residual(h->an.n, 'T', h->at_ptr, h->at_row, h->at_pos, h->aval, b, x, r, h->st, s,
+                    h->red);
   if (h->batch_count > 0)
     launch_seg_stats(h->batch_count, h->d_row_off, op == 'N' ? h->rowabs : h->colabs, r, x,
                      h->inst_out, s);
@@ -1375,7 +1378,8 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
       (ks = dalloc(h, &h->g, m + 1)) != KKT_OK || (ks = dalloc(h, &h->h, m + 1)) != KKT_OK ||
       (ks = dalloc(h, &h->h2, m + 1)) != KKT_OK || (ks = dalloc(h, &h->ww, 1)) != KKT_OK ||
       (ks = dalloc(h, &h->y, m + 1)) != KKT_OK || (ks = dalloc(h, &h->hn, 1)) != KKT_OK ||
-      (ks = dalloc(h, &h->partial, 256 * 32)) != KKT_OK) {
+      (ks = dalloc(h, &h->partial, 256 * 32)) != KKT_OK ||
+      (ks = dalloc(h, &h->red, RED_SCRATCH)) != KKT_OK) {
     free_device(h);
     return ks;
   }
