@@ -204,9 +204,17 @@ void launch_trisolve_seg(int mode, const SegSched& sg, const double* val, const 
 // nr <= SN_MAX_RHS right-hand sides; c, y column-major with leading dimension
 // n + 1, y holding the sentinel wherever it is not yet final.
 constexpr int SN_MAX_RHS = 8;
+// Mode 1, one right-hand side: xend/pre (nullable, both or neither) exclude
+// each row's entries in the dense block's columns from the external terms and
+// add pre[i] instead (launch_udense_pre).
 void launch_trisolve_sn(int mode, int nr, const LUView& lu, const SnSched& sn, const int* tptr,
                         const int* trow, const int* tpos, const double* c, double* y,
-                        SyncState* ss, int slot, int* stall, hipStream_t s);
+                        SyncState* ss, int slot, int* stall, hipStream_t s,
+                        const int* xend = nullptr, const double* pre = nullptr);
+// pre[i] = sum over q in [xend[i], rowptr[i + 1]) of val[q] * y[col[q]] for
+// the nu rows urows (the U rows' terms in the dense block's columns)
+void launch_udense_pre(int nu, const int* urows, const int* xend, const LUView& lu, const double* y,
+                       double* pre, hipStream_t st);
 // Dense trailing block of a solve (rows c0 .. c0 + s - 1, T as left by
 // launch_dense_lu or launch_tail_scatter), nr columns (ld n + 1): modes 0
 // and 2 first form rhs = c - external terms (split[t]: end of row c0 + t's

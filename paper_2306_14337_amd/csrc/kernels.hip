@@ -1089,7 +1089,8 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(
     const int* __restrict__ split, const int* __restrict__ rowptr, const int* __restrict__ col,
     const int* __restrict__ diag, const int* __restrict__ tptr, const int* __restrict__ trow,
     const int* __restrict__ tpos, const double* __restrict__ val, const double* __restrict__ c,
-    double* y, SyncState* ss, int slot, int nstreams, int* stall) {
+    double* y, SyncState* ss, int slot, int nstreams, int* stall, const int* __restrict__ xend,
+    const double* __restrict__ pre) {
   // the block's strictly lower triangle, packed by rows: entry (g, h), h < g,
   // at g (g - 1) / 2 + h (half the LDS of a square, so all eight workgroups
   // per CU fit)
@@ -1121,7 +1122,9 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(
         ib = dpos + 1;
         ie = sp;
         eb = sp;
-        ee = rowptr[i + 1];
+        // xend: the entries in the dense block's columns were summed into
+        // pre[i] by a bulk pass (their inputs are final before this launch)
+        ee = xend ? xend[i] : rowptr[i + 1];
       } else if (MODE == 2) {
         eb = tptr[i];
         ee = sp;
@@ -1186,6 +1189,7 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(
 #pragma unroll
     for (int r = 0; r < NR; r++)
       for (int off = G >> 1; off > 0; off >>= 1) s[r] += __shfl_xor(s[r], off, WAVE);
+    if (MODE == 1 && NR == 1 && pre && active) s[0] += pre[i];
     if (chain) {
       wave_sync();
       // row sg is final at step sg: its values go to every lane, the later
@@ -1207,6 +1211,34 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(
       if (MODE == 1 || MODE == 2) yv /= dv;
       if (r < nr) st_coh(y + (size_t)r * ld + i, yv);
     }
+  }
+}
+
+// U solve, rows before the dense trailing block: pre[i] = sum of the row's
+// entries in the block's columns (positions xend[i] .. rowptr[i + 1]) times
+// the solution values there, final once the block is solved.  8 lanes per
+// row, rows listed in urows.
+__global__ __launch_bounds__(256) void k_udense_pre(int nu, const int* __restrict__ urows,
+                                                    const int* __restrict__ xend,
+                                                    const int* __restrict__ rowptr,
+                                                    const int* __restrict__ col,
+                                                    const double* __restrict__ val,
+                                                    const double* __restrict__ y,
+                                                    double* __restrict__ pre) {
+  constexpr int RL = 8;
+  const int lane = threadIdx.x % WAVE, g = lane / RL, gl = lane % RL;
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int nw = gridDim.x * blockDim.x / WAVE;
+  for (int r0 = wid * (WAVE / RL); r0 < nu; r0 += nw * (WAVE / RL)) {
+    const int t = r0 + g;
+    double acc = 0.0;
+    int i = 0;
+    if (t < nu) {
+      i = urows[t];
+      for (int q = xend[i] + gl; q < rowptr[i + 1]; q += RL) acc += val[q] * y[col[q]];
+    }
+    for (int off = RL >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, WAVE);
+    if (t < nu && gl == 0) pre[i] = acc;
   }
 }
 
@@ -2830,7 +2862,12 @@ void launch_dense_lu(double* T, int S, int s, double* dsc, DevStats* stats, doub
 
 void launch_trisolve_sn(int mode, int nr, const LUView& lu, const SnSched& sn, const int* tptr,
                         const int* trow, const int* tpos, const double* c, double* y,
-                        SyncState* ss, int slot, int* stall, hipStream_t s) {
+                        SyncState* ss, int slot, int* stall, hipStream_t s, const int* xend,
+                        const double* pre) {
+  if (mode != 1 || nr != 1) {
+    xend = nullptr;
+    pre = nullptr;
+  }
   if (sn.nchunks <= 0 || nr <= 0) return;
   static int ncu = 0;
   if (ncu == 0) {
@@ -2868,7 +2905,8 @@ void launch_trisolve_sn(int mode, int nr, const LUView& lu, const SnSched& sn, c
 #define SN_LAUNCH(M, R)                                                                         \
   hipLaunchKernelGGL((k_trisolve_sn<M, R>), dim3(grid), dim3(256), 0, s, lu.n, nr, ld,          \
                      sn.nchunks, sn.start, sn.meta, sn.base, sn.rows, sn.split, lu.rowptr,       \
-                     lu.col, lu.diag, tptr, trow, tpos, lu.val, c, y, ss, slot, nstreams, stall)
+                     lu.col, lu.diag, tptr, trow, tpos, lu.val, c, y, ss, slot, nstreams, stall, \
+                     xend, pre)
 #define SN_MODES(R)                 \
   switch (mode) {                   \
     case 0: SN_LAUNCH(0, R); break; \
@@ -2938,6 +2976,13 @@ void launch_tail_solve(int mode, int nr, const LUView& lu, const double* T, int 
 #undef TT_MODES
 #undef TT_LAUNCH
   }
+}
+
+void launch_udense_pre(int nu, const int* urows, const int* xend, const LUView& lu, const double* y,
+                       double* pre, hipStream_t st) {
+  if (nu <= 0) return;
+  hipLaunchKernelGGL(k_udense_pre, dim3(std::max(1, std::min(cdiv(nu, 32), 2048))), dim3(256), 0,
+                     st, nu, urows, xend, lu.rowptr, lu.col, lu.val, y, pre);
 }
 
 void launch_tail_solve_mw(int mode, const LUView& lu, const double* T, int S, int s, int c0,

@@ -72,6 +72,11 @@ struct kkt_ctx {
   double *tail_T = nullptr, *tail_dsc = nullptr, *tail_rhs = nullptr;
   double* red = nullptr;  // scratch of the two-stage maxima (RED_SCRATCH doubles)
   int *tail_split0 = nullptr, *tail_split2 = nullptr;
+  // U solve: rows with entries in the dense block's columns, where those
+  // entries start, and their terms (launch_udense_pre)
+  int *u_xend = nullptr, *u_rows = nullptr;
+  double* u_pre = nullptr;
+  int u_nrows = 0;
   // chain-blocked single right-hand-side solves (modes 0 L, 1 U, 2 U^T, 3 L^T)
   // single-system pattern (for re-analysis) and the number of re-analyses
   std::vector<int64_t> pat_rowptr;
@@ -251,8 +256,9 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
                            h->tc, h->tail_rhs, h->ty, stall, s);
       launch_tail_solve_mw(1, lu, h->tail_T, S, ts, c0, nullptr, nullptr, nullptr, nullptr, h->ty,
                            h->tail_rhs, h->tz, stall, s);
+      launch_udense_pre(h->u_nrows, h->u_rows, h->u_xend, lu, h->tz, h->u_pre, s);
       launch_trisolve_sn(1, 1, lu, h->chs[1], nullptr, nullptr, nullptr, h->ty, h->tz, h->ss, 2,
-                         stall, s);
+                         stall, s, h->u_xend, h->u_pre);
       launch_scatter(n, h->qperm, h->tz, x, s);
     } else {
       launch_gather_sentinel(n, h->qperm, b, h->tc, h->ty, h->tz, h->ss, 0x6, s, h->sn_triv2,
@@ -1343,6 +1349,34 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
         sn.base = a3;
         sn.rows = a4;
         sn.split = a5;
+      }
+    }
+    // U solve: the rows before the dense block with entries in its columns,
+    // and where those entries start (their terms are summed in one pass once
+    // the block is solved)
+    h->u_xend = nullptr;
+    h->u_rows = nullptr;
+    h->u_pre = nullptr;
+    h->u_nrows = 0;
+    if (h->tail_s > 0) {
+      std::vector<int32_t> xend(n + 1, 0), urows;
+      for (int32_t i = 0; i < c0; i++) {
+        int32_t q = A.diag[i] + 1;
+        const int32_t e = A.lu_rowptr[i + 1];
+        while (q < e && A.lu_col[q] < c0) q++;
+        xend[i] = q;
+        if (q < e) urows.push_back(i);
+      }
+      for (int32_t i = c0; i <= n; i++) xend[i] = i < n ? A.lu_rowptr[i + 1] : 0;
+      if (!urows.empty()) {
+        UP(h->u_xend, xend);
+        UP(h->u_rows, urows);
+        h->u_nrows = (int)urows.size();
+        if ((ks = dalloc(h, &h->u_pre, (size_t)n + 1)) != KKT_OK) {
+          free_device(h);
+          return ks;
+        }
+        HIP_CHECK(h, hipMemset(h->u_pre, 0, ((size_t)n + 1) * sizeof(double)));
       }
     }
     // external/internal boundary of the dense block's rows (modes 0 and 2)
