@@ -8,9 +8,11 @@ Knobs (all fields of the C options struct):
   refactor_waves_per_block  rows in flight per workgroup in the refactorization
   solve_thin_rows           widest level of the one-workgroup solve segments
   dense_tail                size of the dense trailing block (0 auto, -1 none)
+  refactor_short_rows       short-row band as update lists (0) or pivot by pivot (-1)
+  refactor_long_rows        long-row band with prefetched steps (0) or not (-1)
 
 The search is in two stages: the launch-shape candidates first, then the
-segment and dense-block variants of the winner.
+segment, dense-block and refactorization-kernel variants of the winner.
 
 The winner is cached in a JSON file keyed by a hash of the pattern (n, row
 pointers, column indices), so a later run with the same pattern skips the
@@ -60,6 +62,8 @@ def refinements(best: dict):
     for thin in (-1, 16):
         out.append({**best, "solve_thin_rows": thin})
     out.append({**best, "dense_tail": -1})
+    out.append({**best, "refactor_short_rows": -1})
+    out.append({**best, "refactor_long_rows": -1})
     return out
 
 

@@ -31,12 +31,15 @@ def test_cache_round_trip(tmp_path):
     assert c["abc"]["options"] == {"schedule": 2} and c["def"]["options"] == {"schedule": 1}
 
 
-def test_refinements_vary_segments_and_dense_block():
+def test_refinements_vary_segments_dense_block_and_kernels():
     best = autotune.candidates()[0]
     ref = autotune.refinements(best)
     assert {r.get("solve_thin_rows") for r in ref} >= {-1, 16}
     assert any(r.get("dense_tail") == -1 for r in ref)
+    assert any(r.get("refactor_short_rows") == -1 for r in ref)
+    assert any(r.get("refactor_long_rows") == -1 for r in ref)
+    varied = ("solve_thin_rows", "dense_tail", "refactor_short_rows", "refactor_long_rows")
     for r in ref:
         binding.options(**r)  # valid option fields
-        assert {k: v for k, v in r.items() if k not in ("solve_thin_rows", "dense_tail")} == best
+        assert {k: v for k, v in r.items() if k not in varied} == best
     assert autotune.refinements(dict(schedule=1, sync_mode=0)) == []
