@@ -1235,7 +1235,24 @@ __global__ __launch_bounds__(256) void k_udense_pre(int nu, const int* __restric
     int i = 0;
     if (t < nu) {
       i = urows[t];
-      for (int q = xend[i] + gl; q < rowptr[i + 1]; q += RL) acc += val[q] * y[col[q]];
+      const int e = rowptr[i + 1];
+      // four gathers of each lane in flight (rows just before the block
+      // have hundreds of such entries)
+      for (int q0 = xend[i] + gl; q0 < e; q0 += 4 * RL) {
+        double v[4], yv[4];
+#pragma unroll
+        for (int z = 0; z < 4; z++) {
+          const int q = q0 + z * RL;
+          v[z] = 0.0;
+          yv[z] = 0.0;
+          if (q < e) {
+            v[z] = val[q];
+            yv[z] = y[col[q]];
+          }
+        }
+#pragma unroll
+        for (int z = 0; z < 4; z++) acc += v[z] * yv[z];
+      }
     }
     for (int off = RL >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, WAVE);
     if (t < nu && gl == 0) pre[i] = acc;
