@@ -29,6 +29,11 @@ constexpr int WAVE = 64;
 #ifndef KKTLU_DLU_TILE
 #define KKTLU_DLU_TILE 32
 #endif
+// k_dlu_panel: threads per workgroup, one panel row or column each (70k
+// buses, refactorization ms: 256 2.86, 128 2.85, 64 2.83)
+#ifndef KKTLU_DLU_PANEL_THREADS
+#define KKTLU_DLU_PANEL_THREADS 64
+#endif
 constexpr int RG_TRIV = 8;  // lanes per row of k_refactor_trivial
 
 __device__ __forceinline__ void wave_sync() {
@@ -2873,9 +2878,9 @@ void launch_dense_lu(double* T, int S, int s, double* dsc, DevStats* stats, doub
                      hipStream_t st) {
   for (int k0 = 0; k0 < S; k0 += DLU_NB) {
     const int rest = S - k0 - DLU_NB;
-    const int nrw = cdiv(rest, 256);
-    hipLaunchKernelGGL(k_dlu_panel<DLU_NB>, dim3(std::max(1, 2 * nrw)), dim3(256), 0, st, T, S,
-                       k0, nrw, dsc, s, stats, prel);
+    const int nrw = cdiv(rest, KKTLU_DLU_PANEL_THREADS);
+    hipLaunchKernelGGL(k_dlu_panel<DLU_NB>, dim3(std::max(1, 2 * nrw)),
+                       dim3(KKTLU_DLU_PANEL_THREADS), 0, st, T, S, k0, nrw, dsc, s, stats, prel);
     const int nt = std::max(1, cdiv(rest, KKTLU_DLU_TILE));
     hipLaunchKernelGGL((k_dlu_update<DLU_NB, KKTLU_DLU_TILE>), dim3(nt, nt), dim3(256), 0, st, T, S,
                        k0, (const double*)dsc);
