@@ -141,6 +141,8 @@ typedef struct {
   double min_pivot;  /* min |u_kk| of the last refactorization */
   double max_pivot;  /* max |u_kk| of the last refactorization */
   double anorm_inf;  /* ||A||_inf of the last refactorization */
+  double growth;     /* max |u_ij| over U / ||A||_inf of the last refactorization (pivot
+                        growth; Section 5.1.1 re-analyses when the factors degrade) */
 } kkt_report;
 
 typedef struct {
@@ -154,6 +156,10 @@ typedef struct {
   int64_t device_bytes;   /* device memory owned by the handle */
   double analyze_seconds;
   int32_t dense_tail;     /* pivots in the dense trailing block (0 = none) */
+  int64_t factor_epoch;   /* incremented by every call that replaces the factors or the
+                             matrix (analyze, refactor, reanalyze, update_matrix, graph
+                             launch); lets a caller tell whether saved solutions still
+                             belong to the current factors */
 } kkt_info;
 
 /* Fill *opt with the defaults listed above. */

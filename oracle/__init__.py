@@ -57,6 +57,9 @@ def lib():
         L.oracle_lu_sizes.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.oracle_lu_export.argtypes = [P] * 9
         L.oracle_lu_absprod.argtypes = [P, P, P]
+        L.oracle_lu_growth.argtypes = [P]
+        L.oracle_lu_growth.restype = C.c_double
+        L.oracle_lu_apply_jacobi.argtypes = [P, P, C.c_int32, P]
         L.oracle_refactor.argtypes = [P, P, C.c_double]
         L.oracle_refactor.restype = C.c_int
         L.oracle_refactor_perturbed.argtypes = [P, P, C.c_double, C.c_double]
@@ -173,6 +176,17 @@ class OracleLU:
         x = np.empty_like(b)
         lib().oracle_lu_apply(self._h, op.encode(), _p(b), _p(x))
         return x
+
+    def apply_jacobi(self, b, sweeps: int):
+        """Sweep-based approximate M^{-1} b (op 'N')."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.empty_like(b)
+        lib().oracle_lu_apply_jacobi(self._h, _p(b), int(sweeps), _p(x))
+        return x
+
+    def growth(self) -> float:
+        """max |u_ij| / ||A||_inf of the current factors."""
+        return float(lib().oracle_lu_growth(self._h))
 
     def fgmres_trace(self, b, iters: int, prec: str = "L"):
         n = self.n

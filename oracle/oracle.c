@@ -11,8 +11,9 @@
  * that applies the same updates to each entry in the same (ascending pivot
  * step) order reproduces these factors bit for bit.
  *
- * parity unpinned: none (every function is checked against dense LAPACK,
- * brute force, closed forms or invariants in the oracle tests).
+ * parity unpinned: none.  Every exported function is named in a CPU test
+ * that checks it against dense LAPACK, brute force, a closed form or an
+ * invariant (the oracle pin tests).
  */
 #include "oracle.h"
 
@@ -478,6 +479,17 @@ void oracle_lu_absprod(const oracle_lu *lu, double *sL, double *sU) {
   free(w);
 }
 
+/* Growth figure of the current factors: max |u_ij| over every stored entry
+ * of U (diagonal included) divided by ||A||_inf, the ratio a threshold-
+ * pivoting code watches to decide that its pivot sequence has gone bad
+ * (Section 5.1.1: re-analysis when the solution quality degrades). */
+double oracle_lu_growth(const oracle_lu *lu) {
+  double umax = 0.0;
+  for (int64_t t = 0; t < lu->Up[lu->n]; t++)
+    if (!(fabs(lu->Ux[t]) <= umax)) umax = fabs(lu->Ux[t]);
+  return lu->anorm_inf > 0.0 ? umax / lu->anorm_inf : (umax > 0.0 ? INFINITY : 0.0);
+}
+
 /* Replace the matrix used by the solves' residuals without refactoring
  * (gives a stale preconditioner for refinement tests). */
 int oracle_set_values(oracle_lu *lu, const double *val) {
@@ -569,6 +581,41 @@ void oracle_lu_apply(const oracle_lu *lu, char op, const double *b, double *x) {
     for (int32_t i = 0; i < n; i++) x[lu->Q[lu->P[i]]] = y[i]; /* l = Q P^T w */
   }
   free(y);
+}
+
+/* Approximate preconditioner of the sweep-based triangular solves (Section 6
+ * names iterative triangular solves as future work): with c = P Q^T b,
+ * split L = I + L_s and U = D + U_s.  The L triangle takes `sweeps` Jacobi
+ * sweeps y <- c - L_s y from y = c, the U triangle `sweeps` sweeps
+ * z <- D^{-1} (y - U_s z) from z = y, and x = Q z.  Each sweep reads only the
+ * previous iterate.  As many sweeps as the dependency depth of a triangle
+ * give its exact solve (L_s and D^{-1} U_s are nilpotent). */
+void oracle_lu_apply_jacobi(const oracle_lu *lu, const double *b, int32_t sweeps, double *x) {
+  int32_t n = lu->n;
+  size_t N = (size_t)n + 1;
+  double *c = (double *)malloc(N * sizeof(double));
+  double *y = (double *)malloc(N * sizeof(double));
+  double *t = (double *)malloc(N * sizeof(double));
+  for (int32_t i = 0; i < n; i++) c[i] = b[lu->Q[lu->P[i]]];
+  memcpy(y, c, (size_t)n * sizeof(double));
+  for (int32_t k = 0; k < sweeps; k++) {
+    memcpy(t, c, (size_t)n * sizeof(double)); /* t = c - L_s y, column by column */
+    for (int32_t j = 0; j < n; j++)
+      for (int64_t s = lu->Lp[j]; s < lu->Lp[j + 1]; s++) t[lu->Li[s]] -= lu->Lx[s] * y[j];
+    memcpy(y, t, (size_t)n * sizeof(double));
+  }
+  double *z = c; /* c is no longer needed */
+  memcpy(z, y, (size_t)n * sizeof(double));
+  for (int32_t k = 0; k < sweeps; k++) {
+    memcpy(t, y, (size_t)n * sizeof(double)); /* t = y - U_s z */
+    for (int32_t j = 0; j < n; j++)
+      for (int64_t s = lu->Up[j]; s < lu->Up[j + 1] - 1; s++) t[lu->Ui[s]] -= lu->Ux[s] * z[j];
+    for (int32_t j = 0; j < n; j++) z[j] = t[j] / lu->Ux[lu->Up[j + 1] - 1];
+  }
+  for (int32_t k = 0; k < n; k++) x[lu->Q[k]] = z[k];
+  free(c);
+  free(y);
+  free(t);
 }
 
 /* y = op(A) x */

@@ -65,6 +65,9 @@ void oracle_lu_export(const oracle_lu *lu, int32_t *P, int32_t *Q, int64_t *Lp, 
  * CSC layout as the export: sL for L entries, sU for U entries. */
 void oracle_lu_absprod(const oracle_lu *lu, double *sL, double *sU);
 
+/* max |u_ij| over U (diagonal included) / ||A||_inf of the current factors. */
+double oracle_lu_growth(const oracle_lu *lu);
+
 /* Refactor with the stored P, Q and patterns (no pivot search).  Returns
  * ORA_OK or ORA_WARN_TINY_PIVOT (|u_kk| < tiny_rel * ||A||_inf). */
 int oracle_refactor(oracle_lu *lu, const double *val, double tiny_rel);
@@ -85,6 +88,10 @@ int oracle_solve(const oracle_lu *lu, char op, int32_t nrhs, const double *b, do
 
 /* Plain preconditioner application M^{-1} b (no refinement). */
 void oracle_lu_apply(const oracle_lu *lu, char op, const double *b, double *x);
+
+/* Approximate M^{-1} b by `sweeps` Jacobi sweeps per triangle (L from
+ * y = c, then U from z = y), op 'N' only. */
+void oracle_lu_apply_jacobi(const oracle_lu *lu, const double *b, int32_t sweeps, double *x);
 
 /* FGMRES trace for invariant checks: exactly `iters` Arnoldi steps from
  * x0 = 0 on A x = b, preconditioner `prec` ('I' identity, 'L' the LU).

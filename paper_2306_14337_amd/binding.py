@@ -65,14 +65,14 @@ class Options(C.Structure):
 class Report(C.Structure):
     _fields_ = [("warnings", C.c_int32), ("iters", C.c_int32), ("eta", C.c_double),
                 ("eta0", C.c_double), ("min_pivot", C.c_double), ("max_pivot", C.c_double),
-                ("anorm_inf", C.c_double)]
+                ("anorm_inf", C.c_double), ("growth", C.c_double)]
 
 
 class Info(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("nnz_l", C.c_int64), ("nnz_u", C.c_int64),
                 ("levels", C.c_int32), ("levels_u", C.c_int32), ("analyze_status", C.c_int32),
                 ("device_bytes", C.c_int64), ("analyze_seconds", C.c_double),
-                ("dense_tail", C.c_int32)]
+                ("dense_tail", C.c_int32), ("factor_epoch", C.c_int64)]
 
 
 _lib = None
@@ -223,6 +223,7 @@ class SolveReport:
     min_pivot: float
     max_pivot: float
     anorm_inf: float
+    growth: float
 
 
 class KKTSolver:
@@ -350,12 +351,16 @@ class KKTSolver:
         r = Report()
         self._check(lib().kkt_sync_report(self._h, C.byref(r)))
         return SolveReport(r.warnings, r.iters, r.eta, r.eta0, r.min_pivot, r.max_pivot,
-                           r.anorm_inf)
+                           r.anorm_inf, r.growth)
 
     def info(self) -> Info:
         i = Info()
         self._check(lib().kkt_get_info(self._h, C.byref(i)))
         return i
+
+    def factor_epoch(self) -> int:
+        """Counter of the calls that replaced the factors or the matrix."""
+        return int(self.info().factor_epoch)
 
     def perm(self):
         P = np.empty(self.n, np.int32)
@@ -381,7 +386,9 @@ class KKTSolveFn:
     solves; the backward pass solves A^T lambda = dL/dx with the same factors
     (transposed) and returns dL/db = lambda and dL/dvalues[p] =
     -sum_r lambda_r[i] x_r[j] for every stored entry p = (i, j) of the pattern.
-    b is n (one right-hand side) or n * nrhs (column-major).
+    b is n (one right-hand side) or n * nrhs (column-major).  backward raises
+    if the solver's factors were replaced after the forward pass (its factor
+    epoch moved on), since the saved solution then belongs to other factors.
     """
 
     _fn = None
@@ -397,6 +404,7 @@ class KKTSolveFn:
                     solver.refactor(values.detach().contiguous())
                     x = solver.solve(b.detach().contiguous())
                     ctx.solver = solver
+                    ctx.epoch = solver.factor_epoch()
                     ctx.save_for_backward(x)
                     return x
 
@@ -404,6 +412,11 @@ class KKTSolveFn:
                 def backward(ctx, gx):
                     (x,) = ctx.saved_tensors
                     s = ctx.solver
+                    if s.factor_epoch() != ctx.epoch:
+                        raise RuntimeError(
+                            "KKTSolveFn.backward: the solver was refactorized after this forward "
+                            "pass; its factors no longer belong to the saved solution (use one "
+                            "solver per differentiated solve, or run backward first)")
                     lam = s.solve(gx.contiguous(), op="T")
                     gvals = s.grad_values(lam, x) if ctx.needs_input_grad[1] else None
                     gb = lam if ctx.needs_input_grad[2] else None

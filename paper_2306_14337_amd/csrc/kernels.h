@@ -14,6 +14,7 @@ struct DevStats {
   unsigned long long anorm1;   // bits of ||A||_1
   unsigned long long rmax;     // bits of ||r||_inf (scratch of the residual kernel)
   unsigned long long xmax;     // bits of ||x||_inf
+  unsigned long long umax;     // bits of max |u_ij| over U (growth numerator)
   int tiny;                    // a tiny or non-finite pivot was seen
   int stall;                   // a dependency wait hit its spin limit (sticky)
   int perturbed;               // a pivot was raised to the perturbation threshold
@@ -272,7 +273,8 @@ void launch_sync_prep(SyncState* ss, int mask, hipStream_t s);
 void launch_gather_prep(int n, const int* perm, const double* x, double* y, SyncState* ss,
                         int mask, hipStream_t s);
 
-// pivot statistics (min/max |u_kk|, tiny test against tiny_rel * ||A||_inf)
+// pivot statistics (min/max |u_kk|, tiny test against tiny_rel * ||A||_inf,
+// max |u_ij| over U)
 void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStream_t s);
 
 // A copy + ||A||_inf (and, if ss != nullptr, the sync_prep of slot 0; if

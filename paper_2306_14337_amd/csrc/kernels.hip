@@ -1605,44 +1605,6 @@ __global__ void k_gather_prep(int n, const int* __restrict__ perm, const double*
   if (ss && i == 0) sync_prep(ss, mask);
 }
 
-__global__ __launch_bounds__(256) void k_pivot_stats(int n, const int* __restrict__ diag,
-                                                     const double* __restrict__ val, DevStats* st,
-                                                     double tiny_rel) {
-  double mn = __builtin_huge_val(), mx = 0.0;
-  int tiny = 0;
-  const double anorm = __longlong_as_double((long long)st->anorm);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const double d = fabs(val[diag[i]]);
-    mn = fmin(mn, d);
-    mx = fmax(mx, d);
-    tiny |= !(d >= tiny_rel * anorm) || isinf(d);
-  }
-  for (int off = WAVE / 2; off > 0; off >>= 1) {
-    mn = fmin(mn, __shfl_xor(mn, off, WAVE));
-    mx = fmax(mx, __shfl_xor(mx, off, WAVE));
-    tiny |= __shfl_xor(tiny, off, WAVE);
-  }
-  __shared__ double rmn[4], rmx[4];
-  __shared__ int rt[4];
-  const int w = threadIdx.x / WAVE;
-  if (threadIdx.x % WAVE == 0) {
-    rmn[w] = mn;
-    rmx[w] = mx;
-    rt[w] = tiny;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 1; q < (int)(blockDim.x / WAVE); q++) {
-      mn = fmin(mn, rmn[q]);
-      mx = fmax(mx, rmx[q]);
-      tiny |= rt[q];
-    }
-    atomicMin(&st->min_piv, dbits(mn));
-    atomicMax(&st->max_piv, dbits(mx));
-    if (tiny) atomicOr(&st->tiny, 1);
-  }
-}
-
 __global__ void k_reset_stats(DevStats* st, int what) {
   if (threadIdx.x == 0) {
     if (what & 1) {
@@ -1650,6 +1612,7 @@ __global__ void k_reset_stats(DevStats* st, int what) {
       st->max_piv = 0ull;
       st->anorm = 0ull;
       st->anorm1 = 0ull;
+      st->umax = 0ull;
       st->tiny = 0;
       st->perturbed = 0;
     }
@@ -1703,6 +1666,64 @@ __device__ __forceinline__ double block_nanmax(double v, double* red) {
   if (threadIdx.x == 0)
     for (int q = 0; q < (int)(blockDim.x / WAVE); q++) m = nanmax(m, red[q]);
   return m;
+}
+
+// Pivot health after a refactorization: min / max |u_kk|, the tiny or
+// non-finite pivot test against tiny_rel * ||A||_inf, and max |u_ij| over
+// every stored U entry (the growth figure's numerator, NaN-propagating).
+// 8 lanes per row; lane 0 of a row group also takes the diagonal.
+__global__ __launch_bounds__(256) void k_pivot_stats(int n, const int* __restrict__ rowptr,
+                                                     const int* __restrict__ diag,
+                                                     const double* __restrict__ val, DevStats* st,
+                                                     double tiny_rel) {
+  const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int nw = gridDim.x * blockDim.x / WAVE;
+  const double anorm = __longlong_as_double((long long)st->anorm);
+  double mn = __builtin_huge_val(), mx = 0.0, um = 0.0;
+  int tiny = 0;
+  for (int r0 = wid * (WAVE / RG); r0 < n; r0 += nw * (WAVE / RG)) {
+    const int i = r0 + g;
+    if (i < n) {
+      const int d = diag[i], e = rowptr[i + 1];
+      for (int t = d + gl; t < e; t += RG) {
+        const double a = fabs(val[t]);
+        um = nanmax(um, a);
+        if (t == d) {
+          mn = fmin(mn, a);
+          mx = fmax(mx, a);
+          tiny |= !(a >= tiny_rel * anorm) || isinf(a);
+        }
+      }
+    }
+  }
+  for (int off = WAVE / 2; off > 0; off >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, off, WAVE));
+    mx = fmax(mx, __shfl_xor(mx, off, WAVE));
+    tiny |= __shfl_xor(tiny, off, WAVE);
+  }
+  __shared__ double rmn[4], rmx[4], rum[4];
+  __shared__ int rt[4];
+  um = block_nanmax(um, rum);
+  const int w = threadIdx.x / WAVE;
+  if (threadIdx.x % WAVE == 0) {
+    rmn[w] = mn;
+    rmx[w] = mx;
+    rt[w] = tiny;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < (int)(blockDim.x / WAVE); q++) {
+      mn = fmin(mn, rmn[q]);
+      mx = fmax(mx, rmx[q]);
+      tiny |= rt[q];
+    }
+    atomicMin(&st->min_piv, dbits(mn));
+    atomicMax(&st->max_piv, dbits(mx));
+    // NaN bit patterns exceed every finite or infinite one as uint64
+    atomicMax(&st->umax, um != um ? 0x7FF8000000000000ull : dbits(um));
+    if (tiny) atomicOr(&st->tiny, 1);
+  }
 }
 
 // Per-instance maxima of a block-diagonal batch: block t reduces rows
@@ -2596,9 +2617,8 @@ void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxl
 }
 
 void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStream_t s) {
-  hipLaunchKernelGGL(k_pivot_stats, dim3(std::max(1, std::min(cdiv(lu.n, 256), 1024))), dim3(256),
-                     0, s, lu.n, lu.diag, lu.val,
-                     st, tiny_rel);
+  hipLaunchKernelGGL(k_pivot_stats, dim3(rows_grid(lu.n)), dim3(256), 0, s, lu.n, lu.rowptr,
+                     lu.diag, lu.val, st, tiny_rel);
 }
 
 // Row passes with a two-stage maximum (red != nullptr): a larger grid keeps

@@ -135,6 +135,8 @@ struct kkt_ctx {
   hipGraph_t graph = nullptr;
   const double *graph_b = nullptr, *graph_x = nullptr;
   bool graph_eta_pending = false;
+  // calls that replaced the factors or the matrix (kkt_info.factor_epoch)
+  int64_t factor_epoch = 0;
   // report
   int warnings = 0;
   int last_iters = 0;
@@ -1459,6 +1461,7 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   h->anorm1_valid = false;
   h->analyzed = true;
   h->factored = true;
+  h->factor_epoch++;
   h->warnings = st > 0 ? (1 << st) : 0;
   h->analyze_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1590,6 +1593,7 @@ kkt_status kkt_refactor(kkt_handle h, const double* d_values, void* stream) {
   HIP_CHECK(h, hipGetLastError());
   h->anorm1_valid = false;
   h->factored = true;
+  h->factor_epoch++;
   return KKT_OK;
 }
 
@@ -1634,6 +1638,7 @@ kkt_status kkt_graph_launch(kkt_handle h, void* stream) {
   HIP_CHECK(h, hipGraphLaunch(h->graph_exec, (hipStream_t)stream));
   h->anorm1_valid = false;
   h->factored = true;
+  h->factor_epoch++;
   h->graph_eta_pending = true;
   return KKT_OK;
 }
@@ -1650,6 +1655,7 @@ kkt_status kkt_update_matrix(kkt_handle h, const double* d_values, void* stream)
                     h->rowabs);
   HIP_CHECK(h, hipGetLastError());
   h->anorm1_valid = false;
+  h->factor_epoch++;
   return KKT_OK;
 }
 
@@ -1798,6 +1804,7 @@ kkt_status kkt_sync_report(kkt_handle h, kkt_report* out) {
   out->min_pivot = bits_to_double(d.min_piv);
   out->max_pivot = bits_to_double(d.max_piv);
   out->anorm_inf = bits_to_double(d.anorm);
+  out->growth = eta_of(bits_to_double(d.umax), out->anorm_inf, 1.0);
   h->warnings = 0;
   return KKT_OK;
 }
@@ -1816,6 +1823,7 @@ kkt_status kkt_get_info(kkt_handle h, kkt_info* out) {
   out->device_bytes = h->device_bytes;
   out->analyze_seconds = h->analyze_seconds;
   out->dense_tail = h->tail_s;
+  out->factor_epoch = h->factor_epoch;
   return KKT_OK;
 }
 

@@ -369,30 +369,14 @@ def test_reanalysis_restores_a_stable_pivot_order():
 
 def test_jacobi_sweeps_truncated_and_exact():
     # approximate triangular solves: k sweeps per triangle.  The GPU's direct
-    # solve equals the truncated sweeps written out with the oracle's factors,
-    # and as many sweeps as the dependency depth give the exact solve
+    # solve equals the oracle's truncated sweeps, and as many sweeps as the
+    # dependency depth give the exact solve
     pat, seq = kktgen.make_sequence(100, 101, 1)
     vals, b = seq[0]
     ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, vals, tau=1e-10)
-    f = ora.factors()
-    n = pat.n
-    L = sp.csc_matrix((f["Lx"], f["Li"], f["Lp"]), shape=(n, n)).tocsr()
-    U = sp.csc_matrix((f["Ux"], f["Ui"], f["Up"]), shape=(n, n)).tocsr()
-    d = U.diagonal()
-    Us = U - sp.diags(d)
-    pin = f["Q"][f["P"]]
-    c = b[pin]
 
     def sweeps(k):
-        y = c.copy()
-        for _ in range(k):
-            y = c - L @ y
-        z = y.copy()
-        for _ in range(k):
-            z = (y - Us @ z) / d
-        x = np.empty(n)
-        x[f["Q"]] = z
-        return x
+        return ora.apply_jacobi(b, k)
 
     A = pat.scipy(vals)
     for k in (3, 12):
@@ -471,6 +455,47 @@ def test_tiny_pivot_warning_and_report():
     f = ora.factors()
     d = np.abs(f["Ux"][f["Up"][1:] - 1])
     assert rep.min_pivot == d.min() and rep.max_pivot == d.max()
+
+
+@pytest.mark.parametrize("B,seed,layout", [(100, 101, dict()), (2000, 104, dict()),
+                                           (2000, 104, dict(dense_tail=-1)),
+                                           (500, 7, dict(schedule=1))])
+def test_growth_matches_oracle(B, seed, layout):
+    # growth max|u_ij| / ||A||_inf after each refactorization of a sequence,
+    # equal to the oracle's figure (same factors bit for bit, same maxima)
+    pat, seq = kktgen.make_sequence(B, seed, 3)
+    s = binding.KKTSolver(**layout)
+    s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
+    ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, seq[0][0], tau=1e-10)
+    for vals, _ in seq[1:]:
+        s.refactor(dev(vals))
+        rep = s.report()
+        ora.refactor(vals)
+        print(f"  growth {rep.growth:.6e}", flush=True)
+        assert rep.growth == ora.growth()
+    # a non-finite entry makes the figure NaN (and raises the tiny-pivot flag)
+    bad = seq[1][0].copy()
+    bad[pat.rowptr[pat.n // 2]] = np.nan
+    s.refactor(dev(bad))
+    rep = s.report()
+    assert np.isnan(rep.growth) and rep.warnings & (1 << binding.WARN_TINY_PIVOT)
+
+
+def test_autograd_backward_refuses_replaced_factors():
+    # backward after the solver was refactorized for another system would use
+    # the wrong factors: it must raise instead of returning a wrong gradient
+    pat, vals = _twin(100, 31)
+    s = binding.KKTSolver()
+    s.analyze(pat.n, pat.rowptr, pat.colind, vals)
+    b = dev(np.random.default_rng(1).standard_normal(pat.n))
+    v1 = dev(vals).requires_grad_(True)
+    x1 = binding.KKTSolveFn.apply(s, v1, b)
+    v2 = dev(vals * 1.5).requires_grad_(True)
+    x2 = binding.KKTSolveFn.apply(s, v2, b)
+    with pytest.raises(RuntimeError, match="refactorized"):
+        x1.sum().backward()
+    x2.sum().backward()  # the latest forward still differentiates
+    assert torch.isfinite(v2.grad).all()
 
 
 def test_state_and_argument_errors():

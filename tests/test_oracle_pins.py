@@ -663,3 +663,137 @@ def test_gradient_closed_form():
         Lp = np.sum(Cm.T * np.linalg.solve(Ad + dA, Bm.T))
         Lm_ = np.sum(Cm.T * np.linalg.solve(Ad - dA, Bm.T))
         assert (Lp - Lm_) / (2 * h) == pytest.approx(g[p], rel=1e-5, abs=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# |L||U|, growth figure and sweep-based triangular solves
+# ---------------------------------------------------------------------------
+def _dense_factors(ora):
+    f = ora.factors()
+    n = ora.n
+    L, _ = csc_dense(n, f["Lp"], f["Li"], f["Lx"])
+    U, Um = csc_dense(n, f["Up"], f["Ui"], f["Ux"])
+    return f, L + np.eye(n), U, Um
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_absprod_matches_dense_product(seed):
+    # (|L||U|)_ij on the pattern equals the dense product of the absolute
+    # factors (unit diagonal of L included), for L and U entries alike
+    n = 30 + 5 * seed
+    rp, ci, v = kktgen.random_sparse(n, 0.12, seed=400 + seed)
+    ora = oracle.OracleLU(n, rp, ci, v, tau=0.1)
+    f, L, U, _ = _dense_factors(ora)
+    ref = np.abs(L) @ np.abs(U)
+    sL, sU = ora.absprod()
+    for j in range(n):
+        for t in range(f["Up"][j], f["Up"][j + 1]):
+            i = f["Ui"][t]
+            assert abs(sU[t] - ref[i, j]) <= 1e-13 * ref[i, j], (i, j)
+        for t in range(f["Lp"][j], f["Lp"][j + 1]):
+            i = f["Li"][t]
+            assert abs(sL[t] - ref[i, j]) <= 1e-13 * ref[i, j], (i, j)
+
+
+@pytest.mark.parametrize("n", [2, 5, 12, 30])
+def test_growth_wilkinson_closed_form(n):
+    # Wilkinson's matrix (1 on the diagonal, -1 below it, 1 in the last
+    # column) under partial pivoting keeps the diagonal pivots and doubles the
+    # last column at every step: max |U| = u_nn = 2^(n-1) and ||A||_inf = n
+    A = np.eye(n) - np.tril(np.ones((n, n)), -1)
+    A[:, -1] = 1.0
+    rp, ci, v = [0], [], []
+    for i in range(n):
+        for j in range(n):
+            if A[i, j] != 0.0:
+                ci.append(j)
+                v.append(A[i, j])
+        rp.append(len(ci))
+    ora = oracle.OracleLU(n, np.array(rp), np.array(ci), np.array(v),
+                          Q=np.arange(n, dtype=np.int32), tau=1.0)
+    assert np.array_equal(ora.factors()["P"], np.arange(n))
+    assert ora.growth() == 2.0 ** (n - 1) / n
+
+
+def test_growth_tracks_refactorization():
+    # after a refactorization the figure is that of the new factors: scaling
+    # the matrix leaves it unchanged, and a matrix whose U is known (upper
+    # triangular A with Q = P = identity) gives max|a_ij| / ||A||_inf
+    n = 40
+    rp, ci, v = kktgen.random_sparse(n, 0.1, seed=77)
+    ora = oracle.OracleLU(n, rp, ci, v, tau=1e-10)
+    g0 = ora.growth()
+    ora.refactor(v * 1024.0)
+    assert ora.growth() == g0
+    D = np.triu(np.random.default_rng(5).normal(size=(n, n))) + 5 * np.eye(n)
+    rp2 = np.concatenate([[0], np.cumsum(np.arange(n, 0, -1))]).astype(np.int64)
+    ci2 = np.concatenate([np.arange(i, n) for i in range(n)]).astype(np.int32)
+    v2 = np.concatenate([D[i, i:] for i in range(n)])
+    o2 = oracle.OracleLU(n, rp2, ci2, v2, Q=np.arange(n, dtype=np.int32), tau=1e-10)
+    ref = np.abs(D).max() / np.abs(D).sum(1).max()
+    assert abs(o2.growth() - ref) <= 1e-15 * ref  # row sums rounded in another order
+
+
+def _jacobi_setup(seed):
+    n = 36
+    rp, ci, v = kktgen.random_sparse(n, 0.1, seed=500 + seed)
+    ora = oracle.OracleLU(n, rp, ci, v, tau=0.1)
+    f, L, U, _ = _dense_factors(ora)
+    pin = f["Q"][f["P"]]
+    return n, ora, f, L, U, pin
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_jacobi_sweeps_partial_neumann_sums(seed):
+    # k sweeps from the right-hand side unroll into partial Neumann sums:
+    # y_k = sum_{j<=k} (-L_s)^j c and, with U = D (I + N), N = D^{-1} U_s and
+    # z_0 = y_k, z_k = sum_{j<k} (-N)^j D^{-1} y_k + (-N)^k y_k
+    n, ora, f, L, U, pin = _jacobi_setup(seed)
+    b = np.random.default_rng(seed).normal(size=n)
+    c = b[pin]
+    Ls = L - np.eye(n)
+    d = np.diag(U)
+    N = (U - np.diag(d)) / d[:, None]
+    for k in (0, 1, 2, 5):
+        y = sum(np.linalg.matrix_power(-Ls, j) @ c for j in range(k + 1))
+        z = np.linalg.matrix_power(-N, k) @ y
+        for j in range(k):
+            z = z + np.linalg.matrix_power(-N, j) @ (y / d)
+        x = np.empty(n)
+        x[f["Q"]] = z
+        xo = ora.apply_jacobi(b, k)
+        assert np.abs(xo - x).max() <= 1e-10 * np.abs(x).max(), k
+
+
+def test_jacobi_one_sweep_closed_form():
+    # one sweep: z = D^{-1} (I - U_s) (I - L_s) c
+    n, ora, f, L, U, pin = _jacobi_setup(3)
+    b = np.random.default_rng(9).normal(size=n)
+    d = np.diag(U)
+    z = ((np.eye(n) - (U - np.diag(d))) @ ((2 * np.eye(n) - L) @ b[pin])) / d
+    x = np.empty(n)
+    x[f["Q"]] = z
+    assert np.abs(ora.apply_jacobi(b, 1) - x).max() <= 1e-12 * np.abs(x).max()
+
+
+def test_jacobi_depth_sweeps_exact():
+    # as many sweeps as the longer triangle's dependency depth reproduce the
+    # exact triangular solves (scipy's dense triangular solver)
+    n, ora, f, L, U, pin = _jacobi_setup(4)
+    b = np.random.default_rng(11).normal(size=n)
+    y = sla.solve_triangular(L, b[pin], lower=True, unit_diagonal=True)
+    z = sla.solve_triangular(U, y, lower=False)
+    x = np.empty(n)
+    x[f["Q"]] = z
+    xo = ora.apply_jacobi(b, n)
+    assert np.abs(xo - x).max() <= 1e-10 * np.abs(x).max()
+    # fewer sweeps than the depth differ (the test has teeth)
+    depth = 0
+    Lm = np.abs(L - np.eye(n)) > 0
+    lev = np.zeros(n, int)
+    for i in range(n):
+        js = np.nonzero(Lm[i, :i])[0]
+        lev[i] = 1 + lev[js].max() if js.size else 0
+    depth = lev.max()
+    if depth >= 2:
+        assert np.abs(ora.apply_jacobi(b, depth - 1) - x).max() > 1e-8 * np.abs(x).max()
