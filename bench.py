@@ -60,6 +60,47 @@ def algorithmic_bytes(nnz_a: int, nnz_lu: int, n: int):
     return refactor, solve + resid
 
 
+def host_info():
+    """Core count and CPU model of the machine the bench runs on."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["affinity_cores"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("CPU(s)", "Socket(s)", "Core(s) per socket", "Thread(s) per core"):
+                info["lscpu_" + k.strip()] = v.strip()
+    except (OSError, ValueError):
+        pass
+    return info
+
+
+def hop_latency():
+    """Device-coherent store-to-poll hop within one XCD and across XCDs, from
+    the in-tree microbenchmark (paper_2306_14337_amd/hop_latency)."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2306_14337_amd", "hop_latency")
+    if not os.path.exists(exe):
+        return None
+    try:
+        out = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+        return json.loads(out.stdout.strip().splitlines()[-1])
+    except (OSError, ValueError, IndexError, subprocess.TimeoutExpired):
+        return None
+
+
 def cpu_baseline(pat, seq, budget_s: float = 20.0):
     """The oracle (single-threaded C) on the same per-step work, bounded sample."""
     import oracle
@@ -79,6 +120,53 @@ def cpu_baseline(pat, seq, budget_s: float = 20.0):
     return dict(value=done / t_steps, unit="refactor+solve/s", cores=1, kind="oracle",
                 sample=f"{done} refactor+solve steps of the same sequence on 1 host core "
                        f"(oracle analysis {t_an:.1f} s not counted)")
+
+
+def cpu_baseline_batched(insts, patterns, per_group: int = 16):
+    """The oracle on a sample of the batch's instances (the first per_group
+    of the shared-pattern group and of the own-pattern group), instances
+    spread over all host cores (the C oracle releases the interpreter lock);
+    the oracle analyses are done first and not timed."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    sample = [t for t, (p, *_r) in enumerate(insts) if p == 0][:per_group]
+    sample += [t for t, (p, *_r) in enumerate(insts) if p != 0][:per_group]
+    cores = os.cpu_count() or 1
+    solvers = {}
+
+    def mk(p):
+        n, rp, ci, v0 = patterns[p]
+        return p, oracle.OracleLU(n, rp, ci, v0, tau=1e-10)
+
+    need = sorted({insts[t][0] for t in sample})
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        for p, o in ex.map(mk, need):
+            solvers[p] = o
+    # one oracle object per instance of the shared pattern would share state:
+    # give each worker its own copy of the shared analysis
+    shared = [mk(0)[1] for _ in range(min(cores, per_group))] if 0 in solvers else []
+
+    def work(idx_t):
+        idx, t = idx_t
+        p, _pat, v, r = insts[t]
+        o = shared[idx % len(shared)] if p == 0 else solvers[p]
+        o.refactor(v)
+        o.solve(r)
+
+    jobs = list(enumerate(sample))
+    a_jobs = [j for j in jobs if insts[j[1]][0] == 0]
+    b_jobs = [j for j in jobs if insts[j[1]][0] != 0]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=min(cores, max(1, len(shared)))) as ex:
+        list(ex.map(work, a_jobs))
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(work, b_jobs))
+    dt = time.perf_counter() - t0
+    return dict(value=len(sample) / dt, unit="instances/s", cores=cores, kind="oracle",
+                sample=f"{len(a_jobs)} shared-pattern + {len(b_jobs)} own-pattern instances, "
+                       f"refactor + solve each, over {cores} host threads (analyses not timed)")
 
 
 def _eta(A, x, b):
@@ -227,7 +315,32 @@ def bench_batched(torch, binding, kktgen, steps=5, seed=104, n_a=128, n_b=128, B
         s.graph_launch(stream)
     stream.synchronize()
     t_batch = (time.perf_counter() - t0) / steps
+    # the same replays timed with events on the graph's stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        s.graph_launch(stream)
+    ev1.record(stream)
+    stream.synchronize()
+    t_batch_ev = ev0.elapsed_time(ev1) / steps * 1e-3
     etas = s.batch_eta()
+    assert float(etas.max()) <= 1e-12, f"batched accuracy gate failed: eta {etas.max():.3e}"
+    rep = s.report()
+    # algorithmic bytes of one batch step: values and vectors per instance,
+    # index arrays once per distinct pattern (section 8(d) accounting)
+    rp, _, _ = s.lu(values=False)
+    ro, no = s.row_offset, s.nnz_offset
+    inst_f = [int(rp[ro[t + 1]] - rp[ro[t]]) for t in range(len(insts))]
+    inst_a = [int(no[t + 1] - no[t]) for t in range(len(insts))]
+    inst_n = [int(ro[t + 1] - ro[t]) for t in range(len(insts))]
+    seen = set()
+    b_vals = b_idx = 0
+    for t, (p, *_r) in enumerate(insts):
+        a, f, n = inst_a[t], inst_f[t], inst_n[t]
+        b_vals += 8 * a + 8 * f + 8 * f + 8 * a + 100 * n
+        if p not in seen:
+            seen.add(p)
+            b_idx += 4 * a + 4 * f + 4 * f + 4 * a + 8 * n
     # plain loop: one handle per distinct pattern, instances one after another
     handles = [None] * len(patterns)
 
@@ -255,12 +368,28 @@ def bench_batched(torch, binding, kktgen, steps=5, seed=104, n_a=128, n_b=128, B
     torch.cuda.synchronize()
     t_loop = time.perf_counter() - t0
     count = len(insts)
+    loop_etas = []
+    for t, (p, pat, v, r) in enumerate(insts):
+        x = xs[t].cpu().numpy()
+        A = pat.scipy(v)
+        loop_etas.append(_eta(A, x, r))
+    assert max(loop_etas) <= 1e-12, "loop accuracy gate failed"
+    bytes_step = b_vals + b_idx
+    achieved = bytes_step / t_batch_ev / 1e9
     return {"workload": f"batched, {n_a} instances sharing one B={B_a} pattern + {n_b} instances "
-                        f"with own B~U[500,5000], one captured graph per batch step",
+                        f"with own B~U[500,5000], one captured graph per batch step "
+                        f"(refactor + solve + device-checked refinement)",
             "instances": count, "rows_total": s.n, "ms_per_batch": t_batch * 1e3,
+            "ms_per_batch_events": t_batch_ev * 1e3,
             "inst_per_s": count / t_batch, "loop_inst_per_s": count / t_loop,
             "speedup_vs_loop": t_loop / t_batch, "eta_max": float(etas.max()),
-            "generate_s": t_gen, "analyze_s": t_an}
+            "loop_eta_max": max(loop_etas), "refine_iters": rep.iters,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "bytes_per_batch_step": bytes_step,
+                         "kernel": "one replay of the batch graph (all its kernels)"},
+            "generate_s": t_gen, "analyze_s": t_an,
+            "cpu_baseline": cpu_baseline_batched(insts, patterns)}
 
 
 def main():
@@ -364,15 +493,36 @@ def main():
     t_step = ev[0][0].elapsed_time(ev[-1][2]) / args.steps
     rep = s.report()
 
-    # accuracy gate on every timed step (host-side check of the device result)
-    etas = []
+    # accuracy gate on every timed step (host-side check of the device result),
+    # with the 2-norm relative residual next to eta
+    etas, rel2 = [], []
     for i in range(args.steps):
         k = args.warmup + i
         A = pat.scipy(seq[k][0])
         x = xs[k].cpu().numpy()
         b = seq[k][1]
-        etas.append(float(np.abs(b - A @ x).max() / (abs(A).sum(1).max() * np.abs(x).max())))
+        r = b - A @ x
+        etas.append(float(np.abs(r).max() / (abs(A).sum(1).max() * np.abs(x).max())))
+        rel2.append(float(np.linalg.norm(r) / np.linalg.norm(b)))
     assert max(etas) <= 1e-12, f"accuracy gate failed: eta {max(etas):.3e}"
+    t_steps = [a + b for a, b in zip(t_ref, t_sol)]
+
+    # one more step after a 512 MB write that evicts the factors and A from
+    # the 256 MiB last-level cache (cold numbers)
+    flush = torch.empty(64 << 20, dtype=torch.float64, device=dev)
+    flush.fill_(1.0)
+    ec = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    k = args.warmup
+    ec[0].record(stream)
+    s.refactor(vals_d[k])
+    ec[1].record(stream)
+    s.solve(rhs_d[k], xs[k])
+    ec[2].record(stream)
+    torch.cuda.synchronize()
+    cold = {"refactor_ms": ec[0].elapsed_time(ec[1]), "solve_ms": ec[1].elapsed_time(ec[2]),
+            "step_ms": ec[0].elapsed_time(ec[2])}
+    del flush
+    hop = hop_latency()
 
     ref_b, sol_b = algorithmic_bytes(pat.nnz, nnz_lu, pat.n)
     t_ref_med = float(np.median(t_ref)) * 1e-3
@@ -403,12 +553,30 @@ def main():
                      "kernel": "refactorization (all launches of one kkt_refactor)",
                      "bytes_per_launch": ref_b, "avg_ms": t_ref_med * 1e3},
         "phases_ms": {"refactor_median": float(np.median(t_ref)),
-                      "solve_median": float(np.median(t_sol))},
+                      "solve_median": float(np.median(t_sol)),
+                      "step_median": float(np.median(t_steps)),
+                      "step_p90": float(np.percentile(t_steps, 90)),
+                      "refactor_p90": float(np.percentile(t_ref, 90)),
+                      "solve_p90": float(np.percentile(t_sol, 90))},
+        "cold_after_512MB_flush": cold,
         "eta_max": max(etas),
+        "rel_residual_2norm_max": max(rel2),
         "fgmres_iters_last": rep.iters,
         "analyze_s": t_an,
         "wall_s": wall,
+        "host": host_info(),
     }
+    if hop is not None and "same_xcd" in hop:
+        lev = int(info.levels)
+        out["depth_bound"] = {
+            "hop_ns_same_xcd": hop["same_xcd"]["hop_ns"],
+            "hop_ns_cross_xcd": hop["cross_xcd"]["hop_ns"],
+            "refactor_levels": lev, "solve_levels": [int(info.levels), int(info.levels_u)],
+            "refactor_ms_cross_xcd": lev * hop["cross_xcd"]["hop_ns"] * 1e-6,
+            "solve_ms_cross_xcd": (int(info.levels) + int(info.levels_u))
+            * hop["cross_xcd"]["hop_ns"] * 1e-6,
+            "note": "dependency levels x one device-coherent hop: the latency floor of a "
+                    "dependency-driven launch whose every level waits for the one before"}
     del vals_d, rhs_d, xs, s
     torch.cuda.empty_cache()
     if not args.no_extras:

@@ -130,7 +130,17 @@ typedef struct {
                                  0 = the pivot rows of the next steps are loaded into registers
                                  ahead of their steps and only the row's values are staged in LDS
                                  (default), -1 = each step loads its pivot row when it starts */
-  int32_t reserved3;
+  int32_t refine_sync; /* 0 (default): the refinement's stop test runs on the device; kkt_solve
+                         launches the direct solve, the test and a fixed budget of refinement
+                         iterations (refine_budget) whose kernels return at once after the test
+                         stopped them, and never waits for the device (graph-capturable);
+                         1: the host reads eta back after every step and launches only the
+                         iterations needed (kkt_solve then synchronises the stream) */
+  int32_t refine_budget; /* refinement iterations launched per right-hand side when
+                            refine_sync = 0: 0 = fgmres_max_iters (default), k > 0 =
+                            min(k, fgmres_max_iters) (at least min_iters); a solve that has not
+                            met eta_target within the budget reports KKT_WARN_NOT_CONVERGED */
+  int32_t reserved4;
 } kkt_options;
 
 typedef struct {

@@ -59,7 +59,8 @@ class Options(C.Structure):
                 ("refactor_waves_per_cu", C.c_int32), ("refine", C.c_int32),
                 ("auto_reanalyze", C.c_int32), ("solve_jacobi_sweeps", C.c_int32),
                 ("refactor_short_rows", C.c_int32), ("pivot_perturb_rel", C.c_double),
-                ("refactor_long_rows", C.c_int32), ("reserved3", C.c_int32)]
+                ("refactor_long_rows", C.c_int32), ("refine_sync", C.c_int32),
+                ("refine_budget", C.c_int32), ("reserved4", C.c_int32)]
 
 
 class Report(C.Structure):

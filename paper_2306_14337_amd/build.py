@@ -1,4 +1,5 @@
-"""Compile the HIP library (gfx950) in-tree: paper_2306_14337_amd/libkktlu.so."""
+"""Compile the HIP library (gfx950) in-tree, paper_2306_14337_amd/libkktlu.so,
+and the hop-latency microbenchmark, paper_2306_14337_amd/hop_latency."""
 from __future__ import annotations
 
 import os
@@ -10,6 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libkktlu.so")
 SOURCES = ["analyze.cpp", "kernels.hip", "runtime.hip"]
+HOP = os.path.join(PKG, "hop_latency")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -34,6 +36,15 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("hipcc failed to build libkktlu.so")
     os.replace(tmp, LIB)
+    # the hop-latency microbenchmark (an executable; bench.py runs it)
+    flags = [f for f in HIPCC_FLAGS if f not in ("-fPIC", "-shared")]
+    tmp = HOP + ".tmp"
+    cmd = [hipcc, *flags, os.path.join(CSRC, "hop_latency.hip"), "-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed to build hop_latency")
+    os.replace(tmp, HOP)
     return LIB
 
 

@@ -20,6 +20,89 @@ struct DevStats {
   int perturbed;               // a pivot was raised to the perturbation threshold
 };
 
+// Sync-free refinement: the stop test of every right-hand side runs on the
+// device and the host launches a fixed budget of iterations whose kernels
+// return at once for a stopped column.  Right-hand sides are refined in
+// groups of at most FG_MAX_COLS columns in lockstep (one triangular-solve
+// launch per group and step).
+constexpr int FG_MAX_COLS = 8;
+constexpr int FG_BLOCKS = 512;  // workgroups per column of a refinement pass
+struct FgCol {
+  int stop;       // this column's remaining iterations do nothing
+  int it;         // iterations done
+  int breakdown;  // an Arnoldi step produced w = 0
+  int conv;       // eta <= target at the last check
+  double eta, eta0, hn, beta;
+  unsigned int ticket;  // last-workgroup counter of the fused reductions
+  int pad[7];
+};
+struct FgState {
+  FgCol col[FG_MAX_COLS];
+  int stop_all;  // every column of the group stopped: gates the triangular solves
+  int nstopped;
+  // summary over the right-hand sides of the last solve
+  int it_max;
+  int not_conv;
+  unsigned long long eta_max, eta0_max;  // bit patterns (order of non-negative doubles)
+};
+struct FgParams {
+  double eta_target;
+  int min_iters;
+  int max_iters;
+};
+// Device workspace of the sync-free refinement: partial sums (FG_MAX_COLS x
+// FG_BLOCKS x 32), the two Gram-Schmidt coefficient vectors (32 per column),
+// and per column the Hessenberg matrix ((m+1) x m), rotations (m each), g
+// (m+1) and y (m).
+struct FgBufs {
+  FgState* fs;
+  double* part;
+  double* hbuf;
+  double* h2buf;
+  double* H;
+  double* cs;
+  double* sn;
+  double* gvec;
+  double* y;
+};
+
+// Launch gate: while set (non-null), the solve-path kernels launched by this
+// host thread (gathers, scatters, triangular solves, dense-block solves,
+// per-instance statistics) take the device word as an argument and return at
+// once when it is non-zero.  Set around the launches of a sync-free
+// refinement so that its triangular solves stop with the group.
+void set_launch_gate(const int* gate);
+
+void launch_fg_begin(FgState* fs, int reset_summary, hipStream_t s);
+// r = b - op(A) x for ncols columns (column stride n) and the stop test after
+// it_now iterations (first: the check after the direct solve; batch: r only,
+// the test follows in launch_fg_check_batch after the per-instance maxima).
+// (ptr, idx, pos) as for launch_residual; use_anorm1 selects ||A||_1 (op T).
+void launch_fg_resid(int n, int ncols, const int* ptr, const int* idx, const int* pos,
+                     const double* aval, const double* b, const double* x, double* r,
+                     const FgBufs& fb, const DevStats* st, int use_anorm1, int it_now, int first,
+                     int batch, const FgParams& p, hipStream_t s);
+void launch_fg_check_batch(int count, const double* inst, const FgBufs& fb, const DevStats* st,
+                           int it_now, int first, const FgParams& p, hipStream_t s);
+// start of an Arnoldi cycle: x = xt if copy, beta = ||r||, g, v0 = r / beta
+void launch_fg_restart(int n, int ncols, int m, const double* r, const double* xt, double* x,
+                       int copy, double* v0, const FgBufs& fb, hipStream_t s);
+// step j: w = op(A) z_j, h = V^T w; basis vector q of column c at V + (q * ncols + c) * n
+void launch_fg_arnoldi(int n, int ncols, int j, const int* ptr, const int* idx, const int* pos,
+                       const double* aval, const double* Zj, const double* V, double* w,
+                       const FgBufs& fb, hipStream_t s);
+// pass 0: w -= V h, h2 = V^T w; pass 1: w -= V h2, ||w||, Givens update, y
+void launch_fg_cgs(int pass, int n, int ncols, int j, int m, const double* V, double* w,
+                   const FgBufs& fb, hipStream_t s);
+// v_{j+1} = w / ||w||, xt = x + Z y (Z's vector q of column c at Z + (q * ncols + c) * n)
+void launch_fg_update(int n, int ncols, int j, int m, const double* w, double* vnext,
+                      const double* Z, const double* x, double* xt, const FgBufs& fb,
+                      hipStream_t s);
+void launch_fg_add(int n, int ncols, const double* d, double* x, const FgBufs& fb, hipStream_t s);
+// x = xt for FGMRES columns that iterated (ir = 0); summary of the group
+void launch_fg_finish(int n, int ncols, const double* xt, double* x, int ir, const FgBufs& fb,
+                      hipStream_t s);
+
 // Refactorization rows are split into at most this many bands by row length.
 constexpr int REF_MAX_BANDS = 4;
 
@@ -346,9 +429,11 @@ void launch_givens(int j, int m, const double* h, const double* h2, const double
 void launch_arnoldi_start(int n, int m, const double* r, const double* rr, double* v0, double* g,
                           hipStream_t s);
 
-// adjoint: transposes and the sampled dense-dense product on the pattern
-void launch_transpose(int rows, int cols, const double* in, double* out, hipStream_t s);
-void launch_grad_sddmm(int n, int nrhs, const int* arow_ptr, const int* acol,
-                       const double* lam_rm, const double* x_rm, double* grad, hipStream_t s);
+// adjoint: grad[p] = -sum_r lam[r][i] x[r][j] over the stored entries p = (i, j)
+// (lam, x column-major n x nrhs)
+void launch_grad_sddmm(int n, int nrhs, const int* arow_ptr, const int* acol, const double* lam,
+                       const double* x, double* grad, hipStream_t s);
+// y = x (n entries)
+void launch_copy(int n, const double* x, double* y, hipStream_t s);
 
 }  // namespace kktlu

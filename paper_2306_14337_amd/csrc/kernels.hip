@@ -14,6 +14,17 @@ namespace kktlu {
 
 namespace {
 
+// Launch gate of the solve-path kernels (set_launch_gate): every workgroup
+// reads the gate word first and returns when it is non-zero, uniformly, before
+// any barrier, ticket or store.  The word is written by an earlier kernel on
+// the same stream, so a plain load sees it.
+#define KKT_GATE(g)                   \
+  do {                                \
+    if ((g) != nullptr && *(g) != 0) return; \
+  } while (0)
+
+thread_local const int* t_gate = nullptr;
+
 constexpr int WAVE = 64;
 // k_refactor_wg: waves per row and register buffers per wave (pivot steps in
 // flight per row = their product).  Measured at 70k buses (refactorization
@@ -579,12 +590,13 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
 // lane of a group writes its row's (identical) result and flag, and lanes
 // without a row write to the spare slot n of y and ready (n + 1 entries).
 template <int MODE>
-__global__ __launch_bounds__(256) void k_trisolve_syncfree(
+__global__ __launch_bounds__(256) void k_trisolve_syncfree(const int* __restrict__ gate, 
     int n, int nchunks, const int* __restrict__ ch_start, const int* __restrict__ ch_meta,
     const int* __restrict__ rows, const int* __restrict__ rowptr, const int* __restrict__ col,
     const int* __restrict__ diag, const int* __restrict__ tptr, const int* __restrict__ trow,
     const int* __restrict__ tpos, const double* __restrict__ val, double* y, int* ready,
     SyncState* ss, int slot, int* stall) {
+  KKT_GATE(gate);
   const int lane = threadIdx.x % WAVE;
   const int epoch = ss->epoch[slot];
   unsigned int* ticket = &ss->ticket[slot];
@@ -646,12 +658,13 @@ __global__ __launch_bounds__(256) void k_trisolve_syncfree(
 // separate arrays (n + 1 entries; slot n takes idle lanes' writes).
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_trisolve_vflag(
+__global__ __launch_bounds__(256) void k_trisolve_vflag(const int* __restrict__ gate, 
     int n, int nchunks, const int* __restrict__ ch_start, const int* __restrict__ ch_meta,
     const int* __restrict__ rows, const int* __restrict__ rowptr, const int* __restrict__ col,
     const int* __restrict__ diag, const int* __restrict__ tptr, const int* __restrict__ trow,
     const int* __restrict__ tpos, const double* __restrict__ val, const double* __restrict__ c,
     double* y, SyncState* ss, int slot, int* stall) {
+  KKT_GATE(gate);
   const int lane = threadIdx.x % WAVE;
   unsigned int* ticket = &ss->ticket[slot];
   for (;;) {
@@ -830,11 +843,12 @@ __device__ __forceinline__ void seg_fetch(int lev, int nlev, const int* __restri
 }
 
 template <int MODE>
-__global__ __launch_bounds__(SEG_THREADS) void k_trisolve_seg(
+__global__ __launch_bounds__(SEG_THREADS) void k_trisolve_seg(const int* __restrict__ gate, 
     int nlev, const int* __restrict__ lev_ptr, const int* __restrict__ row,
     const int* __restrict__ ptr, const int* __restrict__ src, const int* __restrict__ vpos,
     const int* __restrict__ dpos, const double* __restrict__ val, const double* __restrict__ c,
     double* __restrict__ y) {
+  KKT_GATE(gate);
   __shared__ double ly[SEG_MAX_ROWS];
   __shared__ double part[SEG_WAVES];
   const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
@@ -1093,7 +1107,7 @@ __global__ __launch_bounds__(256) void k_dlu_update(double* T, int S, int k0,
 // NR >= nr right-hand sides (column r at c + r * ld, y + r * ld; ld = n + 1
 // for several, unused for one): every lane keeps nr sums.
 template <int MODE, int NR>
-__global__ __launch_bounds__(256) void k_trisolve_sn(
+__global__ __launch_bounds__(256) void k_trisolve_sn(const int* __restrict__ gate, 
     int n, int nr, int ld, int nchunks, const int* __restrict__ ch_start,
     const int* __restrict__ ch_meta, const int* __restrict__ ch_base, const int* __restrict__ rows,
     const int* __restrict__ split, const int* __restrict__ rowptr, const int* __restrict__ col,
@@ -1101,6 +1115,7 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(
     const int* __restrict__ tpos, const double* __restrict__ val, const double* __restrict__ c,
     double* y, SyncState* ss, int slot, int nstreams, int* stall, const int* __restrict__ xend,
     const double* __restrict__ pre) {
+  KKT_GATE(gate);
   // the block's strictly lower triangle, packed by rows: entry (g, h), h < g,
   // at g (g - 1) / 2 + h (half the LDS of a square, so all eight workgroups
   // per CU fit)
@@ -1228,13 +1243,14 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(
 // entries in the block's columns (positions xend[i] .. rowptr[i + 1]) times
 // the solution values there, final once the block is solved.  8 lanes per
 // row, rows listed in urows.
-__global__ __launch_bounds__(256) void k_udense_pre(int nu, const int* __restrict__ urows,
+__global__ __launch_bounds__(256) void k_udense_pre(const int* __restrict__ gate, int nu, const int* __restrict__ urows,
                                                     const int* __restrict__ xend,
                                                     const int* __restrict__ rowptr,
                                                     const int* __restrict__ col,
                                                     const double* __restrict__ val,
                                                     const double* __restrict__ y,
                                                     double* __restrict__ pre) {
+  KKT_GATE(gate);
   constexpr int RL = 8;
   const int lane = threadIdx.x % WAVE, g = lane / RL, gl = lane % RL;
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
@@ -1273,7 +1289,7 @@ __global__ __launch_bounds__(256) void k_udense_pre(int nu, const int* __restric
 // inputs are final): rhs[t] = c[c0 + t] - sum over the entries before split[t]
 // of row (MODE 0) / column (MODE 2) c0 + t; rhs[t] = 0 on padding rows.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_tail_ext(int c0, int s, int S, int nr, int ld,
+__global__ __launch_bounds__(256) void k_tail_ext(const int* __restrict__ gate, int c0, int s, int S, int nr, int ld,
                                                   const int* __restrict__ split,
                                                   const int* __restrict__ rowptr,
                                                   const int* __restrict__ col,
@@ -1283,6 +1299,7 @@ __global__ __launch_bounds__(256) void k_tail_ext(int c0, int s, int S, int nr, 
                                                   const double* __restrict__ val,
                                                   const double* __restrict__ c,
                                                   const double* __restrict__ y, double* rhs) {
+  KKT_GATE(gate);
   const int lane = threadIdx.x % WAVE;
   const int t = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
   const int r = blockIdx.y;
@@ -1313,9 +1330,10 @@ __global__ __launch_bounds__(256) void k_tail_ext(int c0, int s, int S, int nr, 
 constexpr int TB = 32;
 constexpr int TAIL_NR = 8;  // columns per dense-block solve launch
 template <int MODE, int NRT>
-__global__ __launch_bounds__(1024) void k_tail_trsv(const double* __restrict__ T, int S, int s,
+__global__ __launch_bounds__(1024) void k_tail_trsv(const int* __restrict__ gate, const double* __restrict__ T, int S, int s,
                                                     int c0, int nr, const double* __restrict__ rhs,
                                                     int rld, double* y, int ld) {
+  KKT_GATE(gate);
   extern __shared__ double xs[];
   constexpr bool fwd = MODE == 0 || MODE == 2;
   constexpr bool trans = MODE == 2 || MODE == 3;
@@ -1404,9 +1422,10 @@ __global__ __launch_bounds__(1024) void k_tail_trsv(const double* __restrict__ T
 // k_tail_trsv; rhs[t] (t < s) is the right-hand side of block row t, y + c0
 // the output (rows t >= s are the identity padding, x = 0, not stored).
 template <int MODE>
-__global__ __launch_bounds__(256) void k_tail_mw(const double* __restrict__ T, int S, int s,
+__global__ __launch_bounds__(256) void k_tail_mw(const int* __restrict__ gate, const double* __restrict__ T, int S, int s,
                                                  int c0, const double* __restrict__ rhs,
                                                  double* y, int* stall) {
+  KKT_GATE(gate);
   constexpr bool fwd = MODE == 0 || MODE == 2;
   constexpr bool trans = MODE == 2 || MODE == 3;
   auto M = [&](int r, int q) -> double {
@@ -1475,12 +1494,13 @@ __global__ __launch_bounds__(256) void k_tail_mw(const double* __restrict__ T, i
 // dimension ld = n + 1): each entry's NR dependency loads are in flight
 // together; the dependency depth is paid once for all columns.
 template <int MODE, int NR>
-__global__ __launch_bounds__(256) void k_trisolve_vflag_mr(
+__global__ __launch_bounds__(256) void k_trisolve_vflag_mr(const int* __restrict__ gate, 
     int n, int nr, int ld, int nchunks, const int* __restrict__ ch_start,
     const int* __restrict__ ch_meta, const int* __restrict__ rows, const int* __restrict__ rowptr,
     const int* __restrict__ col, const int* __restrict__ diag, const int* __restrict__ tptr,
     const int* __restrict__ trow, const int* __restrict__ tpos, const double* __restrict__ val,
     const double* __restrict__ c, double* y, SyncState* ss, int slot, int* stall) {
+  KKT_GATE(gate);
   const int lane = threadIdx.x % WAVE;
   unsigned int* ticket = &ss->ticket[slot];
   for (;;) {
@@ -1542,7 +1562,7 @@ __global__ __launch_bounds__(256) void k_trisolve_vflag_mr(
 
 // multi-column gather: c[r][i] = x[r][perm[i]] (x: ld n, c/y/z: ld n + 1),
 // y and z set to the sentinel; plus the sync_prep of mask
-__global__ void k_gather_sentinel_mr(int n, int nr, const int* __restrict__ perm,
+__global__ void k_gather_sentinel_mr(const int* __restrict__ gate, int n, int nr, const int* __restrict__ perm,
                                      const double* __restrict__ x, double* __restrict__ c,
                                      double* __restrict__ y, double* __restrict__ z,
                                      SyncState* ss, int mask,
@@ -1553,12 +1573,13 @@ __global__ void k_gather_sentinel_mr(int n, int nr, const int* __restrict__ perm
 // c[i] = x[perm[i]], and the two solve outputs y, z set to the sentinel
 // Rows without dependencies in the first triangle (triv[i] != 0) get their
 // final value here: y = c, or y = c / u_ii when div is set (a U^T first).
-__global__ void k_gather_sentinel(int n, const int* __restrict__ perm,
+__global__ void k_gather_sentinel(const int* __restrict__ gate, int n, const int* __restrict__ perm,
                                   const double* __restrict__ x, double* __restrict__ c,
                                   double* __restrict__ y, double* __restrict__ z, SyncState* ss,
                                   int mask, const unsigned char* __restrict__ triv,
                                   const int* __restrict__ diag, const double* __restrict__ val,
                                   int div) {
+  KKT_GATE(gate);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     const double ci = x[perm[i]];
@@ -1570,13 +1591,14 @@ __global__ void k_gather_sentinel(int n, const int* __restrict__ perm,
   if (ss && i == 0) sync_prep(ss, mask);
 }
 
-__global__ void k_gather_sentinel_mr(int n, int nr, const int* __restrict__ perm,
+__global__ void k_gather_sentinel_mr(const int* __restrict__ gate, int n, int nr, const int* __restrict__ perm,
                                      const double* __restrict__ x, double* __restrict__ c,
                                      double* __restrict__ y, double* __restrict__ z,
                                      SyncState* ss, int mask,
                                      const unsigned char* __restrict__ triv,
                                      const int* __restrict__ diag,
                                      const double* __restrict__ val, int div) {
+  KKT_GATE(gate);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (i < n && r < nr) {
@@ -1591,15 +1613,17 @@ __global__ void k_gather_sentinel_mr(int n, int nr, const int* __restrict__ perm
 }
 
 // x[r][perm[i]] = z[r][i] (z: ld n + 1, x: ld n)
-__global__ void k_scatter_mr(int n, int nr, const int* __restrict__ perm,
+__global__ void k_scatter_mr(const int* __restrict__ gate, int n, int nr, const int* __restrict__ perm,
                              const double* __restrict__ z, double* __restrict__ x) {
+  KKT_GATE(gate);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (i < n && r < nr) x[(size_t)r * n + perm[i]] = z[(size_t)r * (n + 1) + i];
 }
 
-__global__ void k_gather_prep(int n, const int* __restrict__ perm, const double* __restrict__ x,
+__global__ void k_gather_prep(const int* __restrict__ gate, int n, const int* __restrict__ perm, const double* __restrict__ x,
                               double* __restrict__ y, SyncState* ss, int mask) {
+  KKT_GATE(gate);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = x[perm[i]];
   if (ss && i == 0) sync_prep(ss, mask);
@@ -1729,11 +1753,13 @@ __global__ __launch_bounds__(256) void k_pivot_stats(int n, const int* __restric
 // Per-instance maxima of a block-diagonal batch: block t reduces rows
 // [row_off[t], row_off[t+1]) to out[3t] = max matabs (the instance's matrix
 // norm), out[3t+1] = max |r|, out[3t+2] = max |x|.
-__global__ __launch_bounds__(256) void k_seg_stats(const int* __restrict__ row_off,
+__global__ __launch_bounds__(256) void k_seg_stats(const int* __restrict__ gate,
+                                                   const int* __restrict__ row_off,
                                                    const double* __restrict__ matabs,
                                                    const double* __restrict__ r,
                                                    const double* __restrict__ x,
                                                    double* __restrict__ out) {
+  KKT_GATE(gate);
   __shared__ double red[3][256 / WAVE];
   const int t = blockIdx.x;
   const int a = row_off[t], b = row_off[t + 1];
@@ -1860,11 +1886,12 @@ __global__ __launch_bounds__(256) void k_anorm1(int n, const int* __restrict__ c
 // ---------------------------------------------------------------------------
 // Triangular solves, one wavefront per row (level-synchronous launches).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_lsolve_rows(const int* __restrict__ rows, int nrows,
+__global__ __launch_bounds__(256) void k_lsolve_rows(const int* __restrict__ gate, const int* __restrict__ rows, int nrows,
                                                      const int* __restrict__ rowptr,
                                                      const int* __restrict__ col,
                                                      const int* __restrict__ diag,
                                                      const double* __restrict__ val, double* y) {
+  KKT_GATE(gate);
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
   if (wave >= nrows) return;
   const int i = rows[wave];
@@ -1874,11 +1901,12 @@ __global__ __launch_bounds__(256) void k_lsolve_rows(const int* __restrict__ row
   if (lane == 0) y[i] -= s;
 }
 
-__global__ __launch_bounds__(256) void k_usolve_rows(const int* __restrict__ rows, int nrows,
+__global__ __launch_bounds__(256) void k_usolve_rows(const int* __restrict__ gate, const int* __restrict__ rows, int nrows,
                                                      const int* __restrict__ rowptr,
                                                      const int* __restrict__ col,
                                                      const int* __restrict__ diag,
                                                      const double* __restrict__ val, double* y) {
+  KKT_GATE(gate);
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
   if (wave >= nrows) return;
   const int i = rows[wave];
@@ -1890,11 +1918,12 @@ __global__ __launch_bounds__(256) void k_usolve_rows(const int* __restrict__ row
 }
 
 // U^T t = s: column j of U (rows i <= j, diagonal last)
-__global__ __launch_bounds__(256) void k_utsolve_cols(const int* __restrict__ cols, int ncols,
+__global__ __launch_bounds__(256) void k_utsolve_cols(const int* __restrict__ gate, const int* __restrict__ cols, int ncols,
                                                       const int* __restrict__ tptr,
                                                       const int* __restrict__ trow,
                                                       const int* __restrict__ tpos,
                                                       const double* __restrict__ val, double* y) {
+  KKT_GATE(gate);
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
   if (wave >= ncols) return;
   const int j = cols[wave];
@@ -1906,11 +1935,12 @@ __global__ __launch_bounds__(256) void k_utsolve_cols(const int* __restrict__ co
 }
 
 // L^T w = t: column j of strict L (rows i > j)
-__global__ __launch_bounds__(256) void k_ltsolve_cols(const int* __restrict__ cols, int ncols,
+__global__ __launch_bounds__(256) void k_ltsolve_cols(const int* __restrict__ gate, const int* __restrict__ cols, int ncols,
                                                       const int* __restrict__ tptr,
                                                       const int* __restrict__ trow,
                                                       const int* __restrict__ tpos,
                                                       const double* __restrict__ val, double* y) {
+  KKT_GATE(gate);
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
   if (wave >= ncols) return;
   const int j = cols[wave];
@@ -1920,13 +1950,15 @@ __global__ __launch_bounds__(256) void k_ltsolve_cols(const int* __restrict__ co
   if (lane == 0) y[j] -= s;
 }
 
-__global__ void k_gather(int n, const int* __restrict__ perm, const double* __restrict__ x,
+__global__ void k_gather(const int* __restrict__ gate, int n, const int* __restrict__ perm, const double* __restrict__ x,
                          double* __restrict__ y) {
+  KKT_GATE(gate);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = x[perm[i]];
 }
-__global__ void k_scatter(int n, const int* __restrict__ perm, const double* __restrict__ x,
+__global__ void k_scatter(const int* __restrict__ gate, int n, const int* __restrict__ perm, const double* __restrict__ x,
                           double* __restrict__ y) {
+  KKT_GATE(gate);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[perm[i]] = x[i];
 }
@@ -2103,13 +2135,14 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ ptr
 //   MODE 0  unit L:  yout_i = c_i - sum_{k<i} l_ik yin_k
 //   MODE 1  U:       yout_i = (c_i - sum_{k>i} u_ik yin_k) / u_ii
 template <int MODE>
-__global__ __launch_bounds__(256) void k_jacobi_sweep(int n, const int* __restrict__ rowptr,
+__global__ __launch_bounds__(256) void k_jacobi_sweep(const int* __restrict__ gate, int n, const int* __restrict__ rowptr,
                                                       const int* __restrict__ col,
                                                       const int* __restrict__ diag,
                                                       const double* __restrict__ val,
                                                       const double* __restrict__ c,
                                                       const double* __restrict__ yin,
                                                       double* __restrict__ yout) {
+  KKT_GATE(gate);
   const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = gridDim.x * blockDim.x / WAVE;
@@ -2197,7 +2230,8 @@ __global__ void k_scale_div(int n, const double* __restrict__ x, const double* _
 }
 
 // x += d (classical refinement step)
-__global__ void k_add(int n, const double* __restrict__ d, double* __restrict__ x) {
+__global__ void k_add(const int* __restrict__ gate, int n, const double* __restrict__ d, double* __restrict__ x) {
+  KKT_GATE(gate);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) x[t] += d[t];
 }
@@ -2246,38 +2280,34 @@ __global__ void k_arnoldi_start(int n, int m, const double* __restrict__ r,
 // ---------------------------------------------------------------------------
 // Adjoint on the pattern
 // ---------------------------------------------------------------------------
-__global__ void k_transpose(int rows, int cols, const double* __restrict__ in,
-                            double* __restrict__ out) {
-  // in: rows x cols column-major (ld = rows); out: cols x rows column-major
-  __shared__ double tile[32][33];
-  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
-  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
-    const int r = bx + threadIdx.x, c = by + k;
-    if (r < rows && c < cols) tile[k][threadIdx.x] = in[(long)c * rows + r];
-  }
-  __syncthreads();
-  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
-    const int c = by + threadIdx.x, r = bx + k;
-    if (r < rows && c < cols) out[(long)r * cols + c] = tile[threadIdx.x][k];
-  }
-}
-
-// grad[p] = -sum_r lam[i][r] * x[j][r] for p = (i, j); lam, x row-major n x nrhs
+// grad[p] = -sum_r lam[r][i] * x[r][j] for every stored p = (i, j); lam, x
+// column-major n x nrhs.  Eight lanes per row, one stored entry each; the
+// right-hand sides are summed in ascending order.
 __global__ __launch_bounds__(256) void k_grad_sddmm(int n, int nrhs, const int* __restrict__ arow,
                                                     const int* __restrict__ acol,
                                                     const double* __restrict__ lam,
                                                     const double* __restrict__ x,
                                                     double* __restrict__ grad) {
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE, lane = threadIdx.x % WAVE;
-  if (wave >= n) return;
-  const int i = wave;
-  for (int p = arow[i]; p < arow[i + 1]; p++) {
-    const int j = acol[p];
-    double s = 0.0;
-    for (int r = lane; r < nrhs; r += WAVE) s += lam[(long)i * nrhs + r] * x[(long)j * nrhs + r];
-    s = wave_sum(s);
-    if (lane == 0) grad[p] = -s;
+  const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int nw = gridDim.x * blockDim.x / WAVE;
+  for (int i = wid * (WAVE / RG) + g; i - g < n; i += nw * (WAVE / RG)) {
+    if (i >= n) continue;
+    for (int p = arow[i] + gl; p < arow[i + 1]; p += RG) {
+      const int j = acol[p];
+      double s = 0.0;
+      for (int r = 0; r < nrhs; r++) s += lam[(size_t)r * n + i] * x[(size_t)r * n + j];
+      grad[p] = -s;
+    }
   }
+}
+
+// y = x (gated: part of the solve path)
+__global__ void k_copy(const int* __restrict__ gate, int n, const double* __restrict__ x,
+                       double* __restrict__ y) {
+  KKT_GATE(gate);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) y[t] = x[t];
 }
 
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
@@ -2591,11 +2621,547 @@ __global__ __launch_bounds__(WPR* WAVE) void k_refactor_wg(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Sync-free refinement.  The stop test of every right-hand side runs on the
+// device: each residual pass finishes its maxima in the workgroup that
+// arrives last, which computes eta and raises the column's stop flag, and
+// every later refinement kernel of that column returns at once.  The host
+// therefore launches a fixed budget of iterations and never waits.  One
+// Arnoldi step (operator product, both classical Gram-Schmidt passes, Givens
+// update) is three fused passes whose dot products finish the same way, then
+// one pass forms the next basis vector and the candidate solution.  Sums over
+// workgroups are taken in a fixed order, so results do not depend on timing.
+// ---------------------------------------------------------------------------
+constexpr int FG_T = 256;  // threads per workgroup of the refinement passes
+constexpr int FG_Q = 32;   // basis vectors a dot-product pass handles at most
+
+__device__ __forceinline__ double eta_dev(double rn, double an, double xn) {
+  const double den = an * xn;
+  return den == 0.0 ? (rn == 0.0 ? 0.0 : __builtin_huge_val()) : rn / den;
+}
+
+__device__ __forceinline__ double bits_dev(unsigned long long b) {
+  return __longlong_as_double((long long)b);
+}
+
+// The workgroup that arrives last at a fused reduction.  Every workgroup has
+// stored its partial results with device-coherent stores; each thread waits
+// for its stores, then thread 0 takes a ticket.  The workgroup holding ticket
+// nb - 1 reads every partial with device-coherent loads and resets the
+// counter for the next launch (launches on one stream never overlap).
+__device__ bool fg_last_block(unsigned int* ticket, unsigned int nb) {
+  __shared__ int last;
+  stores_done();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned int t =
+        __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    last = (t == nb - 1u) ? 1 : 0;
+    if (last) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  return last != 0;
+}
+
+// Workgroup sum (fixed order), valid in thread 0.
+__device__ __forceinline__ double fg_block_sum(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();  // red may still be read by a previous call
+  if (threadIdx.x % WAVE == 0) red[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < FG_T / WAVE; q++) s += red[q];
+  return s;
+}
+
+// Last workgroup: out[q] = sum over b < nb of pc[b * FG_Q + q] for q < nq, in
+// a fixed order (eight slices of the workgroups, then the slices in order).
+__device__ void fg_reduce_q(const double* pc, int nb, int nq, double* out) {
+  __shared__ double red[FG_T];
+  const int q = threadIdx.x % FG_Q, k = threadIdx.x / FG_Q;
+  double s = 0.0;
+  if (q < nq)
+    for (int b = k; b < nb; b += FG_T / FG_Q) s += ld_coh(pc + (size_t)b * FG_Q + q);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < nq) {
+    double t = 0.0;
+    for (int kk = 0; kk < FG_T / FG_Q; kk++) t += red[kk * FG_Q + threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+}
+
+// Stop test of column c after `it_now` iterations (0: the direct solve).
+__device__ void fg_decide(FgState* fs, int c, int ncols, double eta, int it_now, int first,
+                          const FgParams& p, int stalled) {
+  FgCol* col = &fs->col[c];
+  col->eta = eta;
+  if (first) col->eta0 = eta;
+  col->it = it_now;
+  const int conv = eta <= p.eta_target ? 1 : 0;  // false for NaN
+  col->conv = conv;
+  const bool stop =
+      (conv && it_now >= p.min_iters) || col->breakdown || it_now >= p.max_iters || stalled;
+  if (stop && !col->stop) {
+    col->stop = 1;
+    if (atomicAdd(&fs->nstopped, 1) + 1 == ncols) fs->stop_all = 1;
+  }
+}
+
+__global__ void k_fg_begin(FgState* fs, int reset_summary) {
+  const int t = threadIdx.x;
+  if (t < FG_MAX_COLS) {
+    FgCol* col = &fs->col[t];
+    col->stop = 0;
+    col->it = 0;
+    col->breakdown = 0;
+    col->conv = 0;
+    col->eta = col->eta0 = col->hn = col->beta = 0.0;
+    col->ticket = 0u;
+  }
+  if (t == 0) {
+    fs->stop_all = 0;
+    fs->nstopped = 0;
+    if (reset_summary) {
+      fs->it_max = 0;
+      fs->not_conv = 0;
+      fs->eta_max = 0ull;
+      fs->eta0_max = 0ull;
+    }
+  }
+}
+
+// r = b - op(A) x for column c = blockIdx.y (all vectors column stride n), then
+// the stop test from max |r|, max |x| and ||A|| (BATCH: r only; the
+// per-instance test follows in k_fg_check_batch).  first: the check after the
+// direct solve (runs even for a stopped column and records eta0).
+template <bool BATCH>
+__global__ __launch_bounds__(FG_T) void k_fg_resid(
+    int n, const int* __restrict__ ptr, const int* __restrict__ idx, const int* __restrict__ pos,
+    const double* __restrict__ aval, const double* __restrict__ b, const double* __restrict__ x,
+    double* __restrict__ r, double* __restrict__ part, FgState* fs, const DevStats* st,
+    int use_anorm1, int ncols, int it_now, int first, FgParams p) {
+  const int c = blockIdx.y;
+  FgCol* col = &fs->col[c];
+  if (!first && ld_flag(&col->stop)) return;
+  const double* bc = b + (size_t)c * n;
+  const double* xc = x + (size_t)c * n;
+  double* rc = r + (size_t)c * n;
+  const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int nw = gridDim.x * blockDim.x / WAVE;
+  double rm = 0.0, xm = 0.0;
+  constexpr int U = 4;  // row groups per round, first loads all in flight
+  const int stride = nw * (WAVE / RG);
+  for (int r0 = wid * (WAVE / RG); r0 < n; r0 += U * stride) {
+    int ii[U], t0[U], te[U];
+    double sacc[U], av[U], xv[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      ii[u] = r0 + u * stride + g;
+      t0[u] = 0;
+      te[u] = 0;
+      if (ii[u] < n) {
+        t0[u] = ptr[ii[u]] + gl;
+        te[u] = ptr[ii[u] + 1];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      av[u] = 0.0;
+      xv[u] = 0.0;
+      if (t0[u] < te[u]) {
+        av[u] = aval[pos ? pos[t0[u]] : t0[u]];
+        xv[u] = xc[idx[t0[u]]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      sacc[u] = av[u] * xv[u];
+      for (int t = t0[u] + RG; t < te[u]; t += RG) sacc[u] += aval[pos ? pos[t] : t] * xc[idx[t]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const double su = group_sum(sacc[u]);
+      const int i = ii[u];
+      if (i < n) {
+        const double ri = bc[i] - su;
+        if (gl == 0) rc[i] = ri;
+        rm = nanmax(rm, fabs(ri));
+        xm = nanmax(xm, fabs(xc[i]));
+      }
+    }
+  }
+  if (BATCH) return;
+  __shared__ double red[2][FG_T / WAVE];
+  rm = block_nanmax(rm, red[0]);
+  xm = block_nanmax(xm, red[1]);
+  double* pc = part + (size_t)c * gridDim.x * 2;
+  if (threadIdx.x == 0) {
+    st_coh(pc + 2 * blockIdx.x, rm);
+    st_coh(pc + 2 * blockIdx.x + 1, xm);
+  }
+  if (!fg_last_block(&col->ticket, gridDim.x)) return;
+  double a = 0.0, bm = 0.0;
+  for (int q = threadIdx.x; q < (int)gridDim.x; q += FG_T) {
+    a = nanmax(a, ld_coh(pc + 2 * q));
+    bm = nanmax(bm, ld_coh(pc + 2 * q + 1));
+  }
+  a = block_nanmax(a, red[0]);
+  bm = block_nanmax(bm, red[1]);
+  if (threadIdx.x == 0) {
+    const double an = bits_dev(use_anorm1 ? st->anorm1 : st->anorm);
+    fg_decide(fs, c, ncols, eta_dev(a, an, bm), it_now, first, p, ld_flag(&st->stall));
+  }
+}
+
+// Stop test of a block-diagonal batch (one column): eta = the largest
+// instance eta from the per-instance maxima (anorm, max |r|, max |x|).
+__global__ __launch_bounds__(FG_T) void k_fg_check_batch(int count, const double* __restrict__ inst,
+                                                          FgState* fs, const DevStats* st,
+                                                          int it_now, int first, FgParams p) {
+  if (!first && ld_flag(&fs->col[0].stop)) return;
+  __shared__ double red[FG_T / WAVE];
+  double e = 0.0;
+  for (int t = threadIdx.x; t < count; t += FG_T)
+    e = nanmax(e, eta_dev(inst[3 * t + 1], inst[3 * t], inst[3 * t + 2]));
+  e = block_nanmax(e, red);
+  if (threadIdx.x == 0) fg_decide(fs, 0, 1, e, it_now, first, p, ld_flag(&st->stall));
+}
+
+// Start of an Arnoldi cycle: x = xt (copy: the cycle continues from the last
+// candidate, whose residual r holds), beta = ||r||, g = (beta, 0, ...).
+__global__ __launch_bounds__(FG_T) void k_fg_restart(int n, int m, const double* __restrict__ r,
+                                                     const double* __restrict__ xt,
+                                                     double* __restrict__ x, int copy,
+                                                     double* __restrict__ part,
+                                                     double* __restrict__ gvec, FgState* fs) {
+  const int c = blockIdx.y;
+  FgCol* col = &fs->col[c];
+  if (ld_flag(&col->stop)) return;
+  const size_t o = (size_t)c * n;
+  double acc = 0.0;
+  for (int t = blockIdx.x * FG_T + threadIdx.x; t < n; t += gridDim.x * FG_T) {
+    if (copy) x[o + t] = xt[o + t];
+    const double v = r[o + t];
+    acc += v * v;
+  }
+  __shared__ double red[FG_T / WAVE];
+  const double sb = fg_block_sum(acc, red);
+  double* pc = part + (size_t)c * gridDim.x;
+  if (threadIdx.x == 0) st_coh(pc + blockIdx.x, sb);
+  if (!fg_last_block(&col->ticket, gridDim.x)) return;
+  double a = 0.0;
+  for (int q = threadIdx.x; q < (int)gridDim.x; q += FG_T) a += ld_coh(pc + q);
+  a = fg_block_sum(a, red);
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(a);
+    col->beta = beta;
+    double* gc = gvec + (size_t)c * (m + 1);
+    gc[0] = beta;
+    for (int i = 1; i <= m; i++) gc[i] = 0.0;
+  }
+}
+
+// v0 = r / beta
+__global__ __launch_bounds__(FG_T) void k_fg_v0(int n, const double* __restrict__ r,
+                                                double* __restrict__ v0, const FgState* fs) {
+  const int c = blockIdx.y;
+  if (ld_flag(&fs->col[c].stop)) return;
+  const double beta = fs->col[c].beta;
+  const size_t o = (size_t)c * n;
+  for (int t = blockIdx.x * FG_T + threadIdx.x; t < n; t += gridDim.x * FG_T)
+    v0[o + t] = beta > 0.0 ? r[o + t] / beta : 0.0;
+}
+
+// Arnoldi step j, first pass: w = op(A) z_j and h[q] = v_q . w for q <= j.
+// The 8 lanes of a row all hold w_i after the group sum; lane gl takes the
+// basis vectors q = gl, gl + 8, gl + 16, gl + 24.  Basis vector q of column
+// c starts at V + (q * g + c) * n.
+__global__ __launch_bounds__(FG_T) void k_fg_arnoldi(
+    int n, int g, int j, const int* __restrict__ ptr, const int* __restrict__ idx,
+    const int* __restrict__ pos, const double* __restrict__ aval, const double* __restrict__ Zj,
+    const double* __restrict__ V, double* __restrict__ w, double* __restrict__ part,
+    double* __restrict__ hbuf, FgState* fs) {
+  const int c = blockIdx.y;
+  FgCol* col = &fs->col[c];
+  if (ld_flag(&col->stop)) return;
+  const double* zc = Zj + (size_t)c * n;
+  double* wc = w + (size_t)c * n;
+  const double* vc = V + (size_t)c * n;
+  const size_t vs = (size_t)g * n;
+  const int lane = threadIdx.x % WAVE, grp = lane / RG, gl = lane % RG;
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int nw = gridDim.x * blockDim.x / WAVE;
+  double acc[FG_Q / RG] = {0.0, 0.0, 0.0, 0.0};
+  for (int i0 = wid * (WAVE / RG); i0 < n; i0 += nw * (WAVE / RG)) {
+    const int i = i0 + grp;
+    double sacc = 0.0;
+    if (i < n)
+      for (int t = ptr[i] + gl; t < ptr[i + 1]; t += RG) sacc += aval[pos ? pos[t] : t] * zc[idx[t]];
+    const double wi = group_sum(sacc);
+    if (i < n) {
+      if (gl == 0) wc[i] = wi;
+#pragma unroll
+      for (int k = 0; k < FG_Q / RG; k++) {
+        const int q = gl + RG * k;
+        if (q <= j) acc[k] += vc[q * vs + i] * wi;
+      }
+    }
+  }
+  // lanes with the same gl (one per row group of the wave) hold the same q
+#pragma unroll
+  for (int k = 0; k < FG_Q / RG; k++)
+    for (int off = RG; off < WAVE; off <<= 1) acc[k] += __shfl_xor(acc[k], off, WAVE);
+  __shared__ double red[FG_T / WAVE][FG_Q];
+  const int wv = threadIdx.x / WAVE;
+  if (lane < RG)
+#pragma unroll
+    for (int k = 0; k < FG_Q / RG; k++) red[wv][lane + RG * k] = acc[k];
+  __syncthreads();
+  double* pc = part + (size_t)c * gridDim.x * FG_Q;
+  if ((int)threadIdx.x <= j) {
+    double s = 0.0;
+    for (int q = 0; q < FG_T / WAVE; q++) s += red[q][threadIdx.x];
+    st_coh(pc + (size_t)blockIdx.x * FG_Q + threadIdx.x, s);
+  }
+  if (!fg_last_block(&col->ticket, gridDim.x)) return;
+  fg_reduce_q(pc, gridDim.x, j + 1, hbuf + c * FG_Q);
+}
+
+// Gram-Schmidt passes of step j.  MODE 0: w -= V h (h from the first pass),
+// then h2[q] = v_q . w.  MODE 1: w -= V h2, then ||w||^2, and the last
+// workgroup updates the least-squares problem: Hessenberg column j = h + h2,
+// ||w|| below it, the earlier rotations applied, rotation j built, g rotated
+// and y solved (j + 1 entries).  H is column-major (m + 1) x m per column.
+template <int MODE>
+__global__ __launch_bounds__(FG_T) void k_fg_cgs(
+    int n, int g, int j, int m, const double* __restrict__ V, double* __restrict__ w,
+    double* __restrict__ part, const double* __restrict__ hb, double* __restrict__ h2b,
+    double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
+    double* __restrict__ gvec, double* __restrict__ yv, FgState* fs) {
+  const int c = blockIdx.y;
+  FgCol* col = &fs->col[c];
+  if (ld_flag(&col->stop)) return;
+  const double* vc = V + (size_t)c * n;
+  const size_t vs = (size_t)g * n;
+  double* wc = w + (size_t)c * n;
+  const double* hin = (MODE == 0 ? hb : h2b) + c * FG_Q;
+  double hc[FG_Q];
+#pragma unroll
+  for (int q = 0; q < FG_Q; q++) hc[q] = q <= j ? hin[q] : 0.0;
+  double acc[MODE == 0 ? FG_Q : 1];
+#pragma unroll
+  for (int q = 0; q < (MODE == 0 ? FG_Q : 1); q++) acc[q] = 0.0;
+  for (int t = blockIdx.x * FG_T + threadIdx.x; t < n; t += gridDim.x * FG_T) {
+    double wt = wc[t];
+#pragma unroll
+    for (int q = 0; q < FG_Q; q++)
+      if (q <= j) wt -= hc[q] * vc[q * vs + t];
+    wc[t] = wt;
+    if (MODE == 0) {
+#pragma unroll
+      for (int q = 0; q < FG_Q; q++)
+        if (q <= j) acc[q] += vc[q * vs + t] * wt;
+    } else {
+      acc[0] += wt * wt;
+    }
+  }
+  if (MODE == 0) {
+    __shared__ double red[FG_T / WAVE][FG_Q];
+    const int wv = threadIdx.x / WAVE;
+#pragma unroll
+    for (int q = 0; q < FG_Q; q++)
+      if (q <= j) {
+        const double sq = wave_sum(acc[q]);
+        if (threadIdx.x % WAVE == 0) red[wv][q] = sq;
+      }
+    __syncthreads();
+    double* pc = part + (size_t)c * gridDim.x * FG_Q;
+    if ((int)threadIdx.x <= j) {
+      double s = 0.0;
+      for (int q = 0; q < FG_T / WAVE; q++) s += red[q][threadIdx.x];
+      st_coh(pc + (size_t)blockIdx.x * FG_Q + threadIdx.x, s);
+    }
+    if (!fg_last_block(&col->ticket, gridDim.x)) return;
+    fg_reduce_q(pc, gridDim.x, j + 1, h2b + c * FG_Q);
+  } else {
+    __shared__ double red[FG_T / WAVE];
+    const double sb = fg_block_sum(acc[0], red);
+    double* pc = part + (size_t)c * gridDim.x;
+    if (threadIdx.x == 0) st_coh(pc + blockIdx.x, sb);
+    if (!fg_last_block(&col->ticket, gridDim.x)) return;
+    double a = 0.0;
+    for (int q = threadIdx.x; q < (int)gridDim.x; q += FG_T) a += ld_coh(pc + q);
+    a = fg_block_sum(a, red);
+    if (threadIdx.x != 0) return;
+    double* Hc = H + (size_t)c * (m + 1) * m;
+    double* csc = cs + (size_t)c * m;
+    double* snc = sn + (size_t)c * m;
+    double* gc = gvec + (size_t)c * (m + 1);
+    double* yc = yv + (size_t)c * m;
+    double* Hj = Hc + (size_t)j * (m + 1);
+    for (int i = 0; i <= j; i++) Hj[i] = hb[c * FG_Q + i] + h2b[c * FG_Q + i];
+    const double hn = sqrt(a);
+    col->hn = hn;
+    if (!(hn > 0.0)) col->breakdown = 1;
+    Hj[j + 1] = hn;
+    for (int i = 0; i < j; i++) {
+      const double p0 = Hj[i], p1 = Hj[i + 1];
+      Hj[i] = csc[i] * p0 + snc[i] * p1;
+      Hj[i + 1] = -snc[i] * p0 + csc[i] * p1;
+    }
+    const double den = hypot(Hj[j], Hj[j + 1]);
+    csc[j] = den > 0.0 ? Hj[j] / den : 1.0;
+    snc[j] = den > 0.0 ? Hj[j + 1] / den : 0.0;
+    Hj[j] = den;
+    Hj[j + 1] = 0.0;
+    gc[j + 1] = -snc[j] * gc[j];
+    gc[j] = csc[j] * gc[j];
+    for (int i = j; i >= 0; i--) {
+      double s = gc[i];
+      for (int t = i + 1; t <= j; t++) s -= Hc[(size_t)t * (m + 1) + i] * yc[t];
+      yc[i] = s / Hc[(size_t)i * (m + 1) + i];
+    }
+  }
+}
+
+// v_{j+1} = w / ||w|| (0 after a breakdown) and the candidate xt = x + Z y.
+__global__ __launch_bounds__(FG_T) void k_fg_update(int n, int g, int j, int m,
+                                                    const double* __restrict__ w,
+                                                    double* __restrict__ vnext,
+                                                    const double* __restrict__ Z,
+                                                    const double* __restrict__ x,
+                                                    double* __restrict__ xt,
+                                                    const double* __restrict__ yv,
+                                                    const FgState* fs) {
+  const int c = blockIdx.y;
+  if (ld_flag(&fs->col[c].stop)) return;
+  const double hn = fs->col[c].hn;
+  double yc[FG_Q];
+#pragma unroll
+  for (int q = 0; q < FG_Q; q++) yc[q] = q <= j ? yv[(size_t)c * m + q] : 0.0;
+  const size_t o = (size_t)c * n, zs = (size_t)g * n;
+  for (int t = blockIdx.x * FG_T + threadIdx.x; t < n; t += gridDim.x * FG_T) {
+    vnext[o + t] = hn > 0.0 ? w[o + t] / hn : 0.0;
+    double s = x[o + t];
+#pragma unroll
+    for (int q = 0; q < FG_Q; q++)
+      if (q <= j) s += yc[q] * Z[q * zs + o + t];
+    xt[o + t] = s;
+  }
+}
+
+// classical refinement step x += d for a running column
+__global__ __launch_bounds__(FG_T) void k_fg_add(int n, const double* __restrict__ d,
+                                                 double* __restrict__ x, const FgState* fs) {
+  const int c = blockIdx.y;
+  if (ld_flag(&fs->col[c].stop)) return;
+  const size_t o = (size_t)c * n;
+  for (int t = blockIdx.x * FG_T + threadIdx.x; t < n; t += gridDim.x * FG_T) x[o + t] += d[o + t];
+}
+
+// End of a group: FGMRES columns that iterated take the last candidate; every
+// column folds its iterations and etas into the solve's summary.
+__global__ __launch_bounds__(FG_T) void k_fg_finish(int n, const double* __restrict__ xt,
+                                                    double* __restrict__ x, int ir, FgState* fs) {
+  const int c = blockIdx.y;
+  const FgCol* col = &fs->col[c];
+  const int it = col->it;
+  const size_t o = (size_t)c * n;
+  if (!ir && it > 0)
+    for (int t = blockIdx.x * FG_T + threadIdx.x; t < n; t += gridDim.x * FG_T) x[o + t] = xt[o + t];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    atomicMax(&fs->it_max, it);
+    if (!col->conv) atomicOr(&fs->not_conv, 1);
+    atomicMax(&fs->eta_max, dbits(col->eta));
+    atomicMax(&fs->eta0_max, dbits(col->eta0));
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+void set_launch_gate(const int* gate) { t_gate = gate; }
+
+namespace {
+// refinement passes: elementwise grids (four elements per thread at least)
+// and row grids (eight lanes per row, four row groups per round)
+int fg_grid(int n) { return std::max(1, std::min(FG_BLOCKS, cdiv(n, FG_T * 4))); }
+int fg_rows_grid(int n) {
+  return std::max(1, std::min(FG_BLOCKS, cdiv(n, (FG_T / WAVE) * (WAVE / RG) * 4)));
+}
+}  // namespace
+
+void launch_fg_begin(FgState* fs, int reset_summary, hipStream_t s) {
+  hipLaunchKernelGGL(k_fg_begin, dim3(1), dim3(64), 0, s, fs, reset_summary);
+}
+
+void launch_fg_resid(int n, int ncols, const int* ptr, const int* idx, const int* pos,
+                     const double* aval, const double* b, const double* x, double* r,
+                     const FgBufs& fb, const DevStats* st, int use_anorm1, int it_now, int first,
+                     int batch, const FgParams& p, hipStream_t s) {
+  const dim3 grid(fg_rows_grid(n), ncols);
+  if (batch)
+    hipLaunchKernelGGL(k_fg_resid<true>, grid, dim3(FG_T), 0, s, n, ptr, idx, pos, aval, b, x, r,
+                       fb.part, fb.fs, st, use_anorm1, ncols, it_now, first, p);
+  else
+    hipLaunchKernelGGL(k_fg_resid<false>, grid, dim3(FG_T), 0, s, n, ptr, idx, pos, aval, b, x, r,
+                       fb.part, fb.fs, st, use_anorm1, ncols, it_now, first, p);
+}
+
+void launch_fg_check_batch(int count, const double* inst, const FgBufs& fb, const DevStats* st,
+                           int it_now, int first, const FgParams& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_fg_check_batch, dim3(1), dim3(FG_T), 0, s, count, inst, fb.fs, st, it_now,
+                     first, p);
+}
+
+void launch_fg_restart(int n, int ncols, int m, const double* r, const double* xt, double* x,
+                       int copy, double* v0, const FgBufs& fb, hipStream_t s) {
+  const dim3 grid(fg_grid(n), ncols);
+  hipLaunchKernelGGL(k_fg_restart, grid, dim3(FG_T), 0, s, n, m, r, xt, x, copy, fb.part, fb.gvec,
+                     fb.fs);
+  hipLaunchKernelGGL(k_fg_v0, grid, dim3(FG_T), 0, s, n, r, v0, (const FgState*)fb.fs);
+}
+
+void launch_fg_arnoldi(int n, int ncols, int j, const int* ptr, const int* idx, const int* pos,
+                       const double* aval, const double* Zj, const double* V, double* w,
+                       const FgBufs& fb, hipStream_t s) {
+  hipLaunchKernelGGL(k_fg_arnoldi, dim3(fg_rows_grid(n), ncols), dim3(FG_T), 0, s, n, ncols, j,
+                     ptr, idx, pos, aval, Zj, V, w, fb.part, fb.hbuf, fb.fs);
+}
+
+void launch_fg_cgs(int pass, int n, int ncols, int j, int m, const double* V, double* w,
+                   const FgBufs& fb, hipStream_t s) {
+  const dim3 grid(fg_grid(n), ncols);
+  if (pass == 0)
+    hipLaunchKernelGGL(k_fg_cgs<0>, grid, dim3(FG_T), 0, s, n, ncols, j, m, V, w, fb.part,
+                       (const double*)fb.hbuf, fb.h2buf, fb.H, fb.cs, fb.sn, fb.gvec, fb.y, fb.fs);
+  else
+    hipLaunchKernelGGL(k_fg_cgs<1>, grid, dim3(FG_T), 0, s, n, ncols, j, m, V, w, fb.part,
+                       (const double*)fb.hbuf, fb.h2buf, fb.H, fb.cs, fb.sn, fb.gvec, fb.y, fb.fs);
+}
+
+void launch_fg_update(int n, int ncols, int j, int m, const double* w, double* vnext,
+                      const double* Z, const double* x, double* xt, const FgBufs& fb,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_fg_update, dim3(fg_grid(n), ncols), dim3(FG_T), 0, s, n, ncols, j, m, w,
+                     vnext, Z, x, xt, (const double*)fb.y, (const FgState*)fb.fs);
+}
+
+void launch_fg_add(int n, int ncols, const double* d, double* x, const FgBufs& fb, hipStream_t s) {
+  hipLaunchKernelGGL(k_fg_add, dim3(fg_grid(n), ncols), dim3(FG_T), 0, s, n, d, x,
+                     (const FgState*)fb.fs);
+}
+
+void launch_fg_finish(int n, int ncols, const double* xt, double* x, int ir, const FgBufs& fb,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_fg_finish, dim3(fg_grid(n), ncols), dim3(FG_T), 0, s, n, xt, x, ir, fb.fs);
+}
+
 void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxlen,
                           const double* aval, DevStats* st, double prel, hipStream_t s) {
   if (nrows <= 0) return;
@@ -2641,7 +3207,7 @@ void launch_copy_anorm(int n, const int* arow, const int*, const double* src, do
 
 void launch_seg_stats(int count, const int* row_off, const double* matabs, const double* r,
                       const double* x, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_seg_stats, dim3(count), dim3(256), 0, s, row_off, matabs, r, x, out);
+  hipLaunchKernelGGL(k_seg_stats, dim3(count), dim3(256), 0, s, t_gate, row_off, matabs, r, x, out);
 }
 
 void launch_fill_sentinel(double* p, long long count, hipStream_t s) {
@@ -2808,7 +3374,7 @@ void launch_trisolve_syncfree(int mode, const LUView& lu, const ChunkSched& cs, 
   }
   const int grid = std::max(1, std::min(ncu * cs.blocks_per_cu, cdiv(cs.nchunks, 4)));
 #define TS_LAUNCH(M)                                                                            \
-  hipLaunchKernelGGL(k_trisolve_syncfree<M>, dim3(grid), dim3(256), 0, s, lu.n, cs.nchunks,       \
+  hipLaunchKernelGGL(k_trisolve_syncfree<M>, dim3(grid), dim3(256), 0, s, t_gate, lu.n, cs.nchunks,       \
                      cs.start, \
                      cs.meta, cs.rows, lu.rowptr, lu.col, lu.diag, tptr, trow, tpos, lu.val, y, \
                      ready, ss, slot, stall)
@@ -2834,7 +3400,7 @@ void launch_trisolve_vflag(int mode, const LUView& lu, const ChunkSched& cs, con
   }
   const int grid = std::max(1, std::min(ncu * cs.blocks_per_cu, cdiv(cs.nchunks, 4)));
 #define TV_LAUNCH(M)                                                                          \
-  hipLaunchKernelGGL(k_trisolve_vflag<M>, dim3(grid), dim3(256), 0, s, lu.n, cs.nchunks,      \
+  hipLaunchKernelGGL(k_trisolve_vflag<M>, dim3(grid), dim3(256), 0, s, t_gate, lu.n, cs.nchunks,      \
                      cs.start, cs.meta, cs.rows, lu.rowptr, lu.col, lu.diag, tptr, trow, tpos, \
                      lu.val, c, y, ss, slot, stall)
   switch (mode) {
@@ -2860,7 +3426,7 @@ void launch_trisolve_vflag_mr(int mode, int nr, const LUView& lu, const ChunkSch
   const int grid = std::max(1, std::min(ncu * cs.blocks_per_cu, cdiv(cs.nchunks, 4)));
   const int ld = lu.n + 1;
 #define TM_LAUNCH(M, R)                                                                        \
-  hipLaunchKernelGGL((k_trisolve_vflag_mr<M, R>), dim3(grid), dim3(256), 0, s, lu.n, nr, ld,   \
+  hipLaunchKernelGGL((k_trisolve_vflag_mr<M, R>), dim3(grid), dim3(256), 0, s, t_gate, lu.n, nr, ld,   \
                      cs.nchunks, cs.start, cs.meta, cs.rows, lu.rowptr, lu.col, lu.diag, tptr, \
                      trow, tpos, lu.val, c, y, ss, slot, stall)
 #define TM_MODES(R)                 \
@@ -2950,7 +3516,7 @@ void launch_trisolve_sn(int mode, int nr, const LUView& lu, const SnSched& sn, c
   const int nstreams = std::min(TICKET_STREAMS, grid);
   const int ld = lu.n + 1;
 #define SN_LAUNCH(M, R)                                                                         \
-  hipLaunchKernelGGL((k_trisolve_sn<M, R>), dim3(grid), dim3(256), 0, s, lu.n, nr, ld,          \
+  hipLaunchKernelGGL((k_trisolve_sn<M, R>), dim3(grid), dim3(256), 0, s, t_gate, lu.n, nr, ld,          \
                      sn.nchunks, sn.start, sn.meta, sn.base, sn.rows, sn.split, lu.rowptr,       \
                      lu.col, lu.diag, tptr, trow, tpos, lu.val, c, y, ss, slot, nstreams, stall, \
                      xend, pre)
@@ -2985,10 +3551,10 @@ void launch_tail_solve(int mode, int nr, const LUView& lu, const double* T, int 
     int rld = ld;
     if (mode == 0 || mode == 2) {
       if (mode == 0)
-        hipLaunchKernelGGL(k_tail_ext<0>, dim3(cdiv(S, 4), k), dim3(256), 0, st, c0, s, S, k, ld,
+        hipLaunchKernelGGL(k_tail_ext<0>, dim3(cdiv(S, 4), k), dim3(256), 0, st, t_gate, c0, s, S, k, ld,
                            split, lu.rowptr, lu.col, tptr, trow, tpos, lu.val, cr, yr, rhs_buf);
       else
-        hipLaunchKernelGGL(k_tail_ext<2>, dim3(cdiv(S, 4), k), dim3(256), 0, st, c0, s, S, k, ld,
+        hipLaunchKernelGGL(k_tail_ext<2>, dim3(cdiv(S, 4), k), dim3(256), 0, st, t_gate, c0, s, S, k, ld,
                            split, lu.rowptr, lu.col, tptr, trow, tpos, lu.val, cr, yr, rhs_buf);
       rhs = rhs_buf;
       rld = S;
@@ -3006,7 +3572,7 @@ void launch_tail_solve(int mode, int nr, const LUView& lu, const double* T, int 
     }
 #undef TT_ATTR
 #define TT_LAUNCH(M, R)                                                                          \
-  hipLaunchKernelGGL((k_tail_trsv<M, R>), dim3(1), dim3(1024), shm, st, T, S, s, c0, k, rhs, rld, \
+  hipLaunchKernelGGL((k_tail_trsv<M, R>), dim3(1), dim3(1024), shm, st, t_gate, T, S, s, c0, k, rhs, rld, \
                      yr, ld)
 #define TT_MODES(R)                 \
   switch (mode) {                   \
@@ -3029,7 +3595,7 @@ void launch_udense_pre(int nu, const int* urows, const int* xend, const LUView& 
                        double* pre, hipStream_t st) {
   if (nu <= 0) return;
   hipLaunchKernelGGL(k_udense_pre, dim3(std::max(1, std::min(cdiv(nu, 32), 2048))), dim3(256), 0,
-                     st, nu, urows, xend, lu.rowptr, lu.col, lu.val, y, pre);
+                     st, t_gate, nu, urows, xend, lu.rowptr, lu.col, lu.val, y, pre);
 }
 
 void launch_tail_solve_mw(int mode, const LUView& lu, const double* T, int S, int s, int c0,
@@ -3041,26 +3607,26 @@ void launch_tail_solve_mw(int mode, const LUView& lu, const double* T, int S, in
   const double* rhs = c + c0;
   if (mode == 0 || mode == 2) {
     if (mode == 0)
-      hipLaunchKernelGGL(k_tail_ext<0>, dim3(cdiv(S, 4), 1), dim3(256), 0, st, c0, s, S, 1, ld,
+      hipLaunchKernelGGL(k_tail_ext<0>, dim3(cdiv(S, 4), 1), dim3(256), 0, st, t_gate, c0, s, S, 1, ld,
                          split, lu.rowptr, lu.col, tptr, trow, tpos, lu.val, c, y, rhs_buf);
     else
-      hipLaunchKernelGGL(k_tail_ext<2>, dim3(cdiv(S, 4), 1), dim3(256), 0, st, c0, s, S, 1, ld,
+      hipLaunchKernelGGL(k_tail_ext<2>, dim3(cdiv(S, 4), 1), dim3(256), 0, st, t_gate, c0, s, S, 1, ld,
                          split, lu.rowptr, lu.col, tptr, trow, tpos, lu.val, c, y, rhs_buf);
     rhs = rhs_buf;
   }
   const int nb = S / TB;
   switch (mode) {
     case 0:
-      hipLaunchKernelGGL(k_tail_mw<0>, dim3(nb), dim3(256), 0, st, T, S, s, c0, rhs, y, stall);
+      hipLaunchKernelGGL(k_tail_mw<0>, dim3(nb), dim3(256), 0, st, t_gate, T, S, s, c0, rhs, y, stall);
       break;
     case 1:
-      hipLaunchKernelGGL(k_tail_mw<1>, dim3(nb), dim3(256), 0, st, T, S, s, c0, rhs, y, stall);
+      hipLaunchKernelGGL(k_tail_mw<1>, dim3(nb), dim3(256), 0, st, t_gate, T, S, s, c0, rhs, y, stall);
       break;
     case 2:
-      hipLaunchKernelGGL(k_tail_mw<2>, dim3(nb), dim3(256), 0, st, T, S, s, c0, rhs, y, stall);
+      hipLaunchKernelGGL(k_tail_mw<2>, dim3(nb), dim3(256), 0, st, t_gate, T, S, s, c0, rhs, y, stall);
       break;
     default:
-      hipLaunchKernelGGL(k_tail_mw<3>, dim3(nb), dim3(256), 0, st, T, S, s, c0, rhs, y, stall);
+      hipLaunchKernelGGL(k_tail_mw<3>, dim3(nb), dim3(256), 0, st, t_gate, T, S, s, c0, rhs, y, stall);
       break;
   }
 }
@@ -3069,7 +3635,7 @@ void launch_trisolve_seg(int mode, const SegSched& sg, const double* val, const 
                          double* y, hipStream_t s) {
   if (sg.nlev <= 0) return;
 #define SG_LAUNCH(M)                                                                             \
-  hipLaunchKernelGGL(k_trisolve_seg<M>, dim3(1), dim3(SEG_THREADS), 0, s, sg.nlev, sg.lev_ptr, \
+  hipLaunchKernelGGL(k_trisolve_seg<M>, dim3(1), dim3(SEG_THREADS), 0, s, t_gate, sg.nlev, sg.lev_ptr, \
                      sg.row, sg.ptr, sg.src, sg.vpos, sg.dpos, val, c, y)
   switch (mode) {
     case 0: SG_LAUNCH(0); break;
@@ -3084,12 +3650,12 @@ void launch_gather_sentinel_mr(int n, int nr, const int* perm, const double* x, 
                                double* y, double* z, SyncState* ss, int mask, hipStream_t s,
                                const unsigned char* triv, const int* diag, const double* val,
                                int div) {
-  hipLaunchKernelGGL(k_gather_sentinel_mr, dim3(cdiv(n, 256), nr), dim3(256), 0, s, n, nr, perm,
+  hipLaunchKernelGGL(k_gather_sentinel_mr, dim3(cdiv(n, 256), nr), dim3(256), 0, s, t_gate, n, nr, perm,
                      x, c, y, z, ss, mask, triv, diag, val, div);
 }
 
 void launch_scatter_mr(int n, int nr, const int* perm, const double* z, double* x, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter_mr, dim3(cdiv(n, 256), nr), dim3(256), 0, s, n, nr, perm, z, x);
+  hipLaunchKernelGGL(k_scatter_mr, dim3(cdiv(n, 256), nr), dim3(256), 0, s, t_gate, n, nr, perm, z, x);
 }
 
 void launch_residual_mr(int n, int nr, const int* ptr, const int* idx, const int* pos,
@@ -3104,7 +3670,7 @@ void launch_gather_sentinel(int n, const int* perm, const double* x, double* c, 
                             double* z, SyncState* ss, int mask, hipStream_t s,
                             const unsigned char* triv, const int* diag, const double* val,
                             int div) {
-  hipLaunchKernelGGL(k_gather_sentinel, dim3(cdiv(n, 256)), dim3(256), 0, s, n, perm, x, c, y, z,
+  hipLaunchKernelGGL(k_gather_sentinel, dim3(cdiv(n, 256)), dim3(256), 0, s, t_gate, n, perm, x, c, y, z,
                      ss, mask, triv, diag, val, div);
 }
 
@@ -3114,7 +3680,7 @@ void launch_sync_prep(SyncState* ss, int mask, hipStream_t s) {
 
 void launch_gather_prep(int n, const int* perm, const double* x, double* y, SyncState* ss,
                         int mask, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_prep, dim3(cdiv(n, 256)), dim3(256), 0, s, n, perm, x, y, ss, mask);
+  hipLaunchKernelGGL(k_gather_prep, dim3(cdiv(n, 256)), dim3(256), 0, s, t_gate, n, perm, x, y, ss, mask);
 }
 
 void launch_anorm1(int n, const int* cptr, const int* cpos, const double* aval, DevStats* st,
@@ -3130,36 +3696,36 @@ void launch_reset_stats(DevStats* st, int what, hipStream_t s) {
 void launch_lsolve_rows(const LUView& lu, const int* rows, int nrows, int, double* y,
                         hipStream_t s) {
   if (nrows <= 0) return;
-  hipLaunchKernelGGL(k_lsolve_rows, dim3(cdiv((long)nrows * WAVE, 256)), dim3(256), 0, s, rows,
+  hipLaunchKernelGGL(k_lsolve_rows, dim3(cdiv((long)nrows * WAVE, 256)), dim3(256), 0, s, t_gate, rows,
                      nrows, lu.rowptr, lu.col, lu.diag, lu.val, y);
 }
 
 void launch_usolve_rows(const LUView& lu, const int* rows, int nrows, int, double* y,
                         hipStream_t s) {
   if (nrows <= 0) return;
-  hipLaunchKernelGGL(k_usolve_rows, dim3(cdiv((long)nrows * WAVE, 256)), dim3(256), 0, s, rows,
+  hipLaunchKernelGGL(k_usolve_rows, dim3(cdiv((long)nrows * WAVE, 256)), dim3(256), 0, s, t_gate, rows,
                      nrows, lu.rowptr, lu.col, lu.diag, lu.val, y);
 }
 
 void launch_utsolve_cols(const LUView& lu, const int* cols, int ncols, const int* tptr,
                          const int* trow, const int* tpos, double* y, hipStream_t s) {
   if (ncols <= 0) return;
-  hipLaunchKernelGGL(k_utsolve_cols, dim3(cdiv((long)ncols * WAVE, 256)), dim3(256), 0, s, cols,
+  hipLaunchKernelGGL(k_utsolve_cols, dim3(cdiv((long)ncols * WAVE, 256)), dim3(256), 0, s, t_gate, cols,
                      ncols, tptr, trow, tpos, lu.val, y);
 }
 
 void launch_ltsolve_cols(const LUView& lu, const int* cols, int ncols, const int* tptr,
                          const int* trow, const int* tpos, double* y, hipStream_t s) {
   if (ncols <= 0) return;
-  hipLaunchKernelGGL(k_ltsolve_cols, dim3(cdiv((long)ncols * WAVE, 256)), dim3(256), 0, s, cols,
+  hipLaunchKernelGGL(k_ltsolve_cols, dim3(cdiv((long)ncols * WAVE, 256)), dim3(256), 0, s, t_gate, cols,
                      ncols, tptr, trow, tpos, lu.val, y);
 }
 
 void launch_gather(int n, const int* perm, const double* x, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather, dim3(cdiv(n, 256)), dim3(256), 0, s, n, perm, x, y);
+  hipLaunchKernelGGL(k_gather, dim3(cdiv(n, 256)), dim3(256), 0, s, t_gate, n, perm, x, y);
 }
 void launch_scatter(int n, const int* perm, const double* x, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter, dim3(cdiv(n, 256)), dim3(256), 0, s, n, perm, x, y);
+  hipLaunchKernelGGL(k_scatter, dim3(cdiv(n, 256)), dim3(256), 0, s, t_gate, n, perm, x, y);
 }
 
 void launch_residual(int n, char, const int* ptr, const int* idx, const int* pos,
@@ -3200,15 +3766,15 @@ void launch_combine(int n, int m, const double* Z, long ld, const double* y, con
 void launch_jacobi_sweep(int mode, const LUView& lu, const double* c, const double* yin,
                          double* yout, hipStream_t s) {
   if (mode == 0)
-    hipLaunchKernelGGL(k_jacobi_sweep<0>, dim3(rows_grid(lu.n)), dim3(256), 0, s, lu.n, lu.rowptr,
+    hipLaunchKernelGGL(k_jacobi_sweep<0>, dim3(rows_grid(lu.n)), dim3(256), 0, s, t_gate, lu.n, lu.rowptr,
                        lu.col, lu.diag, lu.val, c, yin, yout);
   else
-    hipLaunchKernelGGL(k_jacobi_sweep<1>, dim3(rows_grid(lu.n)), dim3(256), 0, s, lu.n, lu.rowptr,
+    hipLaunchKernelGGL(k_jacobi_sweep<1>, dim3(rows_grid(lu.n)), dim3(256), 0, s, t_gate, lu.n, lu.rowptr,
                        lu.col, lu.diag, lu.val, c, yin, yout);
 }
 
 void launch_add(int n, const double* d, double* x, hipStream_t s) {
-  hipLaunchKernelGGL(k_add, dim3(cdiv(n, 256)), dim3(256), 0, s, n, d, x);
+  hipLaunchKernelGGL(k_add, dim3(cdiv(n, 256)), dim3(256), 0, s, t_gate, n, d, x);
 }
 
 void launch_scale_div(int n, const double* x, const double* scal, double* y, hipStream_t s) {
@@ -3226,15 +3792,16 @@ void launch_arnoldi_start(int n, int m, const double* r, const double* rr, doubl
                      r, rr, v0, g);
 }
 
-void launch_transpose(int rows, int cols, const double* in, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_transpose, dim3(cdiv(rows, 32), cdiv(cols, 32)), dim3(32, 8), 0, s, rows,
-                     cols, in, out);
+
+void launch_grad_sddmm(int n, int nrhs, const int* arow_ptr, const int* acol, const double* lam,
+                       const double* x, double* grad, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_sddmm, dim3(rows_grid(n)), dim3(256), 0, s, n, nrhs, arow_ptr, acol,
+                     lam, x, grad);
 }
 
-void launch_grad_sddmm(int n, int nrhs, const int* arow_ptr, const int* acol,
-                       const double* lam_rm, const double* x_rm, double* grad, hipStream_t s) {
-  hipLaunchKernelGGL(k_grad_sddmm, dim3(cdiv((long)n * WAVE, 256)), dim3(256), 0, s, n, nrhs,
-                     arow_ptr, acol, lam_rm, x_rm, grad);
+void launch_copy(int n, const double* x, double* y, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_copy, dim3(cdiv(n, 256)), dim3(256), 0, s, t_gate, n, x, y);
 }
 
 }  // namespace kktlu

@@ -120,9 +120,13 @@ struct kkt_ctx {
   double *V = nullptr, *Z = nullptr, *w = nullptr, *r = nullptr, *xt = nullptr, *tmp = nullptr;
   double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *h = nullptr, *h2 = nullptr,
          *ww = nullptr, *y = nullptr, *hn = nullptr, *partial = nullptr;
-  // adjoint scratch
-  double *lam_rm = nullptr, *x_rm = nullptr;
-  int adj_cap = 0;
+  // sync-free refinement: stop-test state and workspace; fg_cols right-hand
+  // sides are refined in lockstep (the Krylov vectors above hold fg_cols
+  // columns each); fg_pending: a device-checked solve ran since the last report
+  FgState* fs = nullptr;
+  FgBufs fb{};
+  int fg_cols = 1;
+  bool fg_pending = false;
   // block-diagonal batch (batch_count > 0): instance offsets, per-row/column
   // absolute sums, per-instance maxima (3 per instance) and etas
   int batch_count = 0;
@@ -130,11 +134,10 @@ struct kkt_ctx {
   int* d_row_off = nullptr;
   double *rowabs = nullptr, *colabs = nullptr, *inst_out = nullptr;
   std::vector<double> h_inst, inst_eta;
-  // captured refactor + direct solve + residual
+  // captured refactor + solve with device-checked refinement
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
   const double *graph_b = nullptr, *graph_x = nullptr;
-  bool graph_eta_pending = false;
   // calls that replaced the factors or the matrix (kkt_info.factor_epoch)
   int64_t factor_epoch = 0;
   // report
@@ -164,7 +167,6 @@ void free_device(kkt_handle h) {
   if (h->graph) (void)hipGraphDestroy(h->graph);
   h->graph_exec = nullptr;
   h->graph = nullptr;
-  h->graph_eta_pending = false;
   for (auto& b : h->bufs) (void)hipFree(b.p);
   h->bufs.clear();
   h->device_bytes = 0;
@@ -174,8 +176,10 @@ void free_device(kkt_handle h) {
   h->h_colmax = nullptr;
   h->mc = h->my = h->mz = nullptr;
   h->mcap = 0;
-  h->lam_rm = h->x_rm = nullptr;
-  h->adj_cap = 0;
+  h->fs = nullptr;
+  h->fb = FgBufs{};
+  h->fg_cols = 1;
+  h->fg_pending = false;
   h->analyzed = h->factored = false;
 }
 
@@ -233,8 +237,7 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
       cur = bufs[k];
     }
     // U: right-hand side cur (copied to tmp), first iterate the right-hand side
-    HIP_CHECK_VOID(hipMemcpyAsync(h->tmp, cur, (size_t)n * sizeof(double),
-                                  hipMemcpyDeviceToDevice, s));
+    launch_copy(n, cur, h->tmp, s);
     const double* cu = h->tmp;
     cur = h->tmp;
     for (int it = 0; it < sweeps; it++, k ^= 1) {
@@ -339,16 +342,11 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
   }
 }
 
-// (n+1) x nr buffers of the multi-column solve
+// (n+1) x MAX_RHS_PASS buffers of the multi-column solves (allocated by the
+// analysis of a handle whose schedules have multi-column solves)
 kkt_status ensure_multi(kkt_handle h, int nr) {
   if (h->mcap >= nr) return KKT_OK;
-  const size_t cnt = (size_t)(h->an.n + 1) * MAX_RHS_PASS;
-  kkt_status ks;
-  if ((ks = dalloc(h, &h->mc, cnt)) != KKT_OK || (ks = dalloc(h, &h->my, cnt)) != KKT_OK ||
-      (ks = dalloc(h, &h->mz, cnt)) != KKT_OK)
-    return ks;
-  h->mcap = MAX_RHS_PASS;
-  return KKT_OK;
+  return fail(h, KKT_ERR_STATE, "no multi-column solve workspace for this schedule");
 }
 
 // M^{-1} B for nr <= MAX_RHS_PASS columns (dependency-driven, value-as-flag)
@@ -466,7 +464,6 @@ kkt_status read_batch_eta(kkt_handle h, char op, double* eta_max) {
     h->inst_eta[t] = e;
     if (!(e <= mx)) mx = e;
   }
-  h->graph_eta_pending = false;
   if (eta_max) *eta_max = mx;
   return KKT_OK;
 }
@@ -552,6 +549,100 @@ kkt_status solve_one(kkt_handle h, char op, const double* b, double* x, hipStrea
   return (eta <= o.eta_target) ? KKT_OK : KKT_WARN_NOT_CONVERGED;
 }
 
+// Iterations the device-checked refinement launches per group.
+int fg_budget(const kkt_options& o) {
+  const int b = o.refine_budget > 0 ? std::min(o.refine_budget, o.fgmres_max_iters)
+                                    : o.fgmres_max_iters;
+  return std::max(b, std::min(o.min_iters, o.fgmres_max_iters));
+}
+
+// M^{-1} for g columns (column stride n)
+void apply_group(kkt_handle h, char op, int g, const double* b, double* x, hipStream_t s) {
+  if (g == 1)
+    apply_factors(h, op, b, x, s);
+  else
+    apply_factors_multi(h, op, g, b, x, s);
+}
+
+// r = b - op(A) x for g columns and the device stop test after it_now
+// iterations (first: the check of the direct solve); a block-diagonal batch
+// is judged by its largest instance eta.
+void check_group(kkt_handle h, const FgBufs& fb, char op, int g, const double* b,
+                 const double* x, int it_now, int first, const FgParams& p, hipStream_t s) {
+  const int n = h->an.n;
+  const int batch = h->batch_count > 0 ? 1 : 0;
+  if (op == 'N')
+    launch_fg_resid(n, g, h->a_rowptr, h->a_col, nullptr, h->aval, b, x, h->r, fb, h->st, 0,
+                    it_now, first, batch, p, s);
+  else
+    launch_fg_resid(n, g, h->at_ptr, h->at_row, h->at_pos, h->aval, b, x, h->r, fb, h->st, 1,
+                    it_now, first, batch, p, s);
+  if (batch) {
+    launch_seg_stats(h->batch_count, h->d_row_off, op == 'N' ? h->rowabs : h->colabs, h->r, x,
+                     h->inst_out, s);
+    launch_fg_check_batch(h->batch_count, h->inst_out, fb, h->st, it_now, first, p, s);
+  }
+}
+
+// Device-checked solve of g <= fg_cols right-hand sides (b, x column stride
+// n): direct solve, stop test, then a fixed budget of refinement iterations
+// (FGMRES-CGS2, or classical refinement with refine = 1) whose kernels return
+// at once after the test stopped their column; the triangular solves stop
+// with the whole group.  Nothing here waits for the device: the outcome is
+// read by kkt_sync_report.  Stream-ordered only, so it can be captured.
+// fb: the refinement's state and partial sums.
+void solve_group_async(kkt_handle h, const FgBufs& fb, char op, int g, const double* b, double* x,
+                       bool first_group, hipStream_t s) {
+  const int n = h->an.n, m = h->m;
+  const kkt_options& o = h->opt;
+  const FgParams p{o.eta_target, o.min_iters, o.fgmres_max_iters};
+  const size_t gn = (size_t)g * n;
+  launch_fg_begin(fb.fs, first_group ? 1 : 0, s);
+  apply_group(h, op, g, b, x, s);
+  check_group(h, fb, op, g, b, x, 0, 1, p, s);
+  const int budget = fg_budget(o);
+  const bool ir = o.refine == 1;
+  set_launch_gate(&fb.fs->stop_all);
+  for (int it = 0; it < budget; it++) {
+    if (ir) {
+      apply_group(h, op, g, h->r, h->w, s);
+      launch_fg_add(n, g, h->w, x, fb, s);
+      check_group(h, fb, op, g, b, x, it + 1, 0, p, s);
+      continue;
+    }
+    const int j = it % m;
+    if (j == 0) launch_fg_restart(n, g, m, h->r, h->xt, x, it > 0 ? 1 : 0, h->V, fb, s);
+    const double* vj = h->V + j * gn;
+    double* zj = h->Z + j * gn;
+    apply_group(h, op, g, vj, zj, s);
+    if (op == 'N')
+      launch_fg_arnoldi(n, g, j, h->a_rowptr, h->a_col, nullptr, h->aval, zj, h->V, h->w, fb, s);
+    else
+      launch_fg_arnoldi(n, g, j, h->at_ptr, h->at_row, h->at_pos, h->aval, zj, h->V, h->w, fb,
+                        s);
+    launch_fg_cgs(0, n, g, j, m, h->V, h->w, fb, s);
+    launch_fg_cgs(1, n, g, j, m, h->V, h->w, fb, s);
+    launch_fg_update(n, g, j, m, h->w, h->V + (j + 1) * gn, h->Z, x, h->xt, fb, s);
+    check_group(h, fb, op, g, b, h->xt, it + 1, 0, p, s);
+  }
+  set_launch_gate(nullptr);
+  launch_fg_finish(n, g, h->xt, x, ir ? 1 : 0, fb, s);
+}
+
+// All right-hand sides, device-checked, in groups of the handle's width.
+void solve_async(kkt_handle h, const FgBufs& fb, char op, int nrhs, const double* b, double* x,
+                 hipStream_t s) {
+  const int n = h->an.n;
+  // one column at a time for approximate solves (no multi-column form) and
+  // batches (their stop test is per instance of one column)
+  const int gmax =
+      ((op == 'N' && h->opt.solve_jacobi_sweeps > 0) || h->batch_count > 0) ? 1 : h->fg_cols;
+  for (int c0 = 0; c0 < nrhs; c0 += gmax) {
+    const int g = std::min(gmax, nrhs - c0);
+    solve_group_async(h, fb, op, g, b + (size_t)c0 * n, x + (size_t)c0 * n, c0 == 0, s);
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -589,7 +680,7 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
       o.refactor_crit_height < -1 || o.refactor_waves_per_cu < 0 || o.refine < 0 || o.refine > 1 ||
       o.auto_reanalyze < 0 || o.auto_reanalyze > 1 || o.solve_jacobi_sweeps < 0 ||
       o.refactor_short_rows < -1 || o.refactor_short_rows > 0 || o.refactor_long_rows < -1 ||
-      o.refactor_long_rows > 0 ||
+      o.refactor_long_rows > 0 || o.refine_sync < 0 || o.refine_sync > 1 || o.refine_budget < 0 ||
       !(o.pivot_perturb_rel >= 0.0 && o.pivot_perturb_rel < 1.0))
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
@@ -1400,11 +1491,31 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
 #undef UP
   const size_t f = A.lu_col.size();
   const int m = h->m;
+  // right-hand sides refined in lockstep: up to FG_MAX_COLS where the
+  // schedule has multi-column solves, as many as keep the Krylov vectors
+  // ((2m + 4) per column) within 2 GiB
+  int gc = 1;
+  if (h->syncfree && h->light) {
+    gc = FG_MAX_COLS;
+    while (gc > 1 && (size_t)gc * (2 * m + 4) * (size_t)n * sizeof(double) > (size_t(2) << 30))
+      gc >>= 1;
+  }
+  h->fg_cols = gc;
+  const size_t gn = (size_t)gc * n;
   if ((ks = dalloc(h, &h->lu_val, f)) != KKT_OK || (ks = dalloc(h, &h->aval, nnz)) != KKT_OK ||
       (ks = dalloc(h, &h->st, 1)) != KKT_OK ||
-      (ks = dalloc(h, &h->V, (size_t)(m + 1) * n)) != KKT_OK ||
-      (ks = dalloc(h, &h->Z, (size_t)m * n)) != KKT_OK || (ks = dalloc(h, &h->w, n)) != KKT_OK ||
-      (ks = dalloc(h, &h->r, n)) != KKT_OK || (ks = dalloc(h, &h->xt, n)) != KKT_OK ||
+      (ks = dalloc(h, &h->V, (size_t)(m + 1) * gn)) != KKT_OK ||
+      (ks = dalloc(h, &h->Z, (size_t)m * gn)) != KKT_OK || (ks = dalloc(h, &h->w, gn)) != KKT_OK ||
+      (ks = dalloc(h, &h->r, gn)) != KKT_OK || (ks = dalloc(h, &h->xt, gn)) != KKT_OK ||
+      (ks = dalloc(h, &h->fs, 1)) != KKT_OK ||
+      (ks = dalloc(h, &h->fb.part, (size_t)FG_MAX_COLS * FG_BLOCKS * 32)) != KKT_OK ||
+      (ks = dalloc(h, &h->fb.hbuf, (size_t)FG_MAX_COLS * 32)) != KKT_OK ||
+      (ks = dalloc(h, &h->fb.h2buf, (size_t)FG_MAX_COLS * 32)) != KKT_OK ||
+      (ks = dalloc(h, &h->fb.H, (size_t)FG_MAX_COLS * (m + 1) * m)) != KKT_OK ||
+      (ks = dalloc(h, &h->fb.cs, (size_t)FG_MAX_COLS * m)) != KKT_OK ||
+      (ks = dalloc(h, &h->fb.sn, (size_t)FG_MAX_COLS * m)) != KKT_OK ||
+      (ks = dalloc(h, &h->fb.gvec, (size_t)FG_MAX_COLS * (m + 1))) != KKT_OK ||
+      (ks = dalloc(h, &h->fb.y, (size_t)FG_MAX_COLS * m)) != KKT_OK ||
       (ks = dalloc(h, &h->tmp, (size_t)n + 1)) != KKT_OK ||
       (ks = dalloc(h, &h->tc, (size_t)n + 1)) != KKT_OK ||
       (ks = dalloc(h, &h->ty, (size_t)n + 1)) != KKT_OK ||
@@ -1447,6 +1558,23 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   if ((ks = dalloc(h, &h->colmax, 2 * MAX_RHS_PASS)) != KKT_OK) {
     free_device(h);
     return ks;
+  }
+  h->fb.fs = h->fs;
+  HIP_CHECK(h, hipMemset(h->fs, 0, sizeof(FgState)));
+  // Krylov vectors start finite: a column that stopped early still passes
+  // its (unused) basis vector through the group's triangular solves
+  HIP_CHECK(h, hipMemset(h->V, 0, (size_t)(m + 1) * gn * sizeof(double)));
+  HIP_CHECK(h, hipMemset(h->Z, 0, (size_t)m * gn * sizeof(double)));
+  HIP_CHECK(h, hipMemset(h->r, 0, gn * sizeof(double)));
+  if (h->syncfree && h->light) {
+    // multi-column solve buffers, (n+1) x MAX_RHS_PASS each
+    const size_t cnt = (size_t)(n + 1) * MAX_RHS_PASS;
+    if ((ks = dalloc(h, &h->mc, cnt)) != KKT_OK || (ks = dalloc(h, &h->my, cnt)) != KKT_OK ||
+        (ks = dalloc(h, &h->mz, cnt)) != KKT_OK) {
+      free_device(h);
+      return ks;
+    }
+    h->mcap = MAX_RHS_PASS;
   }
   launch_reset_stats(h->st, 1 | 2 | 8, nullptr);
   launch_copy_anorm(n, h->a_rowptr, h->a_col, h->aval, h->aval, h->st, nullptr, nullptr,
@@ -1523,10 +1651,9 @@ kkt_status kkt_batch_layout(kkt_handle h, int64_t* row_offset, int64_t* nnz_offs
 kkt_status kkt_batch_eta(kkt_handle h, double* eta) {
   if (!h || !eta) return KKT_ERR_INVALID_ARG;
   if (!h->analyzed || h->batch_count == 0) return fail(h, KKT_ERR_STATE, "no batch analysis");
-  if (h->graph_eta_pending) {
-    kkt_status ks = read_batch_eta(h, 'N', nullptr);
-    if (ks != KKT_OK) return ks;
-  }
+  // per-instance maxima of the last residual check (the final iterate)
+  kkt_status ks = read_batch_eta(h, 'N', nullptr);
+  if (ks != KKT_OK) return ks;
   std::memcpy(eta, h->inst_eta.data(), h->inst_eta.size() * sizeof(double));
   return KKT_OK;
 }
@@ -1612,10 +1739,7 @@ kkt_status kkt_graph_capture(kkt_handle h, const double* d_values, const double*
   hipStream_t s = (hipStream_t)stream;
   HIP_CHECK(h, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
   kkt_status ks = refactor_launch(h, d_values, s);
-  if (ks == KKT_OK) {
-    apply_factors(h, 'N', d_b, d_x, s);
-    residual_launch(h, 'N', d_b, d_x, h->r, s);
-  }
+  if (ks == KKT_OK) solve_async(h, h->fb, 'N', 1, d_b, d_x, s);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);
   if (ks != KKT_OK) {
@@ -1639,7 +1763,7 @@ kkt_status kkt_graph_launch(kkt_handle h, void* stream) {
   h->anorm1_valid = false;
   h->factored = true;
   h->factor_epoch++;
-  h->graph_eta_pending = true;
+  h->fg_pending = true;
   return KKT_OK;
 }
 
@@ -1673,6 +1797,35 @@ kkt_status kkt_solve(kkt_handle h, char op, int32_t nrhs, const double* d_b, dou
   if (op == 'T' && !h->anorm1_valid) {
     launch_anorm1(n, h->at_ptr, h->at_pos, h->aval, h->st, s, h->colabs);
     h->anorm1_valid = true;
+  }
+  if (h->opt.refine_sync == 0) {
+    // stop test on the device, fixed launch budget, no host synchronisation
+    if (nrhs == 0) {
+      h->fg_pending = false;
+      h->last_iters = 0;
+      h->last_eta = h->last_eta0 = 0.0;
+      return KKT_OK;
+    }
+    solve_async(h, h->fb, op, nrhs, d_b, d_x, s);
+    HIP_CHECK(h, hipGetLastError());
+    h->fg_pending = true;
+    if (h->opt.auto_reanalyze == 1 && !h->in_retry && h->batch_count == 0 &&
+        !h->pat_rowptr.empty()) {
+      // the re-analysis decision needs the outcome on the host
+      FgState fsh;
+      HIP_CHECK(h, hipMemcpyAsync(&fsh, h->fs, sizeof fsh, hipMemcpyDeviceToHost, s));
+      HIP_CHECK(h, hipStreamSynchronize(s));
+      if (fsh.not_conv) {
+        kkt_status ks = kkt_reanalyze(h, h->aval, stream);
+        if (ks < 0) return ks;
+        h->in_retry = true;
+        ks = kkt_solve(h, op, nrhs, d_b, d_x, stream);
+        h->in_retry = false;
+        h->warnings |= 1 << KKT_WARN_REANALYZED;
+        return ks;
+      }
+    }
+    return KKT_OK;
   }
   kkt_status worst = KKT_OK;
   int itmax = 0;
@@ -1735,6 +1888,7 @@ kkt_status kkt_solve(kkt_handle h, char op, int32_t nrhs, const double* d_b, dou
   h->last_iters = itmax;
   h->last_eta = emax;
   h->last_eta0 = e0max;
+  h->fg_pending = false;
   if (worst > 0) h->warnings |= 1 << worst;
   if (worst == KKT_WARN_NOT_CONVERGED && h->opt.auto_reanalyze == 1 && !h->in_retry &&
       h->batch_count == 0 && !h->pat_rowptr.empty()) {
@@ -1760,16 +1914,7 @@ kkt_status kkt_grad_values(kkt_handle h, int32_t nrhs, const double* d_lambda, c
     return fail(h, KKT_ERR_INVALID_ARG, "bad nrhs or pointer");
   HIP_CHECK(h, hipSetDevice(h->opt.device));
   hipStream_t s = (hipStream_t)stream;
-  const int n = h->an.n;
-  if (h->adj_cap < nrhs) {
-    kkt_status ks;
-    if ((ks = dalloc(h, &h->lam_rm, (size_t)n * nrhs)) != KKT_OK) return ks;
-    if ((ks = dalloc(h, &h->x_rm, (size_t)n * nrhs)) != KKT_OK) return ks;
-    h->adj_cap = nrhs;
-  }
-  launch_transpose(n, nrhs, d_lambda, h->lam_rm, s);
-  launch_transpose(n, nrhs, d_x, h->x_rm, s);
-  launch_grad_sddmm(n, nrhs, h->a_rowptr, h->a_col, h->lam_rm, h->x_rm, d_grad, s);
+  launch_grad_sddmm(h->an.n, nrhs, h->a_rowptr, h->a_col, d_lambda, d_x, d_grad, s);
   HIP_CHECK(h, hipGetLastError());
   return KKT_OK;
 }
@@ -1782,17 +1927,15 @@ kkt_status kkt_sync_report(kkt_handle h, kkt_report* out) {
   DevStats d;
   HIP_CHECK(h, hipMemcpy(&d, h->st, sizeof d, hipMemcpyDeviceToHost));
   if (d.stall) return fail(h, KKT_ERR_DEVICE, "a dependency wait hit its spin limit (results invalid)");
-  if (h->graph_eta_pending) {
-    // a replayed graph ran the direct solve and its residual check: no refinement
-    double e = eta_of(bits_to_double(d.rmax), bits_to_double(d.anorm), bits_to_double(d.xmax));
-    if (h->batch_count > 0) {
-      kkt_status ks = read_batch_eta(h, 'N', &e);
-      if (ks != KKT_OK) return ks;
-    }
-    h->last_eta = h->last_eta0 = e;
-    h->last_iters = 0;
-    h->graph_eta_pending = false;
-    if (!(e <= h->opt.eta_target)) h->warnings |= 1 << KKT_WARN_NOT_CONVERGED;
+  if (h->fg_pending) {
+    // outcome of the device-checked solves (kkt_solve, graph replays)
+    FgState fsh;
+    HIP_CHECK(h, hipMemcpy(&fsh, h->fs, sizeof fsh, hipMemcpyDeviceToHost));
+    h->last_iters = fsh.it_max;
+    h->last_eta = bits_to_double(fsh.eta_max);
+    h->last_eta0 = bits_to_double(fsh.eta0_max);
+    if (fsh.not_conv) h->warnings |= 1 << KKT_WARN_NOT_CONVERGED;
+    h->fg_pending = false;
   }
   int warn = h->warnings;
   if (d.tiny) warn |= 1 << KKT_WARN_TINY_PIVOT;
