@@ -237,6 +237,22 @@ kkt_status kkt_solve(kkt_handle h, char op, int32_t nrhs, const double *d_b, dou
 kkt_status kkt_grad_values(kkt_handle h, int32_t nrhs, const double *d_lambda, const double *d_x,
                            double *d_grad, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): kkt_solve
+ * with the device-checked refinement (whatever refine_sync says; no
+ * auto_reanalyze), whose per-call scratch -- the stop-test state, reduction
+ * tickets, partial sums and least-squares arrays, at most 2 MiB for restart
+ * lengths up to 30 -- lives in a static device array of the library instead
+ * of the handle's workspace.  It calls no allocating routine.  The handle's
+ * analysis workspaces (factors, Krylov vectors) are used as by kkt_solve.
+ * Every call on one GPU shares that GPU's array (the state is reset at the
+ * start of each call), so calls that overlap on one GPU -- from several host
+ * threads or streams -- race.  Same arguments, results and errors as
+ * kkt_solve; KKT_ERR_INVALID_ARG if the refinement state does not fit the
+ * array. */
+kkt_status kkt_solve_noalloc(kkt_handle h, char op, int32_t nrhs, const double *d_b, double *d_x,
+                             void *stream);
+
 /* Batch of independent instances (scenarios, contingencies) solved as one
  * block-diagonal system in shared launches.  npat distinct patterns, pattern
  * p given by n[p], nnz[p], rowptr[p], colind[p] and its first values

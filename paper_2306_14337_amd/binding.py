@@ -37,7 +37,7 @@ EXPORTS = [
     "kkt_get_lu", "kkt_last_error", "kkt_analysis_create", "kkt_analysis_info",
     "kkt_analysis_perm", "kkt_analysis_lu", "kkt_analysis_levels", "kkt_analysis_destroy",
     "kkt_analyze_batch", "kkt_batch_layout", "kkt_batch_eta", "kkt_graph_capture",
-    "kkt_graph_launch", "kkt_reanalyze",
+    "kkt_graph_launch", "kkt_reanalyze", "kkt_solve_noalloc",
 ]
 
 
@@ -96,6 +96,7 @@ def lib():
         L.kkt_reanalyze.argtypes = [P, P, P]
         L.kkt_update_matrix.argtypes = [P, P, P]
         L.kkt_solve.argtypes = [P, C.c_char, C.c_int32, P, P, P]
+        L.kkt_solve_noalloc.argtypes = [P, C.c_char, C.c_int32, P, P, P]
         L.kkt_grad_values.argtypes = [P, C.c_int32, P, P, P, P]
         L.kkt_sync_report.argtypes = [P, C.POINTER(Report)]
         L.kkt_get_info.argtypes = [P, C.POINTER(Info)]
@@ -334,6 +335,17 @@ class KKTSolver:
             x = torch.empty_like(b)
         st = lib().kkt_solve(self._h, op.encode(), nrhs, _dev_f64(b, name="b"),
                              _dev_f64(x, b.numel(), "x"), _stream_ptr(stream))
+        self._check(st)
+        return x
+
+    def solve_noalloc(self, b, x, op: str = "N", stream=None):
+        """kkt_solve_noalloc: the solve with its per-call scratch in the
+        library's static device array (no allocation; x must be given)."""
+        if b.numel() % self.n:
+            raise ValueError("b must hold n * nrhs entries")
+        nrhs = b.numel() // self.n
+        st = lib().kkt_solve_noalloc(self._h, op.encode(), nrhs, _dev_f64(b, name="b"),
+                                     _dev_f64(x, b.numel(), "x"), _stream_ptr(stream))
         self._check(st)
         return x
 

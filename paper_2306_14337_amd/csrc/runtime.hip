@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -590,7 +591,8 @@ void check_group(kkt_handle h, const FgBufs& fb, char op, int g, const double* b
 // at once after the test stopped their column; the triangular solves stop
 // with the whole group.  Nothing here waits for the device: the outcome is
 // read by kkt_sync_report.  Stream-ordered only, so it can be captured.
-// fb: the refinement's state and partial sums.
+// fb: the refinement's state and partial sums (the handle's, or the
+// library's static scratch array for kkt_solve_noalloc).
 void solve_group_async(kkt_handle h, const FgBufs& fb, char op, int g, const double* b, double* x,
                        bool first_group, hipStream_t s) {
   const int n = h->an.n, m = h->m;
@@ -645,6 +647,65 @@ void solve_async(kkt_handle h, const FgBufs& fb, char op, int nrhs, const double
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Entry point without allocation (kkt_solve_noalloc): the refinement's
+// per-call scratch -- stop-test state, reduction tickets, partial sums and
+// the small least-squares arrays -- lives in this file-scope device array
+// instead of the handle's workspace.  Each GPU holds its own copy until the
+// process ends; its device address is looked up once per device (kkt_create,
+// with that device current) and only that address is used from host code.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(2) << 20;  // 2 MiB per GPU
+constexpr int NOALLOC_MAX_DEVICES = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch` (looked up once).
+kkt_status scratch_setup(int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return KKT_ERR_DEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return KKT_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return KKT_ERR_DEVICE;
+  g_scratch_ptr[dev] = p;
+  return KKT_OK;
+}
+
+unsigned char* scratch_of(int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (unsigned char*)g_scratch_ptr[dev];
+}
+
+// The refinement buffers for restart length m carved from the scratch array
+// in 256-byte aligned pieces; false when they do not fit.
+bool carve_fgbufs(unsigned char* base, int m, FgBufs* fb) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* p = base + off;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  const size_t d = sizeof(double), c = FG_MAX_COLS;
+  fb->fs = (FgState*)take(sizeof(FgState));
+  fb->part = (double*)take(d * c * FG_BLOCKS * 32);
+  fb->hbuf = (double*)take(d * c * 32);
+  fb->h2buf = (double*)take(d * c * 32);
+  fb->H = (double*)take(d * c * (size_t)(m + 1) * m);
+  fb->cs = (double*)take(d * c * m);
+  fb->sn = (double*)take(d * c * m);
+  fb->gvec = (double*)take(d * c * (m + 1));
+  fb->y = (double*)take(d * c * m);
+  return off <= NOALLOC_SCRATCH_BYTES;
+}
+}  // namespace
+
 extern "C" {
 
 void kkt_options_default(kkt_options* o) {
@@ -685,6 +746,9 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) return KKT_ERR_DEVICE;
+  // the device address of the no-allocation scratch array, once per device
+  if (hipSetDevice(o.device) != hipSuccess || scratch_setup(o.device) != KKT_OK)
+    return KKT_ERR_DEVICE;
   kkt_ctx* h = new (std::nothrow) kkt_ctx();
   if (!h) return KKT_ERR_OUT_OF_MEMORY;
   h->opt = o;
@@ -1916,6 +1980,41 @@ kkt_status kkt_grad_values(kkt_handle h, int32_t nrhs, const double* d_lambda, c
   hipStream_t s = (hipStream_t)stream;
   launch_grad_sddmm(h->an.n, nrhs, h->a_rowptr, h->a_col, d_lambda, d_x, d_grad, s);
   HIP_CHECK(h, hipGetLastError());
+  return KKT_OK;
+}
+
+kkt_status kkt_solve_noalloc(kkt_handle h, char op, int32_t nrhs, const double* d_b, double* d_x,
+                             void* stream) {
+  if (!h) return KKT_ERR_INVALID_ARG;
+  if (!h->factored) return fail(h, KKT_ERR_STATE, "kkt_solve_noalloc before kkt_analyze");
+  if ((op != 'N' && op != 'T') || nrhs < 0 || (nrhs > 0 && (!d_b || !d_x)))
+    return fail(h, KKT_ERR_INVALID_ARG, "bad op, nrhs or pointer");
+  const int n = h->an.n;
+  if (nrhs > 0 && d_b < d_x + (size_t)nrhs * n && d_x < d_b + (size_t)nrhs * n)
+    return fail(h, KKT_ERR_INVALID_ARG, "d_b and d_x overlap");
+  HIP_CHECK(h, hipSetDevice(h->opt.device));
+  unsigned char* base = scratch_of(h->opt.device);
+  if (!base) return fail(h, KKT_ERR_STATE, "no scratch array address for this device");
+  FgBufs fb{};
+  if (!carve_fgbufs(base, h->m, &fb))
+    return fail(h, KKT_ERR_INVALID_ARG,
+                "the refinement state for this restart length exceeds the 2 MiB scratch array");
+  hipStream_t s = (hipStream_t)stream;
+  if (op == 'T' && !h->anorm1_valid) {
+    launch_anorm1(n, h->at_ptr, h->at_pos, h->aval, h->st, s, h->colabs);
+    h->anorm1_valid = true;
+  }
+  if (nrhs == 0) {
+    h->fg_pending = false;
+    h->last_iters = 0;
+    h->last_eta = h->last_eta0 = 0.0;
+    return KKT_OK;
+  }
+  solve_async(h, fb, op, nrhs, d_b, d_x, s);
+  // the outcome into the handle's own state, where kkt_sync_report reads it
+  HIP_CHECK(h, hipMemcpyAsync(h->fs, fb.fs, sizeof(FgState), hipMemcpyDeviceToDevice, s));
+  HIP_CHECK(h, hipGetLastError());
+  h->fg_pending = true;
   return KKT_OK;
 }
 
