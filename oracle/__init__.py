@@ -51,6 +51,8 @@ def lib():
         P = C.c_void_p
         L.oracle_order_md.argtypes = [C.c_int32, P, P, P]
         L.oracle_order_md.restype = C.c_int
+        L.oracle_match_scale.argtypes = [C.c_int32, P, P, P, P, P, P]
+        L.oracle_match_scale.restype = C.c_int
         L.oracle_factor.argtypes = [C.c_int32, P, P, P, P, C.c_double, C.POINTER(C.c_int)]
         L.oracle_factor.restype = P
         L.oracle_lu_free.argtypes = [P]
@@ -93,6 +95,39 @@ def order_md(n: int, rowptr, colind) -> np.ndarray:
     if st != OK:
         raise ValueError(f"oracle_order_md failed ({st})")
     return Q
+
+
+def match_scale(n: int, rowptr, colind, values):
+    """Maximum-product matching and power-of-two scaling: (match, dr, dc) with
+    match[j] = row matched to column j; raises if no perfect matching exists."""
+    rp, ci = _csr(rowptr, colind)
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    match = np.empty(n, dtype=np.int32)
+    dr = np.empty(n, dtype=np.float64)
+    dc = np.empty(n, dtype=np.float64)
+    st = lib().oracle_match_scale(n, _p(rp), _p(ci), _p(v), _p(match), _p(dr), _p(dc))
+    if st != OK:
+        raise ValueError(f"oracle_match_scale failed ({st})")
+    return match, dr, dc
+
+
+def matched_scaled(n: int, rowptr, colind, values, match, dr, dc):
+    """CSR of the matched and scaled matrix: row j is row match[j] of A with
+    entries dr[match[j]] a_ij dc[c] (columns unchanged), and the position in
+    A's values of each of its entries."""
+    rp, ci = _csr(rowptr, colind)
+    v = np.asarray(values, dtype=np.float64)
+    nrp = np.zeros(n + 1, dtype=np.int64)
+    cols, vals, src = [], [], []
+    for j in range(n):
+        i = int(match[j])
+        lo, hi = int(rp[i]), int(rp[i + 1])
+        cols.append(ci[lo:hi])
+        vals.append(dr[i] * v[lo:hi] * dc[ci[lo:hi]])
+        src.append(np.arange(lo, hi, dtype=np.int64))
+        nrp[j + 1] = nrp[j] + (hi - lo)
+    return (nrp, np.concatenate(cols).astype(np.int32), np.concatenate(vals),
+            np.concatenate(src))
 
 
 class OracleLU:

@@ -121,6 +121,137 @@ static int check_csr(int32_t n, const int64_t *rowptr, const int32_t *colind) {
 }
 
 /* ------------------------------------------------------------------ */
+/* Maximum-product matching and scaling (the MC64-style preprocessing   */
+/* of Section 5.2.1, run before the fill-reducing ordering).            */
+/*                                                                      */
+/* Costs c_ij = log(cmax_j) - log|a_ij| >= 0 over the stored nonzero    */
+/* entries (cmax_j = max_i |a_ij|); the perfect matching of minimum     */
+/* total cost maximises the product of the matched magnitudes.  It is   */
+/* found by the textbook dense Hungarian method with shortest           */
+/* augmenting paths (absent entries cost +inf).  With the matching      */
+/* fixed, the column potentials are the largest v <= 0 that keep        */
+/* u_i + v_j <= c_ij with equality on the matching, where u_i =          */
+/* c_{i,s(i)} - v_{s(i)}: shortest distances from a source joined to     */
+/* every column, over edges s(i) -> j of weight c_ij - c_{i,s(i)} for     */
+/* each stored (i, j), by Bellman-Ford.  Scaling by powers of two        */
+/* (exact in floating point): dr_i = 2^round(u_i / ln 2), dc_j =          */
+/* 2^round((v_j - log cmax_j) / ln 2), so |dr_i a_ij dc_j| <= 2 and the    */
+/* matched entries lie in [1/2, 2].                                      */
+/* Output: match[j] = row matched to column j.  Returns ORA_OK, or       */
+/* ORA_ERR_STRUCT_SINGULAR when no perfect matching of nonzeros exists.  */
+/* ------------------------------------------------------------------ */
+int oracle_match_scale(int32_t n, const int64_t *rowptr, const int32_t *colind, const double *val,
+                       int32_t *match, double *dr, double *dc) {
+  if (!check_csr(n, rowptr, colind) || !val || !match || !dr || !dc) return ORA_ERR_ARG;
+  const double INF = HUGE_VAL;
+  size_t N1 = (size_t)n + 1;
+  double *cmax = (double *)calloc(N1, sizeof(double));
+  for (int32_t i = 0; i < n; i++)
+    for (int64_t p = rowptr[i]; p < rowptr[i + 1]; p++)
+      if (fabs(val[p]) > cmax[colind[p]]) cmax[colind[p]] = fabs(val[p]);
+  /* dense cost matrix, 1-based rows and columns as in the textbook form */
+  double *a = (double *)malloc(N1 * N1 * sizeof(double));
+  for (size_t e = 0; e < N1 * N1; e++) a[e] = INF;
+  for (int32_t i = 0; i < n; i++)
+    for (int64_t p = rowptr[i]; p < rowptr[i + 1]; p++)
+      if (val[p] != 0.0) a[(size_t)(i + 1) * N1 + colind[p] + 1] = log(cmax[colind[p]]) - log(fabs(val[p]));
+  double *u = (double *)calloc(N1, sizeof(double)), *v = (double *)calloc(N1, sizeof(double));
+  double *minv = (double *)malloc(N1 * sizeof(double));
+  int32_t *pm = (int32_t *)calloc(N1, sizeof(int32_t)), *way = (int32_t *)calloc(N1, sizeof(int32_t));
+  char *used = (char *)malloc(N1);
+  int st = ORA_OK;
+  for (int32_t i = 1; i <= n && st == ORA_OK; i++) {
+    pm[0] = i;
+    int32_t j0 = 0;
+    for (int32_t j = 0; j <= n; j++) {
+      minv[j] = INF;
+      used[j] = 0;
+    }
+    do {
+      used[j0] = 1;
+      const int32_t i0 = pm[j0];
+      double delta = INF;
+      int32_t j1 = -1;
+      for (int32_t j = 1; j <= n; j++)
+        if (!used[j]) {
+          const double cur = a[(size_t)i0 * N1 + j] - u[i0] - v[j];
+          if (cur < minv[j]) {
+            minv[j] = cur;
+            way[j] = j0;
+          }
+          if (minv[j] < delta) {
+            delta = minv[j];
+            j1 = j;
+          }
+        }
+      if (j1 < 0 || delta == INF) {
+        st = ORA_ERR_STRUCT_SINGULAR;
+        break;
+      }
+      for (int32_t j = 0; j <= n; j++)
+        if (used[j]) {
+          u[pm[j]] += delta;
+          v[j] -= delta;
+        } else {
+          minv[j] -= delta;
+        }
+      j0 = j1;
+    } while (pm[j0] != 0);
+    if (st != ORA_OK) break;
+    do {
+      const int32_t j1 = way[j0];
+      pm[j0] = pm[j1];
+      j0 = j1;
+    } while (j0);
+  }
+  if (st == ORA_OK) {
+    int32_t *scol = (int32_t *)malloc(N1 * sizeof(int32_t)); /* s(i): column of row i */
+    for (int32_t j = 1; j <= n; j++) {
+      match[j - 1] = pm[j] - 1;
+      scol[pm[j] - 1] = j - 1;
+    }
+    /* canonical column potentials by Bellman-Ford from a source joined to all */
+    double *d = (double *)calloc(N1, sizeof(double));
+    for (int32_t pass = 0; pass <= n; pass++) {
+      int changed = 0;
+      for (int32_t i = 0; i < n; i++) {
+        const int32_t js = scol[i];
+        const double cis = a[(size_t)(i + 1) * N1 + js + 1];
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; p++) {
+          const int32_t j = colind[p];
+          const double cij = a[(size_t)(i + 1) * N1 + j + 1];
+          if (cij == INF) continue;
+          const double nd = d[js] + (cij - cis);
+          if (nd < d[j]) {
+            d[j] = nd;
+            changed = 1;
+          }
+        }
+      }
+      if (!changed) break;
+    }
+    const double ln2 = log(2.0);
+    for (int32_t i = 0; i < n; i++) {
+      const int32_t js = scol[i];
+      const double ui = a[(size_t)(i + 1) * N1 + js + 1] - d[js];
+      dr[i] = ldexp(1.0, (int)lround(ui / ln2));
+    }
+    for (int32_t j = 0; j < n; j++) dc[j] = ldexp(1.0, (int)lround((d[j] - log(cmax[j])) / ln2));
+    free(d);
+    free(scol);
+  }
+  free(cmax);
+  free(a);
+  free(u);
+  free(v);
+  free(minv);
+  free(pm);
+  free(way);
+  free(used);
+  return st;
+}
+
+/* ------------------------------------------------------------------ */
 /* Ordering: exact minimum degree on the elimination graph of A + A^T  */
 /* (fill-reducing symmetric ordering, Sections 5.1 and 5.2).           */
 /* The elimination graph is kept explicitly: eliminating v joins all of */

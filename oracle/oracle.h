@@ -45,6 +45,15 @@ typedef struct {
   double eta0;       /* eta after the direct solve (max over right-hand sides) */
 } oracle_solve_info;
 
+/* Maximum-product perfect matching of the nonzero entries and power-of-two
+ * row/column scaling from its canonical dual potentials (Section 5.2.1's
+ * MC64-style preprocessing).  match[j] = row matched to column j; dr, dc: n
+ * scale factors each, so that dr_i a_ij dc_j is at most 2 in magnitude and
+ * the matched entries lie in [1/2, 2].  Dense O(n^2) memory: small systems.
+ * Returns ORA_OK or ORA_ERR_STRUCT_SINGULAR (no perfect matching). */
+int oracle_match_scale(int32_t n, const int64_t *rowptr, const int32_t *colind, const double *val,
+                       int32_t *match, double *dr, double *dc);
+
 /* Exact minimum degree on pattern(A + A^T) without the diagonal; ties go to
  * the smallest original index.  Writes Q[n].  Returns ORA_OK or ORA_ERR_ARG. */
 int oracle_order_md(int32_t n, const int64_t *rowptr, const int32_t *colind, int32_t *Q);

@@ -3,6 +3,7 @@ force with exactly rounded fma, the fill-path theorem, closed forms of the
 minimum-degree ordering, textbook GMRES properties and the adjoint's closed
 form.  CPU only.
 """
+import itertools
 import math
 from fractions import Fraction
 import os
@@ -11,6 +12,7 @@ from collections import deque
 import numpy as np
 import pytest
 import scipy.linalg as sla
+import scipy.sparse as sp
 
 import oracle
 from paper_2306_14337_amd import kktgen
@@ -797,3 +799,90 @@ def test_jacobi_depth_sweeps_exact():
     depth = lev.max()
     if depth >= 2:
         assert np.abs(ora.apply_jacobi(b, depth - 1) - x).max() > 1e-8 * np.abs(x).max()
+
+
+# ---------------------------------------------------------------------------
+# Maximum-product matching and power-of-two scaling (Section 5.2.1)
+# ---------------------------------------------------------------------------
+def _perm_product_argmax(A):
+    n = A.shape[0]
+    best, arg = -1.0, None
+    for perm in itertools.permutations(range(n)):
+        # perm[i] = column of row i
+        p = 1.0
+        for i in range(n):
+            p *= abs(A[i, perm[i]])
+        if p > best:
+            best, arg = p, perm
+    return best, arg
+
+
+@pytest.mark.parametrize("n,density,seed", [(3, 0.5, 1), (5, 0.4, 2), (6, 0.3, 3), (7, 0.35, 4),
+                                            (7, 0.8, 5), (6, 0.6, 6)])
+def test_matching_is_brute_force_max_product(n, density, seed):
+    rp, ci, v = kktgen.random_sparse(n, density, seed=seed)
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n)).toarray()
+    best, arg = _perm_product_argmax(A)
+    match, dr, dc = oracle.match_scale(n, rp, ci, v)
+    col_of_row = np.empty(n, dtype=np.int64)
+    col_of_row[match] = np.arange(n)
+    assert tuple(col_of_row) == tuple(arg)
+    got = np.prod(np.abs(A[np.arange(n), col_of_row]))
+    assert got == best
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_scaling_bounds(seed):
+    n = 40
+    rp, ci, v = kktgen.random_sparse(n, 0.15, seed=100 + seed)
+    v = v * 10.0 ** np.random.default_rng(seed).uniform(-6, 6, v.size)
+    match, dr, dc = oracle.match_scale(n, rp, ci, v)
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n)).toarray()
+    S = dr[:, None] * A * dc[None, :]
+    assert np.abs(S).max() <= 2.0
+    d = np.abs(S[match, np.arange(n)])
+    assert d.min() >= 0.5 and d.max() <= 2.0
+    # powers of two only: the scaled values are exact
+    assert np.all(np.frexp(dr)[0] == 0.5) and np.all(np.frexp(dc)[0] == 0.5)
+
+
+def test_matching_permuted_diagonal_closed_form():
+    # a permuted diagonal matrix with power-of-two magnitudes: the matching is
+    # the permutation and the scaled matched entries are exactly +-1
+    n = 9
+    rng = np.random.default_rng(7)
+    perm = rng.permutation(n)
+    vals = (2.0 ** rng.integers(-20, 20, n)) * rng.choice([-1.0, 1.0], n)
+    A = np.zeros((n, n))
+    A[np.arange(n), perm] = vals
+    Acsr = sp.csr_matrix(A)
+    match, dr, dc = oracle.match_scale(n, Acsr.indptr, Acsr.indices, Acsr.data)
+    assert np.array_equal(match[perm], np.arange(n))
+    S = dr[:, None] * A * dc[None, :]
+    assert np.array_equal(np.abs(S[np.arange(n), perm]), np.ones(n))
+
+
+def test_matching_reports_structural_singularity():
+    # row 2 is all zero values: no perfect matching of nonzeros
+    rp = np.array([0, 2, 5, 6])
+    ci = np.array([0, 1, 0, 1, 2, 1], dtype=np.int32)
+    v = np.array([1.0, 2.0, 0.5, 1.0, 3.0, 0.0])
+    with pytest.raises(ValueError):
+        oracle.match_scale(3, rp, ci, v)
+
+
+def test_matched_scaled_matrix_of_a_kkt_system():
+    # the KKT (2,2) block is -1e-8 I: the matching prefers the O(1) entries
+    # of J, and the matched, scaled matrix has entries of at most 2
+    pat, seq = kktgen.make_sequence(10, 3, 1)
+    vals = seq[0][0]
+    match, dr, dc = oracle.match_scale(pat.n, pat.rowptr, pat.colind, vals)
+    assert np.array_equal(np.sort(match), np.arange(pat.n))
+    rp, ci, sv, src = oracle.matched_scaled(pat.n, pat.rowptr, pat.colind, vals, match, dr, dc)
+    S = sp.csr_matrix((sv, ci, rp), shape=(pat.n, pat.n))
+    assert abs(S).max() <= 2.0
+    assert np.all(np.abs(S.diagonal()) >= 0.5)
+    A = pat.scipy(vals)
+    # the row permutation and scaling are exact: S = diag(dr)[match] A diag(dc)
+    ref = (sp.diags(dr) @ A @ sp.diags(dc)).tocsr()[match]
+    assert np.array_equal(S.toarray(), ref.toarray())
