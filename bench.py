@@ -420,6 +420,9 @@ def main():
                          "(0 default = 32, -1 level order)")
     ap.add_argument("--ref-wpcu", type=int, default=0,
                     help="cap on resident refactorization waves per CU (0 occupancy limit)")
+    ap.add_argument("--refine-budget", type=int, default=-1,
+                    help="refinement iterations launched per solve: -1 adaptive (default here), "
+                         "0 the full budget (the library default), k > 0 at most k")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 2 GiB read + 2 GiB write elementwise kernel before timing, its "
                          "source evicted from the 256 MiB last-level cache by a 1 GiB fill (the "
@@ -446,7 +449,7 @@ def main():
                           solve_thin_rows=args.thin, solve_blocks_per_cu=args.solve_bpc,
                           dense_tail=args.dense_tail, solve_chain=args.solve_chain,
                           refactor_crit_height=args.crit_height,
-                          refactor_waves_per_cu=args.ref_wpcu)
+                          refactor_waves_per_cu=args.ref_wpcu, refine_budget=args.refine_budget)
     t0 = time.perf_counter()
     s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
     t_an = time.perf_counter() - t0
@@ -547,7 +550,8 @@ def main():
                    "levels": info.levels, "seed": args.seed, "schedule": args.schedule,
                    "sync_mode": args.sync_mode, "solve_thin_rows": args.thin,
                    "solve_blocks_per_cu": args.solve_bpc, "solve_chain": args.solve_chain,
-                   "dense_tail": info.dense_tail},
+                   "dense_tail": info.dense_tail, "refine_budget": args.refine_budget,
+                   "refine": "FGMRES(20)-CGS2, stop test on the device, no host synchronisation"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.buses),
                      "kernel": "refactorization (all launches of one kkt_refactor)",
@@ -577,6 +581,41 @@ def main():
             * hop["cross_xcd"]["hop_ns"] * 1e-6,
             "note": "dependency levels x one device-coherent hop: the latency floor of a "
                     "dependency-driven launch whose every level waits for the one before"}
+    if args.refine_budget != 0 and not args.no_extras:
+        # the same steps with the library's default launch budget (the full
+        # fgmres_max_iters iterations, returning at once after the stop test)
+        s0 = binding.KKTSolver(device=0, schedule=args.schedule, sync_mode=args.sync_mode,
+                               solve_thin_rows=args.thin, solve_blocks_per_cu=args.solve_bpc,
+                               dense_tail=args.dense_tail, solve_chain=args.solve_chain,
+                               refactor_crit_height=args.crit_height,
+                               refactor_waves_per_cu=args.ref_wpcu, refine_budget=0)
+        s0.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
+        for k in range(args.warmup):
+            s0.refactor(vals_d[k])
+            s0.solve(rhs_d[k], xs[k])
+        torch.cuda.synchronize()
+        e0 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for i in range(args.steps):
+            k = args.warmup + i
+            e0[i][0].record(stream)
+            s0.refactor(vals_d[k])
+            e0[i][1].record(stream)
+            s0.solve(rhs_d[k], xs[k])
+            e0[i][2].record(stream)
+        torch.cuda.synchronize()
+        k = args.warmup + args.steps - 1
+        A = pat.scipy(seq[k][0])
+        x = xs[k].cpu().numpy()
+        e_last = float(np.abs(seq[k][1] - A @ x).max() / (abs(A).sum(1).max() * np.abs(x).max()))
+        assert e_last <= 1e-12
+        t0s = e0[0][0].elapsed_time(e0[-1][2]) / args.steps
+        out["full_launch_budget"] = {
+            "refine_budget": 0, "value": 1e3 / t0s, "ms_per_step": t0s,
+            "solve_median_ms": float(np.median([b.elapsed_time(c) for _, b, c in e0])),
+            "note": "library default: all fgmres_max_iters iterations launched, each returning "
+                    "at once after the device stop test"}
+        del s0
     del vals_d, rhs_d, xs, s
     torch.cuda.empty_cache()
     if not args.no_extras:

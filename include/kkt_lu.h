@@ -138,9 +138,33 @@ typedef struct {
                          iterations needed (kkt_solve then synchronises the stream) */
   int32_t refine_budget; /* refinement iterations launched per right-hand side when
                             refine_sync = 0: 0 = fgmres_max_iters (default), k > 0 =
-                            min(k, fgmres_max_iters) (at least min_iters); a solve that has not
-                            met eta_target within the budget reports KKT_WARN_NOT_CONVERGED */
-  int32_t reserved4;
+                            min(k, fgmres_max_iters) (at least min_iters), -1 = adaptive:
+                            2 r + 2 where r is the iteration count of the last earlier solve
+                            whose outcome has reached the host without waiting, the full
+                            budget after a solve that missed eta_target, after
+                            kkt_update_matrix, and with static pivoting, Jacobi sweeps or
+                            min_iters > 0 (graph captures always take the full budget).  A
+                            solve that has not met eta_target within its budget reports
+                            KKT_WARN_NOT_CONVERGED */
+  int32_t dense_lu; /* dense trailing block's factorization: 0 = a panel launch and an update
+                       launch per 32 pivots (default), 1 = one dependency-driven launch over
+                       32 x 32 tiles with a look-ahead of one panel; the same values */
+  int32_t debug_spin_limit; /* testing: > 0 makes a dependency wait give up once the wave has
+                               polled this many times (checked on its second poll and every 64th),
+                               raising the stall flag, so every kernel drains and kkt_sync_report
+                               returns KKT_ERR_DEVICE; 0 = off */
+  int32_t debug_schedule;   /* testing: 1 = adversarial ticket schedule in the persistent kernels
+                               (other workgroups take each chunk, pseudo-random pauses); results
+                               are unchanged.  Process-wide on the device, set by the last
+                               analysis; 0 = off */
+  int32_t matching;         /* 1: before the ordering, a maximum-product matching of the nonzero
+                               entries permutes the rows and power-of-two row and column
+                               scalings from its dual potentials make the matched entries about 1
+                               and every entry at most 2 in magnitude (Section 5.2.1's MC64-style
+                               preprocessing); the factors are those of Ahat = Pm Dr A Dc, the
+                               solves and residuals stay those of A.  Fixed at analysis (a
+                               re-analysis keeps it); single systems only.  0 = off (default) */
+  int32_t reserved5;
 } kkt_options;
 
 typedef struct {
@@ -290,8 +314,15 @@ kkt_status kkt_graph_launch(kkt_handle h, void *stream);
 kkt_status kkt_sync_report(kkt_handle h, kkt_report *out);
 kkt_status kkt_get_info(kkt_handle h, kkt_info *out);
 
-/* Host copies of the permutations (n entries each; either may be NULL). */
+/* Host copies of the permutations (n entries each; either may be NULL).
+ * With matching they are those of Ahat (kkt_get_scaling). */
 kkt_status kkt_get_perm(kkt_handle h, int32_t *p, int32_t *q);
+
+/* The matching and scaling of an analysis with opt.matching = 1 (n entries
+ * each; any may be NULL): match[j] = row of A placed at row j of Ahat, which
+ * is scaled by dr[match[j]]; column c is scaled by dc[c].  KKT_ERR_STATE
+ * without matching (Section 5.2.1). */
+kkt_status kkt_get_scaling(kkt_handle h, int32_t *match, double *dr, double *dc);
 
 /* Host copy of the current factors as one CSR matrix in pivot order: row i
  * holds L(i, 0..i-1), then u_ii, then U(i, i+1..), columns ascending.
@@ -318,6 +349,7 @@ kkt_status kkt_analysis_info(kkt_analysis a, kkt_info *out);
 /* As kkt_get_perm / kkt_get_lu, from the host object (values: the pivoting
  * pass's factors of values0). */
 kkt_status kkt_analysis_perm(kkt_analysis a, int32_t *p, int32_t *q);
+kkt_status kkt_analysis_scaling(kkt_analysis a, int32_t *match, double *dr, double *dc);
 kkt_status kkt_analysis_lu(kkt_analysis a, int64_t *rowptr, int32_t *colind, double *values);
 /* Row dependency schedule: level_ptr (levels+1 entries) and rows (n entries,
  * grouped by level); either may be NULL. */

@@ -37,7 +37,8 @@ EXPORTS = [
     "kkt_get_lu", "kkt_last_error", "kkt_analysis_create", "kkt_analysis_info",
     "kkt_analysis_perm", "kkt_analysis_lu", "kkt_analysis_levels", "kkt_analysis_destroy",
     "kkt_analyze_batch", "kkt_batch_layout", "kkt_batch_eta", "kkt_graph_capture",
-    "kkt_graph_launch", "kkt_reanalyze", "kkt_solve_noalloc",
+    "kkt_graph_launch", "kkt_reanalyze", "kkt_solve_noalloc", "kkt_get_scaling",
+    "kkt_analysis_scaling",
 ]
 
 
@@ -60,7 +61,9 @@ class Options(C.Structure):
                 ("auto_reanalyze", C.c_int32), ("solve_jacobi_sweeps", C.c_int32),
                 ("refactor_short_rows", C.c_int32), ("pivot_perturb_rel", C.c_double),
                 ("refactor_long_rows", C.c_int32), ("refine_sync", C.c_int32),
-                ("refine_budget", C.c_int32), ("reserved4", C.c_int32)]
+                ("refine_budget", C.c_int32), ("dense_lu", C.c_int32),
+                ("debug_spin_limit", C.c_int32), ("debug_schedule", C.c_int32),
+                ("matching", C.c_int32), ("reserved5", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -101,6 +104,8 @@ def lib():
         L.kkt_sync_report.argtypes = [P, C.POINTER(Report)]
         L.kkt_get_info.argtypes = [P, C.POINTER(Info)]
         L.kkt_get_perm.argtypes = [P, P, P]
+        L.kkt_get_scaling.argtypes = [P, P, P, P]
+        L.kkt_analysis_scaling.argtypes = [P, P, P, P]
         L.kkt_get_lu.argtypes = [P, P, P, P]
         L.kkt_last_error.argtypes = [P]
         L.kkt_last_error.restype = C.c_char_p
@@ -184,6 +189,16 @@ class HostAnalysis:
         v = np.empty(f, np.float64)
         lib().kkt_analysis_lu(self._h, _np_ptr(rp), _np_ptr(ci), _np_ptr(v))
         return rp, ci, v
+
+    def scaling(self):
+        """(match, dr, dc) of an analysis with matching=1."""
+        m = np.empty(self.n, np.int32)
+        dr = np.empty(self.n, np.float64)
+        dc = np.empty(self.n, np.float64)
+        st = lib().kkt_analysis_scaling(self._h, _np_ptr(m), _np_ptr(dr), _np_ptr(dc))
+        if st < 0:
+            raise KKTError(st, "no matching in this analysis")
+        return m, dr, dc
 
     def levels(self):
         i = self.info()
@@ -380,6 +395,14 @@ class KKTSolver:
         Q = np.empty(self.n, np.int32)
         self._check(lib().kkt_get_perm(self._h, _np_ptr(P), _np_ptr(Q)))
         return P, Q
+
+    def scaling(self):
+        """(match, dr, dc) of an analysis with matching=1."""
+        m = np.empty(self.n, np.int32)
+        dr = np.empty(self.n, np.float64)
+        dc = np.empty(self.n, np.float64)
+        self._check(lib().kkt_get_scaling(self._h, _np_ptr(m), _np_ptr(dr), _np_ptr(dc)))
+        return m, dr, dc
 
     def lu(self, values: bool = True):
         i = self.info()

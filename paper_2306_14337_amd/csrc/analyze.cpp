@@ -15,6 +15,8 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <deque>
+#include <queue>
 #include <limits>
 #include <set>
 #include <thread>
@@ -301,6 +303,161 @@ void levels_forward(int32_t n, const std::vector<int32_t>& ptr, const std::vecto
 
 }  // namespace
 
+int match_scale(int32_t n, const int64_t* rowptr, const int32_t* colind, const double* val,
+                std::vector<int32_t>& match, std::vector<double>& dr, std::vector<double>& dc) {
+  const double INF = std::numeric_limits<double>::infinity();
+  const int64_t nnz = rowptr[n];
+  std::vector<double> cmax(n, 0.0), c(nnz, INF);
+  for (int64_t p = 0; p < nnz; p++) cmax[colind[p]] = std::max(cmax[colind[p]], std::fabs(val[p]));
+  for (int32_t i = 0; i < n; i++)
+    for (int64_t p = rowptr[i]; p < rowptr[i + 1]; p++)
+      if (val[p] != 0.0) c[p] = std::log(cmax[colind[p]]) - std::log(std::fabs(val[p]));
+  // successive shortest augmenting paths from each row; reduced costs
+  // c_ij - u_i - v_j stay non-negative and are zero on the matching
+  std::vector<double> u(n, INF), v(n, 0.0), dist(n, INF);
+  for (int32_t i = 0; i < n; i++)
+    for (int64_t p = rowptr[i]; p < rowptr[i + 1]; p++) u[i] = std::min(u[i], c[p]);
+  for (int32_t i = 0; i < n; i++)
+    if (u[i] == INF) return KKT_ERR_STRUCTURALLY_SINGULAR;
+  std::vector<int32_t> row_of(n, -1), col_of(n, -1), pred(n, -1);
+  std::vector<char> done(n, 0);
+  std::vector<int32_t> touched, settled;
+  using Item = std::pair<double, int32_t>;
+  for (int32_t r = 0; r < n; r++) {
+    std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+    auto relax = [&](int32_t i, double base) {
+      for (int64_t p = rowptr[i]; p < rowptr[i + 1]; p++) {
+        const int32_t j = colind[p];
+        if (c[p] == INF || done[j]) continue;
+        const double d = base + (c[p] - u[i] - v[j]);
+        if (d < dist[j]) {
+          if (dist[j] == INF) touched.push_back(j);
+          dist[j] = d;
+          pred[j] = i;
+          heap.push({d, j});
+        }
+      }
+    };
+    relax(r, 0.0);
+    int32_t jend = -1;
+    double D = 0.0;
+    while (!heap.empty()) {
+      const Item it = heap.top();
+      heap.pop();
+      const int32_t j = it.second;
+      if (done[j] || it.first > dist[j]) continue;
+      done[j] = 1;
+      settled.push_back(j);
+      if (row_of[j] < 0) {
+        jend = j;
+        D = it.first;
+        break;
+      }
+      relax(row_of[j], it.first);
+    }
+    if (jend < 0) return KKT_ERR_STRUCTURALLY_SINGULAR;
+    // new potentials: settled columns down, their rows and the root up, by
+    // D - dist (keeps every reduced cost >= 0 and makes the path tight)
+    for (int32_t j : settled) {
+      const double dj = D - dist[j];
+      if (j != jend) u[row_of[j]] += dj;
+      v[j] -= dj;
+    }
+    u[r] += D;
+    // augment along the predecessors
+    for (int32_t j = jend;;) {
+      const int32_t i = pred[j];
+      const int32_t prev = col_of[i];
+      row_of[j] = i;
+      col_of[i] = j;
+      if (i == r) break;
+      j = prev;
+    }
+    for (int32_t j : touched) {
+      dist[j] = INF;
+      done[j] = 0;
+      pred[j] = -1;
+    }
+    for (int32_t j : settled) done[j] = 0;
+    touched.clear();
+    settled.clear();
+  }
+  // canonical column potentials: shortest distances from a source joined to
+  // every column over edges s(i) -> j of weight c_ij - c_{i,s(i)}
+  std::vector<double> d(n, 0.0), cs(n);
+  for (int32_t i = 0; i < n; i++) {
+    const int32_t js = col_of[i];
+    for (int64_t p = rowptr[i]; p < rowptr[i + 1]; p++)
+      if (colind[p] == js) cs[i] = c[p];
+  }
+  std::deque<int32_t> queue;
+  std::vector<char> inq(n, 1);
+  for (int32_t j = 0; j < n; j++) queue.push_back(j);
+  while (!queue.empty()) {
+    const int32_t j0 = queue.front();
+    queue.pop_front();
+    inq[j0] = 0;
+    const int32_t i = row_of[j0];
+    for (int64_t p = rowptr[i]; p < rowptr[i + 1]; p++) {
+      if (c[p] == INF) continue;
+      const int32_t j = colind[p];
+      const double nd = d[j0] + (c[p] - cs[i]);
+      if (nd < d[j]) {
+        d[j] = nd;
+        if (!inq[j]) {
+          inq[j] = 1;
+          queue.push_back(j);
+        }
+      }
+    }
+  }
+  const double ln2 = std::log(2.0);
+  match.assign(row_of.begin(), row_of.end());
+  dr.assign(n, 1.0);
+  dc.assign(n, 1.0);
+  for (int32_t i = 0; i < n; i++)
+    dr[i] = std::ldexp(1.0, (int)std::lround((cs[i] - d[col_of[i]]) / ln2));
+  for (int32_t j = 0; j < n; j++)
+    dc[j] = std::ldexp(1.0, (int)std::lround((d[j] - std::log(cmax[j])) / ln2));
+  return KKT_OK;
+}
+
+int analyze_scaled(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colind,
+                   const double* values, const std::vector<int32_t>& match,
+                   const std::vector<double>& dr, const std::vector<double>& dc,
+                   const int32_t* user_q, const AnalyzeOptions& opt, Analysis& A,
+                   std::string* msg) {
+  // Ahat: row j is A's row match[j], entries dr_i a_ij dc_j (exact: powers
+  // of two), and the A position of each of its entries
+  std::vector<int64_t> hrp(n + 1, 0), hsrc(nnz);
+  std::vector<int32_t> hci(nnz);
+  std::vector<double> hv(nnz);
+  for (int32_t j = 0; j < n; j++) {
+    const int32_t i = match[j];
+    int64_t q = hrp[j];
+    for (int64_t p = rowptr[i]; p < rowptr[i + 1]; p++, q++) {
+      hci[q] = colind[p];
+      hv[q] = dr[i] * values[p] * dc[colind[p]];
+      hsrc[q] = p;
+    }
+    hrp[j + 1] = q;
+  }
+  AnalyzeOptions o2 = opt;
+  o2.matching = 0;
+  const int st = analyze(n, nnz, hrp.data(), hci.data(), hv.data(), user_q, o2, A, msg);
+  if (st < 0) return st;
+  // the value map refers to A's positions; per-entry scale of A's values
+  for (auto& x : A.lu_src)
+    if (x >= 0) x = (int32_t)hsrc[x];
+  A.ascale.assign(nnz, 1.0);
+  for (int32_t i = 0; i < n; i++)
+    for (int64_t p = rowptr[i]; p < rowptr[i + 1]; p++) A.ascale[p] = dr[i] * dc[colind[p]];
+  A.match = match;
+  A.dr = dr;
+  A.dc = dc;
+  return st;
+}
+
 int analyze(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colind,
             const double* values0, const int32_t* user_q, const AnalyzeOptions& opt, Analysis& A,
             std::string* msg) {
@@ -319,6 +476,16 @@ int analyze(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colind
       if (msg) *msg = "values0 holds NaN or Inf at position " + std::to_string(p);
       return KKT_ERR_NONFINITE;
     }
+  if (opt.matching == 1) {
+    std::vector<int32_t> match;
+    std::vector<double> dr, dc;
+    st = match_scale(n, rowptr, colind, values0, match, dr, dc);
+    if (st != KKT_OK) {
+      if (msg) *msg = "no perfect matching of the nonzero entries (structurally singular)";
+      return st;
+    }
+    return analyze_scaled(n, nnz, rowptr, colind, values0, match, dr, dc, user_q, opt, A, msg);
+  }
   A = Analysis();
   A.n = n;
   A.nnz = nnz;

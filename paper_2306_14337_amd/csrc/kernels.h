@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace kktlu {
 
@@ -15,8 +16,11 @@ struct DevStats {
   unsigned long long rmax;     // bits of ||r||_inf (scratch of the residual kernel)
   unsigned long long xmax;     // bits of ||x||_inf
   unsigned long long umax;     // bits of max |u_ij| over U (growth numerator)
+  unsigned long long anorm_f;  // bits of ||A||_inf of the factored matrix (the matched and
+                               // scaled one when the analysis matched; else = anorm)
   int tiny;                    // a tiny or non-finite pivot was seen
   int stall;                   // a dependency wait hit its spin limit (sticky)
+  int spin_limit;              // host-set debug limit on every wait (0 = none); follows stall
   int perturbed;               // a pivot was raised to the perturbation threshold
 };
 
@@ -72,6 +76,9 @@ struct FgBufs {
 // once when it is non-zero.  Set around the launches of a sync-free
 // refinement so that its triangular solves stop with the group.
 void set_launch_gate(const int* gate);
+// Adversarial ticket schedule of the persistent kernels (debug; process-wide
+// on the current device).  False if the device symbol could not be written.
+bool set_debug_schedule(int on);
 
 void launch_fg_begin(FgState* fs, int reset_summary, hipStream_t s);
 // r = b - op(A) x for ncols columns (column stride n) and the stop test after
@@ -127,6 +134,8 @@ struct SyncState {
   alignas(128) unsigned int band_stream[REF_MAX_BANDS][TICKET_STREAMS * TICKET_STRIDE];
   // chain-blocked solves of slot k, stream s: slot_stream[k][s * TICKET_STRIDE]
   alignas(128) unsigned int slot_stream[4][TICKET_STREAMS * TICKET_STRIDE];
+  // dense trailing block's task launch (reset by launch_dlu_reset)
+  alignas(128) unsigned int dlu_stream[TICKET_STREAMS * TICKET_STRIDE];
 };
 
 // Work chunks of a triangular-solve schedule: chunk c covers rows
@@ -267,6 +276,17 @@ constexpr int DLU_NB = 32;
 void launch_tail_scatter(const LUView& lu, int c0, int s, int S, double* T, hipStream_t st);
 void launch_dense_lu(double* T, int S, int s, double* dsc, DevStats* stats, double perturb_rel,
                      hipStream_t st);
+// The same LU as one dependency-driven launch over DLU_NB x DLU_NB tiles (nt =
+// S / DLU_NB per side): tasks (dense_lu_tasks) factor a diagonal tile, solve a
+// tile of the column or row panel against it, or apply one panel's update to
+// a tile; ver[nt * nt] counts the operations finished on each tile and is
+// what the tasks wait for.  Bitwise the same values as launch_dense_lu.
+// launch_dlu_reset zeroes ver and the task tickets (stream-ordered before).
+std::vector<int> dense_lu_tasks(int nt);
+void launch_dlu_reset(int* ver, int nt, SyncState* ss, hipStream_t st);
+bool launch_dense_lu_tasks(double* T, int S, int s, const int* tasks, int ntasks, int* ver,
+                           SyncState* ss, int* stall, DevStats* stats, double perturb_rel,
+                           hipStream_t st);
 void launch_tail_gather(const LUView& lu, int c0, const double* T, int S, hipStream_t st);
 // Dependency-driven triangular solve of one right-hand side in place on y.
 // mode 0: unit L rows, 1: U rows, 2: U^T columns (tptr/trow/tpos view of U),
@@ -326,12 +346,14 @@ void launch_trisolve_vflag_mr(int mode, int nr, const LUView& lu, const ChunkSch
 // c[r][i] = x[r][perm[i]] (x: ld n; c, y, z: ld n + 1), y, z := sentinel,
 // except y on rows with triv[i] != 0 (no dependencies in the first triangle):
 // y = c, or c / val[diag[i]] if div
-void launch_gather_sentinel_mr(int n, int nr, const int* perm, const double* x, double* c,
+void launch_gather_sentinel_mr(int n, int nr, const int* perm, const double* scale, const double* x,
+                               double* c,
                                double* y, double* z, SyncState* ss, int mask, hipStream_t s,
                                const unsigned char* triv = nullptr, const int* diag = nullptr,
                                const double* val = nullptr, int div = 0);
 // x[r][perm[i]] = z[r][i]
-void launch_scatter_mr(int n, int nr, const int* perm, const double* z, double* x, hipStream_t s);
+void launch_scatter_mr(int n, int nr, const int* perm, const double* scale, const double* z, double* x,
+                       hipStream_t s);
 // per-column max |B - op(A) X| and max |X| into colmax[2r], colmax[2r+1]
 // (uint64 bit patterns of non-negative doubles); zeroes colmax first
 void launch_residual_mr(int n, int nr, const int* ptr, const int* idx, const int* pos,
@@ -339,7 +361,8 @@ void launch_residual_mr(int n, int nr, const int* ptr, const int* idx, const int
                         unsigned long long* colmax, hipStream_t s);
 // c[i] = x[perm[i]]; y, z := sentinel (y on trivial rows as in the _mr form);
 // plus the sync_prep of mask
-void launch_gather_sentinel(int n, const int* perm, const double* x, double* c, double* y,
+void launch_gather_sentinel(int n, const int* perm, const double* scale, const double* x, double* c,
+                            double* y,
                             double* z, SyncState* ss, int mask, hipStream_t s,
                             const unsigned char* triv = nullptr, const int* diag = nullptr,
                             const double* val = nullptr, int div = 0);
@@ -353,7 +376,8 @@ void launch_refactor_trivial(const LUView& lu, const int* rows, int nrows, const
 // zero the tickets and advance the epochs of the slots in mask (bit k = slot k)
 void launch_sync_prep(SyncState* ss, int mask, hipStream_t s);
 // y[i] = x[perm[i]] and, if ss != nullptr, the sync_prep of mask (fused)
-void launch_gather_prep(int n, const int* perm, const double* x, double* y, SyncState* ss,
+void launch_gather_prep(int n, const int* perm, const double* scale, const double* x, double* y,
+                        SyncState* ss,
                         int mask, hipStream_t s);
 
 // pivot statistics (min/max |u_kk|, tiny test against tiny_rel * ||A||_inf,
@@ -365,10 +389,14 @@ void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStre
 // also scattered into factor order: luA[a2lu[p]] = A[p]).  red (nullable,
 // RED_SCRATCH doubles): scratch of a two-stage maximum over a larger grid.
 constexpr int RED_SCRATCH = 2 * 4096;
+// fnorm: also set anorm_f, the norm of the factored matrix (= ||A||_inf, or
+// of the matched and scaled matrix when ascale is given: then avs and luA get
+// a_p * ascale[p]); kkt_update_matrix leaves anorm_f alone (fnorm = 0).
 void launch_copy_anorm(int n, const int* arow, const int* acol, const double* src, double* dst,
                        DevStats* st, hipStream_t s, SyncState* ss = nullptr,
                        double* rowabs = nullptr, const int* a2lu = nullptr,
-                       double* luA = nullptr, double* red = nullptr);
+                       double* luA = nullptr, double* red = nullptr, int fnorm = 1,
+                       const double* ascale = nullptr, double* avs = nullptr);
 // ||A||_1 through the column view (and every column's absolute sum)
 void launch_anorm1(int n, const int* cptr, const int* cpos, const double* aval, DevStats* st,
                    hipStream_t s, double* colabs = nullptr);
@@ -390,8 +418,12 @@ void launch_ltsolve_cols(const LUView& lu, const int* cols, int ncols, const int
                          const int* trow, const int* tpos, double* y, hipStream_t s);
 
 // y[i] = x[perm[i]]  /  y[perm[i]] = x[i]
-void launch_gather(int n, const int* perm, const double* x, double* y, hipStream_t s);
-void launch_scatter(int n, const int* perm, const double* x, double* y, hipStream_t s);
+// gathers and scatters carry an optional per-position scale (nullptr = none):
+// y[i] = x[perm[i]] * scale[i]; scatter y[perm[i]] = x[i] * scale[i]
+void launch_gather(int n, const int* perm, const double* scale, const double* x, double* y,
+                   hipStream_t s);
+void launch_scatter(int n, const int* perm, const double* scale, const double* x, double* y,
+                    hipStream_t s);
 
 // r = b - op(A) x and the maxima ||r||_inf, ||x||_inf into st; red as in
 // launch_copy_anorm

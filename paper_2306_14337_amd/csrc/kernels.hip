@@ -133,7 +133,7 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_rows_lds(
     wave_sync();
   }
   if (prel > 0.0) {
-    const double thr = prel * __longlong_as_double((long long)st->anorm);
+    const double thr = prel * __longlong_as_double((long long)st->anorm_f);
     const double d = sv[dl];
     if (fabs(d) < thr) {
       if (lane == 0) sv[dl] = perturb_pivot(d, thr);
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(WAVE) void k_refactor_rows_global(
     __builtin_amdgcn_wave_barrier();
   }
   if (prel > 0.0) {
-    const double thr = prel * __longlong_as_double((long long)st->anorm);
+    const double thr = prel * __longlong_as_double((long long)st->anorm_f);
     const double d = val[dpos];
     if (fabs(d) < thr) {
       if (lane == 0) val[dpos] = perturb_pivot(d, thr);
@@ -243,10 +243,24 @@ __device__ __forceinline__ unsigned int bcast0(unsigned int v) {
 // stream is lower, hence finished, so that stream's waves are free and one
 // of them fetches u next.  Returns a value >= nchunks once the stream is
 // exhausted.
+//
+// Adversarial schedule (debug, g_debug_schedule != 0): workgroup b fetches
+// from stream nstreams - 1 - b % nstreams instead (a different workgroup,
+// hence XCD, for every chunk; each stream still has as many workgroups), and
+// it pauses a pseudo-random 0-7 x 128 cycles after each fetch, so chunks start
+// and publish in another order.  Results must not change.
+__device__ int g_debug_schedule = 0;
+
 __device__ __forceinline__ int next_chunk(unsigned int* streams, int nstreams, int lane) {
-  const int s = (int)(blockIdx.x % (unsigned int)nstreams);
+  const int dbg = g_debug_schedule;
+  const int b = (int)(blockIdx.x % (unsigned int)nstreams);
+  const int s = dbg ? nstreams - 1 - b : b;
   const unsigned int m =
       bcast0(atomicAdd(streams + s * TICKET_STRIDE, lane == 0 ? 1u : 0u));
+  if (dbg) {
+    const unsigned int h = (m * 2654435761u) ^ (blockIdx.x * 40503u);
+    for (unsigned int k = 0; k < ((h >> 13) & 7u); k++) __builtin_amdgcn_s_sleep(2);
+  }
   return (int)m * nstreams + s;
 }
 
@@ -256,8 +270,17 @@ __device__ __forceinline__ int next_chunk(unsigned int* streams, int nstreams, i
 // pauses 64 cycles.  (A pause growing with the wait, meant to keep far-ahead
 // waves off the memory system, measured slower: it delays the waves at the
 // dependency front by up to the pause length.)
+// stall[1] (DevStats::spin_limit) > 0 is a host-set debug limit on a wave's
+// polls, read on its second poll and with every stall-flag check.
 __device__ __forceinline__ bool keep_waiting(int* spins, int* stall) {
-  if ((*spins & 63) == 63 && ld_flag(stall)) return false;
+  if ((*spins & 63) == 63 || *spins == 1) {
+    if ((*spins & 63) == 63 && ld_flag(stall)) return false;
+    const int lim = stall[1];
+    if (lim > 0 && *spins >= lim) {
+      st_flag(stall, 1);
+      return false;
+    }
+  }
   if (++*spins > SPIN_LIMIT) {
     st_flag(stall, 1);
     return false;
@@ -308,7 +331,7 @@ __global__ __launch_bounds__(256) void k_refactor_trivial(int nrows, const int* 
                                                           DevStats* st, double prel) {
   const int lane = threadIdx.x % WAVE, g = lane / RG_TRIV, gl = lane % RG_TRIV;
   const int epoch = ss->epoch[0];
-  const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm) : 0.0;
+  const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm_f) : 0.0;
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = gridDim.x * blockDim.x / WAVE;
   for (int r0 = wid * (WAVE / RG_TRIV); r0 < nrows; r0 += nw * (WAVE / RG_TRIV)) {
@@ -380,7 +403,7 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_syncfree(
   int2* sk = reinterpret_cast<int2*>(smem_d + (size_t)WPB * cap) + (size_t)wave * cap;
   int* sc = reinterpret_cast<int*>(smem_d + (size_t)WPB * cap * 2) + (size_t)wave * cap;
   const int epoch = ss->epoch[0];
-  const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm) : 0.0;
+  const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm_f) : 0.0;
   for (;;) {
     const int tk = next_chunk(tickets, nstreams, lane);
     if (tk >= nchunks) break;
@@ -970,7 +993,7 @@ __global__ __launch_bounds__(256) void k_dlu_panel(double* T, int S, int k0, int
   const int tid = threadIdx.x;
   if (tid < WAVE) {
     const int t = tid;
-    const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm) : 0.0;
+    const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm_f) : 0.0;
     double r[NB];
 #pragma unroll
     for (int j = 0; j < NB; j++) r[j] = t < NB ? T[(size_t)(k0 + t) * S + k0 + j] : 0.0;
@@ -1087,6 +1110,184 @@ __global__ __launch_bounds__(256) void k_dlu_update(double* T, int S, int k0,
       const int r = r0 + ty + 16 * a, q = q0 + tx + 16 * c;
       if (r < S && q < S) T[(size_t)r * S + q] = acc[a][c];
     }
+}
+
+// Dense trailing block as one dependency-driven launch.  The block is cut
+// into NB x NB tiles; a task is one of
+//   D(k)      factor diagonal tile (k, k)                (wave 0: rows in lanes)
+//   C(i, k)   tile (i, k) := tile (i, k) U_kk^{-1}, L part  (thread per row)
+//   R(k, j)   tile (k, j) := L_kk^{-1} tile (k, j), U part  (thread per column)
+//   G(i,j,k)  tile (i, j) -= L(i, k) U(k, j)             (2 x 2 entries per thread)
+// with exactly the arithmetic of k_dlu_panel / k_dlu_update, so the values
+// are the same bit for bit.  ver[i * nt + j] counts the operations finished
+// on tile (i, j): the G updates of steps 0 .. min(i, j) - 1, then its own
+// D, C or R step.  A task waits for its inputs' counts (device-coherent
+// flags; tile data moves with device-coherent loads and stores, so no cache
+// maintenance is needed between XCDs) and hands out through eight ticket
+// streams in an order where every task's inputs come earlier, which keeps
+// the persistent grid deadlock-free as in the sparse refactorization.  Step
+// k + 1's panel is listed right after the updates of its own tiles, ahead of
+// the rest of step k's update (look-ahead of one panel), so the diagonal
+// chain does not wait for the bulk of the trailing matrix.
+// Task code: type << 18 | i << 12 | j << 6 | k (type 0 D, 1 C, 2 R, 3 G).
+template <int NB>
+__global__ __launch_bounds__(256) void k_dlu_tasks(double* T, int S, int s, int nt,
+                                                   const int* __restrict__ tasks, int ntasks,
+                                                   int* ver, SyncState* ss, int nstreams,
+                                                   int* stall, DevStats* st, double prel) {
+  __shared__ double A[NB][NB + 1];
+  __shared__ double Bt[NB][NB];
+  __shared__ int task_s, ok_s;
+  const int tid = threadIdx.x, lane = tid % WAVE;
+  const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm_f) : 0.0;
+  for (;;) {
+    if (tid < WAVE) {
+      const int c = next_chunk(ss->dlu_stream, nstreams, lane);
+      if (lane == 0) task_s = c < ntasks ? tasks[c] : -1;
+    }
+    __syncthreads();
+    const int code = task_s;
+    if (code < 0) break;
+    const int type = code >> 18, i = (code >> 12) & 63, j = (code >> 6) & 63, k = code & 63;
+    // inputs: (tile index, count it must reach)
+    if (tid == 0) {
+      int dep[3], want[3], nd = 0;
+      if (type == 0) {
+        dep[nd] = k * nt + k, want[nd++] = k;
+      } else if (type == 1) {
+        dep[nd] = i * nt + k, want[nd++] = k;
+        dep[nd] = k * nt + k, want[nd++] = k + 1;
+      } else if (type == 2) {
+        dep[nd] = k * nt + j, want[nd++] = k;
+        dep[nd] = k * nt + k, want[nd++] = k + 1;
+      } else {
+        dep[nd] = i * nt + j, want[nd++] = k;
+        dep[nd] = i * nt + k, want[nd++] = k + 1;
+        dep[nd] = k * nt + j, want[nd++] = k + 1;
+      }
+      int spins = 0, ok = 1;
+      for (int d = 0; d < nd && ok; d++)
+        while (ld_flag(ver + dep[d]) < want[d])
+          if (!keep_waiting(&spins, stall)) {
+            ok = 0;
+            break;
+          }
+      ok_s = ok;
+    }
+    __syncthreads();
+    if (!ok_s) break;
+    const int r0 = (type == 2 ? k : i) * NB, q0 = (type == 1 ? k : j) * NB;
+    if (type == 0) {
+      // diagonal tile: lane t owns row k0 + t, row k's entries by readlane
+      const int k0 = k * NB;
+      if (tid < WAVE) {
+        const int t = tid;
+        double r[NB];
+#pragma unroll
+        for (int c = 0; c < NB; c++) r[c] = t < NB ? ld_coh(T + (size_t)(k0 + t) * S + k0 + c) : 0.0;
+#pragma unroll
+        for (int kk = 0; kk < NB; kk++) {
+          if (t == kk && k0 + kk < s && fabs(r[kk]) < thr) {
+            st->perturbed = 1;
+            r[kk] = perturb_pivot(r[kk], thr);
+          }
+          const double ukk = readlane_d(r[kk], kk);
+          const double l = r[kk] / ukk;
+#pragma unroll
+          for (int c = kk + 1; c < NB; c++) {
+            const double nv = __builtin_fma(-l, readlane_d(r[c], kk), r[c]);
+            r[c] = t > kk ? nv : r[c];
+          }
+          r[kk] = t > kk ? l : r[kk];
+        }
+        if (t < NB)
+#pragma unroll
+          for (int c = 0; c < NB; c++) st_coh(T + (size_t)(k0 + t) * S + k0 + c, r[c]);
+        stores_done();
+      }
+    } else {
+      // the factored diagonal tile (k, k) in LDS
+      const int k0 = k * NB;
+      if (type != 3) {
+        for (int e = tid; e < NB * NB; e += blockDim.x)
+          A[e / NB][e % NB] = ld_coh(T + (size_t)(k0 + e / NB) * S + k0 + e % NB);
+      } else {
+        // A := L(i, k), Bt := U(k, j)
+        for (int e = tid; e < NB * NB; e += blockDim.x) {
+          A[e / NB][e % NB] = ld_coh(T + (size_t)(i * NB + e / NB) * S + k0 + e % NB);
+          Bt[e / NB][e % NB] = ld_coh(T + (size_t)(k0 + e / NB) * S + j * NB + e % NB);
+        }
+      }
+      __syncthreads();
+      if (type == 1) {
+        if (tid < NB) {
+          double* Ti = T + (size_t)(r0 + tid) * S + q0;
+          double r[NB];
+#pragma unroll
+          for (int c = 0; c < NB; c++) r[c] = ld_coh(Ti + c);
+#pragma unroll
+          for (int kk = 0; kk < NB; kk++) {
+            const double l = r[kk] / A[kk][kk];
+            r[kk] = l;
+#pragma unroll
+            for (int c = kk + 1; c < NB; c++) r[c] = __builtin_fma(-l, A[kk][c], r[c]);
+          }
+#pragma unroll
+          for (int c = 0; c < NB; c++) st_coh(Ti + c, r[c]);
+        }
+      } else if (type == 2) {
+        if (tid < NB) {
+          const int q = q0 + tid;
+          double cv[NB];
+#pragma unroll
+          for (int t = 0; t < NB; t++) cv[t] = ld_coh(T + (size_t)(r0 + t) * S + q);
+#pragma unroll
+          for (int kk = 0; kk < NB; kk++) {
+#pragma unroll
+            for (int t = kk + 1; t < NB; t++) cv[t] = __builtin_fma(-A[t][kk], cv[kk], cv[t]);
+          }
+#pragma unroll
+          for (int t = 0; t < NB; t++) st_coh(T + (size_t)(r0 + t) * S + q, cv[t]);
+        }
+      } else {
+        // 2 x 2 entries per thread: rows ty + 16 a, columns tx + 16 c
+        const int tx = tid % 16, ty = tid / 16;
+        double acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+          for (int c = 0; c < 2; c++)
+            acc[a][c] = ld_coh(T + (size_t)(r0 + ty + 16 * a) * S + q0 + tx + 16 * c);
+#pragma unroll 4
+        for (int kk = 0; kk < NB; kk++) {
+          double lv[2], uv[2];
+#pragma unroll
+          for (int a = 0; a < 2; a++) lv[a] = A[ty + 16 * a][kk];
+#pragma unroll
+          for (int c = 0; c < 2; c++) uv[c] = Bt[kk][tx + 16 * c];
+#pragma unroll
+          for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int c = 0; c < 2; c++) acc[a][c] = __builtin_fma(-lv[a], uv[c], acc[a][c]);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+          for (int c = 0; c < 2; c++)
+            st_coh(T + (size_t)(r0 + ty + 16 * a) * S + q0 + tx + 16 * c, acc[a][c]);
+      }
+      stores_done();
+    }
+    __syncthreads();  // every store of the task complete
+    if (tid == 0) st_flag(ver + (type == 2 ? k : i) * nt + (type == 1 ? k : j), k + 1);
+  }
+}
+
+__global__ void k_dlu_reset(int* ver, int count, SyncState* ss) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < count; e += gridDim.x * blockDim.x)
+    ver[e] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < TICKET_STREAMS)
+    ss->dlu_stream[threadIdx.x * TICKET_STRIDE] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1563,7 +1764,7 @@ __global__ __launch_bounds__(256) void k_trisolve_vflag_mr(const int* __restrict
 // multi-column gather: c[r][i] = x[r][perm[i]] (x: ld n, c/y/z: ld n + 1),
 // y and z set to the sentinel; plus the sync_prep of mask
 __global__ void k_gather_sentinel_mr(const int* __restrict__ gate, int n, int nr, const int* __restrict__ perm,
-                                     const double* __restrict__ x, double* __restrict__ c,
+                                     const double* __restrict__ scale, const double* __restrict__ x, double* __restrict__ c,
                                      double* __restrict__ y, double* __restrict__ z,
                                      SyncState* ss, int mask,
                                      const unsigned char* __restrict__ triv,
@@ -1574,7 +1775,7 @@ __global__ void k_gather_sentinel_mr(const int* __restrict__ gate, int n, int nr
 // Rows without dependencies in the first triangle (triv[i] != 0) get their
 // final value here: y = c, or y = c / u_ii when div is set (a U^T first).
 __global__ void k_gather_sentinel(const int* __restrict__ gate, int n, const int* __restrict__ perm,
-                                  const double* __restrict__ x, double* __restrict__ c,
+                                  const double* __restrict__ scale, const double* __restrict__ x, double* __restrict__ c,
                                   double* __restrict__ y, double* __restrict__ z, SyncState* ss,
                                   int mask, const unsigned char* __restrict__ triv,
                                   const int* __restrict__ diag, const double* __restrict__ val,
@@ -1582,7 +1783,7 @@ __global__ void k_gather_sentinel(const int* __restrict__ gate, int n, const int
   KKT_GATE(gate);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
-    const double ci = x[perm[i]];
+    const double ci = scale ? x[perm[i]] * scale[i] : x[perm[i]];
     c[i] = ci;
     const double sent = __longlong_as_double((long long)SENTINEL);
     y[i] = (triv && triv[i]) ? (div ? ci / val[diag[i]] : ci) : sent;
@@ -1592,7 +1793,7 @@ __global__ void k_gather_sentinel(const int* __restrict__ gate, int n, const int
 }
 
 __global__ void k_gather_sentinel_mr(const int* __restrict__ gate, int n, int nr, const int* __restrict__ perm,
-                                     const double* __restrict__ x, double* __restrict__ c,
+                                     const double* __restrict__ scale, const double* __restrict__ x, double* __restrict__ c,
                                      double* __restrict__ y, double* __restrict__ z,
                                      SyncState* ss, int mask,
                                      const unsigned char* __restrict__ triv,
@@ -1603,7 +1804,8 @@ __global__ void k_gather_sentinel_mr(const int* __restrict__ gate, int n, int nr
   const int r = blockIdx.y;
   if (i < n && r < nr) {
     const size_t o = (size_t)r * (n + 1) + i;
-    const double ci = x[(size_t)r * n + perm[i]];
+    const double xi = x[(size_t)r * n + perm[i]];
+    const double ci = scale ? xi * scale[i] : xi;
     c[o] = ci;
     const double sent = __longlong_as_double((long long)SENTINEL);
     y[o] = (triv && triv[i]) ? (div ? ci / val[diag[i]] : ci) : sent;
@@ -1614,18 +1816,23 @@ __global__ void k_gather_sentinel_mr(const int* __restrict__ gate, int n, int nr
 
 // x[r][perm[i]] = z[r][i] (z: ld n + 1, x: ld n)
 __global__ void k_scatter_mr(const int* __restrict__ gate, int n, int nr, const int* __restrict__ perm,
-                             const double* __restrict__ z, double* __restrict__ x) {
+                             const double* __restrict__ scale, const double* __restrict__ z,
+                             double* __restrict__ x) {
   KKT_GATE(gate);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (i < n && r < nr) x[(size_t)r * n + perm[i]] = z[(size_t)r * (n + 1) + i];
+  if (i < n && r < nr) {
+    const double zi = z[(size_t)r * (n + 1) + i];
+    x[(size_t)r * n + perm[i]] = scale ? zi * scale[i] : zi;
+  }
 }
 
-__global__ void k_gather_prep(const int* __restrict__ gate, int n, const int* __restrict__ perm, const double* __restrict__ x,
+__global__ void k_gather_prep(const int* __restrict__ gate, int n, const int* __restrict__ perm,
+                              const double* __restrict__ scale, const double* __restrict__ x,
                               double* __restrict__ y, SyncState* ss, int mask) {
   KKT_GATE(gate);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = x[perm[i]];
+  if (i < n) y[i] = scale ? x[perm[i]] * scale[i] : x[perm[i]];
   if (ss && i == 0) sync_prep(ss, mask);
 }
 
@@ -1637,6 +1844,7 @@ __global__ void k_reset_stats(DevStats* st, int what) {
       st->anorm = 0ull;
       st->anorm1 = 0ull;
       st->umax = 0ull;
+      st->anorm_f = 0ull;
       st->tiny = 0;
       st->perturbed = 0;
     }
@@ -1703,7 +1911,7 @@ __global__ __launch_bounds__(256) void k_pivot_stats(int n, const int* __restric
   const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = gridDim.x * blockDim.x / WAVE;
-  const double anorm = __longlong_as_double((long long)st->anorm);
+  const double anorm = __longlong_as_double((long long)st->anorm_f);
   double mn = __builtin_huge_val(), mx = 0.0, um = 0.0;
   int tiny = 0;
   for (int r0 = wid * (WAVE / RG); r0 < n; r0 += nw * (WAVE / RG)) {
@@ -1788,18 +1996,26 @@ __global__ __launch_bounds__(256) void k_seg_stats(const int* __restrict__ gate,
 
 // copy of A's values and ||A||_inf (and, if rowabs != nullptr, every row's
 // absolute sum for per-instance norms)
+// A's values copied (dst), their row sums of |a| (rowabs) and ||A||_inf.
+// luA: the values scattered into factor order through a2lu.  fnorm: also
+// the factored matrix's norm (anorm_f; red_out then holds two maxima per
+// workgroup).  ascale (with avs): the factored matrix is the matched and
+// scaled one, a_p * ascale[p] (exact powers of two) goes to avs and luA, and
+// its row sums give anorm_f.
 __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict__ arow,
                                                     const double* __restrict__ src, double* dst,
                                                     DevStats* st, SyncState* ss,
                                                     double* __restrict__ rowabs,
                                                     const int* __restrict__ a2lu,
                                                     double* __restrict__ luA,
-                                                    double* __restrict__ red_out) {
+                                                    double* __restrict__ red_out, int fnorm,
+                                                    const double* __restrict__ ascale,
+                                                    double* __restrict__ avs) {
   const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = gridDim.x * blockDim.x / WAVE;
   if (ss && blockIdx.x == 0 && threadIdx.x == 0) sync_prep(ss, 1);
-  double m = 0.0;
+  double m = 0.0, mf = 0.0;
   // four row groups per round, their loads all in flight before any is used
   constexpr int U = 4;
   const int stride = nw * (WAVE / RG);
@@ -1828,33 +2044,49 @@ __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      double s = 0.0;
+      double s = 0.0, sf = 0.0;
       if (p0[u] < pe[u]) {
         dst[p0[u]] = v0[u];
-        if (luA) luA[q0[u]] = v0[u];
+        const double w = ascale ? v0[u] * ascale[p0[u]] : v0[u];
+        if (ascale) avs[p0[u]] = w;
+        if (luA) luA[q0[u]] = w;
         s = fabs(v0[u]);
+        sf = fabs(w);
       }
       for (int p = p0[u] + RG; p < pe[u]; p += RG) {
         const double v = src[p];
         dst[p] = v;
-        if (luA) luA[a2lu[p]] = v;
+        const double w = ascale ? v * ascale[p] : v;
+        if (ascale) avs[p] = w;
+        if (luA) luA[a2lu[p]] = w;
         s += fabs(v);
+        sf += fabs(w);
       }
       s = group_sum(s);
+      sf = group_sum(sf);
       const int i = ii[u];
       if (i < n) {
         m = nanmax(m, s);
+        mf = nanmax(mf, sf);
         if (rowabs && gl == 0) rowabs[i] = s;
       }
     }
   }
-  __shared__ double red[4];
-  m = block_nanmax(m, red);
+  __shared__ double red[2][4];
+  m = block_nanmax(m, red[0]);
+  mf = block_nanmax(mf, red[1]);
   if (threadIdx.x == 0) {
-    if (red_out)
-      red_out[blockIdx.x] = m;  // reduced by k_red_max
-    else
+    if (red_out) {  // reduced by k_red_max
+      if (fnorm) {
+        red_out[2 * blockIdx.x] = m;
+        red_out[2 * blockIdx.x + 1] = mf;
+      } else {
+        red_out[blockIdx.x] = m;
+      }
+    } else {
       atomicMax(&st->anorm, dbits(m));
+      if (fnorm) atomicMax(&st->anorm_f, dbits(mf));
+    }
   }
 }
 
@@ -1950,17 +2182,20 @@ __global__ __launch_bounds__(256) void k_ltsolve_cols(const int* __restrict__ ga
   if (lane == 0) y[j] -= s;
 }
 
-__global__ void k_gather(const int* __restrict__ gate, int n, const int* __restrict__ perm, const double* __restrict__ x,
+// y[i] = x[perm[i]] (times scale[i]); scatter: y[perm[i]] = x[i] (times scale[i])
+__global__ void k_gather(const int* __restrict__ gate, int n, const int* __restrict__ perm,
+                         const double* __restrict__ scale, const double* __restrict__ x,
                          double* __restrict__ y) {
   KKT_GATE(gate);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = x[perm[i]];
+  if (i < n) y[i] = scale ? x[perm[i]] * scale[i] : x[perm[i]];
 }
-__global__ void k_scatter(const int* __restrict__ gate, int n, const int* __restrict__ perm, const double* __restrict__ x,
+__global__ void k_scatter(const int* __restrict__ gate, int n, const int* __restrict__ perm,
+                          const double* __restrict__ scale, const double* __restrict__ x,
                           double* __restrict__ y) {
   KKT_GATE(gate);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[perm[i]] = x[i];
+  if (i < n) y[perm[i]] = scale ? x[i] * scale[i] : x[i];
 }
 
 // r = b - op(A) x, max |r|, max |x| (8 lanes per row of op(A), one atomic
@@ -2345,7 +2580,7 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
   // LDS per wave: values (cap doubles), list bounds per L entry (cap int2)
   double* sv = smem_d + (size_t)wave * cap;
   int2* sf = reinterpret_cast<int2*>(smem_d + (size_t)WPB * cap) + (size_t)wave * cap;
-  const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm) : 0.0;
+  const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm_f) : 0.0;
   for (;;) {
     const int tk = next_chunk(tickets, nstreams, lane);
     if (tk >= nchunks) break;
@@ -2489,7 +2724,7 @@ __global__ __launch_bounds__(WPR* WAVE) void k_refactor_wg(
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
   const int lane = threadIdx.x % WAVE;
   double* sv = smem_d;  // the row's values
-  const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm) : 0.0;
+  const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm_f) : 0.0;
   struct Step {
     double ukk;
     double u[R];
@@ -3087,6 +3322,10 @@ __global__ __launch_bounds__(FG_T) void k_fg_finish(int n, const double* __restr
 // ---------------------------------------------------------------------------
 void set_launch_gate(const int* gate) { t_gate = gate; }
 
+bool set_debug_schedule(int on) {
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_debug_schedule), &on, sizeof(int)) == hipSuccess;
+}
+
 namespace {
 // refinement passes: elementwise grids (four elements per thread at least)
 // and row grids (eight lanes per row, four row groups per round)
@@ -3196,13 +3435,14 @@ inline int rows_grid_red(int n) { return std::max(1, std::min(cdiv(n, 32), RED_B
 
 void launch_copy_anorm(int n, const int* arow, const int*, const double* src, double* dst,
                        DevStats* st, hipStream_t s, SyncState* ss, double* rowabs,
-                       const int* a2lu, double* luA, double* red) {
+                       const int* a2lu, double* luA, double* red, int fnorm,
+                       const double* ascale, double* avs) {
   const int nb = red ? rows_grid_red(n) : rows_grid(n);
   hipLaunchKernelGGL(k_copy_anorm, dim3(nb), dim3(256), 0, s, n, arow, src, dst, st, ss, rowabs,
-                     a2lu, luA, red);
+                     a2lu, luA, red, fnorm, ascale, avs);
   if (red)
-    hipLaunchKernelGGL(k_red_max, dim3(1), dim3(1024), 0, s, (const double*)red, nb, 1,
-                       &st->anorm, &st->anorm);
+    hipLaunchKernelGGL(k_red_max, dim3(1), dim3(1024), 0, s, (const double*)red, nb,
+                       fnorm ? 2 : 1, &st->anorm, fnorm ? &st->anorm_f : &st->anorm);
 }
 
 void launch_seg_stats(int count, const int* row_off, const double* matabs, const double* r,
@@ -3453,6 +3693,60 @@ void launch_tail_scatter(const LUView& lu, int c0, int s, int S, double* T, hipS
                      lu.col, lu.val, T);
 }
 
+std::vector<int> dense_lu_tasks(int nt) {
+  std::vector<int> t;
+  auto code = [](int type, int i, int j, int k) { return type << 18 | i << 12 | j << 6 | k; };
+  auto panel = [&](int k) {
+    t.push_back(code(0, k, k, k));
+    for (int r = k + 1; r < nt; r++) {
+      t.push_back(code(1, r, k, k));
+      t.push_back(code(2, k, r, k));
+    }
+  };
+  panel(0);
+  for (int k = 0; k + 1 < nt; k++) {
+    const int n1 = k + 1;
+    // the next panel's tiles, then that panel, then the rest of step k
+    t.push_back(code(3, n1, n1, k));
+    for (int r = n1 + 1; r < nt; r++) {
+      t.push_back(code(3, r, n1, k));
+      t.push_back(code(3, n1, r, k));
+    }
+    panel(n1);
+    for (int i = n1 + 1; i < nt; i++)
+      for (int j = n1 + 1; j < nt; j++) t.push_back(code(3, i, j, k));
+  }
+  return t;
+}
+
+void launch_dlu_reset(int* ver, int nt, SyncState* ss, hipStream_t st) {
+  hipLaunchKernelGGL(k_dlu_reset, dim3(std::max(1, cdiv(nt * nt, 256))), dim3(256), 0, st, ver,
+                     nt * nt, ss);
+}
+
+bool launch_dense_lu_tasks(double* T, int S, int s, const int* tasks, int ntasks, int* ver,
+                           SyncState* ss, int* stall, DevStats* stats, double prel,
+                           hipStream_t st) {
+  if (S <= 0 || S % DLU_NB != 0 || S / DLU_NB > 64) return false;
+  static int ncu = 0, occ = 0;
+  if (ncu == 0) {
+    int d = 0;
+    (void)hipGetDevice(&d);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
+    if (ncu <= 0) ncu = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, reinterpret_cast<const void*>(&k_dlu_tasks<DLU_NB>), 256, 0) != hipSuccess ||
+        occ <= 0)
+      occ = 1;
+  }
+  // every workgroup resident (each ticket stream needs a running workgroup)
+  const int grid = std::max(1, std::min(ncu * occ, ntasks));
+  const int nstreams = std::min(TICKET_STREAMS, grid);
+  hipLaunchKernelGGL(k_dlu_tasks<DLU_NB>, dim3(grid), dim3(256), 0, st, T, S, s, S / DLU_NB, tasks,
+                     ntasks, ver, ss, nstreams, stall, stats, prel);
+  return true;
+}
+
 void launch_tail_gather(const LUView& lu, int c0, const double* T, int S, hipStream_t st) {
   const int s = lu.n - c0;
   if (s <= 0) return;
@@ -3646,16 +3940,17 @@ void launch_trisolve_seg(int mode, const SegSched& sg, const double* val, const 
 #undef SG_LAUNCH
 }
 
-void launch_gather_sentinel_mr(int n, int nr, const int* perm, const double* x, double* c,
+void launch_gather_sentinel_mr(int n, int nr, const int* perm, const double* scale, const double* x, double* c,
                                double* y, double* z, SyncState* ss, int mask, hipStream_t s,
                                const unsigned char* triv, const int* diag, const double* val,
                                int div) {
-  hipLaunchKernelGGL(k_gather_sentinel_mr, dim3(cdiv(n, 256), nr), dim3(256), 0, s, t_gate, n, nr, perm,
+  hipLaunchKernelGGL(k_gather_sentinel_mr, dim3(cdiv(n, 256), nr), dim3(256), 0, s, t_gate, n, nr, perm, scale,
                      x, c, y, z, ss, mask, triv, diag, val, div);
 }
 
-void launch_scatter_mr(int n, int nr, const int* perm, const double* z, double* x, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter_mr, dim3(cdiv(n, 256), nr), dim3(256), 0, s, t_gate, n, nr, perm, z, x);
+void launch_scatter_mr(int n, int nr, const int* perm, const double* scale, const double* z, double* x,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_mr, dim3(cdiv(n, 256), nr), dim3(256), 0, s, t_gate, n, nr, perm, scale, z, x);
 }
 
 void launch_residual_mr(int n, int nr, const int* ptr, const int* idx, const int* pos,
@@ -3666,11 +3961,11 @@ void launch_residual_mr(int n, int nr, const int* ptr, const int* idx, const int
                      ptr, idx, pos, aval, B, X, colmax);
 }
 
-void launch_gather_sentinel(int n, const int* perm, const double* x, double* c, double* y,
+void launch_gather_sentinel(int n, const int* perm, const double* scale, const double* x, double* c, double* y,
                             double* z, SyncState* ss, int mask, hipStream_t s,
                             const unsigned char* triv, const int* diag, const double* val,
                             int div) {
-  hipLaunchKernelGGL(k_gather_sentinel, dim3(cdiv(n, 256)), dim3(256), 0, s, t_gate, n, perm, x, c, y, z,
+  hipLaunchKernelGGL(k_gather_sentinel, dim3(cdiv(n, 256)), dim3(256), 0, s, t_gate, n, perm, scale, x, c, y, z,
                      ss, mask, triv, diag, val, div);
 }
 
@@ -3678,9 +3973,9 @@ void launch_sync_prep(SyncState* ss, int mask, hipStream_t s) {
   hipLaunchKernelGGL(k_sync_prep, dim3(1), dim3(64), 0, s, ss, mask);
 }
 
-void launch_gather_prep(int n, const int* perm, const double* x, double* y, SyncState* ss,
+void launch_gather_prep(int n, const int* perm, const double* scale, const double* x, double* y, SyncState* ss,
                         int mask, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_prep, dim3(cdiv(n, 256)), dim3(256), 0, s, t_gate, n, perm, x, y, ss, mask);
+  hipLaunchKernelGGL(k_gather_prep, dim3(cdiv(n, 256)), dim3(256), 0, s, t_gate, n, perm, scale, x, y, ss, mask);
 }
 
 void launch_anorm1(int n, const int* cptr, const int* cpos, const double* aval, DevStats* st,
@@ -3721,11 +4016,11 @@ void launch_ltsolve_cols(const LUView& lu, const int* cols, int ncols, const int
                      ncols, tptr, trow, tpos, lu.val, y);
 }
 
-void launch_gather(int n, const int* perm, const double* x, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather, dim3(cdiv(n, 256)), dim3(256), 0, s, t_gate, n, perm, x, y);
+void launch_gather(int n, const int* perm, const double* scale, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather, dim3(cdiv(n, 256)), dim3(256), 0, s, t_gate, n, perm, scale, x, y);
 }
-void launch_scatter(int n, const int* perm, const double* x, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter, dim3(cdiv(n, 256)), dim3(256), 0, s, t_gate, n, perm, x, y);
+void launch_scatter(int n, const int* perm, const double* scale, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter, dim3(cdiv(n, 256)), dim3(256), 0, s, t_gate, n, perm, scale, x, y);
 }
 
 void launch_residual(int n, char, const int* ptr, const int* idx, const int* pos,

@@ -45,6 +45,10 @@ struct kkt_ctx {
   int *ut_ptr = nullptr, *ut_row = nullptr, *ut_pos = nullptr;
   int *lt_ptr = nullptr, *lt_row = nullptr, *lt_pos = nullptr;
   int *pin = nullptr, *qperm = nullptr;  // pin[i] = Q[P[i]], qperm[k] = Q[k]
+  // matching and scaling (null without): pin[i] = match[Q[P[i]]] (A's row),
+  // rowsc[i] = dr[pin[i]], colsc[k] = dc[Q[k]]; ascale[p] = dr_i dc_j per
+  // stored entry of A and avs the scaled values (factored matrix, A's order)
+  double *rowsc = nullptr, *colsc = nullptr, *ascale = nullptr, *avs = nullptr;
   // A (CSR, column view) and the current values
   int *a_rowptr = nullptr, *a_col = nullptr, *at_ptr = nullptr, *at_row = nullptr,
       *at_pos = nullptr;
@@ -71,6 +75,9 @@ struct kkt_ctx {
   // (tail_s of them), row-major tail_S x tail_S workspace and panel scratch
   int tail_s = 0, tail_c0 = 0, tail_S = 0;
   double *tail_T = nullptr, *tail_dsc = nullptr, *tail_rhs = nullptr;
+  // its task-launch factorization: task list and per-tile operation counts
+  int *dlu_tasks = nullptr, *dlu_ver = nullptr;
+  int dlu_ntasks = 0;
   double* red = nullptr;  // scratch of the two-stage maxima (RED_SCRATCH doubles)
   int *tail_split0 = nullptr, *tail_split2 = nullptr;
   // U solve: rows with entries in the dense block's columns, where those
@@ -128,6 +135,14 @@ struct kkt_ctx {
   FgBufs fb{};
   int fg_cols = 1;
   bool fg_pending = false;
+  // adaptive launch budget (refine_budget = -1): each solve's outcome is
+  // copied to pinned host memory behind an event; a later solve reads it
+  // only if the event has completed (never waits)
+  FgState* h_fs = nullptr;  // pinned
+  hipEvent_t ev_fs = nullptr;
+  bool ev_fs_recorded = false;
+  int auto_need = 0;        // iterations the last observed solve needed
+  bool auto_full = false;   // next solve launches the full budget
   // block-diagonal batch (batch_count > 0): instance offsets, per-row/column
   // absolute sums, per-instance maxima (3 per instance) and etas
   int batch_count = 0;
@@ -173,6 +188,13 @@ void free_device(kkt_handle h) {
   h->device_bytes = 0;
   if (h->h_st) (void)hipHostFree(h->h_st);
   h->h_st = nullptr;
+  if (h->h_fs) (void)hipHostFree(h->h_fs);
+  h->h_fs = nullptr;
+  if (h->ev_fs) (void)hipEventDestroy(h->ev_fs);
+  h->ev_fs = nullptr;
+  h->ev_fs_recorded = false;
+  h->auto_need = 0;
+  h->auto_full = false;
   if (h->h_colmax) (void)hipHostFree(h->h_colmax);
   h->h_colmax = nullptr;
   h->mc = h->my = h->mz = nullptr;
@@ -214,6 +236,13 @@ double bits_to_double(unsigned long long b) {
   return d;
 }
 
+// Scale that goes with a permutation in the solves' gathers and scatters:
+// the matched and scaled analysis factors Ahat = Pm Dr A Dc, so the row
+// permutation (pin) carries dr and the column permutation (qperm) dc.
+const double* scale_of(kkt_handle h, const int* perm) {
+  return perm == h->pin ? h->rowsc : perm == h->qperm ? h->colsc : nullptr;
+}
+
 LUView view(kkt_handle h) {
   return LUView{h->an.n, h->lu_rowptr, h->lu_col, h->diag, h->lu_src, h->lu_val};
 }
@@ -229,7 +258,7 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
     // approximate triangular solves: `sweeps` Jacobi sweeps per triangle,
     // starting from the right-hand side (FGMRES takes the variable
     // preconditioner)
-    launch_gather(n, h->pin, b, h->tc, s);
+    launch_gather(n, h->pin, scale_of(h, h->pin), b, h->tc, s);
     const double* cur = h->tc;
     double* bufs[2] = {h->ty, h->tz};
     int k = 0;
@@ -245,7 +274,7 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
       launch_jacobi_sweep(1, lu, cu, cur, bufs[k], s);
       cur = bufs[k];
     }
-    launch_scatter(n, h->qperm, cur, x, s);
+    launch_scatter(n, h->qperm, scale_of(h, h->qperm), cur, x, s);
     return;
   }
   if (h->use_sn) {
@@ -254,7 +283,7 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
     int* stall = &h->st->stall;
     const int c0 = h->tail_c0, ts = h->tail_s, S = h->tail_S;
     if (op == 'N') {
-      launch_gather_sentinel(n, h->pin, b, h->tc, h->ty, h->tz, h->ss, 0x6, s, h->sn_triv0,
+      launch_gather_sentinel(n, h->pin, scale_of(h, h->pin), b, h->tc, h->ty, h->tz, h->ss, 0x6, s, h->sn_triv0,
                              h->diag, h->lu_val, 0);
       launch_trisolve_sn(0, 1, lu, h->chs[0], nullptr, nullptr, nullptr, h->tc, h->ty, h->ss, 1,
                          stall, s);
@@ -265,9 +294,9 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
       launch_udense_pre(h->u_nrows, h->u_rows, h->u_xend, lu, h->tz, h->u_pre, s);
       launch_trisolve_sn(1, 1, lu, h->chs[1], nullptr, nullptr, nullptr, h->ty, h->tz, h->ss, 2,
                          stall, s, h->u_xend, h->u_pre);
-      launch_scatter(n, h->qperm, h->tz, x, s);
+      launch_scatter(n, h->qperm, scale_of(h, h->qperm), h->tz, x, s);
     } else {
-      launch_gather_sentinel(n, h->qperm, b, h->tc, h->ty, h->tz, h->ss, 0x6, s, h->sn_triv2,
+      launch_gather_sentinel(n, h->qperm, scale_of(h, h->qperm), b, h->tc, h->ty, h->tz, h->ss, 0x6, s, h->sn_triv2,
                              h->diag, h->lu_val, 1);
       launch_trisolve_sn(2, 1, lu, h->chs[2], h->ut_ptr, h->ut_row, h->ut_pos, h->tc, h->ty, h->ss,
                          1, stall, s);
@@ -277,7 +306,7 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
                            h->tail_rhs, h->tz, stall, s);
       launch_trisolve_sn(3, 1, lu, h->chs[3], h->lt_ptr, h->lt_row, h->lt_pos, h->ty, h->tz, h->ss,
                          2, stall, s);
-      launch_scatter(n, h->pin, h->tz, x, s);
+      launch_scatter(n, h->pin, scale_of(h, h->pin), h->tz, x, s);
     }
     return;
   }
@@ -292,54 +321,54 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
       launch_trisolve_seg(mode, h->seg_post[mode], h->lu_val, c, y, s);
     };
     if (op == 'N') {
-      launch_gather_sentinel(n, h->pin, b, h->tc, h->ty, h->tz, h->ss, 0x6, s);
+      launch_gather_sentinel(n, h->pin, scale_of(h, h->pin), b, h->tc, h->ty, h->tz, h->ss, 0x6, s);
       tri(0, nullptr, nullptr, nullptr, h->tc, h->ty, 1);
       tri(1, nullptr, nullptr, nullptr, h->ty, h->tz, 2);
-      launch_scatter(n, h->qperm, h->tz, x, s);
+      launch_scatter(n, h->qperm, scale_of(h, h->qperm), h->tz, x, s);
     } else {
-      launch_gather_sentinel(n, h->qperm, b, h->tc, h->ty, h->tz, h->ss, 0x6, s);
+      launch_gather_sentinel(n, h->qperm, scale_of(h, h->qperm), b, h->tc, h->ty, h->tz, h->ss, 0x6, s);
       tri(2, h->ut_ptr, h->ut_row, h->ut_pos, h->tc, h->ty, 1);
       tri(3, h->lt_ptr, h->lt_row, h->lt_pos, h->ty, h->tz, 2);
-      launch_scatter(n, h->pin, h->tz, x, s);
+      launch_scatter(n, h->pin, scale_of(h, h->pin), h->tz, x, s);
     }
     return;
   }
   if (h->syncfree) {
     if (op == 'N') {
-      launch_gather_prep(n, h->pin, b, h->tmp, h->ss, 0x6, s);
+      launch_gather_prep(n, h->pin, scale_of(h, h->pin), b, h->tmp, h->ss, 0x6, s);
       launch_trisolve_syncfree(0, lu, h->ch_l, nullptr, nullptr, nullptr, h->tmp, h->ready_a,
                                h->ss, 1, &h->st->stall, s);
       launch_trisolve_syncfree(1, lu, h->ch_u, nullptr, nullptr, nullptr, h->tmp, h->ready_b,
                                h->ss, 2, &h->st->stall, s);
-      launch_scatter(n, h->qperm, h->tmp, x, s);
+      launch_scatter(n, h->qperm, scale_of(h, h->qperm), h->tmp, x, s);
     } else {
-      launch_gather_prep(n, h->qperm, b, h->tmp, h->ss, 0x6, s);
+      launch_gather_prep(n, h->qperm, scale_of(h, h->qperm), b, h->tmp, h->ss, 0x6, s);
       launch_trisolve_syncfree(2, lu, h->ch_ut, h->ut_ptr, h->ut_row, h->ut_pos, h->tmp,
                                h->ready_a, h->ss, 1, &h->st->stall, s);
       launch_trisolve_syncfree(3, lu, h->ch_lt, h->lt_ptr, h->lt_row, h->lt_pos, h->tmp,
                                h->ready_b, h->ss, 2, &h->st->stall, s);
-      launch_scatter(n, h->pin, h->tmp, x, s);
+      launch_scatter(n, h->pin, scale_of(h, h->pin), h->tmp, x, s);
     }
     return;
   }
   if (op == 'N') {
-    launch_gather(n, h->pin, b, h->tmp, s);
+    launch_gather(n, h->pin, scale_of(h, h->pin), b, h->tmp, s);
     for (size_t l = 0; l + 1 < A.lev_ptr.size(); l++)
       launch_lsolve_rows(lu, h->lev_rows + A.lev_ptr[l], A.lev_ptr[l + 1] - A.lev_ptr[l], 0,
                          h->tmp, s);
     for (size_t l = 0; l + 1 < A.ulev_ptr.size(); l++)
       launch_usolve_rows(lu, h->ulev_rows + A.ulev_ptr[l], A.ulev_ptr[l + 1] - A.ulev_ptr[l], 0,
                          h->tmp, s);
-    launch_scatter(n, h->qperm, h->tmp, x, s);
+    launch_scatter(n, h->qperm, scale_of(h, h->qperm), h->tmp, x, s);
   } else {
-    launch_gather(n, h->qperm, b, h->tmp, s);
+    launch_gather(n, h->qperm, scale_of(h, h->qperm), b, h->tmp, s);
     for (size_t l = 0; l + 1 < A.utlev_ptr.size(); l++)
       launch_utsolve_cols(lu, h->utlev_rows + A.utlev_ptr[l], A.utlev_ptr[l + 1] - A.utlev_ptr[l],
                           h->ut_ptr, h->ut_row, h->ut_pos, h->tmp, s);
     for (size_t l = 0; l + 1 < A.ltlev_ptr.size(); l++)
       launch_ltsolve_cols(lu, h->ltlev_rows + A.ltlev_ptr[l], A.ltlev_ptr[l + 1] - A.ltlev_ptr[l],
                           h->lt_ptr, h->lt_row, h->lt_pos, h->tmp, s);
-    launch_scatter(n, h->pin, h->tmp, x, s);
+    launch_scatter(n, h->pin, scale_of(h, h->pin), h->tmp, x, s);
   }
 }
 
@@ -366,7 +395,7 @@ void apply_factors_multi(kkt_handle h, char op, int nr, const double* b, double*
       double* xx = x + (size_t)r0 * n;
       double *mc = h->mc + r0 * ld, *my = h->my + r0 * ld, *mz = h->mz + r0 * ld;
       if (op == 'N') {
-        launch_gather_sentinel_mr(n, k, h->pin, bb, mc, my, mz, h->ss, 0x6, s, h->sn_triv0,
+        launch_gather_sentinel_mr(n, k, h->pin, scale_of(h, h->pin), bb, mc, my, mz, h->ss, 0x6, s, h->sn_triv0,
                                   h->diag, h->lu_val, 0);
         launch_trisolve_sn(0, k, lu, h->chs[0], nullptr, nullptr, nullptr, mc, my, h->ss, 1,
                            stall, s);
@@ -376,9 +405,9 @@ void apply_factors_multi(kkt_handle h, char op, int nr, const double* b, double*
                           h->tail_rhs, mz, s);
         launch_trisolve_sn(1, k, lu, h->chs[1], nullptr, nullptr, nullptr, my, mz, h->ss, 2,
                            stall, s);
-        launch_scatter_mr(n, k, h->qperm, mz, xx, s);
+        launch_scatter_mr(n, k, h->qperm, scale_of(h, h->qperm), mz, xx, s);
       } else {
-        launch_gather_sentinel_mr(n, k, h->qperm, bb, mc, my, mz, h->ss, 0x6, s, h->sn_triv2,
+        launch_gather_sentinel_mr(n, k, h->qperm, scale_of(h, h->qperm), bb, mc, my, mz, h->ss, 0x6, s, h->sn_triv2,
                                   h->diag, h->lu_val, 1);
         launch_trisolve_sn(2, k, lu, h->chs[2], h->ut_ptr, h->ut_row, h->ut_pos, mc, my, h->ss, 1,
                            stall, s);
@@ -388,25 +417,25 @@ void apply_factors_multi(kkt_handle h, char op, int nr, const double* b, double*
                           h->tail_rhs, mz, s);
         launch_trisolve_sn(3, k, lu, h->chs[3], h->lt_ptr, h->lt_row, h->lt_pos, my, mz, h->ss, 2,
                            stall, s);
-        launch_scatter_mr(n, k, h->pin, mz, xx, s);
+        launch_scatter_mr(n, k, h->pin, scale_of(h, h->pin), mz, xx, s);
       }
     }
     return;
   }
   if (op == 'N') {
-    launch_gather_sentinel_mr(n, nr, h->pin, b, h->mc, h->my, h->mz, h->ss, 0x6, s);
+    launch_gather_sentinel_mr(n, nr, h->pin, scale_of(h, h->pin), b, h->mc, h->my, h->mz, h->ss, 0x6, s);
     launch_trisolve_vflag_mr(0, nr, lu, h->ch_l, nullptr, nullptr, nullptr, h->mc, h->my, h->ss,
                              1, stall, s);
     launch_trisolve_vflag_mr(1, nr, lu, h->ch_u, nullptr, nullptr, nullptr, h->my, h->mz, h->ss,
                              2, stall, s);
-    launch_scatter_mr(n, nr, h->qperm, h->mz, x, s);
+    launch_scatter_mr(n, nr, h->qperm, scale_of(h, h->qperm), h->mz, x, s);
   } else {
-    launch_gather_sentinel_mr(n, nr, h->qperm, b, h->mc, h->my, h->mz, h->ss, 0x6, s);
+    launch_gather_sentinel_mr(n, nr, h->qperm, scale_of(h, h->qperm), b, h->mc, h->my, h->mz, h->ss, 0x6, s);
     launch_trisolve_vflag_mr(2, nr, lu, h->ch_ut, h->ut_ptr, h->ut_row, h->ut_pos, h->mc, h->my,
                              h->ss, 1, stall, s);
     launch_trisolve_vflag_mr(3, nr, lu, h->ch_lt, h->lt_ptr, h->lt_row, h->lt_pos, h->my, h->mz,
                              h->ss, 2, stall, s);
-    launch_scatter_mr(n, nr, h->pin, h->mz, x, s);
+    launch_scatter_mr(n, nr, h->pin, scale_of(h, h->pin), h->mz, x, s);
   }
 }
 
@@ -550,11 +579,36 @@ kkt_status solve_one(kkt_handle h, char op, const double* b, double* x, hipStrea
   return (eta <= o.eta_target) ? KKT_OK : KKT_WARN_NOT_CONVERGED;
 }
 
-// Iterations the device-checked refinement launches per group.
-int fg_budget(const kkt_options& o) {
-  const int b = o.refine_budget > 0 ? std::min(o.refine_budget, o.fgmres_max_iters)
-                                    : o.fgmres_max_iters;
+// Iterations the device-checked refinement launches per group.  Adaptive
+// (refine_budget = -1): twice what the last observed solve needed plus two;
+// the full budget after a solve that did not converge, after the matrix
+// changed without a refactorization (kkt_update_matrix), and whenever
+// refinement is part of the configuration (static pivoting, Jacobi-sweep
+// solves, forced iterations).
+int fg_budget(kkt_handle h) {
+  const kkt_options& o = h->opt;
+  int b = o.fgmres_max_iters;
+  if (o.refine_budget > 0) {
+    b = std::min(o.refine_budget, o.fgmres_max_iters);
+  } else if (o.refine_budget < 0 && o.pivot_perturb_rel == 0.0 && o.solve_jacobi_sweeps == 0 &&
+             o.min_iters == 0) {
+    if (h->ev_fs_recorded && hipEventQuery(h->ev_fs) == hipSuccess) {
+      h->auto_need = h->h_fs->it_max;
+      if (h->h_fs->not_conv) h->auto_full = true;
+      h->ev_fs_recorded = false;
+    }
+    if (!h->auto_full) b = std::min(o.fgmres_max_iters, 2 * h->auto_need + 2);
+    h->auto_full = false;
+  }
   return std::max(b, std::min(o.min_iters, o.fgmres_max_iters));
+}
+
+// Outcome of an adaptive-budget solve, copied behind an event (no wait).
+void fg_observe(kkt_handle h, hipStream_t s) {
+  if (h->opt.refine_budget >= 0 || !h->h_fs || !h->ev_fs) return;
+  if (hipMemcpyAsync(h->h_fs, h->fs, sizeof(FgState), hipMemcpyDeviceToHost, s) == hipSuccess &&
+      hipEventRecord(h->ev_fs, s) == hipSuccess)
+    h->ev_fs_recorded = true;
 }
 
 // M^{-1} for g columns (column stride n)
@@ -594,7 +648,7 @@ void check_group(kkt_handle h, const FgBufs& fb, char op, int g, const double* b
 // fb: the refinement's state and partial sums (the handle's, or the
 // library's static scratch array for kkt_solve_noalloc).
 void solve_group_async(kkt_handle h, const FgBufs& fb, char op, int g, const double* b, double* x,
-                       bool first_group, hipStream_t s) {
+                       bool first_group, int budget, hipStream_t s) {
   const int n = h->an.n, m = h->m;
   const kkt_options& o = h->opt;
   const FgParams p{o.eta_target, o.min_iters, o.fgmres_max_iters};
@@ -602,7 +656,6 @@ void solve_group_async(kkt_handle h, const FgBufs& fb, char op, int g, const dou
   launch_fg_begin(fb.fs, first_group ? 1 : 0, s);
   apply_group(h, op, g, b, x, s);
   check_group(h, fb, op, g, b, x, 0, 1, p, s);
-  const int budget = fg_budget(o);
   const bool ir = o.refine == 1;
   set_launch_gate(&fb.fs->stop_all);
   for (int it = 0; it < budget; it++) {
@@ -632,8 +685,10 @@ void solve_group_async(kkt_handle h, const FgBufs& fb, char op, int g, const dou
 }
 
 // All right-hand sides, device-checked, in groups of the handle's width.
+// budget: iterations launched per group (fg_budget; a captured graph takes the
+// full budget, since it cannot adapt between replays)
 void solve_async(kkt_handle h, const FgBufs& fb, char op, int nrhs, const double* b, double* x,
-                 hipStream_t s) {
+                 int budget, hipStream_t s) {
   const int n = h->an.n;
   // one column at a time for approximate solves (no multi-column form) and
   // batches (their stop test is per instance of one column)
@@ -641,7 +696,7 @@ void solve_async(kkt_handle h, const FgBufs& fb, char op, int nrhs, const double
       ((op == 'N' && h->opt.solve_jacobi_sweeps > 0) || h->batch_count > 0) ? 1 : h->fg_cols;
   for (int c0 = 0; c0 < nrhs; c0 += gmax) {
     const int g = std::min(gmax, nrhs - c0);
-    solve_group_async(h, fb, op, g, b + (size_t)c0 * n, x + (size_t)c0 * n, c0 == 0, s);
+    solve_group_async(h, fb, op, g, b + (size_t)c0 * n, x + (size_t)c0 * n, c0 == 0, budget, s);
   }
 }
 
@@ -741,7 +796,10 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
       o.refactor_crit_height < -1 || o.refactor_waves_per_cu < 0 || o.refine < 0 || o.refine > 1 ||
       o.auto_reanalyze < 0 || o.auto_reanalyze > 1 || o.solve_jacobi_sweeps < 0 ||
       o.refactor_short_rows < -1 || o.refactor_short_rows > 0 || o.refactor_long_rows < -1 ||
-      o.refactor_long_rows > 0 || o.refine_sync < 0 || o.refine_sync > 1 || o.refine_budget < 0 ||
+      o.refactor_long_rows > 0 || o.refine_sync < 0 || o.refine_sync > 1 || o.refine_budget < -1 ||
+      o.dense_lu < 0 || o.dense_lu > 1 || o.debug_spin_limit < 0 || o.debug_schedule < 0 ||
+      o.matching < 0 || o.matching > 1 ||
+      o.debug_schedule > 1 ||
       !(o.pivot_perturb_rel >= 0.0 && o.pivot_perturb_rel < 1.0))
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
@@ -780,6 +838,7 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
   AnalyzeOptions ao;
   ao.ordering = h->opt.ordering;
   ao.tau = h->opt.pivot_tau;
+  ao.matching = h->opt.matching;
   Analysis an;
   std::string msg;
   int st;
@@ -822,7 +881,11 @@ kkt_status kkt_reanalyze(kkt_handle h, const double* d_values, void* stream) {
   std::string msg;
   int st;
   try {
-    st = analyze(n, nnz, rp.data(), ci.data(), vals.data(), q.data(), ao, an, &msg);
+    // with matching: the stored matching and scaling, the pivoting pass redone
+    st = h->an.match.empty()
+             ? analyze(n, nnz, rp.data(), ci.data(), vals.data(), q.data(), ao, an, &msg)
+             : analyze_scaled(n, nnz, rp.data(), ci.data(), vals.data(), h->an.match, h->an.dr,
+                              h->an.dc, q.data(), ao, an, &msg);
   } catch (const std::bad_alloc&) {
     return fail(h, KKT_ERR_OUT_OF_MEMORY, "host allocation failed in analyze");
   }
@@ -872,6 +935,25 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     UP(h->lt_row, lr);
     std::vector<int32_t> pin(n), q(A.Q);
     for (int32_t i = 0; i < n; i++) pin[i] = A.Q[A.P[i]];
+    h->rowsc = h->colsc = h->ascale = h->avs = nullptr;
+    if (!A.match.empty()) {
+      // the factors are those of Ahat = Pm Dr A Dc: factor row i is A's row
+      // match[Q[P[i]]] scaled by dr, factor column k is A's column Q[k]
+      // scaled by dc
+      std::vector<double> rsv(n), csv(n);
+      for (int32_t i = 0; i < n; i++) {
+        pin[i] = A.match[pin[i]];
+        rsv[i] = A.dr[pin[i]];
+        csv[i] = A.dc[A.Q[i]];
+      }
+      UP(h->rowsc, rsv);
+      UP(h->colsc, csv);
+      UP(h->ascale, A.ascale);
+      if ((ks = dalloc(h, &h->avs, (size_t)nnz)) != KKT_OK) {
+        free_device(h);
+        return ks;
+      }
+    }
     UP(h->pin, pin);
     UP(h->qperm, q);
     // A pattern (int32 row pointers) and its column view
@@ -1601,6 +1683,18 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     free_device(h);
     return ks;
   }
+  h->dlu_tasks = h->dlu_ver = nullptr;
+  h->dlu_ntasks = 0;
+  if (h->tail_s > 0 && h->opt.dense_lu == 1) {
+    const int nt = h->tail_S / DLU_NB;
+    const std::vector<int> tasks = dense_lu_tasks(nt);
+    if ((ks = upload(h, &h->dlu_tasks, tasks)) != KKT_OK ||
+        (ks = dalloc(h, &h->dlu_ver, (size_t)nt * nt)) != KKT_OK) {
+      free_device(h);
+      return ks;
+    }
+    h->dlu_ntasks = (int)tasks.size();
+  }
   if (h->batch_count > 0) {
     std::vector<int32_t> ro(h->row_off.begin(), h->row_off.end());
     if ((ks = upload(h, &h->d_row_off, ro)) != KKT_OK ||
@@ -1617,6 +1711,8 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   HIP_CHECK(h, hipMemcpy(h->lu_val, A.lu_val0.data(), f * sizeof(double), hipMemcpyHostToDevice));
   HIP_CHECK(h, hipMemcpy(h->aval, values0, (size_t)nnz * sizeof(double), hipMemcpyHostToDevice));
   HIP_CHECK(h, hipHostMalloc((void**)&h->h_st, sizeof(DevStats), hipHostMallocDefault));
+  HIP_CHECK(h, hipHostMalloc((void**)&h->h_fs, sizeof(FgState), hipHostMallocDefault));
+  HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_fs, hipEventDisableTiming));
   HIP_CHECK(h, hipHostMalloc((void**)&h->h_colmax, sizeof(unsigned long long) * 2 * MAX_RHS_PASS,
                              hipHostMallocDefault));
   if ((ks = dalloc(h, &h->colmax, 2 * MAX_RHS_PASS)) != KKT_OK) {
@@ -1640,9 +1736,13 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     }
     h->mcap = MAX_RHS_PASS;
   }
+  HIP_CHECK(h, hipMemcpy(&h->st->spin_limit, &h->opt.debug_spin_limit, sizeof(int),
+                         hipMemcpyHostToDevice));
+  if (!set_debug_schedule(h->opt.debug_schedule))
+    return fail(h, KKT_ERR_DEVICE, "cannot set the debug schedule flag");
   launch_reset_stats(h->st, 1 | 2 | 8, nullptr);
   launch_copy_anorm(n, h->a_rowptr, h->a_col, h->aval, h->aval, h->st, nullptr, nullptr,
-                    h->rowabs);
+                    h->rowabs, nullptr, nullptr, nullptr, 1, h->ascale, h->avs);
   launch_pivot_stats(view(h), h->st, h->opt.tiny_pivot_rel, nullptr);
   if (h->ref_map) launch_build_refmap(view(h), h->ref_moff, h->ref_map, h->ref_flat, nullptr);
   // the dense block's copy of the pivoting pass's factors (the solves read it)
@@ -1666,6 +1766,8 @@ kkt_status kkt_analyze_batch(kkt_handle h, int32_t npat, const int32_t* n, const
                              const int32_t* inst_pattern) {
   if (!h) return KKT_ERR_INVALID_ARG;
   h->err.clear();
+  if (h->opt.matching != 0)
+    return fail(h, KKT_ERR_INVALID_ARG, "matching is supported for single-system analyses only");
   auto t0 = std::chrono::steady_clock::now();
   AnalyzeOptions ao;
   ao.ordering = h->opt.ordering == 2 ? 0 : h->opt.ordering;
@@ -1726,12 +1828,15 @@ kkt_status kkt_batch_eta(kkt_handle h, double* eta) {
 static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStream_t s) {
   const Analysis& A = h->an;
   LUView lu = view(h);
+  // values of the factored matrix in A's order: A's own, or the matched and
+  // scaled ones (written by the copy pass)
+  const double* fa = h->avs ? h->avs : h->aval;
   launch_reset_stats(h->st, 1, s);
   if (h->syncfree) {
     launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, h->ss, h->rowabs,
-                      h->a2lu, h->luA);
+                      h->a2lu, h->luA, nullptr, 1, h->ascale, h->avs);
     if (h->light) launch_fill_sentinel(h->lu_val, (long long)A.lu_col.size(), s);
-    launch_refactor_trivial(lu, h->ref_triv, h->ref_ntriv, h->aval, h->ready_ref, h->ss, s,
+    launch_refactor_trivial(lu, h->ref_triv, h->ref_ntriv, fa, h->ready_ref, h->ss, s,
                             h->luA, h->tail_c0, h->st, h->opt.pivot_perturb_rel);
     for (int b = 0; b < h->nbands; b++)
       if (h->band_flat[b]) {
@@ -1750,7 +1855,7 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
                                 h->opt.pivot_perturb_rel, s))
           return fail(h, KKT_ERR_DEVICE, "long-row refactorization not launchable");
       } else if (!launch_refactor_syncfree(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
-                                    h->band_nchunks[b], b, h->band_cap[b], h->aval, h->ready_ref,
+                                    h->band_nchunks[b], b, h->band_cap[b], fa, h->ready_ref,
                                     h->ss, &h->st->stall, h->light,
                                     h->opt.refactor_waves_per_block, h->tail_c0, h->ref_moff,
                                     h->ref_map, h->luA, h->ref_pbnd,
@@ -1759,16 +1864,23 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
         return fail(h, KKT_ERR_DEVICE, "dependency-driven refactorization not launchable");
     if (h->tail_s > 0) {
       launch_tail_scatter(lu, h->tail_c0, h->tail_s, h->tail_S, h->tail_T, s);
+      if (h->dlu_tasks) {
+        launch_dlu_reset(h->dlu_ver, h->tail_S / DLU_NB, h->ss, s);
+        if (!launch_dense_lu_tasks(h->tail_T, h->tail_S, h->tail_s, h->dlu_tasks, h->dlu_ntasks,
+                                   h->dlu_ver, h->ss, &h->st->stall, h->st,
+                                   h->opt.pivot_perturb_rel, s))
+          return fail(h, KKT_ERR_DEVICE, "dense-block task launch not launchable");
+      } else
       launch_dense_lu(h->tail_T, h->tail_S, h->tail_s, h->tail_dsc, h->st,
                       h->opt.pivot_perturb_rel, s);
       launch_tail_gather(lu, h->tail_c0, h->tail_T, h->tail_S, s);
     }
   } else {
     launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, nullptr,
-                      h->rowabs);
+                      h->rowabs, nullptr, nullptr, nullptr, 1, h->ascale, h->avs);
     for (size_t l = 0; l + 1 < A.lev_ptr.size(); l++)
       launch_refactor_rows(lu, h->lev_rows + A.lev_ptr[l], A.lev_ptr[l + 1] - A.lev_ptr[l],
-                           A.lev_maxlen[l], h->aval, h->st, h->opt.pivot_perturb_rel, s);
+                           A.lev_maxlen[l], fa, h->st, h->opt.pivot_perturb_rel, s);
   }
   launch_pivot_stats(lu, h->st, h->opt.tiny_pivot_rel, s);
   return KKT_OK;
@@ -1803,7 +1915,13 @@ kkt_status kkt_graph_capture(kkt_handle h, const double* d_values, const double*
   hipStream_t s = (hipStream_t)stream;
   HIP_CHECK(h, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
   kkt_status ks = refactor_launch(h, d_values, s);
-  if (ks == KKT_OK) solve_async(h, h->fb, 'N', 1, d_b, d_x, s);
+  if (ks == KKT_OK) {
+    const kkt_options& o = h->opt;
+    const int full = std::max(o.refine_budget > 0 ? std::min(o.refine_budget, o.fgmres_max_iters)
+                                                  : o.fgmres_max_iters,
+                              std::min(o.min_iters, o.fgmres_max_iters));
+    solve_async(h, h->fb, 'N', 1, d_b, d_x, full, s);
+  }
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);
   if (ks != KKT_OK) {
@@ -1840,10 +1958,11 @@ kkt_status kkt_update_matrix(kkt_handle h, const double* d_values, void* stream)
   // keep the pivot statistics of the current factors, recompute ||A||_inf
   launch_reset_stats(h->st, 4, s);
   launch_copy_anorm(h->an.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, nullptr,
-                    h->rowabs);
+                    h->rowabs, nullptr, nullptr, nullptr, 0);
   HIP_CHECK(h, hipGetLastError());
   h->anorm1_valid = false;
   h->factor_epoch++;
+  h->auto_full = true;  // the factors are now those of another matrix
   return KKT_OK;
 }
 
@@ -1870,7 +1989,8 @@ kkt_status kkt_solve(kkt_handle h, char op, int32_t nrhs, const double* d_b, dou
       h->last_eta = h->last_eta0 = 0.0;
       return KKT_OK;
     }
-    solve_async(h, h->fb, op, nrhs, d_b, d_x, s);
+    solve_async(h, h->fb, op, nrhs, d_b, d_x, fg_budget(h), s);
+    fg_observe(h, s);
     HIP_CHECK(h, hipGetLastError());
     h->fg_pending = true;
     if (h->opt.auto_reanalyze == 1 && !h->in_retry && h->batch_count == 0 &&
@@ -2010,9 +2130,10 @@ kkt_status kkt_solve_noalloc(kkt_handle h, char op, int32_t nrhs, const double* 
     h->last_eta = h->last_eta0 = 0.0;
     return KKT_OK;
   }
-  solve_async(h, fb, op, nrhs, d_b, d_x, s);
+  solve_async(h, fb, op, nrhs, d_b, d_x, fg_budget(h), s);
   // the outcome into the handle's own state, where kkt_sync_report reads it
   HIP_CHECK(h, hipMemcpyAsync(h->fs, fb.fs, sizeof(FgState), hipMemcpyDeviceToDevice, s));
+  fg_observe(h, s);
   HIP_CHECK(h, hipGetLastError());
   h->fg_pending = true;
   return KKT_OK;
@@ -2046,7 +2167,7 @@ kkt_status kkt_sync_report(kkt_handle h, kkt_report* out) {
   out->min_pivot = bits_to_double(d.min_piv);
   out->max_pivot = bits_to_double(d.max_piv);
   out->anorm_inf = bits_to_double(d.anorm);
-  out->growth = eta_of(bits_to_double(d.umax), out->anorm_inf, 1.0);
+  out->growth = eta_of(bits_to_double(d.umax), bits_to_double(d.anorm_f), 1.0);
   h->warnings = 0;
   return KKT_OK;
 }
@@ -2066,6 +2187,17 @@ kkt_status kkt_get_info(kkt_handle h, kkt_info* out) {
   out->analyze_seconds = h->analyze_seconds;
   out->dense_tail = h->tail_s;
   out->factor_epoch = h->factor_epoch;
+  return KKT_OK;
+}
+
+kkt_status kkt_get_scaling(kkt_handle h, int32_t* match, double* dr, double* dc) {
+  if (!h) return KKT_ERR_INVALID_ARG;
+  if (!h->analyzed) return fail(h, KKT_ERR_STATE, "no analysis");
+  const Analysis& A = h->an;
+  if (A.match.empty()) return fail(h, KKT_ERR_STATE, "the analysis did not match and scale");
+  if (match) std::memcpy(match, A.match.data(), A.match.size() * sizeof(int32_t));
+  if (dr) std::memcpy(dr, A.dr.data(), A.dr.size() * sizeof(double));
+  if (dc) std::memcpy(dc, A.dc.data(), A.dc.size() * sizeof(double));
   return KKT_OK;
 }
 
@@ -2115,6 +2247,7 @@ kkt_status kkt_analysis_create(const kkt_options* opt, int32_t n, int64_t nnz,
   AnalyzeOptions ao;
   ao.ordering = o.ordering;
   ao.tau = o.pivot_tau;
+  ao.matching = o.matching;
   kkt_host_analysis* a = new (std::nothrow) kkt_host_analysis();
   if (!a) return KKT_ERR_OUT_OF_MEMORY;
   std::string m;
@@ -2148,6 +2281,16 @@ kkt_status kkt_analysis_info(kkt_analysis a, kkt_info* out) {
   out->levels = (int32_t)A.lev_ptr.size() - 1;
   out->levels_u = (int32_t)A.ulev_ptr.size() - 1;
   out->analyze_status = A.warn_singular ? KKT_WARN_NUMERICALLY_SINGULAR : KKT_OK;
+  return KKT_OK;
+}
+
+kkt_status kkt_analysis_scaling(kkt_analysis a, int32_t* match, double* dr, double* dc) {
+  if (!a) return KKT_ERR_INVALID_ARG;
+  const Analysis& A = a->an;
+  if (A.match.empty()) return KKT_ERR_STATE;
+  if (match) std::memcpy(match, A.match.data(), A.match.size() * sizeof(int32_t));
+  if (dr) std::memcpy(dr, A.dr.data(), A.dr.size() * sizeof(double));
+  if (dc) std::memcpy(dc, A.dc.data(), A.dc.size() * sizeof(double));
   return KKT_OK;
 }
 

@@ -197,3 +197,46 @@ def test_create_rejects_bad_options(field, value):
     h = C.c_void_p()
     assert binding.lib().kkt_create(C.byref(o), C.byref(h)) == binding.ERR_INVALID_ARG
     assert not h.value
+
+
+# ---------------------------------------------------------------------------
+# Maximum-product matching and scaling before the ordering (Section 5.2.1)
+# ---------------------------------------------------------------------------
+def _matched_case(n, rp, ci, v, tau):
+    ha = binding.HostAnalysis(n, rp, ci, v, pivot_tau=tau, matching=1)
+    m1, dr1, dc1 = ha.scaling()
+    m0, dr0, dc0 = oracle.match_scale(n, rp, ci, v)
+    assert np.array_equal(m0, m1), "matching differs"
+    assert np.array_equal(dr0, dr1) and np.array_equal(dc0, dc1), "scaling differs"
+    hrp, hci, hv, _ = oracle.matched_scaled(n, rp, ci, v, m0, dr0, dc0)
+    lu = oracle.OracleLU(n, hrp, hci, hv, tau=tau)
+    P0, Q0, rp0, ci0, v0 = oracle_combined_csr(lu)
+    P1, Q1 = ha.perm()
+    rp1, ci1, v1 = ha.lu()
+    assert np.array_equal(Q0, Q1) and np.array_equal(P0, P1), "permutations differ"
+    assert np.array_equal(rp0, rp1) and np.array_equal(ci0, ci1), "factor pattern differs"
+    assert np.array_equal(v0.view(np.int64), v1.view(np.int64)), "pivoting-pass values differ"
+
+
+@pytest.mark.parametrize("tau", [1.0, 1e-10])
+@pytest.mark.parametrize("seed", range(6))
+def test_matching_random_sparse_bitwise(tau, seed):
+    n = 30 + 7 * seed
+    rp, ci, v = kktgen.random_sparse(n, 0.08, seed=500 + seed)
+    v = v * 10.0 ** np.random.default_rng(seed).uniform(-4, 4, v.size)
+    _matched_case(n, rp, ci, v, tau)
+
+
+@pytest.mark.parametrize("B,seed", [(10, 3), (100, 101)])
+def test_matching_kkt_bitwise(B, seed):
+    pat, seq = kktgen.make_sequence(B, seed, 1)
+    _matched_case(pat.n, pat.rowptr, pat.colind, seq[0][0], 1e-10)
+
+
+def test_matching_structurally_singular_is_an_error():
+    rp = np.array([0, 2, 5, 6], np.int64)
+    ci = np.array([0, 1, 0, 1, 2, 1], np.int32)
+    v = np.array([1.0, 2.0, 0.5, 1.0, 3.0, 0.0])
+    with pytest.raises(binding.KKTError) as e:
+        binding.HostAnalysis(3, rp, ci, v, matching=1)
+    assert e.value.status == binding.ERR_STRUCTURALLY_SINGULAR

@@ -119,12 +119,14 @@ def test_refactor_kernel_variants_bitwise(B, seed, variant):
     (2000, 104, 700),
     (10000, 102, 2048),  # the largest dense block: 64 panels, 64 block solves
 ])
-def test_dense_tail_bitwise(B, seed, tail):
+@pytest.mark.parametrize("dense_lu", [0, 1], ids=["panel-launches", "task-launch"])
+def test_dense_tail_bitwise(B, seed, tail, dense_lu):
     # the trailing block finished as a dense LU gives the oracle's factors bit
-    # for bit (same update order), before and after a change of values
-    print(f"case B={B} seed={seed} dense_tail={tail}", flush=True)
+    # for bit (same update order), before and after a change of values, with
+    # a panel and an update launch per 32 pivots or one task launch
+    print(f"case B={B} seed={seed} dense_tail={tail} dense_lu={dense_lu}", flush=True)
     pat, seq = kktgen.make_sequence(B, seed, 2)
-    s = binding.KKTSolver(schedule=2, sync_mode=2, dense_tail=tail)
+    s = binding.KKTSolver(schedule=2, sync_mode=2, dense_tail=tail, dense_lu=dense_lu)
     s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
     got = s.info().dense_tail
     print(f"  dense tail {got}", flush=True)
@@ -775,6 +777,40 @@ def test_multi_rhs_device_refinement_stale(op):
     assert rep.iters > 1 and max(etas) <= 1e-12 and rep.eta <= 1e-12
 
 
+def test_adaptive_refinement_budget():
+    # refine_budget = -1: exact factors need no iteration, so later solves
+    # launch two; kkt_update_matrix (stale factors) brings the full budget
+    # back, and a later solve on the same stale factors launches enough for
+    # the iterations its predecessor needed
+    pat = kktgen.make_kkt(500, 77)
+    rng = np.random.default_rng(3)
+    sigma = np.clip(kktgen.draw_sigma(rng, pat.n_p), 1e-2, 1e2)
+    v_old = pat.values(sigma)
+    sym = pat.scipy(v_old * (1.0 + 0.05 * rng.standard_normal(v_old.size)))
+    sym = (sym + sym.T) * 0.5
+    sym.sort_indices()
+    v_new = sym.data
+    b = rng.standard_normal(pat.n)
+    s = binding.KKTSolver(refine_budget=-1)
+    s.analyze(pat.n, pat.rowptr, pat.colind, v_old)
+    for _ in range(3):
+        s.refactor(dev(v_old))
+        x = s.solve(dev(b)).cpu().numpy()
+        rep = s.report()
+        assert rep.iters == 0 and eta(pat.scipy(v_old), x, b) <= 1e-12
+    s.update_matrix(dev(v_new))
+    its = []
+    for _ in range(2):
+        x = s.solve(dev(b)).cpu().numpy()
+        torch.cuda.synchronize()
+        rep = s.report()
+        its.append(rep.iters)
+        assert not rep.warnings & (1 << binding.WARN_NOT_CONVERGED)
+        assert eta(pat.scipy(v_new), x, b) <= 1e-12
+    print(f"  stale solves: iters {its}", flush=True)
+    assert its[0] > 2 and its[1] == its[0]
+
+
 def test_solve_does_not_wait_for_the_device():
     # a long spin kernel ahead on the stream: refactor and solve return while
     # it still runs (no host synchronisation), and the result is right after
@@ -795,6 +831,83 @@ def test_solve_does_not_wait_for_the_device():
     torch.cuda.synchronize()
     assert busy, "kkt_solve waited for the device"
     assert eta(pat.scipy(vals), x.cpu().numpy(), b) <= 1e-12
+
+
+@pytest.mark.parametrize("B,seed", [(500, 7), (2000, 104)])
+def test_adversarial_schedule_bitwise(B, seed):
+    # another workgroup (and XCD) for every chunk of the persistent kernels
+    # and pseudo-random pauses after each fetch: the factors are still the
+    # oracle's bit for bit and the solve meets the target
+    pat, seq = kktgen.make_sequence(B, seed, 2)
+    vals, b = seq[1]
+    ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, seq[0][0], tau=1e-10)
+    ora.refactor(vals)
+    s = binding.KKTSolver(debug_schedule=1)
+    s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
+    for _ in range(2):
+        s.refactor(dev(vals))
+        x = s.solve(dev(b)).cpu().numpy()
+        assert_factors_equal(s.lu()[2], oracle_csr_values(ora))
+        assert eta(pat.scipy(vals), x, b) <= 1e-12
+    s.close()
+    # the flag is process-wide: the next analysis restores the plain schedule
+    r = binding.KKTSolver()
+    r.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
+    r.close()
+
+
+def test_tiny_spin_limit_drains_and_reports():
+    # every dependency wait gives up on its second poll: the kernels run to
+    # their end (no hang), the stall flag is raised and the report says so
+    pat, seq = kktgen.make_sequence(2000, 104, 2)
+    vals, b = seq[1]
+    s = binding.KKTSolver(debug_spin_limit=1)
+    s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
+    s.refactor(dev(vals))
+    s.solve(dev(b))
+    torch.cuda.synchronize()
+    with pytest.raises(binding.KKTError) as err:
+        s.report()
+    assert err.value.status == binding.ERR_DEVICE
+    s.close()
+
+
+@pytest.mark.parametrize("layout", [dict(), dict(schedule=1), dict(schedule=2, sync_mode=1),
+                                    dict(solve_chain=-1), dict(dense_tail=300)],
+                         ids=["default", "levels", "fences", "level-chunks", "dense-block"])
+def test_matching_and_scaling_bitwise(layout):
+    # matched and scaled analysis (Section 5.2.1): the product's matching and
+    # power-of-two scaling equal the oracle's, every refactorization of the
+    # sequence gives the oracle's factors of Ahat = Pm Dr A Dc bit for bit,
+    # and the solves of A (both ops, several right-hand sides) meet the target
+    pat, seq = kktgen.make_sequence(100, 101, 3)
+    s = binding.KKTSolver(matching=1, **layout)
+    s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
+    m, dr, dc = s.scaling()
+    m0, dr0, dc0 = oracle.match_scale(pat.n, pat.rowptr, pat.colind, seq[0][0])
+    assert np.array_equal(m, m0) and np.array_equal(dr, dr0) and np.array_equal(dc, dc0)
+    hrp, hci, hv, src = oracle.matched_scaled(pat.n, pat.rowptr, pat.colind, seq[0][0], m, dr, dc)
+    ora = oracle.OracleLU(pat.n, hrp, hci, hv, tau=1e-10)
+    assert not np.array_equal(m, np.arange(pat.n)), "the matching should permute rows here"
+    for vals, b in seq[1:]:
+        s.refactor(dev(vals))
+        ora.refactor(dr[m][np.repeat(np.arange(pat.n), np.diff(hrp))] * vals[src] * dc[hci])
+        assert_factors_equal(s.lu()[2], oracle_csr_values(ora))
+        A = pat.scipy(vals)
+        x = s.solve(dev(b)).cpu().numpy()
+        assert eta(A, x, b) <= 1e-12
+        lam = s.solve(dev(b), op="T").cpu().numpy()
+        assert eta(A.T.tocsr(), lam, b) <= 1e-12
+    B3 = np.random.default_rng(5).standard_normal((3, pat.n))
+    X = s.solve(dev(B3.reshape(-1))).cpu().numpy().reshape(3, pat.n)
+    for r in range(3):
+        assert eta(A, X[r], B3[r]) <= 1e-12
+    # a re-analysis keeps the matching and scaling
+    s.reanalyze(dev(seq[2][0]))
+    m2, dr2, dc2 = s.scaling()
+    assert np.array_equal(m2, m) and np.array_equal(dr2, dr)
+    x = s.solve(dev(seq[2][1])).cpu().numpy()
+    assert eta(pat.scipy(seq[2][0]), x, seq[2][1]) <= 1e-12
 
 
 def test_autotuner_picks_a_working_schedule(tmp_path):
