@@ -164,7 +164,10 @@ typedef struct {
                                preprocessing); the factors are those of Ahat = Pm Dr A Dc, the
                                solves and residuals stay those of A.  Fixed at analysis (a
                                re-analysis keeps it); single systems only.  0 = off (default) */
-  int32_t reserved5;
+  int32_t refactor_micro_rows; /* short-row band of the dependency-driven refactorization: 0 =
+                                  rows of at most 8 entries, 4 pivots and 4 multiply-adds go
+                                  one per lane, up to 64 rows of one level to a wave (default);
+                                  -1 = one wave per row for every row of the band */
 } kkt_options;
 
 typedef struct {
@@ -194,6 +197,11 @@ typedef struct {
                              matrix (analyze, refactor, reanalyze, update_matrix, graph
                              launch); lets a caller tell whether saved solutions still
                              belong to the current factors */
+  int32_t levels_sparse;  /* dependency levels of the rows outside the dense block (the
+                             refactorization's row-to-row waits) */
+  int32_t solve_block_levels[2]; /* dependency levels of the chain-blocked L and U solves
+                             over the rows outside the dense block: a run of chained rows
+                             solved by one wave counts once; 0 where that path is off */
 } kkt_info;
 
 /* Fill *opt with the defaults listed above. */
@@ -344,7 +352,8 @@ kkt_status kkt_analysis_create(const kkt_options *opt, int32_t n, int64_t nnz,
                                const int64_t *rowptr, const int32_t *colind,
                                const double *values0, const int32_t *user_q, kkt_analysis *out,
                                char *msg, int32_t msg_len);
-/* Sizes and depths (device_bytes and analyze_seconds are 0). */
+/* Sizes and depths (device_bytes, analyze_seconds and solve_block_levels are 0; no dense
+ * block is chosen, so levels_sparse equals levels). */
 kkt_status kkt_analysis_info(kkt_analysis a, kkt_info *out);
 /* As kkt_get_perm / kkt_get_lu, from the host object (values: the pivoting
  * pass's factors of values0). */

@@ -63,7 +63,7 @@ class Options(C.Structure):
                 ("refactor_long_rows", C.c_int32), ("refine_sync", C.c_int32),
                 ("refine_budget", C.c_int32), ("dense_lu", C.c_int32),
                 ("debug_spin_limit", C.c_int32), ("debug_schedule", C.c_int32),
-                ("matching", C.c_int32), ("reserved5", C.c_int32)]
+                ("matching", C.c_int32), ("refactor_micro_rows", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -76,7 +76,8 @@ class Info(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("nnz_l", C.c_int64), ("nnz_u", C.c_int64),
                 ("levels", C.c_int32), ("levels_u", C.c_int32), ("analyze_status", C.c_int32),
                 ("device_bytes", C.c_int64), ("analyze_seconds", C.c_double),
-                ("dense_tail", C.c_int32), ("factor_epoch", C.c_int64)]
+                ("dense_tail", C.c_int32), ("factor_epoch", C.c_int64),
+                ("levels_sparse", C.c_int32), ("solve_block_levels", C.c_int32 * 2)]
 
 
 _lib = None

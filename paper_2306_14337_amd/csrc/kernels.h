@@ -31,6 +31,8 @@ struct DevStats {
 // launch per group and step).
 constexpr int FG_MAX_COLS = 8;
 constexpr int FG_BLOCKS = 512;  // workgroups per column of a refinement pass
+constexpr int FG_RESID_BLOCKS = 4096;  // workgroups per column of the residual pass
+constexpr int SEG_SLICES = 16;  // partial per-instance maxima of a batch (launch_seg_stats)
 struct FgCol {
   int stop;       // this column's remaining iterations do nothing
   int it;         // iterations done
@@ -258,12 +260,16 @@ bool launch_refactor_wg(const LUView& lu, const int* order, const int* cstart, i
 // row's L entries q = (offset of pivot q's first multiply-add in the row's
 // list, U row start of pivot q minus that offset), at the diagonal q =
 // (length of the list, 0); map holds packed entries (launch_build_refmap with
-// flat).  Device-coherent value-as-flag publication only.
+// flat).  Device-coherent value-as-flag publication only.  cmicro (may be
+// null): per chunk, non-zero for a chunk of micro rows (one level, at most 64
+// rows of at most MICRO_LEN entries, MICRO_PIV pivots and MICRO_LIST
+// multiply-adds), taken one row per lane.
+constexpr int MICRO_ROW_LEN = 8, MICRO_ROW_PIV = 4, MICRO_ROW_LIST = 4;
 bool launch_refactor_flat(const LUView& lu, const int* order, const int* cstart, int nchunks,
                           int band, int cap, SyncState* ss, int* stall, const int* moff,
                           const unsigned short* map, const double* luA, const int2* fl,
-                          int max_waves_per_cu, DevStats* st, double perturb_rel,
-                          hipStream_t s);
+                          const unsigned char* cmicro, int max_waves_per_cu, DevStats* st,
+                          double perturb_rel, hipStream_t s);
 
 // Dense trailing block: rows and columns c0 .. c0+s-1 of the factors in pivot
 // order, held row-major in T (S x S, S = s rounded up to DLU_NB; the padding
@@ -400,8 +406,10 @@ void launch_copy_anorm(int n, const int* arow, const int* acol, const double* sr
 // ||A||_1 through the column view (and every column's absolute sum)
 void launch_anorm1(int n, const int* cptr, const int* cpos, const double* aval, DevStats* st,
                    hipStream_t s, double* colabs = nullptr);
-// per-instance maxima of a block-diagonal batch: out[3t..3t+2] = max matabs,
-// max |r|, max |x| over rows [row_off[t], row_off[t+1])
+// per-instance maxima of a block-diagonal batch, SEG_SLICES partial results
+// per instance: out[3 (t SEG_SLICES + s) + 0..2] = max matabs, max |r|, max |x|
+// over slice s of rows [row_off[t], row_off[t+1]) (out holds
+// 3 SEG_SLICES count doubles)
 void launch_seg_stats(int count, const int* row_off, const double* matabs, const double* r,
                       const double* x, double* out, hipStream_t s);
 void launch_reset_stats(DevStats* st, int what, hipStream_t s);

@@ -1958,9 +1958,10 @@ __global__ __launch_bounds__(256) void k_pivot_stats(int n, const int* __restric
   }
 }
 
-// Per-instance maxima of a block-diagonal batch: block t reduces rows
-// [row_off[t], row_off[t+1]) to out[3t] = max matabs (the instance's matrix
-// norm), out[3t+1] = max |r|, out[3t+2] = max |x|.
+// Per-instance maxima of a block-diagonal batch, SEG_SLICES partial results
+// per instance: block (s, t) reduces slice s of rows [row_off[t],
+// row_off[t+1]) to out[3 (t SEG_SLICES + s)] = max matabs (the instance's
+// matrix norm), + 1 = max |r|, + 2 = max |x|.
 __global__ __launch_bounds__(256) void k_seg_stats(const int* __restrict__ gate,
                                                    const int* __restrict__ row_off,
                                                    const double* __restrict__ matabs,
@@ -1969,8 +1970,10 @@ __global__ __launch_bounds__(256) void k_seg_stats(const int* __restrict__ gate,
                                                    double* __restrict__ out) {
   KKT_GATE(gate);
   __shared__ double red[3][256 / WAVE];
-  const int t = blockIdx.x;
-  const int a = row_off[t], b = row_off[t + 1];
+  const int t = blockIdx.y, sl = blockIdx.x;
+  const int a0 = row_off[t], len = row_off[t + 1] - a0;
+  const int a = a0 + (int)((long long)len * sl / SEG_SLICES);
+  const int b = a0 + (int)((long long)len * (sl + 1) / SEG_SLICES);
   double m0 = 0.0, m1 = 0.0, m2 = 0.0;
   for (int i = a + threadIdx.x; i < b; i += blockDim.x) {
     m0 = nanmax(m0, matabs[i]);
@@ -1990,7 +1993,7 @@ __global__ __launch_bounds__(256) void k_seg_stats(const int* __restrict__ gate,
   if (threadIdx.x < 3) {
     double m = 0.0;
     for (int q = 0; q < 256 / WAVE; q++) m = nanmax(m, red[threadIdx.x][q]);
-    out[3 * t + threadIdx.x] = m;
+    out[3 * ((size_t)t * SEG_SLICES + sl) + threadIdx.x] = m;
   }
 }
 
@@ -2554,6 +2557,110 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 inline int rows_grid(int n) { return std::max(1, std::min(cdiv(n, 32), 1024)); }
 
 
+// Micro rows of a short-row band: at most MICRO_LEN entries, MICRO_PIV
+// pivots and MICRO_LIST multiply-adds.  One lane takes the whole row (a chunk
+// of such rows is one level of the dependency graph, so its rows do not wait
+// for each other): the row's values sit in the wave's LDS area, entry k of
+// lane l at sa[k * WAVE + l]; the pivot diagonals and every U entry of the
+// list are requested in one round, entries still reading as the sentinel are
+// polled again, then the arithmetic runs pivot after pivot in ascending order
+// with the same quotient and fma(-l, u, a) as the wave-per-row code.  List
+// entry e belongs to the last pivot t whose list offset fl.x is at most e, so
+// the U addresses do not wait for the map.
+constexpr int MICRO_LEN = MICRO_ROW_LEN, MICRO_PIV = MICRO_ROW_PIV, MICRO_LIST = MICRO_ROW_LIST;
+
+// doubles of LDS per wave of k_refactor_flat (cap even)
+__host__ __device__ constexpr int flat_area(int cap) {
+  return 2 * cap > MICRO_LEN * WAVE ? 2 * cap : MICRO_LEN * WAVE;
+}
+
+__device__ __forceinline__ void refactor_micro_row(int i, int lane, double* sa,
+                                                   const int* __restrict__ rowptr,
+                                                   const int* __restrict__ diag, double* val,
+                                                   int* stall, const int* __restrict__ moff,
+                                                   const unsigned short* __restrict__ map,
+                                                   const double* __restrict__ luA,
+                                                   const int2* __restrict__ fl, DevStats* st,
+                                                   double thr) {
+  const int rs = rowptr[i], len = rowptr[i + 1] - rs, dl = diag[i] - rs;
+  const int nl = fl[rs + dl].x;  // list length (the diagonal's entry)
+  const int mb = moff[rs];
+  for (int k = 0; k < len; k++) sa[k * WAVE + lane] = luA[rs + k];
+  double d[MICRO_PIV], u[MICRO_LIST];
+  unsigned int mm[MICRO_LIST];  // packed map entries: pivot << 8 | target position
+  {
+    // fx[t]: list offset of pivot t (MICRO_LIST past the row's pivots), fy[t]:
+    // its U row start minus that offset
+    int fx[MICRO_PIV], fy[MICRO_PIV];
+#pragma unroll
+    for (int t = 0; t < MICRO_PIV; t++) {
+      fx[t] = MICRO_LIST;
+      fy[t] = 0;
+      d[t] = 1.0;
+      if (t < dl) {
+        const int2 f = fl[rs + t];
+        fx[t] = f.x;
+        fy[t] = f.y;
+        d[t] = ld_coh(val + (f.x + f.y - 1));
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < MICRO_LIST; e++) {
+      mm[e] = 0;
+      u[e] = 0.0;
+      if (e < nl) {
+        int y = fy[0];
+#pragma unroll
+        for (int q = 1; q < MICRO_PIV; q++)
+          if (fx[q] <= e) y = fy[q];
+        mm[e] = map[mb + e];
+        u[e] = ld_coh(val + (e + y));
+      }
+    }
+  }
+  // pivot rows not finished when first read: poll the missing values (their
+  // addresses are recomputed from fl)
+  int spins = 0;
+  for (;;) {
+    bool miss = false;
+#pragma unroll
+    for (int t = 0; t < MICRO_PIV; t++) miss = miss || (t < dl && is_sentinel(d[t]));
+#pragma unroll
+    for (int e = 0; e < MICRO_LIST; e++) miss = miss || (e < nl && is_sentinel(u[e]));
+    if (!miss || !keep_waiting(&spins, stall)) break;
+#pragma unroll
+    for (int t = 0; t < MICRO_PIV; t++)
+      if (t < dl && is_sentinel(d[t])) {
+        const int2 f = fl[rs + t];
+        d[t] = ld_coh(val + (f.x + f.y - 1));
+      }
+#pragma unroll
+    for (int e = 0; e < MICRO_LIST; e++)
+      if (e < nl && is_sentinel(u[e])) u[e] = ld_coh(val + (e + fl[rs + (int)(mm[e] >> 8)].y));
+  }
+#pragma unroll
+  for (int t = 0; t < MICRO_PIV; t++) {
+    if (t < dl) {
+      const double l = sa[t * WAVE + lane] / d[t];
+#pragma unroll
+      for (int e = 0; e < MICRO_LIST; e++)
+        if (e < nl && (int)(mm[e] >> 8) == t) {
+          double* w = sa + (int)(mm[e] & 255u) * WAVE + lane;
+          *w = __builtin_fma(-l, u[e], *w);
+        }
+      sa[t * WAVE + lane] = l;
+    }
+  }
+  if (thr > 0.0) {
+    double* w = sa + dl * WAVE + lane;
+    if (fabs(*w) < thr) {
+      *w = perturb_pivot(*w, thr);
+      st->perturbed = 1;
+    }
+  }
+  for (int k = 0; k < len; k++) st_coh(val + rs + k, sa[k * WAVE + lane]);
+}
+
 // Rows of a short-row band (at most 256 entries each; no row of the dense
 // block).  One wave per row, as
 // k_refactor_syncfree, but the row's multiply-adds form one list, pivot after
@@ -2568,22 +2675,34 @@ inline int rows_grid(int n) { return std::max(1, std::min(cdiv(n, 32), 1024)); }
 // Publication: device-coherent stores of the values into a factor array that
 // holds the sentinel; a pivot row is finished once its diagonal is, and each
 // of its other entries is re-polled while it still reads as the sentinel.
+// Chunks flagged in cmicro hold micro rows, one per lane (refactor_micro_row).
 template <int WPB>
 __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
     const int* __restrict__ order, const int* __restrict__ cstart, int nchunks,
     unsigned int* tickets, int nstreams, const int* __restrict__ rowptr,
     const int* __restrict__ diag, double* val, int* stall, int cap,
     const int* __restrict__ moff, const unsigned short* __restrict__ map,
-    const double* __restrict__ luA, const int2* __restrict__ fl, DevStats* st, double prel) {
+    const double* __restrict__ luA, const int2* __restrict__ fl,
+    const unsigned char* __restrict__ cmicro, DevStats* st, double prel) {
   extern __shared__ double smem_d[];
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-  // LDS per wave: values (cap doubles), list bounds per L entry (cap int2)
-  double* sv = smem_d + (size_t)wave * cap;
-  int2* sf = reinterpret_cast<int2*>(smem_d + (size_t)WPB * cap) + (size_t)wave * cap;
+  // LDS per wave, one area of flat_area(cap) doubles: values (cap doubles),
+  // list bounds per L entry (cap int2); or, for a chunk of micro rows, their
+  // values (MICRO_LEN x WAVE doubles)
+  double* sv = smem_d + (size_t)wave * flat_area(cap);
+  int2* sf = reinterpret_cast<int2*>(sv + cap);
   const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm_f) : 0.0;
   for (;;) {
     const int tk = next_chunk(tickets, nstreams, lane);
     if (tk >= nchunks) break;
+    if (cmicro != nullptr && bcast0(cmicro[tk]) != 0u) {
+      wave_sync();  // the last row of a previous chunk is done with the area
+      const int r = cstart[tk] + lane;
+      if (r < cstart[tk + 1])
+        refactor_micro_row(order[r], lane, sv, rowptr, diag, val, stall, moff, map, luA, fl, st,
+                           thr);
+      continue;
+    }
     const int r_end = cstart[tk + 1];
     for (int r = cstart[tk]; r < r_end; r++) {
       const int i = order[r];
@@ -3059,8 +3178,12 @@ __global__ __launch_bounds__(FG_T) void k_fg_check_batch(int count, const double
   if (!first && ld_flag(&fs->col[0].stop)) return;
   __shared__ double red[FG_T / WAVE];
   double e = 0.0;
-  for (int t = threadIdx.x; t < count; t += FG_T)
-    e = nanmax(e, eta_dev(inst[3 * t + 1], inst[3 * t], inst[3 * t + 2]));
+  for (int t = threadIdx.x; t < count; t += FG_T) {
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int sl = 0; sl < SEG_SLICES; sl++)
+      for (int k = 0; k < 3; k++) m[k] = nanmax(m[k], inst[3 * ((size_t)t * SEG_SLICES + sl) + k]);
+    e = nanmax(e, eta_dev(m[1], m[0], m[2]));
+  }
   e = block_nanmax(e, red);
   if (threadIdx.x == 0) fg_decide(fs, 0, 1, e, it_now, first, p, ld_flag(&st->stall));
 }
@@ -3330,8 +3453,11 @@ namespace {
 // refinement passes: elementwise grids (four elements per thread at least)
 // and row grids (eight lanes per row, four row groups per round)
 int fg_grid(int n) { return std::max(1, std::min(FG_BLOCKS, cdiv(n, FG_T * 4))); }
+// (the residual pass keeps two partial maxima per workgroup, so the partial
+// buffer of FG_BLOCKS x 32 per column holds FG_RESID_BLOCKS of them)
 int fg_rows_grid(int n) {
-  return std::max(1, std::min(FG_BLOCKS, cdiv(n, (FG_T / WAVE) * (WAVE / RG) * 4)));
+  static_assert(2 * FG_RESID_BLOCKS <= 32 * FG_BLOCKS, "residual partials exceed their buffer");
+  return std::max(1, std::min(FG_RESID_BLOCKS, cdiv(n, (FG_T / WAVE) * (WAVE / RG) * 4)));
 }
 }  // namespace
 
@@ -3447,7 +3573,8 @@ void launch_copy_anorm(int n, const int* arow, const int*, const double* src, do
 
 void launch_seg_stats(int count, const int* row_off, const double* matabs, const double* r,
                       const double* x, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_seg_stats, dim3(count), dim3(256), 0, s, t_gate, row_off, matabs, r, x, out);
+  hipLaunchKernelGGL(k_seg_stats, dim3(SEG_SLICES, count), dim3(256), 0, s, t_gate, row_off, matabs,
+                     r, x, out);
 }
 
 void launch_fill_sentinel(double* p, long long count, hipStream_t s) {
@@ -3505,13 +3632,13 @@ bool launch_refactor_wg(const LUView& lu, const int* order, const int* cstart, i
 bool launch_refactor_flat(const LUView& lu, const int* order, const int* cstart, int nchunks,
                           int band, int cap, SyncState* ss, int* stall, const int* moff,
                           const unsigned short* map, const double* luA, const int2* fl,
-                          int max_waves_per_cu, DevStats* st, double perturb_rel,
-                          hipStream_t s) {
+                          const unsigned char* cmicro, int max_waves_per_cu, DevStats* st,
+                          double perturb_rel, hipStream_t s) {
   if (nchunks <= 0) return true;
   if (band < 0 || band >= REF_MAX_BANDS || cap > 256 || !moff || !map || !luA || !fl) return false;
   cap = (cap + 1) & ~1;
   constexpr int WPB = 4;
-  const size_t shm = (size_t)cap * (sizeof(double) + sizeof(int2)) * WPB;
+  const size_t shm = (size_t)flat_area(cap) * sizeof(double) * WPB;
   static int ncu = 0;
   if (ncu == 0) {
     int d = 0;
@@ -3528,7 +3655,7 @@ bool launch_refactor_flat(const LUView& lu, const int* order, const int* cstart,
   const int grid = std::max(1, std::min(nb * ncu, cdiv(nchunks, WPB)));
   hipLaunchKernelGGL(k_refactor_flat<WPB>, dim3(grid), dim3(WPB * WAVE), shm, s, order, cstart,
                      nchunks, ss->band_stream[band], std::min(TICKET_STREAMS, grid), lu.rowptr,
-                     lu.diag, lu.val, stall, cap, moff, map, luA, fl, st, perturb_rel);
+                     lu.diag, lu.val, stall, cap, moff, map, luA, fl, cmicro, st, perturb_rel);
   return true;
 }
 

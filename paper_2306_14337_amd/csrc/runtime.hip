@@ -6,6 +6,7 @@
 // and 5.1.2).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -100,6 +101,7 @@ struct kkt_ctx {
   // + band_nchunks[b]] of ref_order (each band's chunk list ends with its end
   // offset), longest row band_cap[b]
   int *ref_order = nullptr, *ref_cstart = nullptr;
+  unsigned char* ref_cmicro = nullptr;  // per chunk: a chunk of micro rows (one per lane)
   int* ref_triv = nullptr;  // rows without pivots (k_refactor_trivial)
   // A's values in factor order (fill positions zero) and the A -> factor map;
   // per L entry (i, k): (diag[k], rowptr[k + 1])
@@ -488,11 +490,17 @@ kkt_status read_batch_eta(kkt_handle h, char op, double* eta_max) {
   HIP_CHECK(h, hipDeviceSynchronize());
   HIP_CHECK(h, hipMemcpy(h->h_inst.data(), h->inst_out, h->h_inst.size() * sizeof(double),
                          hipMemcpyDeviceToHost));
+  // maxima that keep a NaN once seen (a broken instance stays visible)
+  auto nan_max = [](double a, double b) { return (a != a || b != b) ? a + b : (a > b ? a : b); };
   double mx = 0.0;
   for (int t = 0; t < h->batch_count; t++) {
-    const double e = eta_of(h->h_inst[3 * t + 1], h->h_inst[3 * t], h->h_inst[3 * t + 2]);
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int sl = 0; sl < SEG_SLICES; sl++)
+      for (int k = 0; k < 3; k++)
+        m[k] = nan_max(m[k], h->h_inst[3 * ((size_t)t * SEG_SLICES + sl) + k]);
+    const double e = eta_of(m[1], m[0], m[2]);
     h->inst_eta[t] = e;
-    if (!(e <= mx)) mx = e;
+    mx = nan_max(mx, e);
   }
   if (eta_max) *eta_max = mx;
   return KKT_OK;
@@ -798,8 +806,8 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
       o.refactor_short_rows < -1 || o.refactor_short_rows > 0 || o.refactor_long_rows < -1 ||
       o.refactor_long_rows > 0 || o.refine_sync < 0 || o.refine_sync > 1 || o.refine_budget < -1 ||
       o.dense_lu < 0 || o.dense_lu > 1 || o.debug_spin_limit < 0 || o.debug_schedule < 0 ||
-      o.matching < 0 || o.matching > 1 ||
-      o.debug_schedule > 1 ||
+      o.matching < 0 || o.matching > 1 || o.refactor_micro_rows < -1 ||
+      o.refactor_micro_rows > 0 || o.debug_schedule > 1 ||
       !(o.pivot_perturb_rel >= 0.0 && o.pivot_perturb_rel < 1.0))
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
@@ -1272,8 +1280,24 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     }
     // chunks: rows of one level (independent of each other), up to 16 per
     // ticket on wide levels; one device-scope ticket counter serializes at
-    // about 10 ns per ticket, so single-row tickets would bound the wide part
+    // about 10 ns per ticket, so single-row tickets would bound the wide part.
+    // In a short-row band taken by the list kernel, a level's micro rows (at
+    // most MICRO_ROW_LEN entries, MICRO_ROW_PIV pivots and MICRO_ROW_LIST
+    // multiply-adds) come first, up to 64 to a chunk, one row per lane.
     std::vector<int32_t> order, cst;
+    std::vector<unsigned char> cmic;
+    const bool micro_ok = h->light && h->opt.refactor_short_rows == 0 &&
+                          h->opt.refactor_map >= 0 && h->opt.refactor_micro_rows == 0;
+    auto is_micro = [&](int32_t i) {
+      const int32_t rs = A.lu_rowptr[i], d = A.diag[i];
+      if (A.lu_rowptr[i + 1] - rs > MICRO_ROW_LEN || d - rs > MICRO_ROW_PIV) return false;
+      int32_t list = 0;
+      for (int32_t q = rs; q < d; q++) {
+        const int32_t k = A.lu_col[q];
+        list += A.lu_rowptr[k + 1] - A.diag[k] - 1;
+      }
+      return list <= MICRO_ROW_LIST;
+    };
     order.reserve(n);
     h->nbands = 0;
     flat_row.assign(n, 0);
@@ -1305,18 +1329,36 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
         while (e < hi && level[order[e]] == level[order[t]] &&
                (height[order[e]] >= hcrit) == crit)
           e++;
-        const int per = std::max(1, std::min(16, (e - t) / 8192));
-        for (int c = t; c < e; c += per) cst.push_back(c);
+        int m = t;  // [t, m): micro rows, in their order
+        if (short_ok && micro_ok)
+          m = (int)(std::stable_partition(order.begin() + t, order.begin() + e, is_micro) -
+                    order.begin());
+        for (int c = t; c < m; c += 64) {
+          cst.push_back(c);
+          cmic.push_back(1);
+        }
+        const int per = std::max(1, std::min(16, (e - m) / 8192));
+        for (int c = m; c < e; c += per) {
+          cst.push_back(c);
+          cmic.push_back(0);
+        }
         t = e;
       }
       h->band_chunk_lo[h->nbands] = clo;
       h->band_nchunks[h->nbands] = (int)cst.size() - clo;
       h->band_cap[h->nbands] = mx;
       cst.push_back(hi);  // end of the band's last chunk
+      cmic.push_back(0);
       h->nbands++;
     }
     UP(h->ref_order, order);
     UP(h->ref_cstart, cst);
+    h->ref_cmicro = nullptr;
+    for (unsigned char c : cmic)
+      if (c) {
+        UP(h->ref_cmicro, cmic);
+        break;
+      }
   }
   // update maps of the dependency-driven refactorization: one 16-bit row
   // position per multiply-add (rows must be shorter than 65536 entries and
@@ -1403,7 +1445,7 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   }
   // chain-blocked schedules of the four solves over the rows outside the
   // dense trailing block (modes 0 L, 1 U, 2 U^T, 3 L^T)
-  h->use_sn = h->syncfree && h->light && h->batch_count == 0 && h->opt.solve_chain >= 0;
+  h->use_sn = h->syncfree && h->light && h->opt.solve_chain >= 0;
   if (h->use_sn) {
     const int c0 = h->tail_c0;
     const int kmax = h->opt.solve_chain > 0 ? std::min(h->opt.solve_chain, SN_KMAX) : SN_KMAX;
@@ -1553,22 +1595,36 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
           }
         }
         if (singles.empty()) continue;
-        int mx = 0;
-        for (int32_t i : singles) mx = std::max(mx, le(i) - lb(i));
+        // the level's single rows by length, so that each chunk's lane groups
+        // (2^lg lanes per row, at most per_lane entries per lane, 64 >> lg
+        // rows) fit its own longest row rather than the level's
         const int per_lane =
             h->opt.solve_entries_per_lane > 0 ? h->opt.solve_entries_per_lane : 8;
-        int lg = 2;
-        while (lg < 6 && (per_lane << lg) < mx) lg++;
-        const int per = 64 >> lg;
-        for (size_t a = 0; a < singles.size(); a += per) {
-          const int k = (int)std::min<size_t>(per, singles.size() - a);
+        auto lg_for = [&](int32_t i) {
+          int lg = 0;
+          while (lg < 6 && (per_lane << lg) < le(i) - lb(i)) lg++;
+          return lg;
+        };
+        std::stable_sort(singles.begin(), singles.end(), [&](int32_t x, int32_t y) {
+          return le(x) - lb(x) < le(y) - lb(y);
+        });
+        for (size_t a = 0; a < singles.size();) {
+          int lg = lg_for(singles[a]);
+          size_t k = 0;
+          for (;;) {
+            k = std::min<size_t>((size_t)(64 >> lg), singles.size() - a);
+            const int lg2 = lg_for(singles[a + k - 1]);
+            if (lg2 <= lg) break;
+            lg = lg2;
+          }
           cst.push_back((int32_t)crow.size());
-          cmeta.push_back((lg << 8) | k);
+          cmeta.push_back((lg << 8) | (int)k);
           cbase.push_back(0);
-          for (int r = 0; r < k; r++) {
+          for (size_t r = 0; r < k; r++) {
             crow.push_back(singles[a + r]);
             csplit.push_back(split_of(singles[a + r], false, 0));
           }
+          a += k;
         }
       }
       SnSched& sn = h->chs[mode];
@@ -1700,11 +1756,11 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     if ((ks = upload(h, &h->d_row_off, ro)) != KKT_OK ||
         (ks = dalloc(h, &h->rowabs, (size_t)n)) != KKT_OK ||
         (ks = dalloc(h, &h->colabs, (size_t)n)) != KKT_OK ||
-        (ks = dalloc(h, &h->inst_out, (size_t)3 * h->batch_count)) != KKT_OK) {
+        (ks = dalloc(h, &h->inst_out, (size_t)3 * SEG_SLICES * h->batch_count)) != KKT_OK) {
       free_device(h);
       return ks;
     }
-    h->h_inst.assign((size_t)3 * h->batch_count, 0.0);
+    h->h_inst.assign((size_t)3 * SEG_SLICES * h->batch_count, 0.0);
     h->inst_eta.assign(h->batch_count, 0.0);
   }
   // the pivoting pass's factors are the current factors until the first refactor
@@ -1843,6 +1899,7 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
         if (!launch_refactor_flat(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
                                   h->band_nchunks[b], b, h->band_cap[b], h->ss, &h->st->stall,
                                   h->ref_moff, h->ref_map, h->luA, h->ref_fl,
+                                  h->ref_cmicro ? h->ref_cmicro + h->band_chunk_lo[b] : nullptr,
                                   h->opt.refactor_waves_per_cu, h->st, h->opt.pivot_perturb_rel,
                                   s))
           return fail(h, KKT_ERR_DEVICE, "short-row refactorization not launchable");
@@ -2187,6 +2244,15 @@ kkt_status kkt_get_info(kkt_handle h, kkt_info* out) {
   out->analyze_seconds = h->analyze_seconds;
   out->dense_tail = h->tail_s;
   out->factor_epoch = h->factor_epoch;
+  out->levels_sparse = 0;
+  for (int32_t l = 0; l + 1 < (int32_t)A.lev_ptr.size(); l++)
+    for (int32_t k = A.lev_ptr[l]; k < A.lev_ptr[l + 1]; k++)
+      if (A.lev_rows[k] < h->tail_c0) {
+        out->levels_sparse = l + 1;
+        break;
+      }
+  out->solve_block_levels[0] = h->use_sn ? h->chs_levels[0] : 0;
+  out->solve_block_levels[1] = h->use_sn ? h->chs_levels[1] : 0;
   return KKT_OK;
 }
 
@@ -2281,6 +2347,7 @@ kkt_status kkt_analysis_info(kkt_analysis a, kkt_info* out) {
   out->levels = (int32_t)A.lev_ptr.size() - 1;
   out->levels_u = (int32_t)A.ulev_ptr.size() - 1;
   out->analyze_status = A.warn_singular ? KKT_WARN_NUMERICALLY_SINGULAR : KKT_OK;
+  out->levels_sparse = out->levels;  // the dense block is chosen on the device handle
   return KKT_OK;
 }
 

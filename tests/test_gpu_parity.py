@@ -92,14 +92,16 @@ def test_sequence_refactor_solve(B, seed, steps, schedule):
 
 @pytest.mark.parametrize("variant", [dict(refactor_map=-1), dict(refactor_short_rows=-1),
                                      dict(refactor_long_rows=-1),
-                                     dict(refactor_short_rows=-1, refactor_long_rows=-1)],
+                                     dict(refactor_short_rows=-1, refactor_long_rows=-1),
+                                     dict(refactor_micro_rows=-1)],
                          ids=["binary-search", "short-rows-pivot-by-pivot", "long-rows-wave-per-row",
-                              "wave-per-row-everywhere"])
+                              "wave-per-row-everywhere", "no-micro-rows"])
 @pytest.mark.parametrize("B,seed", [(100, 101), (2000, 104)])
 def test_refactor_kernel_variants_bitwise(B, seed, variant):
     # binary search of each update's column instead of the precomputed map;
     # the short-row band pivot by pivot instead of as one list of updates;
-    # one wave per long row instead of a workgroup
+    # one wave per long row instead of a workgroup; a wave for every short row
+    # (no micro rows taken one per lane)
     print(f"case B={B} seed={seed} {variant}", flush=True)
     pat, seq = kktgen.make_sequence(B, seed, 2)
     s = binding.KKTSolver(schedule=2, sync_mode=2, **variant)
@@ -657,6 +659,29 @@ def test_batch_matches_per_instance_oracle():
         e = eta(pat.scipy(v), x[n0:n1], b)
         print(f"  instance {t}: eta {e:.3e} (device {etas[t]:.3e})", flush=True)
         assert e <= 1e-12 and etas[t] <= 1e-12 and abs(etas[t] - e) <= 1e-15
+
+
+@pytest.mark.parametrize("layout", [dict(), dict(solve_chain=1), dict(solve_chain=-1)],
+                         ids=lambda d: "-".join(f"{k}{v}" for k, v in d.items()) or "default")
+def test_batch_direct_solve_matches_oracle_apply(layout):
+    # no refinement: each instance's block of the batch's direct solve (both
+    # operations) against the oracle's direct solve of that instance
+    patterns, insts = _batch_cases()
+    s = binding.KKTSolver(fgmres_max_iters=0, **layout)
+    s.analyze_batch(patterns, [p for p, *_ in insts])
+    vals = np.concatenate([v for _, _, v, _ in insts])
+    rhs = np.concatenate([b for *_, b in insts])
+    s.refactor(dev(vals))
+    for op in ("N", "T"):
+        x = s.solve(dev(rhs), op=op).cpu().numpy()
+        for t, (p, pat, v, b) in enumerate(insts):
+            n0, n1 = s.row_offset[t], s.row_offset[t + 1]
+            pn, prp, pci, pv0 = patterns[p]
+            ora = oracle.OracleLU(pn, prp, pci, pv0, tau=1e-10)
+            ora.refactor(v)
+            xo = ora.apply(b, op)
+            err = np.abs(x[n0:n1] - xo).max() / np.abs(xo).max()
+            assert err <= 1e-8, (layout, op, t, err)
 
 
 def test_graph_replay_matches_eager():
