@@ -289,7 +289,7 @@ def bench_refinement(torch, binding, kktgen, B=10000, seed=102, reps=5):
 
 
 def bench_batched(torch, binding, kktgen, steps=5, seed=104, n_a=128, n_b=128, B_a=2000,
-                  with_cpu_baseline=True):
+                  with_cpu_baseline=True, tune=True):
     """256 scenario instances (128 sharing one B=2000 pattern, 128 with their
     own B ~ U[500, 5000]) in one captured graph replay, vs the plain loop of
     per-instance refactor + solve calls on the same GPU."""
@@ -303,12 +303,23 @@ def bench_batched(torch, binding, kktgen, steps=5, seed=104, n_a=128, n_b=128, B
     insts = [(0, p, v, r) for p, v, r in ga] + [(1 + i, p, v, r) for i, (p, v, r) in enumerate(gb)]
     patterns = [(ga[0][0].n, ga[0][0].rowptr, ga[0][0].colind, ga[0][1])]
     patterns += [(p.n, p.rowptr, p.colind, v) for p, v, _ in gb]
-    s = binding.KKTSolver()
-    t0 = time.perf_counter()
-    s.analyze_batch(patterns, [p for p, *_ in insts])
-    t_an = time.perf_counter() - t0
+    inst_pattern = [p for p, *_ in insts]
     vbuf = torch.from_numpy(np.concatenate([v for _, _, v, _ in insts])).to(dev)
     bbuf = torch.from_numpy(np.concatenate([r for *_, r in insts])).to(dev)
+    # batch knobs chosen by the autotuner (graph replays of each candidate)
+    tuned = {}
+    if tune:
+        from paper_2306_14337_amd import autotune
+        t0 = time.perf_counter()
+        best, cand_ms = autotune.autotune_batch(patterns, inst_pattern, vbuf, bbuf, repeats=3,
+                                                cache_path=None)
+        tuned = {"options": best, "candidates_ms_per_replay": cand_ms,
+                 "search_s": time.perf_counter() - t0}
+        torch.cuda.empty_cache()
+    s = binding.KKTSolver(**tuned.get("options", {}))
+    t0 = time.perf_counter()
+    s.analyze_batch(patterns, inst_pattern)
+    t_an = time.perf_counter() - t0
     xbuf = torch.empty_like(bbuf)
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
@@ -393,7 +404,7 @@ def bench_batched(torch, binding, kktgen, steps=5, seed=104, n_a=128, n_b=128, B
                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                          "bytes_per_batch_step": bytes_step,
                          "kernel": "one replay of the batch graph (all its kernels)"},
-            "generate_s": t_gen, "analyze_s": t_an,
+            "autotune": tuned or None, "generate_s": t_gen, "analyze_s": t_an,
             "cpu_baseline": cpu_baseline_batched(insts, patterns) if with_cpu_baseline else None}
 
 
@@ -407,6 +418,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint and batched workloads")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run the batched workload alone (--steps replays) and print its object")
+    ap.add_argument("--no-batch-tune", action="store_true",
+                    help="batched workload with the library defaults instead of the batch "
+                         "autotuner's choice")
     ap.add_argument("--schedule", type=int, default=0,
                     help="0 auto, 1 level-synchronous launches, 2 dependency-driven")
     ap.add_argument("--sync-mode", type=int, default=0,
@@ -434,13 +450,19 @@ def main():
                          "scale of the PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(a single system does not shard; see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU; multi-GPU runs are not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch
 
     from paper_2306_14337_amd import binding, kktgen
+
+    if args.only_batched:
+        # the batched workload alone (profiling): its JSON object, no oracle baseline
+        out = bench_batched(torch, binding, kktgen, steps=args.steps,
+                            with_cpu_baseline=False, tune=not args.no_batch_tune)
+        print(json.dumps(out), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     total = args.steps + args.warmup
@@ -633,7 +655,7 @@ def main():
         print("# adjoint workload", file=sys.stderr, flush=True)
         out["adjoint"] = bench_adjoint(torch, binding, kktgen, refine_budget=args.refine_budget)
         print("# batched workload", file=sys.stderr, flush=True)
-        out["batched"] = bench_batched(torch, binding, kktgen)
+        out["batched"] = bench_batched(torch, binding, kktgen, tune=not args.no_batch_tune)
         print("# refinement policies", file=sys.stderr, flush=True)
         out["refinement"] = bench_refinement(torch, binding, kktgen)
     if not args.no_cpu_baseline:

@@ -18,6 +18,19 @@ The winner is cached in a JSON file keyed by a hash of the pattern (n, row
 pointers, column indices), so a later run with the same pattern skips the
 search.  Candidates that fail (e.g. a schedule the pattern cannot use) are
 skipped.
+
+autotune_batch does the same for a block-diagonal batch (kkt_analyze_batch):
+it times replays of the captured batch graph (refactorization, solve and
+device-checked refinement) for each candidate, first one knob away from the
+library defaults at a time, then the combination of the knobs that won, and
+caches the winner under a hash of every pattern and the instance map.  Batch
+knobs:
+  refactor_crit_height      rows with this many rows chained after them first
+  refactor_micro_rows       micro rows one per lane (0) or a wave per row (-1)
+  refactor_waves_per_cu     resident waves per CU of the refactorization
+  solve_entries_per_lane    lane-group width of the single-row solve chunks
+  solve_blocks_per_cu       resident workgroups per CU of the solves
+  solve_chain               longest chain block of the solves
 """
 from __future__ import annotations
 
@@ -142,4 +155,99 @@ def autotune(n, rowptr, colind, values0, d_values, d_b, repeats: int = 3, full: 
             best, best_t = cand, dt
     if cache_path:
         store_cache(key, {"options": best, "seconds_per_step": best_t, "n": int(n)}, cache_path)
+    return dict(best), times
+
+
+def batch_key(patterns, inst_pattern) -> str:
+    h = hashlib.sha256(b"batch")
+    for n, rowptr, colind, _ in patterns:
+        h.update(pattern_key(n, rowptr, colind).encode())
+    h.update(np.ascontiguousarray(inst_pattern, dtype=np.int32).tobytes())
+    return h.hexdigest()[:32]
+
+
+def batch_candidates(full: bool = False):
+    """First-stage batch candidates: the library defaults, then one knob away."""
+    out = [dict()]
+    knobs = [dict(refactor_crit_height=-1), dict(refactor_crit_height=8),
+             dict(refactor_micro_rows=-1), dict(solve_entries_per_lane=4),
+             dict(solve_entries_per_lane=16), dict(solve_blocks_per_cu=4)]
+    if full:
+        knobs += [dict(refactor_waves_per_cu=16), dict(solve_chain=8), dict(solve_chain=-1)]
+    return out + knobs
+
+
+def autotune_batch(patterns, inst_pattern, d_values, d_b, repeats: int = 3, full: bool = False,
+                   candidates=None, cache_path: str | None = DEFAULT_CACHE,
+                   base_options: dict | None = None):
+    """Time captured batch-graph replays for every candidate option set on
+    (d_values, d_b); return (best option dict, {repr(candidate): ms per
+    replay}).  Uses the cache when the batch was tuned before."""
+    import torch
+
+    from . import binding
+
+    key = batch_key(patterns, inst_pattern)
+    if cache_path:
+        hit = load_cache(cache_path).get(key)
+        if hit:
+            return dict(hit["options"]), {}
+    base = dict(base_options or {})
+    times = {}
+
+    def run(cand):
+        opts = {**base, **cand}
+        try:
+            s = binding.KKTSolver(**opts)
+            s.analyze_batch(patterns, inst_pattern)
+            x = torch.empty_like(d_b)
+            stream = torch.cuda.Stream()
+            torch.cuda.synchronize()
+            s.graph_capture(d_values, d_b, x, stream)
+            s.graph_launch(stream)
+            stream.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(repeats):
+                s.graph_launch(stream)
+            e1.record(stream)
+            stream.synchronize()
+            if not float(s.batch_eta().max()) <= s.options.eta_target:
+                return None
+            ms = e0.elapsed_time(e1) / repeats
+            s.close()
+        except binding.KKTError:
+            return None
+        return ms
+
+    first = list(candidates) if candidates is not None else batch_candidates(full)
+    best, best_t = None, float("inf")
+    winners = []
+    base_t = None
+    for cand in first:
+        ms = run(cand)
+        if ms is None:
+            continue
+        times[repr(cand)] = ms
+        if cand == {}:
+            base_t = ms
+        elif base_t is not None and ms < base_t:
+            winners.append(cand)
+        if ms < best_t:
+            best, best_t = cand, ms
+    if best is None:
+        raise RuntimeError("no batch autotuner candidate ran")
+    # second stage: every knob that beat the defaults, together
+    if len(winners) > 1:
+        combo = {}
+        for w in winners:
+            for k, v in w.items():
+                combo.setdefault(k, v)
+        ms = run(combo)
+        if ms is not None:
+            times[repr(combo)] = ms
+            if ms < best_t:
+                best, best_t = combo, ms
+    if cache_path:
+        store_cache(key, {"options": best, "ms_per_replay": best_t, "batch": True}, cache_path)
     return dict(best), times

@@ -259,6 +259,7 @@ class KKTSolver:
         if st != OK:
             raise KKTError(st, "kkt_create failed")
         self._h = h
+        self.options = o  # the options the handle was created with
         self.n = None
         self.nnz = None
         self.last_status = OK

@@ -43,3 +43,19 @@ def test_refinements_vary_segments_dense_block_and_kernels():
         binding.options(**r)  # valid option fields
         assert {k: v for k, v in r.items() if k not in varied} == best
     assert autotune.refinements(dict(schedule=1, sync_mode=0)) == []
+
+
+def test_batch_candidates_and_key():
+    for full in (False, True):
+        cands = autotune.batch_candidates(full)
+        assert cands[0] == {} and len(cands) == len({repr(c) for c in cands})
+        for c in cands[1:]:
+            assert len(c) == 1
+            binding.options(**c)  # every knob is an option field
+    a = kktgen.make_kkt(50, 1)
+    b = kktgen.make_kkt(80, 2)
+    pa = [(a.n, a.rowptr, a.colind, None), (b.n, b.rowptr, b.colind, None)]
+    k1 = autotune.batch_key(pa, [0, 1, 0])
+    assert k1 == autotune.batch_key(pa, np.array([0, 1, 0]))
+    assert k1 != autotune.batch_key(pa, [0, 1, 1]) and k1 != autotune.batch_key(pa[::-1], [0, 1, 0])
+    assert k1 != autotune.pattern_key(a.n, a.rowptr, a.colind)

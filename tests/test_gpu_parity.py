@@ -953,3 +953,31 @@ def test_autotuner_picks_a_working_schedule(tmp_path):
     again, t2 = autotune.autotune(pat.n, pat.rowptr, pat.colind, vals, dev(vals), dev(b),
                                   cache_path=cache)
     assert again == best and t2 == {}
+
+
+def test_batch_autotuner_picks_working_knobs(tmp_path):
+    from paper_2306_14337_amd import autotune
+
+    patterns, insts = _batch_cases()
+    inst_pattern = [p for p, *_ in insts]
+    vals = dev(np.concatenate([v for _, _, v, _ in insts]))
+    rhs = np.concatenate([b for *_, b in insts])
+    cache = str(tmp_path / "tune.json")
+    best, times = autotune.autotune_batch(patterns, inst_pattern, vals, dev(rhs), repeats=1,
+                                          cache_path=cache)
+    print(f"  best {best}, times {times}", flush=True)
+    assert len(times) >= 2 and "{}" in times
+    # the winner runs the batch to the target, factors bitwise as the defaults
+    s = binding.KKTSolver(**best)
+    s.analyze_batch(patterns, inst_pattern)
+    s.refactor(vals)
+    x = s.solve(dev(rhs)).cpu().numpy()
+    ref = binding.KKTSolver()
+    ref.analyze_batch(patterns, inst_pattern)
+    ref.refactor(vals)
+    assert np.array_equal(s.lu()[2].view(np.int64), ref.lu()[2].view(np.int64))
+    for t, (p, pat, v, b) in enumerate(insts):
+        n0, n1 = s.row_offset[t], s.row_offset[t + 1]
+        assert eta(pat.scipy(v), x[n0:n1], b) <= 1e-12, t
+    again, t2 = autotune.autotune_batch(patterns, inst_pattern, vals, dev(rhs), cache_path=cache)
+    assert again == best and t2 == {}
