@@ -260,13 +260,15 @@ bool launch_refactor_wg(const LUView& lu, const int* order, const int* cstart, i
 // row's L entries q = (offset of pivot q's first multiply-add in the row's
 // list, U row start of pivot q minus that offset), at the diagonal q =
 // (length of the list, 0); map holds packed entries (launch_build_refmap with
-// flat).  Device-coherent value-as-flag publication only.  cmicro (may be
+// flat).  rmeta: per position of the bands' row order, (row start, length |
+// pivots << 16, update-map offset, list length); cstart holds positions in
+// that order.  Device-coherent value-as-flag publication only.  cmicro (may be
 // null): per chunk, non-zero for a chunk of micro rows (one level, at most 64
 // rows of at most MICRO_LEN entries, MICRO_PIV pivots and MICRO_LIST
 // multiply-adds), taken one row per lane.
 constexpr int MICRO_ROW_LEN = 8, MICRO_ROW_PIV = 4, MICRO_ROW_LIST = 4;
-bool launch_refactor_flat(const LUView& lu, const int* order, const int* cstart, int nchunks,
-                          int band, int cap, SyncState* ss, int* stall, const int* moff,
+bool launch_refactor_flat(const LUView& lu, const int* cstart, int nchunks, int band, int cap,
+                          SyncState* ss, int* stall, const int4* rmeta,
                           const unsigned short* map, const double* luA, const int2* fl,
                           const unsigned char* cmicro, int max_waves_per_cu, DevStats* st,
                           double perturb_rel, hipStream_t s);

@@ -2574,17 +2574,14 @@ __host__ __device__ constexpr int flat_area(int cap) {
   return 2 * cap > MICRO_LEN * WAVE ? 2 * cap : MICRO_LEN * WAVE;
 }
 
-__device__ __forceinline__ void refactor_micro_row(int i, int lane, double* sa,
-                                                   const int* __restrict__ rowptr,
-                                                   const int* __restrict__ diag, double* val,
-                                                   int* stall, const int* __restrict__ moff,
+__device__ __forceinline__ void refactor_micro_row(int4 mt, int lane, double* sa, double* val,
+                                                   int* stall,
                                                    const unsigned short* __restrict__ map,
                                                    const double* __restrict__ luA,
                                                    const int2* __restrict__ fl, DevStats* st,
                                                    double thr) {
-  const int rs = rowptr[i], len = rowptr[i + 1] - rs, dl = diag[i] - rs;
-  const int nl = fl[rs + dl].x;  // list length (the diagonal's entry)
-  const int mb = moff[rs];
+  // row start, length, pivots, update-map offset, list length
+  const int rs = mt.x, len = mt.y & 0xffff, dl = mt.y >> 16, mb = mt.z, nl = mt.w;
   for (int k = 0; k < len; k++) sa[k * WAVE + lane] = luA[rs + k];
   double d[MICRO_PIV], u[MICRO_LIST];
   unsigned int mm[MICRO_LIST];  // packed map entries: pivot << 8 | target position
@@ -2676,14 +2673,20 @@ __device__ __forceinline__ void refactor_micro_row(int i, int lane, double* sa,
 // holds the sentinel; a pivot row is finished once its diagonal is, and each
 // of its other entries is re-polled while it still reads as the sentinel.
 // Chunks flagged in cmicro hold micro rows, one per lane (refactor_micro_row).
+// Per row few dependent memory round trips: the chunk's row metadata (rmeta,
+// per order position: row start, length | pivots << 16, map offset, list
+// length) comes in one load for all its rows; the staging of values and list
+// bounds is the second; the first list window goes out together with the
+// pivot-diagonal poll (entries of pivots not finished yet read as the sentinel
+// and are polled again before use), its U addresses found from the staged list
+// bounds rather than from the map.
 template <int WPB>
 __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
-    const int* __restrict__ order, const int* __restrict__ cstart, int nchunks,
-    unsigned int* tickets, int nstreams, const int* __restrict__ rowptr,
-    const int* __restrict__ diag, double* val, int* stall, int cap,
-    const int* __restrict__ moff, const unsigned short* __restrict__ map,
-    const double* __restrict__ luA, const int2* __restrict__ fl,
-    const unsigned char* __restrict__ cmicro, DevStats* st, double prel) {
+    const int* __restrict__ cstart, int nchunks, unsigned int* tickets, int nstreams,
+    double* val, int* stall, int cap, const int4* __restrict__ rmeta,
+    const unsigned short* __restrict__ map, const double* __restrict__ luA,
+    const int2* __restrict__ fl, const unsigned char* __restrict__ cmicro, DevStats* st,
+    double prel) {
   extern __shared__ double smem_d[];
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   // LDS per wave, one area of flat_area(cap) doubles: values (cap doubles),
@@ -2695,33 +2698,54 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
   for (;;) {
     const int tk = next_chunk(tickets, nstreams, lane);
     if (tk >= nchunks) break;
+    const int cs = cstart[tk], ce = cstart[tk + 1];
+    // the chunk's rows (at most 64), one per lane
+    const int4 mt = cs + lane < ce ? rmeta[cs + lane] : make_int4(0, 0, 0, 0);
     if (cmicro != nullptr && bcast0(cmicro[tk]) != 0u) {
       wave_sync();  // the last row of a previous chunk is done with the area
-      const int r = cstart[tk] + lane;
-      if (r < cstart[tk + 1])
-        refactor_micro_row(order[r], lane, sv, rowptr, diag, val, stall, moff, map, luA, fl, st,
-                           thr);
+      if (cs + lane < ce) refactor_micro_row(mt, lane, sv, val, stall, map, luA, fl, st, thr);
       continue;
     }
-    const int r_end = cstart[tk + 1];
-    for (int r = cstart[tk]; r < r_end; r++) {
-      const int i = order[r];
+    for (int r = cs; r < ce; r++) {
+      const int k = r - cs;
+      const int rs = __builtin_amdgcn_readlane(mt.x, k);
+      const int ld = __builtin_amdgcn_readlane(mt.y, k);
+      const int len = ld & 0xffff, dl = ld >> 16;
+      const int mb = __builtin_amdgcn_readlane(mt.z, k);
+      const int nl = __builtin_amdgcn_readlane(mt.w, k);
       wave_sync();  // the previous row of this chunk is done with the staging area
-      const int rs = rowptr[i], len = rowptr[i + 1] - rs, dl = diag[i] - rs;
       for (int t = lane; t < len; t += WAVE) sv[t] = luA[rs + t];
       for (int t = lane; t <= dl; t += WAVE) sf[t] = fl[rs + t];
-      const int mb = dl > 0 ? moff[rs] : 0;
       wave_sync();
       int ready_upto = 0, t0 = 0, spins = 0;
       double dv = 0.0;  // lane q: diagonal of pivot t0 + q
-      int wbeg = 0, wend = 0;
       double u[4];
       int tp[4];  // packed map entry of the loaded list entry, -1 if none
+      // list window [wbeg, wend): entry e's pivot is the last t with
+      // sf[t].x <= e (pivots without U entries share their successor's
+      // offset), so its U value sits at e + sf[t].y
+      int wbeg = 0, wend = min(4 * WAVE, nl);
+      auto load_window = [&]() {
 #pragma unroll
-      for (int z = 0; z < 4; z++) {
-        u[z] = 0.0;
-        tp[z] = -1;
-      }
+        for (int z = 0; z < 4; z++) {
+          const int e = wbeg + lane + z * WAVE;
+          tp[z] = -1;
+          u[z] = 0.0;
+          if (e < wend) {
+            tp[z] = (int)map[mb + e];
+            int lo = 0, hi = dl - 1;
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (sf[mid].x <= e)
+                lo = mid;
+              else
+                hi = mid - 1;
+            }
+            u[z] = ld_coh(val + (e + sf[lo].y));
+          }
+        }
+      };
+      load_window();  // in flight with the first pivot poll below
       for (int t = 0; t < dl; t++) {
         if (t >= ready_upto) {
           for (;;) {
@@ -2772,26 +2796,16 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
             }
           }
           if (oe <= wend) break;
-          // next window of the list: entries of pivots seen finished
-          // (t < ready_upto <= dl, so the window holds at least pivot t's
-          // next entry; a window that cannot advance means inconsistent
-          // list bounds: report a stall rather than loop)
+          // next window of the list (pivot t's entries continue past this
+          // one; a window that cannot advance means inconsistent list
+          // bounds: report a stall rather than loop)
           wbeg = wend;
-          wend = min(wbeg + 4 * WAVE, sf[ready_upto].x);
+          wend = min(wbeg + 4 * WAVE, nl);
           if (wend <= wbeg) {
             st_flag(stall, 1);
             break;
           }
-#pragma unroll
-          for (int z = 0; z < 4; z++) {
-            const int e = wbeg + lane + z * WAVE;
-            tp[z] = -1;
-            if (e < wend) {
-              const int m = (int)map[mb + e];
-              tp[z] = m;
-              u[z] = ld_coh(val + (e + sf[m >> 8].y));
-            }
-          }
+          load_window();
         }
         wave_sync();
         sv[t] = lik;  // every lane writes the same value
@@ -3629,13 +3643,14 @@ bool launch_refactor_wg(const LUView& lu, const int* order, const int* cstart, i
   return true;
 }
 
-bool launch_refactor_flat(const LUView& lu, const int* order, const int* cstart, int nchunks,
-                          int band, int cap, SyncState* ss, int* stall, const int* moff,
+bool launch_refactor_flat(const LUView& lu, const int* cstart, int nchunks, int band, int cap,
+                          SyncState* ss, int* stall, const int4* rmeta,
                           const unsigned short* map, const double* luA, const int2* fl,
                           const unsigned char* cmicro, int max_waves_per_cu, DevStats* st,
                           double perturb_rel, hipStream_t s) {
   if (nchunks <= 0) return true;
-  if (band < 0 || band >= REF_MAX_BANDS || cap > 256 || !moff || !map || !luA || !fl) return false;
+  if (band < 0 || band >= REF_MAX_BANDS || cap > 256 || !rmeta || !map || !luA || !fl)
+    return false;
   cap = (cap + 1) & ~1;
   constexpr int WPB = 4;
   const size_t shm = (size_t)flat_area(cap) * sizeof(double) * WPB;
@@ -3653,9 +3668,9 @@ bool launch_refactor_flat(const LUView& lu, const int* order, const int* cstart,
     nb = 1;
   if (max_waves_per_cu > 0) nb = std::max(1, std::min(nb, max_waves_per_cu / WPB));
   const int grid = std::max(1, std::min(nb * ncu, cdiv(nchunks, WPB)));
-  hipLaunchKernelGGL(k_refactor_flat<WPB>, dim3(grid), dim3(WPB * WAVE), shm, s, order, cstart,
-                     nchunks, ss->band_stream[band], std::min(TICKET_STREAMS, grid), lu.rowptr,
-                     lu.diag, lu.val, stall, cap, moff, map, luA, fl, cmicro, st, perturb_rel);
+  hipLaunchKernelGGL(k_refactor_flat<WPB>, dim3(grid), dim3(WPB * WAVE), shm, s, cstart, nchunks,
+                     ss->band_stream[band], std::min(TICKET_STREAMS, grid), lu.val, stall, cap,
+                     rmeta, map, luA, fl, cmicro, st, perturb_rel);
   return true;
 }
 

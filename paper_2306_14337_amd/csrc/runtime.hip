@@ -118,6 +118,7 @@ struct kkt_ctx {
   // entries and the per-entry list bounds
   bool band_flat[REF_MAX_BANDS] = {};
   unsigned char* ref_flat = nullptr;
+  int4* ref_rmeta = nullptr;  // list-kernel row metadata per order position
   int2* ref_fl = nullptr;
   int nbands = 0;
   int band_chunk_lo[REF_MAX_BANDS] = {}, band_nchunks[REF_MAX_BANDS] = {},
@@ -1203,6 +1204,7 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   }
   // rows of the short-row bands (packed update maps, launch_refactor_flat)
   std::vector<uint8_t> flat_row;
+  std::vector<int32_t> order_host;  // the bands' row order (row metadata of the list kernel)
   for (bool& f : h->band_flat) f = false;
   // refactorization bands: a row's band is set by its length (LDS staging
   // size, hence rows in flight per CU) and raised to the band of any row it
@@ -1352,6 +1354,7 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
       h->nbands++;
     }
     UP(h->ref_order, order);
+    order_host = order;
     UP(h->ref_cstart, cst);
     h->ref_cmicro = nullptr;
     for (unsigned char c : cmic)
@@ -1368,6 +1371,7 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   h->ref_map_entries = 0;
   h->ref_fl = nullptr;
   h->ref_flat = nullptr;
+  h->ref_rmeta = nullptr;
   if (h->syncfree && h->opt.refactor_map >= 0) {
     std::vector<int32_t> moff(A.lu_col.size(), 0);
     int64_t tot = 0;
@@ -1408,6 +1412,17 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
         }
         UP(h->ref_fl, fl);
         UP(h->ref_flat, flat_row);
+        // per position of the bands' order, for the list kernel's rows: row
+        // start, length | pivots << 16, update-map offset, list length
+        std::vector<int4> meta(order_host.size(), make_int4(0, 0, 0, 0));
+        for (size_t r = 0; r < order_host.size(); r++) {
+          const int32_t i = order_host[r];
+          if (!flat_row[i]) continue;
+          const int32_t rs = A.lu_rowptr[i], d = A.diag[i];
+          meta[r] = make_int4(rs, (A.lu_rowptr[i + 1] - rs) | ((d - rs) << 16), moff[rs],
+                              fl[d].x);
+        }
+        UP(h->ref_rmeta, meta);
       }
     }
   }
@@ -1896,9 +1911,9 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
                             h->luA, h->tail_c0, h->st, h->opt.pivot_perturb_rel);
     for (int b = 0; b < h->nbands; b++)
       if (h->band_flat[b]) {
-        if (!launch_refactor_flat(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
-                                  h->band_nchunks[b], b, h->band_cap[b], h->ss, &h->st->stall,
-                                  h->ref_moff, h->ref_map, h->luA, h->ref_fl,
+        if (!launch_refactor_flat(lu, h->ref_cstart + h->band_chunk_lo[b], h->band_nchunks[b], b,
+                                  h->band_cap[b], h->ss, &h->st->stall,
+                                  h->ref_rmeta, h->ref_map, h->luA, h->ref_fl,
                                   h->ref_cmicro ? h->ref_cmicro + h->band_chunk_lo[b] : nullptr,
                                   h->opt.refactor_waves_per_cu, h->st, h->opt.pivot_perturb_rel,
                                   s))
