@@ -168,6 +168,10 @@ typedef struct {
                                   rows of at most 8 entries, 4 pivots and 4 multiply-adds go
                                   one per lane, up to 64 rows of one level to a wave (default);
                                   -1 = one wave per row for every row of the band */
+  int32_t debug_timeline;   /* profiling: 1 = every refactorization records, per row of its two
+                               band kernels, when the row started, when it last found an input
+                               missing and when its stores completed (kkt_debug_timeline);
+                               0 = off (default) */
 } kkt_options;
 
 typedef struct {
@@ -352,6 +356,14 @@ kkt_status kkt_analysis_create(const kkt_options *opt, int32_t n, int64_t nnz,
                                const int64_t *rowptr, const int32_t *colind,
                                const double *values0, const int32_t *user_q, kkt_analysis *out,
                                char *msg, int32_t msg_len);
+/* Profiling (debug_timeline = 1): the row timeline of the last refactorization, 4 values per
+ * row into out (n x 4 int64, host memory): start, last poll that found an input missing, end
+ * (nanoseconds from the earliest start) and the kernel (1 micro row taken by one lane, 2
+ * short-row list kernel, 3 long-row kernel); rows the two band kernels did not take (rows
+ * without pivots, the dense block's own steps) read -1, -1, -1, 0.  Synchronises the device.
+ * Errors: INVALID_ARG, STATE (no timeline on this handle), DEVICE. */
+kkt_status kkt_debug_timeline(kkt_handle h, int64_t *out);
+
 /* Sizes and depths (device_bytes, analyze_seconds and solve_block_levels are 0; no dense
  * block is chosen, so levels_sparse equals levels). */
 kkt_status kkt_analysis_info(kkt_analysis a, kkt_info *out);

@@ -38,7 +38,7 @@ EXPORTS = [
     "kkt_analysis_perm", "kkt_analysis_lu", "kkt_analysis_levels", "kkt_analysis_destroy",
     "kkt_analyze_batch", "kkt_batch_layout", "kkt_batch_eta", "kkt_graph_capture",
     "kkt_graph_launch", "kkt_reanalyze", "kkt_solve_noalloc", "kkt_get_scaling",
-    "kkt_analysis_scaling",
+    "kkt_analysis_scaling", "kkt_debug_timeline",
 ]
 
 
@@ -63,7 +63,8 @@ class Options(C.Structure):
                 ("refactor_long_rows", C.c_int32), ("refine_sync", C.c_int32),
                 ("refine_budget", C.c_int32), ("dense_lu", C.c_int32),
                 ("debug_spin_limit", C.c_int32), ("debug_schedule", C.c_int32),
-                ("matching", C.c_int32), ("refactor_micro_rows", C.c_int32)]
+                ("matching", C.c_int32), ("refactor_micro_rows", C.c_int32),
+                ("debug_timeline", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -106,6 +107,7 @@ def lib():
         L.kkt_get_info.argtypes = [P, C.POINTER(Info)]
         L.kkt_get_perm.argtypes = [P, P, P]
         L.kkt_get_scaling.argtypes = [P, P, P, P]
+        L.kkt_debug_timeline.argtypes = [P, P]
         L.kkt_analysis_scaling.argtypes = [P, P, P, P]
         L.kkt_get_lu.argtypes = [P, P, P, P]
         L.kkt_last_error.argtypes = [P]
@@ -405,6 +407,15 @@ class KKTSolver:
         dc = np.empty(self.n, np.float64)
         self._check(lib().kkt_get_scaling(self._h, _np_ptr(m), _np_ptr(dr), _np_ptr(dc)))
         return m, dr, dc
+
+    def debug_timeline(self) -> np.ndarray:
+        """Row timeline of the last refactorization (handle created with
+        debug_timeline=1): n x 4 int64 (start, last poll that found an input
+        missing, end in ns; kernel kind 1 micro / 2 list / 3 long-row; -1 and
+        0 for rows outside the two band kernels)."""
+        out = np.empty((self.n, 4), np.int64)
+        self._check(lib().kkt_debug_timeline(self._h, _np_ptr(out)))
+        return out
 
     def lu(self, values: bool = True):
         i = self.info()

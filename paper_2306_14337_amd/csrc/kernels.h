@@ -253,7 +253,7 @@ bool launch_refactor_wg(const LUView& lu, const int* order, const int* cstart, i
                         int band, int cap, SyncState* ss, int* stall, int c0, const int* dlc,
                         const int* moff, const unsigned short* map, const double* luA,
                         const int2* pbnd, int max_waves_per_cu, DevStats* st, double perturb_rel,
-                        hipStream_t s);
+                        hipStream_t s, long long* tl = nullptr);
 
 // A short-row band: one wave per row, every row of the band at most 256
 // entries, no row of the dense block.  fl[q] for the
@@ -271,7 +271,11 @@ bool launch_refactor_flat(const LUView& lu, const int* cstart, int nchunks, int 
                           SyncState* ss, int* stall, const int4* rmeta,
                           const unsigned short* map, const double* luA, const int2* fl,
                           const unsigned char* cmicro, int max_waves_per_cu, DevStats* st,
-                          double perturb_rel, hipStream_t s);
+                          double perturb_rel, hipStream_t s, const int* order = nullptr,
+                          long long* tl = nullptr);
+// tl (debug): per-row timeline of the two band kernels, 3 wall-clock values per
+// row (start, last poll that found an input missing, end | kind << 62); order
+// (the bands' row order) is read only when tl is set
 
 // Dense trailing block: rows and columns c0 .. c0+s-1 of the factors in pivot
 // order, held row-major in T (S x S, S = s rounded up to DLU_NB; the padding

@@ -2569,17 +2569,31 @@ inline int rows_grid(int n) { return std::max(1, std::min(cdiv(n, 32), 1024)); }
 // the U addresses do not wait for the map.
 constexpr int MICRO_LEN = MICRO_ROW_LEN, MICRO_PIV = MICRO_ROW_PIV, MICRO_LIST = MICRO_ROW_LIST;
 
+// Row timeline (debug_timeline): tl[3 i] = the row's start (staged), tl[3 i +
+// 1] = the last poll that still found one of its inputs missing (the start if
+// none did), tl[3 i + 2] = after its stores completed, with the kernel kind in
+// bits 62-63 (1 micro row, 2 list kernel, 3 long-row kernel); wall-clock
+// ticks.
+__device__ __forceinline__ void tl_record(long long* tl, int i, long long t0, long long t1,
+                                          long long kind) {
+  stores_done();
+  tl[3 * (size_t)i] = t0;
+  tl[3 * (size_t)i + 1] = t1;
+  tl[3 * (size_t)i + 2] = (long long)wall_clock64() | (kind << 62);
+}
+
 // doubles of LDS per wave of k_refactor_flat (cap even)
 __host__ __device__ constexpr int flat_area(int cap) {
   return 2 * cap > MICRO_LEN * WAVE ? 2 * cap : MICRO_LEN * WAVE;
 }
 
-__device__ __forceinline__ void refactor_micro_row(int4 mt, int lane, double* sa, double* val,
-                                                   int* stall,
+__device__ __forceinline__ void refactor_micro_row(int4 mt, int i, int lane, double* sa,
+                                                   double* val, int* stall,
                                                    const unsigned short* __restrict__ map,
                                                    const double* __restrict__ luA,
                                                    const int2* __restrict__ fl, DevStats* st,
-                                                   double thr) {
+                                                   double thr, long long* tl) {
+  const long long tl0 = tl ? (long long)wall_clock64() : 0;
   // row start, length, pivots, update-map offset, list length
   const int rs = mt.x, len = mt.y & 0xffff, dl = mt.y >> 16, mb = mt.z, nl = mt.w;
   for (int k = 0; k < len; k++) sa[k * WAVE + lane] = luA[rs + k];
@@ -2618,6 +2632,7 @@ __device__ __forceinline__ void refactor_micro_row(int4 mt, int lane, double* sa
   // pivot rows not finished when first read: poll the missing values (their
   // addresses are recomputed from fl)
   int spins = 0;
+  long long tl1 = tl0;
   for (;;) {
     bool miss = false;
 #pragma unroll
@@ -2625,6 +2640,7 @@ __device__ __forceinline__ void refactor_micro_row(int4 mt, int lane, double* sa
 #pragma unroll
     for (int e = 0; e < MICRO_LIST; e++) miss = miss || (e < nl && is_sentinel(u[e]));
     if (!miss || !keep_waiting(&spins, stall)) break;
+    if (tl) tl1 = (long long)wall_clock64();
 #pragma unroll
     for (int t = 0; t < MICRO_PIV; t++)
       if (t < dl && is_sentinel(d[t])) {
@@ -2656,6 +2672,7 @@ __device__ __forceinline__ void refactor_micro_row(int4 mt, int lane, double* sa
     }
   }
   for (int k = 0; k < len; k++) st_coh(val + rs + k, sa[k * WAVE + lane]);
+  if (tl) tl_record(tl, i, tl0, tl1, 1);
 }
 
 // Rows of a short-row band (at most 256 entries each; no row of the dense
@@ -2686,7 +2703,7 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
     double* val, int* stall, int cap, const int4* __restrict__ rmeta,
     const unsigned short* __restrict__ map, const double* __restrict__ luA,
     const int2* __restrict__ fl, const unsigned char* __restrict__ cmicro, DevStats* st,
-    double prel) {
+    double prel, const int* __restrict__ order, long long* tl) {
   extern __shared__ double smem_d[];
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   // LDS per wave, one area of flat_area(cap) doubles: values (cap doubles),
@@ -2703,7 +2720,9 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
     const int4 mt = cs + lane < ce ? rmeta[cs + lane] : make_int4(0, 0, 0, 0);
     if (cmicro != nullptr && bcast0(cmicro[tk]) != 0u) {
       wave_sync();  // the last row of a previous chunk is done with the area
-      if (cs + lane < ce) refactor_micro_row(mt, lane, sv, val, stall, map, luA, fl, st, thr);
+      if (cs + lane < ce)
+        refactor_micro_row(mt, tl ? order[cs + lane] : 0, lane, sv, val, stall, map, luA, fl, st,
+                           thr, tl);
       continue;
     }
     for (int r = cs; r < ce; r++) {
@@ -2717,6 +2736,8 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
       for (int t = lane; t < len; t += WAVE) sv[t] = luA[rs + t];
       for (int t = lane; t <= dl; t += WAVE) sf[t] = fl[rs + t];
       wave_sync();
+      const long long tl0 = tl ? (long long)wall_clock64() : 0;
+      long long tl1 = tl0;
       int ready_upto = 0, t0 = 0, spins = 0;
       double dv = 0.0;  // lane q: diagonal of pivot t0 + q
       double u[4];
@@ -2774,6 +2795,7 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
             bool go = true;
             while (go && bcast0(is_sentinel(ld_coh(val + dpt)) ? 1u : 0u) != 0u)
               go = bcast0(keep_waiting(&spins, stall) ? 1u : 0u) != 0u;
+            if (tl) tl1 = (long long)wall_clock64();
             if (!go) {  // stalled: drain
               ready_upto = dl;
               t0 = t;
@@ -2789,6 +2811,7 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
 #pragma unroll
           for (int z = 0; z < 4; z++) {
             if ((tp[z] >> 8) == t) {
+              if (tl && is_sentinel(u[z])) tl1 = (long long)wall_clock64();
               while (is_sentinel(u[z]) && keep_waiting(&spins, stall))
                 u[z] = ld_coh(val + (wbeg + lane + z * WAVE + dt));
               const int p = tp[z] & 255;
@@ -2822,6 +2845,14 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
         wave_sync();
       }
       for (int t = lane; t < len; t += WAVE) st_coh(val + rs + t, sv[t]);
+      if (tl) {
+        long long t1 = tl1;  // the latest wait of any lane
+        for (int off = WAVE / 2; off > 0; off >>= 1) {
+          const long long o = __shfl_xor(t1, off, WAVE);
+          t1 = o > t1 ? o : t1;
+        }
+        if (lane == 0) tl_record(tl, order[r], tl0, t1, 2);
+      }
     }
   }
 }
@@ -2848,7 +2879,7 @@ __global__ __launch_bounds__(WPR* WAVE) void k_refactor_wg(
     const int* __restrict__ dlc, double* val, int* stall, const int* __restrict__ moff,
     const unsigned short* __restrict__ map, const double* __restrict__ luA,
     const int2* __restrict__ pbnd, const int* __restrict__ diag, int c0, DevStats* st,
-    double prel) {
+    double prel, long long* tl) {
   constexpr int R = 4;  // prefetched chunks of 64 U entries per pivot step
   constexpr int NT = WPR * WAVE;
   constexpr int AHEAD = WPR * DEPTH;
@@ -2880,6 +2911,7 @@ __global__ __launch_bounds__(WPR* WAVE) void k_refactor_wg(
       const int rs = rowptr[i], len = rowptr[i + 1] - rs;
       const int dl = dlc[i];
       int spins = 0;
+      long long tl0 = 0, tl1 = 0;
       for (int t = threadIdx.x; t < len; t += NT) sv[t] = luA[rs + t];
       // this wave's steps w + WPR * (64 * ib + lane): pivot-row bounds, map offsets
       int ib = -1, ib_mo = 0;
@@ -2917,6 +2949,7 @@ __global__ __launch_bounds__(WPR* WAVE) void k_refactor_wg(
 #pragma unroll
           for (int z = 0; z < R; z++) miss = miss || (b.p[z] >= 0 && is_sentinel(b.u[z]));
           if (__ballot(miss) == 0) break;
+          if (tl) tl1 = (long long)wall_clock64();
           if (bcast0(keep_waiting(&spins, stall) ? 1u : 0u) == 0u) break;
           if (is_sentinel(b.ukk)) b.ukk = ld_coh(val + b.kk.x);
 #pragma unroll
@@ -2958,6 +2991,7 @@ __global__ __launch_bounds__(WPR* WAVE) void k_refactor_wg(
       for (int d = 0; d < DEPTH; d++)
         if (wave + d * WPR < dl) load(buf[d], wave + d * WPR);
       __syncthreads();  // the row's values are staged
+      if (tl) tl0 = tl1 = (long long)wall_clock64();
       for (int tb = 0; tb < dl; tb += AHEAD) {
 #pragma unroll
         for (int d = 0; d < DEPTH; d++) {
@@ -2984,6 +3018,7 @@ __global__ __launch_bounds__(WPR* WAVE) void k_refactor_wg(
         __syncthreads();
       }
       for (int t = threadIdx.x; t < len; t += NT) st_coh(val + rs + t, sv[t]);
+      if (tl && threadIdx.x == 0) tl_record(tl, i, tl0, tl1, 3);
       __syncthreads();  // the staging area is reused by the next row
     }
   }
@@ -3616,7 +3651,7 @@ bool launch_refactor_wg(const LUView& lu, const int* order, const int* cstart, i
                         int band, int cap, SyncState* ss, int* stall, int c0, const int* dlc,
                         const int* moff, const unsigned short* map, const double* luA,
                         const int2* pbnd, int max_waves_per_cu, DevStats* st, double perturb_rel,
-                        hipStream_t s) {
+                        hipStream_t s, long long* tl) {
   if (nchunks <= 0) return true;
   if (band < 0 || band >= REF_MAX_BANDS || !dlc || !moff || !map || !luA || !pbnd) return false;
   constexpr int WPR = KKTLU_WG_WPR, DEPTH = KKTLU_WG_DEPTH;
@@ -3639,7 +3674,7 @@ bool launch_refactor_wg(const LUView& lu, const int* order, const int* cstart, i
   hipLaunchKernelGGL((k_refactor_wg<WPR, DEPTH>), dim3(grid), dim3(WPR * WAVE), shm, s, order,
                      cstart, nchunks, ss->band_stream[band], std::min(TICKET_STREAMS, grid),
                      lu.rowptr, dlc, lu.val, stall, moff, map, luA, pbnd, lu.diag, c0, st,
-                     perturb_rel);
+                     perturb_rel, tl);
   return true;
 }
 
@@ -3647,7 +3682,7 @@ bool launch_refactor_flat(const LUView& lu, const int* cstart, int nchunks, int 
                           SyncState* ss, int* stall, const int4* rmeta,
                           const unsigned short* map, const double* luA, const int2* fl,
                           const unsigned char* cmicro, int max_waves_per_cu, DevStats* st,
-                          double perturb_rel, hipStream_t s) {
+                          double perturb_rel, hipStream_t s, const int* order, long long* tl) {
   if (nchunks <= 0) return true;
   if (band < 0 || band >= REF_MAX_BANDS || cap > 256 || !rmeta || !map || !luA || !fl)
     return false;
@@ -3670,7 +3705,7 @@ bool launch_refactor_flat(const LUView& lu, const int* cstart, int nchunks, int 
   const int grid = std::max(1, std::min(nb * ncu, cdiv(nchunks, WPB)));
   hipLaunchKernelGGL(k_refactor_flat<WPB>, dim3(grid), dim3(WPB * WAVE), shm, s, cstart, nchunks,
                      ss->band_stream[band], std::min(TICKET_STREAMS, grid), lu.val, stall, cap,
-                     rmeta, map, luA, fl, cmicro, st, perturb_rel);
+                     rmeta, map, luA, fl, cmicro, st, perturb_rel, order, tl);
   return true;
 }
 

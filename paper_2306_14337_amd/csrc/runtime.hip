@@ -119,6 +119,7 @@ struct kkt_ctx {
   bool band_flat[REF_MAX_BANDS] = {};
   unsigned char* ref_flat = nullptr;
   int4* ref_rmeta = nullptr;  // list-kernel row metadata per order position
+  long long* tl = nullptr;     // debug_timeline: 3 wall-clock values per row
   int2* ref_fl = nullptr;
   int nbands = 0;
   int band_chunk_lo[REF_MAX_BANDS] = {}, band_nchunks[REF_MAX_BANDS] = {},
@@ -808,7 +809,8 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
       o.refactor_long_rows > 0 || o.refine_sync < 0 || o.refine_sync > 1 || o.refine_budget < -1 ||
       o.dense_lu < 0 || o.dense_lu > 1 || o.debug_spin_limit < 0 || o.debug_schedule < 0 ||
       o.matching < 0 || o.matching > 1 || o.refactor_micro_rows < -1 ||
-      o.refactor_micro_rows > 0 || o.debug_schedule > 1 ||
+      o.refactor_micro_rows > 0 || o.debug_schedule > 1 || o.debug_timeline < 0 ||
+      o.debug_timeline > 1 ||
       !(o.pivot_perturb_rel >= 0.0 && o.pivot_perturb_rel < 1.0))
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
@@ -1372,6 +1374,14 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   h->ref_fl = nullptr;
   h->ref_flat = nullptr;
   h->ref_rmeta = nullptr;
+  h->tl = nullptr;
+  if (h->opt.debug_timeline == 1) {
+    if ((ks = dalloc(h, &h->tl, (size_t)3 * n)) != KKT_OK) {
+      free_device(h);
+      return ks;
+    }
+    HIP_CHECK(h, hipMemset(h->tl, 0, (size_t)3 * n * sizeof(long long)));
+  }
   if (h->syncfree && h->opt.refactor_map >= 0) {
     std::vector<int32_t> moff(A.lu_col.size(), 0);
     int64_t tot = 0;
@@ -1916,7 +1926,7 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
                                   h->ref_rmeta, h->ref_map, h->luA, h->ref_fl,
                                   h->ref_cmicro ? h->ref_cmicro + h->band_chunk_lo[b] : nullptr,
                                   h->opt.refactor_waves_per_cu, h->st, h->opt.pivot_perturb_rel,
-                                  s))
+                                  s, h->ref_order, h->tl))
           return fail(h, KKT_ERR_DEVICE, "short-row refactorization not launchable");
       } else if (h->light && h->ref_map && h->luA && h->ref_pbnd && h->ref_dlc &&
                  h->opt.refactor_long_rows == 0 && (size_t)h->band_cap[b] * 8 <= 64 * 1024) {
@@ -1924,7 +1934,7 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
                                 h->band_nchunks[b], b, h->band_cap[b], h->ss, &h->st->stall,
                                 h->tail_c0, h->ref_dlc, h->ref_moff, h->ref_map, h->luA,
                                 h->ref_pbnd, h->opt.refactor_waves_per_cu, h->st,
-                                h->opt.pivot_perturb_rel, s))
+                                h->opt.pivot_perturb_rel, s, h->tl))
           return fail(h, KKT_ERR_DEVICE, "long-row refactorization not launchable");
       } else if (!launch_refactor_syncfree(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
                                     h->band_nchunks[b], b, h->band_cap[b], fa, h->ready_ref,
@@ -2268,6 +2278,40 @@ kkt_status kkt_get_info(kkt_handle h, kkt_info* out) {
       }
   out->solve_block_levels[0] = h->use_sn ? h->chs_levels[0] : 0;
   out->solve_block_levels[1] = h->use_sn ? h->chs_levels[1] : 0;
+  return KKT_OK;
+}
+
+kkt_status kkt_debug_timeline(kkt_handle h, int64_t* out) {
+  if (!h || !out) return KKT_ERR_INVALID_ARG;
+  if (!h->analyzed || !h->tl)
+    return fail(h, KKT_ERR_STATE, "no timeline (create the handle with debug_timeline = 1)");
+  HIP_CHECK(h, hipSetDevice(h->opt.device));
+  HIP_CHECK(h, hipDeviceSynchronize());
+  const int32_t n = h->an.n;
+  std::vector<long long> raw((size_t)3 * n);
+  HIP_CHECK(h, hipMemcpy(raw.data(), h->tl, raw.size() * sizeof(long long),
+                         hipMemcpyDeviceToHost));
+  int khz = 0;
+  HIP_CHECK(h, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->opt.device));
+  if (khz <= 0) return fail(h, KKT_ERR_DEVICE, "no wall-clock rate");
+  const long long mask = (1ll << 62) - 1;
+  long long t0 = -1;
+  for (int32_t i = 0; i < n; i++)
+    if (raw[3 * (size_t)i + 2] != 0 && (t0 < 0 || raw[3 * (size_t)i] < t0)) t0 = raw[3 * (size_t)i];
+  const double ns = 1e6 / khz;  // nanoseconds per tick
+  for (int32_t i = 0; i < n; i++) {
+    const long long e = raw[3 * (size_t)i + 2];
+    int64_t* o = out + 4 * (size_t)i;
+    if (e == 0) {
+      o[0] = o[1] = o[2] = -1;
+      o[3] = 0;
+      continue;
+    }
+    o[0] = (int64_t)((raw[3 * (size_t)i] - t0) * ns);
+    o[1] = (int64_t)((raw[3 * (size_t)i + 1] - t0) * ns);
+    o[2] = (int64_t)(((e & mask) - t0) * ns);
+    o[3] = (int64_t)((unsigned long long)e >> 62);
+  }
   return KKT_OK;
 }
 

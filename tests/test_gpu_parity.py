@@ -981,3 +981,42 @@ def test_batch_autotuner_picks_working_knobs(tmp_path):
         assert eta(pat.scipy(v), x[n0:n1], b) <= 1e-12, t
     again, t2 = autotune.autotune_batch(patterns, inst_pattern, vals, dev(rhs), cache_path=cache)
     assert again == best and t2 == {}
+
+
+def test_row_timeline_records_every_band_row():
+    # debug_timeline: every row the two band kernels take is stamped, its
+    # start precedes its end, no row ends before an input it read, and the
+    # factors are the oracle's as without the recording
+    from paper_2306_14337_amd import timeline
+
+    pat, seq = kktgen.make_sequence(2000, 104, 2)
+    s = binding.KKTSolver(debug_timeline=1)
+    s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
+    vals, _ = seq[1]
+    s.refactor(dev(vals))
+    tl = s.debug_timeline()
+    ora = oracle.OracleLU(pat.n, pat.rowptr, pat.colind, seq[0][0], tau=1e-10)
+    ora.refactor(vals)
+    assert_factors_equal(s.lu()[2], oracle_csr_values(ora))
+    rp, ci, _ = s.lu(values=False)
+    c0 = pat.n - int(s.info().dense_tail)
+    rec = tl[:, 3] > 0
+    rows = np.repeat(np.arange(pat.n), np.diff(rp))
+    # rows with a pivot before the dense block go through a band kernel
+    has_piv = np.zeros(pat.n, bool)
+    has_piv[rows[(ci < rows) & (ci < c0)]] = True
+    print(f"  recorded {rec.sum()} rows, kinds {np.bincount(tl[:, 3], minlength=4)}", flush=True)
+    assert np.array_equal(rec, has_piv)
+    assert set(np.unique(tl[rec, 3])) <= {1, 2, 3}
+    assert (tl[rec, 0] <= tl[rec, 1]).all() and (tl[rec, 1] <= tl[rec, 2]).all()
+    # causality: a recorded input ended before the row did (2 us of clock slack)
+    dep = (ci < rows) & rec[rows] & rec[np.minimum(ci, pat.n - 1)] & (ci < c0)
+    assert (tl[rows[dep], 2] >= tl[ci[dep], 2] - 2000).all()
+    chain = timeline.critical_chain(tl, rp, ci)
+    assert len(chain) >= 2 and tl[chain[-1], 2] == tl[rec, 2].max()
+    print(timeline.summary(tl, rp, ci, c0), flush=True)
+    s.close()
+    with pytest.raises(binding.KKTError):
+        plain = binding.KKTSolver()
+        plain.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
+        plain.debug_timeline()
