@@ -342,6 +342,36 @@ def bench_batched(torch, binding, kktgen, steps=5, seed=104, n_a=128, n_b=128, B
     etas = s.batch_eta()
     assert float(etas.max()) <= 1e-12, f"batched accuracy gate failed: eta {etas.max():.3e}"
     rep = s.report()
+    # the same batch with the shared-pattern instances in one shared handle (one
+    # analysis, index structures held once) and the own-pattern instances in a
+    # block-diagonal handle: two captured graphs replayed back to back on one stream
+    opts = tuned.get("options", {})
+    pa = ga[0][0]
+    sa = binding.KKTSolver(**opts)
+    t0 = time.perf_counter()
+    sa.analyze_shared(pa.n, pa.rowptr, pa.colind, ga[0][1], n_a)
+    sb = binding.KKTSolver(**opts)
+    sb.analyze_batch(patterns[1:], list(range(n_b)))
+    t_an2 = time.perf_counter() - t0
+    na_v, na_b = n_a * pa.nnz, n_a * pa.n
+    x2 = torch.empty_like(bbuf)
+    sa.graph_capture(vbuf[:na_v], bbuf[:na_b], x2[:na_b], stream)
+    sb.graph_capture(vbuf[na_v:], bbuf[na_b:], x2[na_b:], stream)
+    sa.graph_launch(stream)
+    sb.graph_launch(stream)
+    stream.synchronize()
+    ev2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev2[0].record(stream)
+    for _ in range(steps):
+        sa.graph_launch(stream)
+        sb.graph_launch(stream)
+    ev2[1].record(stream)
+    stream.synchronize()
+    t_shared = ev2[0].elapsed_time(ev2[1]) / steps * 1e-3
+    etas2 = np.concatenate([sa.batch_eta(), sb.batch_eta()])
+    assert float(etas2.max()) <= 1e-12, f"shared-pattern batch accuracy gate failed: {etas2.max():.3e}"
+    sa_bytes = sa.info().device_bytes
+    del sa, sb
     # algorithmic bytes of one batch step: values and vectors per instance,
     # index arrays once per distinct pattern (section 8(d) accounting)
     rp, _, _ = s.lu(values=False)
@@ -392,6 +422,7 @@ def bench_batched(torch, binding, kktgen, steps=5, seed=104, n_a=128, n_b=128, B
     assert max(loop_etas) <= 1e-12, "loop accuracy gate failed"
     bytes_step = b_vals + b_idx
     achieved = bytes_step / t_batch_ev / 1e9
+    achieved2 = bytes_step / t_shared / 1e9
     return {"workload": f"batched, {n_a} instances sharing one B={B_a} pattern + {n_b} instances "
                         f"with own B~U[500,5000], one captured graph per batch step "
                         f"(refactor + solve + device-checked refinement)",
@@ -404,6 +435,15 @@ def bench_batched(torch, binding, kktgen, steps=5, seed=104, n_a=128, n_b=128, B
                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                          "bytes_per_batch_step": bytes_step,
                          "kernel": "one replay of the batch graph (all its kernels)"},
+            "shared_pattern": {
+                "layout": f"{n_a} shared-pattern instances in one kkt_analyze_shared handle, "
+                          f"{n_b} own-pattern instances block-diagonal; two graphs per batch step",
+                "ms_per_batch_events": t_shared * 1e3, "inst_per_s": count / t_shared,
+                "eta_max": float(etas2.max()), "analyze_s": t_an2,
+                "shared_handle_device_bytes": int(sa_bytes),
+                "roofline": {"bound": "hbm", "achieved": achieved2, "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": achieved2 / HBM_PEAK_GBS,
+                             "bytes_per_batch_step": bytes_step}},
             "autotune": tuned or None, "generate_s": t_gen, "analyze_s": t_an,
             "cpu_baseline": cpu_baseline_batched(insts, patterns) if with_cpu_baseline else None}
 

@@ -303,6 +303,26 @@ kkt_status kkt_analyze_batch(kkt_handle h, int32_t npat, const int32_t *n, const
                              const int64_t *const *rowptr, const int32_t *const *colind,
                              const double *const *values0, int32_t count,
                              const int32_t *inst_pattern);
+/* Batch of count instances of ONE pattern (n, nnz, rowptr, colind) sharing a
+ * single analysis: the ordering and pivot sequence come from values0 (the
+ * refactorization premise of Sections 4 and 5.1), and every index structure
+ * and schedule is held once on the device while each instance has its own
+ * values and vectors.  The refactorization and solve launches hand out each
+ * chunk of the shared schedule once per instance.  Afterwards the handle works
+ * as a block-diagonal batch of count identical patterns: kkt_refactor takes
+ * count x nnz values back to back, kkt_solve / kkt_graph_* take count x n
+ * right-hand sides back to back (one right-hand side per instance), eta is
+ * judged per instance (kkt_batch_eta), and kkt_get_lu / kkt_get_perm /
+ * kkt_get_info / kkt_batch_layout answer in that block-diagonal form.  Needs
+ * the default dependency-driven kernels (matching, level-synchronous
+ * schedules, the fence protocol, the kernel-variant switches, Jacobi sweeps and
+ * refine_sync = 1 are rejected with INVALID_ARG, as is a pattern those kernels
+ * cannot take); kkt_grad_values and kkt_solve_noalloc return STATE.  Errors
+ * otherwise as kkt_analyze, plus TOO_LARGE when the batch's totals exceed the
+ * int32 index range. */
+kkt_status kkt_analyze_shared(kkt_handle h, int32_t n, int64_t nnz, const int64_t *rowptr,
+                              const int32_t *colind, const double *values0, int32_t count);
+
 /* Instance offsets of a batch: row_offset[count+1] into vectors,
  * nnz_offset[count+1] into the concatenated values (either may be NULL). */
 kkt_status kkt_batch_layout(kkt_handle h, int64_t *row_offset, int64_t *nnz_offset);

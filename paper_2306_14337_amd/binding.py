@@ -38,7 +38,7 @@ EXPORTS = [
     "kkt_analysis_perm", "kkt_analysis_lu", "kkt_analysis_levels", "kkt_analysis_destroy",
     "kkt_analyze_batch", "kkt_batch_layout", "kkt_batch_eta", "kkt_graph_capture",
     "kkt_graph_launch", "kkt_reanalyze", "kkt_solve_noalloc", "kkt_get_scaling",
-    "kkt_analysis_scaling", "kkt_debug_timeline",
+    "kkt_analysis_scaling", "kkt_debug_timeline", "kkt_analyze_shared",
 ]
 
 
@@ -121,6 +121,7 @@ def lib():
         L.kkt_analysis_destroy.argtypes = [P]
         L.kkt_analysis_destroy.restype = None
         L.kkt_analyze_batch.argtypes = [P, C.c_int32, P, P, P, P, P, C.c_int32, P]
+        L.kkt_analyze_shared.argtypes = [P, C.c_int32, C.c_int64, P, P, P, C.c_int32]
         L.kkt_batch_layout.argtypes = [P, P, P]
         L.kkt_batch_eta.argtypes = [P, P]
         L.kkt_graph_capture.argtypes = [P, P, P, P, P]
@@ -306,6 +307,23 @@ class KKTSolver:
                                      len(ip), _np_ptr(ip))
         self._check(st)
         self.count = len(ip)
+        ro = np.empty(self.count + 1, np.int64)
+        no = np.empty(self.count + 1, np.int64)
+        self._check(lib().kkt_batch_layout(self._h, _np_ptr(ro), _np_ptr(no)))
+        self.row_offset, self.nnz_offset = ro, no
+        self.n = int(ro[-1])
+        self.nnz = int(no[-1])
+        return st
+
+    def analyze_shared(self, n, rowptr, colind, values0, count) -> int:
+        """count instances of one pattern sharing one analysis and one copy of
+        every index structure (values and vectors per instance, back to
+        back; the handle then answers as a block-diagonal batch)."""
+        rp, ci, v = _csr_host(rowptr, colind, values0)
+        st = lib().kkt_analyze_shared(self._h, int(n), int(rp[-1]), _np_ptr(rp), _np_ptr(ci),
+                                      _np_ptr(v), int(count))
+        self._check(st)
+        self.count = int(count)
         ro = np.empty(self.count + 1, np.int64)
         no = np.empty(self.count + 1, np.int64)
         self._check(lib().kkt_batch_layout(self._h, _np_ptr(ro), _np_ptr(no)))

@@ -7,6 +7,16 @@
 
 namespace kktlu {
 
+// Instances of one pattern that share every index structure (a shared-pattern
+// batch): instance t's rows are t n1 .. t n1 + n1 - 1 of the batch vectors, its
+// A values start at t a1 and its factor values at t f1; count = 1 otherwise.
+struct Inst {
+  int count = 1;
+  int n1 = 0;
+  int a1 = 0, f1 = 0;  // the batch's totals stay below 2^31 (checked at analysis)
+};
+
+
 // Refactorization statistics accumulated on the device (reset per refactor).
 struct DevStats {
   unsigned long long min_piv;  // bits of min |u_kk| (non-negative doubles order like uint64)
@@ -90,7 +100,7 @@ void launch_fg_begin(FgState* fs, int reset_summary, hipStream_t s);
 void launch_fg_resid(int n, int ncols, const int* ptr, const int* idx, const int* pos,
                      const double* aval, const double* b, const double* x, double* r,
                      const FgBufs& fb, const DevStats* st, int use_anorm1, int it_now, int first,
-                     int batch, const FgParams& p, hipStream_t s);
+                     int batch, const FgParams& p, hipStream_t s, Inst in = Inst());
 void launch_fg_check_batch(int count, const double* inst, const FgBufs& fb, const DevStats* st,
                            int it_now, int first, const FgParams& p, hipStream_t s);
 // start of an Arnoldi cycle: x = xt if copy, beta = ||r||, g, v0 = r / beta
@@ -99,7 +109,7 @@ void launch_fg_restart(int n, int ncols, int m, const double* r, const double* x
 // step j: w = op(A) z_j, h = V^T w; basis vector q of column c at V + (q * ncols + c) * n
 void launch_fg_arnoldi(int n, int ncols, int j, const int* ptr, const int* idx, const int* pos,
                        const double* aval, const double* Zj, const double* V, double* w,
-                       const FgBufs& fb, hipStream_t s);
+                       const FgBufs& fb, hipStream_t s, Inst in = Inst());
 // pass 0: w -= V h, h2 = V^T w; pass 1: w -= V h2, ||w||, Givens update, y
 void launch_fg_cgs(int pass, int n, int ncols, int j, int m, const double* V, double* w,
                    const FgBufs& fb, hipStream_t s);
@@ -253,7 +263,7 @@ bool launch_refactor_wg(const LUView& lu, const int* order, const int* cstart, i
                         int band, int cap, SyncState* ss, int* stall, int c0, const int* dlc,
                         const int* moff, const unsigned short* map, const double* luA,
                         const int2* pbnd, int max_waves_per_cu, DevStats* st, double perturb_rel,
-                        hipStream_t s, long long* tl = nullptr);
+                        hipStream_t s, long long* tl = nullptr, Inst in = Inst());
 
 // A short-row band: one wave per row, every row of the band at most 256
 // entries, no row of the dense block.  fl[q] for the
@@ -272,7 +282,7 @@ bool launch_refactor_flat(const LUView& lu, const int* cstart, int nchunks, int 
                           const unsigned short* map, const double* luA, const int2* fl,
                           const unsigned char* cmicro, int max_waves_per_cu, DevStats* st,
                           double perturb_rel, hipStream_t s, const int* order = nullptr,
-                          long long* tl = nullptr);
+                          long long* tl = nullptr, Inst in = Inst());
 // tl (debug): per-row timeline of the two band kernels, 3 wall-clock values per
 // row (start, last poll that found an input missing, end | kind << 62); order
 // (the bands' row order) is read only when tl is set
@@ -326,7 +336,8 @@ constexpr int SN_MAX_RHS = 8;
 void launch_trisolve_sn(int mode, int nr, const LUView& lu, const SnSched& sn, const int* tptr,
                         const int* trow, const int* tpos, const double* c, double* y,
                         SyncState* ss, int slot, int* stall, hipStream_t s,
-                        const int* xend = nullptr, const double* pre = nullptr);
+                        const int* xend = nullptr, const double* pre = nullptr,
+                        Inst in = Inst());
 // pre[i] = sum over q in [xend[i], rowptr[i + 1]) of val[q] * y[col[q]] for
 // the nu rows urows (the U rows' terms in the dense block's columns)
 void launch_udense_pre(int nu, const int* urows, const int* xend, const LUView& lu, const double* y,
@@ -362,7 +373,7 @@ void launch_gather_sentinel_mr(int n, int nr, const int* perm, const double* sca
                                double* c,
                                double* y, double* z, SyncState* ss, int mask, hipStream_t s,
                                const unsigned char* triv = nullptr, const int* diag = nullptr,
-                               const double* val = nullptr, int div = 0);
+                               const double* val = nullptr, int div = 0, long long f1 = 0);
 // x[r][perm[i]] = z[r][i]
 void launch_scatter_mr(int n, int nr, const int* perm, const double* scale, const double* z, double* x,
                        hipStream_t s);
@@ -384,7 +395,7 @@ void launch_fill_sentinel(double* p, long long count, hipStream_t s);
 // factor rows without pivots: val = staged A row, ready = current epoch
 void launch_refactor_trivial(const LUView& lu, const int* rows, int nrows, const double* aval,
                              int* ready, const SyncState* ss, hipStream_t s, const double* luA,
-                             int c0, DevStats* st, double perturb_rel);
+                             int c0, DevStats* st, double perturb_rel, Inst in = Inst());
 // zero the tickets and advance the epochs of the slots in mask (bit k = slot k)
 void launch_sync_prep(SyncState* ss, int mask, hipStream_t s);
 // y[i] = x[perm[i]] and, if ss != nullptr, the sync_prep of mask (fused)
@@ -394,7 +405,8 @@ void launch_gather_prep(int n, const int* perm, const double* scale, const doubl
 
 // pivot statistics (min/max |u_kk|, tiny test against tiny_rel * ||A||_inf,
 // max |u_ij| over U)
-void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStream_t s);
+void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStream_t s,
+                        Inst in = Inst());
 
 // A copy + ||A||_inf (and, if ss != nullptr, the sync_prep of slot 0; if
 // rowabs != nullptr, every row's absolute sum; if luA != nullptr, the values
@@ -408,10 +420,10 @@ void launch_copy_anorm(int n, const int* arow, const int* acol, const double* sr
                        DevStats* st, hipStream_t s, SyncState* ss = nullptr,
                        double* rowabs = nullptr, const int* a2lu = nullptr,
                        double* luA = nullptr, double* red = nullptr, int fnorm = 1,
-                       const double* ascale = nullptr, double* avs = nullptr);
+                       const double* ascale = nullptr, double* avs = nullptr, Inst in = Inst());
 // ||A||_1 through the column view (and every column's absolute sum)
 void launch_anorm1(int n, const int* cptr, const int* cpos, const double* aval, DevStats* st,
-                   hipStream_t s, double* colabs = nullptr);
+                   hipStream_t s, double* colabs = nullptr, Inst in = Inst());
 // per-instance maxima of a block-diagonal batch, SEG_SLICES partial results
 // per instance: out[3 (t SEG_SLICES + s) + 0..2] = max matabs, max |r|, max |x|
 // over slice s of rows [row_off[t], row_off[t+1]) (out holds

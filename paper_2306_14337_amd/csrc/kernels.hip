@@ -324,20 +324,24 @@ __global__ __launch_bounds__(256) void k_refactor_trivial(int nrows, const int* 
                                                           const int* __restrict__ rowptr,
                                                           const int* __restrict__ src,
                                                           const double* __restrict__ aval,
-                                                          double* __restrict__ val, int* ready,
+                                                          double* __restrict__ val0, int* ready,
                                                           const SyncState* ss,
-                                                          const double* __restrict__ luA,
+                                                          const double* __restrict__ luA0,
                                                           const int* __restrict__ diag, int c0,
-                                                          DevStats* st, double prel) {
+                                                          DevStats* st, double prel, Inst in) {
   const int lane = threadIdx.x % WAVE, g = lane / RG_TRIV, gl = lane % RG_TRIV;
   const int epoch = ss->epoch[0];
   const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm_f) : 0.0;
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = gridDim.x * blockDim.x / WAVE;
-  for (int r0 = wid * (WAVE / RG_TRIV); r0 < nrows; r0 += nw * (WAVE / RG_TRIV)) {
-    const int r = r0 + g;
-    if (r >= nrows) continue;
-    const int i = rows[r];
+  const int total = nrows * in.count;  // the rows of every instance
+  for (int r0 = wid * (WAVE / RG_TRIV); r0 < total; r0 += nw * (WAVE / RG_TRIV)) {
+    const int rg = r0 + g;
+    if (rg >= total) continue;
+    const int ti = rg / nrows;
+    const int i = rows[rg - ti * nrows];
+    double* val = val0 + ti * in.f1;
+    const double* luA = luA0 ? luA0 + ti * in.f1 : nullptr;
     const int dq = i < c0 ? diag[i] : -1;  // pivots of the dense block: there
     for (int q = rowptr[i] + gl; q < rowptr[i + 1]; q += RG_TRIV) {
       double v;
@@ -345,7 +349,7 @@ __global__ __launch_bounds__(256) void k_refactor_trivial(int nrows, const int* 
         v = luA[q];
       } else {
         const int sq = src[q];
-        v = sq >= 0 ? aval[sq] : 0.0;
+        v = sq >= 0 ? aval[sq + ti * in.a1] : 0.0;
       }
       if (q == dq && fabs(v) < thr) {
         v = perturb_pivot(v, thr);
@@ -1306,17 +1310,21 @@ __global__ void k_dlu_reset(int* ver, int count, SyncState* ss) {
 // j - base (modes 0, 2) or base - j (modes 1, 3).
 // ---------------------------------------------------------------------------
 // NR >= nr right-hand sides (column r at c + r * ld, y + r * ld; ld = n + 1
-// for several, unused for one): every lane keeps nr sums.
-template <int MODE, int NR>
+// for several, unused for one): every lane keeps nr sums.  Instances of a
+// shared-pattern batch (in.count > 1, one right-hand side each): ticket =
+// chunk x instances + instance; instance t's factor values start at t in.f1,
+// its c and y at t (n + 1).
+template <int MODE, int NR, bool SH>
 __global__ __launch_bounds__(256) void k_trisolve_sn(const int* __restrict__ gate, 
     int n, int nr, int ld, int nchunks, const int* __restrict__ ch_start,
     const int* __restrict__ ch_meta, const int* __restrict__ ch_base, const int* __restrict__ rows,
     const int* __restrict__ split, const int* __restrict__ rowptr, const int* __restrict__ col,
     const int* __restrict__ diag, const int* __restrict__ tptr, const int* __restrict__ trow,
-    const int* __restrict__ tpos, const double* __restrict__ val, const double* __restrict__ c,
-    double* y, SyncState* ss, int slot, int nstreams, int* stall, const int* __restrict__ xend,
-    const double* __restrict__ pre) {
+    const int* __restrict__ tpos, const double* __restrict__ val0, const double* __restrict__ c0,
+    double* y0, SyncState* ss, int slot, int nstreams, int* stall, const int* __restrict__ xend,
+    const double* __restrict__ pre, Inst in) {
   KKT_GATE(gate);
+  if constexpr (!SH) in = Inst();  // one instance: the decode below folds away
   // the block's strictly lower triangle, packed by rows: entry (g, h), h < g,
   // at g (g - 1) / 2 + h (half the LDS of a square, so all eight workgroups
   // per CU fit)
@@ -1325,8 +1333,12 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(const int* __restrict__ gat
   const int lane = threadIdx.x % WAVE;
   double* tri = tri_all[threadIdx.x / WAVE];
   for (;;) {
-    const int tk = next_chunk(ss->slot_stream[slot], nstreams, lane);
-    if (tk >= nchunks) break;
+    const int tk0 = next_chunk(ss->slot_stream[slot], nstreams, lane);
+    if (tk0 >= nchunks * in.count) break;
+    const int tk = tk0 / in.count, inst = tk0 - tk * in.count;
+    const double* val = val0 + (size_t)inst * in.f1;
+    const double* c = c0 + (size_t)inst * (n + 1);
+    double* y = y0 + (size_t)inst * (n + 1);
     const int meta = ch_meta[tk];
     const int k = meta & 0xff, lg = (meta >> 8) & 0xf;
     const bool chain = (meta >> 16) != 0;
@@ -1798,7 +1810,7 @@ __global__ void k_gather_sentinel_mr(const int* __restrict__ gate, int n, int nr
                                      SyncState* ss, int mask,
                                      const unsigned char* __restrict__ triv,
                                      const int* __restrict__ diag,
-                                     const double* __restrict__ val, int div) {
+                                     const double* __restrict__ val, int div, long long f1) {
   KKT_GATE(gate);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
@@ -1808,7 +1820,9 @@ __global__ void k_gather_sentinel_mr(const int* __restrict__ gate, int n, int nr
     const double ci = scale ? xi * scale[i] : xi;
     c[o] = ci;
     const double sent = __longlong_as_double((long long)SENTINEL);
-    y[o] = (triv && triv[i]) ? (div ? ci / val[diag[i]] : ci) : sent;
+    // column r's factors at r f1 (the instances of a shared-pattern batch;
+    // f1 = 0 for right-hand sides of one system)
+    y[o] = (triv && triv[i]) ? (div ? ci / val[r * f1 + diag[i]] : ci) : sent;
     z[o] = sent;
   }
   if (ss && i == 0 && r == 0) sync_prep(ss, mask);
@@ -1868,6 +1882,11 @@ __global__ void k_reset_stats(DevStats* st, int what) {
 // ---------------------------------------------------------------------------
 constexpr int RG = 8;  // lanes per row
 
+// instance of batch row r in a shared-pattern batch (0 otherwise)
+__device__ __forceinline__ int inst_of(int r, const Inst& in) {
+  return in.count > 1 ? r / in.n1 : 0;
+}
+
 // max that propagates NaN (fmax would drop it and hide a broken solution)
 __device__ __forceinline__ double nanmax(double a, double b) {
   if (a != a) return a;
@@ -1906,8 +1925,8 @@ __device__ __forceinline__ double block_nanmax(double v, double* red) {
 // 8 lanes per row; lane 0 of a row group also takes the diagonal.
 __global__ __launch_bounds__(256) void k_pivot_stats(int n, const int* __restrict__ rowptr,
                                                      const int* __restrict__ diag,
-                                                     const double* __restrict__ val, DevStats* st,
-                                                     double tiny_rel) {
+                                                     const double* __restrict__ val0, DevStats* st,
+                                                     double tiny_rel, Inst in) {
   const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = gridDim.x * blockDim.x / WAVE;
@@ -1915,8 +1934,11 @@ __global__ __launch_bounds__(256) void k_pivot_stats(int n, const int* __restric
   double mn = __builtin_huge_val(), mx = 0.0, um = 0.0;
   int tiny = 0;
   for (int r0 = wid * (WAVE / RG); r0 < n; r0 += nw * (WAVE / RG)) {
-    const int i = r0 + g;
-    if (i < n) {
+    const int ig = r0 + g;
+    if (ig < n) {
+      const int ti = inst_of(ig, in);
+      const int i = ig - ti * in.n1;
+      const double* val = val0 + ti * in.f1;
       const int d = diag[i], e = rowptr[i + 1];
       for (int t = d + gl; t < e; t += RG) {
         const double a = fabs(val[t]);
@@ -2005,6 +2027,7 @@ __global__ __launch_bounds__(256) void k_seg_stats(const int* __restrict__ gate,
 // workgroup).  ascale (with avs): the factored matrix is the matched and
 // scaled one, a_p * ascale[p] (exact powers of two) goes to avs and luA, and
 // its row sums give anorm_f.
+template <bool SH>
 __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict__ arow,
                                                     const double* __restrict__ src, double* dst,
                                                     DevStats* st, SyncState* ss,
@@ -2013,7 +2036,8 @@ __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict
                                                     double* __restrict__ luA,
                                                     double* __restrict__ red_out, int fnorm,
                                                     const double* __restrict__ ascale,
-                                                    double* __restrict__ avs) {
+                                                    double* __restrict__ avs, Inst in) {
+  if constexpr (!SH) in = Inst();  // one instance: the decode below folds away
   const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = gridDim.x * blockDim.x / WAVE;
@@ -2023,15 +2047,23 @@ __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict
   constexpr int U = 4;
   const int stride = nw * (WAVE / RG);
   for (int r0 = wid * (WAVE / RG); r0 < n; r0 += U * stride) {
-    int ii[U], p0[U], pe[U];
+    // rows of the pattern's CSR: local entries p, A position p + ao, factor
+    // positions a2lu[p] + fo (instance offsets of a shared-pattern batch)
+    int ii[U], p0[U], pe[U], ao[U], fo[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
       ii[u] = r0 + u * stride + g;
       p0[u] = 0;
       pe[u] = 0;
+      ao[u] = 0;
+      fo[u] = 0;
       if (ii[u] < n) {
-        p0[u] = arow[ii[u]] + gl;
-        pe[u] = arow[ii[u] + 1];
+        const int t = inst_of(ii[u], in);
+        const int il = ii[u] - t * in.n1;
+        ao[u] = t * in.a1;
+        fo[u] = t * in.f1;
+        p0[u] = arow[il] + gl;
+        pe[u] = arow[il + 1];
       }
     }
     double v0[U];
@@ -2041,15 +2073,15 @@ __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict
       v0[u] = 0.0;
       q0[u] = 0;
       if (p0[u] < pe[u]) {
-        v0[u] = src[p0[u]];
-        if (luA) q0[u] = a2lu[p0[u]];
+        v0[u] = src[p0[u] + ao[u]];
+        if (luA) q0[u] = a2lu[p0[u]] + fo[u];
       }
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
       double s = 0.0, sf = 0.0;
       if (p0[u] < pe[u]) {
-        dst[p0[u]] = v0[u];
+        dst[p0[u] + ao[u]] = v0[u];
         const double w = ascale ? v0[u] * ascale[p0[u]] : v0[u];
         if (ascale) avs[p0[u]] = w;
         if (luA) luA[q0[u]] = w;
@@ -2057,11 +2089,11 @@ __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict
         sf = fabs(w);
       }
       for (int p = p0[u] + RG; p < pe[u]; p += RG) {
-        const double v = src[p];
-        dst[p] = v;
+        const double v = src[p + ao[u]];
+        dst[p + ao[u]] = v;
         const double w = ascale ? v * ascale[p] : v;
         if (ascale) avs[p] = w;
-        if (luA) luA[a2lu[p]] = w;
+        if (luA) luA[a2lu[p] + fo[u]] = w;
         s += fabs(v);
         sf += fabs(w);
       }
@@ -2097,7 +2129,7 @@ __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict
 __global__ __launch_bounds__(256) void k_anorm1(int n, const int* __restrict__ cptr,
                                                 const int* __restrict__ cpos,
                                                 const double* __restrict__ aval, DevStats* st,
-                                                double* __restrict__ colabs) {
+                                                double* __restrict__ colabs, Inst in) {
   const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = gridDim.x * blockDim.x / WAVE;
@@ -2105,8 +2137,12 @@ __global__ __launch_bounds__(256) void k_anorm1(int n, const int* __restrict__ c
   for (int r0 = wid * (WAVE / RG); r0 < n; r0 += nw * (WAVE / RG)) {
     const int j = r0 + g;
     double s = 0.0;
-    if (j < n)
-      for (int t = cptr[j] + gl; t < cptr[j + 1]; t += RG) s += fabs(aval[cpos[t]]);
+    if (j < n) {
+      const int t = inst_of(j, in);
+      const int jl = j - t * in.n1;
+      const double* av = aval + t * in.a1;
+      for (int q = cptr[jl] + gl; q < cptr[jl + 1]; q += RG) s += fabs(av[cpos[q]]);
+    }
     s = group_sum(s);
     if (j < n) {
       m = nanmax(m, s);
@@ -2587,13 +2623,14 @@ __host__ __device__ constexpr int flat_area(int cap) {
   return 2 * cap > MICRO_LEN * WAVE ? 2 * cap : MICRO_LEN * WAVE;
 }
 
+template <bool TL>
 __device__ __forceinline__ void refactor_micro_row(int4 mt, int i, int lane, double* sa,
                                                    double* val, int* stall,
                                                    const unsigned short* __restrict__ map,
                                                    const double* __restrict__ luA,
                                                    const int2* __restrict__ fl, DevStats* st,
                                                    double thr, long long* tl) {
-  const long long tl0 = tl ? (long long)wall_clock64() : 0;
+  const long long tl0 = TL ? (long long)wall_clock64() : 0;
   // row start, length, pivots, update-map offset, list length
   const int rs = mt.x, len = mt.y & 0xffff, dl = mt.y >> 16, mb = mt.z, nl = mt.w;
   for (int k = 0; k < len; k++) sa[k * WAVE + lane] = luA[rs + k];
@@ -2640,7 +2677,7 @@ __device__ __forceinline__ void refactor_micro_row(int4 mt, int i, int lane, dou
 #pragma unroll
     for (int e = 0; e < MICRO_LIST; e++) miss = miss || (e < nl && is_sentinel(u[e]));
     if (!miss || !keep_waiting(&spins, stall)) break;
-    if (tl) tl1 = (long long)wall_clock64();
+    if constexpr (TL) tl1 = (long long)wall_clock64();
 #pragma unroll
     for (int t = 0; t < MICRO_PIV; t++)
       if (t < dl && is_sentinel(d[t])) {
@@ -2672,7 +2709,7 @@ __device__ __forceinline__ void refactor_micro_row(int4 mt, int i, int lane, dou
     }
   }
   for (int k = 0; k < len; k++) st_coh(val + rs + k, sa[k * WAVE + lane]);
-  if (tl) tl_record(tl, i, tl0, tl1, 1);
+  if constexpr (TL) tl_record(tl, i, tl0, tl1, 1);
 }
 
 // Rows of a short-row band (at most 256 entries each; no row of the dense
@@ -2697,13 +2734,14 @@ __device__ __forceinline__ void refactor_micro_row(int4 mt, int i, int lane, dou
 // pivot-diagonal poll (entries of pivots not finished yet read as the sentinel
 // and are polled again before use), its U addresses found from the staged list
 // bounds rather than from the map.
-template <int WPB>
+template <int WPB, bool TL, bool SH>
 __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
     const int* __restrict__ cstart, int nchunks, unsigned int* tickets, int nstreams,
-    double* val, int* stall, int cap, const int4* __restrict__ rmeta,
-    const unsigned short* __restrict__ map, const double* __restrict__ luA,
+    double* val0, int* stall, int cap, const int4* __restrict__ rmeta,
+    const unsigned short* __restrict__ map, const double* __restrict__ luA0,
     const int2* __restrict__ fl, const unsigned char* __restrict__ cmicro, DevStats* st,
-    double prel, const int* __restrict__ order, long long* tl) {
+    double prel, const int* __restrict__ order, long long* tl, Inst in) {
+  if constexpr (!SH) in = Inst();  // one instance: the decode below folds away
   extern __shared__ double smem_d[];
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   // LDS per wave, one area of flat_area(cap) doubles: values (cap doubles),
@@ -2714,14 +2752,19 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
   const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm_f) : 0.0;
   for (;;) {
     const int tk = next_chunk(tickets, nstreams, lane);
-    if (tk >= nchunks) break;
-    const int cs = cstart[tk], ce = cstart[tk + 1];
+    if (tk >= nchunks * in.count) break;
+    // ticket = chunk x instances + instance (every instance of a chunk before
+    // the next chunk: a topological order for each instance)
+    const int ch = tk / in.count, inst = tk - ch * in.count;
+    double* val = val0 + (size_t)inst * in.f1;
+    const double* luA = luA0 + (size_t)inst * in.f1;
+    const int cs = cstart[ch], ce = cstart[ch + 1];
     // the chunk's rows (at most 64), one per lane
     const int4 mt = cs + lane < ce ? rmeta[cs + lane] : make_int4(0, 0, 0, 0);
-    if (cmicro != nullptr && bcast0(cmicro[tk]) != 0u) {
+    if (cmicro != nullptr && bcast0(cmicro[ch]) != 0u) {
       wave_sync();  // the last row of a previous chunk is done with the area
       if (cs + lane < ce)
-        refactor_micro_row(mt, tl ? order[cs + lane] : 0, lane, sv, val, stall, map, luA, fl, st,
+        refactor_micro_row<TL>(mt, TL ? order[cs + lane] : 0, lane, sv, val, stall, map, luA, fl, st,
                            thr, tl);
       continue;
     }
@@ -2736,7 +2779,7 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
       for (int t = lane; t < len; t += WAVE) sv[t] = luA[rs + t];
       for (int t = lane; t <= dl; t += WAVE) sf[t] = fl[rs + t];
       wave_sync();
-      const long long tl0 = tl ? (long long)wall_clock64() : 0;
+      const long long tl0 = TL ? (long long)wall_clock64() : 0;
       long long tl1 = tl0;
       int ready_upto = 0, t0 = 0, spins = 0;
       double dv = 0.0;  // lane q: diagonal of pivot t0 + q
@@ -2795,7 +2838,7 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
             bool go = true;
             while (go && bcast0(is_sentinel(ld_coh(val + dpt)) ? 1u : 0u) != 0u)
               go = bcast0(keep_waiting(&spins, stall) ? 1u : 0u) != 0u;
-            if (tl) tl1 = (long long)wall_clock64();
+            if constexpr (TL) tl1 = (long long)wall_clock64();
             if (!go) {  // stalled: drain
               ready_upto = dl;
               t0 = t;
@@ -2811,7 +2854,7 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
 #pragma unroll
           for (int z = 0; z < 4; z++) {
             if ((tp[z] >> 8) == t) {
-              if (tl && is_sentinel(u[z])) tl1 = (long long)wall_clock64();
+              if (TL && is_sentinel(u[z])) tl1 = (long long)wall_clock64();
               while (is_sentinel(u[z]) && keep_waiting(&spins, stall))
                 u[z] = ld_coh(val + (wbeg + lane + z * WAVE + dt));
               const int p = tp[z] & 255;
@@ -2845,7 +2888,7 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
         wave_sync();
       }
       for (int t = lane; t < len; t += WAVE) st_coh(val + rs + t, sv[t]);
-      if (tl) {
+      if constexpr (TL) {
         long long t1 = tl1;  // the latest wait of any lane
         for (int off = WAVE / 2; off > 0; off >>= 1) {
           const long long o = __shfl_xor(t1, off, WAVE);
@@ -2872,14 +2915,15 @@ __global__ __launch_bounds__(WPB* WAVE) void k_refactor_flat(
 // pivot-row bounds and update-map offsets of its next 64 steps in registers,
 // one step per lane.  dlc[i]: pivots of row i in this phase (those before the
 // dense trailing block).
-template <int WPR, int DEPTH>
+template <int WPR, int DEPTH, bool TL, bool SH>
 __global__ __launch_bounds__(WPR* WAVE) void k_refactor_wg(
     const int* __restrict__ order, const int* __restrict__ cstart, int nchunks,
     unsigned int* tickets, int nstreams, const int* __restrict__ rowptr,
-    const int* __restrict__ dlc, double* val, int* stall, const int* __restrict__ moff,
-    const unsigned short* __restrict__ map, const double* __restrict__ luA,
+    const int* __restrict__ dlc, double* val0, int* stall, const int* __restrict__ moff,
+    const unsigned short* __restrict__ map, const double* __restrict__ luA0,
     const int2* __restrict__ pbnd, const int* __restrict__ diag, int c0, DevStats* st,
-    double prel, long long* tl) {
+    double prel, long long* tl, Inst in) {
+  if constexpr (!SH) in = Inst();  // one instance: the decode below folds away
   constexpr int R = 4;  // prefetched chunks of 64 U entries per pivot step
   constexpr int NT = WPR * WAVE;
   constexpr int AHEAD = WPR * DEPTH;
@@ -2902,11 +2946,14 @@ __global__ __launch_bounds__(WPR* WAVE) void k_refactor_wg(
       s_tk = tk;  // every lane of wave 0 writes the same value
     }
     __syncthreads();
-    const int tk = s_tk;
+    const int tk = __builtin_amdgcn_readfirstlane(s_tk);
     __syncthreads();  // read by every wave before the next fetch overwrites it
-    if (tk >= nchunks) break;
-    const int r_end = cstart[tk + 1];
-    for (int r = cstart[tk]; r < r_end; r++) {
+    if (tk >= nchunks * in.count) break;
+    const int ch = tk / in.count, inst = tk - ch * in.count;
+    double* val = val0 + (size_t)inst * in.f1;
+    const double* luA = luA0 + (size_t)inst * in.f1;
+    const int r_end = cstart[ch + 1];
+    for (int r = cstart[ch]; r < r_end; r++) {
       const int i = order[r];
       const int rs = rowptr[i], len = rowptr[i + 1] - rs;
       const int dl = dlc[i];
@@ -2949,7 +2996,7 @@ __global__ __launch_bounds__(WPR* WAVE) void k_refactor_wg(
 #pragma unroll
           for (int z = 0; z < R; z++) miss = miss || (b.p[z] >= 0 && is_sentinel(b.u[z]));
           if (__ballot(miss) == 0) break;
-          if (tl) tl1 = (long long)wall_clock64();
+          if constexpr (TL) tl1 = (long long)wall_clock64();
           if (bcast0(keep_waiting(&spins, stall) ? 1u : 0u) == 0u) break;
           if (is_sentinel(b.ukk)) b.ukk = ld_coh(val + b.kk.x);
 #pragma unroll
@@ -2991,7 +3038,7 @@ __global__ __launch_bounds__(WPR* WAVE) void k_refactor_wg(
       for (int d = 0; d < DEPTH; d++)
         if (wave + d * WPR < dl) load(buf[d], wave + d * WPR);
       __syncthreads();  // the row's values are staged
-      if (tl) tl0 = tl1 = (long long)wall_clock64();
+      if constexpr (TL) tl0 = tl1 = (long long)wall_clock64();
       for (int tb = 0; tb < dl; tb += AHEAD) {
 #pragma unroll
         for (int d = 0; d < DEPTH; d++) {
@@ -3018,7 +3065,7 @@ __global__ __launch_bounds__(WPR* WAVE) void k_refactor_wg(
         __syncthreads();
       }
       for (int t = threadIdx.x; t < len; t += NT) st_coh(val + rs + t, sv[t]);
-      if (tl && threadIdx.x == 0) tl_record(tl, i, tl0, tl1, 3);
+      if (TL && threadIdx.x == 0) tl_record(tl, i, tl0, tl1, 3);
       __syncthreads();  // the staging area is reused by the next row
     }
   }
@@ -3144,7 +3191,7 @@ __global__ __launch_bounds__(FG_T) void k_fg_resid(
     int n, const int* __restrict__ ptr, const int* __restrict__ idx, const int* __restrict__ pos,
     const double* __restrict__ aval, const double* __restrict__ b, const double* __restrict__ x,
     double* __restrict__ r, double* __restrict__ part, FgState* fs, const DevStats* st,
-    int use_anorm1, int ncols, int it_now, int first, FgParams p) {
+    int use_anorm1, int ncols, int it_now, int first, FgParams p, Inst in) {
   const int c = blockIdx.y;
   FgCol* col = &fs->col[c];
   if (!first && ld_flag(&col->stop)) return;
@@ -3160,14 +3207,23 @@ __global__ __launch_bounds__(FG_T) void k_fg_resid(
   for (int r0 = wid * (WAVE / RG); r0 < n; r0 += U * stride) {
     int ii[U], t0[U], te[U];
     double sacc[U], av[U], xv[U];
+    // a shared-pattern batch: the pattern's local entries, A values at
+    // + ao, the instance's x at + xo
+    int ao[U], xo[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
       ii[u] = r0 + u * stride + g;
       t0[u] = 0;
       te[u] = 0;
+      ao[u] = 0;
+      xo[u] = 0;
       if (ii[u] < n) {
-        t0[u] = ptr[ii[u]] + gl;
-        te[u] = ptr[ii[u] + 1];
+        const int ti = inst_of(ii[u], in);
+        const int il = ii[u] - ti * in.n1;
+        ao[u] = ti * in.a1;
+        xo[u] = ti * in.n1;
+        t0[u] = ptr[il] + gl;
+        te[u] = ptr[il + 1];
       }
     }
 #pragma unroll
@@ -3175,14 +3231,15 @@ __global__ __launch_bounds__(FG_T) void k_fg_resid(
       av[u] = 0.0;
       xv[u] = 0.0;
       if (t0[u] < te[u]) {
-        av[u] = aval[pos ? pos[t0[u]] : t0[u]];
-        xv[u] = xc[idx[t0[u]]];
+        av[u] = aval[(pos ? pos[t0[u]] : t0[u]) + ao[u]];
+        xv[u] = xc[idx[t0[u]] + xo[u]];
       }
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
       sacc[u] = av[u] * xv[u];
-      for (int t = t0[u] + RG; t < te[u]; t += RG) sacc[u] += aval[pos ? pos[t] : t] * xc[idx[t]];
+      for (int t = t0[u] + RG; t < te[u]; t += RG)
+        sacc[u] += aval[(pos ? pos[t] : t) + ao[u]] * xc[idx[t] + xo[u]];
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
@@ -3290,7 +3347,7 @@ __global__ __launch_bounds__(FG_T) void k_fg_arnoldi(
     int n, int g, int j, const int* __restrict__ ptr, const int* __restrict__ idx,
     const int* __restrict__ pos, const double* __restrict__ aval, const double* __restrict__ Zj,
     const double* __restrict__ V, double* __restrict__ w, double* __restrict__ part,
-    double* __restrict__ hbuf, FgState* fs) {
+    double* __restrict__ hbuf, FgState* fs, Inst in) {
   const int c = blockIdx.y;
   FgCol* col = &fs->col[c];
   if (ld_flag(&col->stop)) return;
@@ -3305,8 +3362,15 @@ __global__ __launch_bounds__(FG_T) void k_fg_arnoldi(
   for (int i0 = wid * (WAVE / RG); i0 < n; i0 += nw * (WAVE / RG)) {
     const int i = i0 + grp;
     double sacc = 0.0;
-    if (i < n)
-      for (int t = ptr[i] + gl; t < ptr[i + 1]; t += RG) sacc += aval[pos ? pos[t] : t] * zc[idx[t]];
+    if (i < n) {
+      // a shared-pattern batch: the pattern's local entries, the instance's
+      // A values and z
+      const int ti = inst_of(i, in);
+      const int il = i - ti * in.n1;
+      const double* av = aval + ti * in.a1;
+      const double* zt = zc + ti * in.n1;
+      for (int t = ptr[il] + gl; t < ptr[il + 1]; t += RG) sacc += av[pos ? pos[t] : t] * zt[idx[t]];
+    }
     const double wi = group_sum(sacc);
     if (i < n) {
       if (gl == 0) wc[i] = wi;
@@ -3502,9 +3566,15 @@ namespace {
 // refinement passes: elementwise grids (four elements per thread at least)
 // and row grids (eight lanes per row, four row groups per round)
 int fg_grid(int n) { return std::max(1, std::min(FG_BLOCKS, cdiv(n, FG_T * 4))); }
-// (the residual pass keeps two partial maxima per workgroup, so the partial
-// buffer of FG_BLOCKS x 32 per column holds FG_RESID_BLOCKS of them)
+// (the Arnoldi pass keeps FG_Q partial sums per workgroup and column: at most
+// FG_BLOCKS workgroups fill the partial buffer of FG_BLOCKS x 32 per column)
 int fg_rows_grid(int n) {
+  static_assert(FG_Q <= 32, "Arnoldi partials exceed their buffer");
+  return std::max(1, std::min(FG_BLOCKS, cdiv(n, (FG_T / WAVE) * (WAVE / RG) * 4)));
+}
+// the residual pass keeps two partial maxima per workgroup and column, so the
+// same buffer holds FG_RESID_BLOCKS workgroups of them
+int fg_resid_grid(int n) {
   static_assert(2 * FG_RESID_BLOCKS <= 32 * FG_BLOCKS, "residual partials exceed their buffer");
   return std::max(1, std::min(FG_RESID_BLOCKS, cdiv(n, (FG_T / WAVE) * (WAVE / RG) * 4)));
 }
@@ -3517,14 +3587,14 @@ void launch_fg_begin(FgState* fs, int reset_summary, hipStream_t s) {
 void launch_fg_resid(int n, int ncols, const int* ptr, const int* idx, const int* pos,
                      const double* aval, const double* b, const double* x, double* r,
                      const FgBufs& fb, const DevStats* st, int use_anorm1, int it_now, int first,
-                     int batch, const FgParams& p, hipStream_t s) {
-  const dim3 grid(fg_rows_grid(n), ncols);
+                     int batch, const FgParams& p, hipStream_t s, Inst in) {
+  const dim3 grid(fg_resid_grid(n), ncols);
   if (batch)
     hipLaunchKernelGGL(k_fg_resid<true>, grid, dim3(FG_T), 0, s, n, ptr, idx, pos, aval, b, x, r,
-                       fb.part, fb.fs, st, use_anorm1, ncols, it_now, first, p);
+                       fb.part, fb.fs, st, use_anorm1, ncols, it_now, first, p, in);
   else
     hipLaunchKernelGGL(k_fg_resid<false>, grid, dim3(FG_T), 0, s, n, ptr, idx, pos, aval, b, x, r,
-                       fb.part, fb.fs, st, use_anorm1, ncols, it_now, first, p);
+                       fb.part, fb.fs, st, use_anorm1, ncols, it_now, first, p, in);
 }
 
 void launch_fg_check_batch(int count, const double* inst, const FgBufs& fb, const DevStats* st,
@@ -3543,9 +3613,9 @@ void launch_fg_restart(int n, int ncols, int m, const double* r, const double* x
 
 void launch_fg_arnoldi(int n, int ncols, int j, const int* ptr, const int* idx, const int* pos,
                        const double* aval, const double* Zj, const double* V, double* w,
-                       const FgBufs& fb, hipStream_t s) {
+                       const FgBufs& fb, hipStream_t s, Inst in) {
   hipLaunchKernelGGL(k_fg_arnoldi, dim3(fg_rows_grid(n), ncols), dim3(FG_T), 0, s, n, ncols, j,
-                     ptr, idx, pos, aval, Zj, V, w, fb.part, fb.hbuf, fb.fs);
+                     ptr, idx, pos, aval, Zj, V, w, fb.part, fb.hbuf, fb.fs, in);
 }
 
 void launch_fg_cgs(int pass, int n, int ncols, int j, int m, const double* V, double* w,
@@ -3596,9 +3666,10 @@ void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxl
   }
 }
 
-void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStream_t s) {
-  hipLaunchKernelGGL(k_pivot_stats, dim3(rows_grid(lu.n)), dim3(256), 0, s, lu.n, lu.rowptr,
-                     lu.diag, lu.val, st, tiny_rel);
+void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStream_t s, Inst in) {
+  const int total = lu.n * in.count;
+  hipLaunchKernelGGL(k_pivot_stats, dim3(rows_grid(total)), dim3(256), 0, s, total, lu.rowptr,
+                     lu.diag, lu.val, st, tiny_rel, in);
 }
 
 // Row passes with a two-stage maximum (red != nullptr): a larger grid keeps
@@ -3611,10 +3682,12 @@ inline int rows_grid_red(int n) { return std::max(1, std::min(cdiv(n, 32), RED_B
 void launch_copy_anorm(int n, const int* arow, const int*, const double* src, double* dst,
                        DevStats* st, hipStream_t s, SyncState* ss, double* rowabs,
                        const int* a2lu, double* luA, double* red, int fnorm,
-                       const double* ascale, double* avs) {
-  const int nb = red ? rows_grid_red(n) : rows_grid(n);
-  hipLaunchKernelGGL(k_copy_anorm, dim3(nb), dim3(256), 0, s, n, arow, src, dst, st, ss, rowabs,
-                     a2lu, luA, red, fnorm, ascale, avs);
+                       const double* ascale, double* avs, Inst in) {
+  const int total = n * in.count;
+  const int nb = red ? rows_grid_red(total) : rows_grid(total);
+  hipLaunchKernelGGL(in.count > 1 ? k_copy_anorm<true> : k_copy_anorm<false>, dim3(nb), dim3(256),
+                     0, s, total, arow, src, dst, st, ss, rowabs, a2lu, luA, red, fnorm, ascale,
+                     avs, in);
   if (red)
     hipLaunchKernelGGL(k_red_max, dim3(1), dim3(1024), 0, s, (const double*)red, nb,
                        fnorm ? 2 : 1, &st->anorm, fnorm ? &st->anorm_f : &st->anorm);
@@ -3634,11 +3707,12 @@ void launch_fill_sentinel(double* p, long long count, hipStream_t s) {
 
 void launch_refactor_trivial(const LUView& lu, const int* rows, int nrows, const double* aval,
                              int* ready, const SyncState* ss, hipStream_t s, const double* luA,
-                             int c0, DevStats* st, double perturb_rel) {
+                             int c0, DevStats* st, double perturb_rel, Inst in) {
   if (nrows <= 0) return;
-  hipLaunchKernelGGL(k_refactor_trivial, dim3(std::max(1, std::min(cdiv(nrows, 32), 2048))),
+  hipLaunchKernelGGL(k_refactor_trivial,
+                     dim3(std::max(1, std::min(cdiv((long)nrows * in.count, 32), 2048))),
                      dim3(256), 0, s, nrows, rows, lu.rowptr, lu.src, aval, lu.val, ready, ss,
-                     luA, lu.diag, c0, st, perturb_rel);
+                     luA, lu.diag, c0, st, perturb_rel, in);
 }
 
 void launch_build_refmap(const LUView& lu, const int* moff, unsigned short* map,
@@ -3651,7 +3725,7 @@ bool launch_refactor_wg(const LUView& lu, const int* order, const int* cstart, i
                         int band, int cap, SyncState* ss, int* stall, int c0, const int* dlc,
                         const int* moff, const unsigned short* map, const double* luA,
                         const int2* pbnd, int max_waves_per_cu, DevStats* st, double perturb_rel,
-                        hipStream_t s, long long* tl) {
+                        hipStream_t s, long long* tl, Inst in) {
   if (nchunks <= 0) return true;
   if (band < 0 || band >= REF_MAX_BANDS || !dlc || !moff || !map || !luA || !pbnd) return false;
   constexpr int WPR = KKTLU_WG_WPR, DEPTH = KKTLU_WG_DEPTH;
@@ -3664,17 +3738,21 @@ bool launch_refactor_wg(const LUView& lu, const int* order, const int* cstart, i
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
     if (ncu <= 0) ncu = 256;
   }
+  // the timeline is recorded by its own instantiation (no cost otherwise),
+  // for single systems and block-diagonal batches
+  if (in.count > 1) tl = nullptr;
+  auto kern = in.count > 1 ? k_refactor_wg<WPR, DEPTH, false, true>
+               : tl          ? k_refactor_wg<WPR, DEPTH, true, false>
+                             : k_refactor_wg<WPR, DEPTH, false, false>;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_refactor_wg<WPR, DEPTH>, WPR * WAVE,
-                                                   shm) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, WPR * WAVE, shm) != hipSuccess ||
       nb <= 0)
     nb = 1;
   if (max_waves_per_cu > 0) nb = std::max(1, std::min(nb, max_waves_per_cu / WPR));
-  const int grid = std::max(1, std::min(nb * ncu, nchunks));
-  hipLaunchKernelGGL((k_refactor_wg<WPR, DEPTH>), dim3(grid), dim3(WPR * WAVE), shm, s, order,
-                     cstart, nchunks, ss->band_stream[band], std::min(TICKET_STREAMS, grid),
-                     lu.rowptr, dlc, lu.val, stall, moff, map, luA, pbnd, lu.diag, c0, st,
-                     perturb_rel, tl);
+  const int grid = std::max(1, (int)std::min<long>(nb * ncu, (long)nchunks * in.count));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(WPR * WAVE), shm, s, order, cstart, nchunks,
+                     ss->band_stream[band], std::min(TICKET_STREAMS, grid), lu.rowptr, dlc, lu.val,
+                     stall, moff, map, luA, pbnd, lu.diag, c0, st, perturb_rel, tl, in);
   return true;
 }
 
@@ -3682,7 +3760,8 @@ bool launch_refactor_flat(const LUView& lu, const int* cstart, int nchunks, int 
                           SyncState* ss, int* stall, const int4* rmeta,
                           const unsigned short* map, const double* luA, const int2* fl,
                           const unsigned char* cmicro, int max_waves_per_cu, DevStats* st,
-                          double perturb_rel, hipStream_t s, const int* order, long long* tl) {
+                          double perturb_rel, hipStream_t s, const int* order, long long* tl,
+                          Inst in) {
   if (nchunks <= 0) return true;
   if (band < 0 || band >= REF_MAX_BANDS || cap > 256 || !rmeta || !map || !luA || !fl)
     return false;
@@ -3696,16 +3775,19 @@ bool launch_refactor_flat(const LUView& lu, const int* cstart, int nchunks, int 
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
     if (ncu <= 0) ncu = 256;
   }
+  if (in.count > 1) tl = nullptr;
+  auto kern = in.count > 1 ? k_refactor_flat<WPB, false, true>
+               : tl          ? k_refactor_flat<WPB, true, false>
+                             : k_refactor_flat<WPB, false, false>;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_refactor_flat<WPB>, WPB * WAVE, shm) !=
-          hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, WPB * WAVE, shm) != hipSuccess ||
       nb <= 0)
     nb = 1;
   if (max_waves_per_cu > 0) nb = std::max(1, std::min(nb, max_waves_per_cu / WPB));
-  const int grid = std::max(1, std::min(nb * ncu, cdiv(nchunks, WPB)));
-  hipLaunchKernelGGL(k_refactor_flat<WPB>, dim3(grid), dim3(WPB * WAVE), shm, s, cstart, nchunks,
+  const int grid = std::max(1, std::min(nb * ncu, cdiv((long)nchunks * in.count, WPB)));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(WPB * WAVE), shm, s, cstart, nchunks,
                      ss->band_stream[band], std::min(TICKET_STREAMS, grid), lu.val, stall, cap,
-                     rmeta, map, luA, fl, cmicro, st, perturb_rel, order, tl);
+                     rmeta, map, luA, fl, cmicro, st, perturb_rel, order, tl, in);
   return true;
 }
 
@@ -3947,8 +4029,8 @@ void launch_dense_lu(double* T, int S, int s, double* dsc, DevStats* stats, doub
 void launch_trisolve_sn(int mode, int nr, const LUView& lu, const SnSched& sn, const int* tptr,
                         const int* trow, const int* tpos, const double* c, double* y,
                         SyncState* ss, int slot, int* stall, hipStream_t s, const int* xend,
-                        const double* pre) {
-  if (mode != 1 || nr != 1) {
+                        const double* pre, Inst in) {
+  if (mode != 1 || nr != 1 || in.count > 1) {
     xend = nullptr;
     pre = nullptr;
   }
@@ -3962,17 +4044,21 @@ void launch_trisolve_sn(int mode, int nr, const LUView& lu, const SnSched& sn, c
   }
   // every workgroup resident at once (the ticket streams need a running
   // workgroup each): at most the occupancy limit per CU
-  static int occ[4][3] = {};
-  const int ri = nr == 1 ? 0 : (nr <= 4 ? 1 : 2);
+  static int occ[4][4] = {};
+  const bool sh = in.count > 1;
+  const int ri = sh ? 3 : (nr == 1 ? 0 : (nr <= 4 ? 1 : 2));
   int& nb = occ[mode & 3][ri];
   if (nb == 0) {
     auto probe = [&](const void* k) {
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) != hipSuccess || nb <= 0)
         nb = 1;
     };
-#define SN_OCC(M, R) probe(reinterpret_cast<const void*>(&k_trisolve_sn<M, R>))
-#define SN_OCC_R(M) \
-  if (ri == 0) SN_OCC(M, 1); else if (ri == 1) SN_OCC(M, 4); else SN_OCC(M, SN_MAX_RHS)
+#define SN_OCC(M, R, S) probe(reinterpret_cast<const void*>(&k_trisolve_sn<M, R, S>))
+#define SN_OCC_R(M)                  \
+  if (ri == 3) SN_OCC(M, 1, true);   \
+  else if (ri == 0) SN_OCC(M, 1, false); \
+  else if (ri == 1) SN_OCC(M, 4, false); \
+  else SN_OCC(M, SN_MAX_RHS, false)
     switch (mode) {
       case 0: SN_OCC_R(0); break;
       case 1: SN_OCC_R(1); break;
@@ -3982,23 +4068,27 @@ void launch_trisolve_sn(int mode, int nr, const LUView& lu, const SnSched& sn, c
 #undef SN_OCC_R
 #undef SN_OCC
   }
-  const int grid =
-      std::max(1, std::min(ncu * std::min(sn.blocks_per_cu, nb), cdiv(sn.nchunks, 4)));
+  if (in.count > 1 && nr != 1) return;  // instances carry one right-hand side each
+  const int grid = std::max(
+      1, std::min(ncu * std::min(sn.blocks_per_cu, nb), cdiv((long)sn.nchunks * in.count, 4)));
   const int nstreams = std::min(TICKET_STREAMS, grid);
   const int ld = lu.n + 1;
-#define SN_LAUNCH(M, R)                                                                         \
-  hipLaunchKernelGGL((k_trisolve_sn<M, R>), dim3(grid), dim3(256), 0, s, t_gate, lu.n, nr, ld,          \
+#define SN_LAUNCH(M, R, S)                                                                      \
+  hipLaunchKernelGGL((k_trisolve_sn<M, R, S>), dim3(grid), dim3(256), 0, s, t_gate, lu.n, nr, ld,       \
                      sn.nchunks, sn.start, sn.meta, sn.base, sn.rows, sn.split, lu.rowptr,       \
                      lu.col, lu.diag, tptr, trow, tpos, lu.val, c, y, ss, slot, nstreams, stall, \
-                     xend, pre)
-#define SN_MODES(R)                 \
-  switch (mode) {                   \
-    case 0: SN_LAUNCH(0, R); break; \
-    case 1: SN_LAUNCH(1, R); break; \
-    case 2: SN_LAUNCH(2, R); break; \
-    default: SN_LAUNCH(3, R); break; \
+                     xend, pre, in)
+#define SN_MODES_S(R, S)               \
+  switch (mode) {                      \
+    case 0: SN_LAUNCH(0, R, S); break; \
+    case 1: SN_LAUNCH(1, R, S); break; \
+    case 2: SN_LAUNCH(2, R, S); break; \
+    default: SN_LAUNCH(3, R, S); break; \
   }
-  if (nr == 1) {
+#define SN_MODES(R) SN_MODES_S(R, false)
+  if (sh) {
+    SN_MODES_S(1, true)
+  } else if (nr == 1) {
     SN_MODES(1)
   } else if (nr <= 4) {
     SN_MODES(4)
@@ -4006,6 +4096,7 @@ void launch_trisolve_sn(int mode, int nr, const LUView& lu, const SnSched& sn, c
     SN_MODES(SN_MAX_RHS)
   }
 #undef SN_MODES
+#undef SN_MODES_S
 #undef SN_LAUNCH
 }
 
@@ -4120,9 +4211,9 @@ void launch_trisolve_seg(int mode, const SegSched& sg, const double* val, const 
 void launch_gather_sentinel_mr(int n, int nr, const int* perm, const double* scale, const double* x, double* c,
                                double* y, double* z, SyncState* ss, int mask, hipStream_t s,
                                const unsigned char* triv, const int* diag, const double* val,
-                               int div) {
+                               int div, long long f1) {
   hipLaunchKernelGGL(k_gather_sentinel_mr, dim3(cdiv(n, 256), nr), dim3(256), 0, s, t_gate, n, nr, perm, scale,
-                     x, c, y, z, ss, mask, triv, diag, val, div);
+                     x, c, y, z, ss, mask, triv, diag, val, div, f1);
 }
 
 void launch_scatter_mr(int n, int nr, const int* perm, const double* scale, const double* z, double* x,
@@ -4156,9 +4247,10 @@ void launch_gather_prep(int n, const int* perm, const double* scale, const doubl
 }
 
 void launch_anorm1(int n, const int* cptr, const int* cpos, const double* aval, DevStats* st,
-                   hipStream_t s, double* colabs) {
-  hipLaunchKernelGGL(k_anorm1, dim3(rows_grid(n)), dim3(256), 0, s, n, cptr, cpos,
-                     aval, st, colabs);
+                   hipStream_t s, double* colabs, Inst in) {
+  const int total = n * in.count;
+  hipLaunchKernelGGL(k_anorm1, dim3(rows_grid(total)), dim3(256), 0, s, total, cptr, cpos,
+                     aval, st, colabs, in);
 }
 
 void launch_reset_stats(DevStats* st, int what, hipStream_t s) {

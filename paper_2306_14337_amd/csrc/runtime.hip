@@ -150,6 +150,9 @@ struct kkt_ctx {
   // block-diagonal batch (batch_count > 0): instance offsets, per-row/column
   // absolute sums, per-instance maxima (3 per instance) and etas
   int batch_count = 0;
+  // shared-pattern batch (kkt_analyze_shared): inst.count instances of the
+  // one analysed pattern, sharing every index structure; count = 1 otherwise
+  Inst inst;
   std::vector<int64_t> row_off, nnz_off;
   int* d_row_off = nullptr;
   double *rowabs = nullptr, *colabs = nullptr, *inst_out = nullptr;
@@ -243,6 +246,10 @@ double bits_to_double(unsigned long long b) {
 // Scale that goes with a permutation in the solves' gathers and scatters:
 // the matched and scaled analysis factors Ahat = Pm Dr A Dc, so the row
 // permutation (pin) carries dr and the column permutation (qperm) dc.
+// length of the handle's vectors (rows of every instance of a shared-pattern
+// batch)
+int vlen(kkt_handle h) { return h->an.n * h->inst.count; }
+
 const double* scale_of(kkt_handle h, const int* perm) {
   return perm == h->pin ? h->rowsc : perm == h->qperm ? h->colsc : nullptr;
 }
@@ -279,6 +286,32 @@ void apply_factors(kkt_handle h, char op, const double* b, double* x, hipStream_
       cur = bufs[k];
     }
     launch_scatter(n, h->qperm, scale_of(h, h->qperm), cur, x, s);
+    return;
+  }
+  if (h->use_sn && h->inst.count > 1) {
+    // shared-pattern batch: the instances' permuted vectors side by side
+    // (stride n + 1, the spare slot per instance taking idle lanes' stores),
+    // the chain-block schedule handed out per (chunk, instance)
+    int* stall = &h->st->stall;
+    const Inst in = h->inst;
+    const int cnt = in.count;
+    if (op == 'N') {
+      launch_gather_sentinel_mr(n, cnt, h->pin, nullptr, b, h->tc, h->ty, h->tz, h->ss, 0x6, s,
+                                h->sn_triv0, h->diag, h->lu_val, 0, in.f1);
+      launch_trisolve_sn(0, 1, lu, h->chs[0], nullptr, nullptr, nullptr, h->tc, h->ty, h->ss, 1,
+                         stall, s, nullptr, nullptr, in);
+      launch_trisolve_sn(1, 1, lu, h->chs[1], nullptr, nullptr, nullptr, h->ty, h->tz, h->ss, 2,
+                         stall, s, nullptr, nullptr, in);
+      launch_scatter_mr(n, cnt, h->qperm, nullptr, h->tz, x, s);
+    } else {
+      launch_gather_sentinel_mr(n, cnt, h->qperm, nullptr, b, h->tc, h->ty, h->tz, h->ss, 0x6, s,
+                                h->sn_triv2, h->diag, h->lu_val, 1, in.f1);
+      launch_trisolve_sn(2, 1, lu, h->chs[2], h->ut_ptr, h->ut_row, h->ut_pos, h->tc, h->ty,
+                         h->ss, 1, stall, s, nullptr, nullptr, in);
+      launch_trisolve_sn(3, 1, lu, h->chs[3], h->lt_ptr, h->lt_row, h->lt_pos, h->ty, h->tz,
+                         h->ss, 2, stall, s, nullptr, nullptr, in);
+      launch_scatter_mr(n, cnt, h->pin, nullptr, h->tz, x, s);
+    }
     return;
   }
   if (h->use_sn) {
@@ -634,14 +667,14 @@ void apply_group(kkt_handle h, char op, int g, const double* b, double* x, hipSt
 // is judged by its largest instance eta.
 void check_group(kkt_handle h, const FgBufs& fb, char op, int g, const double* b,
                  const double* x, int it_now, int first, const FgParams& p, hipStream_t s) {
-  const int n = h->an.n;
+  const int n = vlen(h);
   const int batch = h->batch_count > 0 ? 1 : 0;
   if (op == 'N')
     launch_fg_resid(n, g, h->a_rowptr, h->a_col, nullptr, h->aval, b, x, h->r, fb, h->st, 0,
-                    it_now, first, batch, p, s);
+                    it_now, first, batch, p, s, h->inst);
   else
     launch_fg_resid(n, g, h->at_ptr, h->at_row, h->at_pos, h->aval, b, x, h->r, fb, h->st, 1,
-                    it_now, first, batch, p, s);
+                    it_now, first, batch, p, s, h->inst);
   if (batch) {
     launch_seg_stats(h->batch_count, h->d_row_off, op == 'N' ? h->rowabs : h->colabs, h->r, x,
                      h->inst_out, s);
@@ -659,7 +692,7 @@ void check_group(kkt_handle h, const FgBufs& fb, char op, int g, const double* b
 // library's static scratch array for kkt_solve_noalloc).
 void solve_group_async(kkt_handle h, const FgBufs& fb, char op, int g, const double* b, double* x,
                        bool first_group, int budget, hipStream_t s) {
-  const int n = h->an.n, m = h->m;
+  const int n = vlen(h), m = h->m;
   const kkt_options& o = h->opt;
   const FgParams p{o.eta_target, o.min_iters, o.fgmres_max_iters};
   const size_t gn = (size_t)g * n;
@@ -681,10 +714,11 @@ void solve_group_async(kkt_handle h, const FgBufs& fb, char op, int g, const dou
     double* zj = h->Z + j * gn;
     apply_group(h, op, g, vj, zj, s);
     if (op == 'N')
-      launch_fg_arnoldi(n, g, j, h->a_rowptr, h->a_col, nullptr, h->aval, zj, h->V, h->w, fb, s);
+      launch_fg_arnoldi(n, g, j, h->a_rowptr, h->a_col, nullptr, h->aval, zj, h->V, h->w, fb, s,
+                        h->inst);
     else
       launch_fg_arnoldi(n, g, j, h->at_ptr, h->at_row, h->at_pos, h->aval, zj, h->V, h->w, fb,
-                        s);
+                        s, h->inst);
     launch_fg_cgs(0, n, g, j, m, h->V, h->w, fb, s);
     launch_fg_cgs(1, n, g, j, m, h->V, h->w, fb, s);
     launch_fg_update(n, g, j, m, h->w, h->V + (j + 1) * gn, h->Z, x, h->xt, fb, s);
@@ -699,7 +733,7 @@ void solve_group_async(kkt_handle h, const FgBufs& fb, char op, int g, const dou
 // full budget, since it cannot adapt between replays)
 void solve_async(kkt_handle h, const FgBufs& fb, char op, int nrhs, const double* b, double* x,
                  int budget, hipStream_t s) {
-  const int n = h->an.n;
+  const int n = vlen(h);
   // one column at a time for approximate solves (no multi-column form) and
   // batches (their stop test is per instance of one column)
   const int gmax =
@@ -860,6 +894,7 @@ kkt_status kkt_analyze(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowp
   }
   if (st < 0) return fail(h, (kkt_status)st, msg);
   h->batch_count = 0;
+  h->inst = Inst();
   h->row_off.clear();
   h->nnz_off.clear();
   // the pattern, kept for re-analysis
@@ -1375,7 +1410,7 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   h->ref_flat = nullptr;
   h->ref_rmeta = nullptr;
   h->tl = nullptr;
-  if (h->opt.debug_timeline == 1) {
+  if (h->opt.debug_timeline == 1 && h->inst.count == 1) {
     if ((ks = dalloc(h, &h->tl, (size_t)3 * n)) != KKT_OK) {
       free_device(h);
       return ks;
@@ -1462,11 +1497,11 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
       dlc[i] = q - A.lu_rowptr[i];
     }
     UP(h->ref_dlc, dlc);
-    if ((ks = dalloc(h, &h->luA, fz)) != KKT_OK) {
+    if ((ks = dalloc(h, &h->luA, fz * h->inst.count)) != KKT_OK) {
       free_device(h);
       return ks;
     }
-    HIP_CHECK(h, hipMemset(h->luA, 0, fz * sizeof(double)));
+    HIP_CHECK(h, hipMemset(h->luA, 0, fz * h->inst.count * sizeof(double)));
   }
   // chain-blocked schedules of the four solves over the rows outside the
   // dense trailing block (modes 0 L, 1 U, 2 U^T, 3 L^T)
@@ -1721,15 +1756,18 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   // right-hand sides refined in lockstep: up to FG_MAX_COLS where the
   // schedule has multi-column solves, as many as keep the Krylov vectors
   // ((2m + 4) per column) within 2 GiB
+  // a shared-pattern batch holds every instance's values and vectors
+  const size_t cnt = (size_t)h->inst.count;
   int gc = 1;
-  if (h->syncfree && h->light) {
+  if (h->syncfree && h->light && cnt == 1) {
     gc = FG_MAX_COLS;
     while (gc > 1 && (size_t)gc * (2 * m + 4) * (size_t)n * sizeof(double) > (size_t(2) << 30))
       gc >>= 1;
   }
   h->fg_cols = gc;
-  const size_t gn = (size_t)gc * n;
-  if ((ks = dalloc(h, &h->lu_val, f)) != KKT_OK || (ks = dalloc(h, &h->aval, nnz)) != KKT_OK ||
+  const size_t gn = (size_t)gc * n * cnt;
+  if ((ks = dalloc(h, &h->lu_val, f * cnt)) != KKT_OK ||
+      (ks = dalloc(h, &h->aval, (size_t)nnz * cnt)) != KKT_OK ||
       (ks = dalloc(h, &h->st, 1)) != KKT_OK ||
       (ks = dalloc(h, &h->V, (size_t)(m + 1) * gn)) != KKT_OK ||
       (ks = dalloc(h, &h->Z, (size_t)m * gn)) != KKT_OK || (ks = dalloc(h, &h->w, gn)) != KKT_OK ||
@@ -1743,10 +1781,10 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
       (ks = dalloc(h, &h->fb.sn, (size_t)FG_MAX_COLS * m)) != KKT_OK ||
       (ks = dalloc(h, &h->fb.gvec, (size_t)FG_MAX_COLS * (m + 1))) != KKT_OK ||
       (ks = dalloc(h, &h->fb.y, (size_t)FG_MAX_COLS * m)) != KKT_OK ||
-      (ks = dalloc(h, &h->tmp, (size_t)n + 1)) != KKT_OK ||
-      (ks = dalloc(h, &h->tc, (size_t)n + 1)) != KKT_OK ||
-      (ks = dalloc(h, &h->ty, (size_t)n + 1)) != KKT_OK ||
-      (ks = dalloc(h, &h->tz, (size_t)n + 1)) != KKT_OK ||
+      (ks = dalloc(h, &h->tmp, ((size_t)n + 1) * cnt)) != KKT_OK ||
+      (ks = dalloc(h, &h->tc, ((size_t)n + 1) * cnt)) != KKT_OK ||
+      (ks = dalloc(h, &h->ty, ((size_t)n + 1) * cnt)) != KKT_OK ||
+      (ks = dalloc(h, &h->tz, ((size_t)n + 1) * cnt)) != KKT_OK ||
       (ks = dalloc(h, &h->H, (size_t)(m + 1) * m)) != KKT_OK ||
       (ks = dalloc(h, &h->cs, m + 1)) != KKT_OK || (ks = dalloc(h, &h->sn, m + 1)) != KKT_OK ||
       (ks = dalloc(h, &h->g, m + 1)) != KKT_OK || (ks = dalloc(h, &h->h, m + 1)) != KKT_OK ||
@@ -1779,8 +1817,8 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   if (h->batch_count > 0) {
     std::vector<int32_t> ro(h->row_off.begin(), h->row_off.end());
     if ((ks = upload(h, &h->d_row_off, ro)) != KKT_OK ||
-        (ks = dalloc(h, &h->rowabs, (size_t)n)) != KKT_OK ||
-        (ks = dalloc(h, &h->colabs, (size_t)n)) != KKT_OK ||
+        (ks = dalloc(h, &h->rowabs, (size_t)n * cnt)) != KKT_OK ||
+        (ks = dalloc(h, &h->colabs, (size_t)n * cnt)) != KKT_OK ||
         (ks = dalloc(h, &h->inst_out, (size_t)3 * SEG_SLICES * h->batch_count)) != KKT_OK) {
       free_device(h);
       return ks;
@@ -1788,9 +1826,14 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     h->h_inst.assign((size_t)3 * SEG_SLICES * h->batch_count, 0.0);
     h->inst_eta.assign(h->batch_count, 0.0);
   }
-  // the pivoting pass's factors are the current factors until the first refactor
-  HIP_CHECK(h, hipMemcpy(h->lu_val, A.lu_val0.data(), f * sizeof(double), hipMemcpyHostToDevice));
-  HIP_CHECK(h, hipMemcpy(h->aval, values0, (size_t)nnz * sizeof(double), hipMemcpyHostToDevice));
+  // the pivoting pass's factors are the current factors until the first
+  // refactor (every instance of a shared-pattern batch starts from them)
+  for (size_t t = 0; t < cnt; t++) {
+    HIP_CHECK(h, hipMemcpy(h->lu_val + t * f, A.lu_val0.data(), f * sizeof(double),
+                           hipMemcpyHostToDevice));
+    HIP_CHECK(h, hipMemcpy(h->aval + t * (size_t)nnz, values0, (size_t)nnz * sizeof(double),
+                           hipMemcpyHostToDevice));
+  }
   HIP_CHECK(h, hipHostMalloc((void**)&h->h_st, sizeof(DevStats), hipHostMallocDefault));
   HIP_CHECK(h, hipHostMalloc((void**)&h->h_fs, sizeof(FgState), hipHostMallocDefault));
   HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_fs, hipEventDisableTiming));
@@ -1823,8 +1866,8 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
     return fail(h, KKT_ERR_DEVICE, "cannot set the debug schedule flag");
   launch_reset_stats(h->st, 1 | 2 | 8, nullptr);
   launch_copy_anorm(n, h->a_rowptr, h->a_col, h->aval, h->aval, h->st, nullptr, nullptr,
-                    h->rowabs, nullptr, nullptr, nullptr, 1, h->ascale, h->avs);
-  launch_pivot_stats(view(h), h->st, h->opt.tiny_pivot_rel, nullptr);
+                    h->rowabs, nullptr, nullptr, nullptr, 1, h->ascale, h->avs, h->inst);
+  launch_pivot_stats(view(h), h->st, h->opt.tiny_pivot_rel, nullptr, h->inst);
   if (h->ref_map) launch_build_refmap(view(h), h->ref_moff, h->ref_map, h->ref_flat, nullptr);
   // the dense block's copy of the pivoting pass's factors (the solves read it)
   if (h->tail_s > 0)
@@ -1882,9 +1925,71 @@ kkt_status kkt_analyze_batch(kkt_handle h, int32_t npat, const int32_t* n, const
   }
   rp[N] = NNZ;
   h->batch_count = count;
+  h->inst = Inst();
   h->row_off = row_off;
   h->nnz_off = nnz_off;
   return install_analysis(h, std::move(an), st, N, NNZ, rp.data(), ci.data(), v0.data(), t0);
+}
+
+kkt_status kkt_analyze_shared(kkt_handle h, int32_t n, int64_t nnz, const int64_t* rowptr,
+                              const int32_t* colind, const double* values0, int32_t count) {
+  if (!h) return KKT_ERR_INVALID_ARG;
+  h->err.clear();
+  if (count < 1 || n < 1 || !rowptr || !colind || !values0)
+    return fail(h, KKT_ERR_INVALID_ARG, "bad count, size or pointer");
+  const kkt_options& o = h->opt;
+  if (o.matching != 0 || o.schedule == 1 || o.sync_mode == 1 || o.refactor_short_rows != 0 ||
+      o.refactor_long_rows != 0 || o.refactor_map != 0 || o.solve_chain < 0 ||
+      o.solve_jacobi_sweeps != 0 || o.refine_sync != 0)
+    return fail(h, KKT_ERR_INVALID_ARG,
+                "shared-pattern batches run the default dependency-driven kernels only");
+  const int64_t lim = INT32_MAX;
+  if ((int64_t)n * count + count > lim || nnz * count > lim)
+    return fail(h, KKT_ERR_TOO_LARGE, "the batch exceeds the int32 index range");
+  auto t0 = std::chrono::steady_clock::now();
+  AnalyzeOptions ao;
+  ao.ordering = o.ordering == 2 ? 0 : o.ordering;
+  ao.tau = o.pivot_tau;
+  Analysis an;
+  std::string msg;
+  int st;
+  try {
+    st = analyze(n, nnz, rowptr, colind, values0, nullptr, ao, an, &msg);
+  } catch (const std::bad_alloc&) {
+    return fail(h, KKT_ERR_OUT_OF_MEMORY, "host allocation failed in analyze");
+  }
+  if (st < 0) return fail(h, (kkt_status)st, msg);
+  if ((int64_t)an.lu_col.size() * count > lim)
+    return fail(h, KKT_ERR_TOO_LARGE, "the batch's factors exceed the int32 index range");
+  h->batch_count = count;
+  h->inst = Inst();
+  h->inst.count = count;
+  h->inst.n1 = n;
+  h->inst.a1 = (int)nnz;
+  h->inst.f1 = (int)an.lu_col.size();
+  h->row_off.assign((size_t)count + 1, 0);
+  h->nnz_off.assign((size_t)count + 1, 0);
+  for (int32_t t = 0; t <= count; t++) {
+    h->row_off[t] = (int64_t)t * n;
+    h->nnz_off[t] = (int64_t)t * nnz;
+  }
+  h->pat_rowptr.clear();
+  h->pat_colind.clear();
+  kkt_status ks = install_analysis(h, std::move(an), st, n, nnz, rowptr, colind, values0, t0);
+  if (ks < 0) return ks;
+  bool kernels_ok = h->syncfree && h->light && h->use_sn && h->tail_s == 0 && h->ref_fl;
+  for (int b = 0; kernels_ok && b < h->nbands; b++)
+    kernels_ok = h->band_flat[b] || (h->ref_map && h->luA && h->ref_pbnd && h->ref_dlc &&
+                                     (size_t)h->band_cap[b] * 8 <= 64 * 1024);
+  if (!kernels_ok) {
+    free_device(h);
+    h->inst = Inst();
+    h->batch_count = 0;
+    return fail(h, KKT_ERR_INVALID_ARG,
+                "this pattern does not take the dependency-driven kernels a shared-pattern batch "
+                "needs");
+  }
+  return ks;
 }
 
 kkt_status kkt_batch_layout(kkt_handle h, int64_t* row_offset, int64_t* nnz_offset) {
@@ -1913,12 +2018,13 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
   // scaled ones (written by the copy pass)
   const double* fa = h->avs ? h->avs : h->aval;
   launch_reset_stats(h->st, 1, s);
+  const Inst in = h->inst;  // instances of a shared-pattern batch
   if (h->syncfree) {
     launch_copy_anorm(A.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, h->ss, h->rowabs,
-                      h->a2lu, h->luA, nullptr, 1, h->ascale, h->avs);
-    if (h->light) launch_fill_sentinel(h->lu_val, (long long)A.lu_col.size(), s);
+                      h->a2lu, h->luA, nullptr, 1, h->ascale, h->avs, in);
+    if (h->light) launch_fill_sentinel(h->lu_val, (long long)A.lu_col.size() * in.count, s);
     launch_refactor_trivial(lu, h->ref_triv, h->ref_ntriv, fa, h->ready_ref, h->ss, s,
-                            h->luA, h->tail_c0, h->st, h->opt.pivot_perturb_rel);
+                            h->luA, h->tail_c0, h->st, h->opt.pivot_perturb_rel, in);
     for (int b = 0; b < h->nbands; b++)
       if (h->band_flat[b]) {
         if (!launch_refactor_flat(lu, h->ref_cstart + h->band_chunk_lo[b], h->band_nchunks[b], b,
@@ -1926,7 +2032,7 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
                                   h->ref_rmeta, h->ref_map, h->luA, h->ref_fl,
                                   h->ref_cmicro ? h->ref_cmicro + h->band_chunk_lo[b] : nullptr,
                                   h->opt.refactor_waves_per_cu, h->st, h->opt.pivot_perturb_rel,
-                                  s, h->ref_order, h->tl))
+                                  s, h->ref_order, h->tl, in))
           return fail(h, KKT_ERR_DEVICE, "short-row refactorization not launchable");
       } else if (h->light && h->ref_map && h->luA && h->ref_pbnd && h->ref_dlc &&
                  h->opt.refactor_long_rows == 0 && (size_t)h->band_cap[b] * 8 <= 64 * 1024) {
@@ -1934,7 +2040,7 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
                                 h->band_nchunks[b], b, h->band_cap[b], h->ss, &h->st->stall,
                                 h->tail_c0, h->ref_dlc, h->ref_moff, h->ref_map, h->luA,
                                 h->ref_pbnd, h->opt.refactor_waves_per_cu, h->st,
-                                h->opt.pivot_perturb_rel, s, h->tl))
+                                h->opt.pivot_perturb_rel, s, h->tl, in))
           return fail(h, KKT_ERR_DEVICE, "long-row refactorization not launchable");
       } else if (!launch_refactor_syncfree(lu, h->ref_order, h->ref_cstart + h->band_chunk_lo[b],
                                     h->band_nchunks[b], b, h->band_cap[b], fa, h->ready_ref,
@@ -1964,7 +2070,7 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
       launch_refactor_rows(lu, h->lev_rows + A.lev_ptr[l], A.lev_ptr[l + 1] - A.lev_ptr[l],
                            A.lev_maxlen[l], fa, h->st, h->opt.pivot_perturb_rel, s);
   }
-  launch_pivot_stats(lu, h->st, h->opt.tiny_pivot_rel, s);
+  launch_pivot_stats(lu, h->st, h->opt.tiny_pivot_rel, s, in);
   return KKT_OK;
 }
 
@@ -2040,7 +2146,7 @@ kkt_status kkt_update_matrix(kkt_handle h, const double* d_values, void* stream)
   // keep the pivot statistics of the current factors, recompute ||A||_inf
   launch_reset_stats(h->st, 4, s);
   launch_copy_anorm(h->an.n, h->a_rowptr, h->a_col, d_values, h->aval, h->st, s, nullptr,
-                    h->rowabs, nullptr, nullptr, nullptr, 0);
+                    h->rowabs, nullptr, nullptr, nullptr, 0, nullptr, nullptr, h->inst);
   HIP_CHECK(h, hipGetLastError());
   h->anorm1_valid = false;
   h->factor_epoch++;
@@ -2054,13 +2160,17 @@ kkt_status kkt_solve(kkt_handle h, char op, int32_t nrhs, const double* d_b, dou
   if (!h->factored) return fail(h, KKT_ERR_STATE, "kkt_solve before kkt_analyze");
   if ((op != 'N' && op != 'T') || nrhs < 0 || (nrhs > 0 && (!d_b || !d_x)))
     return fail(h, KKT_ERR_INVALID_ARG, "bad op, nrhs or pointer");
-  const int n = h->an.n;
+  const int n = vlen(h);
   if (nrhs > 0 && d_b < d_x + (size_t)nrhs * n && d_x < d_b + (size_t)nrhs * n)
     return fail(h, KKT_ERR_INVALID_ARG, "d_b and d_x overlap");
+  if (h->inst.count > 1 && (nrhs > 1 || h->opt.refine_sync != 0))
+    return fail(h, KKT_ERR_INVALID_ARG,
+                "a shared-pattern batch solves one right-hand side per instance, with the stop "
+                "test on the device (refine_sync = 0)");
   HIP_CHECK(h, hipSetDevice(h->opt.device));
   hipStream_t s = (hipStream_t)stream;
   if (op == 'T' && !h->anorm1_valid) {
-    launch_anorm1(n, h->at_ptr, h->at_pos, h->aval, h->st, s, h->colabs);
+    launch_anorm1(h->an.n, h->at_ptr, h->at_pos, h->aval, h->st, s, h->colabs, h->inst);
     h->anorm1_valid = true;
   }
   if (h->opt.refine_sync == 0) {
@@ -2178,6 +2288,8 @@ kkt_status kkt_grad_values(kkt_handle h, int32_t nrhs, const double* d_lambda, c
   if (!h->analyzed) return fail(h, KKT_ERR_STATE, "kkt_grad_values before kkt_analyze");
   if (nrhs <= 0 || !d_lambda || !d_x || !d_grad)
     return fail(h, KKT_ERR_INVALID_ARG, "bad nrhs or pointer");
+  if (h->inst.count > 1)
+    return fail(h, KKT_ERR_STATE, "kkt_grad_values is for single systems and block-diagonal batches");
   HIP_CHECK(h, hipSetDevice(h->opt.device));
   hipStream_t s = (hipStream_t)stream;
   launch_grad_sddmm(h->an.n, nrhs, h->a_rowptr, h->a_col, d_lambda, d_x, d_grad, s);
@@ -2191,6 +2303,8 @@ kkt_status kkt_solve_noalloc(kkt_handle h, char op, int32_t nrhs, const double* 
   if (!h->factored) return fail(h, KKT_ERR_STATE, "kkt_solve_noalloc before kkt_analyze");
   if ((op != 'N' && op != 'T') || nrhs < 0 || (nrhs > 0 && (!d_b || !d_x)))
     return fail(h, KKT_ERR_INVALID_ARG, "bad op, nrhs or pointer");
+  if (h->inst.count > 1)
+    return fail(h, KKT_ERR_STATE, "kkt_solve_noalloc is for single systems and block-diagonal batches");
   const int n = h->an.n;
   if (nrhs > 0 && d_b < d_x + (size_t)nrhs * n && d_x < d_b + (size_t)nrhs * n)
     return fail(h, KKT_ERR_INVALID_ARG, "d_b and d_x overlap");
@@ -2203,7 +2317,7 @@ kkt_status kkt_solve_noalloc(kkt_handle h, char op, int32_t nrhs, const double* 
                 "the refinement state for this restart length exceeds the 2 MiB scratch array");
   hipStream_t s = (hipStream_t)stream;
   if (op == 'T' && !h->anorm1_valid) {
-    launch_anorm1(n, h->at_ptr, h->at_pos, h->aval, h->st, s, h->colabs);
+    launch_anorm1(h->an.n, h->at_ptr, h->at_pos, h->aval, h->st, s, h->colabs, h->inst);
     h->anorm1_valid = true;
   }
   if (nrhs == 0) {
@@ -2258,10 +2372,11 @@ kkt_status kkt_get_info(kkt_handle h, kkt_info* out) {
   if (!h || !out) return KKT_ERR_INVALID_ARG;
   if (!h->analyzed) return fail(h, KKT_ERR_STATE, "no analysis");
   const Analysis& A = h->an;
-  out->n = A.n;
-  out->nnz = A.nnz;
-  out->nnz_l = A.nnz_l;
-  out->nnz_u = A.nnz_u;
+  const int32_t cnt = h->inst.count;  // a shared-pattern batch: totals over its instances
+  out->n = A.n * cnt;
+  out->nnz = A.nnz * cnt;
+  out->nnz_l = A.nnz_l * cnt;
+  out->nnz_u = A.nnz_u * cnt;
   out->levels = (int32_t)A.lev_ptr.size() - 1;
   out->levels_u = (int32_t)A.ulev_ptr.size() - 1;
   out->analyze_status = A.warn_singular ? KKT_WARN_NUMERICALLY_SINGULAR : KKT_OK;
@@ -2326,11 +2441,17 @@ kkt_status kkt_get_scaling(kkt_handle h, int32_t* match, double* dr, double* dc)
   return KKT_OK;
 }
 
+// (a shared-pattern batch answers in block-diagonal form: instance t's
+// rows and columns offset by t n, its factor entries by t nnz(L+U))
 kkt_status kkt_get_perm(kkt_handle h, int32_t* p, int32_t* q) {
   if (!h) return KKT_ERR_INVALID_ARG;
   if (!h->analyzed) return fail(h, KKT_ERR_STATE, "no analysis");
-  if (p) std::memcpy(p, h->an.P.data(), h->an.P.size() * sizeof(int32_t));
-  if (q) std::memcpy(q, h->an.Q.data(), h->an.Q.size() * sizeof(int32_t));
+  const int32_t n = h->an.n;
+  for (int32_t t = 0; t < h->inst.count; t++)
+    for (int32_t i = 0; i < n; i++) {
+      if (p) p[(size_t)t * n + i] = h->an.P[i] + t * n;
+      if (q) q[(size_t)t * n + i] = h->an.Q[i] + t * n;
+    }
   return KKT_OK;
 }
 
@@ -2338,14 +2459,20 @@ kkt_status kkt_get_lu(kkt_handle h, int64_t* rowptr, int32_t* colind, double* va
   if (!h) return KKT_ERR_INVALID_ARG;
   if (!h->analyzed) return fail(h, KKT_ERR_STATE, "no analysis");
   const Analysis& A = h->an;
-  if (rowptr)
-    for (size_t i = 0; i < A.lu_rowptr.size(); i++) rowptr[i] = A.lu_rowptr[i];
-  if (colind) std::memcpy(colind, A.lu_col.data(), A.lu_col.size() * sizeof(int32_t));
+  const int32_t n = A.n;
+  const size_t f = A.lu_col.size();
+  const int32_t cnt = h->inst.count;
+  for (int32_t t = 0; t < cnt; t++) {
+    if (rowptr)
+      for (int32_t i = 0; i < n + (t == cnt - 1 ? 1 : 0); i++)
+        rowptr[(size_t)t * n + i] = (int64_t)t * (int64_t)f + A.lu_rowptr[i];
+    if (colind)
+      for (size_t q = 0; q < f; q++) colind[t * f + q] = A.lu_col[q] + t * n;
+  }
   if (values) {
     HIP_CHECK(h, hipSetDevice(h->opt.device));
     HIP_CHECK(h, hipDeviceSynchronize());
-    HIP_CHECK(h, hipMemcpy(values, h->lu_val, A.lu_col.size() * sizeof(double),
-                           hipMemcpyDeviceToHost));
+    HIP_CHECK(h, hipMemcpy(values, h->lu_val, f * cnt * sizeof(double), hipMemcpyDeviceToHost));
   }
   return KKT_OK;
 }

@@ -802,6 +802,26 @@ def test_multi_rhs_device_refinement_stale(op):
     assert rep.iters > 1 and max(etas) <= 1e-12 and rep.eta <= 1e-12
 
 
+def test_multi_rhs_forced_iterations_wide_grid():
+    # eight right-hand sides refined in lockstep on a system of about 70k
+    # rows with two forced iterations: the Arnoldi pass then runs on its
+    # widest grid, whose per-workgroup partial sums for eight columns must
+    # stay inside their buffer (the residual pass may use a wider grid)
+    pat, seq = kktgen.make_sequence(7000, 107, 1)
+    vals, _ = seq[0]
+    nrhs = 8
+    B = np.random.default_rng(5).standard_normal((nrhs, pat.n))
+    s = binding.KKTSolver(min_iters=2)
+    s.analyze(pat.n, pat.rowptr, pat.colind, vals)
+    s.refactor(dev(vals))
+    X = s.solve(dev(B.reshape(-1))).cpu().numpy().reshape(nrhs, pat.n)
+    rep = s.report()
+    A = pat.scipy(vals)
+    etas = [eta(A, X[r], B[r]) for r in range(nrhs)]
+    print(f"  n {pat.n}: iters {rep.iters} max eta {max(etas):.3e}", flush=True)
+    assert pat.n > 512 * 128 and rep.iters == 2 and max(etas) <= 1e-12
+
+
 def test_adaptive_refinement_budget():
     # refine_budget = -1: exact factors need no iteration, so later solves
     # launch two; kkt_update_matrix (stale factors) brings the full budget
