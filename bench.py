@@ -426,7 +426,8 @@ def bench_batched(torch, binding, kktgen, steps=5, seed=104, n_a=128, n_b=128, B
     return {"workload": f"batched, {n_a} instances sharing one B={B_a} pattern + {n_b} instances "
                         f"with own B~U[500,5000], one captured graph per batch step "
                         f"(refactor + solve + device-checked refinement)",
-            "instances": count, "rows_total": s.n, "ms_per_batch": t_batch * 1e3,
+            "instances": count, "rows_total": s.n, "device_bytes": int(s.info().device_bytes),
+            "ms_per_batch": t_batch * 1e3,
             "ms_per_batch_events": t_batch_ev * 1e3,
             "inst_per_s": count / t_batch, "loop_inst_per_s": count / t_loop,
             "speedup_vs_loop": t_loop / t_batch, "eta_max": float(etas.max()),

@@ -172,6 +172,9 @@ typedef struct {
                                band kernels, when the row started, when it last found an input
                                missing and when its stores completed (kkt_debug_timeline);
                                0 = off (default) */
+  int32_t refactor_short_band; /* dependency-driven refactorization: longest row of the short-row
+                                  band (rows fed only by such rows go to the list kernel);
+                                  0 = 128 (default), at most 256 */
 } kkt_options;
 
 typedef struct {

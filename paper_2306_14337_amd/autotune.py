@@ -10,6 +10,7 @@ Knobs (all fields of the C options struct):
   dense_tail                size of the dense trailing block (0 auto, -1 none)
   refactor_short_rows       short-row band as update lists (0) or pivot by pivot (-1)
   refactor_long_rows        long-row band with prefetched steps (0) or not (-1)
+  refactor_short_band       longest row of the short-row band (0 = 128, up to 256)
 
 The search is in two stages: the launch-shape candidates first, then the
 segment, dense-block and refactorization-kernel variants of the winner.
@@ -77,6 +78,7 @@ def refinements(best: dict):
     out.append({**best, "dense_tail": -1})
     out.append({**best, "refactor_short_rows": -1})
     out.append({**best, "refactor_long_rows": -1})
+    out.append({**best, "refactor_short_band": 256})
     return out
 
 
@@ -173,7 +175,8 @@ def batch_candidates(full: bool = False):
              dict(refactor_micro_rows=-1), dict(solve_entries_per_lane=4),
              dict(solve_entries_per_lane=16), dict(solve_blocks_per_cu=4)]
     if full:
-        knobs += [dict(refactor_waves_per_cu=16), dict(solve_chain=8), dict(solve_chain=-1)]
+        knobs += [dict(refactor_waves_per_cu=16), dict(solve_chain=8), dict(solve_chain=-1),
+                  dict(refactor_short_band=256)]
     return out + knobs
 
 

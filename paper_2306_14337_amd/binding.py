@@ -64,7 +64,7 @@ class Options(C.Structure):
                 ("refine_budget", C.c_int32), ("dense_lu", C.c_int32),
                 ("debug_spin_limit", C.c_int32), ("debug_schedule", C.c_int32),
                 ("matching", C.c_int32), ("refactor_micro_rows", C.c_int32),
-                ("debug_timeline", C.c_int32)]
+                ("debug_timeline", C.c_int32), ("refactor_short_band", C.c_int32)]
 
 
 class Report(C.Structure):

@@ -844,7 +844,7 @@ kkt_status kkt_create(const kkt_options* opt, kkt_handle* out) {
       o.dense_lu < 0 || o.dense_lu > 1 || o.debug_spin_limit < 0 || o.debug_schedule < 0 ||
       o.matching < 0 || o.matching > 1 || o.refactor_micro_rows < -1 ||
       o.refactor_micro_rows > 0 || o.debug_schedule > 1 || o.debug_timeline < 0 ||
-      o.debug_timeline > 1 ||
+      o.debug_timeline > 1 || o.refactor_short_band < 0 || o.refactor_short_band > 256 ||
       !(o.pivot_perturb_rel >= 0.0 && o.pivot_perturb_rel < 1.0))
     return KKT_ERR_INVALID_ARG;
   int ndev = 0;
@@ -1255,7 +1255,8 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   // (longest chain of rows depending on them), so that a level's rows on the
   // critical chains are handed out first.
   {
-    static const int band_len[REF_MAX_BANDS - 1] = {128, 1 << 30, 1 << 30};
+    const int band_len[REF_MAX_BANDS - 1] = {
+        h->opt.refactor_short_band > 0 ? h->opt.refactor_short_band : 128, 1 << 30, 1 << 30};
     const int c0 = h->tail_c0;
     std::vector<int32_t> rowof(A.lu_col.size());
     for (int32_t i = 0; i < n; i++)
