@@ -38,7 +38,9 @@ def test_refinements_vary_segments_dense_block_and_kernels():
     assert any(r.get("dense_tail") == -1 for r in ref)
     assert any(r.get("refactor_short_rows") == -1 for r in ref)
     assert any(r.get("refactor_long_rows") == -1 for r in ref)
-    varied = ("solve_thin_rows", "dense_tail", "refactor_short_rows", "refactor_long_rows")
+    assert any(r.get("refactor_short_band") == 256 for r in ref)
+    varied = ("solve_thin_rows", "dense_tail", "refactor_short_rows", "refactor_long_rows",
+              "refactor_short_band")
     for r in ref:
         binding.options(**r)  # valid option fields
         assert {k: v for k, v in r.items() if k not in varied} == best
