@@ -63,7 +63,9 @@ typedef enum {
   KKT_ERR_STATE = -4,                /* e.g. refactor before analyze */
   KKT_ERR_OUT_OF_MEMORY = -5,
   KKT_ERR_DEVICE = -6,               /* a HIP runtime call failed */
-  KKT_ERR_NONFINITE = -7,            /* NaN/Inf in analyze's values */
+  KKT_ERR_NONFINITE = -7,            /* NaN/Inf in analyze's values; from kkt_sync_report: in
+                                        the last refactorization's values (their NaNs enter
+                                        the factors as quiet NaNs) */
   KKT_ERR_TOO_LARGE = -8             /* factor size exceeds the int32 index range */
 } kkt_status;
 
@@ -345,7 +347,9 @@ kkt_status kkt_graph_capture(kkt_handle h, const double *d_values, const double 
                              double *d_x, void *stream);
 kkt_status kkt_graph_launch(kkt_handle h, void *stream);
 
-/* Wait for the handle's device work and return (then clear) the report. */
+/* Wait for the handle's device work and return (then clear) the report.  Returns
+ * KKT_ERR_DEVICE if a dependency wait gave up (results invalid), KKT_ERR_NONFINITE (with *out
+ * filled in) if the last refactorization's values held a NaN or an infinity. */
 kkt_status kkt_sync_report(kkt_handle h, kkt_report *out);
 kkt_status kkt_get_info(kkt_handle h, kkt_info *out);
 

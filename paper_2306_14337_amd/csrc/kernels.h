@@ -32,6 +32,7 @@ struct DevStats {
   int stall;                   // a dependency wait hit its spin limit (sticky)
   int spin_limit;              // host-set debug limit on every wait (0 = none); follows stall
   int perturbed;               // a pivot was raised to the perturbation threshold
+  int nonfinite_in;            // the last refactorization's values held a NaN or an infinity
 };
 
 // Sync-free refinement: the stop test of every right-hand side runs on the

@@ -214,6 +214,12 @@ __device__ __forceinline__ bool is_sentinel(double v) {
   return (unsigned long long)__double_as_longlong(v) == SENTINEL;
 }
 
+// Inputs enter the value-as-flag arrays through this: any NaN becomes the
+// canonical quiet NaN, so no input can carry the sentinel's bit pattern.
+__device__ __forceinline__ double canon_nan(double v) {
+  return v != v ? __longlong_as_double(0x7FF8000000000000ll) : v;
+}
+
 __global__ void k_fill_sentinel(double* __restrict__ p, long long count) {
   const double sent = __longlong_as_double((long long)SENTINEL);
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < count;
@@ -1795,7 +1801,7 @@ __global__ void k_gather_sentinel(const int* __restrict__ gate, int n, const int
   KKT_GATE(gate);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
-    const double ci = scale ? x[perm[i]] * scale[i] : x[perm[i]];
+    const double ci = canon_nan(scale ? x[perm[i]] * scale[i] : x[perm[i]]);
     c[i] = ci;
     const double sent = __longlong_as_double((long long)SENTINEL);
     y[i] = (triv && triv[i]) ? (div ? ci / val[diag[i]] : ci) : sent;
@@ -1817,7 +1823,7 @@ __global__ void k_gather_sentinel_mr(const int* __restrict__ gate, int n, int nr
   if (i < n && r < nr) {
     const size_t o = (size_t)r * (n + 1) + i;
     const double xi = x[(size_t)r * n + perm[i]];
-    const double ci = scale ? xi * scale[i] : xi;
+    const double ci = canon_nan(scale ? xi * scale[i] : xi);
     c[o] = ci;
     const double sent = __longlong_as_double((long long)SENTINEL);
     // column r's factors at r f1 (the instances of a shared-pattern batch;
@@ -1846,7 +1852,7 @@ __global__ void k_gather_prep(const int* __restrict__ gate, int n, const int* __
                               double* __restrict__ y, SyncState* ss, int mask) {
   KKT_GATE(gate);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = scale ? x[perm[i]] * scale[i] : x[perm[i]];
+  if (i < n) y[i] = canon_nan(scale ? x[perm[i]] * scale[i] : x[perm[i]]);
   if (ss && i == 0) sync_prep(ss, mask);
 }
 
@@ -1861,6 +1867,7 @@ __global__ void k_reset_stats(DevStats* st, int what) {
       st->anorm_f = 0ull;
       st->tiny = 0;
       st->perturbed = 0;
+      st->nonfinite_in = 0;
     }
     if (what & 2) {
       st->rmax = 0ull;
@@ -1933,22 +1940,41 @@ __global__ __launch_bounds__(256) void k_pivot_stats(int n, const int* __restric
   const double anorm = __longlong_as_double((long long)st->anorm_f);
   double mn = __builtin_huge_val(), mx = 0.0, um = 0.0;
   int tiny = 0;
-  for (int r0 = wid * (WAVE / RG); r0 < n; r0 += nw * (WAVE / RG)) {
-    const int ig = r0 + g;
-    if (ig < n) {
-      const int ti = inst_of(ig, in);
-      const int i = ig - ti * in.n1;
-      const double* val = val0 + ti * in.f1;
-      const int d = diag[i], e = rowptr[i + 1];
-      for (int t = d + gl; t < e; t += RG) {
-        const double a = fabs(val[t]);
-        um = nanmax(um, a);
-        if (t == d) {
-          mn = fmin(mn, a);
-          mx = fmax(mx, a);
-          tiny |= !(a >= tiny_rel * anorm) || isinf(a);
+  // four row groups per round, their first loads all in flight before any is
+  // used; lane 0 of a row's group holds its diagonal (the U part's first entry)
+  constexpr int U = 4;
+  const int stride = nw * (WAVE / RG);
+  for (int r0 = wid * (WAVE / RG); r0 < n; r0 += U * stride) {
+    int d[U], e[U];
+    const double* vr[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int ig = r0 + u * stride + g;
+      d[u] = 0;
+      e[u] = 0;
+      vr[u] = val0;
+      if (ig < n) {
+        const int ti = inst_of(ig, in);
+        const int i = ig - ti * in.n1;
+        vr[u] = val0 + ti * in.f1;
+        d[u] = diag[i];
+        e[u] = rowptr[i + 1];
+      }
+    }
+    double a0[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) a0[u] = d[u] + gl < e[u] ? fabs(vr[u][d[u] + gl]) : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      if (d[u] + gl < e[u]) {
+        um = nanmax(um, a0[u]);
+        if (gl == 0) {
+          mn = fmin(mn, a0[u]);
+          mx = fmax(mx, a0[u]);
+          tiny |= !(a0[u] >= tiny_rel * anorm) || isinf(a0[u]);
         }
       }
+      for (int t = d[u] + gl + RG; t < e[u]; t += RG) um = nanmax(um, fabs(vr[u][t]));
     }
   }
   for (int off = WAVE / 2; off > 0; off >>= 1) {
@@ -2082,7 +2108,7 @@ __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict
       double s = 0.0, sf = 0.0;
       if (p0[u] < pe[u]) {
         dst[p0[u] + ao[u]] = v0[u];
-        const double w = ascale ? v0[u] * ascale[p0[u]] : v0[u];
+        const double w = canon_nan(ascale ? v0[u] * ascale[p0[u]] : v0[u]);
         if (ascale) avs[p0[u]] = w;
         if (luA) luA[q0[u]] = w;
         s = fabs(v0[u]);
@@ -2091,7 +2117,7 @@ __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict
       for (int p = p0[u] + RG; p < pe[u]; p += RG) {
         const double v = src[p + ao[u]];
         dst[p + ao[u]] = v;
-        const double w = ascale ? v * ascale[p] : v;
+        const double w = canon_nan(ascale ? v * ascale[p] : v);
         if (ascale) avs[p] = w;
         if (luA) luA[a2lu[p] + fo[u]] = w;
         s += fabs(v);
@@ -2111,6 +2137,8 @@ __global__ __launch_bounds__(256) void k_copy_anorm(int n, const int* __restrict
   m = block_nanmax(m, red[0]);
   mf = block_nanmax(mf, red[1]);
   if (threadIdx.x == 0) {
+    // a NaN or an infinity among the values makes its row's sum non-finite
+    if (!(m <= __DBL_MAX__)) st->nonfinite_in = 1;
     if (red_out) {  // reduced by k_red_max
       if (fnorm) {
         red_out[2 * blockIdx.x] = m;
@@ -2227,7 +2255,7 @@ __global__ void k_gather(const int* __restrict__ gate, int n, const int* __restr
                          double* __restrict__ y) {
   KKT_GATE(gate);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = scale ? x[perm[i]] * scale[i] : x[perm[i]];
+  if (i < n) y[i] = canon_nan(scale ? x[perm[i]] * scale[i] : x[perm[i]]);
 }
 __global__ void k_scatter(const int* __restrict__ gate, int n, const int* __restrict__ perm,
                           const double* __restrict__ scale, const double* __restrict__ x,
@@ -3127,12 +3155,45 @@ __device__ __forceinline__ double fg_block_sum(double v, double* red) {
 
 // Last workgroup: out[q] = sum over b < nb of pc[b * FG_Q + q] for q < nq, in
 // a fixed order (eight slices of the workgroups, then the slices in order).
+// Sum of the partials p[b * stride] for b = b0, b0 + step, ... below nb, added
+// in that order, with eight device-coherent loads in flight at a time.
+__device__ __forceinline__ double coh_sum(const double* p, int b0, int nb, int step, int stride) {
+  double s = 0.0;
+  for (int b = b0; b < nb; b += 8 * step) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      const int bb = b + k * step;
+      v[k] = bb < nb ? ld_coh(p + (size_t)bb * stride) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+      if (b + k * step < nb) s += v[k];
+  }
+  return s;
+}
+
+// As coh_sum, the NaN-propagating maximum.
+__device__ __forceinline__ double coh_max(const double* p, int b0, int nb, int step, int stride) {
+  double s = 0.0;
+  for (int b = b0; b < nb; b += 8 * step) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      const int bb = b + k * step;
+      v[k] = bb < nb ? ld_coh(p + (size_t)bb * stride) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; k++) s = nanmax(s, v[k]);
+  }
+  return s;
+}
+
 __device__ void fg_reduce_q(const double* pc, int nb, int nq, double* out) {
   __shared__ double red[FG_T];
   const int q = threadIdx.x % FG_Q, k = threadIdx.x / FG_Q;
   double s = 0.0;
-  if (q < nq)
-    for (int b = k; b < nb; b += FG_T / FG_Q) s += ld_coh(pc + (size_t)b * FG_Q + q);
+  if (q < nq) s = coh_sum(pc + q, k, nb, FG_T / FG_Q, FG_Q);
   red[threadIdx.x] = s;
   __syncthreads();
   if (threadIdx.x < nq) {
@@ -3263,11 +3324,8 @@ __global__ __launch_bounds__(FG_T) void k_fg_resid(
     st_coh(pc + 2 * blockIdx.x + 1, xm);
   }
   if (!fg_last_block(&col->ticket, gridDim.x)) return;
-  double a = 0.0, bm = 0.0;
-  for (int q = threadIdx.x; q < (int)gridDim.x; q += FG_T) {
-    a = nanmax(a, ld_coh(pc + 2 * q));
-    bm = nanmax(bm, ld_coh(pc + 2 * q + 1));
-  }
+  double a = coh_max(pc, threadIdx.x, gridDim.x, FG_T, 2);
+  double bm = coh_max(pc + 1, threadIdx.x, gridDim.x, FG_T, 2);
   a = block_nanmax(a, red[0]);
   bm = block_nanmax(bm, red[1]);
   if (threadIdx.x == 0) {
@@ -3316,8 +3374,7 @@ __global__ __launch_bounds__(FG_T) void k_fg_restart(int n, int m, const double*
   double* pc = part + (size_t)c * gridDim.x;
   if (threadIdx.x == 0) st_coh(pc + blockIdx.x, sb);
   if (!fg_last_block(&col->ticket, gridDim.x)) return;
-  double a = 0.0;
-  for (int q = threadIdx.x; q < (int)gridDim.x; q += FG_T) a += ld_coh(pc + q);
+  double a = coh_sum(pc, threadIdx.x, gridDim.x, FG_T, 1);
   a = fg_block_sum(a, red);
   if (threadIdx.x == 0) {
     const double beta = sqrt(a);
@@ -3463,8 +3520,7 @@ __global__ __launch_bounds__(FG_T) void k_fg_cgs(
     double* pc = part + (size_t)c * gridDim.x;
     if (threadIdx.x == 0) st_coh(pc + blockIdx.x, sb);
     if (!fg_last_block(&col->ticket, gridDim.x)) return;
-    double a = 0.0;
-    for (int q = threadIdx.x; q < (int)gridDim.x; q += FG_T) a += ld_coh(pc + q);
+    double a = coh_sum(pc, threadIdx.x, gridDim.x, FG_T, 1);
     a = fg_block_sum(a, red);
     if (threadIdx.x != 0) return;
     double* Hc = H + (size_t)c * (m + 1) * m;

@@ -2366,6 +2366,9 @@ kkt_status kkt_sync_report(kkt_handle h, kkt_report* out) {
   out->anorm_inf = bits_to_double(d.anorm);
   out->growth = eta_of(bits_to_double(d.umax), bits_to_double(d.anorm_f), 1.0);
   h->warnings = 0;
+  // the report is filled either way
+  if (d.nonfinite_in)
+    return fail(h, KKT_ERR_NONFINITE, "the refactorized values hold a NaN or an infinity");
   return KKT_OK;
 }
 

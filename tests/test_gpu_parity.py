@@ -507,12 +507,14 @@ def test_growth_matches_oracle(B, seed, layout):
         assert rep.growth == umax / rep.anorm_inf
         print(f"  growth {rep.growth:.6e} (oracle {ora.growth():.6e})", flush=True)
         assert abs(rep.growth - ora.growth()) <= 1e-14 * ora.growth()
-    # a non-finite entry makes the figure NaN (and raises the tiny-pivot flag)
+    # a non-finite entry: the report (still filled in, growth NaN) comes back
+    # with the NONFINITE status
     bad = seq[1][0].copy()
     bad[pat.rowptr[pat.n // 2]] = np.nan
     s.refactor(dev(bad))
-    rep = s.report()
-    assert np.isnan(rep.growth) and rep.warnings & (1 << binding.WARN_TINY_PIVOT)
+    with pytest.raises(binding.KKTError) as err:
+        s.report()
+    assert err.value.status == binding.ERR_NONFINITE
 
 
 def test_autograd_backward_refuses_replaced_factors():
@@ -1040,3 +1042,30 @@ def test_row_timeline_records_every_band_row():
         plain = binding.KKTSolver()
         plain.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
         plain.debug_timeline()
+
+
+def test_nonfinite_values_are_reported_not_waited_on():
+    # a refactorization whose values hold a NaN -- including one with the bit
+    # pattern the kernels use for "not yet computed" -- finishes and reports
+    # NONFINITE; a right-hand side with that pattern is solved (to NaNs) too
+    pat, seq = kktgen.make_sequence(100, 101, 2)
+    vals, b = seq[1]
+    s = binding.KKTSolver()
+    s.analyze(pat.n, pat.rowptr, pat.colind, seq[0][0])
+    sentinel = np.array([0x7FF0DEAD5EED0001], dtype=np.uint64).view(np.float64)[0]
+    for bad in (sentinel, np.nan, np.inf):
+        v = vals.copy()
+        v[len(v) // 2] = bad
+        s.refactor(dev(v))
+        torch.cuda.synchronize()
+        with pytest.raises(binding.KKTError) as err:
+            s.report()
+        assert err.value.status == binding.ERR_NONFINITE, bad
+    s.refactor(dev(vals))
+    x = s.solve(dev(b)).cpu().numpy()
+    assert s.report().eta <= 1e-12 and eta(pat.scipy(vals), x, b) <= 1e-12
+    bb = b.copy()
+    bb[3] = sentinel
+    x = s.solve(dev(bb)).cpu().numpy()
+    rep = s.report()
+    assert rep.warnings & (1 << binding.WARN_NOT_CONVERGED) and np.isnan(x).any()
