@@ -40,10 +40,11 @@ constexpr int WAVE = 64;
 #ifndef KKTLU_DLU_TILE
 #define KKTLU_DLU_TILE 32
 #endif
-// k_dlu_panel: threads per workgroup, one panel row or column each (70k
-// buses, refactorization ms: 256 2.86, 128 2.85, 64 2.83)
-#ifndef KKTLU_DLU_PANEL_THREADS
-#define KKTLU_DLU_PANEL_THREADS 64
+// k_dlu_panel: pivots between the barriers that let the row-panel wave follow
+// the diagonal block's wave (1056-row block, one dense LU in microseconds:
+// 1 540, 2 539, 4 541, 8 555, 16 594)
+#ifndef KKTLU_DLU_CHUNK
+#define KKTLU_DLU_CHUNK 4
 #endif
 constexpr int RG_TRIV = 8;  // lanes per row of k_refactor_trivial
 
@@ -989,81 +990,97 @@ __global__ __launch_bounds__(256) void k_tail_gather(int c0, int s, int S,
   }
 }
 
-// Panel k0: wave 0 of every workgroup factors the diagonal block in registers
-// (lane t owns row k0 + t; row k's entries are broadcast with readlane), then
-// workgroups b < nrw update rows k0 + NB + 256 b + tid of the column panel
-// (thread per row) and the others columns of the row panel (thread per
-// column).  The diagonal block in T stays untouched here (other workgroups may
-// still be reading it); its factored form goes to dsc and is copied into T by
-// the following k_dlu_update.
-template <int NB>
-__global__ __launch_bounds__(256) void k_dlu_panel(double* T, int S, int k0, int nrw,
-                                                   double* dsc, int s, DevStats* st, double prel) {
-  __shared__ double D[NB][NB + 1];
-  const int tid = threadIdx.x;
-  if (tid < WAVE) {
-    const int t = tid;
+// Panel k0 (m = S - k0 - NB rows and columns beyond the diagonal block),
+// workgroup b of cdiv(m, NB), two waves:
+//  * wave 0 holds the diagonal block's rows in lanes 0 .. NB-1 and the column
+//    panel's rows k0 + NB + NB b + (lane - NB) in lanes NB .. 2NB-1, and runs
+//    the right-looking elimination on all of them at once: pivot row k's
+//    entries are broadcast with readlane, every lane below it divides by u_kk
+//    and applies the row; the panel rows ride along at no extra cost.  The
+//    multipliers of column k go to LDS (Lt[k][t]) as they are made.
+//  * wave 1 solves NB columns of the row panel (thread per column) with those
+//    multipliers, CH pivots behind wave 0 (a barrier every CH pivots).
+// Every workgroup factors the diagonal block redundantly (no grid-wide
+// wait); the diagonal block in T stays untouched (other workgroups may still
+// be reading it): workgroup 0 leaves its factored form in dsc, which the
+// following k_dlu_update copies into T.  The arithmetic per entry is the
+// plain one (l = a / u_kk, a = fma(-l, u, a) in ascending k), so the factors
+// are those of the sparse refactorization bit for bit.
+template <int NB, int CH>
+__global__ __launch_bounds__(128) void k_dlu_panel(double* T, int S, int k0, int m, double* dsc,
+                                                   int s, DevStats* st, double prel) {
+  static_assert(2 * NB == WAVE && NB % CH == 0, "rows of the panel fill one wave");
+  __shared__ double Lt[NB][NB];      // Lt[k][t] = l_tk (t > k)
+  __shared__ double Ur[NB][NB + 1];  // U rows of the diagonal block
+  const int tid = threadIdx.x, lane = tid % WAVE, b = blockIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+  if (w == 0) {
     const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm_f) : 0.0;
+    const int q = NB * b + lane - NB;  // column-panel row, counted from k0 + NB
+    const bool act = lane < NB || q < m;
+    const size_t row = lane < NB ? (size_t)(k0 + lane) : (size_t)(k0 + NB + q);
     double r[NB];
 #pragma unroll
-    for (int j = 0; j < NB; j++) r[j] = t < NB ? T[(size_t)(k0 + t) * S + k0 + j] : 0.0;
+    for (int j = 0; j < NB; j++) r[j] = 0.0;
+    if (act)
+#pragma unroll
+      for (int j = 0; j < NB; j++) r[j] = T[row * S + k0 + j];
 #pragma unroll
     for (int k = 0; k < NB; k++) {
       // static pivoting of pivot k0 + k (real rows only) before its use
-      if (t == k && k0 + k < s && fabs(r[k]) < thr) {
-        if (blockIdx.x == 0) st->perturbed = 1;
+      if (lane == k && k0 + k < s && fabs(r[k]) < thr) {
+        if (b == 0) st->perturbed = 1;
         r[k] = perturb_pivot(r[k], thr);
       }
       const double ukk = readlane_d(r[k], k);
-      const double l = r[k] / ukk;
+      if (lane > k) {
+        const double l = r[k] / ukk;
 #pragma unroll
-      for (int j = k + 1; j < NB; j++) {
-        const double nv = __builtin_fma(-l, readlane_d(r[j], k), r[j]);
-        r[j] = t > k ? nv : r[j];
-      }
-      r[k] = t > k ? l : r[k];
-    }
-    if (t < NB) {
-#pragma unroll
-      for (int j = 0; j < NB; j++) D[t][j] = r[j];
-    }
-  }
-  __syncthreads();
-  if (blockIdx.x == 0)
-    for (int e = tid; e < NB * NB; e += blockDim.x) dsc[e] = D[e / NB][e % NB];
-  const int b = blockIdx.x;
-  if (b < nrw) {
-    const int i = k0 + NB + b * blockDim.x + tid;
-    if (i < S) {
-      double* Ti = T + (size_t)i * S + k0;
-      double r[NB];
-#pragma unroll
-      for (int j = 0; j < NB; j++) r[j] = Ti[j];
-#pragma unroll
-      for (int k = 0; k < NB; k++) {
-        const double l = r[k] / D[k][k];
+        for (int j = k + 1; j < NB; j++) r[j] = __builtin_fma(-l, readlane_d(r[j], k), r[j]);
         r[k] = l;
-#pragma unroll
-        for (int j = k + 1; j < NB; j++) r[j] = __builtin_fma(-l, D[k][j], r[j]);
+        if (lane < NB) Lt[k][lane] = l;
       }
+      if (k % CH == CH - 1) __syncthreads();
+    }
+    if (lane < NB) {
 #pragma unroll
-      for (int j = 0; j < NB; j++) Ti[j] = r[j];
+      for (int j = 0; j < NB; j++)
+        if (j >= lane) Ur[lane][j] = r[j];
+    } else if (act) {
+#pragma unroll
+      for (int j = 0; j < NB; j++) T[row * S + k0 + j] = r[j];
     }
   } else {
-    const int j = k0 + NB + (b - nrw) * blockDim.x + tid;
-    if (j < S) {
-      double c[NB];
+    const int jc = NB * b + lane;  // row-panel column, counted from k0 + NB
+    const bool act = lane < NB && jc < m;
+    double c[NB];
 #pragma unroll
-      for (int t = 0; t < NB; t++) c[t] = T[(size_t)(k0 + t) * S + j];
+    for (int t = 0; t < NB; t++) c[t] = 0.0;
+    if (act)
 #pragma unroll
-      for (int k = 0; k < NB; k++) {
+      for (int t = 0; t < NB; t++) c[t] = T[(size_t)(k0 + t) * S + k0 + NB + jc];
 #pragma unroll
-        for (int t = k + 1; t < NB; t++) c[t] = __builtin_fma(-D[t][k], c[k], c[t]);
-      }
+    for (int k = 0; k < NB; k++) {
+      if (k % CH == 0) __syncthreads();
 #pragma unroll
-      for (int t = 0; t < NB; t++) T[(size_t)(k0 + t) * S + j] = c[t];
+      for (int t = k + 1; t < NB; t++) c[t] = __builtin_fma(-Lt[k][t], c[k], c[t]);
+      // finish each stretch before the next barrier: left to itself the
+      // compiler sinks these FMAs into the guarded stores below and holds
+      // every multiplier loaded from LDS in registers until then
+      if (k % CH == CH - 1)
+#pragma unroll
+        for (int t = 0; t < NB; t++) asm volatile("" : "+v"(c[t]));
     }
+    if (act)
+#pragma unroll
+      for (int t = 0; t < NB; t++) T[(size_t)(k0 + t) * S + k0 + NB + jc] = c[t];
   }
+  __syncthreads();
+  if (b == 0)
+    for (int e = tid; e < NB * NB; e += blockDim.x) {
+      const int t = e / NB, j = e % NB;
+      dsc[e] = j < t ? Lt[j][t] : Ur[t][j];
+    }
 }
 
 // Trailing update of panel k0 on TS x TS tiles (TS / 16 x TS / 16 entries per
@@ -1189,6 +1206,7 @@ __global__ __launch_bounds__(256) void k_dlu_tasks(double* T, int S, int s, int 
     const int r0 = (type == 2 ? k : i) * NB, q0 = (type == 1 ? k : j) * NB;
     if (type == 0) {
       // diagonal tile: lane t owns row k0 + t, row k's entries by readlane
+      // (the lanes below the pivot under the execution mask, not by selects)
       const int k0 = k * NB;
       if (tid < WAVE) {
         const int t = tid;
@@ -1202,13 +1220,12 @@ __global__ __launch_bounds__(256) void k_dlu_tasks(double* T, int S, int s, int 
             r[kk] = perturb_pivot(r[kk], thr);
           }
           const double ukk = readlane_d(r[kk], kk);
-          const double l = r[kk] / ukk;
+          if (t > kk) {
+            const double l = r[kk] / ukk;
 #pragma unroll
-          for (int c = kk + 1; c < NB; c++) {
-            const double nv = __builtin_fma(-l, readlane_d(r[c], kk), r[c]);
-            r[c] = t > kk ? nv : r[c];
+            for (int c = kk + 1; c < NB; c++) r[c] = __builtin_fma(-l, readlane_d(r[c], kk), r[c]);
+            r[kk] = l;
           }
-          r[kk] = t > kk ? l : r[kk];
         }
         if (t < NB)
 #pragma unroll
@@ -4073,9 +4090,8 @@ void launch_dense_lu(double* T, int S, int s, double* dsc, DevStats* stats, doub
                      hipStream_t st) {
   for (int k0 = 0; k0 < S; k0 += DLU_NB) {
     const int rest = S - k0 - DLU_NB;
-    const int nrw = cdiv(rest, KKTLU_DLU_PANEL_THREADS);
-    hipLaunchKernelGGL(k_dlu_panel<DLU_NB>, dim3(std::max(1, 2 * nrw)),
-                       dim3(KKTLU_DLU_PANEL_THREADS), 0, st, T, S, k0, nrw, dsc, s, stats, prel);
+    hipLaunchKernelGGL((k_dlu_panel<DLU_NB, KKTLU_DLU_CHUNK>), dim3(std::max(1, cdiv(rest, DLU_NB))),
+                       dim3(2 * WAVE), 0, st, T, S, k0, rest, dsc, s, stats, prel);
     const int nt = std::max(1, cdiv(rest, KKTLU_DLU_TILE));
     hipLaunchKernelGGL((k_dlu_update<DLU_NB, KKTLU_DLU_TILE>), dim3(nt, nt), dim3(256), 0, st, T, S,
                        k0, (const double*)dsc);
