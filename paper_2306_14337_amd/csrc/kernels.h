@@ -300,16 +300,18 @@ void launch_tail_scatter(const LUView& lu, int c0, int s, int S, double* T, hipS
 void launch_dense_lu(double* T, int S, int s, double* dsc, DevStats* stats, double perturb_rel,
                      hipStream_t st);
 // The same LU as one dependency-driven launch over DLU_NB x DLU_NB tiles (nt =
-// S / DLU_NB per side): tasks (dense_lu_tasks) factor a diagonal tile, solve a
-// tile of the column or row panel against it, or apply one panel's update to
-// a tile; ver[nt * nt] counts the operations finished on each tile and is
-// what the tasks wait for.  Bitwise the same values as launch_dense_lu.
-// launch_dlu_reset zeroes ver and the task tickets (stream-ordered before).
+// S / DLU_NB per side): tasks (dense_lu_tasks) do one panel workgroup's work
+// (diagonal tile with one column and one row tile) or apply one panel's
+// update to a tile; ver[nt * nt] counts the operations finished on each tile
+// and is what the tasks wait for.  Dk: nt DLU_NB^2 doubles for the factored
+// diagonal tiles, installed in T by a second launch.  Bitwise the same values
+// as launch_dense_lu.  launch_dlu_reset zeroes ver and the task tickets
+// (stream-ordered before).
 std::vector<int> dense_lu_tasks(int nt);
 void launch_dlu_reset(int* ver, int nt, SyncState* ss, hipStream_t st);
 bool launch_dense_lu_tasks(double* T, int S, int s, const int* tasks, int ntasks, int* ver,
-                           SyncState* ss, int* stall, DevStats* stats, double perturb_rel,
-                           hipStream_t st);
+                           double* Dk, SyncState* ss, int* stall, DevStats* stats,
+                           double perturb_rel, hipStream_t st);
 void launch_tail_gather(const LUView& lu, int c0, const double* T, int S, hipStream_t st);
 // Dependency-driven triangular solve of one right-hand side in place on y.
 // mode 0: unit L rows, 1: U rows, 2: U^T columns (tptr/trow/tpos view of U),

@@ -1141,29 +1141,118 @@ __global__ __launch_bounds__(256) void k_dlu_update(double* T, int S, int k0,
 
 // Dense trailing block as one dependency-driven launch.  The block is cut
 // into NB x NB tiles; a task is one of
-//   D(k)      factor diagonal tile (k, k)                (wave 0: rows in lanes)
-//   C(i, k)   tile (i, k) := tile (i, k) U_kk^{-1}, L part  (thread per row)
-//   R(k, j)   tile (k, j) := L_kk^{-1} tile (k, j), U part  (thread per column)
+//   P(k, i)   the panel work of workgroup b = i - k - 1 of k_dlu_panel at
+//             panel k: factor diagonal tile (k, k) (redundantly, as there),
+//             finish column tile (i, k) in the same wave and row tile (k, i)
+//             in a second wave; i = nt: the diagonal tile alone (last panel)
 //   G(i,j,k)  tile (i, j) -= L(i, k) U(k, j)             (2 x 2 entries per thread)
 // with exactly the arithmetic of k_dlu_panel / k_dlu_update, so the values
 // are the same bit for bit.  ver[i * nt + j] counts the operations finished
-// on tile (i, j): the G updates of steps 0 .. min(i, j) - 1, then its own
-// D, C or R step.  A task waits for its inputs' counts (device-coherent
-// flags; tile data moves with device-coherent loads and stores, so no cache
-// maintenance is needed between XCDs) and hands out through eight ticket
-// streams in an order where every task's inputs come earlier, which keeps
-// the persistent grid deadlock-free as in the sparse refactorization.  Step
-// k + 1's panel is listed right after the updates of its own tiles, ahead of
-// the rest of step k's update (look-ahead of one panel), so the diagonal
-// chain does not wait for the bulk of the trailing matrix.
-// Task code: type << 18 | i << 12 | j << 6 | k (type 0 D, 1 C, 2 R, 3 G).
+// on tile (i, j): the G updates of steps 0 .. min(i, j) - 1, then its own P
+// step.  A task waits for its inputs' counts (device-coherent flags; tile
+// data moves with device-coherent loads and stores, so no cache maintenance
+// is needed between XCDs) and hands out through eight ticket streams in an
+// order where every task's inputs come earlier, which keeps the persistent
+// grid deadlock-free as in the sparse refactorization.  Panel k + 1 is listed
+// right after the updates of its own tiles, ahead of the rest of step k's
+// update (look-ahead of one panel), so the diagonal chain does not wait for
+// the bulk of the trailing matrix.  The factored diagonal tiles go to Dk
+// (P(k, k + 1) writes tile k's); k_dlu_install copies them into T after the
+// launch, as no task reads a diagonal tile after its own panel.
+// Task code: type << 21 | i << 14 | j << 7 | k (type 0 P, 1 G).
 template <int NB>
+struct DluPanelLds {
+  struct {
+    double Lt[NB][NB];      // Lt[k][t] = l_tk (t > k)
+    double Ur[NB][NB + 1];  // U rows of the diagonal tile
+  } fac;
+};
+
+template <int NB, int CH>
+__device__ __forceinline__ void dlu_panel_task(double* T, int S, int k0, int q0, double* D,
+                                               int s, DevStats* st, double thr, bool owner,
+                                               DluPanelLds<NB>& sh) {
+  const int tid = threadIdx.x, lane = tid % WAVE;
+  const int w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+  if (w == 0) {
+    // lanes 0 .. NB-1: rows of the diagonal tile; NB .. 2NB-1: column tile
+    const bool act = lane < NB || q0 >= 0;
+    const size_t row = lane < NB ? (size_t)(k0 + lane) : (size_t)(q0 + lane - NB);
+    double r[NB];
+#pragma unroll
+    for (int j = 0; j < NB; j++) r[j] = 0.0;
+    if (act)
+#pragma unroll
+      for (int j = 0; j < NB; j++) r[j] = ld_coh(T + row * S + k0 + j);
+#pragma unroll
+    for (int k = 0; k < NB; k++) {
+      if (lane == k && k0 + k < s && fabs(r[k]) < thr) {
+        if (owner) st->perturbed = 1;
+        r[k] = perturb_pivot(r[k], thr);
+      }
+      const double ukk = readlane_d(r[k], k);
+      if (lane > k) {
+        const double l = r[k] / ukk;
+#pragma unroll
+        for (int j = k + 1; j < NB; j++) r[j] = __builtin_fma(-l, readlane_d(r[j], k), r[j]);
+        r[k] = l;
+        if (lane < NB) sh.fac.Lt[k][lane] = l;
+      }
+      if (k % CH == CH - 1) __syncthreads();
+    }
+    if (lane < NB) {
+#pragma unroll
+      for (int j = 0; j < NB; j++)
+        if (j >= lane) sh.fac.Ur[lane][j] = r[j];
+    } else if (act) {
+#pragma unroll
+      for (int j = 0; j < NB; j++) st_coh(T + row * S + k0 + j, r[j]);
+    }
+  } else if (w == 1) {
+    // row tile, thread per column
+    const bool act = lane < NB && q0 >= 0;
+    double c[NB];
+#pragma unroll
+    for (int t = 0; t < NB; t++) c[t] = 0.0;
+    if (act)
+#pragma unroll
+      for (int t = 0; t < NB; t++) c[t] = ld_coh(T + (size_t)(k0 + t) * S + q0 + lane);
+#pragma unroll
+    for (int k = 0; k < NB; k++) {
+      if (k % CH == 0) __syncthreads();
+#pragma unroll
+      for (int t = k + 1; t < NB; t++) c[t] = __builtin_fma(-sh.fac.Lt[k][t], c[k], c[t]);
+      if (k % CH == CH - 1)
+#pragma unroll
+        for (int t = 0; t < NB; t++) asm volatile("" : "+v"(c[t]));
+    }
+    if (act)
+#pragma unroll
+      for (int t = 0; t < NB; t++) st_coh(T + (size_t)(k0 + t) * S + q0 + lane, c[t]);
+  } else {
+    for (int k = 0; k < NB; k += CH) __syncthreads();
+  }
+  __syncthreads();
+  if (owner)
+    for (int e = tid; e < NB * NB; e += blockDim.x) {
+      const int t = e / NB, j = e % NB;
+      D[e] = j < t ? sh.fac.Lt[j][t] : sh.fac.Ur[t][j];
+    }
+}
+
+template <int NB, int CH>
 __global__ __launch_bounds__(256) void k_dlu_tasks(double* T, int S, int s, int nt,
                                                    const int* __restrict__ tasks, int ntasks,
-                                                   int* ver, SyncState* ss, int nstreams,
-                                                   int* stall, DevStats* st, double prel) {
-  __shared__ double A[NB][NB + 1];
-  __shared__ double Bt[NB][NB];
+                                                   int* ver, double* Dk, SyncState* ss,
+                                                   int nstreams, int* stall, DevStats* st,
+                                                   double prel) {
+  __shared__ union {
+    DluPanelLds<NB> p;
+    struct {
+      double A[NB][NB + 1];
+      double Bt[NB][NB];
+    } g;
+  } sh;
   __shared__ int task_s, ok_s;
   const int tid = threadIdx.x, lane = tid % WAVE;
   const double thr = prel > 0.0 ? prel * __longlong_as_double((long long)st->anorm_f) : 0.0;
@@ -1175,18 +1264,16 @@ __global__ __launch_bounds__(256) void k_dlu_tasks(double* T, int S, int s, int 
     __syncthreads();
     const int code = task_s;
     if (code < 0) break;
-    const int type = code >> 18, i = (code >> 12) & 63, j = (code >> 6) & 63, k = code & 63;
+    const int type = code >> 21, i = (code >> 14) & 127, j = (code >> 7) & 127, k = code & 127;
     // inputs: (tile index, count it must reach)
     if (tid == 0) {
       int dep[3], want[3], nd = 0;
       if (type == 0) {
         dep[nd] = k * nt + k, want[nd++] = k;
-      } else if (type == 1) {
-        dep[nd] = i * nt + k, want[nd++] = k;
-        dep[nd] = k * nt + k, want[nd++] = k + 1;
-      } else if (type == 2) {
-        dep[nd] = k * nt + j, want[nd++] = k;
-        dep[nd] = k * nt + k, want[nd++] = k + 1;
+        if (i < nt) {
+          dep[nd] = i * nt + k, want[nd++] = k;
+          dep[nd] = k * nt + i, want[nd++] = k;
+        }
       } else {
         dep[nd] = i * nt + j, want[nd++] = k;
         dep[nd] = i * nt + k, want[nd++] = k + 1;
@@ -1203,111 +1290,62 @@ __global__ __launch_bounds__(256) void k_dlu_tasks(double* T, int S, int s, int 
     }
     __syncthreads();
     if (!ok_s) break;
-    const int r0 = (type == 2 ? k : i) * NB, q0 = (type == 1 ? k : j) * NB;
     if (type == 0) {
-      // diagonal tile: lane t owns row k0 + t, row k's entries by readlane
-      // (the lanes below the pivot under the execution mask, not by selects)
-      const int k0 = k * NB;
-      if (tid < WAVE) {
-        const int t = tid;
-        double r[NB];
-#pragma unroll
-        for (int c = 0; c < NB; c++) r[c] = t < NB ? ld_coh(T + (size_t)(k0 + t) * S + k0 + c) : 0.0;
-#pragma unroll
-        for (int kk = 0; kk < NB; kk++) {
-          if (t == kk && k0 + kk < s && fabs(r[kk]) < thr) {
-            st->perturbed = 1;
-            r[kk] = perturb_pivot(r[kk], thr);
-          }
-          const double ukk = readlane_d(r[kk], kk);
-          if (t > kk) {
-            const double l = r[kk] / ukk;
-#pragma unroll
-            for (int c = kk + 1; c < NB; c++) r[c] = __builtin_fma(-l, readlane_d(r[c], kk), r[c]);
-            r[kk] = l;
-          }
-        }
-        if (t < NB)
-#pragma unroll
-          for (int c = 0; c < NB; c++) st_coh(T + (size_t)(k0 + t) * S + k0 + c, r[c]);
-        stores_done();
+      dlu_panel_task<NB, CH>(T, S, k * NB, i < nt ? i * NB : -1, Dk + (size_t)k * NB * NB, s, st,
+                             thr, i == k + 1, sh.p);
+      stores_done();
+      __syncthreads();  // every store of the task complete
+      if (tid == 0 && i < nt) {
+        st_flag(ver + i * nt + k, k + 1);
+        st_flag(ver + k * nt + i, k + 1);
       }
     } else {
-      // the factored diagonal tile (k, k) in LDS
-      const int k0 = k * NB;
-      if (type != 3) {
-        for (int e = tid; e < NB * NB; e += blockDim.x)
-          A[e / NB][e % NB] = ld_coh(T + (size_t)(k0 + e / NB) * S + k0 + e % NB);
-      } else {
-        // A := L(i, k), Bt := U(k, j)
-        for (int e = tid; e < NB * NB; e += blockDim.x) {
-          A[e / NB][e % NB] = ld_coh(T + (size_t)(i * NB + e / NB) * S + k0 + e % NB);
-          Bt[e / NB][e % NB] = ld_coh(T + (size_t)(k0 + e / NB) * S + j * NB + e % NB);
-        }
+      // A := L(i, k), Bt := U(k, j); 2 x 2 entries per thread: rows ty + 16 a,
+      // columns tx + 16 c
+      const int k0 = k * NB, r0 = i * NB, q0 = j * NB;
+      for (int e = tid; e < NB * NB; e += blockDim.x) {
+        sh.g.A[e / NB][e % NB] = ld_coh(T + (size_t)(r0 + e / NB) * S + k0 + e % NB);
+        sh.g.Bt[e / NB][e % NB] = ld_coh(T + (size_t)(k0 + e / NB) * S + q0 + e % NB);
       }
       __syncthreads();
-      if (type == 1) {
-        if (tid < NB) {
-          double* Ti = T + (size_t)(r0 + tid) * S + q0;
-          double r[NB];
+      const int tx = tid % 16, ty = tid / 16;
+      double acc[2][2];
 #pragma unroll
-          for (int c = 0; c < NB; c++) r[c] = ld_coh(Ti + c);
+      for (int a = 0; a < 2; a++)
 #pragma unroll
-          for (int kk = 0; kk < NB; kk++) {
-            const double l = r[kk] / A[kk][kk];
-            r[kk] = l;
-#pragma unroll
-            for (int c = kk + 1; c < NB; c++) r[c] = __builtin_fma(-l, A[kk][c], r[c]);
-          }
-#pragma unroll
-          for (int c = 0; c < NB; c++) st_coh(Ti + c, r[c]);
-        }
-      } else if (type == 2) {
-        if (tid < NB) {
-          const int q = q0 + tid;
-          double cv[NB];
-#pragma unroll
-          for (int t = 0; t < NB; t++) cv[t] = ld_coh(T + (size_t)(r0 + t) * S + q);
-#pragma unroll
-          for (int kk = 0; kk < NB; kk++) {
-#pragma unroll
-            for (int t = kk + 1; t < NB; t++) cv[t] = __builtin_fma(-A[t][kk], cv[kk], cv[t]);
-          }
-#pragma unroll
-          for (int t = 0; t < NB; t++) st_coh(T + (size_t)(r0 + t) * S + q, cv[t]);
-        }
-      } else {
-        // 2 x 2 entries per thread: rows ty + 16 a, columns tx + 16 c
-        const int tx = tid % 16, ty = tid / 16;
-        double acc[2][2];
-#pragma unroll
-        for (int a = 0; a < 2; a++)
-#pragma unroll
-          for (int c = 0; c < 2; c++)
-            acc[a][c] = ld_coh(T + (size_t)(r0 + ty + 16 * a) * S + q0 + tx + 16 * c);
+        for (int c = 0; c < 2; c++)
+          acc[a][c] = ld_coh(T + (size_t)(r0 + ty + 16 * a) * S + q0 + tx + 16 * c);
 #pragma unroll 4
-        for (int kk = 0; kk < NB; kk++) {
-          double lv[2], uv[2];
+      for (int kk = 0; kk < NB; kk++) {
+        double lv[2], uv[2];
 #pragma unroll
-          for (int a = 0; a < 2; a++) lv[a] = A[ty + 16 * a][kk];
+        for (int a = 0; a < 2; a++) lv[a] = sh.g.A[ty + 16 * a][kk];
 #pragma unroll
-          for (int c = 0; c < 2; c++) uv[c] = Bt[kk][tx + 16 * c];
-#pragma unroll
-          for (int a = 0; a < 2; a++)
-#pragma unroll
-            for (int c = 0; c < 2; c++) acc[a][c] = __builtin_fma(-lv[a], uv[c], acc[a][c]);
-        }
+        for (int c = 0; c < 2; c++) uv[c] = sh.g.Bt[kk][tx + 16 * c];
 #pragma unroll
         for (int a = 0; a < 2; a++)
 #pragma unroll
-          for (int c = 0; c < 2; c++)
-            st_coh(T + (size_t)(r0 + ty + 16 * a) * S + q0 + tx + 16 * c, acc[a][c]);
+          for (int c = 0; c < 2; c++) acc[a][c] = __builtin_fma(-lv[a], uv[c], acc[a][c]);
       }
+#pragma unroll
+      for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int c = 0; c < 2; c++)
+          st_coh(T + (size_t)(r0 + ty + 16 * a) * S + q0 + tx + 16 * c, acc[a][c]);
       stores_done();
+      __syncthreads();  // every store of the task complete
+      if (tid == 0) st_flag(ver + i * nt + j, k + 1);
     }
-    __syncthreads();  // every store of the task complete
-    if (tid == 0) st_flag(ver + (type == 2 ? k : i) * nt + (type == 1 ? k : j), k + 1);
   }
+}
+
+// The factored diagonal tiles (Dk, tile k at Dk + k NB^2) into T.
+template <int NB>
+__global__ __launch_bounds__(256) void k_dlu_install(double* T, int S, const double* __restrict__ Dk) {
+  const int k = blockIdx.x;
+  const double* D = Dk + (size_t)k * NB * NB;
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x)
+    T[(size_t)(k * NB + e / NB) * S + k * NB + e % NB] = D[e];
 }
 
 __global__ void k_dlu_reset(int* ver, int count, SyncState* ss) {
@@ -4027,26 +4065,22 @@ void launch_tail_scatter(const LUView& lu, int c0, int s, int S, double* T, hipS
 
 std::vector<int> dense_lu_tasks(int nt) {
   std::vector<int> t;
-  auto code = [](int type, int i, int j, int k) { return type << 18 | i << 12 | j << 6 | k; };
+  auto code = [](int type, int i, int j, int k) { return type << 21 | i << 14 | j << 7 | k; };
   auto panel = [&](int k) {
-    t.push_back(code(0, k, k, k));
-    for (int r = k + 1; r < nt; r++) {
-      t.push_back(code(1, r, k, k));
-      t.push_back(code(2, k, r, k));
-    }
+    for (int i = k + 1; i < std::max(nt, k + 2); i++) t.push_back(code(0, i, 0, k));
   };
   panel(0);
   for (int k = 0; k + 1 < nt; k++) {
     const int n1 = k + 1;
     // the next panel's tiles, then that panel, then the rest of step k
-    t.push_back(code(3, n1, n1, k));
+    t.push_back(code(1, n1, n1, k));
     for (int r = n1 + 1; r < nt; r++) {
-      t.push_back(code(3, r, n1, k));
-      t.push_back(code(3, n1, r, k));
+      t.push_back(code(1, r, n1, k));
+      t.push_back(code(1, n1, r, k));
     }
     panel(n1);
     for (int i = n1 + 1; i < nt; i++)
-      for (int j = n1 + 1; j < nt; j++) t.push_back(code(3, i, j, k));
+      for (int j = n1 + 1; j < nt; j++) t.push_back(code(1, i, j, k));
   }
   return t;
 }
@@ -4057,25 +4091,28 @@ void launch_dlu_reset(int* ver, int nt, SyncState* ss, hipStream_t st) {
 }
 
 bool launch_dense_lu_tasks(double* T, int S, int s, const int* tasks, int ntasks, int* ver,
-                           SyncState* ss, int* stall, DevStats* stats, double prel,
+                           double* Dk, SyncState* ss, int* stall, DevStats* stats, double prel,
                            hipStream_t st) {
   if (S <= 0 || S % DLU_NB != 0 || S / DLU_NB > 64) return false;
+  auto kern = k_dlu_tasks<DLU_NB, KKTLU_DLU_CHUNK>;
   static int ncu = 0, occ = 0;
   if (ncu == 0) {
     int d = 0;
     (void)hipGetDevice(&d);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d);
     if (ncu <= 0) ncu = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, reinterpret_cast<const void*>(&k_dlu_tasks<DLU_NB>), 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(kern),
+                                                     256, 0) != hipSuccess ||
         occ <= 0)
       occ = 1;
   }
   // every workgroup resident (each ticket stream needs a running workgroup)
+  const int nt = S / DLU_NB;
   const int grid = std::max(1, std::min(ncu * occ, ntasks));
   const int nstreams = std::min(TICKET_STREAMS, grid);
-  hipLaunchKernelGGL(k_dlu_tasks<DLU_NB>, dim3(grid), dim3(256), 0, st, T, S, s, S / DLU_NB, tasks,
-                     ntasks, ver, ss, nstreams, stall, stats, prel);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, T, S, s, nt, tasks, ntasks, ver, Dk, ss,
+                     nstreams, stall, stats, prel);
+  hipLaunchKernelGGL(k_dlu_install<DLU_NB>, dim3(nt), dim3(256), 0, st, T, S, (const double*)Dk);
   return true;
 }
 

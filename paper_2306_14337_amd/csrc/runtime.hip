@@ -1798,7 +1798,8 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   }
   if (h->tail_s > 0 &&
       ((ks = dalloc(h, &h->tail_T, (size_t)h->tail_S * h->tail_S)) != KKT_OK ||
-       (ks = dalloc(h, &h->tail_dsc, (size_t)DLU_NB * DLU_NB)) != KKT_OK ||
+       (ks = dalloc(h, &h->tail_dsc, (size_t)DLU_NB * DLU_NB *
+                                         (h->opt.dense_lu == 1 ? h->tail_S / DLU_NB : 1))) != KKT_OK ||
        (ks = dalloc(h, &h->tail_rhs, (size_t)h->tail_S * 8)) != KKT_OK)) {
     free_device(h);
     return ks;
@@ -2056,7 +2057,7 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
       if (h->dlu_tasks) {
         launch_dlu_reset(h->dlu_ver, h->tail_S / DLU_NB, h->ss, s);
         if (!launch_dense_lu_tasks(h->tail_T, h->tail_S, h->tail_s, h->dlu_tasks, h->dlu_ntasks,
-                                   h->dlu_ver, h->ss, &h->st->stall, h->st,
+                                   h->dlu_ver, h->tail_dsc, h->ss, &h->st->stall, h->st,
                                    h->opt.pivot_perturb_rel, s))
           return fail(h, KKT_ERR_DEVICE, "dense-block task launch not launchable");
       } else
