@@ -407,9 +407,9 @@ void launch_gather_prep(int n, const int* perm, const double* scale, const doubl
                         int mask, hipStream_t s);
 
 // pivot statistics (min/max |u_kk|, tiny test against tiny_rel * ||A||_inf,
-// max |u_ij| over U)
-void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStream_t s,
-                        Inst in = Inst());
+// max |u_ij| over U); red: RED_SCRATCH doubles for the per-workgroup partials
+void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, double* red,
+                        hipStream_t s, Inst in = Inst());
 
 // A copy + ||A||_inf (and, if ss != nullptr, the sync_prep of slot 0; if
 // rowabs != nullptr, every row's absolute sum; if luA != nullptr, the values

@@ -1988,7 +1988,8 @@ __device__ __forceinline__ double block_nanmax(double v, double* red) {
 __global__ __launch_bounds__(256) void k_pivot_stats(int n, const int* __restrict__ rowptr,
                                                      const int* __restrict__ diag,
                                                      const double* __restrict__ val0, DevStats* st,
-                                                     double tiny_rel, Inst in) {
+                                                     double tiny_rel, double* __restrict__ red,
+                                                     Inst in) {
   const int lane = threadIdx.x % WAVE, g = lane / RG, gl = lane % RG;
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nw = gridDim.x * blockDim.x / WAVE;
@@ -2029,8 +2030,57 @@ __global__ __launch_bounds__(256) void k_pivot_stats(int n, const int* __restric
           tiny |= !(a0[u] >= tiny_rel * anorm) || isinf(a0[u]);
         }
       }
-      for (int t = d[u] + gl + RG; t < e[u]; t += RG) um = nanmax(um, fabs(vr[u][t]));
+      // long U parts (the rows next to and inside the dense block hold up to
+      // a thousand entries): eight loads in flight per lane
+      for (int t = d[u] + gl + RG; t < e[u]; t += 8 * RG) {
+        double q[8];
+#pragma unroll
+        for (int v = 0; v < 8; v++) q[v] = t + v * RG < e[u] ? fabs(vr[u][t + v * RG]) : 0.0;
+#pragma unroll
+        for (int v = 0; v < 8; v++) um = nanmax(um, q[v]);
+      }
     }
+  }
+  for (int off = WAVE / 2; off > 0; off >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, off, WAVE));
+    mx = fmax(mx, __shfl_xor(mx, off, WAVE));
+    tiny |= __shfl_xor(tiny, off, WAVE);
+  }
+  __shared__ double rmn[4], rmx[4], rum[4];
+  __shared__ int rt[4];
+  um = block_nanmax(um, rum);
+  const int w = threadIdx.x / WAVE;
+  if (threadIdx.x % WAVE == 0) {
+    rmn[w] = mn;
+    rmx[w] = mx;
+    rt[w] = tiny;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < (int)(blockDim.x / WAVE); q++) {
+      mn = fmin(mn, rmn[q]);
+      mx = fmax(mx, rmx[q]);
+      tiny |= rt[q];
+    }
+    // the workgroup's partial results; k_pivot_stats_final folds them in
+    // (same-address atomics from every workgroup cost more than the pass)
+    double* o = red + 4 * blockIdx.x;
+    o[0] = mn;
+    o[1] = mx;
+    o[2] = um;
+    o[3] = tiny ? 1.0 : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pivot_stats_final(int nb, const double* __restrict__ red,
+                                                           DevStats* st) {
+  double mn = __builtin_huge_val(), mx = 0.0, um = 0.0;
+  int tiny = 0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    mn = fmin(mn, red[4 * b]);
+    mx = fmax(mx, red[4 * b + 1]);
+    um = nanmax(um, red[4 * b + 2]);
+    tiny |= red[4 * b + 3] != 0.0;
   }
   for (int off = WAVE / 2; off > 0; off >>= 1) {
     mn = fmin(mn, __shfl_xor(mn, off, WAVE));
@@ -3802,10 +3852,15 @@ void launch_refactor_rows(const LUView& lu, const int* rows, int nrows, int maxl
   }
 }
 
-void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, hipStream_t s, Inst in) {
-  const int total = lu.n * in.count;
-  hipLaunchKernelGGL(k_pivot_stats, dim3(rows_grid(total)), dim3(256), 0, s, total, lu.rowptr,
-                     lu.diag, lu.val, st, tiny_rel, in);
+void launch_pivot_stats(const LUView& lu, DevStats* st, double tiny_rel, double* red,
+                        hipStream_t s, Inst in) {
+  // 70k buses, us: 2048 workgroups 35 + 6 (final pass), 1024 43 + 4; one
+  // pass ending in same-address atomics from all 1024 workgroups: 69
+  const int total = lu.n * in.count, nb = std::max(1, std::min(cdiv(total, 32), 2048));
+  static_assert(4 * 2048 <= RED_SCRATCH, "pivot statistics partials exceed their buffer");
+  hipLaunchKernelGGL(k_pivot_stats, dim3(nb), dim3(256), 0, s, total, lu.rowptr, lu.diag, lu.val,
+                     st, tiny_rel, red, in);
+  hipLaunchKernelGGL(k_pivot_stats_final, dim3(1), dim3(256), 0, s, nb, (const double*)red, st);
 }
 
 // Row passes with a two-stage maximum (red != nullptr): a larger grid keeps

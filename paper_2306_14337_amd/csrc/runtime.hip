@@ -1869,7 +1869,7 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
   launch_reset_stats(h->st, 1 | 2 | 8, nullptr);
   launch_copy_anorm(n, h->a_rowptr, h->a_col, h->aval, h->aval, h->st, nullptr, nullptr,
                     h->rowabs, nullptr, nullptr, nullptr, 1, h->ascale, h->avs, h->inst);
-  launch_pivot_stats(view(h), h->st, h->opt.tiny_pivot_rel, nullptr, h->inst);
+  launch_pivot_stats(view(h), h->st, h->opt.tiny_pivot_rel, h->red, nullptr, h->inst);
   if (h->ref_map) launch_build_refmap(view(h), h->ref_moff, h->ref_map, h->ref_flat, nullptr);
   // the dense block's copy of the pivoting pass's factors (the solves read it)
   if (h->tail_s > 0)
@@ -2072,7 +2072,7 @@ static kkt_status refactor_launch(kkt_handle h, const double* d_values, hipStrea
       launch_refactor_rows(lu, h->lev_rows + A.lev_ptr[l], A.lev_ptr[l + 1] - A.lev_ptr[l],
                            A.lev_maxlen[l], fa, h->st, h->opt.pivot_perturb_rel, s);
   }
-  launch_pivot_stats(lu, h->st, h->opt.tiny_pivot_rel, s, in);
+  launch_pivot_stats(lu, h->st, h->opt.tiny_pivot_rel, h->red, s, in);
   return KKT_OK;
 }
 
