@@ -1714,6 +1714,25 @@ __global__ __launch_bounds__(256) void k_tail_mw(const int* __restrict__ gate, c
   int spins = 0;
   double* yb = y + c0;
   double acc = 0.0;
+  // wave 0 finishes the block: its rows of the diagonal block and its
+  // right-hand side are loaded now (inputs of earlier launches), off the
+  // critical path that runs through the dependency polls below
+  const int lr = tid, rr = lr % TB, rw = b * TB + rr;
+  double md[TB], rh = 0.0, dinv = 1.0;
+  if (tid < WAVE) {
+#pragma unroll
+    for (int q = 0; q < TB; q++) md[q] = M(rw, b * TB + q);
+    rh = (lr < TB && rw < s) ? rhs[rw] : 0.0;
+    if (MODE == 1 || MODE == 2) {
+      // the row's own diagonal entry, inverted once here: the triangle's
+      // chain below then multiplies instead of dividing (one more rounding
+      // per entry of x, far inside the solve's accuracy)
+      double d = 1.0;
+#pragma unroll
+      for (int q = 0; q < TB; q++) d = rr == q ? md[q] : d;
+      dinv = 1.0 / d;
+    }
+  }
   // dependency blocks in solve order: 0 .. b-1 (forward), nb-1 .. b+1 (backward)
   const int ndep = fwd ? b : nb - 1 - b;
   double m[4], mn[4];
@@ -1744,17 +1763,11 @@ __global__ __launch_bounds__(256) void k_tail_mw(const int* __restrict__ gate, c
   if (cl == 0) sacc[r] = acc;
   __syncthreads();
   if (tid < WAVE) {
-    const int lr = tid;
-    const int rr = lr % TB;
-    const int rw = b * TB + rr;
-    double md[TB];
-#pragma unroll
-    for (int q = 0; q < TB; q++) md[q] = M(rw, b * TB + q);
-    double xr = (lr < TB && rw < s) ? rhs[rw] - sacc[rr] : 0.0;
+    double xr = (lr < TB && rw < s) ? rh - sacc[rr] : 0.0;
 #pragma unroll
     for (int st = 0; st < TB; st++) {
       const int q = fwd ? st : TB - 1 - st;
-      if (MODE == 1 || MODE == 2) xr = lr == q ? xr / md[q] : xr;
+      if (MODE == 1 || MODE == 2) xr = lr == q ? xr * dinv : xr;
       const double xq = readlane_d(xr, q);
       const bool later = fwd ? lr > q : lr < q;
       const double nx = __builtin_fma(-md[q], xq, xr);
