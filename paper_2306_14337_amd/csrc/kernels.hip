@@ -1441,6 +1441,10 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(const int* __restrict__ gat
 #pragma unroll
     for (int r = 0; r < NR; r++) ci[r] = r < nr ? c[(size_t)r * ld + i] : 0.0;
     const double dv = (MODE == 1 || MODE == 2) && active ? val[dpos] : 1.0;
+    // inverted once, off the critical path: the chain block's row-by-row
+    // steps below multiply instead of dividing (one more rounding per entry
+    // of y, far inside the solve's accuracy)
+    const double dvi = 1.0 / dv;
     if (chain) {
       // the block's own triangle into LDS (issued before the waits below)
       const int b = ch_base[tk];
@@ -1498,7 +1502,7 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(const int* __restrict__ gat
 #pragma unroll
         for (int r = 0; r < NR; r++) {
           double yv = ci[r] - s[r];
-          if (MODE == 1 || MODE == 2) yv /= dv;
+          if (MODE == 1 || MODE == 2) yv *= dvi;
           const double ys = readlane_d(yv, sg << lg);
           s[r] += tv * ys;
         }
@@ -1507,7 +1511,7 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(const int* __restrict__ gat
 #pragma unroll
     for (int r = 0; r < NR; r++) {
       double yv = ci[r] - s[r];
-      if (MODE == 1 || MODE == 2) yv /= dv;
+      if (MODE == 1 || MODE == 2) yv *= dvi;
       if (r < nr) st_coh(y + (size_t)r * ld + i, yv);
     }
   }
