@@ -1462,24 +1462,38 @@ __global__ __launch_bounds__(256) void k_trisolve_sn(const int* __restrict__ gat
 #pragma unroll
     for (int r = 0; r < NR; r++) s[r] = 0.0;
     constexpr int VB = NR == 1 ? 8 : (NR <= 4 ? 2 : 1);
+    // batches of VB entries per lane; the next batch's column indices and
+    // values load while this batch's y values are polled (one memory round
+    // trip per batch on the path after a late input, not two)
+    int kn[VB];
+    double vn[VB];
+    auto load_batch = [&](int q0) {
+#pragma unroll
+      for (int u = 0; u < VB; u++) {
+        const int q = q0 + u * G;
+        kn[u] = n;
+        vn[u] = 0.0;
+        if (q < ee) {
+          kn[u] = MODE <= 1 ? col[q] : trow[q];
+          vn[u] = MODE <= 1 ? val[q] : val[tpos[q]];
+        }
+      }
+    };
+    load_batch(eb + gl);
     for (int q0 = eb + gl; q0 < ee; q0 += VB * G) {
       int kk[VB];
       double v[VB], yk[VB][NR];
 #pragma unroll
       for (int u = 0; u < VB; u++) {
-        const int q = q0 + u * G;
-        kk[u] = n;
-        v[u] = 0.0;
-        if (q < ee) {
-          kk[u] = MODE <= 1 ? col[q] : trow[q];
-          v[u] = MODE <= 1 ? val[q] : val[tpos[q]];
-        }
+        kk[u] = kn[u];
+        v[u] = vn[u];
       }
 #pragma unroll
       for (int u = 0; u < VB; u++)
 #pragma unroll
         for (int r = 0; r < NR; r++)
           yk[u][r] = (q0 + u * G < ee && r < nr) ? ld_coh(y + (size_t)r * ld + kk[u]) : 0.0;
+      if (q0 + VB * G < ee) load_batch(q0 + VB * G);
 #pragma unroll
       for (int u = 0; u < VB; u++)
 #pragma unroll
