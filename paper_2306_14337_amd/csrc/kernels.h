@@ -71,8 +71,13 @@ struct FgParams {
 // FG_BLOCKS x 32), the two Gram-Schmidt coefficient vectors (32 per column),
 // and per column the Hessenberg matrix ((m+1) x m), rotations (m each), g
 // (m+1) and y (m).
+// Residual pass tickets: FG_TICK_GROUPS first-level counters per column,
+// each on its own 128-byte line (FG_TICK_STRIDE unsigned ints apart).
+constexpr int FG_TICK_GROUPS = 16;
+constexpr int FG_TICK_STRIDE = 32;
 struct FgBufs {
   FgState* fs;
+  unsigned int* tick1;  // FG_MAX_COLS x FG_TICK_GROUPS x FG_TICK_STRIDE
   double* part;
   double* hbuf;
   double* h2buf;
@@ -93,7 +98,7 @@ void set_launch_gate(const int* gate);
 // on the current device).  False if the device symbol could not be written.
 bool set_debug_schedule(int on);
 
-void launch_fg_begin(FgState* fs, int reset_summary, hipStream_t s);
+void launch_fg_begin(const FgBufs& fb, int reset_summary, hipStream_t s);
 // r = b - op(A) x for ncols columns (column stride n) and the stop test after
 // it_now iterations (first: the check after the direct solve; batch: r only,
 // the test follows in launch_fg_check_batch after the per-instance maxima).

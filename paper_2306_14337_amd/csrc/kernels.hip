@@ -3277,6 +3277,38 @@ __device__ bool fg_last_block(unsigned int* ticket, unsigned int nb) {
   return last != 0;
 }
 
+// fg_last_block over two levels: workgroup b counts in at counter
+// b % FG_TICK_GROUPS of tick1 (each on its own line, the group's workgroups
+// share an XCD), the last of each group at ticket.  A thousand workgroups at
+// one address serialise at the point of coherence (about 60 us at 1024);
+// here each counter takes at most nb / FG_TICK_GROUPS of them.
+__device__ bool fg_last_block2(unsigned int* ticket, unsigned int* tick1, unsigned int nb) {
+  __shared__ int last;
+  stores_done();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned int G = (unsigned int)FG_TICK_GROUPS;
+    const unsigned int g = blockIdx.x % G;
+    const unsigned int ng = (nb - g + G - 1) / G;  // workgroups of group g
+    unsigned int* t1 = tick1 + g * FG_TICK_STRIDE;
+    last = 0;
+    const unsigned int a =
+        __hip_atomic_fetch_add(t1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (a == ng - 1u) {
+      __hip_atomic_store(t1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned int ngr = nb < G ? nb : G;
+      const unsigned int t =
+          __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (t == ngr - 1u) {
+        last = 1;
+        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+  __syncthreads();
+  return last != 0;
+}
+
 // Workgroup sum (fixed order), valid in thread 0.
 __device__ __forceinline__ double fg_block_sum(double v, double* red) {
   v = wave_sum(v);
@@ -3356,8 +3388,10 @@ __device__ void fg_decide(FgState* fs, int c, int ncols, double eta, int it_now,
   }
 }
 
-__global__ void k_fg_begin(FgState* fs, int reset_summary) {
+__global__ void k_fg_begin(FgState* fs, unsigned int* tick1, int reset_summary) {
   const int t = threadIdx.x;
+  // first-level residual tickets (a stalled earlier pass may have left counts)
+  for (int e = t; e < FG_MAX_COLS * FG_TICK_GROUPS; e += blockDim.x) tick1[e * FG_TICK_STRIDE] = 0u;
   if (t < FG_MAX_COLS) {
     FgCol* col = &fs->col[t];
     col->stop = 0;
@@ -3387,8 +3421,8 @@ template <bool BATCH>
 __global__ __launch_bounds__(FG_T) void k_fg_resid(
     int n, const int* __restrict__ ptr, const int* __restrict__ idx, const int* __restrict__ pos,
     const double* __restrict__ aval, const double* __restrict__ b, const double* __restrict__ x,
-    double* __restrict__ r, double* __restrict__ part, FgState* fs, const DevStats* st,
-    int use_anorm1, int ncols, int it_now, int first, FgParams p, Inst in) {
+    double* __restrict__ r, double* __restrict__ part, FgState* fs, unsigned int* tick1,
+    const DevStats* st, int use_anorm1, int ncols, int it_now, int first, FgParams p, Inst in) {
   const int c = blockIdx.y;
   FgCol* col = &fs->col[c];
   if (!first && ld_flag(&col->stop)) return;
@@ -3481,7 +3515,8 @@ __global__ __launch_bounds__(FG_T) void k_fg_resid(
     st_coh(pc + 2 * blockIdx.x, rm);
     st_coh(pc + 2 * blockIdx.x + 1, xm);
   }
-  if (!fg_last_block(&col->ticket, gridDim.x)) return;
+  if (!fg_last_block2(&col->ticket, tick1 + (size_t)c * FG_TICK_GROUPS * FG_TICK_STRIDE, gridDim.x))
+    return;
   double a = coh_max(pc, threadIdx.x, gridDim.x, FG_T, 2);
   double bm = coh_max(pc + 1, threadIdx.x, gridDim.x, FG_T, 2);
   a = block_nanmax(a, red[0]);
@@ -3794,8 +3829,8 @@ int fg_resid_grid(int n) {
 }
 }  // namespace
 
-void launch_fg_begin(FgState* fs, int reset_summary, hipStream_t s) {
-  hipLaunchKernelGGL(k_fg_begin, dim3(1), dim3(64), 0, s, fs, reset_summary);
+void launch_fg_begin(const FgBufs& fb, int reset_summary, hipStream_t s) {
+  hipLaunchKernelGGL(k_fg_begin, dim3(1), dim3(64), 0, s, fb.fs, fb.tick1, reset_summary);
 }
 
 void launch_fg_resid(int n, int ncols, const int* ptr, const int* idx, const int* pos,
@@ -3808,10 +3843,10 @@ void launch_fg_resid(int n, int ncols, const int* ptr, const int* idx, const int
   const dim3 grid(batch ? fg_resid_grid(n) : std::min(1024, fg_resid_grid(n)), ncols);
   if (batch)
     hipLaunchKernelGGL(k_fg_resid<true>, grid, dim3(FG_T), 0, s, n, ptr, idx, pos, aval, b, x, r,
-                       fb.part, fb.fs, st, use_anorm1, ncols, it_now, first, p, in);
+                       fb.part, fb.fs, fb.tick1, st, use_anorm1, ncols, it_now, first, p, in);
   else
     hipLaunchKernelGGL(k_fg_resid<false>, grid, dim3(FG_T), 0, s, n, ptr, idx, pos, aval, b, x, r,
-                       fb.part, fb.fs, st, use_anorm1, ncols, it_now, first, p, in);
+                       fb.part, fb.fs, fb.tick1, st, use_anorm1, ncols, it_now, first, p, in);
 }
 
 void launch_fg_check_batch(int count, const double* inst, const FgBufs& fb, const DevStats* st,

@@ -696,7 +696,7 @@ void solve_group_async(kkt_handle h, const FgBufs& fb, char op, int g, const dou
   const kkt_options& o = h->opt;
   const FgParams p{o.eta_target, o.min_iters, o.fgmres_max_iters};
   const size_t gn = (size_t)g * n;
-  launch_fg_begin(fb.fs, first_group ? 1 : 0, s);
+  launch_fg_begin(fb, first_group ? 1 : 0, s);
   apply_group(h, op, g, b, x, s);
   check_group(h, fb, op, g, b, x, 0, 1, p, s);
   const bool ir = o.refine == 1;
@@ -793,6 +793,7 @@ bool carve_fgbufs(unsigned char* base, int m, FgBufs* fb) {
   };
   const size_t d = sizeof(double), c = FG_MAX_COLS;
   fb->fs = (FgState*)take(sizeof(FgState));
+  fb->tick1 = (unsigned int*)take(sizeof(unsigned int) * c * FG_TICK_GROUPS * FG_TICK_STRIDE);
   fb->part = (double*)take(d * c * FG_BLOCKS * 32);
   fb->hbuf = (double*)take(d * c * 32);
   fb->h2buf = (double*)take(d * c * 32);
@@ -1775,6 +1776,8 @@ static kkt_status install_analysis(kkt_handle h, Analysis&& an, int st, int32_t 
       (ks = dalloc(h, &h->r, gn)) != KKT_OK || (ks = dalloc(h, &h->xt, gn)) != KKT_OK ||
       (ks = dalloc(h, &h->fs, 1)) != KKT_OK ||
       (ks = dalloc(h, &h->fb.part, (size_t)FG_MAX_COLS * FG_BLOCKS * 32)) != KKT_OK ||
+      (ks = dalloc(h, &h->fb.tick1, (size_t)FG_MAX_COLS * FG_TICK_GROUPS * FG_TICK_STRIDE)) !=
+          KKT_OK ||
       (ks = dalloc(h, &h->fb.hbuf, (size_t)FG_MAX_COLS * 32)) != KKT_OK ||
       (ks = dalloc(h, &h->fb.h2buf, (size_t)FG_MAX_COLS * 32)) != KKT_OK ||
       (ks = dalloc(h, &h->fb.H, (size_t)FG_MAX_COLS * (m + 1) * m)) != KKT_OK ||
