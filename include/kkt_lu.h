@@ -150,7 +150,8 @@ typedef struct {
                             KKT_WARN_NOT_CONVERGED */
   int32_t dense_lu; /* dense trailing block's factorization: 0 = a panel launch and an update
                        launch per 32 pivots (default), 1 = one dependency-driven launch over
-                       32 x 32 tiles with a look-ahead of one panel; the same values */
+                       32 x 32 tiles with a look-ahead of one panel, then a copy of the factored
+                       diagonal tiles; the same values */
   int32_t debug_spin_limit; /* testing: > 0 makes a dependency wait give up once the wave has
                                polled this many times (checked on its second poll and every 64th),
                                raising the stall flag, so every kernel drains and kkt_sync_report
