@@ -42,6 +42,19 @@ def critical_chain(tl: np.ndarray, rowptr: np.ndarray, colind: np.ndarray) -> li
     return chain[::-1]
 
 
+def multiply_adds(rowptr: np.ndarray, colind: np.ndarray, c0: int) -> np.ndarray:
+    """Per row i: the multiply-adds its sparse pivots cost (for each pivot k
+    < min(i, c0) of row i, the U entries of row k right of its diagonal)."""
+    n = len(rowptr) - 1
+    rows = np.repeat(np.arange(n), np.diff(rowptr))
+    diag = np.full(n, -1, np.int64)
+    on = colind == rows
+    diag[rows[on]] = np.nonzero(on)[0]
+    ulen = np.asarray(rowptr[1:], np.int64) - diag - 1
+    piv = (colind < rows) & (colind < c0)
+    return np.bincount(rows[piv], weights=ulen[colind[piv]], minlength=n)
+
+
 def summary(tl: np.ndarray, rowptr: np.ndarray, colind: np.ndarray, c0: int) -> str:
     rec = tl[:, 3] > 0
     chain = critical_chain(tl, rowptr, colind)
@@ -54,6 +67,11 @@ def summary(tl: np.ndarray, rowptr: np.ndarray, colind: np.ndarray, c0: int) -> 
         if m.any():
             lines.append(f"| {name} | {int(m.sum())} | {us[m, 0].min():.1f} | {us[m, 2].max():.1f} | "
                          f"{np.median(us[m, 2] - us[m, 1]):.2f} |")
+    madd = multiply_adds(rowptr, colind, c0)
+    lines += ["", "| kernel | rows | multiply-adds |", "|---|---|---|"]
+    for name, m in (("short-row band kernel (micro rows and list)", (tl[:, 3] == 1) | (tl[:, 3] == 2)),
+                    ("long-row band kernel", tl[:, 3] == 3)):
+        lines.append(f"| {name} | {int(m.sum())} | {int(madd[m].sum())} |")
     adv = np.array([us[b, 2] - us[a, 2] for a, b in zip(chain[:-1], chain[1:])])
     late = np.array([us[b, 0] - us[a, 2] for a, b in zip(chain[:-1], chain[1:])])
     kinds = np.array([tl[b, 3] for b in chain[1:]])

@@ -24,3 +24,17 @@ def test_chain_follows_the_input_that_finished_last():
     # rows without a record (kind 0) are skipped as inputs
     tl[1, 3] = 0
     assert timeline.critical_chain(tl, rowptr, colind) == [0, 3, 4, 5]
+
+
+def test_multiply_adds_count_the_pivot_rows_u_entries():
+    # row i pays, for each pivot k < min(i, c0) in its L part, one multiply-add
+    # per U entry of row k right of k's diagonal; checked against loops over a
+    # small dense-pattern factor
+    rows = [[0, 2], [1, 3], [0, 2, 3], [1, 2, 3]]
+    rowptr = np.cumsum([0] + [len(r) for r in rows])
+    colind = np.array([c for r in rows for c in r])
+    for c0, want in ((4, [0, 0, 1, 2]), (2, [0, 0, 1, 1]), (0, [0, 0, 0, 0])):
+        got = timeline.multiply_adds(rowptr, colind, c0)
+        brute = [sum(sum(1 for c in rows[k] if c > k) for k in r if k < i and k < c0)
+                 for i, r in enumerate(rows)]
+        assert list(got) == want == brute
