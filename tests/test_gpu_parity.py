@@ -313,8 +313,9 @@ def test_classical_refinement_matches_oracle(op, refine_sync):
 
 
 @pytest.mark.parametrize("layout", [dict(schedule=2, sync_mode=2), dict(schedule=2, sync_mode=2, dense_tail=300),
+                                    dict(schedule=2, sync_mode=2, dense_tail=300, dense_lu=1),
                                     dict(schedule=1), dict(schedule=2, sync_mode=1)],
-                         ids=["coherent", "dense-block", "levels", "fences"])
+                         ids=["coherent", "dense-block", "dense-block-tasks", "levels", "fences"])
 def test_static_pivoting_bitwise(layout):
     # threshold at the median pivot magnitude: about half of the pivots are
     # raised, identically in every refactorization kernel and in the oracle
